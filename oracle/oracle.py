@@ -1,0 +1,255 @@
+"""ctypes front end of the FP64 CPU oracle (test infrastructure only).
+
+Only the test suite, the smoke entry point and the benchmark's CPU-baseline leg use
+this module. It packs the generator dicts of ``paper_2201_13240_amd.workloads`` into
+the oracle's own C structs (nothing is shared with the GPU library) and calls the
+C++ oracle in ``wos_oracle.cpp``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SRC_PATH = os.path.join(HERE, "wos_oracle.cpp")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (plain -O2, no vectorisation flags)."""
+    if force or not os.path.exists(LIB_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread",
+                               SRC_PATH, "-o", tmp])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class OField(C.Structure):
+    _fields_ = [("base", C.c_int32), ("transform", C.c_int32), ("c0", C.c_double),
+                ("c1", C.c_double), ("n", C.c_int32), ("u_id", C.c_int32),
+                ("p", C.POINTER(C.c_double)), ("q", C.c_double * 8)]
+
+
+class OGeom(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("pad", C.c_int32), ("n_vertices", C.c_int64),
+                ("n_prims", C.c_int64), ("vertices", C.POINTER(C.c_double)),
+                ("prims", C.POINTER(C.c_int32)), ("center", C.c_double * 3),
+                ("radius", C.c_double), ("lo", C.c_double * 3), ("hi", C.c_double * 3)]
+
+
+class OProblem(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("pad", C.c_int32), ("geom", OGeom), ("alpha", OField),
+                ("psi", OField), ("sigma", OField), ("source", OField), ("boundary", OField),
+                ("epsilon", C.c_double)]
+
+
+class OOptions(C.Structure):
+    _fields_ = [("sigma_bar", C.c_double), ("seed", C.c_uint64), ("walk_offset", C.c_uint64),
+                ("n_walks", C.c_uint64), ("problem_index", C.c_uint32), ("variant", C.c_int32),
+                ("russian_roulette", C.c_int32), ("ww_lo", C.c_double), ("max_steps", C.c_uint64),
+                ("threads", C.c_int32), ("pad", C.c_int32)]
+
+
+_BASES = {"none": 0, "fourier": 1, "bumps": 2, "tanh": 3, "tanh_drift": 4, "manufactured": 5}
+_TRANSFORMS = {"affine": 0, "exp": 1}
+_GEOMS = {"ball": 0, "box": 1, "polygon": 2, "trimesh": 3}
+_US = {"expcos": 1, "quadratic": 2}
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        dp = C.POINTER(C.c_double)
+        L.oracle_philox4x32_10.argtypes = [C.POINTER(C.c_uint32)] * 3
+        L.oracle_uniforms.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int64, dp]
+        for name in ("oracle_ball_pb", "oracle_radial_cdf", "oracle_radial_pdf",
+                     "oracle_radial_quantile"):
+            getattr(L, name).argtypes = [C.c_int, C.c_double, C.c_double]
+            getattr(L, name).restype = C.c_double
+        L.oracle_ball_pb.argtypes = [C.c_int, C.c_double]
+        L.oracle_ball_gnorm.argtypes = [C.c_int, C.c_double, C.c_double]
+        L.oracle_ball_gnorm.restype = C.c_double
+        L.oracle_bessel.argtypes = [C.c_int, C.c_double]
+        L.oracle_bessel.restype = C.c_double
+        L.oracle_coefficients.argtypes = [C.POINTER(OProblem), dp, C.c_int64, dp]
+        L.oracle_distance.argtypes = [C.POINTER(OProblem), dp, C.c_int64, dp, dp]
+        L.oracle_sigma_prime_range.argtypes = [C.POINTER(OProblem), dp, C.c_int64, dp, dp]
+        L.oracle_solve.argtypes = [C.POINTER(OProblem), C.POINTER(OOptions), dp, C.c_int64, dp, dp,
+                                   C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
+        L.oracle_solve.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Problem:
+    """Holds an OProblem and the numpy buffers it points into."""
+
+    def __init__(self, prob: dict):
+        self._keep = []
+        self.dim = prob["dim"]
+        P = OProblem()
+        P.dim = self.dim
+        P.epsilon = prob["epsilon"]
+        self._geom(P.geom, prob["geometry"])
+        for name in ("alpha", "psi", "sigma", "source", "boundary"):
+            self._field(getattr(P, name), prob[name])
+        self.c = P
+
+    def _arr(self, a, dtype=np.float64):
+        a = np.ascontiguousarray(np.asarray(a, dtype))
+        self._keep.append(a)
+        return a
+
+    def _geom(self, G, g):
+        G.kind = _GEOMS[g["kind"]]
+        if g["kind"] == "ball":
+            for i, v in enumerate(g["center"]):
+                G.center[i] = v
+            G.radius = g["radius"]
+        elif g["kind"] == "box":
+            for i in range(len(g["lo"])):
+                G.lo[i] = g["lo"][i]
+                G.hi[i] = g["hi"][i]
+        else:
+            V = self._arr(g["vertices"])
+            G.vertices = _dptr(V)
+            G.n_vertices = V.shape[0]
+            if g["kind"] == "trimesh":
+                T = self._arr(g["triangles"], np.int32)
+                G.prims = T.ctypes.data_as(C.POINTER(C.c_int32))
+                G.n_prims = T.shape[0]
+            else:
+                G.n_prims = V.shape[0]
+
+    def _field(self, F, f):
+        F.base = _BASES[f["base"]]
+        F.transform = _TRANSFORMS[f["transform"]]
+        F.c0 = f["c0"]
+        F.c1 = f["c1"]
+        b = f["base"]
+        if b == "fourier":
+            packed = np.concatenate([f["k"], f["a"][:, None], f["phi"][:, None]], 1)
+            F.n = packed.shape[0]
+            F.p = _dptr(self._arr(packed))
+        elif b == "bumps":
+            packed = np.concatenate([f["centers"], f["widths"][:, None], f["amps"][:, None]], 1)
+            F.n = packed.shape[0]
+            F.p = _dptr(self._arr(packed))
+        elif b == "tanh":
+            F.q[0], F.q[1], F.q[2] = f["axis"], f["x0"], f["width"]
+        elif b == "tanh_drift":
+            vals = [f["axis"], f["x0"], f["width"], f["low"], f["high"], f["omega"]]
+            for i, v in enumerate(vals):
+                F.q[i] = v
+        elif b == "manufactured":
+            F.u_id = _US[f["u"]]
+
+
+def philox(ctr, key):
+    c = (C.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (C.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    o = (C.c_uint32 * 4)()
+    lib().oracle_philox4x32_10(c, k, o)
+    return [int(x) for x in o]
+
+
+def uniforms(seed, walk, point, problem, n):
+    out = np.empty(n)
+    lib().oracle_uniforms(seed, walk, point, problem, n, _dptr(out))
+    return out
+
+
+def ball_pb(dim, s):
+    return lib().oracle_ball_pb(dim, s)
+
+
+def ball_gnorm(dim, R, sigma_bar):
+    return lib().oracle_ball_gnorm(dim, R, sigma_bar)
+
+
+def radial_cdf(dim, s, t):
+    return lib().oracle_radial_cdf(dim, s, t)
+
+
+def radial_pdf(dim, s, t):
+    return lib().oracle_radial_pdf(dim, s, t)
+
+
+def radial_quantile(dim, s, u):
+    return lib().oracle_radial_quantile(dim, s, u)
+
+
+def bessel(which, x):
+    """which: 'i0', 'i1', 'k0', 'k1' (libstdc++ special functions)."""
+    return lib().oracle_bessel({"i0": 0, "i1": 1, "k0": 2, "k1": 3}[which], x)
+
+
+def coefficients(prob, pts):
+    """Per point [alpha, gamma, sigma', f, f', g]."""
+    P = Problem(prob)
+    pts = np.ascontiguousarray(pts, np.float64)
+    out = np.empty((pts.shape[0], 6))
+    lib().oracle_coefficients(C.byref(P.c), _dptr(pts), pts.shape[0], _dptr(out))
+    return out
+
+
+def distance(prob, pts):
+    P = Problem(prob)
+    pts = np.ascontiguousarray(pts, np.float64)
+    d = np.empty(pts.shape[0])
+    xb = np.empty_like(pts)
+    lib().oracle_distance(C.byref(P.c), _dptr(pts), pts.shape[0], _dptr(d), _dptr(xb))
+    return d, xb
+
+
+def sigma_prime_range(prob, pts):
+    P = Problem(prob)
+    pts = np.ascontiguousarray(pts, np.float64)
+    mn, mx = C.c_double(), C.c_double()
+    lib().oracle_sigma_prime_range(C.byref(P.c), _dptr(pts), pts.shape[0], C.byref(mn), C.byref(mx))
+    return mn.value, mx.value
+
+
+def sigma_bar_default(prob, samples):
+    """Default majorant max(sigma'_max, 0) - min(sigma'_min, 0) over interior samples."""
+    mn, mx = sigma_prime_range(prob, samples)
+    return max(mx, 0.0) - min(mn, 0.0)
+
+
+def solve(prob, pts, n_walks, sigma_bar, seed=0, walk_offset=0, problem_index=0, variant=0,
+          russian_roulette=False, ww_lo=0.5, max_steps=10**7, threads=0):
+    """Returns dict(sum, sum_sq, steps, mean, se, counters)."""
+    P = Problem(prob)
+    pts = np.ascontiguousarray(pts, np.float64)
+    n = pts.shape[0]
+    o = OOptions(sigma_bar=float(sigma_bar), seed=int(seed), walk_offset=int(walk_offset),
+                 n_walks=int(n_walks), problem_index=int(problem_index), variant=int(variant),
+                 russian_roulette=int(bool(russian_roulette)), ww_lo=float(ww_lo),
+                 max_steps=int(max_steps), threads=int(threads))
+    s = np.zeros(n)
+    q = np.zeros(n)
+    st = np.zeros(n, np.uint64)
+    cnt = np.zeros(3, np.uint64)
+    rc = lib().oracle_solve(C.byref(P.c), C.byref(o), _dptr(pts), n, _dptr(s), _dptr(q),
+                            st.ctypes.data_as(C.POINTER(C.c_uint64)),
+                            cnt.ctypes.data_as(C.POINTER(C.c_uint64)))
+    if rc != 0:
+        raise ValueError("oracle_solve rejected its arguments")
+    N = float(n_walks)
+    mean = s / N
+    var = np.maximum(q / N - mean * mean, 0.0) * N / max(N - 1.0, 1.0)
+    return {"sum": s, "sum_sq": q, "steps": st, "mean": mean, "se": np.sqrt(var / N),
+            "counters": cnt, "n_walks": n_walks}

@@ -1,0 +1,777 @@
+// FP64 CPU oracle for the delta-tracking walk on spheres of
+//   Sawhney, Seyb, Jarosz, Crane, "Grid-Free Monte Carlo for PDEs with
+//   Spatially Varying Coefficients" (SIGGRAPH 2022).
+//
+// TEST INFRASTRUCTURE ONLY. This file is a plain, slow, deliberately unoptimised
+// restatement of the method used to check the GPU library. Only the test suite,
+// the smoke entry point and the benchmark's CPU-baseline leg may load it. It
+// shares no code, header, table or constant with the GPU library.
+//
+// What it computes (each function cites the passage it follows):
+//   * the PDE of Sec. 1 (eq. 1): div(alpha grad u) + omega.grad u - sigma u = -f,
+//     u = g on the boundary, with omega = alpha grad(psi) (App. A needs the drift
+//     to be a gradient field);
+//   * the change of variables of Sec. 4.1 (eqs. 20-21) and App. A:
+//     U = e^gamma u, gamma = (ln alpha + psi)/2, giving
+//     Laplace(U) - sigma' U = -f', sigma' = sigma/alpha + Lap(gamma) + |grad gamma|^2,
+//     f' = e^gamma f / alpha;
+//   * the delta-tracking shift by a constant sigma_bar (eq. 23) and the
+//     delta-tracking walk on spheres (Sec. 5.1, eq. 28, supplemental Alg. 1);
+//   * the centred screened-Poisson Green's function of a ball, its integral |G|
+//     and its Poisson kernel (supplemental Sec. 1.1), sampled here by numerical
+//     inversion of the closed-form radial CDF (no rejection envelope);
+//   * the low side of the static weight window (Russian roulette, Sec. 6);
+//   * the per-point Monte Carlo mean (Sec. 3.1, eqs. 17-18).
+//
+// Readings of the paper taken here (where it is silent, ambiguous or garbled):
+//   R1  the source sign in eq. 21 is taken as -f' (consistent with eq. 23 and App. A);
+//   R2  with drift, gamma = (ln alpha + psi)/2 and the weights use e^{gamma(y)-gamma(x)}
+//       (reduces to sqrt(alpha(y)/alpha(x)) of Alg. 1 when omega = 0);
+//   R3  termination returns g(xbar) as printed in Alg. 1 (no e^gamma ratio);
+//   R4  Alg. 1 (source estimated at every step) is the default; eq. 28 (source only on
+//       volume events, weight 1/sigma_bar) is available as variant 1;
+//   R5  Russian roulette: when |W| < w_lo the walk survives with probability |W|/w_lo
+//       and then carries W = sign(W) w_lo; the estimate accumulated so far is kept;
+//   R6  for s = R sqrt(sigma_bar) < 1e-4 the harmonic (sigma_bar -> 0) limits are used
+//       for P_B = s^2/4 (2D), s^2/6 (3D) and for the radial law (relative error O(s^2)).
+//
+// Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), key = (seed lo,
+// seed hi), counter = (block index, walk index, point index, problem index); each
+// uniform double takes 53 bits from two consecutive 32-bit words.
+//
+// Build: g++ -O2 -std=c++17 -fPIC -shared -pthread (see build_oracle.py).
+
+#include <atomic>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+namespace {
+
+const double kPi = 3.14159265358979323846;
+
+// ------------------------------------------------------------------ Philox4x32-10
+
+void philox_round(uint32_t c[4], const uint32_t k[2]) {
+  const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+  const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+  const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+  const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+  const uint32_t n0 = hi1 ^ c[1] ^ k[0];
+  const uint32_t n2 = hi0 ^ c[3] ^ k[1];
+  c[0] = n0;
+  c[1] = lo1;
+  c[2] = n2;
+  c[3] = lo0;
+}
+
+void philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+  uint32_t k[2] = {key[0], key[1]};
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k[0] += 0x9E3779B9u;
+      k[1] += 0xBB67AE85u;
+    }
+    philox_round(c, k);
+  }
+  for (int i = 0; i < 4; ++i) out[i] = c[i];
+}
+
+struct Stream {
+  uint32_t key[2];
+  uint32_t ctr[4];
+  uint32_t buf[4];
+  int pos;
+};
+
+void stream_init(Stream* st, uint64_t seed, uint32_t walk, uint32_t point, uint32_t problem) {
+  st->key[0] = (uint32_t)seed;
+  st->key[1] = (uint32_t)(seed >> 32);
+  st->ctr[0] = 0;
+  st->ctr[1] = walk;
+  st->ctr[2] = point;
+  st->ctr[3] = problem;
+  st->pos = 4;
+}
+
+uint32_t next_u32(Stream* st) {
+  if (st->pos == 4) {
+    philox4x32_10(st->ctr, st->key, st->buf);
+    st->ctr[0] += 1;
+    st->pos = 0;
+  }
+  return st->buf[st->pos++];
+}
+
+double uniform(Stream* st) {  // [0, 1)
+  const uint64_t a = next_u32(st);
+  const uint64_t b = next_u32(st);
+  const uint64_t x = ((a << 32) | b) >> 11;
+  return (double)x * (1.0 / 9007199254740992.0);
+}
+
+// ------------------------------------------------------------------ problem description
+
+enum { B_NONE = 0, B_FOURIER = 1, B_BUMPS = 2, B_TANH = 3, B_TANH_DRIFT = 4, B_MANUFACTURED = 5 };
+enum { T_AFFINE = 0, T_EXP = 1 };
+enum { G_BALL = 0, G_BOX = 1, G_POLYGON = 2, G_TRIMESH = 3 };
+enum { U_EXPCOS = 1, U_QUADRATIC = 2 };
+
+}  // namespace
+
+extern "C" {
+
+struct OField {
+  int32_t base;
+  int32_t transform;
+  double c0, c1;
+  int32_t n;       // number of terms (fourier modes / bumps)
+  int32_t u_id;    // manufactured solution id
+  const double* p; // fourier: per term k[dim], a, phi;  bumps: per term c[dim], w, amp
+  double q[8];     // tanh: axis, x0, width;  tanh_drift: axis, x0, width, low, high, omega
+};
+
+struct OGeom {
+  int32_t kind;
+  int32_t pad;
+  int64_t n_vertices;
+  int64_t n_prims;
+  const double* vertices;  // [n_vertices][dim]
+  const int32_t* prims;    // trimesh: [n_prims][3]; polygon: unused (closed loop)
+  double center[3];
+  double radius;
+  double lo[3];
+  double hi[3];
+};
+
+struct OProblem {
+  int32_t dim;
+  int32_t pad;
+  OGeom geom;
+  OField alpha, psi, sigma, source, boundary;
+  double epsilon;
+};
+
+struct OOptions {
+  double sigma_bar;       // > 0, or 0 only for sigma' == 0 problems
+  uint64_t seed;
+  uint64_t walk_offset;
+  uint64_t n_walks;
+  uint32_t problem_index;
+  int32_t variant;        // 0: Alg. 1 (source every step), 1: eq. 28 (source on volume events)
+  int32_t russian_roulette;
+  double ww_lo;
+  uint64_t max_steps;
+  int32_t threads;
+  int32_t pad;
+};
+
+}  // extern "C"
+
+namespace {
+
+// A scalar field with its gradient and Laplacian.
+struct FVal {
+  double v;
+  double g[3];
+  double lap;
+};
+
+double dot(const double* a, const double* b, int dim) {
+  double s = 0;
+  for (int i = 0; i < dim; ++i) s += a[i] * b[i];
+  return s;
+}
+
+// Base B(x), grad B, Laplace B of the field families of the synthetic workloads.
+FVal eval_base(const OField& f, const double* x, int dim) {
+  FVal r = {0, {0, 0, 0}, 0};
+  if (f.base == B_FOURIER) {
+    // B = sum a cos(2 pi k.x + phi)
+    const int stride = dim + 2;
+    for (int j = 0; j < f.n; ++j) {
+      const double* k = f.p + j * stride;
+      const double a = f.p[j * stride + dim];
+      const double phi = f.p[j * stride + dim + 1];
+      const double arg = 2 * kPi * dot(k, x, dim) + phi;
+      const double c = std::cos(arg), s = std::sin(arg);
+      r.v += a * c;
+      for (int i = 0; i < dim; ++i) r.g[i] += -a * s * 2 * kPi * k[i];
+      r.lap += -a * c * 4 * kPi * kPi * dot(k, k, dim);
+    }
+  } else if (f.base == B_BUMPS) {
+    // B = sum amp exp(-|x-c|^2 / (2 w^2))
+    const int stride = dim + 2;
+    for (int j = 0; j < f.n; ++j) {
+      const double* c = f.p + j * stride;
+      const double w = f.p[j * stride + dim];
+      const double amp = f.p[j * stride + dim + 1];
+      double d[3], r2 = 0;
+      for (int i = 0; i < dim; ++i) {
+        d[i] = x[i] - c[i];
+        r2 += d[i] * d[i];
+      }
+      const double e = amp * std::exp(-r2 / (2 * w * w));
+      r.v += e;
+      for (int i = 0; i < dim; ++i) r.g[i] += -e * d[i] / (w * w);
+      r.lap += e * (r2 / (w * w * w * w) - dim / (w * w));
+    }
+  } else if (f.base == B_TANH) {
+    // B = (1 + tanh z)/2, z = (x_axis - x0)/width
+    const int ax = (int)f.q[0];
+    const double w = f.q[2];
+    const double th = std::tanh((x[ax] - f.q[1]) / w);
+    r.v = 0.5 * (1 + th);
+    r.g[ax] = 0.5 * (1 - th * th) / w;
+    r.lap = -th * (1 - th * th) / (w * w);
+  } else if (f.base == B_TANH_DRIFT) {
+    // psi with alpha psi' = omega, alpha = A + Bc tanh z, A = (lo+hi)/2, Bc = (hi-lo)/2,
+    // psi = omega w [A z - Bc ln(A cosh z + Bc sinh z) + Bc ln A] / (A^2 - Bc^2)
+    const int ax = (int)f.q[0];
+    const double x0 = f.q[1], w = f.q[2], lo = f.q[3], hi = f.q[4], om = f.q[5];
+    const double A = 0.5 * (lo + hi), Bc = 0.5 * (hi - lo);
+    const double z = (x[ax] - x0) / w;
+    const double az = std::fabs(z);
+    const double sg = z >= 0 ? 1.0 : -1.0;
+    const double lnmix = az + std::log(0.5 * (A + sg * Bc) + 0.5 * (A - sg * Bc) * std::exp(-2 * az));
+    r.v = om * w * (A * z - Bc * lnmix + Bc * std::log(A)) / (A * A - Bc * Bc);
+    const double th = std::tanh(z);
+    const double al = A + Bc * th;
+    const double dal = Bc * (1 - th * th) / w;
+    r.g[ax] = om / al;
+    r.lap = -om * dal / (al * al);
+  }
+  return r;
+}
+
+// Field value after its transform: affine c0 + c1 B, or exp(c0 + c1 B).
+FVal eval_field(const OField& f, const double* x, int dim) {
+  const FVal b = eval_base(f, x, dim);
+  FVal r;
+  if (f.transform == T_EXP) {
+    r.v = std::exp(f.c0 + f.c1 * b.v);
+    double gb2 = 0;
+    for (int i = 0; i < 3; ++i) {
+      r.g[i] = r.v * f.c1 * b.g[i];
+      gb2 += b.g[i] * b.g[i];
+    }
+    r.lap = r.v * (f.c1 * b.lap + f.c1 * f.c1 * gb2);
+  } else {
+    r.v = f.c0 + f.c1 * b.v;
+    for (int i = 0; i < 3; ++i) r.g[i] = f.c1 * b.g[i];
+    r.lap = f.c1 * b.lap;
+  }
+  return r;
+}
+
+// Manufactured solutions u with grad u and Laplace u.
+FVal eval_u(int id, const double* x) {
+  FVal r = {0, {0, 0, 0}, 0};
+  if (id == U_EXPCOS) {
+    const double e = std::exp(x[0]);
+    r.v = e * std::cos(x[1]);
+    r.g[0] = e * std::cos(x[1]);
+    r.g[1] = -e * std::sin(x[1]);
+    r.lap = 0;
+  } else if (id == U_QUADRATIC) {
+    r.v = 1 + x[0] * x[0] + 0.5 * x[0] * x[1];
+    r.g[0] = 2 * x[0] + 0.5 * x[1];
+    r.g[1] = 0.5 * x[0];
+    r.lap = 2;
+  }
+  return r;
+}
+
+// Everything the walk needs at a point (Sec. 4.1 eqs. 20-21 and App. A).
+struct Coef {
+  double alpha;
+  double gamma;        // (ln alpha + psi) / 2
+  double sigma_prime;  // sigma/alpha + Lap gamma + |grad gamma|^2
+  double f;            // source of eq. 1
+  double f_prime;      // e^gamma f / alpha
+};
+
+double source_value(const OProblem& P, const double* x, const FVal& al, const FVal& ps, double sg) {
+  const OField& f = P.source;
+  if (f.base == B_MANUFACTURED) {
+    // f = -div(alpha grad u) - omega.grad u + sigma u, omega = alpha grad psi (eq. 1)
+    const FVal u = eval_u(f.u_id, x);
+    double ga_gu = 0, gp_gu = 0;
+    for (int i = 0; i < P.dim; ++i) {
+      ga_gu += al.g[i] * u.g[i];
+      gp_gu += ps.g[i] * u.g[i];
+    }
+    return -(al.v * u.lap + ga_gu) - al.v * gp_gu + sg * u.v;
+  }
+  return eval_field(f, x, P.dim).v;
+}
+
+double boundary_value(const OProblem& P, const double* x) {
+  const OField& g = P.boundary;
+  if (g.base == B_MANUFACTURED) return eval_u(g.u_id, x).v;
+  return eval_field(g, x, P.dim).v;
+}
+
+Coef coefficients(const OProblem& P, const double* x) {
+  const int dim = P.dim;
+  const FVal al = eval_field(P.alpha, x, dim);
+  const FVal ps = eval_field(P.psi, x, dim);
+  const double sg = eval_field(P.sigma, x, dim).v;
+  // Eq. 20: dividing by alpha leaves Laplace u + b.grad u - (sigma/alpha) u = -f/alpha with
+  // first-order coefficient b = grad(alpha)/alpha + omega/alpha = grad(ln alpha + psi).
+  // App. A (generator Laplace/2): halve the equation, b/2 = grad(gamma) with
+  // gamma = (ln alpha + psi)/2, and the Girsanov/Ito weight yields the zeroth-order
+  // coefficient sigma/(2 alpha) + (Lap gamma + |grad gamma|^2)/2 and the source
+  // e^gamma f/(2 alpha). Multiplying back by 2 gives the screened Poisson form below.
+  double grad_gamma[3], lap_gamma;
+  {
+    double grad_ln_alpha[3];
+    double ga2 = 0;
+    for (int i = 0; i < 3; ++i) {
+      grad_ln_alpha[i] = al.g[i] / al.v;
+      ga2 += al.g[i] * al.g[i];
+    }
+    const double lap_ln_alpha = al.lap / al.v - ga2 / (al.v * al.v);
+    for (int i = 0; i < 3; ++i) grad_gamma[i] = 0.5 * (grad_ln_alpha[i] + ps.g[i]);
+    lap_gamma = 0.5 * (lap_ln_alpha + ps.lap);
+  }
+  Coef c;
+  c.alpha = al.v;
+  c.gamma = 0.5 * (std::log(al.v) + ps.v);
+  c.sigma_prime = sg / al.v + lap_gamma + dot(grad_gamma, grad_gamma, 3);
+  c.f = source_value(P, x, al, ps, sg);
+  c.f_prime = std::exp(c.gamma) * c.f / al.v;
+  return c;
+}
+
+// ------------------------------------------------------------------ distance to the boundary
+
+void closest_on_segment(const double* p, const double* a, const double* b, int dim, double* out) {
+  double ab[3], ap[3];
+  for (int i = 0; i < dim; ++i) {
+    ab[i] = b[i] - a[i];
+    ap[i] = p[i] - a[i];
+  }
+  const double l2 = dot(ab, ab, dim);
+  double t = l2 > 0 ? dot(ap, ab, dim) / l2 : 0.0;
+  if (t < 0) t = 0;
+  if (t > 1) t = 1;
+  for (int i = 0; i < dim; ++i) out[i] = a[i] + t * ab[i];
+}
+
+double dist2(const double* a, const double* b, int dim) {
+  double s = 0;
+  for (int i = 0; i < dim; ++i) s += (a[i] - b[i]) * (a[i] - b[i]);
+  return s;
+}
+
+// Closest point of a triangle: the projection onto its plane if that lies inside the
+// triangle, otherwise the closest of the three edge points.
+void closest_on_triangle(const double* p, const double* a, const double* b, const double* c, double* out) {
+  double e0[3], e1[3], n[3], ap[3];
+  for (int i = 0; i < 3; ++i) {
+    e0[i] = b[i] - a[i];
+    e1[i] = c[i] - a[i];
+    ap[i] = p[i] - a[i];
+  }
+  n[0] = e0[1] * e1[2] - e0[2] * e1[1];
+  n[1] = e0[2] * e1[0] - e0[0] * e1[2];
+  n[2] = e0[0] * e1[1] - e0[1] * e1[0];
+  const double nn = dot(n, n, 3);
+  if (nn > 0) {
+    const double h = dot(ap, n, 3) / nn;
+    double q[3];
+    for (int i = 0; i < 3; ++i) q[i] = p[i] - h * n[i];
+    // barycentric test via signed sub-areas
+    auto side = [&](const double* u, const double* v) {
+      double uv[3], uq[3], cr[3];
+      for (int i = 0; i < 3; ++i) {
+        uv[i] = v[i] - u[i];
+        uq[i] = q[i] - u[i];
+      }
+      cr[0] = uv[1] * uq[2] - uv[2] * uq[1];
+      cr[1] = uv[2] * uq[0] - uv[0] * uq[2];
+      cr[2] = uv[0] * uq[1] - uv[1] * uq[0];
+      return dot(cr, n, 3);
+    };
+    if (side(a, b) >= 0 && side(b, c) >= 0 && side(c, a) >= 0) {
+      for (int i = 0; i < 3; ++i) out[i] = q[i];
+      return;
+    }
+  }
+  double best = INFINITY, tmp[3];
+  const double* V[3] = {a, b, c};
+  for (int e = 0; e < 3; ++e) {
+    closest_on_segment(p, V[e], V[(e + 1) % 3], 3, tmp);
+    const double d2 = dist2(p, tmp, 3);
+    if (d2 < best) {
+      best = d2;
+      for (int i = 0; i < 3; ++i) out[i] = tmp[i];
+    }
+  }
+}
+
+// Unsigned distance d and closest point xbar on the boundary (Alg. 1, first line),
+// by brute force over all primitives.
+double distance_to_boundary(const OProblem& P, const double* x, double* xbar) {
+  const OGeom& g = P.geom;
+  const int dim = P.dim;
+  if (g.kind == G_BALL) {
+    double v[3], r = 0;
+    for (int i = 0; i < dim; ++i) {
+      v[i] = x[i] - g.center[i];
+      r += v[i] * v[i];
+    }
+    r = std::sqrt(r);
+    for (int i = 0; i < dim; ++i) xbar[i] = r > 0 ? g.center[i] + g.radius * v[i] / r : g.center[i] + (i == 0 ? g.radius : 0);
+    return std::fabs(g.radius - r);
+  }
+  if (g.kind == G_BOX) {
+    double best = INFINITY;
+    for (int i = 0; i < dim; ++i) {
+      for (int side = 0; side < 2; ++side) {
+        const double plane = side ? g.hi[i] : g.lo[i];
+        double q[3];
+        for (int j = 0; j < dim; ++j) q[j] = std::fmin(std::fmax(x[j], g.lo[j]), g.hi[j]);
+        q[i] = plane;
+        const double d2 = dist2(x, q, dim);
+        if (d2 < best) {
+          best = d2;
+          for (int j = 0; j < dim; ++j) xbar[j] = q[j];
+        }
+      }
+    }
+    return std::sqrt(best);
+  }
+  if (g.kind == G_POLYGON) {
+    double best = INFINITY, q[3];
+    const int64_t n = g.n_vertices;
+    for (int64_t j = 0; j < n; ++j) {
+      const double* a = g.vertices + 2 * j;
+      const double* b = g.vertices + 2 * ((j + 1) % n);
+      closest_on_segment(x, a, b, 2, q);
+      const double d2 = dist2(x, q, 2);
+      if (d2 < best) {
+        best = d2;
+        xbar[0] = q[0];
+        xbar[1] = q[1];
+      }
+    }
+    return std::sqrt(best);
+  }
+  // triangle mesh
+  double best = INFINITY, q[3];
+  for (int64_t j = 0; j < g.n_prims; ++j) {
+    const int32_t* t = g.prims + 3 * j;
+    closest_on_triangle(x, g.vertices + 3 * t[0], g.vertices + 3 * t[1], g.vertices + 3 * t[2], q);
+    const double d2 = dist2(x, q, 3);
+    if (d2 < best) {
+      best = d2;
+      for (int i = 0; i < 3; ++i) xbar[i] = q[i];
+    }
+  }
+  return std::sqrt(best);
+}
+
+// ------------------------------------------------------------------ ball kernels (supp. Sec. 1.1)
+
+double I0(double x) { return std::cyl_bessel_i(0.0, x); }
+double I1(double x) { return std::cyl_bessel_i(1.0, x); }
+double K0(double x) { return std::cyl_bessel_k(0.0, x); }
+double K1(double x) { return std::cyl_bessel_k(1.0, x); }
+
+const double kSmallS = 1e-4;  // reading R6
+
+// P_B = sigma_bar |G| for the ball of radius R centred at x, s = R sqrt(sigma_bar).
+double ball_pb(int dim, double s) {
+  if (s < kSmallS) return dim == 2 ? s * s / 4 : s * s / 6;
+  if (dim == 2) return 1.0 - 1.0 / I0(s);
+  return 1.0 - s / std::sinh(s);
+}
+
+// |G| = integral of the centred Green's function over the ball.
+double ball_gnorm(int dim, double R, double sigma_bar) {
+  const double s = R * std::sqrt(sigma_bar);
+  if (sigma_bar <= 0 || s < kSmallS) return dim == 2 ? R * R / 4 : R * R / 6;
+  return ball_pb(dim, s) / sigma_bar;
+}
+
+// Radial CDF of y ~ G(x,.)/|G| in t = |y-x|/R, from integrating 2 pi r G (2D) or
+// 4 pi r^2 G (3D) of supp. Sec. 1.1 in closed form.
+//   2D: C(t) = [1 - ts K1(ts) - s (K0(s)/I0(s)) t I1(ts)] / (1 - 1/I0(s))
+//   3D: C(t) = [1 - sinh(s(1-t))/sinh s - ts cosh(s(1-t))/sinh s] / (1 - s/sinh s)
+// and their harmonic limits t^2 (1 - 2 ln t), 3t^2 - 2t^3.
+double radial_cdf(int dim, double s, double t) {
+  if (t <= 0) return 0.0;
+  if (t >= 1) return 1.0;
+  if (s < kSmallS) return dim == 2 ? t * t * (1 - 2 * std::log(t)) : t * t * (3 - 2 * t);
+  if (dim == 2) {
+    const double i0s = I0(s);
+    const double ratio = K0(s) / i0s;
+    const double ts = t * s;
+    double num = 1.0 - ts * K1(ts);
+    if (ratio > 0) num -= s * ratio * t * I1(ts);
+    return num / (1.0 - 1.0 / i0s);
+  }
+  // sinh(s(1-t))/sinh(s) and cosh(s(1-t))/sinh(s), written with decaying exponentials
+  // 1 - e^{-x} is formed with expm1 to avoid cancellation at small s
+  const double one_m_em2s = -std::expm1(-2 * s);
+  const double em2st = std::exp(-2 * s * (1 - t));
+  const double est = std::exp(-s * t);
+  const double sh_ratio = est * -std::expm1(-2 * s * (1 - t)) / one_m_em2s;
+  const double ch_ratio = est * (1 + em2st) / one_m_em2s;
+  const double num = 1.0 - sh_ratio - t * s * ch_ratio;
+  return num / ball_pb(3, s);
+}
+
+// Radial density dC/dt.
+double radial_pdf(int dim, double s, double t) {
+  if (t <= 0 || t >= 1) return 0.0;
+  if (s < kSmallS) return dim == 2 ? -4 * t * std::log(t) : 6 * t * (1 - t);
+  if (dim == 2) {
+    const double ts = t * s;
+    return t * s * s * (K0(ts) - K0(s) / I0(s) * I0(ts)) / ball_pb(2, s);
+  }
+  const double sh_ratio = std::exp(-s * t) * std::expm1(-2 * s * (1 - t)) / std::expm1(-2 * s);
+  return t * s * s * sh_ratio / ball_pb(3, s);
+}
+
+// Inverse of the radial CDF by safeguarded Newton iteration on [0, 1].
+double radial_quantile(int dim, double s, double u) {
+  double lo = 0.0, hi = 1.0, t = 0.5;
+  for (int it = 0; it < 200; ++it) {
+    const double c = radial_cdf(dim, s, t) - u;
+    if (c < 0) lo = t; else hi = t;
+    const double p = radial_pdf(dim, s, t);
+    double tn = (p > 0) ? t - c / p : 0.5 * (lo + hi);
+    if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+    if (std::fabs(tn - t) < 1e-15 || hi - lo < 1e-15) return tn;
+    t = tn;
+  }
+  return t;
+}
+
+void uniform_direction(Stream* st, int dim, double* v) {
+  if (dim == 2) {
+    const double th = 2 * kPi * uniform(st);
+    v[0] = std::cos(th);
+    v[1] = std::sin(th);
+    v[2] = 0;
+  } else {
+    const double z = 1 - 2 * uniform(st);
+    const double ph = 2 * kPi * uniform(st);
+    const double rr = std::sqrt(std::fmax(0.0, 1 - z * z));
+    v[0] = rr * std::cos(ph);
+    v[1] = rr * std::sin(ph);
+    v[2] = z;
+  }
+}
+
+// ------------------------------------------------------------------ one walk (Sec. 5.1, Alg. 1)
+
+struct WalkResult {
+  double value;
+  uint64_t steps;   // distance queries
+  int capped;
+  int rr_killed;
+};
+
+WalkResult walk(const OProblem& P, const OOptions& o, const double* x0, Stream* st) {
+  const int dim = P.dim;
+  const double sb = o.sigma_bar;
+  double x[3] = {0, 0, 0};
+  for (int i = 0; i < dim; ++i) x[i] = x0[i];
+  Coef cx = coefficients(P, x);
+  // The estimate of u(x0) is sum_k W_k * (source estimate at ball k) + W_K g(xbar_K),
+  // with W the product of the per-step factors that multiply the recursive estimate.
+  double W = 1.0;
+  double A = 0.0;
+  WalkResult res = {0, 0, 0, 0};
+  for (;;) {
+    if (res.steps >= o.max_steps) {
+      res.capped = 1;
+      break;
+    }
+    double xbar[3] = {0, 0, 0};
+    const double d = distance_to_boundary(P, x, xbar);
+    res.steps++;
+    if (d < P.epsilon) {               // epsilon shell: return g(xbar)  (R3)
+      A += W * boundary_value(P, xbar);
+      break;
+    }
+    const double R = d;                // largest ball centred at x inside the domain
+    const double s = R * std::sqrt(sb);
+    const double gnorm = ball_gnorm(dim, R, sb);
+    const double pb = sb > 0 ? sb * gnorm : 0.0;  // probability of the volume term
+    // y ~ G(x, .)/|G| : uniform direction and the radial law (supp. Sec. 1.4)
+    double v[3];
+    uniform_direction(st, dim, v);
+    const double t = radial_quantile(dim, s, uniform(st));
+    double y[3] = {0, 0, 0};
+    for (int i = 0; i < dim; ++i) y[i] = x[i] + t * R * v[i];
+    const Coef cy = coefficients(P, y);
+    const double mu = uniform(st);
+    const bool volume = mu < pb;
+    // source estimate |G| f'(y) / (e^gamma(x)) = |G| e^{gamma(y)-gamma(x)} f(y)/alpha(y)
+    if (o.variant == 0) {
+      A += W * gnorm * std::exp(cy.gamma - cx.gamma) * cy.f / cy.alpha;
+    } else if (volume) {
+      A += W * std::exp(cy.gamma - cx.gamma) * cy.f / (cy.alpha * sb);
+    }
+    if (volume) {
+      // null event: weight (1 - sigma'(y)/sigma_bar) e^{gamma(y) - gamma(x)}, continue at y
+      W *= (1.0 - cy.sigma_prime / sb) * std::exp(cy.gamma - cx.gamma);
+      for (int i = 0; i < dim; ++i) x[i] = y[i];
+      cx = cy;
+    } else {
+      // boundary term: z uniform on the sphere, weight e^{gamma(z) - gamma(x)}
+      double vz[3];
+      uniform_direction(st, dim, vz);
+      double z[3] = {0, 0, 0};
+      for (int i = 0; i < dim; ++i) z[i] = x[i] + R * vz[i];
+      const Coef cz = coefficients(P, z);
+      W *= std::exp(cz.gamma - cx.gamma);
+      for (int i = 0; i < dim; ++i) x[i] = z[i];
+      cx = cz;
+    }
+    if (o.russian_roulette && std::fabs(W) < o.ww_lo) {  // weight window, low side (R5)
+      const double q = std::fabs(W) / o.ww_lo;
+      if (uniform(st) < q) {
+        W = (W < 0 ? -o.ww_lo : o.ww_lo);
+      } else {
+        res.rr_killed = 1;
+        break;
+      }
+    }
+  }
+  res.value = A;
+  return res;
+}
+
+bool point_ok(const OProblem& P, const double* x) {
+  for (int i = 0; i < P.dim; ++i)
+    if (!std::isfinite(x[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+// ====================================================================== C entry points
+
+extern "C" {
+
+void oracle_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
+  philox4x32_10(ctr, key, out);
+}
+
+// n uniform doubles of the stream of (seed, walk, point, problem).
+void oracle_uniforms(uint64_t seed, uint32_t walk, uint32_t point, uint32_t problem, int64_t n, double* out) {
+  Stream st;
+  stream_init(&st, seed, walk, point, problem);
+  for (int64_t i = 0; i < n; ++i) out[i] = uniform(&st);
+}
+
+double oracle_ball_pb(int dim, double s) { return ball_pb(dim, s); }
+double oracle_ball_gnorm(int dim, double R, double sigma_bar) { return ball_gnorm(dim, R, sigma_bar); }
+double oracle_radial_cdf(int dim, double s, double t) { return radial_cdf(dim, s, t); }
+double oracle_radial_pdf(int dim, double s, double t) { return radial_pdf(dim, s, t); }
+double oracle_radial_quantile(int dim, double s, double u) { return radial_quantile(dim, s, u); }
+double oracle_bessel(int which, double x) {
+  switch (which) {
+    case 0: return I0(x);
+    case 1: return I1(x);
+    case 2: return K0(x);
+    default: return K1(x);
+  }
+}
+
+// Per point: alpha, gamma, sigma', f, f', g (boundary field evaluated at the point).
+void oracle_coefficients(const OProblem* P, const double* pts, int64_t n, double* out) {
+  for (int64_t i = 0; i < n; ++i) {
+    const double* x = pts + i * P->dim;
+    const Coef c = coefficients(*P, x);
+    double* o = out + 6 * i;
+    o[0] = c.alpha;
+    o[1] = c.gamma;
+    o[2] = c.sigma_prime;
+    o[3] = c.f;
+    o[4] = c.f_prime;
+    o[5] = boundary_value(*P, x);
+  }
+}
+
+void oracle_distance(const OProblem* P, const double* pts, int64_t n, double* d, double* xbar) {
+  for (int64_t i = 0; i < n; ++i) d[i] = distance_to_boundary(*P, pts + i * P->dim, xbar + i * P->dim);
+}
+
+// sigma' min and max over the given sample points (the default majorant of Sec. 5.1 /
+// Sec. 7.1 is max - min over the domain; the caller supplies interior samples).
+void oracle_sigma_prime_range(const OProblem* P, const double* pts, int64_t n, double* mn, double* mx) {
+  double lo = INFINITY, hi = -INFINITY;
+  for (int64_t i = 0; i < n; ++i) {
+    const double sp = coefficients(*P, pts + i * P->dim).sigma_prime;
+    lo = std::fmin(lo, sp);
+    hi = std::fmax(hi, sp);
+  }
+  *mn = lo;
+  *mx = hi;
+}
+
+// Monte Carlo solve: per point, walks j = walk_offset .. walk_offset + n_walks - 1.
+// Outputs (per point): sum of estimates, sum of squares, total distance queries.
+// counters: [0] invalid points, [1] capped walks, [2] Russian-roulette kills.
+int oracle_solve(const OProblem* P, const OOptions* o, const double* pts, int64_t n_points,
+                 double* sum, double* sum_sq, uint64_t* steps, uint64_t* counters) {
+  if (o->sigma_bar < 0) return 1;
+  std::atomic<int64_t> next(0);
+  std::atomic<uint64_t> bad(0), capped(0), killed(0);
+  auto worker = [&]() {
+    for (;;) {
+      const int64_t i = next.fetch_add(1);
+      if (i >= n_points) break;
+      const double* x0 = pts + i * P->dim;
+      if (!point_ok(*P, x0)) {
+        sum[i] = NAN;
+        sum_sq[i] = NAN;
+        steps[i] = 0;
+        bad++;
+        continue;
+      }
+      // Neumaier-compensated sums
+      double s = 0, cs = 0, q = 0, cq = 0;
+      uint64_t nst = 0;
+      for (uint64_t j = 0; j < o->n_walks; ++j) {
+        Stream st;
+        stream_init(&st, o->seed, (uint32_t)(o->walk_offset + j), (uint32_t)i, o->problem_index);
+        const WalkResult r = walk(*P, *o, x0, &st);
+        nst += r.steps;
+        capped += r.capped;
+        killed += r.rr_killed;
+        const double v = r.value, v2 = r.value * r.value;
+        double t = s + v;
+        cs += std::fabs(s) >= std::fabs(v) ? (s - t) + v : (v - t) + s;
+        s = t;
+        t = q + v2;
+        cq += std::fabs(q) >= std::fabs(v2) ? (q - t) + v2 : (v2 - t) + q;
+        q = t;
+      }
+      sum[i] = s + cs;
+      sum_sq[i] = q + cq;
+      steps[i] = nst;
+    }
+  };
+  int nt = o->threads > 0 ? o->threads : (int)std::thread::hardware_concurrency();
+  if (nt < 1) nt = 1;
+  std::vector<std::thread> pool;
+  for (int k = 0; k < nt; ++k) pool.emplace_back(worker);
+  for (auto& th : pool) th.join();
+  counters[0] = bad;
+  counters[1] = capped;
+  counters[2] = killed;
+  return 0;
+}
+
+}  // extern "C"
