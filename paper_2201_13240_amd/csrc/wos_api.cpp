@@ -1,0 +1,1025 @@
+// C ABI of the walk-on-spheres library: problem compilation (fields, geometry, BVH,
+// sigma_bar), solves, plans with hipGraph replay, and diagnostics.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/wos.h"
+#include "bvh.h"
+#include "wos_launch.h"
+#include "wos_types.h"
+
+using namespace wos;
+
+namespace {
+
+thread_local std::string g_error;
+
+wos_status fail(wos_status s, const std::string& msg) {
+  g_error = msg;
+  return s;
+}
+
+#define WOS_HIP(call)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(e_ == hipErrorOutOfMemory ? WOS_ERR_OUT_OF_MEMORY : WOS_ERR_DEVICE,       \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                       \
+  } while (0)
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// Bump allocator over one host staging buffer mirrored by one device allocation.
+struct Blob {
+  std::vector<unsigned char> host;
+  size_t alloc(size_t bytes, size_t align = 256) {
+    size_t off = (host.size() + align - 1) / align * align;
+    host.resize(off + bytes);
+    return off;
+  }
+};
+
+}  // namespace
+
+struct wos_problem {
+  int device = 0;
+  int dim = 2;
+  int geom = 0;
+  double epsilon = 0;
+  double sigma_bar = 0;
+  double sp_min = NAN, sp_max = NAN;
+  void* dmem = nullptr;
+  size_t off32 = 0, off64 = 0;
+  int64_t n_nodes = 0, n_prims = 0;
+  int32_t depth = 0;
+  std::vector<unsigned char> staging;  // host copy of the device blob
+  const void* d32() const { return (const unsigned char*)dmem + off32; }
+  const void* d64() const { return (const unsigned char*)dmem + off64; }
+};
+
+namespace {
+
+// ------------------------------------------------------------------ fields
+
+wos_status check_field(const wos_field_desc& f, int dim, const char* name, bool source_or_boundary) {
+  if (f.transform != WOS_TRANSFORM_AFFINE && f.transform != WOS_TRANSFORM_EXP)
+    return fail(WOS_ERR_INVALID_ARG, std::string(name) + ": unknown transform");
+  switch (f.base) {
+    case WOS_FIELD_NONE: break;
+    case WOS_FIELD_FOURIER:
+    case WOS_FIELD_BUMPS:
+      if (f.n_terms < 0 || (f.n_terms > 0 && !f.terms))
+        return fail(WOS_ERR_INVALID_ARG, std::string(name) + ": terms missing");
+      for (int j = 0; j < f.n_terms; ++j)
+        for (int k = 0; k < dim + 2; ++k)
+          if (!std::isfinite(f.terms[j * (dim + 2) + k]))
+            return fail(WOS_ERR_INVALID_ARG, std::string(name) + ": non-finite term");
+      if (f.base == WOS_FIELD_BUMPS)
+        for (int j = 0; j < f.n_terms; ++j)
+          if (!(f.terms[j * (dim + 2) + dim] > 0)) return fail(WOS_ERR_INVALID_ARG, std::string(name) + ": bump width <= 0");
+      break;
+    case WOS_FIELD_TANH:
+    case WOS_FIELD_TANH_DRIFT: {
+      const int ax = (int)f.params[0];
+      if (ax < 0 || ax >= dim || !(f.params[2] > 0))
+        return fail(WOS_ERR_INVALID_ARG, std::string(name) + ": bad tanh axis or width");
+      if (f.base == WOS_FIELD_TANH_DRIFT && (!(f.params[3] > 0) || !(f.params[4] > 0) || f.params[3] == f.params[4] ||
+                                            f.transform != WOS_TRANSFORM_AFFINE || f.c0 != 0 || f.c1 != 1))
+        return fail(WOS_ERR_INVALID_ARG, std::string(name) + ": tanh_drift needs 0 < low != high, affine (0, 1)");
+      break;
+    }
+    case WOS_FIELD_MANUFACTURED:
+      if (!source_or_boundary) return fail(WOS_ERR_INVALID_ARG, std::string(name) + ": manufactured only for f and g");
+      if (f.solution_id != 1 && f.solution_id != 2) return fail(WOS_ERR_INVALID_ARG, std::string(name) + ": unknown solution");
+      break;
+    default: return fail(WOS_ERR_INVALID_ARG, std::string(name) + ": unknown base");
+  }
+  if (!std::isfinite(f.c0) || !std::isfinite(f.c1)) return fail(WOS_ERR_INVALID_ARG, std::string(name) + ": bad c0/c1");
+  return WOS_OK;
+}
+
+template <typename T>
+std::vector<T> field_terms(const wos_field_desc& f, int dim) {
+  std::vector<T> out((size_t)std::max(f.n_terms, 0) * kTermStride, (T)0);
+  for (int j = 0; j < f.n_terms; ++j) {
+    const double* t = f.terms + j * (dim + 2);
+    T* o = out.data() + (size_t)j * kTermStride;
+    if (f.base == WOS_FIELD_FOURIER) {
+      double k2 = 0;
+      for (int i = 0; i < dim; ++i) {
+        o[i] = (T)(kTwoPi * t[i]);
+        k2 += (kTwoPi * t[i]) * (kTwoPi * t[i]);
+      }
+      const double a = t[dim], phi = t[dim + 1];
+      o[3] = (T)(a * std::cos(phi));
+      o[4] = (T)(a * std::sin(phi));
+      o[5] = (T)k2;
+    } else {  // bumps
+      for (int i = 0; i < dim; ++i) o[i] = (T)t[i];
+      const double w = t[dim];
+      o[3] = (T)(1.0 / (2 * w * w));
+      o[4] = (T)t[dim + 1];
+      o[5] = (T)(1.0 / (w * w));
+    }
+  }
+  return out;
+}
+
+template <typename T>
+DevField<T> field_header(const wos_field_desc& f) {
+  DevField<T> d;
+  std::memset(&d, 0, sizeof(d));
+  d.base = f.base;
+  d.transform = f.transform;
+  d.n = (f.base == WOS_FIELD_FOURIER || f.base == WOS_FIELD_BUMPS) ? f.n_terms : 0;
+  d.sol = f.solution_id;
+  d.c0 = (T)f.c0;
+  d.c1 = (T)f.c1;
+  if (f.base == WOS_FIELD_TANH) {
+    d.prm[0] = (T)f.params[0];
+    d.prm[1] = (T)f.params[1];
+    d.prm[2] = (T)(1.0 / f.params[2]);
+  } else if (f.base == WOS_FIELD_TANH_DRIFT) {
+    const double w = f.params[2], lo = f.params[3], hi = f.params[4], om = f.params[5];
+    const double A = 0.5 * (lo + hi), B = 0.5 * (hi - lo);
+    d.prm[0] = (T)f.params[0];
+    d.prm[1] = (T)f.params[1];
+    d.prm[2] = (T)(1.0 / w);
+    d.prm[3] = (T)A;
+    d.prm[4] = (T)B;
+    d.prm[5] = (T)(om * w / (A * A - B * B));
+    d.prm[6] = (T)std::log(A);
+    d.prm[7] = (T)om;
+  }
+  return d;
+}
+
+// ------------------------------------------------------------------ geometry
+
+struct HostGeometry {
+  int kind = 0;
+  int64_t n_prims = 0;
+  std::vector<double> prims64;       // leaf order, device layout
+  std::vector<float> prims32;
+  BvhTopology topo;
+  std::vector<double> bounds64;      // node child bounds
+  std::vector<float> bounds32;
+};
+
+wos_status build_geometry(const wos_problem_desc& d, HostGeometry& g) {
+  const wos_geometry_desc& G = d.geometry;
+  const int dim = d.dim;
+  g.kind = G.kind;
+  if (G.kind == WOS_GEOM_BALL) {
+    if (!(G.radius > 0) || !std::isfinite(G.radius)) return fail(WOS_ERR_GEOMETRY, "ball radius must be > 0");
+    return WOS_OK;
+  }
+  if (G.kind == WOS_GEOM_BOX) {
+    for (int i = 0; i < dim; ++i)
+      if (!(G.hi[i] > G.lo[i])) return fail(WOS_ERR_GEOMETRY, "box needs lo < hi");
+    return WOS_OK;
+  }
+  const int pdim = dim;
+  int stride;
+  std::vector<double> lo, hi, cen, raw;
+  if (G.kind == WOS_GEOM_POLYGON) {
+    if (dim != 2) return fail(WOS_ERR_GEOMETRY, "polygons are 2D");
+    if (!G.vertices || G.n_vertices < 3) return fail(WOS_ERR_GEOMETRY, "polygon needs >= 3 vertices");
+    const int64_t n = G.n_vertices;
+    g.n_prims = n;
+    stride = 4;
+    raw.resize((size_t)n * 4);
+    for (int64_t j = 0; j < n; ++j) {
+      const double* a = G.vertices + 2 * j;
+      const double* b = G.vertices + 2 * ((j + 1) % n);
+      if (!std::isfinite(a[0]) || !std::isfinite(a[1])) return fail(WOS_ERR_GEOMETRY, "non-finite vertex");
+      raw[4 * j] = a[0];
+      raw[4 * j + 1] = a[1];
+      raw[4 * j + 2] = b[0];
+      raw[4 * j + 3] = b[1];
+    }
+  } else if (G.kind == WOS_GEOM_TRIMESH) {
+    if (dim != 3) return fail(WOS_ERR_GEOMETRY, "triangle meshes are 3D");
+    if (!G.vertices || !G.triangles || G.n_vertices < 4 || G.n_triangles < 4)
+      return fail(WOS_ERR_GEOMETRY, "mesh needs >= 4 vertices and triangles");
+    const int64_t n = G.n_triangles;
+    g.n_prims = n;
+    stride = 12;
+    raw.assign((size_t)n * 12, 0.0);
+    for (int64_t j = 0; j < n; ++j)
+      for (int v = 0; v < 3; ++v) {
+        const int32_t vi = G.triangles[3 * j + v];
+        if (vi < 0 || vi >= G.n_vertices) return fail(WOS_ERR_GEOMETRY, "triangle index out of range");
+        for (int k = 0; k < 3; ++k) {
+          const double c = G.vertices[3 * (int64_t)vi + k];
+          if (!std::isfinite(c)) return fail(WOS_ERR_GEOMETRY, "non-finite vertex");
+          raw[12 * j + 3 * v + k] = c;
+        }
+      }
+  } else {
+    return fail(WOS_ERR_INVALID_ARG, "unknown geometry kind");
+  }
+  if (g.n_prims >= (1ll << 27)) return fail(WOS_ERR_GEOMETRY, "too many primitives");
+  const int64_t n = g.n_prims;
+  const int nv = G.kind == WOS_GEOM_POLYGON ? 2 : 3;
+  lo.resize((size_t)n * pdim);
+  hi.resize((size_t)n * pdim);
+  cen.resize((size_t)n * pdim);
+  for (int64_t j = 0; j < n; ++j)
+    for (int k = 0; k < pdim; ++k) {
+      double mn = 1e300, mx = -1e300, s = 0;
+      for (int v = 0; v < nv; ++v) {
+        const double c = raw[(size_t)stride * j + pdim * v + k];
+        mn = std::min(mn, c);
+        mx = std::max(mx, c);
+        s += c;
+      }
+      lo[j * pdim + k] = mn;
+      hi[j * pdim + k] = mx;
+      cen[j * pdim + k] = s / nv;
+    }
+  g.topo = build_bvh(lo, hi, cen, pdim, n, 4);
+  if (g.topo.depth >= 46) return fail(WOS_ERR_GEOMETRY, "BVH too deep");
+  g.prims64.resize((size_t)n * stride);
+  g.prims32.resize((size_t)n * stride);
+  std::vector<double> plo64((size_t)n * pdim), phi64((size_t)n * pdim);
+  std::vector<float> plo32((size_t)n * pdim), phi32((size_t)n * pdim);
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t src = g.topo.order[i];
+    for (int k = 0; k < stride; ++k) {
+      g.prims64[(size_t)stride * i + k] = raw[(size_t)stride * src + k];
+      g.prims32[(size_t)stride * i + k] = (float)raw[(size_t)stride * src + k];
+    }
+    for (int k = 0; k < pdim; ++k) {
+      double mn = 1e300, mx = -1e300;
+      float mnf = 3e38f, mxf = -3e38f;
+      for (int v = 0; v < nv; ++v) {
+        mn = std::min(mn, g.prims64[(size_t)stride * i + pdim * v + k]);
+        mx = std::max(mx, g.prims64[(size_t)stride * i + pdim * v + k]);
+        mnf = std::min(mnf, g.prims32[(size_t)stride * i + pdim * v + k]);
+        mxf = std::max(mxf, g.prims32[(size_t)stride * i + pdim * v + k]);
+      }
+      plo64[i * pdim + k] = mn;
+      phi64[i * pdim + k] = mx;
+      plo32[i * pdim + k] = mnf;
+      phi32[i * pdim + k] = mxf;
+    }
+  }
+  bvh_child_bounds<double>(g.topo, plo64, phi64, pdim, g.bounds64);
+  bvh_child_bounds<float>(g.topo, plo32, phi32, pdim, g.bounds32);
+  return WOS_OK;
+}
+
+template <typename T>
+const std::vector<T>& pick(const std::vector<float>& f, const std::vector<double>& d) {
+  if constexpr (sizeof(T) == 4) {
+    (void)d;
+    return f;
+  } else {
+    (void)f;
+    return d;
+  }
+}
+
+template <typename T, int DIM>
+void write_nodes(const HostGeometry& g, const std::vector<T>& bounds, BvhNode<T, DIM>* out) {
+  const size_t nn = g.topo.child.size() / 2;
+  for (size_t i = 0; i < nn; ++i) {
+    const T* b = bounds.data() + i * 4 * DIM;
+    for (int s = 0; s < 2; ++s)
+      for (int k = 0; k < DIM; ++k) {
+        out[i].lo[s][k] = b[s * DIM + k];
+        out[i].hi[s][k] = b[2 * DIM + s * DIM + k];
+      }
+    out[i].child[0] = g.topo.child[2 * i];
+    out[i].child[1] = g.topo.child[2 * i + 1];
+  }
+}
+
+// Lays out DevProblem<T> and everything it points to inside the blob; pointers are
+// device addresses (dbase + offset), patched once the device allocation exists.
+template <typename T>
+size_t layout_problem(Blob& blob, const wos_problem_desc& d, const HostGeometry& g, std::vector<std::pair<size_t, size_t>>& ptr_fixups) {
+  const size_t off_struct = blob.alloc(sizeof(DevProblem<T>));
+  DevProblem<T> P;
+  std::memset(&P, 0, sizeof(P));
+  P.dim = d.dim;
+  P.epsilon = (T)d.epsilon;
+  const wos_field_desc* fd[5] = {&d.alpha, &d.psi, &d.sigma, &d.source, &d.boundary};
+  DevField<T>* fp[5] = {&P.alpha, &P.psi, &P.sigma, &P.source, &P.boundary};
+  size_t term_off[5] = {0, 0, 0, 0, 0};
+  for (int k = 0; k < 5; ++k) {
+    *fp[k] = field_header<T>(*fd[k]);
+    if (fp[k]->n > 0) {
+      const std::vector<T> terms = field_terms<T>(*fd[k], d.dim);
+      term_off[k] = blob.alloc(terms.size() * sizeof(T));
+      std::memcpy(blob.host.data() + term_off[k], terms.data(), terms.size() * sizeof(T));
+    }
+  }
+  DevGeometry<T>& G = P.geom;
+  G.kind = d.geometry.kind;
+  for (int i = 0; i < 3; ++i) {
+    G.center[i] = (T)d.geometry.center[i];
+    G.lo[i] = (T)d.geometry.lo[i];
+    G.hi[i] = (T)d.geometry.hi[i];
+  }
+  G.radius = (T)d.geometry.radius;
+  size_t node_off = 0, prim_off = 0;
+  if (g.n_prims > 0) {
+    G.n_prims = (int32_t)g.n_prims;
+    G.n_nodes = (int32_t)(g.topo.child.size() / 2);
+    G.root = g.topo.root;
+    const std::vector<T>& prims = pick<T>(g.prims32, g.prims64);
+    prim_off = blob.alloc(prims.size() * sizeof(T));
+    std::memcpy(blob.host.data() + prim_off, prims.data(), prims.size() * sizeof(T));
+    const std::vector<T>& bounds = pick<T>(g.bounds32, g.bounds64);
+    if (d.dim == 2) {
+      node_off = blob.alloc(std::max<size_t>(1, G.n_nodes) * sizeof(BvhNode<T, 2>));
+      write_nodes<T, 2>(g, bounds, (BvhNode<T, 2>*)(blob.host.data() + node_off));
+    } else {
+      node_off = blob.alloc(std::max<size_t>(1, G.n_nodes) * sizeof(BvhNode<T, 3>));
+      write_nodes<T, 3>(g, bounds, (BvhNode<T, 3>*)(blob.host.data() + node_off));
+    }
+  }
+  std::memcpy(blob.host.data() + off_struct, &P, sizeof(P));
+  // record pointer fields (location in blob, target offset) to patch with the device base
+  auto field_ptr_loc = [&](int k) {
+    const size_t base = off_struct + ((const unsigned char*)fp[k] - (const unsigned char*)&P);
+    return base + offsetof(DevField<T>, terms);
+  };
+  for (int k = 0; k < 5; ++k)
+    if (fp[k]->n > 0) ptr_fixups.push_back({field_ptr_loc(k), term_off[k]});
+  if (g.n_prims > 0) {
+    const size_t gbase = off_struct + offsetof(DevProblem<T>, geom);
+    ptr_fixups.push_back({gbase + offsetof(DevGeometry<T>, nodes), node_off});
+    ptr_fixups.push_back({gbase + offsetof(DevGeometry<T>, prims), prim_off});
+  }
+  return off_struct;
+}
+
+template <typename T>
+void set_sigma_bar(unsigned char* host_struct, double sb) {
+  DevProblem<T>* P = (DevProblem<T>*)host_struct;
+  P->sigma_bar = (T)sb;
+  P->inv_sigma_bar = sb > 0 ? (T)(1.0 / sb) : (T)0;
+  P->sqrt_sigma_bar = (T)std::sqrt(std::max(sb, 0.0));
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+const char* wos_last_error(void) { return g_error.c_str(); }
+
+int wos_version(void) { return 100; }
+
+wos_status wos_problem_create(const wos_problem_desc* desc, int device, wos_problem** out) {
+  if (!desc || !out) return fail(WOS_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  const wos_problem_desc& d = *desc;
+  if (d.dim != 2 && d.dim != 3) return fail(WOS_ERR_INVALID_ARG, "dim must be 2 or 3");
+  if (!(d.epsilon > 0) || !std::isfinite(d.epsilon)) return fail(WOS_ERR_INVALID_ARG, "epsilon must be > 0");
+  if (std::isnan(d.sigma_bar)) return fail(WOS_ERR_INVALID_ARG, "sigma_bar is NaN");
+  if (d.geometry.kind < 0 || d.geometry.kind > 3) return fail(WOS_ERR_INVALID_ARG, "unknown geometry kind");
+  const char* names[5] = {"alpha", "psi", "sigma", "source", "boundary"};
+  const wos_field_desc* fds[5] = {&d.alpha, &d.psi, &d.sigma, &d.source, &d.boundary};
+  for (int k = 0; k < 5; ++k) {
+    const wos_status s = check_field(*fds[k], d.dim, names[k], k >= 3);
+    if (s != WOS_OK) return s;
+  }
+  HostGeometry g;
+  {
+    const wos_status s = build_geometry(d, g);
+    if (s != WOS_OK) return s;
+  }
+  int n_dev = 0;
+  WOS_HIP(hipGetDeviceCount(&n_dev));
+  if (device < 0 || device >= n_dev) return fail(WOS_ERR_DEVICE, "no such device");
+  WOS_HIP(hipSetDevice(device));
+
+  wos_problem* p = new wos_problem();
+  p->device = device;
+  p->dim = d.dim;
+  p->geom = d.geometry.kind;
+  p->epsilon = d.epsilon;
+  p->n_prims = g.n_prims;
+  p->n_nodes = (int64_t)(g.topo.child.size() / 2);
+  p->depth = g.topo.depth;
+  Blob blob;
+  std::vector<std::pair<size_t, size_t>> fix;
+  p->off32 = layout_problem<float>(blob, d, g, fix);
+  p->off64 = layout_problem<double>(blob, d, g, fix);
+  hipError_t e = hipMalloc(&p->dmem, blob.host.size());
+  if (e != hipSuccess) {
+    delete p;
+    return fail(e == hipErrorOutOfMemory ? WOS_ERR_OUT_OF_MEMORY : WOS_ERR_DEVICE, "hipMalloc of problem data failed");
+  }
+  for (const auto& f : fix) {
+    const uint64_t addr = (uint64_t)p->dmem + f.second;
+    std::memcpy(blob.host.data() + f.first, &addr, sizeof(addr));
+  }
+  p->staging = blob.host;
+  auto upload = [&]() { return hipMemcpy(p->dmem, p->staging.data(), p->staging.size(), hipMemcpyHostToDevice); };
+  if ((e = upload()) != hipSuccess) {
+    (void)hipFree(p->dmem);
+    delete p;
+    return fail(WOS_ERR_DEVICE, "upload of problem data failed");
+  }
+  // sample alpha, sigma and sigma' in FP64 over a grid of the bounding box (interior points)
+  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  if (g.kind == WOS_GEOM_BALL) {
+    for (int i = 0; i < d.dim; ++i) {
+      lo[i] = d.geometry.center[i] - d.geometry.radius;
+      hi[i] = d.geometry.center[i] + d.geometry.radius;
+    }
+  } else if (g.kind == WOS_GEOM_BOX) {
+    for (int i = 0; i < d.dim; ++i) {
+      lo[i] = d.geometry.lo[i];
+      hi[i] = d.geometry.hi[i];
+    }
+  } else {
+    for (int i = 0; i < d.dim; ++i) {
+      lo[i] = 1e300;
+      hi[i] = -1e300;
+    }
+    for (int64_t v = 0; v < d.geometry.n_vertices; ++v)
+      for (int i = 0; i < d.dim; ++i) {
+        lo[i] = std::min(lo[i], d.geometry.vertices[v * d.dim + i]);
+        hi[i] = std::max(hi[i], d.geometry.vertices[v * d.dim + i]);
+      }
+  }
+  const int grid = d.sigma_bar_grid > 0 ? d.sigma_bar_grid : (d.dim == 2 ? 1024 : 128);
+  double h[3] = {0, 0, 0};
+  for (int i = 0; i < d.dim; ++i) h[i] = (hi[i] - lo[i]) / grid;
+  const int nblocks = 1024;
+  double* dout = nullptr;
+  std::vector<double> hout((size_t)nblocks * 6);
+  auto cleanup = [&]() {
+    if (dout) (void)hipFree(dout);
+    (void)hipFree(p->dmem);
+    delete p;
+  };
+  if ((e = hipMalloc(&dout, hout.size() * sizeof(double))) != hipSuccess ||
+      (e = launch_sigma_sample(d.dim, g.kind, p->d64(), lo, h, grid, nblocks, dout, 0)) != hipSuccess ||
+      (e = hipMemcpy(hout.data(), dout, hout.size() * sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess) {
+    cleanup();
+    return fail(WOS_ERR_DEVICE, std::string("sigma' sampling failed: ") + hipGetErrorString(e));
+  }
+  (void)hipFree(dout);
+  dout = nullptr;
+  double mn = INFINITY, mx = -INFINITY, amin = INFINITY, smin = INFINITY, bad = 0, cnt = 0;
+  for (int b = 0; b < nblocks; ++b) {
+    mn = std::min(mn, hout[6 * b]);
+    mx = std::max(mx, hout[6 * b + 1]);
+    amin = std::min(amin, hout[6 * b + 2]);
+    smin = std::min(smin, hout[6 * b + 3]);
+    bad += hout[6 * b + 4];
+    cnt += hout[6 * b + 5];
+  }
+  wos_status st = WOS_OK;
+  std::string msg;
+  if (cnt == 0) {
+    st = WOS_ERR_GEOMETRY;
+    msg = "no interior sample points (domain empty or inside-out)";
+  } else if (bad > 0) {
+    st = WOS_ERR_COEFFICIENT;
+    msg = "non-finite alpha or sigma' at sample points";
+  } else if (!(amin > 0)) {
+    st = WOS_ERR_COEFFICIENT;
+    msg = "alpha <= 0 at sample points";
+  } else if (smin < 0 && !d.allow_negative_sigma) {
+    st = WOS_ERR_COEFFICIENT;
+    msg = "sigma < 0 at sample points";
+  }
+  double sb = d.sigma_bar;
+  if (st == WOS_OK) {
+    p->sp_min = mn;
+    p->sp_max = mx;
+    const double scale = std::max(1.0, std::max(std::fabs(mn), std::fabs(mx)));
+    const bool sp_zero = std::fabs(mn) <= 1e-12 * scale && std::fabs(mx) <= 1e-12 * scale && mx - mn <= 1e-12;
+    if (sb < 0) {
+      sb = sp_zero ? 0.0 : std::max(mx, 0.0) - std::min(mn, 0.0);
+    } else if (sb == 0 && !sp_zero) {
+      st = WOS_ERR_COEFFICIENT;
+      msg = "sigma_bar = 0 requires sigma' = 0 everywhere";
+    }
+  }
+  if (st != WOS_OK) {
+    cleanup();
+    return fail(st, msg);
+  }
+  p->sigma_bar = sb;
+  set_sigma_bar<float>(p->staging.data() + p->off32, sb);
+  set_sigma_bar<double>(p->staging.data() + p->off64, sb);
+  if ((e = upload()) != hipSuccess) {
+    cleanup();
+    return fail(WOS_ERR_DEVICE, "upload of sigma_bar failed");
+  }
+  *out = p;
+  return WOS_OK;
+}
+
+wos_status wos_problem_info(const wos_problem* p, double* sp_min, double* sp_max, double* sigma_bar) {
+  if (!p) return fail(WOS_ERR_INVALID_ARG, "null problem");
+  if (sp_min) *sp_min = p->sp_min;
+  if (sp_max) *sp_max = p->sp_max;
+  if (sigma_bar) *sigma_bar = p->sigma_bar;
+  return WOS_OK;
+}
+
+wos_status wos_problem_bvh_info(const wos_problem* p, int64_t* n_nodes, int32_t* depth, int64_t* n_prims) {
+  if (!p) return fail(WOS_ERR_INVALID_ARG, "null problem");
+  if (n_nodes) *n_nodes = p->n_nodes;
+  if (depth) *depth = p->depth;
+  if (n_prims) *n_prims = p->n_prims;
+  return WOS_OK;
+}
+
+wos_status wos_problem_destroy(wos_problem* p) {
+  if (!p) return WOS_OK;
+  (void)hipSetDevice(p->device);
+  if (p->dmem) (void)hipFree(p->dmem);
+  delete p;
+  return WOS_OK;
+}
+
+}  // extern "C"
+
+// ====================================================================== solving
+
+namespace {
+
+struct Schedule {
+  int fp64 = 0, compensated = 0, dim = 2, geom = 0, device = 0;
+  unsigned block = 256, grid = 0;
+  uint32_t tile_walks = 256;
+  uint64_t chunk_walks = 0;   // walks per point per launch
+  uint64_t total_points = 0;
+  int n_launches = 0;
+};
+
+wos_status check_items(const wos_batch_item* items, int n_items, const wos_options* opt, Schedule& s) {
+  if (!items || n_items <= 0 || !opt) return fail(WOS_ERR_INVALID_ARG, "null or empty batch");
+  if (opt->precision < 0 || opt->precision > 2) return fail(WOS_ERR_INVALID_ARG, "unknown precision");
+  if (opt->variant != 0 && opt->variant != 1) return fail(WOS_ERR_INVALID_ARG, "unknown variant");
+  if (opt->walks_per_point == 0) return fail(WOS_ERR_INVALID_ARG, "walks_per_point must be > 0");
+  if (opt->walk_offset + opt->walks_per_point > (1ull << 32)) return fail(WOS_ERR_INVALID_ARG, "walk indices exceed 32 bits");
+  if (opt->russian_roulette && !(opt->ww_lo > 0)) return fail(WOS_ERR_INVALID_ARG, "ww_lo must be > 0");
+  if (opt->block_size != 0 && (opt->block_size < 64 || opt->block_size > 256 || opt->block_size % 64))
+    return fail(WOS_ERR_INVALID_ARG, "block_size must be 64, 128, 192 or 256");
+  const wos_problem* p0 = items[0].problem;
+  if (!p0) return fail(WOS_ERR_INVALID_ARG, "null problem in item 0");
+  s.dim = p0->dim;
+  s.geom = p0->geom;
+  s.device = p0->device;
+  s.fp64 = opt->precision == WOS_FP64;
+  s.compensated = opt->precision == WOS_FP32_COMPENSATED;
+  s.total_points = 0;
+  for (int k = 0; k < n_items; ++k) {
+    const wos_batch_item& it = items[k];
+    if (!it.problem) return fail(WOS_ERR_INVALID_ARG, "null problem in batch");
+    if (it.problem->dim != s.dim || it.problem->geom != s.geom || it.problem->device != s.device)
+      return fail(WOS_ERR_UNSUPPORTED, "batch items must share dim, geometry kind and device");
+    if (it.n_points < 0) return fail(WOS_ERR_INVALID_ARG, "n_points < 0");
+    if (it.n_points >= (1ll << 32)) return fail(WOS_ERR_INVALID_ARG, "n_points must be < 2^32");
+    if (it.n_points > 0 && (!it.points || !it.sum || !it.sum_sq || !it.n_walks || !it.n_steps))
+      return fail(WOS_ERR_INVALID_ARG, "null device pointer in batch item");
+    s.total_points += (uint64_t)it.n_points;
+  }
+  return WOS_OK;
+}
+
+std::mutex g_occ_mutex;
+std::map<std::tuple<int, int, int, int, unsigned>, unsigned> g_occ;
+
+wos_status pick_shape(const wos_options* opt, Schedule& s) {
+  s.block = opt->block_size ? (unsigned)opt->block_size : 256u;
+  s.tile_walks = opt->tile_walks > 0 ? (uint32_t)opt->tile_walks : 256u;
+  const auto key = std::make_tuple(s.device, s.fp64, s.dim, s.geom, s.block);
+  std::lock_guard<std::mutex> lk(g_occ_mutex);
+  auto it = g_occ.find(key);
+  if (it == g_occ.end()) {
+    int per_cu = 0, cus = 0;
+    WOS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, walker_symbol(s.fp64, s.dim, s.geom), (int)s.block, 0));
+    WOS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s.device));
+    unsigned grid = (unsigned)std::max(1, per_cu) * (unsigned)std::max(1, cus);
+    it = g_occ.emplace(key, grid).first;
+  }
+  s.grid = it->second;
+  const uint64_t cap = opt->workspace_bytes ? opt->workspace_bytes : (4ull << 30);
+  const uint64_t per_walk = 16;
+  const uint64_t max_ids = std::max<uint64_t>(cap / per_walk, 1);
+  const uint64_t N = opt->walks_per_point;
+  uint64_t nc = s.total_points ? std::max<uint64_t>(1, max_ids / s.total_points) : N;
+  nc = std::min(nc, N);
+  s.chunk_walks = nc;
+  s.n_launches = (int)((N + nc - 1) / nc);
+  return WOS_OK;
+}
+
+// Per-launch tables: item copies with walks/walk_offset of this chunk, and tiles.
+void build_tables(const wos_batch_item* items, int n_items, const wos_options* opt, const Schedule& s,
+                  uint64_t w0, uint64_t nw, const std::vector<int8_t*>& inside, std::vector<DevItem>& dit,
+                  std::vector<Tile>& tiles) {
+  dit.resize(n_items);
+  tiles.clear();
+  uint64_t wbase = 0, pbase = 0;
+  for (int k = 0; k < n_items; ++k) {
+    const wos_batch_item& it = items[k];
+    DevItem& d = dit[k];
+    std::memset(&d, 0, sizeof(d));
+    d.problem = s.fp64 ? it.problem->d64() : it.problem->d32();
+    d.points = it.points;
+    d.inside = inside[k];
+    d.sum = it.sum;
+    d.sum_sq = it.sum_sq;
+    d.n_walks = it.n_walks;
+    d.n_steps = it.n_steps;
+    d.counters = it.counters;
+    d.n_points = it.n_points;
+    d.walks = nw;
+    d.walk_offset = opt->walk_offset + w0;
+    d.walk_base = wbase;
+    d.point_base = pbase;
+    d.problem_index = it.problem_index;
+    const uint64_t total = (uint64_t)it.n_points * nw;
+    for (uint64_t f = 0; f < total; f += s.tile_walks) {
+      Tile t;
+      t.item = (uint32_t)k;
+      t.count = (uint32_t)std::min<uint64_t>(s.tile_walks, total - f);
+      t.first = wbase + f;
+      tiles.push_back(t);
+    }
+    wbase += total;
+    pbase += (uint64_t)it.n_points;
+  }
+}
+
+struct Workspace {
+  int8_t* inside = nullptr;
+  DevItem* items = nullptr;       // [n_launches][n_items]
+  Tile* tiles = nullptr;          // [n_launches][max tiles]
+  uint32_t* counter = nullptr;
+  LaunchParams* lp = nullptr;
+  double* vals = nullptr;
+  uint32_t* steps = nullptr;
+  uint32_t* trials = nullptr;
+};
+
+}  // namespace
+
+struct wos_plan {
+  Schedule s;
+  std::vector<wos_batch_item> items;
+  wos_options opt;
+  Workspace ws;
+  void* dmem = nullptr;
+  std::vector<uint32_t> n_tiles;      // per launch
+  std::vector<std::vector<DevItem>> dit;
+  size_t max_tiles = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+__attribute__((unused)) size_t align_up(size_t v) { return (v + 255) / 256 * 256; }
+
+// Builds every launch's tables; returns the byte layout of the workspace.
+struct WsLayout {
+  size_t inside, items, tiles, counter, lp, vals, steps, trials, total;
+};
+
+WsLayout ws_layout(const Schedule& s, int n_items, size_t max_tiles) {
+  WsLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  const uint64_t ids = s.total_points * s.chunk_walks;
+  L.inside = take(std::max<uint64_t>(s.total_points, 1));
+  L.items = take(sizeof(DevItem) * (size_t)n_items * s.n_launches);
+  L.tiles = take(sizeof(Tile) * std::max<size_t>(max_tiles, 1) * s.n_launches);
+  L.counter = take(sizeof(uint32_t) * 64);
+  L.lp = take(sizeof(LaunchParams));
+  L.vals = take(sizeof(double) * std::max<uint64_t>(ids, 1));
+  L.steps = take(sizeof(uint32_t) * std::max<uint64_t>(ids, 1));
+  L.trials = take(sizeof(uint32_t) * std::max<uint64_t>(ids, 1));
+  L.total = off;
+  return L;
+}
+
+void ws_bind(Workspace& w, void* base, const WsLayout& L) {
+  unsigned char* b = (unsigned char*)base;
+  w.inside = (int8_t*)(b + L.inside);
+  w.items = (DevItem*)(b + L.items);
+  w.tiles = (Tile*)(b + L.tiles);
+  w.counter = (uint32_t*)(b + L.counter);
+  w.lp = (LaunchParams*)(b + L.lp);
+  w.vals = (double*)(b + L.vals);
+  w.steps = (uint32_t*)(b + L.steps);
+  w.trials = (uint32_t*)(b + L.trials);
+}
+
+// Prepares all tables of a job on the host.
+void prepare(const wos_batch_item* items, int n_items, const wos_options* opt, const Schedule& s,
+             const Workspace& w, std::vector<std::vector<DevItem>>& dit, std::vector<std::vector<Tile>>& tiles) {
+  std::vector<int8_t*> inside(n_items);
+  uint64_t pb = 0;
+  for (int k = 0; k < n_items; ++k) {
+    inside[k] = w.inside + pb;
+    pb += (uint64_t)items[k].n_points;
+  }
+  dit.resize(s.n_launches);
+  tiles.resize(s.n_launches);
+  for (int c = 0; c < s.n_launches; ++c) {
+    const uint64_t w0 = (uint64_t)c * s.chunk_walks;
+    const uint64_t nw = std::min(s.chunk_walks, opt->walks_per_point - w0);
+    build_tables(items, n_items, opt, s, w0, nw, inside, dit[c], tiles[c]);
+  }
+}
+
+// Enqueues classification (once) and, per launch, reset + walker + reduce.
+wos_status enqueue_job(const wos_batch_item* items, int n_items, const wos_options* opt, const Schedule& s,
+                       const Workspace& w, const std::vector<std::vector<DevItem>>& dit,
+                       const std::vector<std::vector<Tile>>& tiles, size_t max_tiles, bool classify, hipStream_t st) {
+  if (classify) {
+    uint64_t pb = 0;
+    for (int k = 0; k < n_items; ++k) {
+      WOS_HIP(launch_classify(s.dim, s.geom, items[k].problem->d64(), items[k].points, items[k].n_points,
+                              w.inside + pb, items[k].counters, st));
+      pb += (uint64_t)items[k].n_points;
+    }
+  }
+  for (int c = 0; c < s.n_launches; ++c) {
+    if (tiles[c].empty()) continue;
+    WOS_HIP(launch_reset(w.counter, st));
+    WalkerLaunch L;
+    L.fp64 = s.fp64;
+    L.dim = s.dim;
+    L.geom = s.geom;
+    L.grid = s.grid;
+    L.block = s.block;
+    L.items = w.items + (size_t)c * n_items;
+    L.tiles = w.tiles + (size_t)c * max_tiles;
+    L.n_tiles = (uint32_t)tiles[c].size();
+    L.tile_counter = w.counter;
+    L.vals = w.vals;
+    L.steps = w.steps;
+    L.trials = w.trials;
+    L.lp = w.lp;
+    L.max_steps = opt->max_steps ? opt->max_steps : 1000000ull;
+    L.variant = opt->variant;
+    L.compensated = s.compensated;
+    L.rr = opt->russian_roulette;
+    L.ww_lo = opt->ww_lo > 0 ? opt->ww_lo : 0.5;
+    WOS_HIP(launch_walker(L, st));
+    for (int k = 0; k < n_items; ++k) WOS_HIP(launch_reduce(dit[c][k], w.vals, w.steps, w.trials, st));
+  }
+  return WOS_OK;
+}
+
+wos_status upload_tables(const Schedule& s, int n_items, const Workspace& w,
+                         const std::vector<std::vector<DevItem>>& dit, const std::vector<std::vector<Tile>>& tiles,
+                         size_t max_tiles, hipStream_t st) {
+  // Pageable host sources: the runtime stages these copies before returning.
+  std::vector<DevItem> all_items((size_t)n_items * s.n_launches);
+  std::vector<Tile> all_tiles(std::max<size_t>(max_tiles, 1) * s.n_launches);
+  for (int c = 0; c < s.n_launches; ++c) {
+    std::copy(dit[c].begin(), dit[c].end(), all_items.begin() + (size_t)c * n_items);
+    std::copy(tiles[c].begin(), tiles[c].end(), all_tiles.begin() + (size_t)c * max_tiles);
+  }
+  WOS_HIP(hipMemcpyAsync(w.items, all_items.data(), all_items.size() * sizeof(DevItem), hipMemcpyHostToDevice, st));
+  WOS_HIP(hipMemcpyAsync(w.tiles, all_tiles.data(), all_tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, st));
+  WOS_HIP(hipStreamSynchronize(st));
+  return WOS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+wos_status wos_solve(const wos_batch_item* items, int32_t n_items, const wos_options* opt, void* stream) {
+  Schedule s;
+  wos_status r = check_items(items, n_items, opt, s);
+  if (r != WOS_OK) return r;
+  WOS_HIP(hipSetDevice(s.device));
+  if ((r = pick_shape(opt, s)) != WOS_OK) return r;
+  if (s.total_points == 0) return WOS_OK;
+  hipStream_t st = (hipStream_t)stream;
+  Workspace w;
+  std::vector<std::vector<DevItem>> dit;
+  std::vector<std::vector<Tile>> tiles;
+  // tables reference workspace addresses, so allocate first
+  size_t max_tiles = 0;
+  {
+    // tile counts only depend on the schedule
+    for (int c = 0; c < s.n_launches; ++c) {
+      const uint64_t w0 = (uint64_t)c * s.chunk_walks;
+      const uint64_t nw = std::min(s.chunk_walks, opt->walks_per_point - w0);
+      size_t nt = 0;
+      for (int k = 0; k < n_items; ++k) nt += (size_t)(((uint64_t)items[k].n_points * nw + s.tile_walks - 1) / s.tile_walks);
+      max_tiles = std::max(max_tiles, nt);
+    }
+  }
+  const WsLayout L = ws_layout(s, n_items, max_tiles);
+  void* base = nullptr;
+  WOS_HIP(hipMallocAsync(&base, L.total, st));
+  ws_bind(w, base, L);
+  prepare(items, n_items, opt, s, w, dit, tiles);
+  r = upload_tables(s, n_items, w, dit, tiles, max_tiles, st);
+  if (r == WOS_OK) {
+    const hipError_t e = launch_set_params(w.lp, opt->seed, 0, st);
+    r = e != hipSuccess ? fail(WOS_ERR_DEVICE, "launch failed") : enqueue_job(items, n_items, opt, s, w, dit, tiles, max_tiles, true, st);
+  }
+  (void)hipFreeAsync(base, st);
+  return r;
+}
+
+wos_status wos_finalize(const double* sum, const double* sum_sq, const uint64_t* n_walks, int64_t n, double* mean,
+                        double* std_err, void* stream) {
+  if (n < 0 || (n > 0 && (!sum || !sum_sq || !n_walks || !mean || !std_err)))
+    return fail(WOS_ERR_INVALID_ARG, "bad finalize arguments");
+  WOS_HIP(launch_finalize(sum, sum_sq, n_walks, n, mean, std_err, (hipStream_t)stream));
+  return WOS_OK;
+}
+
+wos_status wos_plan_create(const wos_batch_item* items, int32_t n_items, const wos_options* opt, void* stream,
+                           wos_plan** out) {
+  if (!out) return fail(WOS_ERR_INVALID_ARG, "null out");
+  *out = nullptr;
+  wos_plan* P = new wos_plan();
+  wos_status r = check_items(items, n_items, opt, P->s);
+  if (r != WOS_OK) {
+    delete P;
+    return r;
+  }
+  (void)hipSetDevice(P->s.device);
+  if ((r = pick_shape(opt, P->s)) != WOS_OK) {
+    delete P;
+    return r;
+  }
+  P->items.assign(items, items + n_items);
+  P->opt = *opt;
+  hipStream_t st = (hipStream_t)stream;
+  const Schedule& s = P->s;
+  size_t max_tiles = 0;
+  for (int c = 0; c < s.n_launches; ++c) {
+    const uint64_t w0 = (uint64_t)c * s.chunk_walks;
+    const uint64_t nw = std::min(s.chunk_walks, opt->walks_per_point - w0);
+    size_t nt = 0;
+    for (int k = 0; k < n_items; ++k) nt += (size_t)(((uint64_t)items[k].n_points * nw + s.tile_walks - 1) / s.tile_walks);
+    max_tiles = std::max(max_tiles, nt);
+  }
+  P->max_tiles = max_tiles;
+  const WsLayout L = ws_layout(s, n_items, max_tiles);
+  hipError_t e = hipMalloc(&P->dmem, L.total);
+  if (e != hipSuccess) {
+    delete P;
+    return fail(e == hipErrorOutOfMemory ? WOS_ERR_OUT_OF_MEMORY : WOS_ERR_DEVICE, "plan workspace allocation failed");
+  }
+  ws_bind(P->ws, P->dmem, L);
+  std::vector<std::vector<Tile>> tiles;
+  prepare(items, n_items, opt, s, P->ws, P->dit, tiles);
+  for (auto& t : tiles) P->n_tiles.push_back((uint32_t)t.size());
+  auto bail = [&](wos_status code, const std::string& m) {
+    if (P->exec) (void)hipGraphExecDestroy(P->exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    (void)hipFree(P->dmem);
+    delete P;
+    return fail(code, m);
+  };
+  if ((r = upload_tables(s, n_items, P->ws, P->dit, tiles, max_tiles, st)) != WOS_OK) return bail(r, g_error);
+  // classification once, outside the graph
+  uint64_t pb = 0;
+  for (int k = 0; k < n_items; ++k) {
+    if ((e = launch_classify(s.dim, s.geom, items[k].problem->d64(), items[k].points, items[k].n_points,
+                             P->ws.inside + pb, items[k].counters, st)) != hipSuccess)
+      return bail(WOS_ERR_DEVICE, "classification launch failed");
+    pb += (uint64_t)items[k].n_points;
+  }
+  // capture reset + walker + reduce of every launch on a private stream
+  hipStream_t cap;
+  if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) return bail(WOS_ERR_DEVICE, "stream creation failed");
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) {
+    (void)hipStreamDestroy(cap);
+    return bail(WOS_ERR_DEVICE, "classification failed");
+  }
+  if ((e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+    (void)hipStreamDestroy(cap);
+    return bail(WOS_ERR_DEVICE, "graph capture failed to start");
+  }
+  r = enqueue_job(items, n_items, opt, s, P->ws, P->dit, tiles, max_tiles, false, cap);
+  const hipError_t ec = hipStreamEndCapture(cap, &P->graph);
+  (void)hipStreamDestroy(cap);
+  if (r != WOS_OK || ec != hipSuccess) return bail(WOS_ERR_DEVICE, "graph capture failed");
+  if ((e = hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0)) != hipSuccess)
+    return bail(WOS_ERR_DEVICE, "graph instantiation failed");
+  *out = P;
+  return WOS_OK;
+}
+
+wos_status wos_plan_launch(wos_plan* P, uint64_t seed, uint64_t walk_offset_add, void* stream) {
+  if (!P) return fail(WOS_ERR_INVALID_ARG, "null plan");
+  if (P->opt.walk_offset + walk_offset_add + P->opt.walks_per_point > (1ull << 32))
+    return fail(WOS_ERR_INVALID_ARG, "walk indices exceed 32 bits");
+  WOS_HIP(hipSetDevice(P->s.device));
+  hipStream_t st = (hipStream_t)stream;
+  WOS_HIP(launch_set_params(P->ws.lp, seed, walk_offset_add, st));
+  WOS_HIP(hipGraphLaunch(P->exec, st));
+  return WOS_OK;
+}
+
+wos_status wos_plan_info(const wos_plan* P, int32_t* block_size, int32_t* tile_walks, int32_t* grid_size,
+                         int32_t* n_launches) {
+  if (!P) return fail(WOS_ERR_INVALID_ARG, "null plan");
+  if (block_size) *block_size = (int32_t)P->s.block;
+  if (tile_walks) *tile_walks = (int32_t)P->s.tile_walks;
+  if (grid_size) *grid_size = (int32_t)P->s.grid;
+  if (n_launches) *n_launches = P->s.n_launches;
+  return WOS_OK;
+}
+
+wos_status wos_plan_destroy(wos_plan* P) {
+  if (!P) return WOS_OK;
+  (void)hipSetDevice(P->s.device);
+  if (P->exec) (void)hipGraphExecDestroy(P->exec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  if (P->dmem) (void)hipFree(P->dmem);
+  delete P;
+  return WOS_OK;
+}
+
+// ====================================================================== diagnostics
+
+wos_status wos_eval_coefficients(const wos_problem* p, const double* points, int64_t n, int32_t precision, double* out,
+                                 void* stream) {
+  if (!p || n < 0 || (n > 0 && (!points || !out))) return fail(WOS_ERR_INVALID_ARG, "bad arguments");
+  if (precision != WOS_FP32 && precision != WOS_FP64) return fail(WOS_ERR_INVALID_ARG, "precision must be FP32 or FP64");
+  WOS_HIP(hipSetDevice(p->device));
+  const int fp64 = precision == WOS_FP64;
+  WOS_HIP(launch_coefficients(fp64, p->dim, fp64 ? p->d64() : p->d32(), points, n, out, (hipStream_t)stream));
+  return WOS_OK;
+}
+
+wos_status wos_eval_distance(const wos_problem* p, const double* points, int64_t n, int32_t precision, double* d,
+                             double* closest, void* stream) {
+  if (!p || n < 0 || (n > 0 && (!points || !d || !closest))) return fail(WOS_ERR_INVALID_ARG, "bad arguments");
+  if (precision != WOS_FP32 && precision != WOS_FP64) return fail(WOS_ERR_INVALID_ARG, "precision must be FP32 or FP64");
+  WOS_HIP(hipSetDevice(p->device));
+  const int fp64 = precision == WOS_FP64;
+  WOS_HIP(launch_distance(fp64, p->dim, p->geom, fp64 ? p->d64() : p->d32(), points, n, d, closest, (hipStream_t)stream));
+  return WOS_OK;
+}
+
+wos_status wos_eval_ball(int32_t dim, int32_t precision, const double* s, int64_t n, double* out, void* stream) {
+  if ((dim != 2 && dim != 3) || n < 0 || (n > 0 && (!s || !out))) return fail(WOS_ERR_INVALID_ARG, "bad arguments");
+  if (precision != WOS_FP32 && precision != WOS_FP64) return fail(WOS_ERR_INVALID_ARG, "precision must be FP32 or FP64");
+  WOS_HIP(launch_ball(precision == WOS_FP64, dim, s, n, out, (hipStream_t)stream));
+  return WOS_OK;
+}
+
+wos_status wos_sample_radius(int32_t dim, int32_t precision, double s, int64_t n, uint64_t seed, double* t,
+                             uint64_t* trials, void* stream) {
+  if ((dim != 2 && dim != 3) || n < 0 || (n > 0 && !t) || !(s >= 0) || !std::isfinite(s))
+    return fail(WOS_ERR_INVALID_ARG, "bad arguments");
+  if (n >= (1ll << 32)) return fail(WOS_ERR_INVALID_ARG, "n must be < 2^32");
+  if (precision != WOS_FP32 && precision != WOS_FP64) return fail(WOS_ERR_INVALID_ARG, "precision must be FP32 or FP64");
+  WOS_HIP(launch_sample(precision == WOS_FP64, dim, s, n, seed, t, trials, (hipStream_t)stream));
+  return WOS_OK;
+}
+
+wos_status wos_philox(const uint32_t* ctr, uint64_t key, int64_t n, uint32_t* out, void* stream) {
+  if (n < 0 || (n > 0 && (!ctr || !out))) return fail(WOS_ERR_INVALID_ARG, "bad arguments");
+  WOS_HIP(launch_philox(ctr, key, n, out, (hipStream_t)stream));
+  return WOS_OK;
+}
+
+wos_status wos_eval_bessel(int32_t which, int32_t precision, const double* x, int64_t n, double* out, void* stream) {
+  if ((which != 0 && which != 1) || n < 0 || (n > 0 && (!x || !out))) return fail(WOS_ERR_INVALID_ARG, "bad arguments");
+  if (precision != WOS_FP32 && precision != WOS_FP64) return fail(WOS_ERR_INVALID_ARG, "precision must be FP32 or FP64");
+  WOS_HIP(launch_bessel(precision == WOS_FP64, which, x, n, out, (hipStream_t)stream));
+  return WOS_OK;
+}
+
+wos_status wos_classify(const wos_problem* p, const double* points, int64_t n, int8_t* inside, void* stream) {
+  if (!p || n < 0 || (n > 0 && (!points || !inside))) return fail(WOS_ERR_INVALID_ARG, "bad arguments");
+  WOS_HIP(hipSetDevice(p->device));
+  WOS_HIP(launch_classify(p->dim, p->geom, p->d64(), points, n, inside, nullptr, (hipStream_t)stream));
+  return WOS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,745 @@
+// Device functions of the delta-tracking walk on spheres (gfx950).
+//
+// Everything here is templated on the arithmetic type T (float or double) so the FP32
+// and FP64 walkers are one source. Citations refer to Sawhney, Seyb, Jarosz, Crane,
+// "Grid-Free Monte Carlo for PDEs with Spatially Varying Coefficients" (2022) and its
+// supplemental material.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "bessel_tables.h"
+#include "wos_types.h"
+
+namespace wos {
+
+// ------------------------------------------------------------------ math wrappers
+
+__device__ __forceinline__ float m_exp(float x) { return __expf(x); }
+__device__ __forceinline__ double m_exp(double x) { return ::exp(x); }
+__device__ __forceinline__ float m_expm1(float x) { return ::expm1f(x); }
+__device__ __forceinline__ double m_expm1(double x) { return ::expm1(x); }
+__device__ __forceinline__ float m_log(float x) { return __logf(x); }
+__device__ __forceinline__ double m_log(double x) { return ::log(x); }
+__device__ __forceinline__ float m_sqrt(float x) { return __fsqrt_rn(x); }
+__device__ __forceinline__ double m_sqrt(double x) { return ::sqrt(x); }
+__device__ __forceinline__ float m_tanh(float x) { return ::tanhf(x); }
+__device__ __forceinline__ double m_tanh(double x) { return ::tanh(x); }
+__device__ __forceinline__ float m_fabs(float x) { return ::fabsf(x); }
+__device__ __forceinline__ double m_fabs(double x) { return ::fabs(x); }
+__device__ __forceinline__ float m_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double m_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// sin and cos of 2*pi*r (r in revolutions)
+__device__ __forceinline__ void m_sincospi2(float r, float* s, float* c) { ::sincospif(2.0f * r, s, c); }
+__device__ __forceinline__ void m_sincospi2(double r, double* s, double* c) { ::sincospi(2.0 * r, s, c); }
+__device__ __forceinline__ void m_sincos(float x, float* s, float* c) { ::sincosf(x, s, c); }
+__device__ __forceinline__ void m_sincos(double x, double* s, double* c) { ::sincos(x, s, c); }
+
+template <typename T> struct Consts;
+template <> struct Consts<float> {
+  static constexpr float kInf = __builtin_huge_valf();
+  static constexpr float kEulerGamma = 0.5772156649015329f;
+};
+template <> struct Consts<double> {
+  static constexpr double kInf = __builtin_huge_val();
+  static constexpr double kEulerGamma = 0.57721566490153286061;
+};
+
+// ------------------------------------------------------------------ Philox4x32-10
+// Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3" (SC'11).
+
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k.x += 0x9E3779B9u;
+      k.y += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c.x;
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
+    const uint32_t lo1 = 0xCD9E8D57u * c.z;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+  }
+  return c;
+}
+
+// Per-walk counter-based stream: key = seed, counter = (block, walk, point, problem).
+struct Rng {
+  uint2 key;
+  uint32_t walk, point, problem;
+  uint32_t block;   // next block index
+  uint4 buf;
+  uint32_t pos;     // words of buf already used (4 = empty)
+
+  __device__ __forceinline__ void init(uint64_t seed, uint32_t w, uint32_t p, uint32_t prob) {
+    key = make_uint2((uint32_t)seed, (uint32_t)(seed >> 32));
+    walk = w;
+    point = p;
+    problem = prob;
+    block = 0;
+    pos = 4;
+  }
+  __device__ __forceinline__ uint32_t next() {
+    if (pos >= 4) {
+      buf = philox4x32_10(make_uint4(block, walk, point, problem), key);
+      ++block;
+      pos = 0;
+    }
+    const uint32_t v = pos == 0 ? buf.x : pos == 1 ? buf.y : pos == 2 ? buf.z : buf.w;
+    ++pos;
+    return v;
+  }
+};
+
+// Uniform in (0, 1]: never zero, so logarithms are finite.
+template <typename T> __device__ __forceinline__ T uniform01(Rng& r);
+template <> __device__ __forceinline__ float uniform01<float>(Rng& r) {
+  return (float)((r.next() >> 8) + 1u) * 5.9604644775390625e-8f;  // 2^-24
+}
+template <> __device__ __forceinline__ double uniform01<double>(Rng& r) {
+  const uint64_t a = r.next();
+  const uint64_t b = r.next();
+  return (double)((((a << 32) | b) >> 11) + 1ull) * 1.1102230246251565404e-16;  // 2^-53
+}
+
+// ------------------------------------------------------------------ modified Bessel functions
+
+template <typename T>
+__device__ __forceinline__ T chebyshev(const double* c, int n, T t) {
+  // Clenshaw recurrence for sum_j c_j T_j(t)
+  T b1 = 0, b2 = 0;
+  const T t2 = t + t;
+  for (int j = n - 1; j >= 1; --j) {
+    const T b0 = m_fma(t2, b1, (T)c[j] - b2);
+    b2 = b1;
+    b1 = b0;
+  }
+  return m_fma(t, b1, (T)c[0] - b2);
+}
+
+template <typename T> struct BesselTerms;
+template <> struct BesselTerms<float> {
+  static constexpr int kSeries = 9, kI0Mid = WOS_I0E_MID_N32, kI0Tail = WOS_I0E_TAIL_N32,
+                       kK0Low = WOS_K0E_LOW_N32, kK0Mid = WOS_K0E_MID_N32, kK0Tail = WOS_K0E_TAIL_N32;
+};
+template <> struct BesselTerms<double> {
+  static constexpr int kSeries = 15, kI0Mid = WOS_I0E_MID_N64, kI0Tail = WOS_I0E_TAIL_N64,
+                       kK0Low = WOS_K0E_LOW_N64, kK0Mid = WOS_K0E_MID_N64, kK0Tail = WOS_K0E_TAIL_N64;
+};
+
+// Power series of I0 and K0 for small x (x <= 2 for I0, x <= 1 for K0):
+//   I0(x) - 1 = sum_{k>=1} q^k/(k!)^2,  q = x^2/4
+//   K0(x) = -(ln(x/2) + gamma_E) I0(x) + sum_{k>=1} q^k/(k!)^2 H_k
+template <typename T>
+__device__ __forceinline__ void bessel_series(T x, T* i0m1, T* k0) {
+  const T q = (T)0.25 * x * x;
+  T term = 1, s_i = 0, s_k = 0, h = 0;
+  for (int k = 1; k <= BesselTerms<T>::kSeries; ++k) {
+    term *= q / (T)(k * k);
+    h += (T)1 / (T)k;
+    s_i += term;
+    s_k = m_fma(term, h, s_k);
+  }
+  *i0m1 = s_i;
+  if (k0) *k0 = -(m_log((T)0.5 * x) + Consts<T>::kEulerGamma) * ((T)1 + s_i) + s_k;
+}
+
+// e^-x I0(x), x >= 0
+template <typename T>
+__device__ T bessel_i0e(T x) {
+  if (x <= (T)2) {
+    T i0m1;
+    bessel_series<T>(x, &i0m1, nullptr);
+    return ((T)1 + i0m1) * m_exp(-x);
+  }
+  if (x <= (T)8) return chebyshev<T>(WOS_I0E_MID, BesselTerms<T>::kI0Mid, (x - (T)5) * (T)(1.0 / 3.0));
+  return chebyshev<T>(WOS_I0E_TAIL, BesselTerms<T>::kI0Tail, (T)16 / x - (T)1) / m_sqrt(x);
+}
+
+// e^x K0(x), x > 0
+template <typename T>
+__device__ T bessel_k0e(T x) {
+  if (x <= (T)1) {
+    T i0m1, k0;
+    bessel_series<T>(x, &i0m1, &k0);
+    return k0 * m_exp(x);
+  }
+  if (x <= (T)3) return chebyshev<T>(WOS_K0E_LOW, BesselTerms<T>::kK0Low, x - (T)2);
+  if (x <= (T)8) return chebyshev<T>(WOS_K0E_MID, BesselTerms<T>::kK0Mid, ((T)2 * x - (T)11) * (T)0.2);
+  return chebyshev<T>(WOS_K0E_TAIL, BesselTerms<T>::kK0Tail, (T)16 / x - (T)1) / m_sqrt(x);
+}
+
+// ------------------------------------------------------------------ ball kernels
+// Centred Green's function of Laplace - sigma_bar on the ball of radius R (supp. Sec. 1.1):
+//   |G| = P_B / sigma_bar with P_B = 1 - 1/I0(s) (2D), 1 - s/sinh(s) (3D), s = R sqrt(sigma_bar),
+// and the Poisson kernel (1 - P_B)/|dB|, so P_B is the probability of the volume term
+// (Sec. 5.1). Small s uses the series of I0 - 1 and sinh(s) - s to avoid cancellation.
+template <typename T, int DIM>
+struct Ball {
+  T pb;        // P_B = sigma_bar |G|
+  T gnorm;     // |G|
+  T c2d;       // 2D: K0(s)/I0(s) (s < 2) or e^{2s} K0(s)/I0(s) = K0e/I0e (s >= 2)
+};
+
+template <typename T, int DIM>
+__device__ __forceinline__ Ball<T, DIM> ball_terms(T R, T s, T inv_sigma_bar, bool harmonic) {
+  Ball<T, DIM> b;
+  b.c2d = 0;
+  if (harmonic) {  // sigma_bar = 0: harmonic Green's function, |G| = R^2/(2n)
+    b.pb = 0;
+    b.gnorm = R * R * (T)(DIM == 2 ? 0.25 : 1.0 / 6.0);
+    return b;
+  }
+  if (DIM == 2) {
+    if (s < (T)2) {
+      T i0m1, k0;
+      if (s <= (T)1) {
+        bessel_series<T>(s, &i0m1, &k0);
+      } else {
+        bessel_series<T>(s, &i0m1, nullptr);
+        k0 = bessel_k0e<T>(s) * m_exp(-s);
+      }
+      const T i0 = (T)1 + i0m1;
+      b.pb = i0m1 / i0;
+      b.c2d = k0 / i0;
+    } else {
+      const T i0e = bessel_i0e<T>(s);
+      b.pb = (T)1 - m_exp(-s) / i0e;
+      b.c2d = bessel_k0e<T>(s) / i0e;
+    }
+  } else {
+    if (s < (T)1) {
+      // (sinh s - s) = s^3 sum_{k>=0} s^{2k} / (2k+3)!
+      const T s2 = s * s;
+      T term = (T)(1.0 / 6.0), acc = term;
+      for (int k = 1; k <= (sizeof(T) == 4 ? 4 : 8); ++k) {
+        term *= s2 / (T)((2 * k + 2) * (2 * k + 3));
+        acc += term;
+      }
+      const T shm = s * s2 * acc;
+      b.pb = shm / (s + shm);
+    } else {
+      // 1 - s/sinh(s) = 1 - 2 s e^{-s} / (1 - e^{-2s})
+      b.pb = (T)1 + (T)2 * s * m_exp(-s) / m_expm1((T)-2 * s);
+    }
+  }
+  b.gnorm = b.pb * inv_sigma_bar;
+  return b;
+}
+
+// Radius fraction t = |y - x|/R of y ~ G(x, .)/|G| (supp. Sec. 1.4). Exact rejection
+// sampling with two proposals whose envelopes follow from two inequalities:
+//  * the screened Green's function never exceeds the harmonic one on the same ball,
+//    so the harmonic radial law (2D: t = sqrt(U1 U2), density 4 t ln(1/t); 3D: Beta(2,2))
+//    is a proposal with acceptance G^s/G^0 = (K0(ts) - c I0(ts))/ln(1/t) (2D) or
+//    sinh(s(1-t)) / ((1-t) sinh s) (3D) and mean cost (R^2/2n)/|G| trials;
+//  * it never exceeds the free-space Green's function, whose radial law is u = ts =
+//    2 sqrt(E1 E2) (2D) or E1 + E2 (3D) with E ~ Exp(1); acceptance is G^s/G^free on
+//    u < s, mean cost 1/P_B trials.
+// The cheaper proposal is used: s < 2 (2D) or s < sqrt 6 (3D) takes the harmonic one.
+// `trials` counts proposals drawn. Acceptance per proposal is >= 0.56, so kMaxTrials is
+// never reached for finite s; a non-finite s returns -1 after kMaxTrials proposals.
+constexpr uint32_t kMaxTrials = 256;
+
+template <typename T, int DIM>
+__device__ __forceinline__ T sample_radius(Rng& rng, T s, const Ball<T, DIM>& b, bool harmonic, uint32_t& trials) {
+  uint32_t budget = kMaxTrials;
+  if (DIM == 2) {
+    if (harmonic) {
+      ++trials;
+      return m_sqrt(uniform01<T>(rng) * uniform01<T>(rng));
+    }
+    if (s < (T)2) {
+      while (budget--) {
+        ++trials;
+        const T t = m_sqrt(uniform01<T>(rng) * uniform01<T>(rng));
+        const T u3 = uniform01<T>(rng);
+        const T x = t * s;
+        T i0m1, k0;
+        if (x <= (T)1) {
+          bessel_series<T>(x, &i0m1, &k0);
+        } else {
+          bessel_series<T>(x, &i0m1, nullptr);
+          k0 = bessel_k0e<T>(x) * m_exp(-x);
+        }
+        const T g = k0 - b.c2d * ((T)1 + i0m1);
+        if (u3 * -m_log(t) <= g) return t;
+      }
+      return (T)-1;
+    }
+    while (budget--) {
+      ++trials;
+      const T e1 = -m_log(uniform01<T>(rng));
+      const T e2 = -m_log(uniform01<T>(rng));
+      const T u3 = uniform01<T>(rng);
+      const T u = (T)2 * m_sqrt(e1 * e2);
+      if (u >= s) continue;
+      const T r = b.c2d * bessel_i0e<T>(u) / bessel_k0e<T>(u) * m_exp((T)2 * (u - s));
+      if (u3 <= (T)1 - r) return u / s;
+    }
+    return (T)-1;
+  } else {
+    if (harmonic || s < (T)2.449489742783178) {
+      while (budget--) {
+        ++trials;
+        // Beta(2,2) = median of three uniforms
+        const T a = uniform01<T>(rng), c = uniform01<T>(rng), d = uniform01<T>(rng);
+        const T t = fmax(fmin(a, c), fmin(fmax(a, c), d));
+        if (harmonic) return t;
+        const T u4 = uniform01<T>(rng);
+        const T omt = (T)1 - t;
+        // sinh(s(1-t)) / ((1-t) sinh s) = e^{-st} (1 - e^{-2s(1-t)}) / ((1 - e^{-2s}) (1-t))
+        const T acc = omt > (T)0 ? m_exp(-s * t) * m_expm1((T)-2 * s * omt) / (m_expm1((T)-2 * s) * omt) : (T)0;
+        if (u4 <= acc) return t;
+      }
+      return (T)-1;
+    }
+    while (budget--) {
+      ++trials;
+      const T u = -m_log(uniform01<T>(rng) * uniform01<T>(rng));
+      const T u3 = uniform01<T>(rng);
+      if (u >= s) continue;
+      // G^s/G^free = 1 - e^{u-s} sinh(u)/sinh(s) = 1 - e^{2(u-s)} (1 - e^{-2u})/(1 - e^{-2s})
+      const T r = m_exp((T)2 * (u - s)) * m_expm1((T)-2 * u) / m_expm1((T)-2 * s);
+      if (u3 <= (T)1 - r) return u / s;
+    }
+    return (T)-1;
+  }
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ void uniform_direction(Rng& rng, T* v) {
+  if (DIM == 2) {
+    T sn, cs;
+    m_sincospi2(uniform01<T>(rng), &sn, &cs);
+    v[0] = cs;
+    v[1] = sn;
+  } else {
+    const T z = (T)1 - (T)2 * uniform01<T>(rng);
+    T sn, cs;
+    m_sincospi2(uniform01<T>(rng), &sn, &cs);
+    const T rr = m_sqrt(fmax((T)0, (T)1 - z * z));
+    v[0] = rr * cs;
+    v[1] = rr * sn;
+    v[2] = z;
+  }
+}
+
+// ------------------------------------------------------------------ coefficient fields
+
+template <typename T, int DIM>
+struct FV {
+  T v;
+  T g[DIM];
+  T lap;
+};
+
+// Base function B of a field at x, with gradient and Laplacian when D is true.
+template <typename T, int DIM, bool D>
+__device__ __forceinline__ FV<T, DIM> field_base(const DevField<T>& f, const T* x) {
+  FV<T, DIM> r;
+  r.v = 0;
+  r.lap = 0;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) r.g[i] = 0;
+  const int base = f.base;
+  if (base == FB_FOURIER) {
+    const T* p = f.terms;
+    for (int j = 0; j < f.n; ++j, p += kTermStride) {
+      T th = p[0] * x[0] + p[1] * x[1];
+      if (DIM == 3) th = m_fma(p[2], x[2], th);
+      T sn, cs;
+      m_sincos(th, &sn, &cs);
+      const T ac = p[3], as = p[4];
+      const T val = ac * cs - as * sn;                 // a cos(th + phi)
+      r.v += val;
+      if (D) {
+        const T dval = -(ac * sn + as * cs);            // -a sin(th + phi)
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) r.g[i] = m_fma(dval, p[i], r.g[i]);
+        r.lap = m_fma(-val, p[5], r.lap);                // Laplacian: -|2 pi k|^2 B_j
+      }
+    }
+  } else if (base == FB_BUMPS) {
+    const T* p = f.terms;
+    for (int j = 0; j < f.n; ++j, p += kTermStride) {
+      T d[DIM], r2 = 0;
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) {
+        d[i] = x[i] - p[i];
+        r2 = m_fma(d[i], d[i], r2);
+      }
+      const T e = p[4] * m_exp(-r2 * p[3]);
+      r.v += e;
+      if (D) {
+        const T iw2 = p[5];
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) r.g[i] = m_fma(-e * iw2, d[i], r.g[i]);
+        r.lap = m_fma(e, iw2 * (r2 * iw2 - (T)DIM), r.lap);
+      }
+    }
+  } else if (base == FB_TANH) {
+    const int ax = (int)f.prm[0];
+    const T iw = f.prm[2];
+    const T th = m_tanh((x[ax] - f.prm[1]) * iw);
+    r.v = (T)0.5 * ((T)1 + th);
+    if (D) {
+      const T sech2 = (T)1 - th * th;
+      r.g[ax] = (T)0.5 * sech2 * iw;
+      r.lap = -th * sech2 * iw * iw;
+    }
+  } else if (base == FB_TANH_DRIFT) {
+    // psi = K [A z - B ln(A cosh z + B sinh z) + B ln A], alpha psi' = omega along the axis
+    const int ax = (int)f.prm[0];
+    const T iw = f.prm[2], A = f.prm[3], B = f.prm[4], K = f.prm[5], lnA = f.prm[6], om = f.prm[7];
+    const T z = (x[ax] - f.prm[1]) * iw;
+    const T az = m_fabs(z);
+    const T sg = z >= (T)0 ? (T)1 : (T)-1;
+    const T lnmix = az + m_log((T)0.5 * (A + sg * B) + (T)0.5 * (A - sg * B) * m_exp((T)-2 * az));
+    r.v = K * (A * z - B * lnmix + B * lnA);
+    if (D) {
+      const T th = m_tanh(z);
+      const T al = A + B * th;
+      const T dal = B * ((T)1 - th * th) * iw;
+      r.g[ax] = om / al;
+      r.lap = -om * dal / (al * al);
+    }
+  }
+  return r;
+}
+
+// Field after its transform (c0 + c1 B or exp(c0 + c1 B)); `log` of the exp transform
+// is available without a logarithm.
+template <typename T, int DIM, bool D>
+__device__ __forceinline__ FV<T, DIM> field_eval(const DevField<T>& f, const T* x, T* log_value = nullptr) {
+  FV<T, DIM> b = field_base<T, DIM, D>(f, x);
+  FV<T, DIM> r;
+  const T c1 = f.c1;
+  if (f.transform == FT_EXP) {
+    const T lv = m_fma(c1, b.v, f.c0);
+    if (log_value) *log_value = lv;
+    r.v = m_exp(lv);
+    if (D) {
+      T gb2 = 0;
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) {
+        r.g[i] = r.v * c1 * b.g[i];
+        gb2 = m_fma(b.g[i], b.g[i], gb2);
+      }
+      r.lap = r.v * (c1 * b.lap + c1 * c1 * gb2);
+    }
+  } else {
+    r.v = m_fma(c1, b.v, f.c0);
+    if (D) {
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) r.g[i] = c1 * b.g[i];
+      r.lap = c1 * b.lap;
+    }
+  }
+  return r;
+}
+
+// Manufactured solutions u (value, gradient, Laplacian).
+template <typename T, int DIM>
+__device__ __forceinline__ FV<T, DIM> solution(int id, const T* x) {
+  FV<T, DIM> u;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) u.g[i] = 0;
+  if (id == SOL_EXPCOS) {
+    const T e = m_exp(x[0]);
+    T sn, cs;
+    m_sincos(x[1], &sn, &cs);
+    u.v = e * cs;
+    u.g[0] = e * cs;
+    u.g[1] = -e * sn;
+    u.lap = 0;
+  } else {
+    u.v = (T)1 + x[0] * x[0] + (T)0.5 * x[0] * x[1];
+    u.g[0] = (T)2 * x[0] + (T)0.5 * x[1];
+    u.g[1] = (T)0.5 * x[0];
+    u.lap = 2;
+  }
+  return u;
+}
+
+// What one step needs at a point after the change of variables (Sec. 4.1, App. A):
+//   gamma = (ln alpha + psi)/2, sigma' = sigma/alpha + Lap(gamma) + |grad gamma|^2 and
+//   f/alpha (the source enters as e^{gamma(y) - gamma(x)} f(y)/alpha(y)).
+template <typename T>
+struct PointCoef {
+  T gamma;
+  T sigma_prime;
+  T f_over_alpha;
+  T alpha;
+};
+
+template <typename T, int DIM, bool WITH_SOURCE>
+__device__ __forceinline__ PointCoef<T> point_coef(const DevProblem<T>& P, const T* x) {
+  // ln alpha with its gradient and Laplacian: grad ln a = grad a / a,
+  // Lap ln a = Lap a / a - |grad ln a|^2 (for the exp transform ln a = c0 + c1 B directly)
+  T lnal;
+  const FV<T, DIM> al = field_eval<T, DIM, true>(P.alpha, x, &lnal);
+  if (P.alpha.transform != FT_EXP) lnal = m_log(al.v);
+  const T inv_al = (T)1 / al.v;
+  T gl[DIM], ga2 = 0;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) {
+    gl[i] = al.g[i] * inv_al;
+    ga2 = m_fma(gl[i], gl[i], ga2);
+  }
+  const T lapl = m_fma(al.lap, inv_al, -ga2);
+  T gg[DIM], lapg;
+  T gamma;
+  if (P.psi.base == FB_NONE && P.psi.transform == FT_AFFINE) {
+    gamma = (T)0.5 * (lnal + P.psi.c0);
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) gg[i] = (T)0.5 * gl[i];
+    lapg = (T)0.5 * lapl;
+  } else {
+    const FV<T, DIM> ps = field_eval<T, DIM, true>(P.psi, x);
+    gamma = (T)0.5 * (lnal + ps.v);
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) gg[i] = (T)0.5 * (gl[i] + ps.g[i]);
+    lapg = (T)0.5 * (lapl + ps.lap);
+  }
+  T g2 = 0;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) g2 = m_fma(gg[i], gg[i], g2);
+  const T sig = field_eval<T, DIM, false>(P.sigma, x).v;
+  PointCoef<T> c;
+  c.gamma = gamma;
+  c.alpha = al.v;
+  c.sigma_prime = m_fma(sig, inv_al, lapg + g2);
+  c.f_over_alpha = 0;
+  if (WITH_SOURCE) {
+    if (P.source.base == FB_MANUFACTURED) {
+      // f = -div(alpha grad u) - omega.grad u + sigma u = -alpha (Lap u + 2 grad(gamma).grad u) + sigma u
+      const FV<T, DIM> u = solution<T, DIM>(P.source.sol, x);
+      T gu = 0;
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) gu = m_fma(gg[i], u.g[i], gu);
+      c.f_over_alpha = -(u.lap + (T)2 * gu) + sig * inv_al * u.v;
+    } else {
+      c.f_over_alpha = field_eval<T, DIM, false>(P.source, x).v * inv_al;
+    }
+  }
+  return c;
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ T boundary_value(const DevProblem<T>& P, const T* x) {
+  if (P.boundary.base == FB_MANUFACTURED) return solution<T, DIM>(P.boundary.sol, x).v;
+  return field_eval<T, DIM, false>(P.boundary, x).v;
+}
+
+// gamma alone (exit points of walks that need the full weight, and the last point)
+template <typename T, int DIM>
+__device__ __forceinline__ T point_gamma(const DevProblem<T>& P, const T* x) {
+  T lnal;
+  const FV<T, DIM> al = field_eval<T, DIM, false>(P.alpha, x, &lnal);
+  if (P.alpha.transform != FT_EXP) lnal = m_log(al.v);
+  T ps = P.psi.c0;
+  if (!(P.psi.base == FB_NONE && P.psi.transform == FT_AFFINE)) ps = field_eval<T, DIM, false>(P.psi, x).v;
+  return (T)0.5 * (lnal + ps);
+}
+
+// ------------------------------------------------------------------ distance queries
+
+template <typename T, int DIM>
+__device__ __forceinline__ T box_dist2(const T* x, const T* lo, const T* hi) {
+  T d2 = 0;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) {
+    const T e = fmax(fmax(lo[i] - x[i], x[i] - hi[i]), (T)0);
+    d2 = m_fma(e, e, d2);
+  }
+  return d2;
+}
+
+template <typename T>
+__device__ __forceinline__ T segment_dist2(const T* x, const T* s, T* tpar) {
+  const T ex = s[2] - s[0], ey = s[3] - s[1];
+  const T px = x[0] - s[0], py = x[1] - s[1];
+  const T l2 = m_fma(ex, ex, ey * ey);
+  T t = l2 > (T)0 ? m_fma(px, ex, py * ey) / l2 : (T)0;
+  t = fmin(fmax(t, (T)0), (T)1);
+  const T dx = px - t * ex, dy = py - t * ey;
+  *tpar = t;
+  return m_fma(dx, dx, dy * dy);
+}
+
+// Closest point of triangle (a, a+e0, a+e1) to p, by Voronoi regions of the
+// barycentric coordinates (Ericson, Real-Time Collision Detection, Sec. 5.1.5).
+template <typename T>
+__device__ __forceinline__ void triangle_closest(const T* p, const T* tri, T* q) {
+  const T* a = tri;
+  const T* ab = tri + 3;
+  const T* ac = tri + 6;
+  T ap[3];
+  for (int i = 0; i < 3; ++i) ap[i] = p[i] - a[i];
+  const T d1 = ab[0] * ap[0] + ab[1] * ap[1] + ab[2] * ap[2];
+  const T d2 = ac[0] * ap[0] + ac[1] * ap[1] + ac[2] * ap[2];
+  if (d1 <= (T)0 && d2 <= (T)0) { for (int i = 0; i < 3; ++i) q[i] = a[i]; return; }
+  T bp[3];
+  for (int i = 0; i < 3; ++i) bp[i] = ap[i] - ab[i];
+  const T d3 = ab[0] * bp[0] + ab[1] * bp[1] + ab[2] * bp[2];
+  const T d4 = ac[0] * bp[0] + ac[1] * bp[1] + ac[2] * bp[2];
+  if (d3 >= (T)0 && d4 <= d3) { for (int i = 0; i < 3; ++i) q[i] = a[i] + ab[i]; return; }
+  const T vc = d1 * d4 - d3 * d2;
+  if (vc <= (T)0 && d1 >= (T)0 && d3 <= (T)0) {
+    const T v = d1 / (d1 - d3);
+    for (int i = 0; i < 3; ++i) q[i] = a[i] + v * ab[i];
+    return;
+  }
+  T cp[3];
+  for (int i = 0; i < 3; ++i) cp[i] = ap[i] - ac[i];
+  const T d5 = ab[0] * cp[0] + ab[1] * cp[1] + ab[2] * cp[2];
+  const T d6 = ac[0] * cp[0] + ac[1] * cp[1] + ac[2] * cp[2];
+  if (d6 >= (T)0 && d5 <= d6) { for (int i = 0; i < 3; ++i) q[i] = a[i] + ac[i]; return; }
+  const T vb = d5 * d2 - d1 * d6;
+  if (vb <= (T)0 && d2 >= (T)0 && d6 <= (T)0) {
+    const T w = d2 / (d2 - d6);
+    for (int i = 0; i < 3; ++i) q[i] = a[i] + w * ac[i];
+    return;
+  }
+  const T va = d3 * d6 - d5 * d4;
+  if (va <= (T)0 && (d4 - d3) >= (T)0 && (d5 - d6) >= (T)0) {
+    const T w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+    for (int i = 0; i < 3; ++i) q[i] = a[i] + ab[i] + w * (ac[i] - ab[i]);
+    return;
+  }
+  const T denom = (T)1 / (va + vb + vc);
+  const T v = vb * denom, w = vc * denom;
+  for (int i = 0; i < 3; ++i) q[i] = a[i] + ab[i] * v + ac[i] * w;
+}
+
+template <typename T>
+__device__ __forceinline__ T triangle_dist2(const T* p, const T* tri) {
+  T q[3];
+  triangle_closest<T>(p, tri, q);
+  const T dx = p[0] - q[0], dy = p[1] - q[1], dz = p[2] - q[2];
+  return m_fma(dx, dx, m_fma(dy, dy, dz * dz));
+}
+
+constexpr int kPrimStride2 = 4;    // segment: x0 y0 x1 y1
+constexpr int kPrimStride3 = 12;   // triangle: a, b - a, c - a, (pad)
+constexpr int kStackDepth = 48;
+
+// Nearest primitive by BVH traversal; returns squared distance and primitive index.
+template <typename T, int DIM>
+__device__ __forceinline__ T bvh_nearest(const DevGeometry<T>& g, const T* x, int* best_prim) {
+  const BvhNode<T, DIM>* nodes = (const BvhNode<T, DIM>*)g.nodes;
+  T best = Consts<T>::kInf;
+  int bp = -1;
+  int stack[kStackDepth];
+  T stack_d[kStackDepth];
+  int sp = 0;
+  int cur = g.root;
+  T cur_d = 0;
+  for (;;) {
+    if (cur_d < best) {
+      if (cur < 0) {
+        const int code = -1 - cur;
+        const int first = code >> 3, cnt = code & 7;
+        for (int k = 0; k < cnt; ++k) {
+          const int pi = first + k;
+          T d2;
+          if (DIM == 2) {
+            T tp;
+            d2 = segment_dist2<T>(x, g.prims + (size_t)pi * kPrimStride2, &tp);
+          } else {
+            d2 = triangle_dist2<T>(x, g.prims + (size_t)pi * kPrimStride3);
+          }
+          if (d2 < best) {
+            best = d2;
+            bp = pi;
+          }
+        }
+      } else {
+        const BvhNode<T, DIM>& n = nodes[cur];
+        const T da = box_dist2<T, DIM>(x, n.lo[0], n.hi[0]);
+        const T db = box_dist2<T, DIM>(x, n.lo[1], n.hi[1]);
+        const int ca = n.child[0], cb = n.child[1];
+        const bool a_first = da <= db;
+        const int near_c = a_first ? ca : cb, far_c = a_first ? cb : ca;
+        const T near_d = a_first ? da : db, far_d = a_first ? db : da;
+        if (far_d < best && sp < kStackDepth) {
+          stack[sp] = far_c;
+          stack_d[sp] = far_d;
+          ++sp;
+        }
+        cur = near_c;
+        cur_d = near_d;
+        continue;
+      }
+    }
+    if (sp == 0) break;
+    --sp;
+    cur = stack[sp];
+    cur_d = stack_d[sp];
+  }
+  *best_prim = bp;
+  return best;
+}
+
+// Distance d from x to the boundary (Alg. 1, first step); prim receives what
+// closest_point needs to recover xbar.
+template <typename T, int DIM, int GEOM>
+__device__ __forceinline__ T boundary_distance(const DevGeometry<T>& g, const T* x, int* prim) {
+  if (GEOM == GK_BALL) {
+    T r2 = 0;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+      const T e = x[i] - g.center[i];
+      r2 = m_fma(e, e, r2);
+    }
+    *prim = 0;
+    return g.radius - m_sqrt(r2);
+  } else if (GEOM == GK_BOX) {
+    T d = Consts<T>::kInf;
+    int best = 0;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+      const T dl = x[i] - g.lo[i], dh = g.hi[i] - x[i];
+      if (dl < d) { d = dl; best = 2 * i; }
+      if (dh < d) { d = dh; best = 2 * i + 1; }
+    }
+    *prim = best;
+    return d;
+  } else {
+    return m_sqrt(bvh_nearest<T, DIM>(g, x, prim));
+  }
+}
+
+template <typename T, int DIM, int GEOM>
+__device__ __forceinline__ void closest_point(const DevGeometry<T>& g, const T* x, int prim, T* xb) {
+  if (GEOM == GK_BALL) {
+    T e[DIM], r2 = 0;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+      e[i] = x[i] - g.center[i];
+      r2 = m_fma(e[i], e[i], r2);
+    }
+    const T r = m_sqrt(r2);
+    const T sc = r > (T)0 ? g.radius / r : (T)0;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) xb[i] = g.center[i] + (r > (T)0 ? sc * e[i] : (i == 0 ? g.radius : (T)0));
+  } else if (GEOM == GK_BOX) {
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) xb[i] = x[i];
+    const int ax = prim >> 1;
+    xb[ax] = (prim & 1) ? g.hi[ax] : g.lo[ax];
+  } else if (DIM == 2) {
+    const T* s = g.prims + (size_t)prim * kPrimStride2;
+    T t;
+    segment_dist2<T>(x, s, &t);
+    xb[0] = s[0] + t * (s[2] - s[0]);
+    xb[1] = s[1] + t * (s[3] - s[1]);
+  } else {
+    triangle_closest<T>(x, g.prims + (size_t)prim * kPrimStride3, xb);
+  }
+}
+
+}  // namespace wos

@@ -1,0 +1,734 @@
+// Kernels of the delta-tracking walk on spheres and their host-side launchers.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "wos_device.h"
+#include "wos_launch.h"
+
+namespace wos {
+
+// ------------------------------------------------------------------ wave helpers (wave64)
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// ------------------------------------------------------------------ walker
+//
+// Persistent kernel. Work is a table of tiles (contiguous walk ids of one item); a
+// wavefront takes one tile at a time with a single atomic and hands its walks to idle
+// lanes (ballot + mbcnt), so lanes whose walk ends pick up a new walk at the next step
+// instead of idling until the longest walk of the wave finishes. A wave only switches
+// to a tile of another item (another problem) once all its lanes are idle, so the
+// problem, and with it every field table and geometry pointer, stays wave-uniform.
+//
+// One walk (Sec. 5.1, supplemental Alg. 1, after the change of variables of Sec. 4.1
+// and App. A) keeps
+//   x, gamma0 = gamma(x0), Pi = product of the null-event factors (1 - sigma'(y)/sigma_bar),
+//   A = running estimate.
+// The weight of the recursive estimate after k balls is W_k = Pi e^{gamma(x_k) - gamma0}
+// (the e^{gamma} ratios of consecutive steps telescope), so the source estimate of ball k,
+// W_k |G| e^{gamma(y) - gamma(x_k)} f(y)/alpha(y), is Pi |G| e^{gamma(y) - gamma0} f(y)/alpha(y)
+// and gamma is only needed at y, at the final point, and at exit points when Russian
+// roulette must know W.
+
+template <typename T>
+struct WalkerArgs {
+  const DevItem* items;
+  const Tile* tiles;
+  uint32_t n_tiles;
+  uint32_t* tile_counter;
+  double* vals;          // [walk id] estimate of the walk
+  uint32_t* steps;       // [walk id] distance queries | flags
+  uint32_t* trials;      // [walk id] radius proposals
+  const LaunchParams* lp;
+  uint64_t max_steps;
+  int32_t variant;
+  int32_t compensated;
+  int32_t rr;
+  T ww_lo;
+};
+
+constexpr uint32_t kFlagCapped = 1u << 31;
+constexpr uint32_t kFlagRR = 1u << 30;
+constexpr uint32_t kStepMask = (1u << 30) - 1;
+
+template <typename T, int DIM, int GEOM>
+__global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a) {
+  const uint32_t lane = __lane_id();
+  const uint64_t seed = a.lp->seed;
+  const uint64_t offset_add = a.lp->walk_offset_add;
+  // ---- wave-uniform scheduling state
+  int cur_item = -1;
+  uint64_t res_next = 0, res_end = 0;
+  int pend_tile = -1;
+  bool queue_done = false;
+  // ---- lane state
+  bool active = false;
+  uint64_t wid = 0;
+  T x[DIM];
+  T gamma0 = 0, gx = 0;
+  bool gx_known = false;
+  T Pi = 1, A = 0, Ac = 0;
+  uint32_t nsteps = 0, ntrials = 0;
+  Rng rng;
+  const DevProblem<T>* Pp = nullptr;
+
+  for (;;) {
+    // ---------------------------------------------------------------- refill idle lanes
+    uint64_t idle = __ballot(!active);
+    while (idle != 0) {
+      if (res_next >= res_end) {
+        if (pend_tile < 0) {
+          if (queue_done) break;
+          uint32_t t = 0;
+          if (lane == 0) t = atomicAdd(a.tile_counter, 1u);
+          t = __shfl(t, 0);
+          if (t >= a.n_tiles) {
+            queue_done = true;
+            break;
+          }
+          pend_tile = uniform_int((int)t);
+        }
+        const Tile tl = a.tiles[pend_tile];
+        if ((int)tl.item != cur_item) {
+          if (idle != ~0ull) break;  // drain the wave before switching problems
+          cur_item = uniform_int((int)tl.item);
+          Pp = (const DevProblem<T>*)a.items[cur_item].problem;
+        }
+        res_next = uniform_u64(tl.first);
+        res_end = uniform_u64(tl.first + tl.count);
+        pend_tile = -1;
+      }
+      const uint32_t n_idle = __popcll(idle);
+      const uint64_t avail = res_end - res_next;
+      const uint32_t take = avail < (uint64_t)n_idle ? (uint32_t)avail : n_idle;
+      const uint32_t rank = lanes_below(idle);
+      if (!active && rank < take) {
+        const DevItem& it = a.items[cur_item];
+        wid = res_next + rank;
+        const uint64_t local = wid - it.walk_base;
+        const uint64_t n = (uint64_t)it.n_points;
+        const uint64_t p = local % n;
+        const uint64_t j = local / n;
+        nsteps = 0;
+        ntrials = 0;
+        if (!it.inside[p]) {
+          a.vals[wid] = __builtin_nan("");
+          a.steps[wid] = 0;
+          a.trials[wid] = 0;
+        } else {
+#pragma unroll
+          for (int i = 0; i < DIM; ++i) x[i] = (T)it.points[p * DIM + i];
+          rng.init(seed, (uint32_t)(it.walk_offset + offset_add + j), (uint32_t)p, it.problem_index);
+          gamma0 = point_gamma<T, DIM>(*Pp, x);
+          gx = gamma0;
+          gx_known = true;
+          Pi = 1;
+          A = 0;
+          Ac = 0;
+          active = true;
+        }
+      }
+      res_next += take;
+      idle = __ballot(!active);
+    }
+    if (__ballot(active) == 0) {
+      if (queue_done) break;
+      continue;
+    }
+    // ---------------------------------------------------------------- one step
+    if (active) {
+      const DevProblem<T>& P = *Pp;
+      bool done = false;
+      uint32_t flag = 0;
+      if (nsteps >= a.max_steps) {
+        done = true;
+        flag = kFlagCapped;
+      } else {
+        int prim;
+        const T d = boundary_distance<T, DIM, GEOM>(P.geom, x, &prim);
+        ++nsteps;
+        if (!(d == d)) {
+          // a non-finite position cannot continue; report the walk as cut
+          done = true;
+          flag = kFlagCapped;
+        } else if (d < P.epsilon) {
+          // epsilon shell: the walk returns g(xbar) (Alg. 1), times its weight
+          T xb[DIM];
+          closest_point<T, DIM, GEOM>(P.geom, x, prim, xb);
+          const T gb = boundary_value<T, DIM>(P, xb);
+          if (!gx_known) gx = point_gamma<T, DIM>(P, x);
+          const T term = Pi * m_exp(gx - gamma0) * gb;
+          if (a.compensated) {
+            const T s = A + term;
+            const T bb = s - A;
+            Ac += (A - (s - bb)) + (term - bb);
+            A = s;
+          } else {
+            A += term;
+          }
+          done = true;
+        } else {
+          const T R = d;
+          const bool harmonic = !(P.sigma_bar > (T)0);
+          const T s = R * P.sqrt_sigma_bar;
+          const Ball<T, DIM> b = ball_terms<T, DIM>(R, s, P.inv_sigma_bar, harmonic);
+          T v[DIM];
+          uniform_direction<T, DIM>(rng, v);
+          T t = sample_radius<T, DIM>(rng, s, b, harmonic, ntrials);
+          if (t < (T)0) {  // sampler gave up (non-finite s): cut the walk
+            done = true;
+            flag = kFlagCapped;
+            t = 0;
+          }
+          T y[DIM];
+#pragma unroll
+          for (int i = 0; i < DIM; ++i) y[i] = m_fma(t * R, v[i], x[i]);
+          const T mu = uniform01<T>(rng);
+          const bool volume = mu <= b.pb;
+          const PointCoef<T> cy = point_coef<T, DIM, true>(P, y);
+          const T src = Pi * m_exp(cy.gamma - gamma0) * cy.f_over_alpha;
+          T term = 0;
+          if (a.variant == 0) term = b.gnorm * src;
+          else if (volume) term = src * P.inv_sigma_bar;
+          if (a.compensated) {
+            const T s2 = A + term;
+            const T bb = s2 - A;
+            Ac += (A - (s2 - bb)) + (term - bb);
+            A = s2;
+          } else {
+            A += term;
+          }
+          if (volume) {
+            // null event: weight (1 - sigma'(y)/sigma_bar) e^{gamma(y) - gamma(x)}, move to y
+            Pi *= (T)1 - cy.sigma_prime * P.inv_sigma_bar;
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) x[i] = y[i];
+            gx = cy.gamma;
+            gx_known = true;
+          } else {
+            // boundary term: uniform point on the sphere, weight e^{gamma(z) - gamma(x)}
+            T vz[DIM];
+            uniform_direction<T, DIM>(rng, vz);
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) x[i] = m_fma(R, vz[i], x[i]);
+            gx_known = false;
+            if (a.rr) {
+              gx = point_gamma<T, DIM>(P, x);
+              gx_known = true;
+            }
+          }
+          if (a.rr) {
+            // static weight window, low side (Sec. 6): survive with probability |W|/w-
+            const T e = m_exp(gx - gamma0);
+            const T W = Pi * e;
+            if (m_fabs(W) < a.ww_lo) {
+              const T u = uniform01<T>(rng);
+              if (u * a.ww_lo <= m_fabs(W)) {
+                Pi = (W < (T)0 ? -a.ww_lo : a.ww_lo) / e;
+              } else {
+                done = true;
+                flag = kFlagRR;
+              }
+            }
+          }
+        }
+      }
+      if (done) {
+        a.vals[wid] = (double)A + (double)Ac;
+        a.steps[wid] = (nsteps & kStepMask) | flag;
+        a.trials[wid] = ntrials;
+        active = false;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ reduce (fixed order)
+
+__global__ void reduce_kernel(DevItem it, const double* vals, const uint32_t* steps, const uint32_t* trials) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t capped = 0, killed = 0, ntr = 0;
+  if (p < it.n_points) {
+    double s = 0, cs = 0, q = 0, cq = 0;
+    uint64_t nst = 0;
+    for (uint64_t j = 0; j < it.walks; ++j) {
+      const uint64_t idx = it.walk_base + j * (uint64_t)it.n_points + (uint64_t)p;
+      const double v = vals[idx];
+      const uint32_t st = steps[idx];
+      nst += st & kStepMask;
+      capped += (st & kFlagCapped) ? 1 : 0;
+      killed += (st & kFlagRR) ? 1 : 0;
+      ntr += trials[idx];
+      // Neumaier summation of v and v^2
+      double t = s + v;
+      cs += fabs(s) >= fabs(v) ? (s - t) + v : (v - t) + s;
+      s = t;
+      const double v2 = v * v;
+      t = q + v2;
+      cq += fabs(q) >= fabs(v2) ? (q - t) + v2 : (v2 - t) + q;
+      q = t;
+    }
+    it.sum[p] += s + cs;
+    it.sum_sq[p] += q + cq;
+    it.n_walks[p] += it.walks;
+    it.n_steps[p] += nst;
+  }
+  if (it.counters) {
+    for (int off = 32; off > 0; off >>= 1) {
+      capped += __shfl_xor(capped, off);
+      killed += __shfl_xor(killed, off);
+      ntr += __shfl_xor(ntr, off);
+    }
+    if (__lane_id() == 0) {
+      if (capped) atomicAdd((unsigned long long*)&it.counters[1], (unsigned long long)capped);
+      if (killed) atomicAdd((unsigned long long*)&it.counters[2], (unsigned long long)killed);
+      if (ntr) atomicAdd((unsigned long long*)&it.counters[3], (unsigned long long)ntr);
+    }
+  }
+}
+
+__global__ void reset_kernel(uint32_t* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+}
+
+__global__ void set_params_kernel(LaunchParams* lp, uint64_t seed, uint64_t add) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    lp->seed = seed;
+    lp->walk_offset_add = add;
+  }
+}
+
+// ------------------------------------------------------------------ inside classification (FP64)
+
+template <int DIM, int GEOM>
+__device__ bool inside_point(const DevGeometry<double>& g, const double* x) {
+#pragma unroll
+  for (int i = 0; i < DIM; ++i)
+    if (!isfinite(x[i])) return false;
+  if (GEOM == GK_BALL) {
+    double r2 = 0;
+    for (int i = 0; i < DIM; ++i) r2 += (x[i] - g.center[i]) * (x[i] - g.center[i]);
+    return r2 < g.radius * g.radius;
+  } else if (GEOM == GK_BOX) {
+    for (int i = 0; i < DIM; ++i)
+      if (!(x[i] > g.lo[i] && x[i] < g.hi[i])) return false;
+    return true;
+  } else if (GEOM == GK_POLYGON) {
+    // even-odd crossing count of a horizontal ray
+    bool in = false;
+    for (int j = 0; j < g.n_prims; ++j) {
+      const double* s = g.prims + (size_t)j * kPrimStride2;
+      const double ay = s[1], by = s[3];
+      if ((ay > x[1]) != (by > x[1])) {
+        const double xi = s[0] + (x[1] - ay) * (s[2] - s[0]) / (by - ay);
+        if (x[0] < xi) in = !in;
+      }
+    }
+    return in;
+  } else {
+    // generalized winding number: sum of signed solid angles / 4 pi
+    // (Van Oosterom and Strackee: tan(Omega/2) = det[a b c] / (|a||b||c| + (a.b)|c| + (a.c)|b| + (b.c)|a|))
+    double w = 0;
+    for (int j = 0; j < g.n_prims; ++j) {
+      const double* t = g.prims + (size_t)j * kPrimStride3;
+      double a[3], b[3], c[3];
+      for (int i = 0; i < 3; ++i) {
+        a[i] = t[i] - x[i];
+        b[i] = t[3 + i] - x[i];
+        c[i] = t[6 + i] - x[i];
+      }
+      const double la = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+      const double lb = sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+      const double lc = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+      const double det = a[0] * (b[1] * c[2] - b[2] * c[1]) - a[1] * (b[0] * c[2] - b[2] * c[0]) +
+                         a[2] * (b[0] * c[1] - b[1] * c[0]);
+      const double ab = a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+      const double ac = a[0] * c[0] + a[1] * c[1] + a[2] * c[2];
+      const double bc = b[0] * c[0] + b[1] * c[1] + b[2] * c[2];
+      w += 2.0 * atan2(det, la * lb * lc + ab * lc + ac * lb + bc * la);
+    }
+    return fabs(w) > 2.0 * M_PI;
+  }
+}
+
+template <int DIM, int GEOM>
+__global__ void classify_kernel(const DevProblem<double>* P, const double* pts, int64_t n, int8_t* inside,
+                                uint64_t* counters) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool bad = false;
+  if (i < n) {
+    const bool in = inside_point<DIM, GEOM>(P->geom, pts + i * DIM);
+    inside[i] = in ? 1 : 0;
+    bad = !in;
+  }
+  if (counters) {
+    const uint64_t m = __ballot(bad);
+    if (__lane_id() == 0 && m) atomicAdd((unsigned long long*)&counters[0], (unsigned long long)__popcll(m));
+  }
+}
+
+// ------------------------------------------------------------------ sigma' sampling (FP64)
+// out per block: [min sigma', max sigma', min alpha, min sigma, #non-finite, #samples]
+
+template <int DIM, int GEOM>
+__global__ void sigma_sample_kernel(const DevProblem<double>* P, double lo0, double lo1, double lo2, double h0,
+                                    double h1, double h2, int grid, double* out) {
+  const double lo[3] = {lo0, lo1, lo2}, h[3] = {h0, h1, h2};
+  double mn = __builtin_huge_val(), mx = -__builtin_huge_val(), amin = __builtin_huge_val(),
+         smin = __builtin_huge_val(), bad = 0, cnt = 0;
+  const int64_t total = DIM == 2 ? (int64_t)grid * grid : (int64_t)grid * grid * grid;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = k;
+    double x[DIM];
+    for (int i = 0; i < DIM; ++i) {
+      x[i] = lo[i] + h[i] * ((double)(r % grid) + 0.5);
+      r /= grid;
+    }
+    if (!inside_point<DIM, GEOM>(P->geom, x)) continue;
+    const PointCoef<double> c = point_coef<double, DIM, false>(*P, x);
+    const double sig = field_eval<double, DIM, false>(P->sigma, x).v;
+    cnt += 1;
+    if (!isfinite(c.sigma_prime) || !isfinite(c.alpha)) {
+      bad += 1;
+      continue;
+    }
+    mn = fmin(mn, c.sigma_prime);
+    mx = fmax(mx, c.sigma_prime);
+    amin = fmin(amin, c.alpha);
+    smin = fmin(smin, sig);
+  }
+  __shared__ double red[6][256];
+  const int t = threadIdx.x;
+  red[0][t] = mn; red[1][t] = mx; red[2][t] = amin; red[3][t] = smin; red[4][t] = bad; red[5][t] = cnt;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      red[0][t] = fmin(red[0][t], red[0][t + s]);
+      red[1][t] = fmax(red[1][t], red[1][t + s]);
+      red[2][t] = fmin(red[2][t], red[2][t + s]);
+      red[3][t] = fmin(red[3][t], red[3][t + s]);
+      red[4][t] += red[4][t + s];
+      red[5][t] += red[5][t + s];
+    }
+    __syncthreads();
+  }
+  if (t == 0)
+    for (int k = 0; k < 6; ++k) out[blockIdx.x * 6 + k] = red[k][0];
+}
+
+// ------------------------------------------------------------------ diagnostics
+
+template <typename T, int DIM>
+__global__ void coef_kernel(const DevProblem<T>* P, const double* pts, int64_t n, double* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T x[DIM];
+  for (int k = 0; k < DIM; ++k) x[k] = (T)pts[i * DIM + k];
+  const PointCoef<T> c = point_coef<T, DIM, true>(*P, x);
+  double* o = out + i * 6;
+  o[0] = c.alpha;
+  o[1] = c.gamma;
+  o[2] = c.sigma_prime;
+  o[3] = (double)c.f_over_alpha * (double)c.alpha;
+  o[4] = (double)m_exp(c.gamma) * (double)c.f_over_alpha;
+  o[5] = boundary_value<T, DIM>(*P, x);
+}
+
+template <typename T, int DIM, int GEOM>
+__global__ void distance_kernel(const DevProblem<T>* P, const double* pts, int64_t n, double* d, double* xb) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T x[DIM], q[DIM];
+  for (int k = 0; k < DIM; ++k) x[k] = (T)pts[i * DIM + k];
+  int prim;
+  d[i] = boundary_distance<T, DIM, GEOM>(P->geom, x, &prim);
+  closest_point<T, DIM, GEOM>(P->geom, x, prim, q);
+  for (int k = 0; k < DIM; ++k) xb[i * DIM + k] = q[k];
+}
+
+template <typename T, int DIM>
+__global__ void ball_kernel(const double* s, int64_t n, double* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  // unit radius: sigma_bar = s^2
+  const T si = (T)s[i];
+  const bool harmonic = !(si > (T)0);
+  const Ball<T, DIM> b = ball_terms<T, DIM>((T)1, si, harmonic ? (T)0 : (T)1 / (si * si), harmonic);
+  out[2 * i] = b.pb;
+  out[2 * i + 1] = b.gnorm;
+}
+
+template <typename T, int DIM>
+__global__ void sample_kernel(double s, int64_t n, uint64_t seed, double* t, uint64_t* trials) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t tr = 0;
+  if (i < n) {
+    Rng rng;
+    rng.init(seed, (uint32_t)i, 0, 0);
+    const T sv = (T)s;
+    const bool harmonic = !(sv > (T)0);
+    const Ball<T, DIM> b = ball_terms<T, DIM>((T)1, sv, harmonic ? (T)0 : (T)1 / (sv * sv), harmonic);
+    t[i] = sample_radius<T, DIM>(rng, sv, b, harmonic, tr);
+  }
+  if (trials) {
+    uint64_t v = tr;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (__lane_id() == 0 && v) atomicAdd((unsigned long long*)trials, (unsigned long long)v);
+  }
+}
+
+__global__ void philox_kernel(const uint32_t* ctr, uint64_t key, int64_t n, uint32_t* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint4 c = make_uint4(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3]);
+  const uint4 r = philox4x32_10(c, make_uint2((uint32_t)key, (uint32_t)(key >> 32)));
+  out[4 * i] = r.x;
+  out[4 * i + 1] = r.y;
+  out[4 * i + 2] = r.z;
+  out[4 * i + 3] = r.w;
+}
+
+template <typename T>
+__global__ void bessel_kernel(int which, const double* x, int64_t n, double* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] = which == 0 ? (double)bessel_i0e<T>((T)x[i]) : (double)bessel_k0e<T>((T)x[i]);
+}
+
+__global__ void finalize_kernel(const double* sum, const double* sum_sq, const uint64_t* nw, int64_t n, double* mean,
+                                double* se) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double N = (double)nw[i];
+  const double m = sum[i] / N;
+  const double var = N > 1 ? fmax(sum_sq[i] / N - m * m, 0.0) * N / (N - 1) : __builtin_nan("");
+  mean[i] = m;
+  se[i] = sqrt(var / N);
+}
+
+// ====================================================================== launchers
+
+static inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+template <typename T, int DIM, int GEOM>
+static hipError_t launch_walker_t(const WalkerLaunch& L, hipStream_t st) {
+  WalkerArgs<T> a;
+  a.items = L.items;
+  a.tiles = L.tiles;
+  a.n_tiles = L.n_tiles;
+  a.tile_counter = L.tile_counter;
+  a.vals = L.vals;
+  a.steps = L.steps;
+  a.trials = L.trials;
+  a.lp = L.lp;
+  a.max_steps = L.max_steps;
+  a.variant = L.variant;
+  a.compensated = L.compensated;
+  a.rr = L.rr;
+  a.ww_lo = (T)L.ww_lo;
+  hipLaunchKernelGGL((walker_kernel<T, DIM, GEOM>), dim3(L.grid), dim3(L.block), 0, st, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_walker_dim(const WalkerLaunch& L, hipStream_t st) {
+  if (L.dim == 2) {
+    switch (L.geom) {
+      case GK_BALL: return launch_walker_t<T, 2, GK_BALL>(L, st);
+      case GK_BOX: return launch_walker_t<T, 2, GK_BOX>(L, st);
+      case GK_POLYGON: return launch_walker_t<T, 2, GK_POLYGON>(L, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (L.geom) {
+    case GK_BALL: return launch_walker_t<T, 3, GK_BALL>(L, st);
+    case GK_BOX: return launch_walker_t<T, 3, GK_BOX>(L, st);
+    case GK_TRIMESH: return launch_walker_t<T, 3, GK_TRIMESH>(L, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_walker(const WalkerLaunch& L, hipStream_t st) {
+  return L.fp64 ? launch_walker_dim<double>(L, st) : launch_walker_dim<float>(L, st);
+}
+
+template <typename T, int DIM, int GEOM>
+static const void* walker_symbol_t() { return (const void*)&walker_kernel<T, DIM, GEOM>; }
+
+const void* walker_symbol(int fp64, int dim, int geom) {
+  if (fp64) {
+    if (dim == 2) return geom == GK_BALL ? walker_symbol_t<double, 2, GK_BALL>() : geom == GK_BOX ? walker_symbol_t<double, 2, GK_BOX>() : walker_symbol_t<double, 2, GK_POLYGON>();
+    return geom == GK_BALL ? walker_symbol_t<double, 3, GK_BALL>() : geom == GK_BOX ? walker_symbol_t<double, 3, GK_BOX>() : walker_symbol_t<double, 3, GK_TRIMESH>();
+  }
+  if (dim == 2) return geom == GK_BALL ? walker_symbol_t<float, 2, GK_BALL>() : geom == GK_BOX ? walker_symbol_t<float, 2, GK_BOX>() : walker_symbol_t<float, 2, GK_POLYGON>();
+  return geom == GK_BALL ? walker_symbol_t<float, 3, GK_BALL>() : geom == GK_BOX ? walker_symbol_t<float, 3, GK_BOX>() : walker_symbol_t<float, 3, GK_TRIMESH>();
+}
+
+hipError_t launch_reduce(const DevItem& it, const double* vals, const uint32_t* steps, const uint32_t* trials,
+                         hipStream_t st) {
+  if (it.n_points == 0) return hipSuccess;
+  hipLaunchKernelGGL(reduce_kernel, dim3(blocks_for(it.n_points, 256)), dim3(256), 0, st, it, vals, steps, trials);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_params(LaunchParams* lp, uint64_t seed, uint64_t walk_offset_add, hipStream_t st) {
+  hipLaunchKernelGGL(set_params_kernel, dim3(1), dim3(64), 0, st, lp, seed, walk_offset_add);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset(uint32_t* counter, hipStream_t st) {
+  hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, st, counter);
+  return hipGetLastError();
+}
+
+template <int DIM, int GEOM>
+static hipError_t classify_t(const void* P, const double* pts, int64_t n, int8_t* inside, uint64_t* counters,
+                             hipStream_t st) {
+  hipLaunchKernelGGL((classify_kernel<DIM, GEOM>), dim3(blocks_for(n, 256)), dim3(256), 0, st,
+                     (const DevProblem<double>*)P, pts, n, inside, counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_classify(int dim, int geom, const void* P64, const double* pts, int64_t n, int8_t* inside,
+                           uint64_t* counters, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  if (dim == 2) {
+    switch (geom) {
+      case GK_BALL: return classify_t<2, GK_BALL>(P64, pts, n, inside, counters, st);
+      case GK_BOX: return classify_t<2, GK_BOX>(P64, pts, n, inside, counters, st);
+      case GK_POLYGON: return classify_t<2, GK_POLYGON>(P64, pts, n, inside, counters, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (geom) {
+    case GK_BALL: return classify_t<3, GK_BALL>(P64, pts, n, inside, counters, st);
+    case GK_BOX: return classify_t<3, GK_BOX>(P64, pts, n, inside, counters, st);
+    case GK_TRIMESH: return classify_t<3, GK_TRIMESH>(P64, pts, n, inside, counters, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int DIM, int GEOM>
+static hipError_t sigma_t(const void* P, const double* lo, const double* h, int grid, int nblocks, double* out,
+                          hipStream_t st) {
+  hipLaunchKernelGGL((sigma_sample_kernel<DIM, GEOM>), dim3(nblocks), dim3(256), 0, st, (const DevProblem<double>*)P,
+                     lo[0], lo[1], lo[2], h[0], h[1], h[2], grid, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sigma_sample(int dim, int geom, const void* P64, const double* lo, const double* h, int grid,
+                               int nblocks, double* out, hipStream_t st) {
+  if (dim == 2) {
+    switch (geom) {
+      case GK_BALL: return sigma_t<2, GK_BALL>(P64, lo, h, grid, nblocks, out, st);
+      case GK_BOX: return sigma_t<2, GK_BOX>(P64, lo, h, grid, nblocks, out, st);
+      case GK_POLYGON: return sigma_t<2, GK_POLYGON>(P64, lo, h, grid, nblocks, out, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (geom) {
+    case GK_BALL: return sigma_t<3, GK_BALL>(P64, lo, h, grid, nblocks, out, st);
+    case GK_BOX: return sigma_t<3, GK_BOX>(P64, lo, h, grid, nblocks, out, st);
+    case GK_TRIMESH: return sigma_t<3, GK_TRIMESH>(P64, lo, h, grid, nblocks, out, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_coefficients(int fp64, int dim, const void* P, const double* pts, int64_t n, double* out,
+                               hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const dim3 g(blocks_for(n, 256)), b(256);
+  if (fp64) {
+    if (dim == 2) hipLaunchKernelGGL((coef_kernel<double, 2>), g, b, 0, st, (const DevProblem<double>*)P, pts, n, out);
+    else hipLaunchKernelGGL((coef_kernel<double, 3>), g, b, 0, st, (const DevProblem<double>*)P, pts, n, out);
+  } else {
+    if (dim == 2) hipLaunchKernelGGL((coef_kernel<float, 2>), g, b, 0, st, (const DevProblem<float>*)P, pts, n, out);
+    else hipLaunchKernelGGL((coef_kernel<float, 3>), g, b, 0, st, (const DevProblem<float>*)P, pts, n, out);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t distance_t(int dim, int geom, const void* P, const double* pts, int64_t n, double* d, double* xb,
+                             hipStream_t st) {
+  const dim3 g(blocks_for(n, 256)), b(256);
+  const DevProblem<T>* p = (const DevProblem<T>*)P;
+  if (dim == 2) {
+    if (geom == GK_BALL) hipLaunchKernelGGL((distance_kernel<T, 2, GK_BALL>), g, b, 0, st, p, pts, n, d, xb);
+    else if (geom == GK_BOX) hipLaunchKernelGGL((distance_kernel<T, 2, GK_BOX>), g, b, 0, st, p, pts, n, d, xb);
+    else hipLaunchKernelGGL((distance_kernel<T, 2, GK_POLYGON>), g, b, 0, st, p, pts, n, d, xb);
+  } else {
+    if (geom == GK_BALL) hipLaunchKernelGGL((distance_kernel<T, 3, GK_BALL>), g, b, 0, st, p, pts, n, d, xb);
+    else if (geom == GK_BOX) hipLaunchKernelGGL((distance_kernel<T, 3, GK_BOX>), g, b, 0, st, p, pts, n, d, xb);
+    else hipLaunchKernelGGL((distance_kernel<T, 3, GK_TRIMESH>), g, b, 0, st, p, pts, n, d, xb);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_distance(int fp64, int dim, int geom, const void* P, const double* pts, int64_t n, double* d,
+                           double* xb, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  return fp64 ? distance_t<double>(dim, geom, P, pts, n, d, xb, st) : distance_t<float>(dim, geom, P, pts, n, d, xb, st);
+}
+
+hipError_t launch_ball(int fp64, int dim, const double* s, int64_t n, double* out, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const dim3 g(blocks_for(n, 256)), b(256);
+  if (fp64) {
+    if (dim == 2) hipLaunchKernelGGL((ball_kernel<double, 2>), g, b, 0, st, s, n, out);
+    else hipLaunchKernelGGL((ball_kernel<double, 3>), g, b, 0, st, s, n, out);
+  } else {
+    if (dim == 2) hipLaunchKernelGGL((ball_kernel<float, 2>), g, b, 0, st, s, n, out);
+    else hipLaunchKernelGGL((ball_kernel<float, 3>), g, b, 0, st, s, n, out);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sample(int fp64, int dim, double s, int64_t n, uint64_t seed, double* t, uint64_t* trials,
+                         hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const dim3 g(blocks_for(n, 256)), b(256);
+  if (fp64) {
+    if (dim == 2) hipLaunchKernelGGL((sample_kernel<double, 2>), g, b, 0, st, s, n, seed, t, trials);
+    else hipLaunchKernelGGL((sample_kernel<double, 3>), g, b, 0, st, s, n, seed, t, trials);
+  } else {
+    if (dim == 2) hipLaunchKernelGGL((sample_kernel<float, 2>), g, b, 0, st, s, n, seed, t, trials);
+    else hipLaunchKernelGGL((sample_kernel<float, 3>), g, b, 0, st, s, n, seed, t, trials);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_philox(const uint32_t* ctr, uint64_t key, int64_t n, uint32_t* out, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(philox_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, ctr, key, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_bessel(int fp64, int which, const double* x, int64_t n, double* out, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const dim3 g(blocks_for(n, 256)), b(256);
+  if (fp64) hipLaunchKernelGGL((bessel_kernel<double>), g, b, 0, st, which, x, n, out);
+  else hipLaunchKernelGGL((bessel_kernel<float>), g, b, 0, st, which, x, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double* sum, const double* sum_sq, const uint64_t* nw, int64_t n, double* mean,
+                           double* se, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(finalize_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, sum, sum_sq, nw, n, mean, se);
+  return hipGetLastError();
+}
+
+}  // namespace wos

@@ -1,0 +1,54 @@
+// Host-side launchers of the kernels in wos_kernels.hip (internal interface).
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+#include "wos_types.h"
+
+namespace wos {
+
+struct WalkerLaunch {
+  int fp64;
+  int dim;
+  int geom;
+  unsigned grid;
+  unsigned block;
+  const DevItem* items;
+  const Tile* tiles;
+  uint32_t n_tiles;
+  uint32_t* tile_counter;
+  double* vals;
+  uint32_t* steps;
+  uint32_t* trials;
+  const LaunchParams* lp;
+  uint64_t max_steps;
+  int variant;
+  int compensated;
+  int rr;
+  double ww_lo;
+};
+
+hipError_t launch_walker(const WalkerLaunch& L, hipStream_t st);
+const void* walker_symbol(int fp64, int dim, int geom);
+hipError_t launch_reduce(const DevItem& it, const double* vals, const uint32_t* steps, const uint32_t* trials,
+                         hipStream_t st);
+hipError_t launch_reset(uint32_t* counter, hipStream_t st);
+hipError_t launch_set_params(LaunchParams* lp, uint64_t seed, uint64_t walk_offset_add, hipStream_t st);
+hipError_t launch_classify(int dim, int geom, const void* P64, const double* pts, int64_t n, int8_t* inside,
+                           uint64_t* counters, hipStream_t st);
+hipError_t launch_sigma_sample(int dim, int geom, const void* P64, const double* lo, const double* h, int grid,
+                               int nblocks, double* out, hipStream_t st);
+hipError_t launch_coefficients(int fp64, int dim, const void* P, const double* pts, int64_t n, double* out,
+                               hipStream_t st);
+hipError_t launch_distance(int fp64, int dim, int geom, const void* P, const double* pts, int64_t n, double* d,
+                           double* xb, hipStream_t st);
+hipError_t launch_ball(int fp64, int dim, const double* s, int64_t n, double* out, hipStream_t st);
+hipError_t launch_sample(int fp64, int dim, double s, int64_t n, uint64_t seed, double* t, uint64_t* trials,
+                         hipStream_t st);
+hipError_t launch_philox(const uint32_t* ctr, uint64_t key, int64_t n, uint32_t* out, hipStream_t st);
+hipError_t launch_bessel(int fp64, int which, const double* x, int64_t n, double* out, hipStream_t st);
+hipError_t launch_finalize(const double* sum, const double* sum_sq, const uint64_t* nw, int64_t n, double* mean,
+                           double* se, hipStream_t st);
+
+}  // namespace wos

@@ -1,0 +1,96 @@
+// Device-side data layout of a compiled problem (shared by host set-up and kernels).
+#pragma once
+#include <cstdint>
+
+namespace wos {
+
+enum FieldBase : int32_t { FB_NONE = 0, FB_FOURIER = 1, FB_BUMPS = 2, FB_TANH = 3, FB_TANH_DRIFT = 4, FB_MANUFACTURED = 5 };
+enum FieldTransform : int32_t { FT_AFFINE = 0, FT_EXP = 1 };
+enum GeomKind : int32_t { GK_BALL = 0, GK_BOX = 1, GK_POLYGON = 2, GK_TRIMESH = 3 };
+enum SolutionId : int32_t { SOL_EXPCOS = 1, SOL_QUADRATIC = 2 };
+
+// Six numbers per term, in the precision of the walker:
+//   fourier: 2 pi k0, 2 pi k1, 2 pi k2, a cos(phi), a sin(phi), |2 pi k|^2
+//            (a cos(2 pi k.x + phi) = ac cos(th) - as sin(th), th = 2 pi k.x)
+//   bumps:   c0, c1, c2, 1/(2 w^2), amp, 1/w^2
+constexpr int kTermStride = 6;
+
+template <typename T>
+struct DevField {
+  int32_t base;
+  int32_t transform;
+  int32_t n;         // number of terms
+  int32_t sol;       // manufactured solution id
+  T c0, c1;          // value = c0 + c1 B  or  exp(c0 + c1 B)
+  const T* terms;    // [n][kTermStride]
+  T prm[8];          // tanh: axis, x0, 1/width ; tanh_drift: axis, x0, 1/width, A, B, omega*width/(A^2-B^2), ln A, omega
+};
+
+// Binary BVH node that stores the bounds of both children, so a visit tests both
+// boxes with one load. A child reference c >= 0 is an inner node index; c < 0 encodes
+// a leaf: -1 - c = (first primitive << 3) | count, count in 1..7.
+template <typename T, int DIM>
+struct BvhNode {
+  T lo[2][DIM];
+  T hi[2][DIM];
+  int32_t child[2];
+};
+
+template <typename T>
+struct DevGeometry {
+  int32_t kind;
+  int32_t n_prims;
+  int32_t n_nodes;
+  int32_t root;          // root child reference (same encoding as BvhNode::child)
+  T center[3];
+  T radius;
+  T lo[3];
+  T hi[3];
+  const void* nodes;     // BvhNode<T, DIM>[n_nodes]
+  const T* prims;        // polygon: [n][4] (x0, y0, x1, y1); trimesh: [n][12] (a, b-a, c-a, n) with padding
+};
+
+template <typename T>
+struct DevProblem {
+  int32_t dim;
+  int32_t pad;
+  DevGeometry<T> geom;
+  DevField<T> alpha, psi, sigma, source, boundary;
+  T epsilon;
+  T sigma_bar;
+  T inv_sigma_bar;
+  T sqrt_sigma_bar;
+};
+
+// One query batch of a launch (device copy).
+struct DevItem {
+  const void* problem;       // DevProblem<T>* in the walker's precision
+  const double* points;      // [n_points][dim]
+  const int8_t* inside;      // [n_points] classification (1 = interior)
+  double* sum;
+  double* sum_sq;
+  uint64_t* n_walks;
+  uint64_t* n_steps;
+  uint64_t* counters;        // [4] or null
+  int64_t n_points;
+  uint64_t walks;            // walks per point in this launch
+  uint64_t walk_offset;      // first global walk index of this launch
+  uint64_t walk_base;        // offset of this item in the launch's walk-id space
+  uint64_t point_base;       // offset of this item in the launch's point space
+  uint32_t problem_index;
+  uint32_t pad;
+};
+
+// A contiguous range of walk ids of one item; waves take whole tiles.
+struct Tile {
+  uint32_t item;
+  uint32_t count;
+  uint64_t first;            // first walk id (launch space)
+};
+
+struct LaunchParams {
+  uint64_t seed;
+  uint64_t walk_offset_add;  // added to every item's walk_offset (plan relaunches)
+};
+
+}  // namespace wos

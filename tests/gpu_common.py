@@ -1,0 +1,38 @@
+"""Shared helpers of the GPU tests (device tensors, problems, oracle references)."""
+import numpy as np
+
+from paper_2201_13240_amd import workloads as WL
+
+
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        import pytest
+        pytest.skip("no GPU")
+    return torch
+
+
+def dev(a, dtype=None):
+    torch = torch_cuda()
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype or torch.float64, device="cuda")
+
+
+def interior_samples(prob, n=256):
+    g = WL.grid_points(n, -2.0, 2.0) if prob["dim"] == 2 else None
+    if prob["dim"] == 2:
+        return g[WL.inside_mask(prob["geometry"], g)]
+    rng = np.random.default_rng(0)
+    return WL.sample_inside(rng, prob["geometry"], 3, 20000)
+
+
+def gpu_solve(W, prob_handle, pts, walks, precision="fp32", seed=0, **kw):
+    torch = torch_cuda()
+    P = dev(pts)
+    acc = W.Accumulators(P.shape[0])
+    W.solve([(prob_handle, P, acc, kw.pop("problem_index", 0))], W.options(precision=precision, walks=walks,
+                                                                             seed=seed, **kw))
+    mean, se = W.finalize(acc)
+    torch.cuda.synchronize()
+    return {"mean": mean.cpu().numpy(), "se": se.cpu().numpy(), "steps": acc.n_steps.cpu().numpy(),
+            "n": acc.n_walks.cpu().numpy(), "counters": acc.counters.cpu().numpy(),
+            "sum": acc.sum.cpu().numpy()}

@@ -1,0 +1,85 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol declared in
+include/wos.h, and rejects invalid descriptors with the documented status codes
+before touching a device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "wos.h")).read()
+    return sorted(set(re.findall(r"\b(wos_[a-z_0-9]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def W():
+    from paper_2201_13240_amd import wos
+    if not os.path.exists(wos.LIB_PATH):
+        pytest.fail("libwos.so is not built (run __graft_entry__.build())")
+    wos.lib()
+    return wos
+
+
+def test_exports_every_declared_symbol(W):
+    L = W.lib()
+    declared = _declared()
+    assert len(declared) >= 19
+    for name in declared:
+        assert hasattr(L, name), name
+    assert sorted(W.EXPORTS) == declared
+
+
+def test_version_and_struct_sizes(W):
+    assert W.lib().wos_version() >= 100
+    # wos_options / wos_batch_item layouts as declared in the header
+    assert C.sizeof(W.Options) == 80
+    assert C.sizeof(W.BatchItem) == 72
+
+
+def _base_problem():
+    from paper_2201_13240_amd import workloads as WL
+    return WL.config1()["problems"][0]
+
+
+def _create(W, prob, **kw):
+    with pytest.raises(W.WosError) as e:
+        W.Problem(prob, **kw)
+    return e.value.status
+
+
+def test_invalid_descriptors_are_rejected(W):
+    from paper_2201_13240_amd import workloads as WL
+    p = dict(_base_problem())
+    p["epsilon"] = 0.0
+    assert _create(W, p) == 1                      # WOS_ERR_INVALID_ARG
+    c = WL.field_const(1.0)
+    p = WL.make_problem(4, WL.geom_ball([0, 0], 1.0), c, c, c, c, c)
+    assert _create(W, p) == 1
+    p = dict(_base_problem())
+    p["geometry"] = WL.geom_ball([0, 0], -1.0)
+    assert _create(W, p) == 2                      # WOS_ERR_GEOMETRY
+    p = dict(_base_problem())
+    p["geometry"] = WL.geom_polygon(np.zeros((2, 2)))
+    assert _create(W, p) == 2
+    p = dict(_base_problem())
+    p["alpha"] = WL.field_bumps([[0, 0]], [0.0], [1.0])   # zero width
+    assert _create(W, p) == 1
+    p = dict(_base_problem())
+    p["alpha"] = WL.field_manufactured("expcos")   # manufactured only for f and g
+    assert _create(W, p) == 1
+    c = WL.field_const(1.0)
+    p = WL.make_problem(3, WL.geom_trimesh(np.zeros((4, 3)), np.array([[0, 1, 9]] * 4)), c, c, c, c, c)
+    assert _create(W, p) == 2                      # triangle index out of range
+
+
+def test_solve_rejects_bad_batches_without_device(W):
+    o = W.options(walks=0)
+    assert W.lib().wos_solve(None, 0, C.byref(o), None) == 1
+    items = (W.BatchItem * 1)()
+    assert W.lib().wos_solve(items, 1, C.byref(o), None) == 1   # null problem / zero walks
+    assert W.lib().wos_last_error()

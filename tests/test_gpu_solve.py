@@ -1,0 +1,217 @@
+"""GPU walk-on-spheres parity: the HIP walker (through the C ABI) against closed-form
+solutions and against the FP64 CPU oracle on the same seeded inputs, per point within
+the statistical bound of tests/parity.py (4 combined standard errors with a
+multiple-comparison allowance)."""
+import math
+
+import numpy as np
+import pytest
+from scipy import special
+
+from paper_2201_13240_amd import workloads as WL
+from tests.gpu_common import dev, gpu_solve, torch_cuda
+from tests.parity import assert_parity
+
+pytestmark = pytest.mark.gpu
+
+Z = WL.field_const(0.0)
+ONE = WL.field_const(1.0)
+
+
+@pytest.fixture(scope="module")
+def W():
+    torch_cuda()
+    from paper_2201_13240_amd import wos
+    wos.lib()
+    return wos
+
+
+def u_expcos(p):
+    return np.exp(p[:, 0]) * np.cos(p[:, 1])
+
+
+def harmonic(geom, dim, eps=1e-4):
+    return WL.make_problem(dim, geom, ONE, Z, Z, Z, WL.field_manufactured("expcos"), eps)
+
+
+HARMONIC = {
+    "disk": lambda: harmonic(WL.geom_ball([0, 0], 1.0), 2),
+    "box": lambda: harmonic(WL.geom_box([0, 0], [1, 0.6]), 2),
+    "star256": lambda: harmonic(WL.star_polygon(np.random.default_rng(7), 256), 2),
+    "ball3": lambda: harmonic(WL.geom_ball([0, 0, 0], 1.0), 3),
+    "ico1280": lambda: harmonic(WL.icosphere(np.random.default_rng(8), 3, 0.1), 3),
+}
+
+
+@pytest.mark.parametrize("name", sorted(HARMONIC))
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("sigma_bar", [0.0, 9.0])
+def test_harmonic_data_reproduced(W, name, precision, sigma_bar):
+    prob = HARMONIC[name]()
+    h = W.Problem(prob, sigma_bar=sigma_bar)
+    pts = WL.sample_inside(np.random.default_rng(1), prob["geometry"], prob["dim"], 200)
+    r = gpu_solve(W, h, pts, 4000, precision, seed=3)
+    assert np.all(r["n"] == 4000) and r["counters"][:3].sum() == 0
+    assert_parity(r["mean"], r["se"], u_expcos(pts), 0 * pts[:, 0], f"{name}/{precision}/{sigma_bar}")
+
+
+def screened_exact(dim, r, sigma, f0):
+    k = math.sqrt(sigma)
+    if dim == 2:
+        return f0 / sigma * (1 - special.i0(k * r) / special.i0(k))
+    return f0 / sigma * (1 - np.sinh(k * r) / (np.maximum(r, 1e-12) * np.sinh(k)))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("ratio", [1.0, 3.0])
+def test_constant_sigma_screened_poisson(W, dim, precision, ratio):
+    sigma, f0 = 30.0, 5.0
+    prob = WL.make_problem(dim, WL.geom_ball(np.zeros(dim), 1.0), ONE, Z, WL.field_const(sigma),
+                           WL.field_const(f0), Z, 1e-4)
+    h = W.Problem(prob, sigma_bar=sigma * ratio)
+    pts = WL.sample_inside(np.random.default_rng(2), prob["geometry"], dim, 200)
+    r = gpu_solve(W, h, pts, 4000, precision, seed=4)
+    ex = screened_exact(dim, np.linalg.norm(pts, axis=1), sigma, f0)
+    assert_parity(r["mean"], r["se"], ex, 0 * ex, f"screened {dim}D {precision} x{ratio}")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32c"])
+def test_config1_matches_oracle_and_solution(W, oracle, precision):
+    """Unit disk, alpha = 1 + sin(2 pi x) sin(2 pi y)/2, u = e^x cos y: the full 812-point grid
+    at 128 walks against the oracle, and at 4096 walks against the exact solution."""
+    c = WL.config1()
+    prob, pts = c["problems"][0], c["points"][0]
+    assert pts.shape[0] == 812
+    h = W.Problem(prob, sigma_bar_grid=512)
+    sb = h.sigma_bar
+    r = gpu_solve(W, h, pts, 128, precision, seed=0)
+    o = oracle.solve(prob, pts, 128, sb, seed=1000)
+    assert_parity(r["mean"], r["se"], o["mean"], o["se"], f"cfg1 vs oracle {precision}")
+    r2 = gpu_solve(W, h, pts, 4096, precision, seed=5)
+    assert_parity(r2["mean"], r2["se"], u_expcos(pts), 0 * pts[:, 0], f"cfg1 vs exact {precision}")
+
+
+def test_config2_subset_matches_oracle(W, oracle):
+    c = WL.config2(n_grid=128)
+    prob, pts = c["problems"][0], c["points"][0]
+    sel = pts[np.random.default_rng(0).choice(pts.shape[0], 96, replace=False)]
+    h = W.Problem(prob)
+    sb = h.sigma_bar
+    o = oracle.solve(prob, sel, 512, sb, seed=11)
+    for precision in ("fp64", "fp32"):
+        r = gpu_solve(W, h, sel, 4096, precision, seed=12)
+        assert_parity(r["mean"], r["se"], o["mean"], o["se"], f"cfg2 {precision}")
+
+
+def test_config3_shape_subset_matches_oracle(W, oracle):
+    """3D perturbed icosphere (subdivision 3 keeps the brute-force oracle fast) with the
+    32-mode alpha and sigma of the 3D workload."""
+    c = WL.config3(n_grid=32, subdiv=3)
+    prob, pts = c["problems"][0], c["points"][0]
+    sel = pts[np.random.default_rng(1).choice(pts.shape[0], 48, replace=False)]
+    h = W.Problem(prob)
+    o = oracle.solve(prob, sel, 256, h.sigma_bar, seed=13)
+    r = gpu_solve(W, h, sel, 4096, "fp32", seed=14)
+    assert_parity(r["mean"], r["se"], o["mean"], o["se"], "cfg3-shape fp32")
+
+
+def test_config5_subset_with_roulette_matches_oracle(W, oracle):
+    c = WL.config5(n_grid=16)
+    prob, pts = c["problems"][0], c["points"][0]
+    sel = pts[::5]
+    h = W.Problem(prob)
+    sb = h.sigma_bar
+    o = oracle.solve(prob, sel, 256, sb, seed=15, russian_roulette=True)
+    for precision in ("fp64", "fp32c"):
+        r = gpu_solve(W, h, sel, 2048, precision, seed=16, russian_roulette=True)
+        assert r["counters"][2] > 0
+        assert_parity(r["mean"], r["se"], o["mean"], o["se"], f"cfg5 RR {precision}")
+
+
+def test_equation_28_variant_agrees(W):
+    c = WL.config1(n_grid=16)
+    prob, pts = c["problems"][0], c["points"][0]
+    h = W.Problem(prob)
+    a = gpu_solve(W, h, pts, 8192, "fp64", seed=21)
+    b = gpu_solve(W, h, pts, 8192, "fp64", seed=22, variant=1)
+    assert_parity(a["mean"], a["se"], b["mean"], b["se"], "Alg. 1 vs eq. 28")
+
+
+def test_deterministic_and_offsets_compose(W):
+    c = WL.config1(n_grid=16)
+    prob, pts = c["problems"][0], c["points"][0]
+    h = W.Problem(prob)
+    a = gpu_solve(W, h, pts, 256, "fp32", seed=7)
+    b = gpu_solve(W, h, pts, 256, "fp32", seed=7)
+    assert np.array_equal(a["sum"], b["sum"]) and np.array_equal(a["steps"], b["steps"])
+    # 100 walks then 156 more (walk_offset = 100) reproduce the 256 walks up to summation order
+    torch = torch_cuda()
+    P = dev(pts)
+    acc = W.Accumulators(P.shape[0])
+    W.solve([(h, P, acc, 0)], W.options(precision="fp32", walks=100, seed=7))
+    W.solve([(h, P, acc, 0)], W.options(precision="fp32", walks=156, seed=7, walk_offset=100))
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(acc.sum.cpu().numpy(), a["sum"], rtol=1e-12, atol=1e-12)
+    assert np.array_equal(acc.n_steps.cpu().numpy(), a["steps"])
+    # chunked launches (tiny workspace) give the same per-walk values
+    acc2 = W.Accumulators(P.shape[0])
+    W.solve([(h, P, acc2, 0)], W.options(precision="fp32", walks=256, seed=7, workspace_bytes=16 * 60 * P.shape[0]))
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(acc2.sum.cpu().numpy(), a["sum"], rtol=1e-12, atol=1e-12)
+
+
+def test_plan_graph_replays_match_solve(W):
+    torch = torch_cuda()
+    probs, pts = [], []
+    c4 = WL.config4(n_problems=4, min_pts=64, max_pts=512, max_edges=512)
+    for p, q in zip(c4["problems"], c4["points"]):
+        probs.append(W.Problem(p))
+        pts.append(dev(q))
+    opt = W.options(precision="fp32", walks=64, seed=0)
+    accs = [W.Accumulators(q.shape[0]) for q in pts]
+    plan = W.Plan([(h, q, a, i) for i, (h, q, a) in enumerate(zip(probs, pts, accs))], opt)
+    ref = [W.Accumulators(q.shape[0]) for q in pts]
+    for rep in range(3):
+        plan.launch(seed=100 + rep, walk_offset_add=64 * rep)
+        torch.cuda.synchronize()
+        W.solve([(h, q, a, i) for i, (h, q, a) in enumerate(zip(probs, pts, ref))],
+                W.options(precision="fp32", walks=64, seed=100 + rep, walk_offset=64 * rep))
+        torch.cuda.synchronize()
+    for a, b in zip(accs, ref):
+        np.testing.assert_allclose(a.sum.cpu().numpy(), b.sum.cpu().numpy(), rtol=1e-12, atol=1e-12)
+        assert np.array_equal(a.n_steps.cpu().numpy(), b.n_steps.cpu().numpy())
+        assert np.all(a.n_walks.cpu().numpy() == 192)
+
+
+def test_batched_problems_match_oracle(W, oracle):
+    c4 = WL.config4(n_problems=3, min_pts=32, max_pts=64, max_edges=256)
+    torch = torch_cuda()
+    entries, refs = [], []
+    for i, (p, q) in enumerate(zip(c4["problems"], c4["points"])):
+        h = W.Problem(p)
+        sel = q[:24]
+        entries.append((h, dev(sel), W.Accumulators(24), i))
+        refs.append(oracle.solve(p, sel, 256, h.sigma_bar, seed=31, problem_index=i))
+    W.solve(entries, W.options(precision="fp32", walks=2048, seed=32))
+    m_all, s_all, om, os_ = [], [], [], []
+    for (h, P, acc, i), o in zip(entries, refs):
+        mean, se = W.finalize(acc)
+        torch.cuda.synchronize()
+        m_all.append(mean.cpu().numpy())
+        s_all.append(se.cpu().numpy())
+        om.append(o["mean"])
+        os_.append(o["se"])
+    assert_parity(np.concatenate(m_all), np.concatenate(s_all), np.concatenate(om), np.concatenate(os_), "batch")
+
+
+def test_outside_points_and_step_cap(W):
+    prob = HARMONIC["disk"]()
+    h = W.Problem(prob, sigma_bar=0.0)
+    pts = np.array([[0.2, 0.1], [1.5, 0.0], [np.nan, 0.0], [0.0, -0.3]])
+    r = gpu_solve(W, h, pts, 64, "fp32", seed=1)
+    assert np.isnan(r["sum"][1]) and np.isnan(r["sum"][2]) and np.isfinite(r["sum"][[0, 3]]).all()
+    assert r["counters"][0] == 2
+    r = gpu_solve(W, h, pts[[0, 3]], 64, "fp32", seed=1, max_steps=2)
+    assert r["counters"][1] > 0
+    assert np.all(r["steps"] <= 2 * 64)
