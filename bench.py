@@ -37,6 +37,84 @@ def parse():
     ap.add_argument("--no-events", action="store_true")
     return ap.parse_args()
 
+# ----------------------------------------------------------------------------- cost model
+# Algorithmic floating-point operations of one event of the walk (FMA = 2, add / sub /
+# mul / div / min / max / compare = 1; sqrt, exp, log, sin and cos are counted apart as
+# transcendental operations). The counts follow the arithmetic of the device functions
+# in csrc/wos_device.h for the 2D FP32 walker; event totals come from the event-counting
+# build of the walker (wos_count_events), so the FLOP figure is measured work times
+# fixed per-event weights.
+
+def _field_cost(f, dim, derivs):
+    """(flops, transcendentals) of one evaluation of a field, with or without gradient and
+    Laplacian."""
+    b = f["base"]
+    fl, tr = 0, 0
+    if b == "fourier":
+        n = len(f["a"])
+        per = (2 * dim - 1) + 3 + 1 + ((3 + 2 * dim + 2) if derivs else 0)   # phase, value, sum, derivatives
+        fl += n * per
+        tr += n * (2 if derivs else 1)                                        # sin and cos, or cos only
+    elif b == "bumps":
+        n = len(f["amps"])
+        per = dim + (2 * dim - 1) + 3 + ((2 * dim + 4) if derivs else 0)
+        fl += n * per
+        tr += n
+    elif b in ("tanh", "tanh_drift"):
+        fl += 12 if derivs else 6
+        tr += 2
+    if f["transform"] == "exp":
+        fl += 2 + ((4 * dim + 4) if derivs else 0)
+        tr += 1
+    else:
+        fl += 2 + ((dim + 1) if derivs else 0)
+    return fl, tr
+
+
+def event_weights(prob):
+    dim = prob["dim"]
+    af, at = _field_cost(prob["alpha"], dim, True)
+    pf, pt = _field_cost(prob["psi"], dim, True) if prob["psi"]["base"] != "none" else (0, 0)
+    sf, st = _field_cost(prob["sigma"], dim, False)
+    if prob["source"]["base"] == "manufactured":
+        ff, ft = 12 + 4 * dim, 3
+    else:
+        ff, ft = _field_cost(prob["source"], dim, False)
+    coef = af + pf + sf + ff + (9 + 3 * dim) + (8 + 2 * dim) + 4     # ln-alpha derivatives, gamma, sigma'
+    coef_t = at + pt + st + ft + (0 if prob["alpha"]["transform"] == "exp" else 1)
+    ga_f = _field_cost(prob["alpha"], dim, False)
+    ps_f = _field_cost(prob["psi"], dim, False) if prob["psi"]["base"] != "none" else (0, 0)
+    gamma_only = (ga_f[0] + ps_f[0] + 2, ga_f[1] + ps_f[1])
+    bf, bt = _field_cost(prob["boundary"], dim, False) if prob["boundary"]["base"] != "manufactured" else (6, 3)
+    seg = 21 if dim == 2 else 75                                         # segment / triangle distance
+    node = 2 * (3 * dim) + 2                                             # two child boxes + ordering
+    W = {
+        # per distance query: sqrt, epsilon test, ball radius
+        "steps": (3, 1),
+        "bvh_nodes": (node, 0),
+        "prims": (seg, 0),
+        # per sampled ball: normalisation (series), direction, y, mu, coefficients at y, source
+        "sampled": (73 + 2 + 5 + 1 + coef + 5, 1 + 2 + coef_t + 1),
+        "ball_large_s": (42, 2),                                         # Chebyshev instead of series
+        "trials": (78, 3),                                               # harmonic-law proposal
+        "trials_free": (37, 1),                                          # free-space proposal, extra
+        "volume": (3, 0),
+        "exit": (6, 2),
+        "terminal": (12 + bf + 4, bt + 1),
+        "gamma_evals": gamma_only,
+        "rr_draws": (4, 0),
+    }
+    return W
+
+
+def algorithmic_work(events, prob):
+    W = event_weights(prob)
+    ev = dict(events)
+    ev["sampled"] = ev["steps"] - ev["terminal"]
+    flops = sum(W[k][0] * ev[k] for k in W)
+    trans = sum(W[k][1] * ev[k] for k in W)
+    return flops, trans
+
 
 def main():
     args = parse()
@@ -87,6 +165,21 @@ def main():
                 "counters": acc.counters.cpu().numpy().tolist(), "plan": info}
 
     r32 = run(args.precision, args.steps, args.warmup, args.walks)
+
+    # algorithmic work per distance query from the event-counting walker on a sample of
+    # the same workload (every 8th query point, 64 walks each)
+    sub = P[::8].contiguous()
+    acc_c = wos.Accumulators(sub.shape[0])
+    events = wos.count_events([(h, sub, acc_c, 0)], wos.options(precision=args.precision, walks=64, seed=99))
+    flops_ev, trans_ev = algorithmic_work(events, prob)
+    flops_per_step = flops_ev / events["steps"]
+    trans_per_step = trans_ev / events["steps"]
+    steps_per_pass = r32["steps"] / args.steps
+    achieved = flops_per_step * steps_per_pass / (np.mean(r32["ms"]) / 1e3) / 1e12
+    peak = 157.3 if args.precision != "fp64" else 78.6
+    roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": None, "flops_per_step": flops_per_step, "transcendentals_per_step": trans_per_step,
+                "events_per_step": {k: v / events["steps"] for k, v in events.items()}}
     r64 = run("fp64", args.fp64_steps, 0, args.walks) if args.fp64_steps > 0 else None
     ms_step = float(np.mean(r32["ms"]))
     steps_per_s = r32["steps"] / (sum(r32["ms"]) / 1e3)
@@ -149,7 +242,7 @@ def main():
         "walks_for_rmse_1e-2": n_star,
         "steps_per_walk": r32["steps"] / r32["walks"],
         "counters": r32["counters"],
-        "roofline": None,
+        "roofline": roofline,
         "cpu_baseline": cpu,
         "rmse": rmse,
     }

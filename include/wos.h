@@ -110,7 +110,7 @@ typedef struct {
  *             domain, which is the paper's max - min (Sec. 5.1, Sec. 7.1) whenever
  *             sigma' changes sign; sigma' is sampled in FP64 on a grid of
  *             `sigma_bar_grid` points per axis over the bounding box (0: 1024 in 2D,
- *             128 in 3D), keeping interior points only. 0 is allowed only when
+ *             64 in 3D), keeping interior points only. 0 is allowed only when
  *             sigma' = 0 everywhere (classic walk on spheres).
  *  allow_negative_sigma: 0 rejects sigma < 0 found while sampling (Sec. 2.2). */
 typedef struct {
@@ -138,7 +138,7 @@ typedef struct wos_problem wos_problem;
  * WOS_ERR_DEVICE / WOS_ERR_OUT_OF_MEMORY. */
 wos_status wos_problem_create(const wos_problem_desc* desc, int device, wos_problem** out);
 
-/* sigma' range seen while sampling (NaN if sigma_bar was given) and sigma_bar in use. */
+/* sigma' range seen while sampling the grid and the sigma_bar in use. */
 wos_status wos_problem_info(const wos_problem* p, double* sigma_prime_min, double* sigma_prime_max,
                             double* sigma_bar);
 
@@ -204,6 +204,17 @@ typedef struct {
  * in a fixed order, so results are bit-reproducible. Scratch memory is allocated and
  * freed in stream order. */
 wos_status wos_solve(const wos_batch_item* items, int32_t n_items, const wos_options* opt, void* stream);
+
+/* Runs the same walks as wos_solve (same outputs, accumulated the same way) with the
+ * event-counting build of the walker, and adds per-launch totals into `events` (device
+ * uint64 [12]): [0] distance queries, [1] BVH inner nodes visited, [2] primitives whose
+ * distance was computed, [3] radius proposals, [4] of which from the free-space law,
+ * [5] volume (null-collision) events, [6] exit events, [7] epsilon-shell terminations,
+ * [8] gamma-only evaluations, [9] walks started, [10] Russian-roulette draws,
+ * [11] balls with large s (2D s >= 2, 3D s >= 1). For measuring the algorithmic work
+ * of a workload; slower than wos_solve. */
+wos_status wos_count_events(const wos_batch_item* items, int32_t n_items, const wos_options* opt, uint64_t* events,
+                            void* stream);
 
 /* mean = sum / n, std_err = sqrt((sum_sq/n - mean^2) / (n - 1)) per point (eqs. 17-18);
  * all device arrays of length n. */

@@ -76,6 +76,7 @@ def lib():
             getattr(L, name).argtypes = [C.c_int, C.c_double, C.c_double]
             getattr(L, name).restype = C.c_double
         L.oracle_ball_pb.argtypes = [C.c_int, C.c_double]
+        L.oracle_radial_cdf_many.argtypes = [C.c_int, C.c_double, dp, C.c_int64, dp]
         L.oracle_ball_gnorm.argtypes = [C.c_int, C.c_double, C.c_double]
         L.oracle_ball_gnorm.restype = C.c_double
         L.oracle_bessel.argtypes = [C.c_int, C.c_double]
@@ -182,6 +183,13 @@ def ball_gnorm(dim, R, sigma_bar):
 
 def radial_cdf(dim, s, t):
     return lib().oracle_radial_cdf(dim, s, t)
+
+
+def radial_cdf_many(dim, s, t):
+    t = np.ascontiguousarray(t, np.float64)
+    out = np.empty_like(t)
+    lib().oracle_radial_cdf_many(dim, s, _dptr(t), t.size, _dptr(out))
+    return out
 
 
 def radial_pdf(dim, s, t):

@@ -679,6 +679,9 @@ double oracle_ball_gnorm(int dim, double R, double sigma_bar) { return ball_gnor
 double oracle_radial_cdf(int dim, double s, double t) { return radial_cdf(dim, s, t); }
 double oracle_radial_pdf(int dim, double s, double t) { return radial_pdf(dim, s, t); }
 double oracle_radial_quantile(int dim, double s, double u) { return radial_quantile(dim, s, u); }
+void oracle_radial_cdf_many(int dim, double s, const double* t, int64_t n, double* out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = radial_cdf(dim, s, t[i]);
+}
 double oracle_bessel(int which, double x) {
   switch (which) {
     case 0: return I0(x);

@@ -459,7 +459,7 @@ wos_status wos_problem_create(const wos_problem_desc* desc, int device, wos_prob
         hi[i] = std::max(hi[i], d.geometry.vertices[v * d.dim + i]);
       }
   }
-  const int grid = d.sigma_bar_grid > 0 ? d.sigma_bar_grid : (d.dim == 2 ? 1024 : 128);
+  const int grid = d.sigma_bar_grid > 0 ? d.sigma_bar_grid : (d.dim == 2 ? 1024 : 64);
   double h[3] = {0, 0, 0};
   for (int i = 0; i < d.dim; ++i) h[i] = (hi[i] - lo[i]) / grid;
   const int nblocks = 1024;
@@ -755,7 +755,8 @@ void prepare(const wos_batch_item* items, int n_items, const wos_options* opt, c
 // Enqueues classification (once) and, per launch, reset + walker + reduce.
 wos_status enqueue_job(const wos_batch_item* items, int n_items, const wos_options* opt, const Schedule& s,
                        const Workspace& w, const std::vector<std::vector<DevItem>>& dit,
-                       const std::vector<std::vector<Tile>>& tiles, size_t max_tiles, bool classify, hipStream_t st) {
+                       const std::vector<std::vector<Tile>>& tiles, size_t max_tiles, bool classify, uint64_t* events,
+                       hipStream_t st) {
   if (classify) {
     uint64_t pb = 0;
     for (int k = 0; k < n_items; ++k) {
@@ -786,6 +787,7 @@ wos_status enqueue_job(const wos_batch_item* items, int n_items, const wos_optio
     L.compensated = s.compensated;
     L.rr = opt->russian_roulette;
     L.ww_lo = opt->ww_lo > 0 ? opt->ww_lo : 0.5;
+    L.events = events;
     WOS_HIP(launch_walker(L, st));
     for (int k = 0; k < n_items; ++k) WOS_HIP(launch_reduce(dit[c][k], w.vals, w.steps, w.trials, st));
   }
@@ -812,7 +814,8 @@ wos_status upload_tables(const Schedule& s, int n_items, const Workspace& w,
 
 extern "C" {
 
-wos_status wos_solve(const wos_batch_item* items, int32_t n_items, const wos_options* opt, void* stream) {
+static wos_status solve_impl(const wos_batch_item* items, int32_t n_items, const wos_options* opt, uint64_t* events,
+                             void* stream) {
   Schedule s;
   wos_status r = check_items(items, n_items, opt, s);
   if (r != WOS_OK) return r;
@@ -843,10 +846,21 @@ wos_status wos_solve(const wos_batch_item* items, int32_t n_items, const wos_opt
   r = upload_tables(s, n_items, w, dit, tiles, max_tiles, st);
   if (r == WOS_OK) {
     const hipError_t e = launch_set_params(w.lp, opt->seed, 0, st);
-    r = e != hipSuccess ? fail(WOS_ERR_DEVICE, "launch failed") : enqueue_job(items, n_items, opt, s, w, dit, tiles, max_tiles, true, st);
+    r = e != hipSuccess ? fail(WOS_ERR_DEVICE, "launch failed")
+                        : enqueue_job(items, n_items, opt, s, w, dit, tiles, max_tiles, true, events, st);
   }
   (void)hipFreeAsync(base, st);
   return r;
+}
+
+wos_status wos_solve(const wos_batch_item* items, int32_t n_items, const wos_options* opt, void* stream) {
+  return solve_impl(items, n_items, opt, nullptr, stream);
+}
+
+wos_status wos_count_events(const wos_batch_item* items, int32_t n_items, const wos_options* opt, uint64_t* events,
+                            void* stream) {
+  if (!events) return fail(WOS_ERR_INVALID_ARG, "null events");
+  return solve_impl(items, n_items, opt, events, stream);
 }
 
 wos_status wos_finalize(const double* sum, const double* sum_sq, const uint64_t* n_walks, int64_t n, double* mean,
@@ -922,7 +936,7 @@ wos_status wos_plan_create(const wos_batch_item* items, int32_t n_items, const w
     (void)hipStreamDestroy(cap);
     return bail(WOS_ERR_DEVICE, "graph capture failed to start");
   }
-  r = enqueue_job(items, n_items, opt, s, P->ws, P->dit, tiles, max_tiles, false, cap);
+  r = enqueue_job(items, n_items, opt, s, P->ws, P->dit, tiles, max_tiles, false, nullptr, cap);
   const hipError_t ec = hipStreamEndCapture(cap, &P->graph);
   (void)hipStreamDestroy(cap);
   if (r != WOS_OK || ec != hipSuccess) return bail(WOS_ERR_DEVICE, "graph capture failed");

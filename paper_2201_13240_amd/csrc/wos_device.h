@@ -46,6 +46,13 @@ template <> struct Consts<double> {
   static constexpr double kEulerGamma = 0.57721566490153286061;
 };
 
+// Work counters of one lane, kept only by the event-counting build of the walker.
+struct Tally {
+  uint32_t nodes;        // BVH inner nodes visited
+  uint32_t prims;        // primitives whose distance was computed
+  uint32_t trials_free;  // radius proposals drawn from the free-space law
+};
+
 // ------------------------------------------------------------------ Philox4x32-10
 // Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3" (SC'11).
 
@@ -243,8 +250,9 @@ __device__ __forceinline__ Ball<T, DIM> ball_terms(T R, T s, T inv_sigma_bar, bo
 // never reached for finite s; a non-finite s returns -1 after kMaxTrials proposals.
 constexpr uint32_t kMaxTrials = 256;
 
-template <typename T, int DIM>
-__device__ __forceinline__ T sample_radius(Rng& rng, T s, const Ball<T, DIM>& b, bool harmonic, uint32_t& trials) {
+template <typename T, int DIM, bool COUNT = false>
+__device__ __forceinline__ T sample_radius(Rng& rng, T s, const Ball<T, DIM>& b, bool harmonic, uint32_t& trials,
+                                         Tally* tally = nullptr) {
   uint32_t budget = kMaxTrials;
   if (DIM == 2) {
     if (harmonic) {
@@ -271,6 +279,7 @@ __device__ __forceinline__ T sample_radius(Rng& rng, T s, const Ball<T, DIM>& b,
     }
     while (budget--) {
       ++trials;
+      if constexpr (COUNT) ++tally->trials_free;
       const T e1 = -m_log(uniform01<T>(rng));
       const T e2 = -m_log(uniform01<T>(rng));
       const T u3 = uniform01<T>(rng);
@@ -298,6 +307,7 @@ __device__ __forceinline__ T sample_radius(Rng& rng, T s, const Ball<T, DIM>& b,
     }
     while (budget--) {
       ++trials;
+      if constexpr (COUNT) ++tally->trials_free;
       const T u = -m_log(uniform01<T>(rng) * uniform01<T>(rng));
       const T u3 = uniform01<T>(rng);
       if (u >= s) continue;
@@ -570,13 +580,17 @@ __device__ __forceinline__ T segment_dist2(const T* x, const T* s, T* tpar) {
   return m_fma(dx, dx, dy * dy);
 }
 
-// Closest point of triangle (a, a+e0, a+e1) to p, by Voronoi regions of the
-// barycentric coordinates (Ericson, Real-Time Collision Detection, Sec. 5.1.5).
+// Closest point of triangle (a, b, c) = (tri[0..2], tri[3..5], tri[6..8]) to p, by the
+// Voronoi regions of its vertices, edges and face (Ericson, Real-Time Collision
+// Detection, Sec. 5.1.5).
 template <typename T>
 __device__ __forceinline__ void triangle_closest(const T* p, const T* tri, T* q) {
   const T* a = tri;
-  const T* ab = tri + 3;
-  const T* ac = tri + 6;
+  T ab[3], ac[3];
+  for (int i = 0; i < 3; ++i) {
+    ab[i] = tri[3 + i] - a[i];
+    ac[i] = tri[6 + i] - a[i];
+  }
   T ap[3];
   for (int i = 0; i < 3; ++i) ap[i] = p[i] - a[i];
   const T d1 = ab[0] * ap[0] + ab[1] * ap[1] + ab[2] * ap[2];
@@ -624,12 +638,12 @@ __device__ __forceinline__ T triangle_dist2(const T* p, const T* tri) {
 }
 
 constexpr int kPrimStride2 = 4;    // segment: x0 y0 x1 y1
-constexpr int kPrimStride3 = 12;   // triangle: a, b - a, c - a, (pad)
+constexpr int kPrimStride3 = 12;   // triangle: a, b, c, (pad)
 constexpr int kStackDepth = 48;
 
 // Nearest primitive by BVH traversal; returns squared distance and primitive index.
-template <typename T, int DIM>
-__device__ __forceinline__ T bvh_nearest(const DevGeometry<T>& g, const T* x, int* best_prim) {
+template <typename T, int DIM, bool COUNT = false>
+__device__ __forceinline__ T bvh_nearest(const DevGeometry<T>& g, const T* x, int* best_prim, Tally* tally = nullptr) {
   const BvhNode<T, DIM>* nodes = (const BvhNode<T, DIM>*)g.nodes;
   T best = Consts<T>::kInf;
   int bp = -1;
@@ -643,6 +657,7 @@ __device__ __forceinline__ T bvh_nearest(const DevGeometry<T>& g, const T* x, in
       if (cur < 0) {
         const int code = -1 - cur;
         const int first = code >> 3, cnt = code & 7;
+        if constexpr (COUNT) tally->prims += cnt;
         for (int k = 0; k < cnt; ++k) {
           const int pi = first + k;
           T d2;
@@ -659,6 +674,7 @@ __device__ __forceinline__ T bvh_nearest(const DevGeometry<T>& g, const T* x, in
         }
       } else {
         const BvhNode<T, DIM>& n = nodes[cur];
+        if constexpr (COUNT) ++tally->nodes;
         const T da = box_dist2<T, DIM>(x, n.lo[0], n.hi[0]);
         const T db = box_dist2<T, DIM>(x, n.lo[1], n.hi[1]);
         const int ca = n.child[0], cb = n.child[1];
@@ -686,8 +702,8 @@ __device__ __forceinline__ T bvh_nearest(const DevGeometry<T>& g, const T* x, in
 
 // Distance d from x to the boundary (Alg. 1, first step); prim receives what
 // closest_point needs to recover xbar.
-template <typename T, int DIM, int GEOM>
-__device__ __forceinline__ T boundary_distance(const DevGeometry<T>& g, const T* x, int* prim) {
+template <typename T, int DIM, int GEOM, bool COUNT = false>
+__device__ __forceinline__ T boundary_distance(const DevGeometry<T>& g, const T* x, int* prim, Tally* tally = nullptr) {
   if (GEOM == GK_BALL) {
     T r2 = 0;
 #pragma unroll
@@ -709,7 +725,7 @@ __device__ __forceinline__ T boundary_distance(const DevGeometry<T>& g, const T*
     *prim = best;
     return d;
   } else {
-    return m_sqrt(bvh_nearest<T, DIM>(g, x, prim));
+    return m_sqrt(bvh_nearest<T, DIM, COUNT>(g, x, prim, tally));
   }
 }
 

@@ -57,15 +57,27 @@ struct WalkerArgs {
   int32_t compensated;
   int32_t rr;
   T ww_lo;
+  uint64_t* events;      // event-counting build only: [kEvents]
+};
+
+// Events counted by the event-counting build of the walker (algorithmic work per step).
+enum Event {
+  EV_STEPS = 0, EV_NODES, EV_PRIMS, EV_TRIALS, EV_TRIALS_FREE, EV_VOLUME, EV_EXIT, EV_TERMINAL,
+  EV_GAMMA, EV_WALKS, EV_RR_TESTS, EV_BALL_LARGE_S, kEvents
 };
 
 constexpr uint32_t kFlagCapped = 1u << 31;
 constexpr uint32_t kFlagRR = 1u << 30;
 constexpr uint32_t kStepMask = (1u << 30) - 1;
 
-template <typename T, int DIM, int GEOM>
+template <typename T, int DIM, int GEOM, bool COUNT>
 __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a) {
   const uint32_t lane = __lane_id();
+  Tally tally = {0, 0, 0};
+  uint32_t ev[kEvents];
+  if constexpr (COUNT) {
+    for (int e = 0; e < kEvents; ++e) ev[e] = 0;
+  }
   const uint64_t seed = a.lp->seed;
   const uint64_t offset_add = a.lp->walk_offset_add;
   // ---- wave-uniform scheduling state
@@ -132,6 +144,10 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a) {
           for (int i = 0; i < DIM; ++i) x[i] = (T)it.points[p * DIM + i];
           rng.init(seed, (uint32_t)(it.walk_offset + offset_add + j), (uint32_t)p, it.problem_index);
           gamma0 = point_gamma<T, DIM>(*Pp, x);
+          if constexpr (COUNT) {
+            ++ev[EV_GAMMA];
+            ++ev[EV_WALKS];
+          }
           gx = gamma0;
           gx_known = true;
           Pi = 1;
@@ -147,6 +163,9 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a) {
       if (queue_done) break;
       continue;
     }
+    if constexpr (COUNT) {
+      if (active && nsteps < a.max_steps) ++ev[EV_STEPS];
+    }
     // ---------------------------------------------------------------- one step
     if (active) {
       const DevProblem<T>& P = *Pp;
@@ -157,7 +176,7 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a) {
         flag = kFlagCapped;
       } else {
         int prim;
-        const T d = boundary_distance<T, DIM, GEOM>(P.geom, x, &prim);
+        const T d = boundary_distance<T, DIM, GEOM, COUNT>(P.geom, x, &prim, &tally);
         ++nsteps;
         if (!(d == d)) {
           // a non-finite position cannot continue; report the walk as cut
@@ -168,6 +187,10 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a) {
           T xb[DIM];
           closest_point<T, DIM, GEOM>(P.geom, x, prim, xb);
           const T gb = boundary_value<T, DIM>(P, xb);
+          if constexpr (COUNT) {
+            ++ev[EV_TERMINAL];
+            if (!gx_known) ++ev[EV_GAMMA];
+          }
           if (!gx_known) gx = point_gamma<T, DIM>(P, x);
           const T term = Pi * m_exp(gx - gamma0) * gb;
           if (a.compensated) {
@@ -186,7 +209,10 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a) {
           const Ball<T, DIM> b = ball_terms<T, DIM>(R, s, P.inv_sigma_bar, harmonic);
           T v[DIM];
           uniform_direction<T, DIM>(rng, v);
-          T t = sample_radius<T, DIM>(rng, s, b, harmonic, ntrials);
+          if constexpr (COUNT) {
+            if (s >= (DIM == 2 ? (T)2 : (T)1)) ++ev[EV_BALL_LARGE_S];
+          }
+          T t = sample_radius<T, DIM, COUNT>(rng, s, b, harmonic, ntrials, &tally);
           if (t < (T)0) {  // sampler gave up (non-finite s): cut the walk
             done = true;
             flag = kFlagCapped;
@@ -210,6 +236,7 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a) {
           } else {
             A += term;
           }
+          if constexpr (COUNT) ++ev[volume ? EV_VOLUME : EV_EXIT];
           if (volume) {
             // null event: weight (1 - sigma'(y)/sigma_bar) e^{gamma(y) - gamma(x)}, move to y
             Pi *= (T)1 - cy.sigma_prime * P.inv_sigma_bar;
@@ -227,6 +254,7 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a) {
             if (a.rr) {
               gx = point_gamma<T, DIM>(P, x);
               gx_known = true;
+              if constexpr (COUNT) ++ev[EV_GAMMA];
             }
           }
           if (a.rr) {
@@ -234,6 +262,7 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a) {
             const T e = m_exp(gx - gamma0);
             const T W = Pi * e;
             if (m_fabs(W) < a.ww_lo) {
+              if constexpr (COUNT) ++ev[EV_RR_TESTS];
               const T u = uniform01<T>(rng);
               if (u * a.ww_lo <= m_fabs(W)) {
                 Pi = (W < (T)0 ? -a.ww_lo : a.ww_lo) / e;
@@ -249,8 +278,19 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a) {
         a.vals[wid] = (double)A + (double)Ac;
         a.steps[wid] = (nsteps & kStepMask) | flag;
         a.trials[wid] = ntrials;
+        if constexpr (COUNT) ev[EV_TRIALS] += ntrials;
         active = false;
       }
+    }
+  }
+  if constexpr (COUNT) {
+    ev[EV_NODES] = tally.nodes;
+    ev[EV_PRIMS] = tally.prims;
+    ev[EV_TRIALS_FREE] = tally.trials_free;
+    for (int e = 0; e < kEvents; ++e) {
+      uint64_t v = ev[e];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      if (lane == 0 && v) atomicAdd((unsigned long long*)&a.events[e], (unsigned long long)v);
     }
   }
 }
@@ -538,7 +578,11 @@ static hipError_t launch_walker_t(const WalkerLaunch& L, hipStream_t st) {
   a.compensated = L.compensated;
   a.rr = L.rr;
   a.ww_lo = (T)L.ww_lo;
-  hipLaunchKernelGGL((walker_kernel<T, DIM, GEOM>), dim3(L.grid), dim3(L.block), 0, st, a);
+  a.events = L.events;
+  if (L.events)
+    hipLaunchKernelGGL((walker_kernel<T, DIM, GEOM, true>), dim3(L.grid), dim3(L.block), 0, st, a);
+  else
+    hipLaunchKernelGGL((walker_kernel<T, DIM, GEOM, false>), dim3(L.grid), dim3(L.block), 0, st, a);
   return hipGetLastError();
 }
 
@@ -565,7 +609,7 @@ hipError_t launch_walker(const WalkerLaunch& L, hipStream_t st) {
 }
 
 template <typename T, int DIM, int GEOM>
-static const void* walker_symbol_t() { return (const void*)&walker_kernel<T, DIM, GEOM>; }
+static const void* walker_symbol_t() { return (const void*)&walker_kernel<T, DIM, GEOM, false>; }
 
 const void* walker_symbol(int fp64, int dim, int geom) {
   if (fp64) {

@@ -27,6 +27,7 @@ struct WalkerLaunch {
   int compensated;
   int rr;
   double ww_lo;
+  uint64_t* events;   // non-null selects the event-counting build of the walker
 };
 
 hipError_t launch_walker(const WalkerLaunch& L, hipStream_t st);

@@ -47,7 +47,7 @@ struct DevGeometry {
   T lo[3];
   T hi[3];
   const void* nodes;     // BvhNode<T, DIM>[n_nodes]
-  const T* prims;        // polygon: [n][4] (x0, y0, x1, y1); trimesh: [n][12] (a, b-a, c-a, n) with padding
+  const T* prims;        // polygon: [n][4] (x0, y0, x1, y1); trimesh: [n][12] (a, b, c, padding)
 };
 
 template <typename T>

@@ -63,7 +63,7 @@ class BatchItem(C.Structure):
 
 # Every symbol declared in include/wos.h.
 EXPORTS = ["wos_last_error", "wos_version", "wos_problem_create", "wos_problem_info", "wos_problem_bvh_info",
-           "wos_problem_destroy", "wos_solve", "wos_finalize", "wos_plan_create", "wos_plan_launch",
+           "wos_problem_destroy", "wos_solve", "wos_count_events", "wos_finalize", "wos_plan_create", "wos_plan_launch",
            "wos_plan_info", "wos_plan_destroy", "wos_eval_coefficients", "wos_eval_distance", "wos_eval_ball",
            "wos_sample_radius", "wos_philox", "wos_eval_bessel", "wos_classify"]
 
@@ -85,6 +85,7 @@ def lib():
         L.wos_problem_bvh_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i32), C.POINTER(i64)]
         L.wos_problem_destroy.argtypes = [vp]
         L.wos_solve.argtypes = [C.POINTER(BatchItem), i32, C.POINTER(Options), vp]
+        L.wos_count_events.argtypes = [C.POINTER(BatchItem), i32, C.POINTER(Options), vp, vp]
         L.wos_finalize.argtypes = [vp, vp, vp, i64, vp, vp, vp]
         L.wos_plan_create.argtypes = [C.POINTER(BatchItem), i32, C.POINTER(Options), vp, C.POINTER(vp)]
         L.wos_plan_launch.argtypes = [vp, u64, u64, vp]
@@ -267,6 +268,20 @@ def solve(entries, opt, stream=None):
     """entries: list of (Problem, points[n, dim] float64 cuda tensor, Accumulators, problem_index)."""
     arr = _items(entries)
     _check(lib().wos_solve(arr, len(entries), C.byref(opt), _stream(stream)))
+
+
+EVENT_NAMES = ["steps", "bvh_nodes", "prims", "trials", "trials_free", "volume", "exit", "terminal", "gamma_evals",
+               "walks", "rr_draws", "ball_large_s"]
+
+
+def count_events(entries, opt, stream=None):
+    """Same walks as solve() with the event-counting walker; returns {event: count}."""
+    import torch
+    arr = _items(entries)
+    ev = torch.zeros(len(EVENT_NAMES), dtype=torch.int64, device=entries[0][1].device)
+    _check(lib().wos_count_events(arr, len(entries), C.byref(opt), _ptr(ev), _stream(stream)))
+    torch.cuda.synchronize()
+    return dict(zip(EVENT_NAMES, ev.cpu().tolist()))
 
 
 def finalize(acc, stream=None):

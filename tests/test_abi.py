@@ -28,7 +28,7 @@ def W():
 def test_exports_every_declared_symbol(W):
     L = W.lib()
     declared = _declared()
-    assert len(declared) >= 19
+    assert len(declared) >= 20
     for name in declared:
         assert hasattr(L, name), name
     assert sorted(W.EXPORTS) == declared
