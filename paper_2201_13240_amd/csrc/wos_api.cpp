@@ -325,6 +325,56 @@ size_t layout_problem(Blob& blob, const wos_problem_desc& d, const HostGeometry&
       std::memcpy(blob.host.data() + term_off[k], terms.data(), terms.size() * sizeof(T));
     }
   }
+  // dense trigonometric table for 2D Fourier fields with integer wave vectors |k_i| <= 3,
+  // used when it replaces enough per-mode sin/cos evaluations
+  if (d.dim == 2) {
+    const wos_field_desc* slots[3] = {&d.alpha, &d.psi, &d.sigma};
+    int eligible = 0, modes = 0;
+    for (int sidx = 0; sidx < 3; ++sidx) {
+      const wos_field_desc& f = *slots[sidx];
+      if (f.base != WOS_FIELD_FOURIER || f.n_terms <= 0) continue;
+      bool ok = true;
+      for (int j = 0; j < f.n_terms && ok; ++j)
+        for (int i = 0; i < 2; ++i) {
+          const double k = f.terms[j * 4 + i];
+          if (k != std::floor(k) || std::fabs(k) > kSpecK) ok = false;
+        }
+      if (ok) {
+        eligible |= 1 << sidx;
+        modes += f.n_terms;
+      }
+    }
+    if (eligible && modes >= 12) {
+      P.spectral = eligible;
+      for (int sidx = 0; sidx < 3; ++sidx) {
+        if (!(eligible & (1 << sidx))) continue;
+        const wos_field_desc& f = *slots[sidx];
+        double re[kSpecBasis] = {0}, im[kSpecBasis] = {0}, c = 0;
+        for (int j = 0; j < f.n_terms; ++j) {
+          int kx = (int)f.terms[j * 4], ky = (int)f.terms[j * 4 + 1];
+          const double a = f.terms[j * 4 + 2], phi = f.terms[j * 4 + 3];
+          double cr = a * std::cos(phi), ci = a * std::sin(phi);
+          if (kx == 0 && ky == 0) {
+            c += cr;
+            continue;
+          }
+          if (kx < 0 || (kx == 0 && ky < 0)) {  // cos is even: use -k and the conjugate
+            kx = -kx;
+            ky = -ky;
+            ci = -ci;
+          }
+          const int b = kx == 0 ? ky - 1 : 3 + (kx - 1) * (2 * kSpecK + 1) + (ky + kSpecK);
+          re[b] += cr;
+          im[b] += ci;
+        }
+        for (int b = 0; b < kSpecBasis; ++b) {
+          P.spec.re[sidx][b] = (T)re[b];
+          P.spec.im[sidx][b] = (T)im[b];
+        }
+        P.spec.c[sidx] = (T)c;
+      }
+    }
+  }
   DevGeometry<T>& G = P.geom;
   G.kind = d.geometry.kind;
   for (int i = 0; i < 3; ++i) {

@@ -14,6 +14,18 @@
 
 namespace wos {
 
+// Problem tables, BVHs, query points and work tables never change while a kernel runs,
+// so they are read through constant-address-space references: the compiler then serves
+// wave-uniform reads with scalar loads and lane-varying ones with global loads (a
+// generic pointer would force flat loads for both).
+#define WOS_GLOBAL __attribute__((address_space(4)))
+template <typename T>
+using G = const WOS_GLOBAL T;
+template <typename T>
+__device__ __forceinline__ const WOS_GLOBAL T* gptr(const T* p) {
+  return (const WOS_GLOBAL T*)p;
+}
+
 // ------------------------------------------------------------------ math wrappers
 
 __device__ __forceinline__ float m_exp(float x) { return __expf(x); }
@@ -348,7 +360,7 @@ struct FV {
 
 // Base function B of a field at x, with gradient and Laplacian when D is true.
 template <typename T, int DIM, bool D>
-__device__ __forceinline__ FV<T, DIM> field_base(const DevField<T>& f, const T* x) {
+__device__ __forceinline__ FV<T, DIM> field_base(G<DevField<T>>& f, const T* x) {
   FV<T, DIM> r;
   r.v = 0;
   r.lap = 0;
@@ -356,7 +368,7 @@ __device__ __forceinline__ FV<T, DIM> field_base(const DevField<T>& f, const T* 
   for (int i = 0; i < DIM; ++i) r.g[i] = 0;
   const int base = f.base;
   if (base == FB_FOURIER) {
-    const T* p = f.terms;
+    const WOS_GLOBAL T* p = gptr(f.terms);
     for (int j = 0; j < f.n; ++j, p += kTermStride) {
       T th = p[0] * x[0] + p[1] * x[1];
       if (DIM == 3) th = m_fma(p[2], x[2], th);
@@ -373,7 +385,7 @@ __device__ __forceinline__ FV<T, DIM> field_base(const DevField<T>& f, const T* 
       }
     }
   } else if (base == FB_BUMPS) {
-    const T* p = f.terms;
+    const WOS_GLOBAL T* p = gptr(f.terms);
     for (int j = 0; j < f.n; ++j, p += kTermStride) {
       T d[DIM], r2 = 0;
 #pragma unroll
@@ -420,11 +432,63 @@ __device__ __forceinline__ FV<T, DIM> field_base(const DevField<T>& f, const T* 
   return r;
 }
 
-// Field after its transform (c0 + c1 B or exp(c0 + c1 B)); `log` of the exp transform
-// is available without a logarithm.
+// Bases of the Fourier fields of a 2D problem from the dense table (slots 0, 1, 2 =
+// alpha, psi, sigma), with gradient and Laplacian for slots 0 and 1 when D is true.
+// e^{2 pi i k.x} comes from the powers of e^{2 pi i x} and e^{2 pi i y} (two sincos
+// calls per point instead of one per mode), all loops unrolled at compile time.
+template <typename T, bool D>
+__device__ __forceinline__ void spectral2d(G<Spectral2D<T>>& sp, const T* x, FV<T, 2>* out) {
+  T cx[kSpecK + 1], sx[kSpecK + 1], cy[kSpecK + 1], sy[kSpecK + 1];
+  cx[0] = 1; sx[0] = 0; cy[0] = 1; sy[0] = 0;
+  m_sincospi2(x[0], &sx[1], &cx[1]);
+  m_sincospi2(x[1], &sy[1], &cy[1]);
+#pragma unroll
+  for (int m = 2; m <= kSpecK; ++m) {
+    cx[m] = cx[m - 1] * cx[1] - sx[m - 1] * sx[1];
+    sx[m] = sx[m - 1] * cx[1] + cx[m - 1] * sx[1];
+    cy[m] = cy[m - 1] * cy[1] - sy[m - 1] * sy[1];
+    sy[m] = sy[m - 1] * cy[1] + cy[m - 1] * sy[1];
+  }
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    out[s].v = sp.c[s];
+    out[s].g[0] = 0;
+    out[s].g[1] = 0;
+    out[s].lap = 0;
+  }
+  constexpr T kTwoPi = (T)6.283185307179586476925286766559;
+  int b = 0;
+#pragma unroll
+  for (int kx = 0; kx <= kSpecK; ++kx) {
+#pragma unroll
+    for (int ky = -kSpecK; ky <= kSpecK; ++ky) {
+      if (kx == 0 && ky <= 0) continue;
+      const int ay = ky < 0 ? -ky : ky;
+      const T yr = cy[ay], yi = ky < 0 ? -sy[ay] : sy[ay];
+      const T er = cx[kx] * yr - sx[kx] * yi;
+      const T ei = cx[kx] * yi + sx[kx] * yr;
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        const T cr = sp.re[s][b], ci = sp.im[s][b];
+        const T re = m_fma(cr, er, -ci * ei);
+        out[s].v += re;
+        if (D && s < 2) {
+          const T im = m_fma(cr, ei, ci * er);
+          out[s].g[0] = m_fma(-im, kTwoPi * (T)kx, out[s].g[0]);
+          out[s].g[1] = m_fma(-im, kTwoPi * (T)ky, out[s].g[1]);
+          out[s].lap = m_fma(-re, kTwoPi * kTwoPi * (T)(kx * kx + ky * ky), out[s].lap);
+        }
+      }
+      ++b;
+    }
+  }
+}
+
+// Field after its transform (c0 + c1 B or exp(c0 + c1 B)) from its base B; `log` of the
+// exp transform is available without a logarithm.
 template <typename T, int DIM, bool D>
-__device__ __forceinline__ FV<T, DIM> field_eval(const DevField<T>& f, const T* x, T* log_value = nullptr) {
-  FV<T, DIM> b = field_base<T, DIM, D>(f, x);
+__device__ __forceinline__ FV<T, DIM> field_transform(G<DevField<T>>& f, const FV<T, DIM>& b,
+                                                      T* log_value = nullptr) {
   FV<T, DIM> r;
   const T c1 = f.c1;
   if (f.transform == FT_EXP) {
@@ -449,6 +513,11 @@ __device__ __forceinline__ FV<T, DIM> field_eval(const DevField<T>& f, const T* 
     }
   }
   return r;
+}
+
+template <typename T, int DIM, bool D>
+__device__ __forceinline__ FV<T, DIM> field_eval(G<DevField<T>>& f, const T* x, T* log_value = nullptr) {
+  return field_transform<T, DIM, D>(f, field_base<T, DIM, D>(f, x), log_value);
 }
 
 // Manufactured solutions u (value, gradient, Laplacian).
@@ -485,12 +554,27 @@ struct PointCoef {
   T alpha;
 };
 
+// Bases of alpha, psi and sigma at x: from the dense 2D table where the problem has one,
+// else field by field.
+template <typename T, int DIM, bool D>
+__device__ __forceinline__ void coefficient_bases(G<DevProblem<T>>& P, const T* x, FV<T, DIM>* b) {
+  const int sp = DIM == 2 ? P.spectral : 0;
+  if constexpr (DIM == 2) {
+    if (sp) spectral2d<T, D>(P.spec, x, b);
+  }
+  if (!(sp & 1)) b[0] = field_base<T, DIM, D>(P.alpha, x);
+  if (!(sp & 2)) b[1] = field_base<T, DIM, D>(P.psi, x);
+  if (!(sp & 4)) b[2] = field_base<T, DIM, false>(P.sigma, x);
+}
+
 template <typename T, int DIM, bool WITH_SOURCE>
-__device__ __forceinline__ PointCoef<T> point_coef(const DevProblem<T>& P, const T* x) {
+__device__ __forceinline__ PointCoef<T> point_coef(G<DevProblem<T>>& P, const T* x) {
+  FV<T, DIM> base[3];
+  coefficient_bases<T, DIM, true>(P, x, base);
   // ln alpha with its gradient and Laplacian: grad ln a = grad a / a,
   // Lap ln a = Lap a / a - |grad ln a|^2 (for the exp transform ln a = c0 + c1 B directly)
   T lnal;
-  const FV<T, DIM> al = field_eval<T, DIM, true>(P.alpha, x, &lnal);
+  const FV<T, DIM> al = field_transform<T, DIM, true>(P.alpha, base[0], &lnal);
   if (P.alpha.transform != FT_EXP) lnal = m_log(al.v);
   const T inv_al = (T)1 / al.v;
   T gl[DIM], ga2 = 0;
@@ -508,7 +592,7 @@ __device__ __forceinline__ PointCoef<T> point_coef(const DevProblem<T>& P, const
     for (int i = 0; i < DIM; ++i) gg[i] = (T)0.5 * gl[i];
     lapg = (T)0.5 * lapl;
   } else {
-    const FV<T, DIM> ps = field_eval<T, DIM, true>(P.psi, x);
+    const FV<T, DIM> ps = field_transform<T, DIM, true>(P.psi, base[1]);
     gamma = (T)0.5 * (lnal + ps.v);
 #pragma unroll
     for (int i = 0; i < DIM; ++i) gg[i] = (T)0.5 * (gl[i] + ps.g[i]);
@@ -517,7 +601,7 @@ __device__ __forceinline__ PointCoef<T> point_coef(const DevProblem<T>& P, const
   T g2 = 0;
 #pragma unroll
   for (int i = 0; i < DIM; ++i) g2 = m_fma(gg[i], gg[i], g2);
-  const T sig = field_eval<T, DIM, false>(P.sigma, x).v;
+  const T sig = field_transform<T, DIM, false>(P.sigma, base[2]).v;
   PointCoef<T> c;
   c.gamma = gamma;
   c.alpha = al.v;
@@ -539,26 +623,36 @@ __device__ __forceinline__ PointCoef<T> point_coef(const DevProblem<T>& P, const
 }
 
 template <typename T, int DIM>
-__device__ __forceinline__ T boundary_value(const DevProblem<T>& P, const T* x) {
+__device__ __forceinline__ T boundary_value(G<DevProblem<T>>& P, const T* x) {
   if (P.boundary.base == FB_MANUFACTURED) return solution<T, DIM>(P.boundary.sol, x).v;
   return field_eval<T, DIM, false>(P.boundary, x).v;
 }
 
 // gamma alone (exit points of walks that need the full weight, and the last point)
 template <typename T, int DIM>
-__device__ __forceinline__ T point_gamma(const DevProblem<T>& P, const T* x) {
-  T lnal;
-  const FV<T, DIM> al = field_eval<T, DIM, false>(P.alpha, x, &lnal);
-  if (P.alpha.transform != FT_EXP) lnal = m_log(al.v);
-  T ps = P.psi.c0;
-  if (!(P.psi.base == FB_NONE && P.psi.transform == FT_AFFINE)) ps = field_eval<T, DIM, false>(P.psi, x).v;
+__device__ __forceinline__ T point_gamma(G<DevProblem<T>>& P, const T* x) {
+  T lnal, ps = P.psi.c0;
+  const bool has_psi = !(P.psi.base == FB_NONE && P.psi.transform == FT_AFFINE);
+  if (DIM == 2 && P.spectral) {
+    FV<T, DIM> base[3];
+    if constexpr (DIM == 2) spectral2d<T, false>(P.spec, x, base);
+    if (!(P.spectral & 1)) base[0] = field_base<T, DIM, false>(P.alpha, x);
+    if (has_psi && !(P.spectral & 2)) base[1] = field_base<T, DIM, false>(P.psi, x);
+    const FV<T, DIM> al = field_transform<T, DIM, false>(P.alpha, base[0], &lnal);
+    if (P.alpha.transform != FT_EXP) lnal = m_log(al.v);
+    if (has_psi) ps = field_transform<T, DIM, false>(P.psi, base[1]).v;
+  } else {
+    const FV<T, DIM> al = field_eval<T, DIM, false>(P.alpha, x, &lnal);
+    if (P.alpha.transform != FT_EXP) lnal = m_log(al.v);
+    if (has_psi) ps = field_eval<T, DIM, false>(P.psi, x).v;
+  }
   return (T)0.5 * (lnal + ps);
 }
 
 // ------------------------------------------------------------------ distance queries
 
-template <typename T, int DIM>
-__device__ __forceinline__ T box_dist2(const T* x, const T* lo, const T* hi) {
+template <typename T, int DIM, typename PT>
+__device__ __forceinline__ T box_dist2(const T* x, PT lo, PT hi) {
   T d2 = 0;
 #pragma unroll
   for (int i = 0; i < DIM; ++i) {
@@ -568,8 +662,8 @@ __device__ __forceinline__ T box_dist2(const T* x, const T* lo, const T* hi) {
   return d2;
 }
 
-template <typename T>
-__device__ __forceinline__ T segment_dist2(const T* x, const T* s, T* tpar) {
+template <typename T, typename PT>
+__device__ __forceinline__ T segment_dist2(const T* x, PT s, T* tpar) {
   const T ex = s[2] - s[0], ey = s[3] - s[1];
   const T px = x[0] - s[0], py = x[1] - s[1];
   const T l2 = m_fma(ex, ex, ey * ey);
@@ -583,9 +677,9 @@ __device__ __forceinline__ T segment_dist2(const T* x, const T* s, T* tpar) {
 // Closest point of triangle (a, b, c) = (tri[0..2], tri[3..5], tri[6..8]) to p, by the
 // Voronoi regions of its vertices, edges and face (Ericson, Real-Time Collision
 // Detection, Sec. 5.1.5).
-template <typename T>
-__device__ __forceinline__ void triangle_closest(const T* p, const T* tri, T* q) {
-  const T* a = tri;
+template <typename T, typename PT>
+__device__ __forceinline__ void triangle_closest(const T* p, PT tri, T* q) {
+  const T a[3] = {tri[0], tri[1], tri[2]};
   T ab[3], ac[3];
   for (int i = 0; i < 3; ++i) {
     ab[i] = tri[3 + i] - a[i];
@@ -629,8 +723,8 @@ __device__ __forceinline__ void triangle_closest(const T* p, const T* tri, T* q)
   for (int i = 0; i < 3; ++i) q[i] = a[i] + ab[i] * v + ac[i] * w;
 }
 
-template <typename T>
-__device__ __forceinline__ T triangle_dist2(const T* p, const T* tri) {
+template <typename T, typename PT>
+__device__ __forceinline__ T triangle_dist2(const T* p, PT tri) {
   T q[3];
   triangle_closest<T>(p, tri, q);
   const T dx = p[0] - q[0], dy = p[1] - q[1], dz = p[2] - q[2];
@@ -643,8 +737,9 @@ constexpr int kStackDepth = 48;
 
 // Nearest primitive by BVH traversal; returns squared distance and primitive index.
 template <typename T, int DIM, bool COUNT = false>
-__device__ __forceinline__ T bvh_nearest(const DevGeometry<T>& g, const T* x, int* best_prim, Tally* tally = nullptr) {
-  const BvhNode<T, DIM>* nodes = (const BvhNode<T, DIM>*)g.nodes;
+__device__ __forceinline__ T bvh_nearest(G<DevGeometry<T>>& g, const T* x, int* best_prim, Tally* tally = nullptr) {
+  const WOS_GLOBAL BvhNode<T, DIM>* nodes = (const WOS_GLOBAL BvhNode<T, DIM>*)g.nodes;
+  const WOS_GLOBAL T* prims = gptr(g.prims);
   T best = Consts<T>::kInf;
   int bp = -1;
   int stack[kStackDepth];
@@ -663,9 +758,9 @@ __device__ __forceinline__ T bvh_nearest(const DevGeometry<T>& g, const T* x, in
           T d2;
           if (DIM == 2) {
             T tp;
-            d2 = segment_dist2<T>(x, g.prims + (size_t)pi * kPrimStride2, &tp);
+            d2 = segment_dist2<T>(x, prims + (size_t)pi * kPrimStride2, &tp);
           } else {
-            d2 = triangle_dist2<T>(x, g.prims + (size_t)pi * kPrimStride3);
+            d2 = triangle_dist2<T>(x, prims + (size_t)pi * kPrimStride3);
           }
           if (d2 < best) {
             best = d2;
@@ -673,7 +768,7 @@ __device__ __forceinline__ T bvh_nearest(const DevGeometry<T>& g, const T* x, in
           }
         }
       } else {
-        const BvhNode<T, DIM>& n = nodes[cur];
+        G<BvhNode<T, DIM>>& n = nodes[cur];
         if constexpr (COUNT) ++tally->nodes;
         const T da = box_dist2<T, DIM>(x, n.lo[0], n.hi[0]);
         const T db = box_dist2<T, DIM>(x, n.lo[1], n.hi[1]);
@@ -703,7 +798,7 @@ __device__ __forceinline__ T bvh_nearest(const DevGeometry<T>& g, const T* x, in
 // Distance d from x to the boundary (Alg. 1, first step); prim receives what
 // closest_point needs to recover xbar.
 template <typename T, int DIM, int GEOM, bool COUNT = false>
-__device__ __forceinline__ T boundary_distance(const DevGeometry<T>& g, const T* x, int* prim, Tally* tally = nullptr) {
+__device__ __forceinline__ T boundary_distance(G<DevGeometry<T>>& g, const T* x, int* prim, Tally* tally = nullptr) {
   if (GEOM == GK_BALL) {
     T r2 = 0;
 #pragma unroll
@@ -730,7 +825,7 @@ __device__ __forceinline__ T boundary_distance(const DevGeometry<T>& g, const T*
 }
 
 template <typename T, int DIM, int GEOM>
-__device__ __forceinline__ void closest_point(const DevGeometry<T>& g, const T* x, int prim, T* xb) {
+__device__ __forceinline__ void closest_point(G<DevGeometry<T>>& g, const T* x, int prim, T* xb) {
   if (GEOM == GK_BALL) {
     T e[DIM], r2 = 0;
 #pragma unroll
@@ -748,13 +843,13 @@ __device__ __forceinline__ void closest_point(const DevGeometry<T>& g, const T* 
     const int ax = prim >> 1;
     xb[ax] = (prim & 1) ? g.hi[ax] : g.lo[ax];
   } else if (DIM == 2) {
-    const T* s = g.prims + (size_t)prim * kPrimStride2;
+    const WOS_GLOBAL T* s = gptr(g.prims) + (size_t)prim * kPrimStride2;
     T t;
     segment_dist2<T>(x, s, &t);
     xb[0] = s[0] + t * (s[2] - s[0]);
     xb[1] = s[1] + t * (s[3] - s[1]);
   } else {
-    triangle_closest<T>(x, g.prims + (size_t)prim * kPrimStride3, xb);
+    triangle_closest<T>(x, gptr(g.prims) + (size_t)prim * kPrimStride3, xb);
   }
 }
 

@@ -70,8 +70,15 @@ constexpr uint32_t kFlagCapped = 1u << 31;
 constexpr uint32_t kFlagRR = 1u << 30;
 constexpr uint32_t kStepMask = (1u << 30) - 1;
 
+__device__ __forceinline__ const void* uniform_ptr(const void* p) { return (const void*)uniform_u64((uint64_t)p); }
+
+// Buffers written by the walker are separate __restrict__ parameters, so loads of the
+// problem tables (read-only, at wave-uniform addresses) can be served by scalar loads.
 template <typename T, int DIM, int GEOM, bool COUNT>
-__global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a) {
+__global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* __restrict__ tile_counter,
+                                                     double* __restrict__ vals, uint32_t* __restrict__ steps_out,
+                                                     uint32_t* __restrict__ trials_out,
+                                                     uint64_t* __restrict__ events_out) {
   const uint32_t lane = __lane_id();
   Tally tally = {0, 0, 0};
   uint32_t ev[kEvents];
@@ -94,7 +101,9 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a) {
   T Pi = 1, A = 0, Ac = 0;
   uint32_t nsteps = 0, ntrials = 0;
   Rng rng;
-  const DevProblem<T>* Pp = nullptr;
+  const WOS_GLOBAL DevProblem<T>* Pp = nullptr;
+  const WOS_GLOBAL DevItem* items = gptr(a.items);
+  const WOS_GLOBAL Tile* tiles = gptr(a.tiles);
 
   for (;;) {
     // ---------------------------------------------------------------- refill idle lanes
@@ -103,23 +112,25 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a) {
       if (res_next >= res_end) {
         if (pend_tile < 0) {
           if (queue_done) break;
+          // every lane is active here, so the first active lane is lane 0
           uint32_t t = 0;
-          if (lane == 0) t = atomicAdd(a.tile_counter, 1u);
-          t = __shfl(t, 0);
+          if (lane == 0) t = atomicAdd(tile_counter, 1u);
+          t = __builtin_amdgcn_readfirstlane(t);
           if (t >= a.n_tiles) {
             queue_done = true;
             break;
           }
           pend_tile = uniform_int((int)t);
         }
-        const Tile tl = a.tiles[pend_tile];
-        if ((int)tl.item != cur_item) {
+        const uint32_t tl_item = tiles[pend_tile].item;
+        if ((int)tl_item != cur_item) {
           if (idle != ~0ull) break;  // drain the wave before switching problems
-          cur_item = uniform_int((int)tl.item);
-          Pp = (const DevProblem<T>*)a.items[cur_item].problem;
+          cur_item = uniform_int((int)tl_item);
+          Pp = (const WOS_GLOBAL DevProblem<T>*)uniform_ptr(items[cur_item].problem);
         }
-        res_next = uniform_u64(tl.first);
-        res_end = uniform_u64(tl.first + tl.count);
+        const uint64_t tl_first = tiles[pend_tile].first;
+        res_next = uniform_u64(tl_first);
+        res_end = uniform_u64(tl_first + tiles[pend_tile].count);
         pend_tile = -1;
       }
       const uint32_t n_idle = __popcll(idle);
@@ -127,7 +138,7 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a) {
       const uint32_t take = avail < (uint64_t)n_idle ? (uint32_t)avail : n_idle;
       const uint32_t rank = lanes_below(idle);
       if (!active && rank < take) {
-        const DevItem& it = a.items[cur_item];
+        G<DevItem>& it = items[cur_item];
         wid = res_next + rank;
         const uint64_t local = wid - it.walk_base;
         const uint64_t n = (uint64_t)it.n_points;
@@ -135,13 +146,13 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a) {
         const uint64_t j = local / n;
         nsteps = 0;
         ntrials = 0;
-        if (!it.inside[p]) {
-          a.vals[wid] = __builtin_nan("");
-          a.steps[wid] = 0;
-          a.trials[wid] = 0;
+        if (!gptr(it.inside)[p]) {
+          vals[wid] = __builtin_nan("");
+          steps_out[wid] = 0;
+          trials_out[wid] = 0;
         } else {
 #pragma unroll
-          for (int i = 0; i < DIM; ++i) x[i] = (T)it.points[p * DIM + i];
+          for (int i = 0; i < DIM; ++i) x[i] = (T)gptr(it.points)[p * DIM + i];
           rng.init(seed, (uint32_t)(it.walk_offset + offset_add + j), (uint32_t)p, it.problem_index);
           gamma0 = point_gamma<T, DIM>(*Pp, x);
           if constexpr (COUNT) {
@@ -168,7 +179,7 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a) {
     }
     // ---------------------------------------------------------------- one step
     if (active) {
-      const DevProblem<T>& P = *Pp;
+      G<DevProblem<T>>& P = *Pp;
       bool done = false;
       uint32_t flag = 0;
       if (nsteps >= a.max_steps) {
@@ -275,9 +286,9 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a) {
         }
       }
       if (done) {
-        a.vals[wid] = (double)A + (double)Ac;
-        a.steps[wid] = (nsteps & kStepMask) | flag;
-        a.trials[wid] = ntrials;
+        vals[wid] = (double)A + (double)Ac;
+        steps_out[wid] = (nsteps & kStepMask) | flag;
+        trials_out[wid] = ntrials;
         if constexpr (COUNT) ev[EV_TRIALS] += ntrials;
         active = false;
       }
@@ -290,7 +301,7 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a) {
     for (int e = 0; e < kEvents; ++e) {
       uint64_t v = ev[e];
       for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-      if (lane == 0 && v) atomicAdd((unsigned long long*)&a.events[e], (unsigned long long)v);
+      if (lane == 0 && v) atomicAdd((unsigned long long*)&events_out[e], (unsigned long long)v);
     }
   }
 }
@@ -353,7 +364,7 @@ __global__ void set_params_kernel(LaunchParams* lp, uint64_t seed, uint64_t add)
 // ------------------------------------------------------------------ inside classification (FP64)
 
 template <int DIM, int GEOM>
-__device__ bool inside_point(const DevGeometry<double>& g, const double* x) {
+__device__ bool inside_point(G<DevGeometry<double>>& g, const double* x) {
 #pragma unroll
   for (int i = 0; i < DIM; ++i)
     if (!isfinite(x[i])) return false;
@@ -369,7 +380,7 @@ __device__ bool inside_point(const DevGeometry<double>& g, const double* x) {
     // even-odd crossing count of a horizontal ray
     bool in = false;
     for (int j = 0; j < g.n_prims; ++j) {
-      const double* s = g.prims + (size_t)j * kPrimStride2;
+      const WOS_GLOBAL double* s = gptr(g.prims) + (size_t)j * kPrimStride2;
       const double ay = s[1], by = s[3];
       if ((ay > x[1]) != (by > x[1])) {
         const double xi = s[0] + (x[1] - ay) * (s[2] - s[0]) / (by - ay);
@@ -382,7 +393,7 @@ __device__ bool inside_point(const DevGeometry<double>& g, const double* x) {
     // (Van Oosterom and Strackee: tan(Omega/2) = det[a b c] / (|a||b||c| + (a.b)|c| + (a.c)|b| + (b.c)|a|))
     double w = 0;
     for (int j = 0; j < g.n_prims; ++j) {
-      const double* t = g.prims + (size_t)j * kPrimStride3;
+      const WOS_GLOBAL double* t = gptr(g.prims) + (size_t)j * kPrimStride3;
       double a[3], b[3], c[3];
       for (int i = 0; i < 3; ++i) {
         a[i] = t[i] - x[i];
@@ -409,7 +420,7 @@ __global__ void classify_kernel(const DevProblem<double>* P, const double* pts, 
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool bad = false;
   if (i < n) {
-    const bool in = inside_point<DIM, GEOM>(P->geom, pts + i * DIM);
+    const bool in = inside_point<DIM, GEOM>(gptr(P)->geom, pts + i * DIM);
     inside[i] = in ? 1 : 0;
     bad = !in;
   }
@@ -436,9 +447,10 @@ __global__ void sigma_sample_kernel(const DevProblem<double>* P, double lo0, dou
       x[i] = lo[i] + h[i] * ((double)(r % grid) + 0.5);
       r /= grid;
     }
-    if (!inside_point<DIM, GEOM>(P->geom, x)) continue;
-    const PointCoef<double> c = point_coef<double, DIM, false>(*P, x);
-    const double sig = field_eval<double, DIM, false>(P->sigma, x).v;
+    G<DevProblem<double>>& PR = *gptr(P);
+    if (!inside_point<DIM, GEOM>(PR.geom, x)) continue;
+    const PointCoef<double> c = point_coef<double, DIM, false>(PR, x);
+    const double sig = field_eval<double, DIM, false>(PR.sigma, x).v;
     cnt += 1;
     if (!isfinite(c.sigma_prime) || !isfinite(c.alpha)) {
       bad += 1;
@@ -476,14 +488,15 @@ __global__ void coef_kernel(const DevProblem<T>* P, const double* pts, int64_t n
   if (i >= n) return;
   T x[DIM];
   for (int k = 0; k < DIM; ++k) x[k] = (T)pts[i * DIM + k];
-  const PointCoef<T> c = point_coef<T, DIM, true>(*P, x);
+  G<DevProblem<T>>& PR = *gptr(P);
+  const PointCoef<T> c = point_coef<T, DIM, true>(PR, x);
   double* o = out + i * 6;
   o[0] = c.alpha;
   o[1] = c.gamma;
   o[2] = c.sigma_prime;
   o[3] = (double)c.f_over_alpha * (double)c.alpha;
   o[4] = (double)m_exp(c.gamma) * (double)c.f_over_alpha;
-  o[5] = boundary_value<T, DIM>(*P, x);
+  o[5] = boundary_value<T, DIM>(PR, x);
 }
 
 template <typename T, int DIM, int GEOM>
@@ -493,8 +506,8 @@ __global__ void distance_kernel(const DevProblem<T>* P, const double* pts, int64
   T x[DIM], q[DIM];
   for (int k = 0; k < DIM; ++k) x[k] = (T)pts[i * DIM + k];
   int prim;
-  d[i] = boundary_distance<T, DIM, GEOM>(P->geom, x, &prim);
-  closest_point<T, DIM, GEOM>(P->geom, x, prim, q);
+  d[i] = boundary_distance<T, DIM, GEOM>(gptr(P)->geom, x, &prim);
+  closest_point<T, DIM, GEOM>(gptr(P)->geom, x, prim, q);
   for (int k = 0; k < DIM; ++k) xb[i * DIM + k] = q[k];
 }
 
@@ -580,9 +593,11 @@ static hipError_t launch_walker_t(const WalkerLaunch& L, hipStream_t st) {
   a.ww_lo = (T)L.ww_lo;
   a.events = L.events;
   if (L.events)
-    hipLaunchKernelGGL((walker_kernel<T, DIM, GEOM, true>), dim3(L.grid), dim3(L.block), 0, st, a);
+    hipLaunchKernelGGL((walker_kernel<T, DIM, GEOM, true>), dim3(L.grid), dim3(L.block), 0, st, a, L.tile_counter,
+                       L.vals, L.steps, L.trials, L.events);
   else
-    hipLaunchKernelGGL((walker_kernel<T, DIM, GEOM, false>), dim3(L.grid), dim3(L.block), 0, st, a);
+    hipLaunchKernelGGL((walker_kernel<T, DIM, GEOM, false>), dim3(L.grid), dim3(L.block), 0, st, a, L.tile_counter,
+                       L.vals, L.steps, L.trials, (uint64_t*)nullptr);
   return hipGetLastError();
 }
 

@@ -50,16 +50,32 @@ struct DevGeometry {
   const T* prims;        // polygon: [n][4] (x0, y0, x1, y1); trimesh: [n][12] (a, b, c, padding)
 };
 
+// Dense trigonometric table of the 2D Fourier fields: for alpha, psi and sigma (slots
+// 0, 1, 2) the complex coefficient C_k of each wave vector k of the half plane
+// {kx > 0, |ky| <= 3} u {kx = 0, ky > 0}, kx <= 3, in the order kx = 0..3, ky = -3..3, so
+// that B(x) = const + sum_k Re(C_k e^{2 pi i k.x}). A mode a cos(2 pi k.x + phi) adds
+// a e^{i phi} at k, or a e^{-i phi} at -k when k is in the other half plane.
+constexpr int kSpecK = 3;
+constexpr int kSpecBasis = 24;
+
+template <typename T>
+struct Spectral2D {
+  T re[3][kSpecBasis];
+  T im[3][kSpecBasis];
+  T c[3];
+};
+
 template <typename T>
 struct DevProblem {
   int32_t dim;
-  int32_t pad;
+  int32_t spectral;        // bit s set: field slot s (alpha, psi, sigma) is in `spec`
   DevGeometry<T> geom;
   DevField<T> alpha, psi, sigma, source, boundary;
   T epsilon;
   T sigma_bar;
   T inv_sigma_bar;
   T sqrt_sigma_bar;
+  Spectral2D<T> spec;
 };
 
 // One query batch of a launch (device copy).
