@@ -388,6 +388,7 @@ size_t layout_problem(Blob& blob, const wos_problem_desc& d, const HostGeometry&
     G.n_prims = (int32_t)g.n_prims;
     G.n_nodes = (int32_t)(g.topo.child.size() / 2);
     G.root = g.topo.root;
+    G.depth = g.topo.depth;
     const std::vector<T>& prims = pick<T>(g.prims32, g.prims64);
     prim_off = blob.alloc(prims.size() * sizeof(T));
     std::memcpy(blob.host.data() + prim_off, prims.data(), prims.size() * sizeof(T));

@@ -733,11 +733,77 @@ __device__ __forceinline__ T triangle_dist2(const T* p, PT tri) {
 
 constexpr int kPrimStride2 = 4;    // segment: x0 y0 x1 y1
 constexpr int kPrimStride3 = 12;   // triangle: a, b, c, (pad)
-constexpr int kStackDepth = 48;
+constexpr int kStackDepth = 48;     // private (scratch) stack: any tree the host accepts
+constexpr int kLdsStackDepth = 16;  // LDS stack: trees of depth <= 16 (up to ~2^18 primitives)
+
+// Traversal stack of far children with their box distances, either in LDS (one column
+// per lane: entry k of lane t at k * stride + t, conflict-free) or in private memory.
+template <typename T>
+struct LdsStack {
+  int32_t* node;   // null: use the private stack
+  T* dist;
+  int stride;
+};
 
 // Nearest primitive by BVH traversal; returns squared distance and primitive index.
 template <typename T, int DIM, bool COUNT = false>
-__device__ __forceinline__ T bvh_nearest(G<DevGeometry<T>>& g, const T* x, int* best_prim, Tally* tally = nullptr) {
+__device__ __forceinline__ T bvh_nearest(G<DevGeometry<T>>& g, const T* x, int* best_prim, Tally* tally = nullptr,
+                                         LdsStack<T> lds = LdsStack<T>{nullptr, nullptr, 0}) {
+  if (lds.node && g.depth <= kLdsStackDepth) {
+    const WOS_GLOBAL BvhNode<T, DIM>* nodes = (const WOS_GLOBAL BvhNode<T, DIM>*)g.nodes;
+    const WOS_GLOBAL T* prims = gptr(g.prims);
+    T best = Consts<T>::kInf;
+    int bp = -1;
+    int sp = 0;
+    int cur = g.root;
+    T cur_d = 0;
+    for (;;) {
+      if (cur_d < best) {
+        if (cur < 0) {
+          const int code = -1 - cur;
+          const int first = code >> 3, cnt = code & 7;
+          if constexpr (COUNT) tally->prims += cnt;
+          for (int k = 0; k < cnt; ++k) {
+            const int pi = first + k;
+            T d2;
+            if (DIM == 2) {
+              T tp;
+              d2 = segment_dist2<T>(x, prims + (size_t)pi * kPrimStride2, &tp);
+            } else {
+              d2 = triangle_dist2<T>(x, prims + (size_t)pi * kPrimStride3);
+            }
+            if (d2 < best) {
+              best = d2;
+              bp = pi;
+            }
+          }
+        } else {
+          G<BvhNode<T, DIM>>& n = nodes[cur];
+          if constexpr (COUNT) ++tally->nodes;
+          const T da = box_dist2<T, DIM>(x, n.lo[0], n.hi[0]);
+          const T db = box_dist2<T, DIM>(x, n.lo[1], n.hi[1]);
+          const int ca = n.child[0], cb = n.child[1];
+          const bool a_first = da <= db;
+          const int near_c = a_first ? ca : cb, far_c = a_first ? cb : ca;
+          const T near_d = a_first ? da : db, far_d = a_first ? db : da;
+          if (far_d < best) {  // at most one entry per level above the current node
+            lds.node[sp * lds.stride] = far_c;
+            lds.dist[sp * lds.stride] = far_d;
+            ++sp;
+          }
+          cur = near_c;
+          cur_d = near_d;
+          continue;
+        }
+      }
+      if (sp == 0) break;
+      --sp;
+      cur = lds.node[sp * lds.stride];
+      cur_d = lds.dist[sp * lds.stride];
+    }
+    *best_prim = bp;
+    return best;
+  }
   const WOS_GLOBAL BvhNode<T, DIM>* nodes = (const WOS_GLOBAL BvhNode<T, DIM>*)g.nodes;
   const WOS_GLOBAL T* prims = gptr(g.prims);
   T best = Consts<T>::kInf;
@@ -798,7 +864,8 @@ __device__ __forceinline__ T bvh_nearest(G<DevGeometry<T>>& g, const T* x, int* 
 // Distance d from x to the boundary (Alg. 1, first step); prim receives what
 // closest_point needs to recover xbar.
 template <typename T, int DIM, int GEOM, bool COUNT = false>
-__device__ __forceinline__ T boundary_distance(G<DevGeometry<T>>& g, const T* x, int* prim, Tally* tally = nullptr) {
+__device__ __forceinline__ T boundary_distance(G<DevGeometry<T>>& g, const T* x, int* prim, Tally* tally = nullptr,
+                                               LdsStack<T> lds = LdsStack<T>{nullptr, nullptr, 0}) {
   if (GEOM == GK_BALL) {
     T r2 = 0;
 #pragma unroll
@@ -820,7 +887,7 @@ __device__ __forceinline__ T boundary_distance(G<DevGeometry<T>>& g, const T* x,
     *prim = best;
     return d;
   } else {
-    return m_sqrt(bvh_nearest<T, DIM, COUNT>(g, x, prim, tally));
+    return m_sqrt(bvh_nearest<T, DIM, COUNT>(g, x, prim, tally, lds));
   }
 }
 

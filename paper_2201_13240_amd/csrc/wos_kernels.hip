@@ -80,6 +80,12 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* 
                                                      uint32_t* __restrict__ trials_out,
                                                      uint64_t* __restrict__ events_out) {
   const uint32_t lane = __lane_id();
+  LdsStack<T> lds_stack{nullptr, nullptr, 0};
+  if constexpr (GEOM == GK_POLYGON || GEOM == GK_TRIMESH) {
+    __shared__ int32_t s_node[kLdsStackDepth * 256];
+    __shared__ T s_dist[kLdsStackDepth * 256];
+    lds_stack = LdsStack<T>{s_node + threadIdx.x, s_dist + threadIdx.x, (int)blockDim.x};
+  }
   Tally tally = {0, 0, 0};
   uint32_t ev[kEvents];
   if constexpr (COUNT) {
@@ -87,13 +93,16 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* 
   }
   const uint64_t seed = a.lp->seed;
   const uint64_t offset_add = a.lp->walk_offset_add;
+  const WOS_GLOBAL DevItem* items = gptr(a.items);
+  const WOS_GLOBAL Tile* tiles = gptr(a.tiles);
   // ---- wave-uniform scheduling state
   int cur_item = -1;
   uint64_t res_next = 0, res_end = 0;
   int pend_tile = -1;
   bool queue_done = false;
-  // ---- lane state
-  bool active = false;
+  const WOS_GLOBAL DevProblem<T>* Pp = nullptr;
+  // ---- lane state: phase 0 = idle, 1 = new walk (gamma0 pending), 2 = walking
+  int phase = 0;
   uint64_t wid = 0;
   T x[DIM];
   T gamma0 = 0, gx = 0;
@@ -101,13 +110,10 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* 
   T Pi = 1, A = 0, Ac = 0;
   uint32_t nsteps = 0, ntrials = 0;
   Rng rng;
-  const WOS_GLOBAL DevProblem<T>* Pp = nullptr;
-  const WOS_GLOBAL DevItem* items = gptr(a.items);
-  const WOS_GLOBAL Tile* tiles = gptr(a.tiles);
 
   for (;;) {
     // ---------------------------------------------------------------- refill idle lanes
-    uint64_t idle = __ballot(!active);
+    uint64_t idle = __ballot(phase == 0);
     while (idle != 0) {
       if (res_next >= res_end) {
         if (pend_tile < 0) {
@@ -137,7 +143,8 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* 
       const uint64_t avail = res_end - res_next;
       const uint32_t take = avail < (uint64_t)n_idle ? (uint32_t)avail : n_idle;
       const uint32_t rank = lanes_below(idle);
-      if (!active && rank < take) {
+      if (phase == 0 && rank < take) {
+        // new walk: only set-up here; gamma(x0) is evaluated with the other lanes' step
         G<DevItem>& it = items[cur_item];
         wid = res_next + rank;
         const uint64_t local = wid - it.walk_base;
@@ -154,133 +161,156 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* 
 #pragma unroll
           for (int i = 0; i < DIM; ++i) x[i] = (T)gptr(it.points)[p * DIM + i];
           rng.init(seed, (uint32_t)(it.walk_offset + offset_add + j), (uint32_t)p, it.problem_index);
-          gamma0 = point_gamma<T, DIM>(*Pp, x);
+          Pi = 1;
+          A = 0;
+          Ac = 0;
+          phase = 1;
           if constexpr (COUNT) {
             ++ev[EV_GAMMA];
             ++ev[EV_WALKS];
           }
-          gx = gamma0;
-          gx_known = true;
-          Pi = 1;
-          A = 0;
-          Ac = 0;
-          active = true;
         }
       }
       res_next += take;
-      idle = __ballot(!active);
+      idle = __ballot(phase == 0);
     }
-    if (__ballot(active) == 0) {
+    if (__ballot(phase != 0) == 0) {
       if (queue_done) break;
       continue;
     }
-    if constexpr (COUNT) {
-      if (active && nsteps < a.max_steps) ++ev[EV_STEPS];
-    }
     // ---------------------------------------------------------------- one step
-    if (active) {
+    // Every active lane evaluates the coefficients at exactly one point per iteration:
+    // x0 for a new walk, the current point for a walk that ends in the epsilon shell, and
+    // the sampled point y otherwise, so the most expensive part runs in lockstep.
+    if (phase != 0) {
       G<DevProblem<T>>& P = *Pp;
-      bool done = false;
+      bool done = false, terminal = false, sampled = false;
       uint32_t flag = 0;
-      if (nsteps >= a.max_steps) {
-        done = true;
-        flag = kFlagCapped;
-      } else {
-        int prim;
-        const T d = boundary_distance<T, DIM, GEOM, COUNT>(P.geom, x, &prim, &tally);
-        ++nsteps;
-        if (!(d == d)) {
-          // a non-finite position cannot continue; report the walk as cut
+      T q[DIM];
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) q[i] = x[i];
+      T gb = 0, R = 0, t = 0;
+      T v[DIM];
+      Ball<T, DIM> b;
+      b.pb = 0;
+      b.gnorm = 0;
+      b.c2d = 0;
+      if (phase == 2) {
+        if constexpr (COUNT) ++ev[EV_STEPS];
+        if (nsteps >= a.max_steps) {
           done = true;
           flag = kFlagCapped;
-        } else if (d < P.epsilon) {
-          // epsilon shell: the walk returns g(xbar) (Alg. 1), times its weight
-          T xb[DIM];
-          closest_point<T, DIM, GEOM>(P.geom, x, prim, xb);
-          const T gb = boundary_value<T, DIM>(P, xb);
-          if constexpr (COUNT) {
-            ++ev[EV_TERMINAL];
-            if (!gx_known) ++ev[EV_GAMMA];
-          }
-          if (!gx_known) gx = point_gamma<T, DIM>(P, x);
-          const T term = Pi * m_exp(gx - gamma0) * gb;
-          if (a.compensated) {
-            const T s = A + term;
-            const T bb = s - A;
-            Ac += (A - (s - bb)) + (term - bb);
-            A = s;
-          } else {
-            A += term;
-          }
-          done = true;
         } else {
-          const T R = d;
-          const bool harmonic = !(P.sigma_bar > (T)0);
-          const T s = R * P.sqrt_sigma_bar;
-          const Ball<T, DIM> b = ball_terms<T, DIM>(R, s, P.inv_sigma_bar, harmonic);
-          T v[DIM];
-          uniform_direction<T, DIM>(rng, v);
-          if constexpr (COUNT) {
-            if (s >= (DIM == 2 ? (T)2 : (T)1)) ++ev[EV_BALL_LARGE_S];
-          }
-          T t = sample_radius<T, DIM, COUNT>(rng, s, b, harmonic, ntrials, &tally);
-          if (t < (T)0) {  // sampler gave up (non-finite s): cut the walk
+          int prim;
+          const T d = boundary_distance<T, DIM, GEOM, COUNT>(P.geom, x, &prim, &tally, lds_stack);
+          ++nsteps;
+          if (!(d == d)) {
+            // a non-finite position cannot continue; report the walk as cut
             done = true;
             flag = kFlagCapped;
-            t = 0;
-          }
-          T y[DIM];
-#pragma unroll
-          for (int i = 0; i < DIM; ++i) y[i] = m_fma(t * R, v[i], x[i]);
-          const T mu = uniform01<T>(rng);
-          const bool volume = mu <= b.pb;
-          const PointCoef<T> cy = point_coef<T, DIM, true>(P, y);
-          const T src = Pi * m_exp(cy.gamma - gamma0) * cy.f_over_alpha;
-          T term = 0;
-          if (a.variant == 0) term = b.gnorm * src;
-          else if (volume) term = src * P.inv_sigma_bar;
-          if (a.compensated) {
-            const T s2 = A + term;
-            const T bb = s2 - A;
-            Ac += (A - (s2 - bb)) + (term - bb);
-            A = s2;
+          } else if (d < P.epsilon) {
+            // epsilon shell: the walk returns g(xbar) (Alg. 1) times its weight, which
+            // needs gamma at the current point
+            T xb[DIM];
+            closest_point<T, DIM, GEOM>(P.geom, x, prim, xb);
+            gb = boundary_value<T, DIM>(P, xb);
+            terminal = true;
+            if constexpr (COUNT) {
+              ++ev[EV_TERMINAL];
+              if (!gx_known) ++ev[EV_GAMMA];
+            }
           } else {
-            A += term;
-          }
-          if constexpr (COUNT) ++ev[volume ? EV_VOLUME : EV_EXIT];
-          if (volume) {
-            // null event: weight (1 - sigma'(y)/sigma_bar) e^{gamma(y) - gamma(x)}, move to y
-            Pi *= (T)1 - cy.sigma_prime * P.inv_sigma_bar;
+            R = d;
+            const bool harmonic = !(P.sigma_bar > (T)0);
+            const T s = R * P.sqrt_sigma_bar;
+            b = ball_terms<T, DIM>(R, s, P.inv_sigma_bar, harmonic);
+            if constexpr (COUNT) {
+              if (s >= (DIM == 2 ? (T)2 : (T)1)) ++ev[EV_BALL_LARGE_S];
+            }
+            uniform_direction<T, DIM>(rng, v);
+            t = sample_radius<T, DIM, COUNT>(rng, s, b, harmonic, ntrials, &tally);
+            if (t < (T)0) {  // sampler gave up (non-finite s): cut the walk
+              done = true;
+              flag = kFlagCapped;
+            } else {
 #pragma unroll
-            for (int i = 0; i < DIM; ++i) x[i] = y[i];
-            gx = cy.gamma;
-            gx_known = true;
-          } else {
-            // boundary term: uniform point on the sphere, weight e^{gamma(z) - gamma(x)}
-            T vz[DIM];
-            uniform_direction<T, DIM>(rng, vz);
-#pragma unroll
-            for (int i = 0; i < DIM; ++i) x[i] = m_fma(R, vz[i], x[i]);
-            gx_known = false;
-            if (a.rr) {
-              gx = point_gamma<T, DIM>(P, x);
-              gx_known = true;
-              if constexpr (COUNT) ++ev[EV_GAMMA];
+              for (int i = 0; i < DIM; ++i) q[i] = m_fma(t * R, v[i], x[i]);
+              sampled = true;
             }
           }
+        }
+      }
+      const bool evaluate = !done;
+      PointCoef<T> cq;
+      cq.gamma = 0;
+      cq.sigma_prime = 0;
+      cq.f_over_alpha = 0;
+      cq.alpha = 1;
+      if (evaluate) cq = point_coef<T, DIM, true>(P, q);
+      if (phase == 1) {
+        gamma0 = cq.gamma;
+        gx = gamma0;
+        gx_known = true;
+        phase = 2;
+      } else if (terminal) {
+        const T term = Pi * m_exp(cq.gamma - gamma0) * gb;
+        if (a.compensated) {
+          const T s2 = A + term;
+          const T bb = s2 - A;
+          Ac += (A - (s2 - bb)) + (term - bb);
+          A = s2;
+        } else {
+          A += term;
+        }
+        done = true;
+      } else if (sampled) {
+        const T mu = uniform01<T>(rng);
+        const bool volume = mu <= b.pb;
+        const T src = Pi * m_exp(cq.gamma - gamma0) * cq.f_over_alpha;
+        T term = 0;
+        if (a.variant == 0) term = b.gnorm * src;
+        else if (volume) term = src * P.inv_sigma_bar;
+        if (a.compensated) {
+          const T s2 = A + term;
+          const T bb = s2 - A;
+          Ac += (A - (s2 - bb)) + (term - bb);
+          A = s2;
+        } else {
+          A += term;
+        }
+        if constexpr (COUNT) ++ev[volume ? EV_VOLUME : EV_EXIT];
+        if (volume) {
+          // null event: weight (1 - sigma'(y)/sigma_bar) e^{gamma(y) - gamma(x)}, move to y
+          Pi *= (T)1 - cq.sigma_prime * P.inv_sigma_bar;
+#pragma unroll
+          for (int i = 0; i < DIM; ++i) x[i] = q[i];
+          gx = cq.gamma;
+          gx_known = true;
+        } else {
+          // boundary term: uniform point on the sphere, weight e^{gamma(z) - gamma(x)}
+          T vz[DIM];
+          uniform_direction<T, DIM>(rng, vz);
+#pragma unroll
+          for (int i = 0; i < DIM; ++i) x[i] = m_fma(R, vz[i], x[i]);
+          gx_known = false;
           if (a.rr) {
-            // static weight window, low side (Sec. 6): survive with probability |W|/w-
-            const T e = m_exp(gx - gamma0);
-            const T W = Pi * e;
-            if (m_fabs(W) < a.ww_lo) {
-              if constexpr (COUNT) ++ev[EV_RR_TESTS];
-              const T u = uniform01<T>(rng);
-              if (u * a.ww_lo <= m_fabs(W)) {
-                Pi = (W < (T)0 ? -a.ww_lo : a.ww_lo) / e;
-              } else {
-                done = true;
-                flag = kFlagRR;
-              }
+            gx = point_gamma<T, DIM>(P, x);
+            gx_known = true;
+            if constexpr (COUNT) ++ev[EV_GAMMA];
+          }
+        }
+        if (a.rr) {
+          // static weight window, low side (Sec. 6): survive with probability |W|/w-
+          const T e = m_exp(gx - gamma0);
+          const T W = Pi * e;
+          if (m_fabs(W) < a.ww_lo) {
+            if constexpr (COUNT) ++ev[EV_RR_TESTS];
+            const T u = uniform01<T>(rng);
+            if (u * a.ww_lo <= m_fabs(W)) {
+              Pi = (W < (T)0 ? -a.ww_lo : a.ww_lo) / e;
+            } else {
+              done = true;
+              flag = kFlagRR;
             }
           }
         }
@@ -290,7 +320,7 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* 
         steps_out[wid] = (nsteps & kStepMask) | flag;
         trials_out[wid] = ntrials;
         if constexpr (COUNT) ev[EV_TRIALS] += ntrials;
-        active = false;
+        phase = 0;
       }
     }
   }
@@ -299,9 +329,9 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* 
     ev[EV_PRIMS] = tally.prims;
     ev[EV_TRIALS_FREE] = tally.trials_free;
     for (int e = 0; e < kEvents; ++e) {
-      uint64_t v = ev[e];
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-      if (lane == 0 && v) atomicAdd((unsigned long long*)&events_out[e], (unsigned long long)v);
+      uint64_t val = ev[e];
+      for (int off = 32; off > 0; off >>= 1) val += __shfl_xor(val, off);
+      if (lane == 0 && val) atomicAdd((unsigned long long*)&events_out[e], (unsigned long long)val);
     }
   }
 }

@@ -42,6 +42,8 @@ struct DevGeometry {
   int32_t n_prims;
   int32_t n_nodes;
   int32_t root;          // root child reference (same encoding as BvhNode::child)
+  int32_t depth;         // deepest inner node level (root = 0) plus one
+  int32_t pad;
   T center[3];
   T radius;
   T lo[3];
