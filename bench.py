@@ -92,6 +92,7 @@ def event_weights(prob):
         # per distance query: sqrt, epsilon test, ball radius
         "steps": (3, 1),
         "bvh_nodes": (node, 0),
+        "grid_cells": (2 * dim + 4, 0),                                  # cell index of the query point
         "prims": (seg, 0),
         # per sampled ball: normalisation (series), direction, y, mu, coefficients at y, source
         "sampled": (73 + 2 + 5 + 1 + coef + 5, 1 + 2 + coef_t + 1),

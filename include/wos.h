@@ -145,6 +145,11 @@ wos_status wos_problem_info(const wos_problem* p, double* sigma_prime_min, doubl
 /* BVH statistics: nodes, depth, primitives (0 for analytic shapes). */
 wos_status wos_problem_bvh_info(const wos_problem* p, int64_t* n_nodes, int32_t* depth, int64_t* n_prims);
 
+/* Candidate grid of a polygon (nx = ny = 0 otherwise): a uniform grid whose cells list
+ * every segment that can be nearest to a point of the cell; closest-point queries then
+ * scan one short list instead of traversing the BVH. n_candidates: total list length. */
+wos_status wos_problem_grid_info(const wos_problem* p, int32_t* nx, int32_t* ny, int64_t* n_candidates);
+
 wos_status wos_problem_destroy(wos_problem* p);
 
 /* ---------------------------------------------------------------- solving */
@@ -207,12 +212,13 @@ wos_status wos_solve(const wos_batch_item* items, int32_t n_items, const wos_opt
 
 /* Runs the same walks as wos_solve (same outputs, accumulated the same way) with the
  * event-counting build of the walker, and adds per-launch totals into `events` (device
- * uint64 [12]): [0] distance queries, [1] BVH inner nodes visited, [2] primitives whose
+ * uint64 [13]): [0] distance queries, [1] BVH inner nodes visited, [2] primitives whose
  * distance was computed, [3] radius proposals, [4] of which from the free-space law,
  * [5] volume (null-collision) events, [6] exit events, [7] epsilon-shell terminations,
  * [8] gamma-only evaluations, [9] walks started, [10] Russian-roulette draws,
- * [11] balls with large s (2D s >= 2, 3D s >= 1). For measuring the algorithmic work
- * of a workload; slower than wos_solve. */
+ * [11] balls with large s (2D s >= 2, 3D s >= 1), [12] candidate-grid lookups. For
+ * measuring the algorithmic work of a workload; slower than wos_solve. events: device
+ * uint64 [13]. */
 wos_status wos_count_events(const wos_batch_item* items, int32_t n_items, const wos_options* opt, uint64_t* events,
                             void* stream);
 

@@ -1,6 +1,7 @@
 #include "bvh.h"
 
 #include <algorithm>
+#include <cmath>
 #include <functional>
 #include <limits>
 
@@ -86,5 +87,99 @@ template void bvh_child_bounds<float>(const BvhTopology&, const std::vector<floa
                                       std::vector<float>&);
 template void bvh_child_bounds<double>(const BvhTopology&, const std::vector<double>&, const std::vector<double>&,
                                        int, std::vector<double>&);
+
+}  // namespace wos
+
+namespace wos {
+
+namespace {
+
+double seg_dist2(const double* s, double px, double py) {
+  const double ex = s[2] - s[0], ey = s[3] - s[1];
+  const double qx = px - s[0], qy = py - s[1];
+  const double l2 = ex * ex + ey * ey;
+  double t = l2 > 0 ? (qx * ex + qy * ey) / l2 : 0.0;
+  t = std::min(1.0, std::max(0.0, t));
+  const double dx = qx - t * ex, dy = qy - t * ey;
+  return dx * dx + dy * dy;
+}
+
+double box_d2(const double* lo, const double* hi, double px, double py) {
+  const double ex = std::max(std::max(lo[0] - px, px - hi[0]), 0.0);
+  const double ey = std::max(std::max(lo[1] - py, py - hi[1]), 0.0);
+  return ex * ex + ey * ey;
+}
+
+struct SegQuery {
+  const std::vector<double>& segs;
+  const BvhTopology& topo;
+  const std::vector<double>& bounds;
+
+  // visits every leaf segment whose subtree box lies within sqrt(r2) of (px, py)
+  template <typename F>
+  void within(int32_t c, double px, double py, const double* r2, F&& f) const {
+    if (c < 0) {
+      const int32_t code = -1 - c;
+      const int32_t first = code >> 3, cnt = code & 7;
+      for (int32_t i = first; i < first + cnt; ++i) f(i, seg_dist2(&segs[4 * (size_t)i], px, py));
+      return;
+    }
+    const double* b = &bounds[(size_t)c * 8];  // lo[2][2], hi[2][2]
+    const double da = box_d2(b + 0, b + 4, px, py), db = box_d2(b + 2, b + 6, px, py);
+    const int32_t ca = topo.child[2 * c], cb = topo.child[2 * c + 1];
+    if (da <= db) {
+      if (da <= *r2) within(ca, px, py, r2, f);
+      if (db <= *r2) within(cb, px, py, r2, f);
+    } else {
+      if (db <= *r2) within(cb, px, py, r2, f);
+      if (da <= *r2) within(ca, px, py, r2, f);
+    }
+  }
+};
+
+}  // namespace
+
+SegmentGrid build_segment_grid(const std::vector<double>& segs, int64_t n, const BvhTopology& topo,
+                               const std::vector<double>& bounds, int64_t target_cells, double margin,
+                               int max_candidates) {
+  SegmentGrid g;
+  double lo[2] = {1e300, 1e300}, hi[2] = {-1e300, -1e300};
+  for (int64_t i = 0; i < n; ++i)
+    for (int v = 0; v < 2; ++v)
+      for (int k = 0; k < 2; ++k) {
+        lo[k] = std::min(lo[k], segs[4 * i + 2 * v + k]);
+        hi[k] = std::max(hi[k], segs[4 * i + 2 * v + k]);
+      }
+  const double ex = hi[0] - lo[0], ey = hi[1] - lo[1];
+  const double pad = 1e-6 * std::max(ex, ey) + 1e-12;
+  lo[0] -= pad;
+  lo[1] -= pad;
+  const double h = std::sqrt((ex + 2 * pad) * (ey + 2 * pad) / (double)target_cells);
+  g.nx = std::max(1, (int32_t)std::ceil((ex + 2 * pad) / h));
+  g.ny = std::max(1, (int32_t)std::ceil((ey + 2 * pad) / h));
+  g.lo[0] = lo[0];
+  g.lo[1] = lo[1];
+  g.h = h;
+  const double halfdiag = 0.5 * h * std::sqrt(2.0);
+  SegQuery q{segs, topo, bounds};
+  const int64_t ncell = (int64_t)g.nx * g.ny;
+  g.start.resize(ncell + 1);
+  g.start[0] = 0;
+  for (int32_t j = 0; j < g.ny; ++j)
+    for (int32_t i = 0; i < g.nx; ++i) {
+      const double cx = lo[0] + (i + 0.5) * h, cy = lo[1] + (j + 0.5) * h;
+      double best = 1e300;
+      q.within(topo.root, cx, cy, &best, [&](int32_t, double d2) { best = std::min(best, d2); });
+      const double r = std::sqrt(best) + 2 * halfdiag + margin;
+      const double r2 = r * r;
+      const size_t first = g.prim.size();
+      q.within(topo.root, cx, cy, &r2, [&](int32_t s, double d2) {
+        if (d2 <= r2) g.prim.push_back(s);
+      });
+      if (g.prim.size() - first > (size_t)max_candidates) g.prim.resize(first);  // empty list: use the BVH
+      g.start[(int64_t)j * g.nx + i + 1] = (uint32_t)g.prim.size();
+    }
+  return g;
+}
 
 }  // namespace wos

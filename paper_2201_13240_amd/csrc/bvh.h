@@ -24,3 +24,26 @@ void bvh_child_bounds(const BvhTopology& t, const std::vector<T>& plo, const std
                       std::vector<T>& out);
 
 }  // namespace wos
+
+namespace wos {
+
+// Uniform grid over the bounding box of a 2D segment set. Cell c lists every segment
+// within d(center_c) + 2 * halfdiag + margin of its centre, a superset of the segments
+// that can be nearest to any point of the cell (or within `margin` of it): for p in the
+// cell and s* nearest to p, |c - s*| <= |p - s*| + halfdiag <= d(c) + 2 halfdiag.
+struct SegmentGrid {
+  int32_t nx = 0, ny = 0;
+  double lo[2] = {0, 0};
+  double h = 0;
+  std::vector<uint32_t> start;   // [nx * ny + 1]
+  std::vector<int32_t> prim;     // candidate segment indices (leaf order)
+};
+
+// segs: [n][4] in leaf order; topo/bounds: the BVH over them (child bounds as produced
+// by bvh_child_bounds<double>). target_cells bounds the grid size. A cell with more
+// than max_candidates candidates gets an empty list (its queries use the BVH).
+SegmentGrid build_segment_grid(const std::vector<double>& segs, int64_t n, const BvhTopology& topo,
+                               const std::vector<double>& bounds, int64_t target_cells, double margin,
+                               int max_candidates);
+
+}  // namespace wos

@@ -61,6 +61,8 @@ struct wos_problem {
   size_t off32 = 0, off64 = 0;
   int64_t n_nodes = 0, n_prims = 0;
   int32_t depth = 0;
+  int32_t grid_nx = 0, grid_ny = 0;
+  int64_t grid_candidates = 0;
   std::vector<unsigned char> staging;  // host copy of the device blob
   const void* d32() const { return (const unsigned char*)dmem + off32; }
   const void* d64() const { return (const unsigned char*)dmem + off64; }
@@ -173,6 +175,7 @@ struct HostGeometry {
   BvhTopology topo;
   std::vector<double> bounds64;      // node child bounds
   std::vector<float> bounds32;
+  SegmentGrid grid;                  // 2D polygons
 };
 
 wos_status build_geometry(const wos_problem_desc& d, HostGeometry& g) {
@@ -276,6 +279,14 @@ wos_status build_geometry(const wos_problem_desc& d, HostGeometry& g) {
   }
   bvh_child_bounds<double>(g.topo, plo64, phi64, pdim, g.bounds64);
   bvh_child_bounds<float>(g.topo, plo32, phi32, pdim, g.bounds32);
+  if (G.kind == WOS_GEOM_POLYGON) {
+    // about 64 cells per segment, between 64^2 and 2^20 cells; the margin covers
+    // FP32 rounding of the query point and of the cell index
+    double scale = 0;
+    for (double c : g.prims64) scale = std::max(scale, std::fabs(c));
+    const int64_t target = std::min<int64_t>(1 << 20, std::max<int64_t>(4096, 64 * n));
+    g.grid = build_segment_grid(g.prims64, n, g.topo, g.bounds64, target, 4e-6 * (scale + 1.0), 32);
+  }
   return WOS_OK;
 }
 
@@ -383,7 +394,7 @@ size_t layout_problem(Blob& blob, const wos_problem_desc& d, const HostGeometry&
     G.hi[i] = (T)d.geometry.hi[i];
   }
   G.radius = (T)d.geometry.radius;
-  size_t node_off = 0, prim_off = 0;
+  size_t node_off = 0, prim_off = 0, grid_start_off = 0, grid_prim_off = 0, grid_seg_off = 0;
   if (g.n_prims > 0) {
     G.n_prims = (int32_t)g.n_prims;
     G.n_nodes = (int32_t)(g.topo.child.size() / 2);
@@ -396,6 +407,22 @@ size_t layout_problem(Blob& blob, const wos_problem_desc& d, const HostGeometry&
     if (d.dim == 2) {
       node_off = blob.alloc(std::max<size_t>(1, G.n_nodes) * sizeof(BvhNode<T, 2>));
       write_nodes<T, 2>(g, bounds, (BvhNode<T, 2>*)(blob.host.data() + node_off));
+      if (g.grid.nx > 0) {
+        G.grid_nx = g.grid.nx;
+        G.grid_ny = g.grid.ny;
+        G.grid_lo[0] = (T)g.grid.lo[0];
+        G.grid_lo[1] = (T)g.grid.lo[1];
+        G.grid_inv_h = (T)(1.0 / g.grid.h);
+        const size_t nc = g.grid.prim.size();
+        grid_start_off = blob.alloc(g.grid.start.size() * sizeof(uint32_t));
+        std::memcpy(blob.host.data() + grid_start_off, g.grid.start.data(), g.grid.start.size() * sizeof(uint32_t));
+        grid_prim_off = blob.alloc(std::max<size_t>(nc, 1) * sizeof(int32_t));
+        std::memcpy(blob.host.data() + grid_prim_off, g.grid.prim.data(), nc * sizeof(int32_t));
+        grid_seg_off = blob.alloc(std::max<size_t>(nc, 1) * 4 * sizeof(T));
+        T* cs = (T*)(blob.host.data() + grid_seg_off);
+        for (size_t k = 0; k < nc; ++k)
+          for (int c = 0; c < 4; ++c) cs[4 * k + c] = prims[(size_t)g.grid.prim[k] * 4 + c];
+      }
     } else {
       node_off = blob.alloc(std::max<size_t>(1, G.n_nodes) * sizeof(BvhNode<T, 3>));
       write_nodes<T, 3>(g, bounds, (BvhNode<T, 3>*)(blob.host.data() + node_off));
@@ -413,6 +440,11 @@ size_t layout_problem(Blob& blob, const wos_problem_desc& d, const HostGeometry&
     const size_t gbase = off_struct + offsetof(DevProblem<T>, geom);
     ptr_fixups.push_back({gbase + offsetof(DevGeometry<T>, nodes), node_off});
     ptr_fixups.push_back({gbase + offsetof(DevGeometry<T>, prims), prim_off});
+    if (g.grid.nx > 0) {
+      ptr_fixups.push_back({gbase + offsetof(DevGeometry<T>, cell_start), grid_start_off});
+      ptr_fixups.push_back({gbase + offsetof(DevGeometry<T>, cell_prim), grid_prim_off});
+      ptr_fixups.push_back({gbase + offsetof(DevGeometry<T>, cell_segs), grid_seg_off});
+    }
   }
   return off_struct;
 }
@@ -467,6 +499,9 @@ wos_status wos_problem_create(const wos_problem_desc* desc, int device, wos_prob
   p->n_prims = g.n_prims;
   p->n_nodes = (int64_t)(g.topo.child.size() / 2);
   p->depth = g.topo.depth;
+  p->grid_nx = g.grid.nx;
+  p->grid_ny = g.grid.ny;
+  p->grid_candidates = (int64_t)g.grid.prim.size();
   Blob blob;
   std::vector<std::pair<size_t, size_t>> fix;
   p->off32 = layout_problem<float>(blob, d, g, fix);
@@ -594,6 +629,14 @@ wos_status wos_problem_bvh_info(const wos_problem* p, int64_t* n_nodes, int32_t*
   if (n_nodes) *n_nodes = p->n_nodes;
   if (depth) *depth = p->depth;
   if (n_prims) *n_prims = p->n_prims;
+  return WOS_OK;
+}
+
+wos_status wos_problem_grid_info(const wos_problem* p, int32_t* nx, int32_t* ny, int64_t* n_candidates) {
+  if (!p) return fail(WOS_ERR_INVALID_ARG, "null problem");
+  if (nx) *nx = p->grid_nx;
+  if (ny) *ny = p->grid_ny;
+  if (n_candidates) *n_candidates = p->grid_candidates;
   return WOS_OK;
 }
 

@@ -63,6 +63,7 @@ struct Tally {
   uint32_t nodes;        // BVH inner nodes visited
   uint32_t prims;        // primitives whose distance was computed
   uint32_t trials_free;  // radius proposals drawn from the free-space law
+  uint32_t cells;        // candidate-grid lookups
 };
 
 // ------------------------------------------------------------------ Philox4x32-10
@@ -85,12 +86,17 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
 }
 
 // Per-walk counter-based stream: key = seed, counter = (block, walk, point, problem).
+// Words come from an 8-word buffer. The walker refills it at the top of every step, in
+// lockstep across the wave (two Philox blocks), so the cipher does not run inside the
+// divergent branches that consume the words; a branch that runs out refills on its own.
+// Words left over at the end of a step are skipped, so the stream of a walk is a fixed
+// function of (seed, walk, point, problem) whatever the schedule.
 struct Rng {
   uint2 key;
   uint32_t walk, point, problem;
   uint32_t block;   // next block index
-  uint4 buf;
-  uint32_t pos;     // words of buf already used (4 = empty)
+  uint4 b0, b1;
+  uint32_t pos;     // words of the buffer already used (8 = empty)
 
   __device__ __forceinline__ void init(uint64_t seed, uint32_t w, uint32_t p, uint32_t prob) {
     key = make_uint2((uint32_t)seed, (uint32_t)(seed >> 32));
@@ -98,15 +104,19 @@ struct Rng {
     point = p;
     problem = prob;
     block = 0;
-    pos = 4;
+    pos = 8;
+  }
+  __device__ __forceinline__ void refill() {
+    b0 = philox4x32_10(make_uint4(block, walk, point, problem), key);
+    b1 = philox4x32_10(make_uint4(block + 1, walk, point, problem), key);
+    block += 2;
+    pos = 0;
   }
   __device__ __forceinline__ uint32_t next() {
-    if (pos >= 4) {
-      buf = philox4x32_10(make_uint4(block, walk, point, problem), key);
-      ++block;
-      pos = 0;
-    }
-    const uint32_t v = pos == 0 ? buf.x : pos == 1 ? buf.y : pos == 2 ? buf.z : buf.w;
+    if (pos >= 8) refill();
+    const uint4 q = pos < 4 ? b0 : b1;
+    const uint32_t k = pos & 3;
+    const uint32_t v = k == 0 ? q.x : k == 1 ? q.y : k == 2 ? q.z : q.w;
     ++pos;
     return v;
   }
@@ -746,14 +756,33 @@ struct LdsStack {
 };
 
 // Nearest primitive by BVH traversal; returns squared distance and primitive index.
+template <typename T, int DIM>
+__device__ __forceinline__ T prim_dist2(const WOS_GLOBAL T* prims, const T* x, int pi) {
+  if (DIM == 2) {
+    T tp;
+    return segment_dist2<T>(x, prims + (size_t)pi * kPrimStride2, &tp);
+  }
+  return triangle_dist2<T>(x, prims + (size_t)pi * kPrimStride3);
+}
+
+// Nearest primitive by BVH traversal; returns squared distance and primitive index.
+// `hint` (>= 0) is a primitive whose distance seeds the bound: a walk moves by at most
+// the previous distance per step, so the previous closest primitive is usually still
+// closest or nearly so, and the traversal then prunes all but a few nodes. The result
+// is the exact nearest distance either way.
 template <typename T, int DIM, bool COUNT = false>
 __device__ __forceinline__ T bvh_nearest(G<DevGeometry<T>>& g, const T* x, int* best_prim, Tally* tally = nullptr,
-                                         LdsStack<T> lds = LdsStack<T>{nullptr, nullptr, 0}) {
+                                         LdsStack<T> lds = LdsStack<T>{nullptr, nullptr, 0}, int hint = -1) {
   if (lds.node && g.depth <= kLdsStackDepth) {
     const WOS_GLOBAL BvhNode<T, DIM>* nodes = (const WOS_GLOBAL BvhNode<T, DIM>*)g.nodes;
     const WOS_GLOBAL T* prims = gptr(g.prims);
     T best = Consts<T>::kInf;
     int bp = -1;
+    if (hint >= 0) {
+      best = prim_dist2<T, DIM>(prims, x, hint);
+      bp = hint;
+      if constexpr (COUNT) ++tally->prims;
+    }
     int sp = 0;
     int cur = g.root;
     T cur_d = 0;
@@ -865,7 +894,7 @@ __device__ __forceinline__ T bvh_nearest(G<DevGeometry<T>>& g, const T* x, int* 
 // closest_point needs to recover xbar.
 template <typename T, int DIM, int GEOM, bool COUNT = false>
 __device__ __forceinline__ T boundary_distance(G<DevGeometry<T>>& g, const T* x, int* prim, Tally* tally = nullptr,
-                                               LdsStack<T> lds = LdsStack<T>{nullptr, nullptr, 0}) {
+                                               LdsStack<T> lds = LdsStack<T>{nullptr, nullptr, 0}, int hint = -1) {
   if (GEOM == GK_BALL) {
     T r2 = 0;
 #pragma unroll
@@ -887,7 +916,37 @@ __device__ __forceinline__ T boundary_distance(G<DevGeometry<T>>& g, const T* x,
     *prim = best;
     return d;
   } else {
-    return m_sqrt(bvh_nearest<T, DIM, COUNT>(g, x, prim, tally, lds));
+    if constexpr (GEOM == GK_POLYGON) {
+      if (g.grid_nx > 0) {
+        // candidate grid: scan the list of the cell that contains x
+        const T fx = (x[0] - g.grid_lo[0]) * g.grid_inv_h;
+        const T fy = (x[1] - g.grid_lo[1]) * g.grid_inv_h;
+        if (fx >= (T)0 && fy >= (T)0 && fx < (T)g.grid_nx && fy < (T)g.grid_ny) {
+          const int c = (int)fy * g.grid_nx + (int)fx;
+          const uint32_t b = gptr(g.cell_start)[c], e = gptr(g.cell_start)[c + 1];
+          if (e > b) {
+            const WOS_GLOBAL T* segs = gptr(g.cell_segs);
+            T best = Consts<T>::kInf;
+            uint32_t bk = b;
+            for (uint32_t k = b; k < e; ++k) {
+              T tp;
+              const T d2 = segment_dist2<T>(x, segs + (size_t)k * 4, &tp);
+              if (d2 < best) {
+                best = d2;
+                bk = k;
+              }
+            }
+            if constexpr (COUNT) {
+              ++tally->cells;
+              tally->prims += e - b;
+            }
+            *prim = gptr(g.cell_prim)[bk];
+            return m_sqrt(best);
+          }
+        }
+      }
+    }
+    return m_sqrt(bvh_nearest<T, DIM, COUNT>(g, x, prim, tally, lds, hint));
   }
 }
 

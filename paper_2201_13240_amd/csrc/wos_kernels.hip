@@ -63,7 +63,7 @@ struct WalkerArgs {
 // Events counted by the event-counting build of the walker (algorithmic work per step).
 enum Event {
   EV_STEPS = 0, EV_NODES, EV_PRIMS, EV_TRIALS, EV_TRIALS_FREE, EV_VOLUME, EV_EXIT, EV_TERMINAL,
-  EV_GAMMA, EV_WALKS, EV_RR_TESTS, EV_BALL_LARGE_S, kEvents
+  EV_GAMMA, EV_WALKS, EV_RR_TESTS, EV_BALL_LARGE_S, EV_CELLS, kEvents
 };
 
 constexpr uint32_t kFlagCapped = 1u << 31;
@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* 
     __shared__ T s_dist[kLdsStackDepth * 256];
     lds_stack = LdsStack<T>{s_node + threadIdx.x, s_dist + threadIdx.x, (int)blockDim.x};
   }
-  Tally tally = {0, 0, 0};
+  Tally tally = {0, 0, 0, 0};
   uint32_t ev[kEvents];
   if constexpr (COUNT) {
     for (int e = 0; e < kEvents; ++e) ev[e] = 0;
@@ -109,6 +109,7 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* 
   bool gx_known = false;
   T Pi = 1, A = 0, Ac = 0;
   uint32_t nsteps = 0, ntrials = 0;
+  int last_prim = -1;   // closest primitive of the previous step (bounds the next query)
   Rng rng;
 
   for (;;) {
@@ -164,6 +165,7 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* 
           Pi = 1;
           A = 0;
           Ac = 0;
+          last_prim = -1;
           phase = 1;
           if constexpr (COUNT) {
             ++ev[EV_GAMMA];
@@ -195,6 +197,7 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* 
       b.pb = 0;
       b.gnorm = 0;
       b.c2d = 0;
+      if (phase == 2) rng.refill();
       if (phase == 2) {
         if constexpr (COUNT) ++ev[EV_STEPS];
         if (nsteps >= a.max_steps) {
@@ -202,7 +205,8 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* 
           flag = kFlagCapped;
         } else {
           int prim;
-          const T d = boundary_distance<T, DIM, GEOM, COUNT>(P.geom, x, &prim, &tally, lds_stack);
+          const T d = boundary_distance<T, DIM, GEOM, COUNT>(P.geom, x, &prim, &tally, lds_stack, last_prim);
+          last_prim = prim;
           ++nsteps;
           if (!(d == d)) {
             // a non-finite position cannot continue; report the walk as cut
@@ -328,6 +332,7 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* 
     ev[EV_NODES] = tally.nodes;
     ev[EV_PRIMS] = tally.prims;
     ev[EV_TRIALS_FREE] = tally.trials_free;
+    ev[EV_CELLS] = tally.cells;
     for (int e = 0; e < kEvents; ++e) {
       uint64_t val = ev[e];
       for (int off = 32; off > 0; off >>= 1) val += __shfl_xor(val, off);

@@ -62,7 +62,7 @@ class BatchItem(C.Structure):
 
 
 # Every symbol declared in include/wos.h.
-EXPORTS = ["wos_last_error", "wos_version", "wos_problem_create", "wos_problem_info", "wos_problem_bvh_info",
+EXPORTS = ["wos_last_error", "wos_version", "wos_problem_create", "wos_problem_info", "wos_problem_bvh_info", "wos_problem_grid_info",
            "wos_problem_destroy", "wos_solve", "wos_count_events", "wos_finalize", "wos_plan_create", "wos_plan_launch",
            "wos_plan_info", "wos_plan_destroy", "wos_eval_coefficients", "wos_eval_distance", "wos_eval_ball",
            "wos_sample_radius", "wos_philox", "wos_eval_bessel", "wos_classify"]
@@ -83,6 +83,7 @@ def lib():
         L.wos_problem_create.argtypes = [C.POINTER(ProblemDesc), C.c_int, C.POINTER(vp)]
         L.wos_problem_info.argtypes = [vp, dp, dp, dp]
         L.wos_problem_bvh_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i32), C.POINTER(i64)]
+        L.wos_problem_grid_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i64)]
         L.wos_problem_destroy.argtypes = [vp]
         L.wos_solve.argtypes = [C.POINTER(BatchItem), i32, C.POINTER(Options), vp]
         L.wos_count_events.argtypes = [C.POINTER(BatchItem), i32, C.POINTER(Options), vp, vp]
@@ -199,6 +200,11 @@ class Problem:
         _check(lib().wos_problem_bvh_info(self.handle, C.byref(n), C.byref(dpt), C.byref(p)))
         return {"nodes": n.value, "depth": dpt.value, "prims": p.value}
 
+    def grid_info(self):
+        nx, ny, nc = C.c_int32(), C.c_int32(), C.c_int64()
+        _check(lib().wos_problem_grid_info(self.handle, C.byref(nx), C.byref(ny), C.byref(nc)))
+        return {"nx": nx.value, "ny": ny.value, "candidates": nc.value}
+
     @property
     def sigma_bar(self):
         return self.info()["sigma_bar"]
@@ -271,7 +277,7 @@ def solve(entries, opt, stream=None):
 
 
 EVENT_NAMES = ["steps", "bvh_nodes", "prims", "trials", "trials_free", "volume", "exit", "terminal", "gamma_evals",
-               "walks", "rr_draws", "ball_large_s"]
+               "walks", "rr_draws", "ball_large_s", "grid_cells"]
 
 
 def count_events(entries, opt, stream=None):
