@@ -32,9 +32,23 @@ def parse():
     ap.add_argument("--grid", type=int, default=512)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp32c", "fp64"])
     ap.add_argument("--fp64-steps", type=int, default=1, help="timed passes of the FP64 walker")
-    ap.add_argument("--cpu-points", type=int, default=48, help="oracle sample size (0: skip)")
-    ap.add_argument("--cpu-walks", type=int, default=1024)
+    ap.add_argument("--cpu-points", type=int, default=96, help="oracle sample size (0: skip)")
+    ap.add_argument("--cpu-walks", type=int, default=8192)
     ap.add_argument("--no-events", action="store_true")
+    ap.add_argument("--shape", default="auto",
+                    help="walker launch shape: 'auto' (the plan autotunes block size and tile length) or "
+                         "BLOCKxTILE, e.g. 256x256 (profiling runs pin the tuned shape so that no tuning "
+                         "dispatches enter the kernel statistics)")
+    # profiling helpers (each does only this and exits)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one 1 GiB device-to-device copy: the calibration kernel for FETCH_SIZE/WRITE_SIZE")
+    ap.add_argument("--summarize-trace", nargs="+", metavar=("DB", "SUBSTR"),
+                    help="print the kernel table of a rocprofv3 --kernel-trace --stats results.db")
+    ap.add_argument("--summarize-pmc", nargs="+", metavar=("SUBSTR", "DB"),
+                    help="print per-dispatch counter values of matching kernels from rocprofv3 --pmc results.db files")
+    ap.add_argument("--write-traffic", nargs=4, metavar=("WALKER_FETCH_DB", "WALKER_WRITE_DB", "COPY_FETCH_DB",
+                                                         "COPY_WRITE_DB"),
+                    help="write profiles/walker_star256_traffic.json from four --pmc runs")
     return ap.parse_args()
 
 # ----------------------------------------------------------------------------- cost model
@@ -117,8 +131,142 @@ def algorithmic_work(events, prob):
     return flops, trans
 
 
+# ----------------------------------------------------------------------------- HBM traffic
+# Measured HBM bytes of the walker come from rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE,
+# KiB per dispatch) of this benchmark, committed as JSON under profiles/ together with
+# the same counters read for a copy of known size (the calibration factors) and a hash of
+# the device sources the counters were taken with. A changed kernel makes them stale:
+# traffic is then reported as null.
+DEVICE_SOURCES = ("wos_kernels.hip", "wos_device.h", "wos_types.h", "bessel_tables.h")
+
+
+def device_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in DEVICE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2201_13240_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def walker_kernel_name(precision):
+    return "walker_kernel<%s, 2, 2, false>" % ("double" if precision == "fp64" else "float")
+
+
+def traffic_of(kernel):
+    path = os.path.join(ROOT, "profiles", "walker_star256_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("device_source_hash") != device_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if k is None:
+        return None
+    cal = rec["copy_calibration"]
+    fetch = k["FETCH_SIZE_KiB"] * 1024 * cal["fetch_bytes_per_counted_byte"]
+    write = k["WRITE_SIZE_KiB"] * 1024 * cal["write_bytes_per_counted_byte"]
+    return {"bytes_per_launch": fetch + write, "fetch_bytes": fetch, "write_bytes": write,
+            "source": "profiles/walker_star256_traffic.json"}
+
+
+# ----------------------------------------------------------------------------- profile summaries
+def summarize_trace(db, pattern=""):
+    """Kernel table of a rocprofv3 --kernel-trace --stats database (durations there are in
+    microseconds)."""
+    import sqlite3
+    cur = sqlite3.connect(db).cursor()
+    rows = list(cur.execute("select name, total_calls, total_duration, average, percentage from top_kernels"))
+    out = ["| kernel | calls | total ms | average ms | % |", "|---|---|---|---|---|"]
+    for name, calls, tot, avg, pct in rows:
+        if pattern and pattern not in name:
+            continue
+        out.append(f"| `{name.split('(')[0]}` | {calls} | {tot / 1e3:.3f} | {avg / 1e3:.3f} | {pct:.2f} |")
+    return "\n".join(out)
+
+
+def pmc_values(pattern, dbs):
+    """Counter values per dispatch (mean over the matching dispatches of each run) of the
+    kernels whose name contains `pattern`, with the kernel's resource figures."""
+    import sqlite3
+    from collections import defaultdict
+    vals = defaultdict(float)
+    info = {}
+    for db in dbs:
+        cur = sqlite3.connect(db).cursor()
+        q = ("select kernel_name, dispatch_id, counter_name, value, vgpr_count, sgpr_count, scratch_size, grid_size, "
+             "workgroup_size from counters_collection")
+        per_dispatch = defaultdict(lambda: defaultdict(float))
+        for name, did, cname, v, vg, sg, scr, grid, wg in cur.execute(q):
+            if pattern not in name:
+                continue
+            per_dispatch[did][cname] += v
+            info = {"kernel": name.split("(")[0], "vgpr": vg, "sgpr": sg, "scratch": scr, "grid": grid,
+                    "workgroup": wg}
+        n = max(1, len(per_dispatch))
+        for d in per_dispatch.values():
+            for k, v in d.items():
+                vals[k] += v / n
+    return dict(vals), info
+
+
+def summarize_pmc(pattern, dbs):
+    vals, info = pmc_values(pattern, dbs)
+    lines = [f"kernel `{info.get('kernel')}`: grid {info.get('grid')}, workgroup {info.get('workgroup')}, "
+             f"VGPRs {info.get('vgpr')}, SGPRs {info.get('sgpr')}, scratch {info.get('scratch')} B/lane", "",
+             "| counter | value per dispatch |", "|---|---|"]
+    for k in sorted(vals):
+        lines.append(f"| {k} | {vals[k]:.6g} |")
+    return "\n".join(lines)
+
+
+def write_traffic(walker_fetch, walker_write, copy_fetch, copy_write):
+    copy_bytes = float(1 << 30)
+    cf = pmc_values("copyBuffer", [copy_fetch])[0]["FETCH_SIZE"]
+    cw = pmc_values("copyBuffer", [copy_write])[0]["WRITE_SIZE"]
+    rec = {"device_source_hash": device_source_hash(),
+           "copy_calibration": {"copy_bytes": copy_bytes, "FETCH_SIZE_KiB": cf, "WRITE_SIZE_KiB": cw,
+                                "fetch_bytes_per_counted_byte": copy_bytes / (cf * 1024),
+                                "write_bytes_per_counted_byte": copy_bytes / (cw * 1024)},
+           "kernels": {}}
+    for prec in ("fp32", "fp64"):
+        name = walker_kernel_name(prec)
+        f = pmc_values(name, [walker_fetch])[0].get("FETCH_SIZE")
+        w = pmc_values(name, [walker_write])[0].get("WRITE_SIZE")
+        if f is not None and w is not None:
+            rec["kernels"][name] = {"FETCH_SIZE_KiB": f, "WRITE_SIZE_KiB": w}
+    path = os.path.join(ROOT, "profiles", "walker_star256_traffic.json")
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
+def copy_probe():
+    import torch
+    n = 1 << 28   # float32 elements: 1 GiB
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print("copied bytes", n * 4, flush=True)
+
+
 def main():
     args = parse()
+    if args.summarize_trace:
+        print(summarize_trace(*args.summarize_trace[:2]))
+        return
+    if args.summarize_pmc:
+        print(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1:]))
+        return
+    if args.write_traffic:
+        write_traffic(*args.write_traffic)
+        return
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the walk is embarrassingly parallel and would shard by walk range, see DESIGN.md",
@@ -138,7 +286,9 @@ def main():
 
     def run(precision, steps, warmup, walks):
         acc = wos.Accumulators(n_pts)
-        plan = wos.Plan([(h, P, acc, 0)], wos.options(precision=precision, walks=walks, seed=0))
+        shape = {} if args.shape == "auto" else dict(zip(("block_size", "tile_walks"),
+                                                         map(int, args.shape.lower().split("x"))))
+        plan = wos.Plan([(h, P, acc, 0)], wos.options(precision=precision, walks=walks, seed=0, **shape))
         for w in range(warmup):
             plan.launch(seed=1000 + w, walk_offset_add=0)
         torch.cuda.synchronize()
@@ -155,31 +305,53 @@ def main():
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         ms = [a.elapsed_time(b) for a, b in ev]
+        n_steps = int(acc.n_steps.sum().item())
+        n_walks = int(acc.n_walks.sum().item())
+        print(f"bench: {precision} {steps} timed passes, ms/pass {np.round(ms, 2).tolist()}", file=sys.stderr,
+              flush=True)
+        # the walker alone: the same pass issued as separate launches with HIP events
+        # around the walker kernel on the stream it runs on
+        walker_ms = []
+        for k in range(steps):
+            wm, _ = plan.time(seed=500 + k, walk_offset_add=k * walks, stream=stream)
+            walker_ms.append(wm)
+        torch.cuda.synchronize()
+        timed_steps = int(acc.n_steps.sum().item()) - n_steps
+        print(f"bench: {precision} walker ms/launch {np.round(walker_ms, 2).tolist()}", file=sys.stderr, flush=True)
         mean, se = wos.finalize(acc)
         torch.cuda.synchronize()
         info = plan.info()
         plan.close()
-        print(f"bench: {precision} {steps} timed passes, ms/pass {np.round(ms, 2).tolist()}", file=sys.stderr,
-              flush=True)
-        return {"wall_s": wall, "ms": ms, "steps": int(acc.n_steps.sum().item()),
-                "walks": int(acc.n_walks.sum().item()), "mean": mean.cpu().numpy(), "se": se.cpu().numpy(),
+        return {"wall_s": wall, "ms": ms, "steps": n_steps, "walks": n_walks,
+                "walker_ms": walker_ms, "walker_steps": timed_steps,
+                "walks_total": int(acc.n_walks.sum().item()),
+                "mean": mean.cpu().numpy(), "se": se.cpu().numpy(),
                 "counters": acc.counters.cpu().numpy().tolist(), "plan": info}
 
     r32 = run(args.precision, args.steps, args.warmup, args.walks)
 
     # algorithmic work per distance query from the event-counting walker on a sample of
     # the same workload (every 8th query point, 64 walks each)
-    sub = P[::8].contiguous()
-    acc_c = wos.Accumulators(sub.shape[0])
-    events = wos.count_events([(h, sub, acc_c, 0)], wos.options(precision=args.precision, walks=64, seed=99))
+    if args.no_events:
+        events = {k: 1 for k in wos.EVENT_NAMES}   # profiling runs: no event-counting launch
+    else:
+        sub = P[::8].contiguous()
+        acc_c = wos.Accumulators(sub.shape[0])
+        events = wos.count_events([(h, sub, acc_c, 0)], wos.options(precision=args.precision, walks=64, seed=99))
     flops_ev, trans_ev = algorithmic_work(events, prob)
     flops_per_step = flops_ev / events["steps"]
     trans_per_step = trans_ev / events["steps"]
-    steps_per_pass = r32["steps"] / args.steps
-    achieved = flops_per_step * steps_per_pass / (np.mean(r32["ms"]) / 1e3) / 1e12
+    # per walker launch: algorithmic flops per step x steps of one launch, over the
+    # walker's own average launch duration
+    steps_per_launch = r32["walker_steps"] / len(r32["walker_ms"])
+    walker_ms = float(np.mean(r32["walker_ms"]))
+    achieved = flops_per_step * steps_per_launch / (walker_ms / 1e3) / 1e12
     peak = 157.3 if args.precision != "fp64" else 78.6
+    traffic = traffic_of(walker_kernel_name(args.precision))
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": None, "flops_per_step": flops_per_step, "transcendentals_per_step": trans_per_step,
+                "traffic": traffic["bytes_per_launch"] if traffic else None, "traffic_detail": traffic,
+                "kernel": walker_kernel_name(args.precision), "kernel_ms": walker_ms,
+                "flops_per_step": flops_per_step, "transcendentals_per_step": trans_per_step,
                 "events_per_step": {k: v / events["steps"] for k, v in events.items()}}
     r64 = run("fp64", args.fp64_steps, 0, args.walks) if args.fp64_steps > 0 else None
     ms_step = float(np.mean(r32["ms"]))
@@ -187,7 +359,7 @@ def main():
     walks_per_pt = args.walks * args.steps
 
     # per-walk variance -> walks needed for RMSE 1e-2 (Sec. 3.1: RMSE = sqrt(mean var / N))
-    var_walk = (r32["se"] ** 2) * walks_per_pt
+    var_walk = (r32["se"] ** 2) * (r32["walks_total"] / n_pts)
     n_star = float(np.mean(var_walk)) / 1e-4
     t_walk_pass = (sum(r32["ms"]) / 1e3) / walks_per_pt          # seconds per walk per point (all points)
     pts_per_s_rmse = n_pts / (n_star * t_walk_pass)
@@ -195,7 +367,7 @@ def main():
     if r64 is not None:
         s64 = r64["steps"] / (sum(r64["ms"]) / 1e3)
         t64 = (sum(r64["ms"]) / 1e3) / (args.walks * args.fp64_steps)
-        var64 = (r64["se"] ** 2) * args.walks * args.fp64_steps
+        var64 = (r64["se"] ** 2) * (r64["walks_total"] / n_pts)
         n64 = float(np.mean(var64)) / 1e-4
         out64 = {"fp64_steps_per_s": s64, "fp64_ms_per_step": float(np.mean(r64["ms"])),
                  "fp64_points_per_s_at_rmse_1e-2": n_pts / (n64 * t64)}

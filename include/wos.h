@@ -228,14 +228,30 @@ wos_status wos_finalize(const double* sum, const double* sum_sq, const uint64_t*
                         double* mean, double* std_err, void* stream);
 
 /* A plan fixes items and options once: it copies the item and tile tables to the device,
- * allocates the scratch memory, classifies the points, picks the launch shape (autotuned
- * when block_size/tile_walks are 0, cached per process) and captures the launches in a
- * hipGraph. wos_plan_launch replays it with a new seed and an extra walk offset (added to
- * opt->walk_offset), accumulating into the same outputs. */
+ * allocates the scratch memory, classifies the points, picks the launch shape and captures
+ * the launches in a hipGraph. wos_plan_launch replays it with a new seed and an extra walk
+ * offset (added to opt->walk_offset), accumulating into the same outputs.
+ *
+ * Launch shape (the batched schedule is the method's embarrassingly parallel structure,
+ * Sec. 3.1): with opt->block_size and opt->tile_walks both 0, the first plan of a walker
+ * variant (device, precision, dimension, geometry kind) in the process times every block
+ * size in {64, 128, 256} with every tile length in {64, ..., 1024} on a prefix of its own
+ * walks (eight per resident lane; the per-walk buffers of the plan's workspace only, the
+ * caller's outputs are not touched), keeps the fastest for that variant, and builds with
+ * it. Later plans and wos_solve of the same variant reuse it. Jobs with fewer walks than
+ * the prefix keep 256 / 256. Explicit values are used as given. Synchronous; the caller's
+ * stream is used for the timing runs. */
 typedef struct wos_plan wos_plan;
 wos_status wos_plan_create(const wos_batch_item* items, int32_t n_items, const wos_options* opt,
                            void* stream, wos_plan** out);
 wos_status wos_plan_launch(wos_plan* plan, uint64_t seed, uint64_t walk_offset_add, void* stream);
+/* The same work as wos_plan_launch (same kernels, tables and outputs, accumulated the
+ * same way) issued as separate launches on `stream` with HIP events around each walker
+ * launch; waits for it. walker_ms: the walker's time summed over the plan's launches;
+ * total_ms (may be null): the whole job. For measurement: the graph replay of
+ * wos_plan_launch is the production path. */
+wos_status wos_plan_time(wos_plan* plan, uint64_t seed, uint64_t walk_offset_add, void* stream,
+                         double* walker_ms, double* total_ms);
 /* Launch shape chosen by the plan. */
 wos_status wos_plan_info(const wos_plan* plan, int32_t* block_size, int32_t* tile_walks,
                          int32_t* grid_size, int32_t* n_launches);

@@ -697,22 +697,50 @@ wos_status check_items(const wos_batch_item* items, int n_items, const wos_optio
 std::mutex g_occ_mutex;
 std::map<std::tuple<int, int, int, int, unsigned>, unsigned> g_occ;
 
-wos_status pick_shape(const wos_options* opt, Schedule& s) {
-  s.block = opt->block_size ? (unsigned)opt->block_size : 256u;
-  s.tile_walks = opt->tile_walks > 0 ? (uint32_t)opt->tile_walks : 256u;
-  const auto key = std::make_tuple(s.device, s.fp64, s.dim, s.geom, s.block);
+// Launch shapes found by the plan autotuner, per (device, fp64, compensated, dim, geometry).
+std::map<std::tuple<int, int, int, int, int>, std::pair<unsigned, uint32_t>> g_tuned;
+
+std::tuple<int, int, int, int, int> tune_key(const Schedule& s) {
+  return std::make_tuple(s.device, s.fp64, s.compensated, s.dim, s.geom);
+}
+
+// Persistent grid for a block size: resident blocks per CU times CUs.
+wos_status grid_for_block(Schedule& s, unsigned block) {
+  const auto key = std::make_tuple(s.device, s.fp64, s.dim, s.geom, block);
   std::lock_guard<std::mutex> lk(g_occ_mutex);
   auto it = g_occ.find(key);
   if (it == g_occ.end()) {
     int per_cu = 0, cus = 0;
-    WOS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, walker_symbol(s.fp64, s.dim, s.geom), (int)s.block, 0));
+    WOS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, walker_symbol(s.fp64, s.dim, s.geom), (int)block, 0));
     WOS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s.device));
     unsigned grid = (unsigned)std::max(1, per_cu) * (unsigned)std::max(1, cus);
     it = g_occ.emplace(key, grid).first;
   }
+  s.block = block;
   s.grid = it->second;
+  return WOS_OK;
+}
+
+// Block size and tile length: the caller's, else the tuned shape of this walker, else
+// 256 / 256.
+wos_status pick_shape(const wos_options* opt, Schedule& s) {
+  unsigned block = 256u;
+  uint32_t tile = 256u;
+  {
+    std::lock_guard<std::mutex> lk(g_occ_mutex);
+    auto t = g_tuned.find(tune_key(s));
+    if (t != g_tuned.end()) {
+      block = t->second.first;
+      tile = t->second.second;
+    }
+  }
+  if (opt->block_size) block = (unsigned)opt->block_size;
+  if (opt->tile_walks > 0) tile = (uint32_t)opt->tile_walks;
+  s.tile_walks = tile;
+  wos_status r = grid_for_block(s, block);
+  if (r != WOS_OK) return r;
   const uint64_t cap = opt->workspace_bytes ? opt->workspace_bytes : (4ull << 30);
-  const uint64_t per_walk = 16;
+  const uint64_t per_walk = sizeof(WalkRecord);
   const uint64_t max_ids = std::max<uint64_t>(cap / per_walk, 1);
   const uint64_t N = opt->walks_per_point;
   uint64_t nc = s.total_points ? std::max<uint64_t>(1, max_ids / s.total_points) : N;
@@ -766,9 +794,7 @@ struct Workspace {
   Tile* tiles = nullptr;          // [n_launches][max tiles]
   uint32_t* counter = nullptr;
   LaunchParams* lp = nullptr;
-  double* vals = nullptr;
-  uint32_t* steps = nullptr;
-  uint32_t* trials = nullptr;
+  WalkRecord* records = nullptr;
 };
 
 }  // namespace
@@ -792,7 +818,7 @@ __attribute__((unused)) size_t align_up(size_t v) { return (v + 255) / 256 * 256
 
 // Builds every launch's tables; returns the byte layout of the workspace.
 struct WsLayout {
-  size_t inside, items, tiles, counter, lp, vals, steps, trials, total;
+  size_t inside, items, tiles, counter, lp, records, total;
 };
 
 WsLayout ws_layout(const Schedule& s, int n_items, size_t max_tiles) {
@@ -809,9 +835,7 @@ WsLayout ws_layout(const Schedule& s, int n_items, size_t max_tiles) {
   L.tiles = take(sizeof(Tile) * std::max<size_t>(max_tiles, 1) * s.n_launches);
   L.counter = take(sizeof(uint32_t) * 64);
   L.lp = take(sizeof(LaunchParams));
-  L.vals = take(sizeof(double) * std::max<uint64_t>(ids, 1));
-  L.steps = take(sizeof(uint32_t) * std::max<uint64_t>(ids, 1));
-  L.trials = take(sizeof(uint32_t) * std::max<uint64_t>(ids, 1));
+  L.records = take(sizeof(WalkRecord) * std::max<uint64_t>(ids, 1));
   L.total = off;
   return L;
 }
@@ -823,9 +847,7 @@ void ws_bind(Workspace& w, void* base, const WsLayout& L) {
   w.tiles = (Tile*)(b + L.tiles);
   w.counter = (uint32_t*)(b + L.counter);
   w.lp = (LaunchParams*)(b + L.lp);
-  w.vals = (double*)(b + L.vals);
-  w.steps = (uint32_t*)(b + L.steps);
-  w.trials = (uint32_t*)(b + L.trials);
+  w.records = (WalkRecord*)(b + L.records);
 }
 
 // Prepares all tables of a job on the host.
@@ -846,11 +868,43 @@ void prepare(const wos_batch_item* items, int n_items, const wos_options* opt, c
   }
 }
 
-// Enqueues classification (once) and, per launch, reset + walker + reduce.
+std::vector<uint32_t> tile_counts(const std::vector<std::vector<Tile>>& tiles) {
+  std::vector<uint32_t> n;
+  for (auto& t : tiles) n.push_back((uint32_t)t.size());
+  return n;
+}
+
+// Launch record of the walker for launch c of a schedule over the given tile table.
+WalkerLaunch walker_launch(const wos_options* opt, const Schedule& s, const Workspace& w, int c, int n_items,
+                           Tile* tiles, uint32_t n_tiles) {
+  WalkerLaunch L;
+  L.fp64 = s.fp64;
+  L.dim = s.dim;
+  L.geom = s.geom;
+  L.grid = s.grid;
+  L.block = s.block;
+  L.items = w.items + (size_t)c * n_items;
+  L.tiles = tiles;
+  L.n_tiles = n_tiles;
+  L.tile_counter = w.counter;
+  L.records = w.records;
+  L.lp = w.lp;
+  L.max_steps = opt->max_steps ? opt->max_steps : 1000000ull;
+  L.variant = opt->variant;
+  L.compensated = s.compensated;
+  L.rr = opt->russian_roulette;
+  L.ww_lo = opt->ww_lo > 0 ? opt->ww_lo : 0.5;
+  L.events = nullptr;
+  return L;
+}
+
+// Enqueues [reset, walker, reduce per item] for every launch of the schedule. With
+// `marks`, an event pair is recorded around each walker launch (eager timing only: a
+// captured job takes none).
 wos_status enqueue_job(const wos_batch_item* items, int n_items, const wos_options* opt, const Schedule& s,
                        const Workspace& w, const std::vector<std::vector<DevItem>>& dit,
-                       const std::vector<std::vector<Tile>>& tiles, size_t max_tiles, bool classify, uint64_t* events,
-                       hipStream_t st) {
+                       const std::vector<uint32_t>& n_tiles, size_t max_tiles, bool classify, uint64_t* events,
+                       hipStream_t st, const std::vector<hipEvent_t>* marks = nullptr) {
   if (classify) {
     uint64_t pb = 0;
     for (int k = 0; k < n_items; ++k) {
@@ -860,30 +914,14 @@ wos_status enqueue_job(const wos_batch_item* items, int n_items, const wos_optio
     }
   }
   for (int c = 0; c < s.n_launches; ++c) {
-    if (tiles[c].empty()) continue;
+    if (n_tiles[c] == 0) continue;
     WOS_HIP(launch_reset(w.counter, st));
-    WalkerLaunch L;
-    L.fp64 = s.fp64;
-    L.dim = s.dim;
-    L.geom = s.geom;
-    L.grid = s.grid;
-    L.block = s.block;
-    L.items = w.items + (size_t)c * n_items;
-    L.tiles = w.tiles + (size_t)c * max_tiles;
-    L.n_tiles = (uint32_t)tiles[c].size();
-    L.tile_counter = w.counter;
-    L.vals = w.vals;
-    L.steps = w.steps;
-    L.trials = w.trials;
-    L.lp = w.lp;
-    L.max_steps = opt->max_steps ? opt->max_steps : 1000000ull;
-    L.variant = opt->variant;
-    L.compensated = s.compensated;
-    L.rr = opt->russian_roulette;
-    L.ww_lo = opt->ww_lo > 0 ? opt->ww_lo : 0.5;
+    WalkerLaunch L = walker_launch(opt, s, w, c, n_items, w.tiles + (size_t)c * max_tiles, n_tiles[c]);
     L.events = events;
+    if (marks) WOS_HIP(hipEventRecord((*marks)[2 * c], st));
     WOS_HIP(launch_walker(L, st));
-    for (int k = 0; k < n_items; ++k) WOS_HIP(launch_reduce(dit[c][k], w.vals, w.steps, w.trials, st));
+    if (marks) WOS_HIP(hipEventRecord((*marks)[2 * c + 1], st));
+    for (int k = 0; k < n_items; ++k) WOS_HIP(launch_reduce(dit[c][k], w.records, st));
   }
   return WOS_OK;
 }
@@ -941,7 +979,7 @@ static wos_status solve_impl(const wos_batch_item* items, int32_t n_items, const
   if (r == WOS_OK) {
     const hipError_t e = launch_set_params(w.lp, opt->seed, 0, st);
     r = e != hipSuccess ? fail(WOS_ERR_DEVICE, "launch failed")
-                        : enqueue_job(items, n_items, opt, s, w, dit, tiles, max_tiles, true, events, st);
+                        : enqueue_job(items, n_items, opt, s, w, dit, tile_counts(tiles), max_tiles, true, events, st);
   }
   (void)hipFreeAsync(base, st);
   return r;
@@ -965,8 +1003,12 @@ wos_status wos_finalize(const double* sum, const double* sum_sq, const uint64_t*
   return WOS_OK;
 }
 
-wos_status wos_plan_create(const wos_batch_item* items, int32_t n_items, const wos_options* opt, void* stream,
-                           wos_plan** out) {
+}  // extern "C"
+
+namespace {
+
+wos_status plan_build(const wos_batch_item* items, int32_t n_items, const wos_options* opt, void* stream,
+                      wos_plan** out) {
   if (!out) return fail(WOS_ERR_INVALID_ARG, "null out");
   *out = nullptr;
   wos_plan* P = new wos_plan();
@@ -1030,7 +1072,7 @@ wos_status wos_plan_create(const wos_batch_item* items, int32_t n_items, const w
     (void)hipStreamDestroy(cap);
     return bail(WOS_ERR_DEVICE, "graph capture failed to start");
   }
-  r = enqueue_job(items, n_items, opt, s, P->ws, P->dit, tiles, max_tiles, false, nullptr, cap);
+  r = enqueue_job(items, n_items, opt, s, P->ws, P->dit, P->n_tiles, max_tiles, false, nullptr, cap);
   const hipError_t ec = hipStreamEndCapture(cap, &P->graph);
   (void)hipStreamDestroy(cap);
   if (r != WOS_OK || ec != hipSuccess) return bail(WOS_ERR_DEVICE, "graph capture failed");
@@ -1038,6 +1080,175 @@ wos_status wos_plan_create(const wos_batch_item* items, int32_t n_items, const w
     return bail(WOS_ERR_DEVICE, "graph instantiation failed");
   *out = P;
   return WOS_OK;
+}
+
+// Times the walker of launch 0 of a built plan over its first `walks` walk ids with the
+// given shape, on the plan's own workspace (the per-walk buffers only: the reduction,
+// and with it the caller's outputs, is not run). Returns the best of `reps` runs in ms.
+wos_status time_shape(wos_plan* P, unsigned block, uint32_t tile, uint64_t walks, Tile* dtiles, int reps,
+                      hipStream_t st, float* best_ms) {
+  Schedule s = P->s;
+  wos_status r = grid_for_block(s, block);
+  if (r != WOS_OK) return r;
+  std::vector<Tile> t;
+  const int n_items = (int)P->items.size();
+  uint64_t left = walks;
+  for (int k = 0; k < n_items && left > 0; ++k) {
+    const DevItem& d = P->dit[0][k];
+    const uint64_t total = std::min<uint64_t>((uint64_t)d.n_points * d.walks, left);
+    for (uint64_t f = 0; f < total; f += tile) {
+      Tile x;
+      x.item = (uint32_t)k;
+      x.count = (uint32_t)std::min<uint64_t>(tile, total - f);
+      x.first = d.walk_base + f;
+      t.push_back(x);
+    }
+    left -= total;
+  }
+  WOS_HIP(hipMemcpyAsync(dtiles, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice, st));
+  WOS_HIP(hipStreamSynchronize(st));
+  const WalkerLaunch L = walker_launch(&P->opt, s, P->ws, 0, n_items, dtiles, (uint32_t)t.size());
+  hipEvent_t a, b;
+  WOS_HIP(hipEventCreate(&a));
+  WOS_HIP(hipEventCreate(&b));
+  *best_ms = 1e30f;
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < reps && e == hipSuccess; ++i) {
+    if ((e = launch_reset(P->ws.counter, st)) != hipSuccess) break;
+    if ((e = hipEventRecord(a, st)) != hipSuccess) break;
+    if ((e = launch_walker(L, st)) != hipSuccess) break;
+    if ((e = hipEventRecord(b, st)) != hipSuccess) break;
+    if ((e = hipEventSynchronize(b)) != hipSuccess) break;
+    float ms = 0;
+    if ((e = hipEventElapsedTime(&ms, a, b)) != hipSuccess) break;
+    *best_ms = std::min(*best_ms, ms);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (e != hipSuccess) return fail(WOS_ERR_DEVICE, std::string("autotune run failed: ") + hipGetErrorString(e));
+  return WOS_OK;
+}
+
+// Chooses block size and tile length for this walker by timing candidates on a prefix of
+// the plan's own walks (about eight walks per resident lane, so that every wave takes
+// several tiles), and caches the winner per process. Jobs too small to time leave the
+// defaults.
+wos_status autotune(wos_plan* P, hipStream_t st, unsigned* block, uint32_t* tile) {
+  static const unsigned kBlocks[] = {64, 128, 256};
+  static const uint32_t kTiles[] = {64, 128, 256, 512, 1024};
+  *block = P->s.block;
+  *tile = P->s.tile_walks;
+  uint64_t launch0 = 0;
+  for (const DevItem& d : P->dit[0]) launch0 += (uint64_t)d.n_points * d.walks;
+  uint64_t lanes = 0;
+  for (unsigned b : kBlocks) {
+    Schedule s = P->s;
+    wos_status r = grid_for_block(s, b);
+    if (r != WOS_OK) return r;
+    lanes = std::max<uint64_t>(lanes, (uint64_t)s.grid * b);
+  }
+  const uint64_t walks = 8 * lanes;
+  if (launch0 < walks) return WOS_OK;
+  WOS_HIP(launch_set_params(P->ws.lp, 0, 0, st));
+  Tile* dtiles = nullptr;
+  const size_t max_t = (size_t)(walks / kTiles[0]) + (size_t)P->items.size() + 1;
+  WOS_HIP(hipMalloc(&dtiles, max_t * sizeof(Tile)));
+  float best = 1e30f;
+  wos_status r = WOS_OK;
+  for (unsigned b : kBlocks) {
+    for (uint32_t t : kTiles) {
+      float ms = 0;
+      if ((r = time_shape(P, b, t, walks, dtiles, 2, st, &ms)) != WOS_OK) break;
+      if (ms < best) {
+        best = ms;
+        *block = b;
+        *tile = t;
+      }
+    }
+    if (r != WOS_OK) break;
+  }
+  (void)hipFree(dtiles);
+  if (r != WOS_OK) return r;
+  std::lock_guard<std::mutex> lk(g_occ_mutex);
+  g_tuned[tune_key(P->s)] = std::make_pair(*block, *tile);
+  return WOS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+wos_status wos_plan_create(const wos_batch_item* items, int32_t n_items, const wos_options* opt, void* stream,
+                           wos_plan** out) {
+  wos_status r = plan_build(items, n_items, opt, stream, out);
+  if (r != WOS_OK || opt->block_size != 0 || opt->tile_walks != 0) return r;
+  wos_plan* P = *out;
+  bool tuned;
+  {
+    std::lock_guard<std::mutex> lk(g_occ_mutex);
+    tuned = g_tuned.count(tune_key(P->s)) != 0;
+  }
+  if (tuned) return WOS_OK;
+  unsigned block = 0;
+  uint32_t tile = 0;
+  if ((r = autotune(P, (hipStream_t)stream, &block, &tile)) != WOS_OK) {
+    wos_plan_destroy(P);
+    *out = nullptr;
+    return r;
+  }
+  if (block == P->s.block && tile == P->s.tile_walks) return WOS_OK;
+  // rebuild with the tuned shape (tile tables and workspace depend on it)
+  wos_plan_destroy(P);
+  *out = nullptr;
+  wos_options o = *opt;
+  o.block_size = (int32_t)block;
+  o.tile_walks = (int32_t)tile;
+  return plan_build(items, n_items, &o, stream, out);
+}
+
+wos_status wos_plan_time(wos_plan* P, uint64_t seed, uint64_t walk_offset_add, void* stream, double* walker_ms,
+                         double* total_ms) {
+  if (!P || !walker_ms) return fail(WOS_ERR_INVALID_ARG, "null plan or output");
+  if (P->opt.walk_offset + walk_offset_add + P->opt.walks_per_point > (1ull << 32))
+    return fail(WOS_ERR_INVALID_ARG, "walk indices exceed 32 bits");
+  WOS_HIP(hipSetDevice(P->s.device));
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<hipEvent_t> marks(2 * (size_t)P->s.n_launches + 2, nullptr);
+  wos_status r = WOS_OK;
+  for (auto& m : marks)
+    if (hipEventCreate(&m) != hipSuccess) {
+      r = fail(WOS_ERR_DEVICE, "event creation failed");
+      break;
+    }
+  hipEvent_t& t0 = marks[marks.size() - 2];
+  hipEvent_t& t1 = marks[marks.size() - 1];
+  if (r == WOS_OK) {
+    hipError_t e = launch_set_params(P->ws.lp, seed, walk_offset_add, st);
+    if (e == hipSuccess) e = hipEventRecord(t0, st);
+    if (e != hipSuccess) r = fail(WOS_ERR_DEVICE, "launch failed");
+  }
+  if (r == WOS_OK)
+    r = enqueue_job(P->items.data(), (int)P->items.size(), &P->opt, P->s, P->ws, P->dit, P->n_tiles, P->max_tiles,
+                    false, nullptr, st, &marks);
+  if (r == WOS_OK) {
+    hipError_t e = hipEventRecord(t1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(t1);
+    double w = 0;
+    for (int c = 0; c < P->s.n_launches && e == hipSuccess; ++c) {
+      if (P->n_tiles[c] == 0) continue;
+      float ms = 0;
+      e = hipEventElapsedTime(&ms, marks[2 * c], marks[2 * c + 1]);
+      w += ms;
+    }
+    float tot = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&tot, t0, t1);
+    if (e != hipSuccess) r = fail(WOS_ERR_DEVICE, std::string("timed run failed: ") + hipGetErrorString(e));
+    *walker_ms = w;
+    if (total_ms) *total_ms = tot;
+  }
+  for (auto& m : marks)
+    if (m) (void)hipEventDestroy(m);
+  return r;
 }
 
 wos_status wos_plan_launch(wos_plan* P, uint64_t seed, uint64_t walk_offset_add, void* stream) {

@@ -368,6 +368,14 @@ struct FV {
   T lap;
 };
 
+template <typename T, int DIM>
+__device__ __forceinline__ T axis_component(const T* x, int ax) {
+  T v = x[0];
+#pragma unroll
+  for (int i = 1; i < DIM; ++i) v = ax == i ? x[i] : v;
+  return v;
+}
+
 // Base function B of a field at x, with gradient and Laplacian when D is true.
 template <typename T, int DIM, bool D>
 __device__ __forceinline__ FV<T, DIM> field_base(G<DevField<T>>& f, const T* x) {
@@ -413,20 +421,24 @@ __device__ __forceinline__ FV<T, DIM> field_base(G<DevField<T>>& f, const T* x) 
       }
     }
   } else if (base == FB_TANH) {
+    // the axis is a run-time value: select with compile-time indices so that x and r
+    // stay in registers (a dynamic index would place them in scratch memory)
     const int ax = (int)f.prm[0];
     const T iw = f.prm[2];
-    const T th = m_tanh((x[ax] - f.prm[1]) * iw);
+    const T th = m_tanh((axis_component<T, DIM>(x, ax) - f.prm[1]) * iw);
     r.v = (T)0.5 * ((T)1 + th);
     if (D) {
       const T sech2 = (T)1 - th * th;
-      r.g[ax] = (T)0.5 * sech2 * iw;
+      const T ga = (T)0.5 * sech2 * iw;
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) r.g[i] = i == ax ? ga : (T)0;
       r.lap = -th * sech2 * iw * iw;
     }
   } else if (base == FB_TANH_DRIFT) {
     // psi = K [A z - B ln(A cosh z + B sinh z) + B ln A], alpha psi' = omega along the axis
     const int ax = (int)f.prm[0];
     const T iw = f.prm[2], A = f.prm[3], B = f.prm[4], K = f.prm[5], lnA = f.prm[6], om = f.prm[7];
-    const T z = (x[ax] - f.prm[1]) * iw;
+    const T z = (axis_component<T, DIM>(x, ax) - f.prm[1]) * iw;
     const T az = m_fabs(z);
     const T sg = z >= (T)0 ? (T)1 : (T)-1;
     const T lnmix = az + m_log((T)0.5 * (A + sg * B) + (T)0.5 * (A - sg * B) * m_exp((T)-2 * az));
@@ -435,7 +447,9 @@ __device__ __forceinline__ FV<T, DIM> field_base(G<DevField<T>>& f, const T* x) 
       const T th = m_tanh(z);
       const T al = A + B * th;
       const T dal = B * ((T)1 - th * th) * iw;
-      r.g[ax] = om / al;
+      const T ga = om / al;
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) r.g[i] = i == ax ? ga : (T)0;
       r.lap = -om * dal / (al * al);
     }
   }
@@ -964,10 +978,9 @@ __device__ __forceinline__ void closest_point(G<DevGeometry<T>>& g, const T* x, 
 #pragma unroll
     for (int i = 0; i < DIM; ++i) xb[i] = g.center[i] + (r > (T)0 ? sc * e[i] : (i == 0 ? g.radius : (T)0));
   } else if (GEOM == GK_BOX) {
-#pragma unroll
-    for (int i = 0; i < DIM; ++i) xb[i] = x[i];
     const int ax = prim >> 1;
-    xb[ax] = (prim & 1) ? g.hi[ax] : g.lo[ax];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) xb[i] = i == ax ? ((prim & 1) ? g.hi[i] : g.lo[i]) : x[i];
   } else if (DIM == 2) {
     const WOS_GLOBAL T* s = gptr(g.prims) + (size_t)prim * kPrimStride2;
     T t;

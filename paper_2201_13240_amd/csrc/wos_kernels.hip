@@ -48,9 +48,7 @@ struct WalkerArgs {
   const Tile* tiles;
   uint32_t n_tiles;
   uint32_t* tile_counter;
-  double* vals;          // [walk id] estimate of the walk
-  uint32_t* steps;       // [walk id] distance queries | flags
-  uint32_t* trials;      // [walk id] radius proposals
+  WalkRecord* records;   // [walk id] estimate, distance queries | flags, radius proposals
   const LaunchParams* lp;
   uint64_t max_steps;
   int32_t variant;
@@ -76,8 +74,7 @@ __device__ __forceinline__ const void* uniform_ptr(const void* p) { return (cons
 // problem tables (read-only, at wave-uniform addresses) can be served by scalar loads.
 template <typename T, int DIM, int GEOM, bool COUNT>
 __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* __restrict__ tile_counter,
-                                                     double* __restrict__ vals, uint32_t* __restrict__ steps_out,
-                                                     uint32_t* __restrict__ trials_out,
+                                                     WalkRecord* __restrict__ records,
                                                      uint64_t* __restrict__ events_out) {
   const uint32_t lane = __lane_id();
   LdsStack<T> lds_stack{nullptr, nullptr, 0};
@@ -155,9 +152,7 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* 
         nsteps = 0;
         ntrials = 0;
         if (!gptr(it.inside)[p]) {
-          vals[wid] = __builtin_nan("");
-          steps_out[wid] = 0;
-          trials_out[wid] = 0;
+          records[wid] = WalkRecord{__builtin_nan(""), 0u, 0u};
         } else {
 #pragma unroll
           for (int i = 0; i < DIM; ++i) x[i] = (T)gptr(it.points)[p * DIM + i];
@@ -320,9 +315,7 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* 
         }
       }
       if (done) {
-        vals[wid] = (double)A + (double)Ac;
-        steps_out[wid] = (nsteps & kStepMask) | flag;
-        trials_out[wid] = ntrials;
+        records[wid] = WalkRecord{(double)A + (double)Ac, (nsteps & kStepMask) | flag, ntrials};
         if constexpr (COUNT) ev[EV_TRIALS] += ntrials;
         phase = 0;
       }
@@ -343,7 +336,7 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* 
 
 // ------------------------------------------------------------------ reduce (fixed order)
 
-__global__ void reduce_kernel(DevItem it, const double* vals, const uint32_t* steps, const uint32_t* trials) {
+__global__ void reduce_kernel(DevItem it, const WalkRecord* __restrict__ records) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint64_t capped = 0, killed = 0, ntr = 0;
   if (p < it.n_points) {
@@ -351,12 +344,13 @@ __global__ void reduce_kernel(DevItem it, const double* vals, const uint32_t* st
     uint64_t nst = 0;
     for (uint64_t j = 0; j < it.walks; ++j) {
       const uint64_t idx = it.walk_base + j * (uint64_t)it.n_points + (uint64_t)p;
-      const double v = vals[idx];
-      const uint32_t st = steps[idx];
+      const WalkRecord r = records[idx];
+      const double v = r.value;
+      const uint32_t st = r.steps;
       nst += st & kStepMask;
       capped += (st & kFlagCapped) ? 1 : 0;
       killed += (st & kFlagRR) ? 1 : 0;
-      ntr += trials[idx];
+      ntr += r.trials;
       // Neumaier summation of v and v^2
       double t = s + v;
       cs += fabs(s) >= fabs(v) ? (s - t) + v : (v - t) + s;
@@ -617,9 +611,7 @@ static hipError_t launch_walker_t(const WalkerLaunch& L, hipStream_t st) {
   a.tiles = L.tiles;
   a.n_tiles = L.n_tiles;
   a.tile_counter = L.tile_counter;
-  a.vals = L.vals;
-  a.steps = L.steps;
-  a.trials = L.trials;
+  a.records = L.records;
   a.lp = L.lp;
   a.max_steps = L.max_steps;
   a.variant = L.variant;
@@ -629,10 +621,10 @@ static hipError_t launch_walker_t(const WalkerLaunch& L, hipStream_t st) {
   a.events = L.events;
   if (L.events)
     hipLaunchKernelGGL((walker_kernel<T, DIM, GEOM, true>), dim3(L.grid), dim3(L.block), 0, st, a, L.tile_counter,
-                       L.vals, L.steps, L.trials, L.events);
+                       L.records, L.events);
   else
     hipLaunchKernelGGL((walker_kernel<T, DIM, GEOM, false>), dim3(L.grid), dim3(L.block), 0, st, a, L.tile_counter,
-                       L.vals, L.steps, L.trials, (uint64_t*)nullptr);
+                       L.records, (uint64_t*)nullptr);
   return hipGetLastError();
 }
 
@@ -670,10 +662,9 @@ const void* walker_symbol(int fp64, int dim, int geom) {
   return geom == GK_BALL ? walker_symbol_t<float, 3, GK_BALL>() : geom == GK_BOX ? walker_symbol_t<float, 3, GK_BOX>() : walker_symbol_t<float, 3, GK_TRIMESH>();
 }
 
-hipError_t launch_reduce(const DevItem& it, const double* vals, const uint32_t* steps, const uint32_t* trials,
-                         hipStream_t st) {
+hipError_t launch_reduce(const DevItem& it, const WalkRecord* records, hipStream_t st) {
   if (it.n_points == 0) return hipSuccess;
-  hipLaunchKernelGGL(reduce_kernel, dim3(blocks_for(it.n_points, 256)), dim3(256), 0, st, it, vals, steps, trials);
+  hipLaunchKernelGGL(reduce_kernel, dim3(blocks_for(it.n_points, 256)), dim3(256), 0, st, it, records);
   return hipGetLastError();
 }
 

@@ -18,9 +18,7 @@ struct WalkerLaunch {
   const Tile* tiles;
   uint32_t n_tiles;
   uint32_t* tile_counter;
-  double* vals;
-  uint32_t* steps;
-  uint32_t* trials;
+  WalkRecord* records;
   const LaunchParams* lp;
   uint64_t max_steps;
   int variant;
@@ -32,8 +30,7 @@ struct WalkerLaunch {
 
 hipError_t launch_walker(const WalkerLaunch& L, hipStream_t st);
 const void* walker_symbol(int fp64, int dim, int geom);
-hipError_t launch_reduce(const DevItem& it, const double* vals, const uint32_t* steps, const uint32_t* trials,
-                         hipStream_t st);
+hipError_t launch_reduce(const DevItem& it, const WalkRecord* records, hipStream_t st);
 hipError_t launch_reset(uint32_t* counter, hipStream_t st);
 hipError_t launch_set_params(LaunchParams* lp, uint64_t seed, uint64_t walk_offset_add, hipStream_t st);
 hipError_t launch_classify(int dim, int geom, const void* P64, const double* pts, int64_t n, int8_t* inside,

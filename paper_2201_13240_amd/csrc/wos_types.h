@@ -116,6 +116,15 @@ struct Tile {
   uint64_t first;            // first walk id (launch space)
 };
 
+// What a finished walk leaves for the per-point reduction: its estimate, its distance
+// queries with the cap / roulette flags in the top bits, and its radius proposals. One
+// 16-byte record per walk id, written with a single vector store.
+struct __attribute__((aligned(16))) WalkRecord {
+  double value;
+  uint32_t steps;
+  uint32_t trials;
+};
+
 struct LaunchParams {
   uint64_t seed;
   uint64_t walk_offset_add;  // added to every item's walk_offset (plan relaunches)

@@ -64,7 +64,7 @@ class BatchItem(C.Structure):
 # Every symbol declared in include/wos.h.
 EXPORTS = ["wos_last_error", "wos_version", "wos_problem_create", "wos_problem_info", "wos_problem_bvh_info", "wos_problem_grid_info",
            "wos_problem_destroy", "wos_solve", "wos_count_events", "wos_finalize", "wos_plan_create", "wos_plan_launch",
-           "wos_plan_info", "wos_plan_destroy", "wos_eval_coefficients", "wos_eval_distance", "wos_eval_ball",
+           "wos_plan_time", "wos_plan_info", "wos_plan_destroy", "wos_eval_coefficients", "wos_eval_distance", "wos_eval_ball",
            "wos_sample_radius", "wos_philox", "wos_eval_bessel", "wos_classify"]
 
 _lib = None
@@ -90,6 +90,7 @@ def lib():
         L.wos_finalize.argtypes = [vp, vp, vp, i64, vp, vp, vp]
         L.wos_plan_create.argtypes = [C.POINTER(BatchItem), i32, C.POINTER(Options), vp, C.POINTER(vp)]
         L.wos_plan_launch.argtypes = [vp, u64, u64, vp]
+        L.wos_plan_time.argtypes = [vp, u64, u64, vp, dp, dp]
         L.wos_plan_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
         L.wos_plan_destroy.argtypes = [vp]
         L.wos_eval_coefficients.argtypes = [vp, vp, i64, i32, vp, vp]
@@ -189,6 +190,13 @@ class Problem:
                 F.params[i] = v
         elif b == "manufactured":
             F.solution_id = _SOLUTION[f["u"]]
+
+    def time(self, seed, walk_offset_add=0, stream=None):
+        """Runs the plan's work once as separate launches with HIP events around the
+        walker; returns (walker_ms, total_ms). Accumulates like launch()."""
+        w, t = C.c_double(), C.c_double()
+        _check(lib().wos_plan_time(self.handle, seed, walk_offset_add, _stream(stream), C.byref(w), C.byref(t)))
+        return w.value, t.value
 
     def info(self):
         a, b, c = C.c_double(), C.c_double(), C.c_double()
@@ -312,6 +320,13 @@ class Plan:
 
     def launch(self, seed, walk_offset_add=0, stream=None):
         _check(lib().wos_plan_launch(self.handle, seed, walk_offset_add, _stream(stream)))
+
+    def time(self, seed, walk_offset_add=0, stream=None):
+        """Runs the plan's work once as separate launches with HIP events around the
+        walker; returns (walker_ms, total_ms). Accumulates like launch()."""
+        w, t = C.c_double(), C.c_double()
+        _check(lib().wos_plan_time(self.handle, seed, walk_offset_add, _stream(stream), C.byref(w), C.byref(t)))
+        return w.value, t.value
 
     def info(self):
         b, t, g, n = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()

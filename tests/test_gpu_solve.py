@@ -234,3 +234,46 @@ def test_outside_points_and_step_cap(W):
     r = gpu_solve(W, h, pts[[0, 3]], 64, "fp32", seed=1, max_steps=2)
     assert r["counters"][1] > 0
     assert np.all(r["steps"] <= 2 * 64)
+
+
+def test_autotuned_plan_and_timed_run_match_fixed_shapes(W):
+    """Per-walk values depend only on (seed, problem, point, walk) and the per-point
+    reduction runs in a fixed order, so every launch shape, the autotuned plan, its graph
+    replay and its separately timed run give bit-identical sums. The job (2^22 walks) is
+    large enough for the plan to run its tuning pass."""
+    torch = torch_cuda()
+    prob = harmonic(WL.geom_ball([0, 0], 1.0), 2)
+    h = W.Problem(prob)
+    g = WL.grid_points(48, -1.0, 1.0)
+    pts = dev(g[WL.inside_mask(prob["geometry"], g)][:2048])
+    n = pts.shape[0]
+    walks = (1 << 22) // n + 1
+
+    def fresh():
+        return W.Accumulators(n)
+
+    outs = []
+    for shape in ({"block_size": 64, "tile_walks": 64}, {"block_size": 256, "tile_walks": 1024}):
+        acc = fresh()
+        W.solve([(h, pts, acc, 0)], W.options(precision="fp32", walks=walks, seed=5, **shape))
+        outs.append(acc)
+    acc_plan, acc_timed = fresh(), fresh()
+    plan = W.Plan([(h, pts, acc_plan, 0)], W.options(precision="fp32", walks=walks, seed=5))
+    info = plan.info()
+    assert info["block_size"] in (64, 128, 256) and info["tile_walks"] in (64, 128, 256, 512, 1024)
+    plan.launch(seed=5)
+    torch.cuda.synchronize()
+    plan.close()
+    plan = W.Plan([(h, pts, acc_timed, 0)], W.options(precision="fp32", walks=walks, seed=5))
+    assert plan.info() == info   # the tuned shape is cached for the process
+    walker_ms, total_ms = plan.time(seed=5)
+    assert 0 < walker_ms <= total_ms
+    plan.close()
+    torch.cuda.synchronize()
+    outs += [acc_plan, acc_timed]
+    ref = outs[0]
+    for a in outs[1:]:
+        assert np.array_equal(a.sum.cpu().numpy(), ref.sum.cpu().numpy())
+        assert np.array_equal(a.sum_sq.cpu().numpy(), ref.sum_sq.cpu().numpy())
+        assert np.array_equal(a.n_steps.cpu().numpy(), ref.n_steps.cpu().numpy())
+        assert np.all(a.n_walks.cpu().numpy() == walks)
