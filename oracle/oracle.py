@@ -239,7 +239,9 @@ def sigma_bar_default(prob, samples):
 
 def solve(prob, pts, n_walks, sigma_bar, seed=0, walk_offset=0, problem_index=0, variant=0,
           russian_roulette=False, ww_lo=0.5, max_steps=10**7, threads=0):
-    """Returns dict(sum, sum_sq, steps, mean, se, counters)."""
+    """Returns dict(sum, sum_sq, steps, mean, se, counters). variant: 0 Alg. 1, 1 eq. 28,
+    2 next flight (Alg. 2). counters: invalid points, capped walks, roulette kills, inner
+    samples (next flight)."""
     P = Problem(prob)
     pts = np.ascontiguousarray(pts, np.float64)
     n = pts.shape[0]
@@ -250,7 +252,7 @@ def solve(prob, pts, n_walks, sigma_bar, seed=0, walk_offset=0, problem_index=0,
     s = np.zeros(n)
     q = np.zeros(n)
     st = np.zeros(n, np.uint64)
-    cnt = np.zeros(3, np.uint64)
+    cnt = np.zeros(4, np.uint64)
     rc = lib().oracle_solve(C.byref(P.c), C.byref(o), _dptr(pts), n, _dptr(s), _dptr(q),
                             st.ctypes.data_as(C.POINTER(C.c_uint64)),
                             cnt.ctypes.data_as(C.POINTER(C.c_uint64)))

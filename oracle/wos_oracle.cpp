@@ -20,6 +20,9 @@
 //   * the centred screened-Poisson Green's function of a ball, its integral |G|
 //     and its Poisson kernel (supplemental Sec. 1.1), sampled here by numerical
 //     inversion of the closed-form radial CDF (no rejection envelope);
+//   * the next-flight walk on spheres (Sec. 5.2, supplemental Alg. 2) with the
+//     off-centred Green's function and Poisson kernel approximations of supplemental
+//     Sec. 1.2 and uniform points inside each ball;
 //   * the low side of the static weight window (Russian roulette, Sec. 6);
 //   * the per-point Monte Carlo mean (Sec. 3.1, eqs. 17-18).
 //
@@ -161,7 +164,8 @@ struct OOptions {
   uint64_t walk_offset;
   uint64_t n_walks;
   uint32_t problem_index;
-  int32_t variant;        // 0: Alg. 1 (source every step), 1: eq. 28 (source on volume events)
+  int32_t variant;        // 0: Alg. 1 (source every step), 1: eq. 28 (source on volume events),
+                          // 2: next flight (Sec. 5.2, supplemental Alg. 2)
   int32_t russian_roulette;
   double ww_lo;
   uint64_t max_steps;
@@ -577,6 +581,7 @@ struct WalkResult {
   uint64_t steps;   // distance queries
   int capped;
   int rr_killed;
+  uint64_t inner;   // next flight: points sampled inside balls
 };
 
 WalkResult walk(const OProblem& P, const OOptions& o, const double* x0, Stream* st) {
@@ -589,7 +594,7 @@ WalkResult walk(const OProblem& P, const OOptions& o, const double* x0, Stream* 
   // with W the product of the per-step factors that multiply the recursive estimate.
   double W = 1.0;
   double A = 0.0;
-  WalkResult res = {0, 0, 0, 0};
+  WalkResult res = {0, 0, 0, 0, 0};
   for (;;) {
     if (res.steps >= o.max_steps) {
       res.capped = 1;
@@ -646,6 +651,133 @@ WalkResult walk(const OProblem& P, const OOptions& o, const double* x0, Stream* 
         break;
       }
     }
+  }
+  res.value = A;
+  return res;
+}
+
+// ------------------------------------------------------------------ next flight (Sec. 5.2, Alg. 2)
+//
+// Off-centred Green's function and Poisson kernel of the ball B(c, R) for the operator
+// Lap - sigma_bar, in the closed-form approximations of supplemental Sec. 1.2. With
+// u = x - c, v = y - c, w = y - x and rho = (R^2 - u.v)/R:
+//   G(x, y) = (Q(|w|) - Q(rho)) / (2 pi)                         (2D; 4 pi in 3D)
+//   P(x, z) = (V(|w|) (|v|^2 - u.v)/(|w||v|) + V(rho) u.v/(R|v|)) / (2 pi)
+// Q and V are the radial profiles of the centred Green's function and of its radial
+// derivative (supplemental Sec. 1.1 and 1.2); at u = 0 both reduce to the centred
+// expressions. sigma_bar = 0 takes the harmonic profiles Q = ln(R/r), V = 1/r (2D) and
+// Q = 1/r - 1/R, V = 1/r^2 (3D).
+double nf_Q(int dim, double r, double R, double sb) {
+  if (sb <= 0) return dim == 2 ? std::log(R / r) : 1.0 / r - 1.0 / R;
+  const double k = std::sqrt(sb);
+  if (dim == 2) return K0(r * k) - K0(R * k) / I0(R * k) * I0(r * k);
+  return std::exp(-r * k) / r - std::exp(-R * k) / R * (std::sinh(r * k) / (r * k)) * (R * k / std::sinh(R * k));
+}
+
+double nf_V(int dim, double r, double R, double sb) {
+  if (sb <= 0) return dim == 2 ? 1.0 / r : 1.0 / (r * r);
+  const double k = std::sqrt(sb);
+  if (dim == 2) return k * (K1(r * k) + K0(R * k) / I0(R * k) * I1(r * k));
+  const double a = r * k;
+  return k / r * (std::exp(-a) * (1 + 1 / a) + std::exp(-R * k) / std::sinh(R * k) * (std::cosh(a) - std::sinh(a) / a));
+}
+
+double nf_green(int dim, const double* u, const double* v, double R, double sb) {
+  double w2 = 0, uv = 0;
+  for (int i = 0; i < dim; ++i) {
+    w2 += (v[i] - u[i]) * (v[i] - u[i]);
+    uv += u[i] * v[i];
+  }
+  const double rho = (R * R - uv) / R;
+  const double c = dim == 2 ? 1.0 / (2 * kPi) : 1.0 / (4 * kPi);
+  return c * (nf_Q(dim, std::sqrt(w2), R, sb) - nf_Q(dim, rho, R, sb));
+}
+
+double nf_poisson(int dim, const double* u, const double* v, double R, double sb) {
+  double w2 = 0, uv = 0, v2 = 0;
+  for (int i = 0; i < dim; ++i) {
+    w2 += (v[i] - u[i]) * (v[i] - u[i]);
+    uv += u[i] * v[i];
+    v2 += v[i] * v[i];
+  }
+  const double w = std::sqrt(w2), vn = std::sqrt(v2);
+  const double rho = (R * R - uv) / R;
+  const double c = dim == 2 ? 1.0 / (2 * kPi) : 1.0 / (4 * kPi);
+  return c * (nf_V(dim, w, R, sb) * (v2 - uv) / (w * vn) + nf_V(dim, rho, R, sb) * uv / (R * vn));
+}
+
+// Uniform point in the unit ball, by the radius law r = U^{1/n} and a uniform direction.
+void uniform_in_ball(Stream* st, int dim, double* p) {
+  double v[3];
+  uniform_direction(st, dim, v);
+  const double r = std::pow(uniform(st), 1.0 / dim);
+  for (int i = 0; i < 3; ++i) p[i] = r * v[i];
+}
+
+// One walk of Alg. 2 in the transformed unknown U = e^gamma u (Sec. 4.1, App. A). For the
+// ball B(x_k, R) with exit point z uniform on its sphere, the unrolled series
+//   T_k = sum_j P(x^j, z) |dB| prod_{l<j} theta_l,
+//   S_k = sum_{j>=1} f'(x^j)/(sigma_bar - sigma'(x^j)) prod_{l<j} theta_l,
+//   theta_l = G(x^l, x^{l+1}) (sigma_bar - sigma'(x^{l+1})) |B|,
+// with x^0 = x_k and x^{l+1} uniform in the ball, give U(x_k) ~ T_k U(z) + S_k; the number
+// of terms is set by Russian roulette on the running throughput min(1, prod theta).
+// The (sigma_bar - sigma') of the last theta cancels against the division in S (the
+// term is f' G |B| times the previous throughput), so sigma' = sigma_bar needs no
+// special case. Unrolled over the balls, with f' = e^gamma f/alpha:
+//   u(x_0) ~ e^{-gamma(x_0)} [sum_k (prod_{i<k} T_i) S_k + (prod_{i<K} T_i) e^{gamma(x_K)} g(xbar_K)],
+// kept here relative to gamma(x_0) so that no absolute e^gamma is formed.
+WalkResult walk_next_flight(const OProblem& P, const OOptions& o, const double* x0, Stream* st) {
+  const int dim = P.dim;
+  const double sb = o.sigma_bar;
+  double x[3] = {0, 0, 0};
+  for (int i = 0; i < dim; ++i) x[i] = x0[i];
+  const double g0 = coefficients(P, x).gamma;
+  const double unit_ball = dim == 2 ? kPi : 4.0 * kPi / 3.0;
+  const double unit_sphere = dim == 2 ? 2 * kPi : 4 * kPi;
+  double W = 1.0;   // prod_{i<k} T_i
+  double A = 0.0;
+  WalkResult res = {0, 0, 0, 0, 0};
+  for (;;) {
+    if (res.steps >= o.max_steps) {
+      res.capped = 1;
+      break;
+    }
+    double xbar[3] = {0, 0, 0};
+    const double d = distance_to_boundary(P, x, xbar);
+    res.steps++;
+    if (d < P.epsilon) {
+      A += W * std::exp(coefficients(P, x).gamma - g0) * boundary_value(P, xbar);
+      break;
+    }
+    const double R = d;
+    const double vol = unit_ball * std::pow(R, dim);
+    const double area = unit_sphere * std::pow(R, dim - 1);
+    double vz[3];
+    uniform_direction(st, dim, vz);
+    double zr[3] = {0, 0, 0};     // z - x_k
+    for (int i = 0; i < dim; ++i) zr[i] = R * vz[i];
+    double xc[3] = {0, 0, 0};     // current inner point, relative to x_k
+    double T = 0, S = 0, beta = 1;
+    for (;;) {
+      T += nf_poisson(dim, xc, zr, R, sb) * area * beta;
+      const double prr = std::fmin(1.0, beta);
+      if (prr < uniform(st)) break;
+      beta /= prr;
+      double xn[3] = {0, 0, 0};
+      uniform_in_ball(st, dim, xn);
+      for (int i = 0; i < dim; ++i) xn[i] *= R;
+      double y[3] = {0, 0, 0};
+      for (int i = 0; i < dim; ++i) y[i] = x[i] + xn[i];
+      const Coef cy = coefficients(P, y);
+      const double gv = nf_green(dim, xc, xn, R, sb) * vol;
+      S += beta * gv * std::exp(cy.gamma - g0) * cy.f / cy.alpha;
+      beta *= gv * (sb - cy.sigma_prime);
+      res.inner++;
+      for (int i = 0; i < dim; ++i) xc[i] = xn[i];
+    }
+    A += W * S;
+    W *= T;
+    for (int i = 0; i < dim; ++i) x[i] += zr[i];
   }
   res.value = A;
   return res;
@@ -725,12 +857,15 @@ void oracle_sigma_prime_range(const OProblem* P, const double* pts, int64_t n, d
 
 // Monte Carlo solve: per point, walks j = walk_offset .. walk_offset + n_walks - 1.
 // Outputs (per point): sum of estimates, sum of squares, total distance queries.
-// counters: [0] invalid points, [1] capped walks, [2] Russian-roulette kills.
+// counters: [0] invalid points, [1] capped walks, [2] Russian-roulette kills,
+// [3] next flight: points sampled inside balls.
 int oracle_solve(const OProblem* P, const OOptions* o, const double* pts, int64_t n_points,
                  double* sum, double* sum_sq, uint64_t* steps, uint64_t* counters) {
   if (o->sigma_bar < 0) return 1;
+  if (o->variant < 0 || o->variant > 2) return 1;
+  if (o->variant == 2 && o->russian_roulette) return 1;   // next flight has its own roulette
   std::atomic<int64_t> next(0);
-  std::atomic<uint64_t> bad(0), capped(0), killed(0);
+  std::atomic<uint64_t> bad(0), capped(0), killed(0), inner(0);
   auto worker = [&]() {
     for (;;) {
       const int64_t i = next.fetch_add(1);
@@ -749,10 +884,11 @@ int oracle_solve(const OProblem* P, const OOptions* o, const double* pts, int64_
       for (uint64_t j = 0; j < o->n_walks; ++j) {
         Stream st;
         stream_init(&st, o->seed, (uint32_t)(o->walk_offset + j), (uint32_t)i, o->problem_index);
-        const WalkResult r = walk(*P, *o, x0, &st);
+        const WalkResult r = o->variant == 2 ? walk_next_flight(*P, *o, x0, &st) : walk(*P, *o, x0, &st);
         nst += r.steps;
         capped += r.capped;
         killed += r.rr_killed;
+        inner += r.inner;
         const double v = r.value, v2 = r.value * r.value;
         double t = s + v;
         cs += std::fabs(s) >= std::fabs(v) ? (s - t) + v : (v - t) + s;
@@ -774,6 +910,7 @@ int oracle_solve(const OProblem* P, const OOptions* o, const double* pts, int64_
   counters[0] = bad;
   counters[1] = capped;
   counters[2] = killed;
+  counters[3] = inner;
   return 0;
 }
 
