@@ -77,6 +77,7 @@ def lib():
             getattr(L, name).restype = C.c_double
         L.oracle_ball_pb.argtypes = [C.c_int, C.c_double]
         L.oracle_radial_cdf_many.argtypes = [C.c_int, C.c_double, dp, C.c_int64, dp]
+        L.oracle_nf_kernel.argtypes = [C.c_int, C.c_int, dp, dp, C.c_int64, C.c_double, C.c_double, dp]
         L.oracle_ball_gnorm.argtypes = [C.c_int, C.c_double, C.c_double]
         L.oracle_ball_gnorm.restype = C.c_double
         L.oracle_bessel.argtypes = [C.c_int, C.c_double]
@@ -181,6 +182,20 @@ def ball_gnorm(dim, R, sigma_bar):
     return lib().oracle_ball_gnorm(dim, R, sigma_bar)
 
 
+def nf_kernel(which, dim, u, v, R, sigma_bar):
+    """Off-centred G ('green') or P ('poisson') of the next-flight walk for u = x - c and
+    v = y - c (rows of [n][dim] arrays); 'green_exact' / 'poisson_exact' sum the exact
+    series instead of the closed-form approximations."""
+    u = np.ascontiguousarray(np.atleast_2d(u), np.float64)
+    v = np.ascontiguousarray(np.atleast_2d(v), np.float64)
+    u, v = np.broadcast_arrays(u, v)
+    u, v = np.ascontiguousarray(u), np.ascontiguousarray(v)
+    out = np.empty(u.shape[0])
+    lib().oracle_nf_kernel({"green": 0, "poisson": 1, "green_exact": 2, "poisson_exact": 3}[which], dim, _dptr(u), _dptr(v), u.shape[0], R, sigma_bar,
+                           _dptr(out))
+    return out
+
+
 def radial_cdf(dim, s, t):
     return lib().oracle_radial_cdf(dim, s, t)
 
@@ -240,7 +255,7 @@ def sigma_bar_default(prob, samples):
 def solve(prob, pts, n_walks, sigma_bar, seed=0, walk_offset=0, problem_index=0, variant=0,
           russian_roulette=False, ww_lo=0.5, max_steps=10**7, threads=0):
     """Returns dict(sum, sum_sq, steps, mean, se, counters). variant: 0 Alg. 1, 1 eq. 28,
-    2 next flight (Alg. 2). counters: invalid points, capped walks, roulette kills, inner
+    2 next flight (Alg. 2), 3 next flight with exact series kernels. counters: invalid points, capped walks, roulette kills, inner
     samples (next flight)."""
     P = Problem(prob)
     pts = np.ascontiguousarray(pts, np.float64)

@@ -165,7 +165,8 @@ struct OOptions {
   uint64_t n_walks;
   uint32_t problem_index;
   int32_t variant;        // 0: Alg. 1 (source every step), 1: eq. 28 (source on volume events),
-                          // 2: next flight (Sec. 5.2, supplemental Alg. 2)
+                          // 2: next flight (Sec. 5.2, supplemental Alg. 2) with the closed-form
+                          // off-centred kernels, 3: next flight with the exact series kernels
   int32_t russian_roulette;
   double ww_lo;
   uint64_t max_steps;
@@ -706,6 +707,122 @@ double nf_poisson(int dim, const double* u, const double* v, double R, double sb
   return c * (nf_V(dim, w, R, sb) * (v2 - uv) / (w * vn) + nf_V(dim, rho, R, sb) * uv / (R * vn));
 }
 
+// Exact off-centred kernels, from the separable series of supplemental Sec. 1.2. They
+// serve the oracle's exact-kernel next-flight walk (variant 3), which pins the walk's
+// bookkeeping independently of the approximations. The free-space part of G is summed in
+// closed form by the addition theorem of the screened kernel, so only the regular part
+// is a series (theta: angle between u and v; a = |u|, b = |v|):
+//   2D: G = (K0(k|w|) - sum_n c_n cos(n theta) I_n(ka) I_n(kb) K_n(kR)/I_n(kR)) / (2 pi)
+//   3D: G = (e^{-k|w|}/|w| - (2k/pi) sum_n (2n+1) P_n(cos theta) i_n(ka) i_n(kb) k_n(kR)/i_n(kR)) / (4 pi)
+//   2D: P = sum_n c_n cos(n theta) I_n(ka)/I_n(kR) / (2 pi R)
+//   3D: P = sum_n (2n+1) P_n(cos theta) i_n(ka)/i_n(kR) / (4 pi R^2)
+// with c_0 = 1, c_n = 2, i_n(x) = sqrt(pi/2x) I_{n+1/2}(x), k_n(x) = sqrt(pi/2x) K_{n+1/2}(x).
+// Orders are stepped through ratios (I_v/I_{v-1} by backward recurrence, K_{v+1}/K_v by
+// forward recurrence) in logarithms, so no term overflows.
+const int kSeriesMax = 20000;
+
+// log I_n(x) (2D) or log i_n(x) (3D), n = 0 .. N-1; at x = 0 only n = 0 is nonzero (= 1).
+void log_i_orders(int dim, double x, int N, std::vector<double>& out) {
+  out.assign(N, -1e300);
+  if (x <= 0) {
+    out[0] = 0.0;
+    return;
+  }
+  const double v0 = dim == 2 ? 0.0 : 0.5;
+  std::vector<double> r(N + 1, 0.0);   // r[n] = I_{v0+n}(x) / I_{v0+n-1}(x)
+  double rr = 0.0;
+  for (int n = N + 80; n >= 1; --n) {
+    rr = 1.0 / (2.0 * (v0 + n) / x + rr);
+    if (n <= N) r[n] = rr;
+  }
+  out[0] = std::log(std::cyl_bessel_i(v0, x)) + (dim == 3 ? 0.5 * std::log(kPi / (2 * x)) : 0.0);
+  for (int n = 1; n < N; ++n) out[n] = out[n - 1] + std::log(r[n]);
+}
+
+// log K_n(x) (2D) or log k_n(x) (3D), n = 0 .. N-1, x > 0.
+void log_k_orders(int dim, double x, int N, std::vector<double>& out) {
+  out.assign(N, 0.0);
+  const double v0 = dim == 2 ? 0.0 : 0.5;
+  const double k0 = std::cyl_bessel_k(v0, x), k1 = std::cyl_bessel_k(v0 + 1.0, x);
+  const double sh = dim == 3 ? 0.5 * std::log(kPi / (2 * x)) : 0.0;
+  out[0] = std::log(k0) + sh;
+  double s = k1 / k0;                  // K_{v0+n}/K_{v0+n-1}
+  for (int n = 1; n < N; ++n) {
+    if (n > 1) s = 1.0 / s + 2.0 * (v0 + n - 1) / x;
+    out[n] = out[n - 1] + std::log(s);
+  }
+}
+
+int series_terms(double q) {
+  if (q <= 0) return 2;
+  return std::min(kSeriesMax, 8 + (int)(std::log(1e-18) / std::log(std::fmin(q, 0.99999))));
+}
+
+// sum_n c_n cos(n theta) t_n (2D) or sum_n (2n+1) P_n(cos theta) t_n (3D)
+double angular_sum(int dim, double cth, const std::vector<double>& logt) {
+  const double theta = std::acos(cth);
+  double tot = 0, pm2 = 1, pm1 = cth;
+  for (size_t n = 0; n < logt.size(); ++n) {
+    const double t = logt[n] < -700 ? 0.0 : std::exp(logt[n]);
+    if (dim == 2) {
+      tot += (n == 0 ? 1.0 : 2.0 * std::cos(n * theta)) * t;
+    } else {
+      double Pn = n == 0 ? 1.0 : cth;
+      if (n >= 2) {
+        Pn = ((2.0 * n - 1.0) * cth * pm1 - (n - 1.0) * pm2) / n;
+        pm2 = pm1;
+        pm1 = Pn;
+      }
+      tot += (2.0 * n + 1.0) * Pn * t;
+    }
+  }
+  return tot;
+}
+
+double cos_angle(int dim, const double* u, const double* v) {
+  double uv = 0, a2 = 0, b2 = 0;
+  for (int i = 0; i < dim; ++i) {
+    uv += u[i] * v[i];
+    a2 += u[i] * u[i];
+    b2 += v[i] * v[i];
+  }
+  if (a2 <= 0 || b2 <= 0) return 1.0;
+  return std::fmax(-1.0, std::fmin(1.0, uv / std::sqrt(a2 * b2)));
+}
+
+double nf_green_exact(int dim, const double* u, const double* v, double R, double sb) {
+  double w2 = 0, a2 = 0, b2 = 0;
+  for (int i = 0; i < dim; ++i) {
+    w2 += (v[i] - u[i]) * (v[i] - u[i]);
+    a2 += u[i] * u[i];
+    b2 += v[i] * v[i];
+  }
+  const double k = std::sqrt(sb), w = std::sqrt(w2), a = std::sqrt(a2), b = std::sqrt(b2);
+  const int N = series_terms(a * b / (R * R));
+  std::vector<double> la, lb, li, lk;
+  log_i_orders(dim, k * a, N, la);
+  log_i_orders(dim, k * b, N, lb);
+  log_i_orders(dim, k * R, N, li);
+  log_k_orders(dim, k * R, N, lk);
+  for (int n = 0; n < N; ++n) la[n] += lb[n] + lk[n] - li[n];
+  const double reg = angular_sum(dim, cos_angle(dim, u, v), la);
+  if (dim == 2) return (K0(k * w) - reg) / (2 * kPi);
+  return (std::exp(-k * w) / w - 2 * k / kPi * reg) / (4 * kPi);
+}
+
+double nf_poisson_exact(int dim, const double* u, const double* v, double R, double sb) {
+  double a2 = 0;
+  for (int i = 0; i < dim; ++i) a2 += u[i] * u[i];
+  const double k = std::sqrt(sb), a = std::sqrt(a2);
+  const int N = series_terms(a / R);
+  std::vector<double> la, li;
+  log_i_orders(dim, k * a, N, la);
+  log_i_orders(dim, k * R, N, li);
+  for (int n = 0; n < N; ++n) la[n] -= li[n];
+  const double tot = angular_sum(dim, cos_angle(dim, u, v), la);
+  return dim == 2 ? tot / (2 * kPi * R) : tot / (4 * kPi * R * R);
+}
+
 // Uniform point in the unit ball, by the radius law r = U^{1/n} and a uniform direction.
 void uniform_in_ball(Stream* st, int dim, double* p) {
   double v[3];
@@ -729,6 +846,7 @@ void uniform_in_ball(Stream* st, int dim, double* p) {
 WalkResult walk_next_flight(const OProblem& P, const OOptions& o, const double* x0, Stream* st) {
   const int dim = P.dim;
   const double sb = o.sigma_bar;
+  const bool exact = o.variant == 3;   // exact series kernels instead of the approximations
   double x[3] = {0, 0, 0};
   for (int i = 0; i < dim; ++i) x[i] = x0[i];
   const double g0 = coefficients(P, x).gamma;
@@ -759,7 +877,7 @@ WalkResult walk_next_flight(const OProblem& P, const OOptions& o, const double* 
     double xc[3] = {0, 0, 0};     // current inner point, relative to x_k
     double T = 0, S = 0, beta = 1;
     for (;;) {
-      T += nf_poisson(dim, xc, zr, R, sb) * area * beta;
+      T += (exact ? nf_poisson_exact(dim, xc, zr, R, sb) : nf_poisson(dim, xc, zr, R, sb)) * area * beta;
       const double prr = std::fmin(1.0, beta);
       if (prr < uniform(st)) break;
       beta /= prr;
@@ -769,7 +887,7 @@ WalkResult walk_next_flight(const OProblem& P, const OOptions& o, const double* 
       double y[3] = {0, 0, 0};
       for (int i = 0; i < dim; ++i) y[i] = x[i] + xn[i];
       const Coef cy = coefficients(P, y);
-      const double gv = nf_green(dim, xc, xn, R, sb) * vol;
+      const double gv = (exact ? nf_green_exact(dim, xc, xn, R, sb) : nf_green(dim, xc, xn, R, sb)) * vol;
       S += beta * gv * std::exp(cy.gamma - g0) * cy.f / cy.alpha;
       beta *= gv * (sb - cy.sigma_prime);
       res.inner++;
@@ -804,6 +922,18 @@ void oracle_uniforms(uint64_t seed, uint32_t walk, uint32_t point, uint32_t prob
   Stream st;
   stream_init(&st, seed, walk, point, problem);
   for (int64_t i = 0; i < n; ++i) out[i] = uniform(&st);
+}
+
+// Off-centred Green's function G(x, y) and Poisson kernel P(x, z) of the ball B(c, R) for
+// Lap - sigma_bar in the approximations of supplemental Sec. 1.2; u = x - c, v = y - c (or
+// z - c). which: 0 = G, 1 = P, 2 = exact G, 3 = exact P (series). u, v: [n][dim].
+void oracle_nf_kernel(int which, int dim, const double* u, const double* v, int64_t n, double R, double sigma_bar,
+                      double* out) {
+  for (int64_t i = 0; i < n; ++i)
+    out[i] = which == 0 ? nf_green(dim, u + i * dim, v + i * dim, R, sigma_bar)
+             : which == 1 ? nf_poisson(dim, u + i * dim, v + i * dim, R, sigma_bar)
+             : which == 2 ? nf_green_exact(dim, u + i * dim, v + i * dim, R, sigma_bar)
+                          : nf_poisson_exact(dim, u + i * dim, v + i * dim, R, sigma_bar);
 }
 
 double oracle_ball_pb(int dim, double s) { return ball_pb(dim, s); }
@@ -862,8 +992,9 @@ void oracle_sigma_prime_range(const OProblem* P, const double* pts, int64_t n, d
 int oracle_solve(const OProblem* P, const OOptions* o, const double* pts, int64_t n_points,
                  double* sum, double* sum_sq, uint64_t* steps, uint64_t* counters) {
   if (o->sigma_bar < 0) return 1;
-  if (o->variant < 0 || o->variant > 2) return 1;
-  if (o->variant == 2 && o->russian_roulette) return 1;   // next flight has its own roulette
+  if (o->variant < 0 || o->variant > 3) return 1;
+  if (o->variant >= 2 && o->russian_roulette) return 1;   // next flight has its own roulette
+  if (o->variant == 3 && !(o->sigma_bar > 0)) return 1;    // exact kernels need sigma_bar > 0
   std::atomic<int64_t> next(0);
   std::atomic<uint64_t> bad(0), capped(0), killed(0), inner(0);
   auto worker = [&]() {
@@ -884,7 +1015,7 @@ int oracle_solve(const OProblem* P, const OOptions* o, const double* pts, int64_
       for (uint64_t j = 0; j < o->n_walks; ++j) {
         Stream st;
         stream_init(&st, o->seed, (uint32_t)(o->walk_offset + j), (uint32_t)i, o->problem_index);
-        const WalkResult r = o->variant == 2 ? walk_next_flight(*P, *o, x0, &st) : walk(*P, *o, x0, &st);
+        const WalkResult r = o->variant >= 2 ? walk_next_flight(*P, *o, x0, &st) : walk(*P, *o, x0, &st);
         nst += r.steps;
         capped += r.capped;
         killed += r.rr_killed;
