@@ -164,7 +164,13 @@ typedef enum { WOS_FP32 = 0, WOS_FP32_COMPENSATED = 1, WOS_FP64 = 2 } wos_precis
 typedef struct {
   int32_t precision;          /* wos_precision */
   int32_t variant;            /* 0: Alg. 1 (source estimated at every ball);
-                                 1: eq. 28 (source only on volume events, weight 1/sigma_bar) */
+                                 1: eq. 28 (source only on volume events, weight 1/sigma_bar);
+                                 2: next flight (Sec. 5.2, supplemental Alg. 2): every ball
+                                    exits on its sphere, the recursion inside the ball is
+                                    unrolled over uniform inner points with roulette on the
+                                    throughput, using the closed-form off-centred kernels of
+                                    supplemental Sec. 1.2 (biased off the centre, as the
+                                    supplement states). russian_roulette must be 0. */
   uint64_t seed;              /* Philox4x32-10 key */
   uint64_t walks_per_point;   /* > 0 */
   uint64_t walk_offset;       /* global index of the first walk: running N walks and then
@@ -186,7 +192,7 @@ typedef struct {
  *  counters: device uint64 [4] or NULL, also accumulated: [0] query points outside the
  *            domain or non-finite (their sum becomes NaN), [1] walks cut at max_steps,
  *            [2] walks ended by Russian roulette, [3] radius proposals drawn by the
- *            Green's-function sampler.
+ *            Green's-function sampler (next flight: points sampled inside balls).
  *  problem_index: fourth word of the Philox counter (distinguishes problems of a batch). */
 typedef struct {
   const wos_problem* problem;
@@ -285,9 +291,19 @@ wos_status wos_sample_radius(int32_t dim, int32_t precision, double s, int64_t n
 /* Philox4x32-10 blocks: out[i] = philox(ctr[i], key). ctr, out: device uint32 [n][4]. */
 wos_status wos_philox(const uint32_t* ctr, uint64_t key, int64_t n, uint32_t* out, void* stream);
 
-/* e^-x I0(x) (which = 0) or e^x K0(x) (which = 1) at x[i] > 0. device double [n]. */
+/* Exponentially scaled modified Bessel functions used by the ball kernels (supplemental
+ * Sec. 1.1-1.2): which = 0: e^-x I0(x), 1: e^x K0(x), 2: e^-x I1(x), 3: e^x K1(x), at
+ * x[i] > 0. device double [n]. */
 wos_status wos_eval_bessel(int32_t which, int32_t precision, const double* x, int64_t n, double* out,
                            void* stream);
+
+/* Off-centred kernels of the next-flight walk on the ball B(c, R) for Laplace - sigma_bar,
+ * in the closed-form approximations of supplemental Sec. 1.2 (exact at the centre):
+ * which = 0: G(x, y) |B| with u = x - c, v = y - c; which = 1: P(x, z) |dB| with u = x - c,
+ * v = z - c on the sphere. u, v: device double [n][dim]; out: device double [n].
+ * sigma_bar = 0 takes the harmonic kernels. */
+wos_status wos_eval_offcentred(int32_t which, int32_t dim, int32_t precision, double R, double sigma_bar,
+                               const double* u, const double* v, int64_t n, double* out, void* stream);
 
 /* 1 if points[i] lies strictly inside the domain, else 0 (harness helper; not on the
  * walk's path). inside: device int8 [n]. */

@@ -656,6 +656,7 @@ namespace {
 
 struct Schedule {
   int fp64 = 0, compensated = 0, dim = 2, geom = 0, device = 0;
+  int variant = 0;            // 2 selects the next-flight walker
   unsigned block = 256, grid = 0;
   uint32_t tile_walks = 256;
   uint64_t chunk_walks = 0;   // walks per point per launch
@@ -666,7 +667,9 @@ struct Schedule {
 wos_status check_items(const wos_batch_item* items, int n_items, const wos_options* opt, Schedule& s) {
   if (!items || n_items <= 0 || !opt) return fail(WOS_ERR_INVALID_ARG, "null or empty batch");
   if (opt->precision < 0 || opt->precision > 2) return fail(WOS_ERR_INVALID_ARG, "unknown precision");
-  if (opt->variant != 0 && opt->variant != 1) return fail(WOS_ERR_INVALID_ARG, "unknown variant");
+  if (opt->variant < 0 || opt->variant > 2) return fail(WOS_ERR_INVALID_ARG, "unknown variant");
+  if (opt->variant == 2 && opt->russian_roulette)
+    return fail(WOS_ERR_INVALID_ARG, "the next-flight walk has its own roulette; russian_roulette must be 0");
   if (opt->walks_per_point == 0) return fail(WOS_ERR_INVALID_ARG, "walks_per_point must be > 0");
   if (opt->walk_offset + opt->walks_per_point > (1ull << 32)) return fail(WOS_ERR_INVALID_ARG, "walk indices exceed 32 bits");
   if (opt->russian_roulette && !(opt->ww_lo > 0)) return fail(WOS_ERR_INVALID_ARG, "ww_lo must be > 0");
@@ -678,6 +681,7 @@ wos_status check_items(const wos_batch_item* items, int n_items, const wos_optio
   s.geom = p0->geom;
   s.device = p0->device;
   s.fp64 = opt->precision == WOS_FP64;
+  s.variant = opt->variant;
   s.compensated = opt->precision == WOS_FP32_COMPENSATED;
   s.total_points = 0;
   for (int k = 0; k < n_items; ++k) {
@@ -695,23 +699,23 @@ wos_status check_items(const wos_batch_item* items, int n_items, const wos_optio
 }
 
 std::mutex g_occ_mutex;
-std::map<std::tuple<int, int, int, int, unsigned>, unsigned> g_occ;
+std::map<std::tuple<int, int, int, int, int, unsigned>, unsigned> g_occ;
 
 // Launch shapes found by the plan autotuner, per (device, fp64, compensated, dim, geometry).
-std::map<std::tuple<int, int, int, int, int>, std::pair<unsigned, uint32_t>> g_tuned;
+std::map<std::tuple<int, int, int, int, int, int>, std::pair<unsigned, uint32_t>> g_tuned;
 
-std::tuple<int, int, int, int, int> tune_key(const Schedule& s) {
-  return std::make_tuple(s.device, s.fp64, s.compensated, s.dim, s.geom);
+std::tuple<int, int, int, int, int, int> tune_key(const Schedule& s) {
+  return std::make_tuple(s.device, s.fp64, s.compensated, s.dim, s.geom, s.variant == 2);
 }
 
 // Persistent grid for a block size: resident blocks per CU times CUs.
 wos_status grid_for_block(Schedule& s, unsigned block) {
-  const auto key = std::make_tuple(s.device, s.fp64, s.dim, s.geom, block);
+  const auto key = std::make_tuple(s.device, s.fp64, s.dim, s.geom, (int)(s.variant == 2), block);
   std::lock_guard<std::mutex> lk(g_occ_mutex);
   auto it = g_occ.find(key);
   if (it == g_occ.end()) {
     int per_cu = 0, cus = 0;
-    WOS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, walker_symbol(s.fp64, s.dim, s.geom), (int)block, 0));
+    WOS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, walker_symbol(s.fp64, s.dim, s.geom, s.variant), (int)block, 0));
     WOS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s.device));
     unsigned grid = (unsigned)std::max(1, per_cu) * (unsigned)std::max(1, cus);
     it = g_occ.emplace(key, grid).first;
@@ -1328,9 +1332,19 @@ wos_status wos_philox(const uint32_t* ctr, uint64_t key, int64_t n, uint32_t* ou
 }
 
 wos_status wos_eval_bessel(int32_t which, int32_t precision, const double* x, int64_t n, double* out, void* stream) {
-  if ((which != 0 && which != 1) || n < 0 || (n > 0 && (!x || !out))) return fail(WOS_ERR_INVALID_ARG, "bad arguments");
+  if (which < 0 || which > 3 || n < 0 || (n > 0 && (!x || !out))) return fail(WOS_ERR_INVALID_ARG, "bad arguments");
   if (precision != WOS_FP32 && precision != WOS_FP64) return fail(WOS_ERR_INVALID_ARG, "precision must be FP32 or FP64");
   WOS_HIP(launch_bessel(precision == WOS_FP64, which, x, n, out, (hipStream_t)stream));
+  return WOS_OK;
+}
+
+wos_status wos_eval_offcentred(int32_t which, int32_t dim, int32_t precision, double R, double sigma_bar,
+                               const double* u, const double* v, int64_t n, double* out, void* stream) {
+  if ((which != 0 && which != 1) || (dim != 2 && dim != 3) || n < 0 || (n > 0 && (!u || !v || !out)))
+    return fail(WOS_ERR_INVALID_ARG, "bad arguments");
+  if (!(R > 0) || !(sigma_bar >= 0)) return fail(WOS_ERR_INVALID_ARG, "R must be > 0 and sigma_bar >= 0");
+  if (precision != WOS_FP32 && precision != WOS_FP64) return fail(WOS_ERR_INVALID_ARG, "precision must be FP32 or FP64");
+  WOS_HIP(launch_offcentred(precision == WOS_FP64, dim, which, R, sigma_bar, u, v, n, out, (hipStream_t)stream));
   return WOS_OK;
 }
 

@@ -38,6 +38,8 @@ __device__ __forceinline__ float m_sqrt(float x) { return __fsqrt_rn(x); }
 __device__ __forceinline__ double m_sqrt(double x) { return ::sqrt(x); }
 __device__ __forceinline__ float m_tanh(float x) { return ::tanhf(x); }
 __device__ __forceinline__ double m_tanh(double x) { return ::tanh(x); }
+__device__ __forceinline__ float m_cbrt(float x) { return ::cbrtf(x); }
+__device__ __forceinline__ double m_cbrt(double x) { return ::cbrt(x); }
 __device__ __forceinline__ float m_fabs(float x) { return ::fabsf(x); }
 __device__ __forceinline__ double m_fabs(double x) { return ::fabs(x); }
 __device__ __forceinline__ float m_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -52,10 +54,12 @@ template <typename T> struct Consts;
 template <> struct Consts<float> {
   static constexpr float kInf = __builtin_huge_valf();
   static constexpr float kEulerGamma = 0.5772156649015329f;
+  static constexpr float kTiny = 1e-30f;
 };
 template <> struct Consts<double> {
   static constexpr double kInf = __builtin_huge_val();
   static constexpr double kEulerGamma = 0.57721566490153286061;
+  static constexpr double kTiny = 1e-300;
 };
 
 // Work counters of one lane, kept only by the event-counting build of the walker.
@@ -151,11 +155,15 @@ __device__ __forceinline__ T chebyshev(const double* c, int n, T t) {
 template <typename T> struct BesselTerms;
 template <> struct BesselTerms<float> {
   static constexpr int kSeries = 9, kI0Mid = WOS_I0E_MID_N32, kI0Tail = WOS_I0E_TAIL_N32,
-                       kK0Low = WOS_K0E_LOW_N32, kK0Mid = WOS_K0E_MID_N32, kK0Tail = WOS_K0E_TAIL_N32;
+                       kK0Low = WOS_K0E_LOW_N32, kK0Mid = WOS_K0E_MID_N32, kK0Tail = WOS_K0E_TAIL_N32,
+                       kI1Mid = WOS_I1E_MID_N32, kI1Tail = WOS_I1E_TAIL_N32, kK1Low = WOS_K1E_LOW_N32,
+                       kK1Mid = WOS_K1E_MID_N32, kK1Tail = WOS_K1E_TAIL_N32;
 };
 template <> struct BesselTerms<double> {
   static constexpr int kSeries = 15, kI0Mid = WOS_I0E_MID_N64, kI0Tail = WOS_I0E_TAIL_N64,
-                       kK0Low = WOS_K0E_LOW_N64, kK0Mid = WOS_K0E_MID_N64, kK0Tail = WOS_K0E_TAIL_N64;
+                       kK0Low = WOS_K0E_LOW_N64, kK0Mid = WOS_K0E_MID_N64, kK0Tail = WOS_K0E_TAIL_N64,
+                       kI1Mid = WOS_I1E_MID_N64, kI1Tail = WOS_I1E_TAIL_N64, kK1Low = WOS_K1E_LOW_N64,
+                       kK1Mid = WOS_K1E_MID_N64, kK1Tail = WOS_K1E_TAIL_N64;
 };
 
 // Power series of I0 and K0 for small x (x <= 2 for I0, x <= 1 for K0):
@@ -198,6 +206,52 @@ __device__ T bessel_k0e(T x) {
   if (x <= (T)3) return chebyshev<T>(WOS_K0E_LOW, BesselTerms<T>::kK0Low, x - (T)2);
   if (x <= (T)8) return chebyshev<T>(WOS_K0E_MID, BesselTerms<T>::kK0Mid, ((T)2 * x - (T)11) * (T)0.2);
   return chebyshev<T>(WOS_K0E_TAIL, BesselTerms<T>::kK0Tail, (T)16 / x - (T)1) / m_sqrt(x);
+}
+
+// Power series of I1 and K1 for small x (x <= 2 for I1, x <= 1 for K1), q = x^2/4:
+//   I1(x) = (x/2) sum_{k>=0} q^k/(k!(k+1)!)
+//   K1(x) = 1/x + ln(x/2) I1(x) - (x/4) sum_{k>=0} (psi(k+1) + psi(k+2)) q^k/(k!(k+1)!)
+// with psi(k+1) + psi(k+2) = H_k + H_{k+1} - 2 gamma_E.
+template <typename T>
+__device__ __forceinline__ void bessel_series1(T x, T* i1, T* k1) {
+  const T q = (T)0.25 * x * x;
+  T term = 1, s_i = 1, h = 0, s_k = -(T)2 * Consts<T>::kEulerGamma + (T)1;   // k = 0: H_0 + H_1 = 1
+  for (int k = 1; k <= BesselTerms<T>::kSeries; ++k) {
+    term *= q / (T)(k * (k + 1));
+    const T hk = h + (T)1 / (T)k;                 // H_k
+    const T hk1 = hk + (T)1 / (T)(k + 1);         // H_{k+1}
+    h = hk;
+    s_i += term;
+    s_k = m_fma(term, hk + hk1 - (T)2 * Consts<T>::kEulerGamma, s_k);
+  }
+  const T hx = (T)0.5 * x;
+  *i1 = hx * s_i;
+  if (k1) *k1 = (T)1 / x + m_log(hx) * (*i1) - (T)0.5 * hx * s_k;
+}
+
+// e^-x I1(x), x >= 0
+template <typename T>
+__device__ T bessel_i1e(T x) {
+  if (x <= (T)2) {
+    T i1;
+    bessel_series1<T>(x, &i1, nullptr);
+    return i1 * m_exp(-x);
+  }
+  if (x <= (T)8) return chebyshev<T>(WOS_I1E_MID, BesselTerms<T>::kI1Mid, (x - (T)5) * (T)(1.0 / 3.0));
+  return chebyshev<T>(WOS_I1E_TAIL, BesselTerms<T>::kI1Tail, (T)16 / x - (T)1) / m_sqrt(x);
+}
+
+// e^x K1(x), x > 0
+template <typename T>
+__device__ T bessel_k1e(T x) {
+  if (x <= (T)1) {
+    T i1, k1;
+    bessel_series1<T>(x, &i1, &k1);
+    return k1 * m_exp(x);
+  }
+  if (x <= (T)3) return chebyshev<T>(WOS_K1E_LOW, BesselTerms<T>::kK1Low, x - (T)2);
+  if (x <= (T)8) return chebyshev<T>(WOS_K1E_MID, BesselTerms<T>::kK1Mid, ((T)2 * x - (T)11) * (T)0.2);
+  return chebyshev<T>(WOS_K1E_TAIL, BesselTerms<T>::kK1Tail, (T)16 / x - (T)1) / m_sqrt(x);
 }
 
 // ------------------------------------------------------------------ ball kernels
@@ -256,6 +310,130 @@ __device__ __forceinline__ Ball<T, DIM> ball_terms(T R, T s, T inv_sigma_bar, bo
   }
   b.gnorm = b.pb * inv_sigma_bar;
   return b;
+}
+
+// ------------------------------------------------------------------ off-centred kernels
+// Closed-form approximations of the off-centred Green's function and Poisson kernel of
+// the ball B(c, R) for Lap - sigma_bar (supplemental Sec. 1.2), used by the next-flight
+// walk (Sec. 5.2). With u = x - c, v = y - c, w = y - x and rho = (R^2 - u.v)/R:
+//   G(x, y) |B|   = (Q(|w|) - Q(rho)) R^2/2            (2D; R^3/3 in 3D)
+//   P(x, z) |dB|  = R^{n-1} (V(|w|) (R^2 - u.v)/(|w| R) + V(rho) u.v / R^2)     (|z - c| = R)
+// Q and V are the radial profiles of the centred kernels (V = -Q'):
+//   2D: Q = K0(kr) - (K0(kR)/I0(kR)) I0(kr),   V = k (K1(kr) + (K0(kR)/I0(kR)) I1(kr))
+//   3D: Q = (e^{-kr} - e^{-kR} sinh(kr)/sinh(kR)) / r,
+//       V = (k/r) (e^{-kr} (1 + 1/(kr)) + e^{-kR}/sinh(kR) (cosh(kr) - sinh(kr)/(kr)))
+// and for sigma_bar = 0 the harmonic profiles Q = ln(R/r), V = 1/r (2D), Q = 1/r - 1/R,
+// V = 1/r^2 (3D). Growing exponentials are carried as e^{kr - 2kR} (kr <= 2kR), so no
+// term overflows in FP32.
+template <typename T, int DIM>
+struct NfBall {
+  T R, k, s;
+  T c;        // 2D: K0(s)/I0(s) (s < 2) or e^{2s} K0(s)/I0(s) (s >= 2); 3D: 1/(1 - e^{-2s})
+  T shift;    // 2D: 0 (s < 2) or 2s; 3D: 2s
+  bool harmonic;
+};
+
+template <typename T, int DIM>
+__device__ __forceinline__ NfBall<T, DIM> nf_ball(T R, T sqrt_sigma_bar, T c2d) {
+  NfBall<T, DIM> b;
+  b.R = R;
+  b.k = sqrt_sigma_bar;
+  b.s = R * sqrt_sigma_bar;
+  b.harmonic = !(sqrt_sigma_bar > (T)0);
+  if (DIM == 2) {
+    b.c = c2d;      // as produced by ball_terms
+    b.shift = b.s < (T)2 ? (T)0 : (T)2 * b.s;
+  } else {
+    b.c = (T)-1 / m_expm1((T)-2 * b.s);
+    b.shift = (T)2 * b.s;
+  }
+  return b;
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ T nf_Q(const NfBall<T, DIM>& b, T r) {
+  r = fmax(r, Consts<T>::kTiny);
+  if (b.harmonic) return DIM == 2 ? m_log(b.R / r) : (T)1 / r - (T)1 / b.R;
+  const T x = r * b.k;
+  if (DIM == 2) {
+    T k0;
+    if (x <= (T)1) {
+      T i0m1;
+      bessel_series<T>(x, &i0m1, &k0);
+    } else {
+      k0 = bessel_k0e<T>(x) * m_exp(-x);
+    }
+    return k0 - b.c * bessel_i0e<T>(x) * m_exp(x - b.shift);
+  }
+  // e^{-s} sinh(x)/sinh(s) = (e^{x-2s} - e^{-x-2s}) / (1 - e^{-2s})
+  T img;
+  if (b.s < (T)1) {
+    const T shx = (T)0.5 * (m_expm1(x) - m_expm1(-x));
+    const T shs = (T)0.5 * (m_expm1(b.s) - m_expm1(-b.s));
+    img = m_exp(-b.s) * shx / shs;
+  } else {
+    img = (m_exp(x - b.shift) - m_exp(-x - b.shift)) * b.c;
+  }
+  return (m_exp(-x) - img) / r;
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ T nf_V(const NfBall<T, DIM>& b, T r) {
+  r = fmax(r, Consts<T>::kTiny);
+  if (b.harmonic) return DIM == 2 ? (T)1 / r : (T)1 / (r * r);
+  const T x = r * b.k;
+  if (DIM == 2) {
+    T k1;
+    if (x <= (T)1) {
+      T i1;
+      bessel_series1<T>(x, &i1, &k1);
+    } else {
+      k1 = bessel_k1e<T>(x) * m_exp(-x);
+    }
+    return b.k * (k1 + b.c * bessel_i1e<T>(x) * m_exp(x - b.shift));
+  }
+  // e^{-s}/sinh(s) (cosh x - sinh(x)/x) = 2 e^{-2s}/(1 - e^{-2s}) (cosh x - sinh(x)/x)
+  T reg;
+  if (x < (T)0.5) {
+    const T x2 = x * x;   // cosh x - sinh(x)/x = x^2/3 + x^4/30 + x^6/840 + x^8/45360
+    const T ser = x2 * ((T)(1.0 / 3.0) + x2 * ((T)(1.0 / 30.0) + x2 * ((T)(1.0 / 840.0) + x2 * (T)(1.0 / 45360.0))));
+    reg = (T)2 * m_exp(-b.shift) * b.c * ser;
+  } else {
+    const T ix = (T)1 / x;
+    reg = (m_exp(x - b.shift) * ((T)1 - ix) + m_exp(-x - b.shift) * ((T)1 + ix)) * b.c;
+  }
+  return b.k / r * (m_exp(-x) * ((T)1 + (T)1 / x) + reg);
+}
+
+// G(x, y) |B| for u = x - c, v = y - c.
+template <typename T, int DIM>
+__device__ __forceinline__ T nf_green_vol(const NfBall<T, DIM>& b, const T* u, const T* v) {
+  T w2 = 0, uv = 0;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) {
+    const T d = v[i] - u[i];
+    w2 = m_fma(d, d, w2);
+    uv = m_fma(u[i], v[i], uv);
+  }
+  const T rho = (b.R * b.R - uv) / b.R;
+  const T vol = DIM == 2 ? (T)0.5 * b.R * b.R : b.R * b.R * b.R * (T)(1.0 / 3.0);
+  return (nf_Q<T, DIM>(b, m_sqrt(w2)) - nf_Q<T, DIM>(b, rho)) * vol;
+}
+
+// P(x, z) |dB| for u = x - c and z - c = v on the sphere.
+template <typename T, int DIM>
+__device__ __forceinline__ T nf_poisson_area(const NfBall<T, DIM>& b, const T* u, const T* v) {
+  T w2 = 0, uv = 0;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) {
+    const T d = v[i] - u[i];
+    w2 = m_fma(d, d, w2);
+    uv = m_fma(u[i], v[i], uv);
+  }
+  const T R = b.R, w = fmax(m_sqrt(w2), Consts<T>::kTiny);
+  const T rho = (R * R - uv) / R;
+  const T p = nf_V<T, DIM>(b, w) * (R * R - uv) / (w * R) + nf_V<T, DIM>(b, rho) * uv / (R * R);
+  return DIM == 2 ? p * R : p * R * R;
 }
 
 // Radius fraction t = |y - x|/R of y ~ G(x, .)/|G| (supp. Sec. 1.4). Exact rejection
@@ -357,6 +535,17 @@ __device__ __forceinline__ void uniform_direction(Rng& rng, T* v) {
     v[1] = rr * sn;
     v[2] = z;
   }
+}
+
+// Uniform point in the ball of radius R centred at the origin: uniform direction and
+// radius R U^{1/n}.
+template <typename T, int DIM>
+__device__ __forceinline__ void uniform_in_ball(Rng& rng, T R, T* p) {
+  uniform_direction<T, DIM>(rng, p);
+  const T u = uniform01<T>(rng);
+  const T r = R * (DIM == 2 ? m_sqrt(u) : m_cbrt(u));
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) p[i] *= r;
 }
 
 // ------------------------------------------------------------------ coefficient fields

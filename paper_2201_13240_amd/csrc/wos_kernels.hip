@@ -70,9 +70,23 @@ constexpr uint32_t kStepMask = (1u << 30) - 1;
 
 __device__ __forceinline__ const void* uniform_ptr(const void* p) { return (const void*)uniform_u64((uint64_t)p); }
 
+// A += term, with the rounding error of the addition carried in Ac when compensated
+// (TwoSum: Ac collects (A - (s - b)) + (term - b), b = s - A).
+template <typename T>
+__device__ __forceinline__ void add_estimate(T& A, T& Ac, T term, int compensated) {
+  if (compensated) {
+    const T s2 = A + term;
+    const T bb = s2 - A;
+    Ac += (A - (s2 - bb)) + (term - bb);
+    A = s2;
+  } else {
+    A += term;
+  }
+}
+
 // Buffers written by the walker are separate __restrict__ parameters, so loads of the
 // problem tables (read-only, at wave-uniform addresses) can be served by scalar loads.
-template <typename T, int DIM, int GEOM, bool COUNT>
+template <typename T, int DIM, int GEOM, bool COUNT, bool NF>
 __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* __restrict__ tile_counter,
                                                      WalkRecord* __restrict__ records,
                                                      uint64_t* __restrict__ events_out) {
@@ -108,6 +122,11 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* 
   uint32_t nsteps = 0, ntrials = 0;
   int last_prim = -1;   // closest primitive of the previous step (bounds the next query)
   Rng rng;
+  // next flight (phase 3 = inside the unrolled series of a ball): exit point z and current
+  // inner point, both relative to the ball centre x; the series T and S of the ball, the
+  // throughput, the ball radius and its 2D kernel constant. Pi holds prod_k T_k.
+  T zr[DIM], xc[DIM];
+  T nf_T = 0, nf_S = 0, nf_beta = 1, nf_R = 0, nf_c = 0;
 
   for (;;) {
     // ---------------------------------------------------------------- refill idle lanes
@@ -181,143 +200,251 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* 
     // the sampled point y otherwise, so the most expensive part runs in lockstep.
     if (phase != 0) {
       G<DevProblem<T>>& P = *Pp;
-      bool done = false, terminal = false, sampled = false;
-      uint32_t flag = 0;
-      T q[DIM];
+      if constexpr (NF) {
+        // ------------------------------------------------ next flight (Sec. 5.2, Alg. 2)
+        // A ball samples its exit point z once; the recursion inside the ball is unrolled
+        // into the series T (boundary) and S (source) over uniform inner points x^j, with
+        // roulette on the throughput prod theta_l, theta_l = G(x^l, x^{l+1}) (sigma_bar -
+        // sigma'(x^{l+1})) |B|. The source term f'(x^j)/(sigma_bar - sigma'(x^j)) times the
+        // throughput is taken as f'(x^j) G |B| times the throughput before theta_{j-1}, so
+        // sigma' = sigma_bar needs no division. U(x_k) ~ T U(z) + S; Pi = prod T.
+        bool done = false, terminal = false, sample = false;
+        uint32_t flag = 0;
+        T gb = 0;
+        T q[DIM], xn[DIM];
 #pragma unroll
-      for (int i = 0; i < DIM; ++i) q[i] = x[i];
-      T gb = 0, R = 0, t = 0;
-      T v[DIM];
-      Ball<T, DIM> b;
-      b.pb = 0;
-      b.gnorm = 0;
-      b.c2d = 0;
-      if (phase == 2) rng.refill();
-      if (phase == 2) {
-        if constexpr (COUNT) ++ev[EV_STEPS];
-        if (nsteps >= a.max_steps) {
-          done = true;
-          flag = kFlagCapped;
-        } else {
-          int prim;
-          const T d = boundary_distance<T, DIM, GEOM, COUNT>(P.geom, x, &prim, &tally, lds_stack, last_prim);
-          last_prim = prim;
-          ++nsteps;
-          if (!(d == d)) {
-            // a non-finite position cannot continue; report the walk as cut
+        for (int i = 0; i < DIM; ++i) {
+          q[i] = x[i];
+          xn[i] = 0;
+        }
+        if (phase >= 2) rng.refill();
+        if (phase == 3) {
+          const NfBall<T, DIM> nb = nf_ball<T, DIM>(nf_R, P.sqrt_sigma_bar, nf_c);
+          nf_T = m_fma(nf_poisson_area<T, DIM>(nb, xc, zr), nf_beta, nf_T);
+          const T prr = fmin((T)1, nf_beta);
+          if (uniform01<T>(rng) <= prr) {
+            nf_beta /= prr;
+            sample = true;
+          } else {
+            add_estimate(A, Ac, Pi * nf_S, a.compensated);
+            Pi *= nf_T;
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) x[i] += zr[i];
+            phase = 2;
+          }
+        }
+        if (phase == 2 && !sample) {
+          if constexpr (COUNT) ++ev[EV_STEPS];
+          if (nsteps >= a.max_steps) {
             done = true;
             flag = kFlagCapped;
-          } else if (d < P.epsilon) {
-            // epsilon shell: the walk returns g(xbar) (Alg. 1) times its weight, which
-            // needs gamma at the current point
-            T xb[DIM];
-            closest_point<T, DIM, GEOM>(P.geom, x, prim, xb);
-            gb = boundary_value<T, DIM>(P, xb);
-            terminal = true;
-            if constexpr (COUNT) {
-              ++ev[EV_TERMINAL];
-              if (!gx_known) ++ev[EV_GAMMA];
-            }
           } else {
-            R = d;
-            const bool harmonic = !(P.sigma_bar > (T)0);
-            const T s = R * P.sqrt_sigma_bar;
-            b = ball_terms<T, DIM>(R, s, P.inv_sigma_bar, harmonic);
-            if constexpr (COUNT) {
-              if (s >= (DIM == 2 ? (T)2 : (T)1)) ++ev[EV_BALL_LARGE_S];
-            }
-            uniform_direction<T, DIM>(rng, v);
-            t = sample_radius<T, DIM, COUNT>(rng, s, b, harmonic, ntrials, &tally);
-            if (t < (T)0) {  // sampler gave up (non-finite s): cut the walk
+            int prim;
+            const T d = boundary_distance<T, DIM, GEOM, COUNT>(P.geom, x, &prim, &tally, lds_stack, last_prim);
+            last_prim = prim;
+            ++nsteps;
+            if (!(d == d)) {
               done = true;
               flag = kFlagCapped;
+            } else if (d < P.epsilon) {
+              T xb[DIM];
+              closest_point<T, DIM, GEOM>(P.geom, x, prim, xb);
+              gb = boundary_value<T, DIM>(P, xb);
+              terminal = true;
+              if constexpr (COUNT) {
+                ++ev[EV_TERMINAL];
+                ++ev[EV_GAMMA];
+              }
             } else {
+              const bool harmonic = !(P.sigma_bar > (T)0);
+              const Ball<T, DIM> b = ball_terms<T, DIM>(d, d * P.sqrt_sigma_bar, P.inv_sigma_bar, harmonic);
+              nf_R = d;
+              nf_c = b.c2d;
+              nf_T = (T)1 - b.pb;     // P(x, z) |dB| at the centre
+              nf_S = 0;
+              nf_beta = 1;            // the first inner point is always taken
+              T v[DIM];
+              uniform_direction<T, DIM>(rng, v);
 #pragma unroll
-              for (int i = 0; i < DIM; ++i) q[i] = m_fma(t * R, v[i], x[i]);
-              sampled = true;
+              for (int i = 0; i < DIM; ++i) {
+                zr[i] = d * v[i];
+                xc[i] = 0;
+              }
+              sample = true;
             }
           }
         }
-      }
-      const bool evaluate = !done;
-      PointCoef<T> cq;
-      cq.gamma = 0;
-      cq.sigma_prime = 0;
-      cq.f_over_alpha = 0;
-      cq.alpha = 1;
-      if (evaluate) cq = point_coef<T, DIM, true>(P, q);
-      if (phase == 1) {
-        gamma0 = cq.gamma;
-        gx = gamma0;
-        gx_known = true;
-        phase = 2;
-      } else if (terminal) {
-        const T term = Pi * m_exp(cq.gamma - gamma0) * gb;
-        if (a.compensated) {
-          const T s2 = A + term;
-          const T bb = s2 - A;
-          Ac += (A - (s2 - bb)) + (term - bb);
-          A = s2;
-        } else {
-          A += term;
-        }
-        done = true;
-      } else if (sampled) {
-        const T mu = uniform01<T>(rng);
-        const bool volume = mu <= b.pb;
-        const T src = Pi * m_exp(cq.gamma - gamma0) * cq.f_over_alpha;
-        T term = 0;
-        if (a.variant == 0) term = b.gnorm * src;
-        else if (volume) term = src * P.inv_sigma_bar;
-        if (a.compensated) {
-          const T s2 = A + term;
-          const T bb = s2 - A;
-          Ac += (A - (s2 - bb)) + (term - bb);
-          A = s2;
-        } else {
-          A += term;
-        }
-        if constexpr (COUNT) ++ev[volume ? EV_VOLUME : EV_EXIT];
-        if (volume) {
-          // null event: weight (1 - sigma'(y)/sigma_bar) e^{gamma(y) - gamma(x)}, move to y
-          Pi *= (T)1 - cq.sigma_prime * P.inv_sigma_bar;
+        if (sample) {
+          uniform_in_ball<T, DIM>(rng, nf_R, xn);
 #pragma unroll
-          for (int i = 0; i < DIM; ++i) x[i] = q[i];
-          gx = cq.gamma;
-          gx_known = true;
-        } else {
-          // boundary term: uniform point on the sphere, weight e^{gamma(z) - gamma(x)}
-          T vz[DIM];
-          uniform_direction<T, DIM>(rng, vz);
-#pragma unroll
-          for (int i = 0; i < DIM; ++i) x[i] = m_fma(R, vz[i], x[i]);
-          gx_known = false;
-          if (a.rr) {
-            gx = point_gamma<T, DIM>(P, x);
-            gx_known = true;
-            if constexpr (COUNT) ++ev[EV_GAMMA];
-          }
+          for (int i = 0; i < DIM; ++i) q[i] = x[i] + xn[i];
         }
-        if (a.rr) {
-          // static weight window, low side (Sec. 6): survive with probability |W|/w-
-          const T e = m_exp(gx - gamma0);
-          const T W = Pi * e;
-          if (m_fabs(W) < a.ww_lo) {
-            if constexpr (COUNT) ++ev[EV_RR_TESTS];
-            const T u = uniform01<T>(rng);
-            if (u * a.ww_lo <= m_fabs(W)) {
-              Pi = (W < (T)0 ? -a.ww_lo : a.ww_lo) / e;
-            } else {
+        PointCoef<T> cq;
+        cq.gamma = 0;
+        cq.sigma_prime = 0;
+        cq.f_over_alpha = 0;
+        cq.alpha = 1;
+        if (phase == 1 || terminal || sample) cq = point_coef<T, DIM, true>(P, q);
+        if (phase == 1) {
+          gamma0 = cq.gamma;
+          phase = 2;
+        } else if (terminal) {
+          add_estimate(A, Ac, Pi * m_exp(cq.gamma - gamma0) * gb, a.compensated);
+          done = true;
+        } else if (sample) {
+          const NfBall<T, DIM> nb = nf_ball<T, DIM>(nf_R, P.sqrt_sigma_bar, nf_c);
+          const T gv = nf_green_vol<T, DIM>(nb, xc, xn);
+          nf_S = m_fma(nf_beta * gv, m_exp(cq.gamma - gamma0) * cq.f_over_alpha, nf_S);
+          nf_beta *= gv * (P.sigma_bar - cq.sigma_prime);
+#pragma unroll
+          for (int i = 0; i < DIM; ++i) xc[i] = xn[i];
+          ++ntrials;
+          phase = 3;
+        }
+        if (done) {
+          records[wid] = WalkRecord{(double)A + (double)Ac, (nsteps & kStepMask) | flag, ntrials};
+          if constexpr (COUNT) ev[EV_TRIALS] += ntrials;
+          phase = 0;
+        }
+      } else {
+        bool done = false, terminal = false, sampled = false;
+        uint32_t flag = 0;
+        T q[DIM];
+  #pragma unroll
+        for (int i = 0; i < DIM; ++i) q[i] = x[i];
+        T gb = 0, R = 0, t = 0;
+        T v[DIM];
+        Ball<T, DIM> b;
+        b.pb = 0;
+        b.gnorm = 0;
+        b.c2d = 0;
+        if (phase == 2) rng.refill();
+        if (phase == 2) {
+          if constexpr (COUNT) ++ev[EV_STEPS];
+          if (nsteps >= a.max_steps) {
+            done = true;
+            flag = kFlagCapped;
+          } else {
+            int prim;
+            const T d = boundary_distance<T, DIM, GEOM, COUNT>(P.geom, x, &prim, &tally, lds_stack, last_prim);
+            last_prim = prim;
+            ++nsteps;
+            if (!(d == d)) {
+              // a non-finite position cannot continue; report the walk as cut
               done = true;
-              flag = kFlagRR;
+              flag = kFlagCapped;
+            } else if (d < P.epsilon) {
+              // epsilon shell: the walk returns g(xbar) (Alg. 1) times its weight, which
+              // needs gamma at the current point
+              T xb[DIM];
+              closest_point<T, DIM, GEOM>(P.geom, x, prim, xb);
+              gb = boundary_value<T, DIM>(P, xb);
+              terminal = true;
+              if constexpr (COUNT) {
+                ++ev[EV_TERMINAL];
+                if (!gx_known) ++ev[EV_GAMMA];
+              }
+            } else {
+              R = d;
+              const bool harmonic = !(P.sigma_bar > (T)0);
+              const T s = R * P.sqrt_sigma_bar;
+              b = ball_terms<T, DIM>(R, s, P.inv_sigma_bar, harmonic);
+              if constexpr (COUNT) {
+                if (s >= (DIM == 2 ? (T)2 : (T)1)) ++ev[EV_BALL_LARGE_S];
+              }
+              uniform_direction<T, DIM>(rng, v);
+              t = sample_radius<T, DIM, COUNT>(rng, s, b, harmonic, ntrials, &tally);
+              if (t < (T)0) {  // sampler gave up (non-finite s): cut the walk
+                done = true;
+                flag = kFlagCapped;
+              } else {
+  #pragma unroll
+                for (int i = 0; i < DIM; ++i) q[i] = m_fma(t * R, v[i], x[i]);
+                sampled = true;
+              }
             }
           }
         }
-      }
-      if (done) {
-        records[wid] = WalkRecord{(double)A + (double)Ac, (nsteps & kStepMask) | flag, ntrials};
-        if constexpr (COUNT) ev[EV_TRIALS] += ntrials;
-        phase = 0;
+        const bool evaluate = !done;
+        PointCoef<T> cq;
+        cq.gamma = 0;
+        cq.sigma_prime = 0;
+        cq.f_over_alpha = 0;
+        cq.alpha = 1;
+        if (evaluate) cq = point_coef<T, DIM, true>(P, q);
+        if (phase == 1) {
+          gamma0 = cq.gamma;
+          gx = gamma0;
+          gx_known = true;
+          phase = 2;
+        } else if (terminal) {
+          const T term = Pi * m_exp(cq.gamma - gamma0) * gb;
+          if (a.compensated) {
+            const T s2 = A + term;
+            const T bb = s2 - A;
+            Ac += (A - (s2 - bb)) + (term - bb);
+            A = s2;
+          } else {
+            A += term;
+          }
+          done = true;
+        } else if (sampled) {
+          const T mu = uniform01<T>(rng);
+          const bool volume = mu <= b.pb;
+          const T src = Pi * m_exp(cq.gamma - gamma0) * cq.f_over_alpha;
+          T term = 0;
+          if (a.variant == 0) term = b.gnorm * src;
+          else if (volume) term = src * P.inv_sigma_bar;
+          if (a.compensated) {
+            const T s2 = A + term;
+            const T bb = s2 - A;
+            Ac += (A - (s2 - bb)) + (term - bb);
+            A = s2;
+          } else {
+            A += term;
+          }
+          if constexpr (COUNT) ++ev[volume ? EV_VOLUME : EV_EXIT];
+          if (volume) {
+            // null event: weight (1 - sigma'(y)/sigma_bar) e^{gamma(y) - gamma(x)}, move to y
+            Pi *= (T)1 - cq.sigma_prime * P.inv_sigma_bar;
+  #pragma unroll
+            for (int i = 0; i < DIM; ++i) x[i] = q[i];
+            gx = cq.gamma;
+            gx_known = true;
+          } else {
+            // boundary term: uniform point on the sphere, weight e^{gamma(z) - gamma(x)}
+            T vz[DIM];
+            uniform_direction<T, DIM>(rng, vz);
+  #pragma unroll
+            for (int i = 0; i < DIM; ++i) x[i] = m_fma(R, vz[i], x[i]);
+            gx_known = false;
+            if (a.rr) {
+              gx = point_gamma<T, DIM>(P, x);
+              gx_known = true;
+              if constexpr (COUNT) ++ev[EV_GAMMA];
+            }
+          }
+          if (a.rr) {
+            // static weight window, low side (Sec. 6): survive with probability |W|/w-
+            const T e = m_exp(gx - gamma0);
+            const T W = Pi * e;
+            if (m_fabs(W) < a.ww_lo) {
+              if constexpr (COUNT) ++ev[EV_RR_TESTS];
+              const T u = uniform01<T>(rng);
+              if (u * a.ww_lo <= m_fabs(W)) {
+                Pi = (W < (T)0 ? -a.ww_lo : a.ww_lo) / e;
+              } else {
+                done = true;
+                flag = kFlagRR;
+              }
+            }
+          }
+        }
+        if (done) {
+          records[wid] = WalkRecord{(double)A + (double)Ac, (nsteps & kStepMask) | flag, ntrials};
+          if constexpr (COUNT) ev[EV_TRIALS] += ntrials;
+          phase = 0;
+        }
       }
     }
   }
@@ -586,7 +713,31 @@ template <typename T>
 __global__ void bessel_kernel(int which, const double* x, int64_t n, double* out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  out[i] = which == 0 ? (double)bessel_i0e<T>((T)x[i]) : (double)bessel_k0e<T>((T)x[i]);
+  const T v = (T)x[i];
+  out[i] = which == 0 ? (double)bessel_i0e<T>(v)
+           : which == 1 ? (double)bessel_k0e<T>(v)
+           : which == 2 ? (double)bessel_i1e<T>(v)
+                        : (double)bessel_k1e<T>(v);
+}
+
+// Off-centred kernels of the next-flight walk at explicit points: which 0 = G(x, y) |B|,
+// 1 = P(x, z) |dB|, for u = x - c, v = y - c (rows of [n][DIM]).
+template <typename T, int DIM>
+__global__ void offcentred_kernel(int which, T R, T sigma_bar, const double* u, const double* v, int64_t n,
+                                  double* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T uu[DIM], vv[DIM];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    uu[k] = (T)u[i * DIM + k];
+    vv[k] = (T)v[i * DIM + k];
+  }
+  const bool harmonic = !(sigma_bar > (T)0);
+  const T k = harmonic ? (T)0 : m_sqrt(sigma_bar);
+  const Ball<T, DIM> b = ball_terms<T, DIM>(R, R * k, harmonic ? (T)0 : (T)1 / sigma_bar, harmonic);
+  const NfBall<T, DIM> nb = nf_ball<T, DIM>(R, k, b.c2d);
+  out[i] = which == 0 ? (double)nf_green_vol<T, DIM>(nb, uu, vv) : (double)nf_poisson_area<T, DIM>(nb, uu, vv);
 }
 
 __global__ void finalize_kernel(const double* sum, const double* sum_sq, const uint64_t* nw, int64_t n, double* mean,
@@ -619,12 +770,22 @@ static hipError_t launch_walker_t(const WalkerLaunch& L, hipStream_t st) {
   a.rr = L.rr;
   a.ww_lo = (T)L.ww_lo;
   a.events = L.events;
-  if (L.events)
-    hipLaunchKernelGGL((walker_kernel<T, DIM, GEOM, true>), dim3(L.grid), dim3(L.block), 0, st, a, L.tile_counter,
-                       L.records, L.events);
-  else
-    hipLaunchKernelGGL((walker_kernel<T, DIM, GEOM, false>), dim3(L.grid), dim3(L.block), 0, st, a, L.tile_counter,
-                       L.records, (uint64_t*)nullptr);
+  const dim3 g(L.grid), b(L.block);
+  if (L.variant == 2) {
+    if (L.events)
+      hipLaunchKernelGGL((walker_kernel<T, DIM, GEOM, true, true>), g, b, 0, st, a, L.tile_counter, L.records,
+                         L.events);
+    else
+      hipLaunchKernelGGL((walker_kernel<T, DIM, GEOM, false, true>), g, b, 0, st, a, L.tile_counter, L.records,
+                         (uint64_t*)nullptr);
+  } else {
+    if (L.events)
+      hipLaunchKernelGGL((walker_kernel<T, DIM, GEOM, true, false>), g, b, 0, st, a, L.tile_counter, L.records,
+                         L.events);
+    else
+      hipLaunchKernelGGL((walker_kernel<T, DIM, GEOM, false, false>), g, b, 0, st, a, L.tile_counter, L.records,
+                         (uint64_t*)nullptr);
+  }
   return hipGetLastError();
 }
 
@@ -651,15 +812,23 @@ hipError_t launch_walker(const WalkerLaunch& L, hipStream_t st) {
 }
 
 template <typename T, int DIM, int GEOM>
-static const void* walker_symbol_t() { return (const void*)&walker_kernel<T, DIM, GEOM, false>; }
+static const void* walker_symbol_t(bool nf) {
+  return nf ? (const void*)&walker_kernel<T, DIM, GEOM, false, true> : (const void*)&walker_kernel<T, DIM, GEOM, false, false>;
+}
 
-const void* walker_symbol(int fp64, int dim, int geom) {
-  if (fp64) {
-    if (dim == 2) return geom == GK_BALL ? walker_symbol_t<double, 2, GK_BALL>() : geom == GK_BOX ? walker_symbol_t<double, 2, GK_BOX>() : walker_symbol_t<double, 2, GK_POLYGON>();
-    return geom == GK_BALL ? walker_symbol_t<double, 3, GK_BALL>() : geom == GK_BOX ? walker_symbol_t<double, 3, GK_BOX>() : walker_symbol_t<double, 3, GK_TRIMESH>();
-  }
-  if (dim == 2) return geom == GK_BALL ? walker_symbol_t<float, 2, GK_BALL>() : geom == GK_BOX ? walker_symbol_t<float, 2, GK_BOX>() : walker_symbol_t<float, 2, GK_POLYGON>();
-  return geom == GK_BALL ? walker_symbol_t<float, 3, GK_BALL>() : geom == GK_BOX ? walker_symbol_t<float, 3, GK_BOX>() : walker_symbol_t<float, 3, GK_TRIMESH>();
+template <typename T>
+static const void* walker_symbol_dim(int dim, int geom, bool nf) {
+  if (dim == 2)
+    return geom == GK_BALL ? walker_symbol_t<T, 2, GK_BALL>(nf)
+           : geom == GK_BOX ? walker_symbol_t<T, 2, GK_BOX>(nf)
+                            : walker_symbol_t<T, 2, GK_POLYGON>(nf);
+  return geom == GK_BALL ? walker_symbol_t<T, 3, GK_BALL>(nf)
+         : geom == GK_BOX ? walker_symbol_t<T, 3, GK_BOX>(nf)
+                          : walker_symbol_t<T, 3, GK_TRIMESH>(nf);
+}
+
+const void* walker_symbol(int fp64, int dim, int geom, int variant) {
+  return fp64 ? walker_symbol_dim<double>(dim, geom, variant == 2) : walker_symbol_dim<float>(dim, geom, variant == 2);
 }
 
 hipError_t launch_reduce(const DevItem& it, const WalkRecord* records, hipStream_t st) {
@@ -798,6 +967,22 @@ hipError_t launch_sample(int fp64, int dim, double s, int64_t n, uint64_t seed, 
 hipError_t launch_philox(const uint32_t* ctr, uint64_t key, int64_t n, uint32_t* out, hipStream_t st) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(philox_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, ctr, key, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_offcentred(int fp64, int dim, int which, double R, double sigma_bar, const double* u,
+                             const double* v, int64_t n, double* out, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const dim3 g(blocks_for(n, 256)), b(256);
+  if (fp64) {
+    if (dim == 2) hipLaunchKernelGGL((offcentred_kernel<double, 2>), g, b, 0, st, which, R, sigma_bar, u, v, n, out);
+    else hipLaunchKernelGGL((offcentred_kernel<double, 3>), g, b, 0, st, which, R, sigma_bar, u, v, n, out);
+  } else {
+    if (dim == 2)
+      hipLaunchKernelGGL((offcentred_kernel<float, 2>), g, b, 0, st, which, (float)R, (float)sigma_bar, u, v, n, out);
+    else
+      hipLaunchKernelGGL((offcentred_kernel<float, 3>), g, b, 0, st, which, (float)R, (float)sigma_bar, u, v, n, out);
+  }
   return hipGetLastError();
 }
 

@@ -29,7 +29,7 @@ struct WalkerLaunch {
 };
 
 hipError_t launch_walker(const WalkerLaunch& L, hipStream_t st);
-const void* walker_symbol(int fp64, int dim, int geom);
+const void* walker_symbol(int fp64, int dim, int geom, int variant);
 hipError_t launch_reduce(const DevItem& it, const WalkRecord* records, hipStream_t st);
 hipError_t launch_reset(uint32_t* counter, hipStream_t st);
 hipError_t launch_set_params(LaunchParams* lp, uint64_t seed, uint64_t walk_offset_add, hipStream_t st);
@@ -46,6 +46,8 @@ hipError_t launch_sample(int fp64, int dim, double s, int64_t n, uint64_t seed, 
                          hipStream_t st);
 hipError_t launch_philox(const uint32_t* ctr, uint64_t key, int64_t n, uint32_t* out, hipStream_t st);
 hipError_t launch_bessel(int fp64, int which, const double* x, int64_t n, double* out, hipStream_t st);
+hipError_t launch_offcentred(int fp64, int dim, int which, double R, double sigma_bar, const double* u,
+                             const double* v, int64_t n, double* out, hipStream_t st);
 hipError_t launch_finalize(const double* sum, const double* sum_sq, const uint64_t* nw, int64_t n, double* mean,
                            double* se, hipStream_t st);
 

@@ -65,7 +65,7 @@ class BatchItem(C.Structure):
 EXPORTS = ["wos_last_error", "wos_version", "wos_problem_create", "wos_problem_info", "wos_problem_bvh_info", "wos_problem_grid_info",
            "wos_problem_destroy", "wos_solve", "wos_count_events", "wos_finalize", "wos_plan_create", "wos_plan_launch",
            "wos_plan_time", "wos_plan_info", "wos_plan_destroy", "wos_eval_coefficients", "wos_eval_distance", "wos_eval_ball",
-           "wos_sample_radius", "wos_philox", "wos_eval_bessel", "wos_classify"]
+           "wos_sample_radius", "wos_philox", "wos_eval_bessel", "wos_eval_offcentred", "wos_classify"]
 
 _lib = None
 
@@ -99,6 +99,7 @@ def lib():
         L.wos_sample_radius.argtypes = [i32, i32, C.c_double, i64, u64, vp, vp, vp]
         L.wos_philox.argtypes = [vp, u64, i64, vp, vp]
         L.wos_eval_bessel.argtypes = [i32, i32, vp, i64, vp, vp]
+        L.wos_eval_offcentred.argtypes = [i32, i32, i32, C.c_double, C.c_double, vp, vp, i64, vp, vp]
         L.wos_classify.argtypes = [vp, vp, i64, vp, vp]
         _lib = L
     return _lib
@@ -243,11 +244,14 @@ class Accumulators:
         self.counters = torch.zeros(4, dtype=torch.int64, device=device)
 
 
+VARIANTS = {"alg1": 0, "eq28": 1, "next_flight": 2}
+
+
 def options(precision="fp32", walks=128, seed=0, walk_offset=0, variant=0, russian_roulette=False, ww_lo=0.5,
             max_steps=0, block_size=0, tile_walks=0, workspace_bytes=0):
     o = Options()
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    o.variant = variant
+    o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
     o.seed = seed
     o.walks_per_point = walks
     o.walk_offset = walk_offset
@@ -393,8 +397,20 @@ def philox(ctr, key, stream=None):
 def eval_bessel(which, x, precision="fp64", stream=None):
     import torch
     out = torch.empty_like(x)
-    _check(lib().wos_eval_bessel({"i0e": 0, "k0e": 1}[which], _prec(precision), _ptr(x), x.shape[0], _ptr(out),
-                                 _stream(stream)))
+    _check(lib().wos_eval_bessel({"i0e": 0, "k0e": 1, "i1e": 2, "k1e": 3}[which], _prec(precision), _ptr(x),
+                                 x.shape[0], _ptr(out), _stream(stream)))
+    return out
+
+
+def eval_offcentred(which, dim, R, sigma_bar, u, v, precision="fp64", stream=None):
+    """Next-flight kernels: which 'green' gives G(x, y)|B| (u = x - c, v = y - c), 'poisson'
+    gives P(x, z)|dB| (v = z - c on the sphere). u, v: device float64 [n][dim]."""
+    import torch
+    assert u.shape == v.shape and u.shape[1] == dim and u.dtype == torch.float64 and v.dtype == torch.float64
+    out = torch.empty(u.shape[0], dtype=torch.float64, device=u.device)
+    _check(lib().wos_eval_offcentred({"green": 0, "poisson": 1}[which], dim, _prec(precision), float(R),
+                                     float(sigma_bar), _ptr(u.contiguous()), _ptr(v.contiguous()), u.shape[0],
+                                     _ptr(out), _stream(stream)))
     return out
 
 

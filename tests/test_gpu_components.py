@@ -39,6 +39,40 @@ def test_scaled_bessel(W, precision, tol):
     k0e = W.eval_bessel("k0e", xi, precision).cpu().numpy()
     np.testing.assert_allclose(i0e, special.i0e(x), rtol=tol)
     np.testing.assert_allclose(k0e, special.k0e(x), rtol=tol * (20 if precision == "fp32" else 2))
+    # order 1 (off-centred Poisson kernel of the next-flight walk)
+    i1e = W.eval_bessel("i1e", xi, precision).cpu().numpy()
+    k1e = W.eval_bessel("k1e", xi, precision).cpu().numpy()
+    np.testing.assert_allclose(i1e, special.i1e(x), rtol=tol * 2)
+    np.testing.assert_allclose(k1e, special.k1e(x), rtol=tol * (20 if precision == "fp32" else 2))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("sb", [0.0, 0.3, 4.0, 60.0, 3000.0])
+def test_offcentred_kernels_match_oracle(W, oracle, dim, precision, sb):
+    """G(x, y)|B| and P(x, z)|dB| of the next-flight walk (supplemental Sec. 1.2
+    approximations) against the oracle's at uniform points of the ball; the error is
+    measured against the kernel scale (R^2 for G|B|, 1 for P|dB|)."""
+    rng = np.random.default_rng(int(10 * sb) + dim)
+    R, n = 0.8, 4000
+    d = rng.normal(size=(n, dim))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    u = d * (R * rng.uniform(0, 1, (n, 1)) ** (1 / dim))
+    d2 = rng.normal(size=(n, dim))
+    d2 /= np.linalg.norm(d2, axis=1, keepdims=True)
+    v = d2 * (R * rng.uniform(0, 1, (n, 1)) ** (1 / dim))
+    z = d2 * R
+    g = W.eval_offcentred("green", dim, R, sb, dev(u), dev(v), precision).cpu().numpy()
+    p = W.eval_offcentred("poisson", dim, R, sb, dev(u), dev(z), precision).cpu().numpy()
+    vol = np.pi * R * R if dim == 2 else 4 / 3 * np.pi * R ** 3
+    area = 2 * np.pi * R if dim == 2 else 4 * np.pi * R * R
+    g_ref = oracle.nf_kernel("green", dim, u, v, R, sb) * vol
+    p_ref = oracle.nf_kernel("poisson", dim, u, z, R, sb) * area
+    tol = 1e-9 if precision == "fp64" else 1e-3
+    eg = np.abs(g - g_ref) / np.maximum(np.abs(g_ref), 1e-3 * R * R)
+    ep = np.abs(p - p_ref) / np.maximum(np.abs(p_ref), 1e-6)
+    assert eg.max() < tol and ep.max() < tol, (eg.max(), ep.max())
+    assert np.median(eg) < tol / 100 and np.median(ep) < tol / 100
 
 
 @pytest.mark.parametrize("dim", [2, 3])
