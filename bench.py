@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--cpu-points", type=int, default=96, help="oracle sample size (0: skip)")
     ap.add_argument("--cpu-walks", type=int, default=8192)
     ap.add_argument("--no-events", action="store_true")
+    ap.add_argument("--variants", type=int, default=1,
+                    help="also time next flight against delta tracking on the high-contrast square (0: skip)")
     ap.add_argument("--shape", default="auto",
                     help="walker launch shape: 'auto' (the plan autotunes block size and tile length) or "
                          "BLOCKxTILE, e.g. 256x256 (profiling runs pin the tuned shape so that no tuning "
@@ -253,6 +255,60 @@ def copy_probe():
     print("copied bytes", n * 4, flush=True)
 
 
+def compare_variants(wos, WL, args):
+    """Next flight (Sec. 5.2) against delta tracking (Sec. 5.1) on the high-contrast unit
+    square: 65,536 query points, sigma_bar about 1.2e4, where delta tracking takes many
+    short steps. Both FP32 at the same walks per point, one captured plan each; reports
+    pass time, distance queries per walk, per-walk variance, points per second at RMSE
+    1e-2 from that variance, and how far the two means are apart in combined standard
+    errors (next flight's off-centred kernel approximations are biased off the centre)."""
+    import torch
+    c = WL.config5()
+    prob, pts = c["problems"][0], c["points"][0]
+    n = pts.shape[0]
+    h = wos.Problem(prob)
+    P = torch.as_tensor(pts, dtype=torch.float64, device="cuda")
+    walks = 256
+    out = {"workload": "unit square, alpha tanh jump 1..100, omega = (50, 0), sigma in [100, 1000], "
+                       "256x256 points", "walks_per_point": walks, "sigma_bar": h.sigma_bar}
+    res = {}
+    for name, variant, rr in (("delta_tracking", 0, True), ("next_flight", 2, False)):
+        acc = wos.Accumulators(n)
+        plan = wos.Plan([(h, P, acc, 0)], wos.options(precision="fp32", walks=walks, seed=0, variant=variant,
+                                                      russian_roulette=rr))
+        plan.launch(seed=99)
+        torch.cuda.synchronize()
+        for t in (acc.sum, acc.sum_sq, acc.n_walks, acc.n_steps, acc.counters):
+            t.zero_()
+        ms = []
+        for k in range(3):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            plan.launch(seed=k, walk_offset_add=k * walks)
+            b.record()
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        mean, se = wos.finalize(acc)
+        torch.cuda.synchronize()
+        plan.close()
+        nw = float(acc.n_walks[0].item())
+        var = float(np.mean((se.cpu().numpy() ** 2) * nw))
+        t_walk = (np.mean(ms) / 1e3) / walks
+        res[name] = (mean.cpu().numpy(), se.cpu().numpy())
+        out[name] = {"ms_per_pass": float(np.mean(ms)),
+                     "distance_queries_per_walk": float(acc.n_steps.sum().item()) / (nw * n),
+                     "ball_samples_per_walk": float(acc.counters[3].item()) / (nw * n),
+                     "per_walk_variance": var,
+                     "points_per_s_at_rmse_1e-2": n / ((var / 1e-4) * t_walk)}
+        print(f"bench: {name} on the high-contrast square, ms/pass {np.round(ms, 2).tolist()}", file=sys.stderr,
+              flush=True)
+    (m0, s0), (m1, s1) = res["delta_tracking"], res["next_flight"]
+    z = (m1 - m0) / np.sqrt(s0 ** 2 + s1 ** 2)
+    out["mean_abs_z_next_flight_vs_delta_tracking"] = float(np.mean(np.abs(z)))
+    out["mean_abs_difference"] = float(np.mean(np.abs(m1 - m0)))
+    return out
+
+
 def main():
     args = parse()
     if args.summarize_trace:
@@ -420,6 +476,8 @@ def main():
         "rmse": rmse,
     }
     line.update(out64)
+    if args.variants:
+        line["next_flight_vs_delta_tracking"] = compare_variants(wos, WL, args)
     print(json.dumps(line), flush=True)
 
 

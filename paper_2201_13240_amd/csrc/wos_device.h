@@ -40,6 +40,12 @@ __device__ __forceinline__ float m_tanh(float x) { return ::tanhf(x); }
 __device__ __forceinline__ double m_tanh(double x) { return ::tanh(x); }
 __device__ __forceinline__ float m_cbrt(float x) { return ::cbrtf(x); }
 __device__ __forceinline__ double m_cbrt(double x) { return ::cbrt(x); }
+// Reciprocal and quotient: FP32 takes the hardware reciprocal (1 ulp) instead of the
+// correctly rounded division sequence; FP64 divides exactly.
+__device__ __forceinline__ float m_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double m_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float m_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double m_div(double a, double b) { return a / b; }
 __device__ __forceinline__ float m_fabs(float x) { return ::fabsf(x); }
 __device__ __forceinline__ double m_fabs(double x) { return ::fabs(x); }
 __device__ __forceinline__ float m_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -174,7 +180,7 @@ __device__ __forceinline__ void bessel_series(T x, T* i0m1, T* k0) {
   const T q = (T)0.25 * x * x;
   T term = 1, s_i = 0, s_k = 0, h = 0;
   for (int k = 1; k <= BesselTerms<T>::kSeries; ++k) {
-    term *= q / (T)(k * k);
+    term *= q * (T)(1.0 / (k * k));
     h += (T)1 / (T)k;
     s_i += term;
     s_k = m_fma(term, h, s_k);
@@ -192,7 +198,7 @@ __device__ T bessel_i0e(T x) {
     return ((T)1 + i0m1) * m_exp(-x);
   }
   if (x <= (T)8) return chebyshev<T>(WOS_I0E_MID, BesselTerms<T>::kI0Mid, (x - (T)5) * (T)(1.0 / 3.0));
-  return chebyshev<T>(WOS_I0E_TAIL, BesselTerms<T>::kI0Tail, (T)16 / x - (T)1) / m_sqrt(x);
+  return m_div(chebyshev<T>(WOS_I0E_TAIL, BesselTerms<T>::kI0Tail, (T)16 * m_rcp(x) - (T)1), m_sqrt(x));
 }
 
 // e^x K0(x), x > 0
@@ -205,7 +211,7 @@ __device__ T bessel_k0e(T x) {
   }
   if (x <= (T)3) return chebyshev<T>(WOS_K0E_LOW, BesselTerms<T>::kK0Low, x - (T)2);
   if (x <= (T)8) return chebyshev<T>(WOS_K0E_MID, BesselTerms<T>::kK0Mid, ((T)2 * x - (T)11) * (T)0.2);
-  return chebyshev<T>(WOS_K0E_TAIL, BesselTerms<T>::kK0Tail, (T)16 / x - (T)1) / m_sqrt(x);
+  return m_div(chebyshev<T>(WOS_K0E_TAIL, BesselTerms<T>::kK0Tail, (T)16 * m_rcp(x) - (T)1), m_sqrt(x));
 }
 
 // Power series of I1 and K1 for small x (x <= 2 for I1, x <= 1 for K1), q = x^2/4:
@@ -217,7 +223,7 @@ __device__ __forceinline__ void bessel_series1(T x, T* i1, T* k1) {
   const T q = (T)0.25 * x * x;
   T term = 1, s_i = 1, h = 0, s_k = -(T)2 * Consts<T>::kEulerGamma + (T)1;   // k = 0: H_0 + H_1 = 1
   for (int k = 1; k <= BesselTerms<T>::kSeries; ++k) {
-    term *= q / (T)(k * (k + 1));
+    term *= q * (T)(1.0 / (k * (k + 1)));
     const T hk = h + (T)1 / (T)k;                 // H_k
     const T hk1 = hk + (T)1 / (T)(k + 1);         // H_{k+1}
     h = hk;
@@ -226,7 +232,7 @@ __device__ __forceinline__ void bessel_series1(T x, T* i1, T* k1) {
   }
   const T hx = (T)0.5 * x;
   *i1 = hx * s_i;
-  if (k1) *k1 = (T)1 / x + m_log(hx) * (*i1) - (T)0.5 * hx * s_k;
+  if (k1) *k1 = m_rcp(x) + m_log(hx) * (*i1) - (T)0.5 * hx * s_k;
 }
 
 // e^-x I1(x), x >= 0
@@ -238,7 +244,7 @@ __device__ T bessel_i1e(T x) {
     return i1 * m_exp(-x);
   }
   if (x <= (T)8) return chebyshev<T>(WOS_I1E_MID, BesselTerms<T>::kI1Mid, (x - (T)5) * (T)(1.0 / 3.0));
-  return chebyshev<T>(WOS_I1E_TAIL, BesselTerms<T>::kI1Tail, (T)16 / x - (T)1) / m_sqrt(x);
+  return m_div(chebyshev<T>(WOS_I1E_TAIL, BesselTerms<T>::kI1Tail, (T)16 * m_rcp(x) - (T)1), m_sqrt(x));
 }
 
 // e^x K1(x), x > 0
@@ -251,7 +257,7 @@ __device__ T bessel_k1e(T x) {
   }
   if (x <= (T)3) return chebyshev<T>(WOS_K1E_LOW, BesselTerms<T>::kK1Low, x - (T)2);
   if (x <= (T)8) return chebyshev<T>(WOS_K1E_MID, BesselTerms<T>::kK1Mid, ((T)2 * x - (T)11) * (T)0.2);
-  return chebyshev<T>(WOS_K1E_TAIL, BesselTerms<T>::kK1Tail, (T)16 / x - (T)1) / m_sqrt(x);
+  return m_div(chebyshev<T>(WOS_K1E_TAIL, BesselTerms<T>::kK1Tail, (T)16 * m_rcp(x) - (T)1), m_sqrt(x));
 }
 
 // ------------------------------------------------------------------ ball kernels
@@ -285,12 +291,14 @@ __device__ __forceinline__ Ball<T, DIM> ball_terms(T R, T s, T inv_sigma_bar, bo
         k0 = bessel_k0e<T>(s) * m_exp(-s);
       }
       const T i0 = (T)1 + i0m1;
-      b.pb = i0m1 / i0;
-      b.c2d = k0 / i0;
+      const T ii0 = m_rcp(i0);
+      b.pb = i0m1 * ii0;
+      b.c2d = k0 * ii0;
     } else {
       const T i0e = bessel_i0e<T>(s);
-      b.pb = (T)1 - m_exp(-s) / i0e;
-      b.c2d = bessel_k0e<T>(s) / i0e;
+      const T ii0 = m_rcp(i0e);
+      b.pb = (T)1 - m_exp(-s) * ii0;
+      b.c2d = bessel_k0e<T>(s) * ii0;
     }
   } else {
     if (s < (T)1) {
@@ -298,14 +306,14 @@ __device__ __forceinline__ Ball<T, DIM> ball_terms(T R, T s, T inv_sigma_bar, bo
       const T s2 = s * s;
       T term = (T)(1.0 / 6.0), acc = term;
       for (int k = 1; k <= (sizeof(T) == 4 ? 4 : 8); ++k) {
-        term *= s2 / (T)((2 * k + 2) * (2 * k + 3));
+        term *= s2 * (T)(1.0 / ((2 * k + 2) * (2 * k + 3)));
         acc += term;
       }
       const T shm = s * s2 * acc;
-      b.pb = shm / (s + shm);
+      b.pb = m_div(shm, s + shm);
     } else {
       // 1 - s/sinh(s) = 1 - 2 s e^{-s} / (1 - e^{-2s})
-      b.pb = (T)1 + (T)2 * s * m_exp(-s) / m_expm1((T)-2 * s);
+      b.pb = (T)1 + m_div((T)2 * s * m_exp(-s), m_expm1((T)-2 * s));
     }
   }
   b.gnorm = b.pb * inv_sigma_bar;
@@ -450,73 +458,67 @@ __device__ __forceinline__ T nf_poisson_area(const NfBall<T, DIM>& b, const T* u
 // never reached for finite s; a non-finite s returns -1 after kMaxTrials proposals.
 constexpr uint32_t kMaxTrials = 256;
 
+// One proposal and its accept/reject test; returns t in (0, 1] on acceptance and -1 on
+// rejection. The walker calls it once per iteration and lane, so a rejected lane retries
+// at the next iteration instead of holding its whole wavefront in a rejection loop.
+template <typename T, int DIM, bool COUNT = false>
+__device__ __forceinline__ T radius_trial(Rng& rng, T s, const Ball<T, DIM>& b, bool harmonic, Tally* tally = nullptr) {
+  if (DIM == 2) {
+    const T u1 = uniform01<T>(rng), u2 = uniform01<T>(rng);
+    if (harmonic) return m_sqrt(u1 * u2);
+    const T u3 = uniform01<T>(rng);
+    if (s < (T)2) {
+      // harmonic proposal t = sqrt(U1 U2), accept with G^s/G^0
+      const T t = m_sqrt(u1 * u2);
+      const T x = t * s;
+      T i0m1, k0;
+      if (x <= (T)1) {
+        bessel_series<T>(x, &i0m1, &k0);
+      } else {
+        bessel_series<T>(x, &i0m1, nullptr);
+        k0 = bessel_k0e<T>(x) * m_exp(-x);
+      }
+      const T g = k0 - b.c2d * ((T)1 + i0m1);
+      return u3 * -m_log(t) <= g ? t : (T)-1;
+    }
+    // free-space proposal u = 2 sqrt(E1 E2), accept with G_ball/G_free on u < s
+    if constexpr (COUNT) ++tally->trials_free;
+    const T u = (T)2 * m_sqrt(m_log(u1) * m_log(u2));
+    if (!(u < s)) return (T)-1;
+    const T r = b.c2d * m_div(bessel_i0e<T>(u), bessel_k0e<T>(u)) * m_exp((T)2 * (u - s));
+    return u3 <= (T)1 - r ? m_div(u, s) : (T)-1;
+  } else {
+    if (harmonic || s < (T)2.449489742783178) {
+      // Beta(2,2) = median of three uniforms
+      const T a = uniform01<T>(rng), c = uniform01<T>(rng), d = uniform01<T>(rng);
+      const T t = fmax(fmin(a, c), fmin(fmax(a, c), d));
+      if (harmonic) return t;
+      const T u4 = uniform01<T>(rng);
+      const T omt = (T)1 - t;
+      // sinh(s(1-t)) / ((1-t) sinh s) = e^{-st} (1 - e^{-2s(1-t)}) / ((1 - e^{-2s}) (1-t))
+      const T acc = omt > (T)0 ? m_div(m_exp(-s * t) * m_expm1((T)-2 * s * omt), m_expm1((T)-2 * s) * omt) : (T)0;
+      return u4 <= acc ? t : (T)-1;
+    }
+    if constexpr (COUNT) ++tally->trials_free;
+    const T u = -m_log(uniform01<T>(rng) * uniform01<T>(rng));
+    const T u3 = uniform01<T>(rng);
+    if (!(u < s)) return (T)-1;
+    // G^s/G^free = 1 - e^{u-s} sinh(u)/sinh(s) = 1 - e^{2(u-s)} (1 - e^{-2u})/(1 - e^{-2s})
+    const T r = m_div(m_exp((T)2 * (u - s)) * m_expm1((T)-2 * u), m_expm1((T)-2 * s));
+    return u3 <= (T)1 - r ? m_div(u, s) : (T)-1;
+  }
+}
+
+// Trials until acceptance (at most kMaxTrials; -1 if none is accepted).
 template <typename T, int DIM, bool COUNT = false>
 __device__ __forceinline__ T sample_radius(Rng& rng, T s, const Ball<T, DIM>& b, bool harmonic, uint32_t& trials,
                                          Tally* tally = nullptr) {
-  uint32_t budget = kMaxTrials;
-  if (DIM == 2) {
-    if (harmonic) {
-      ++trials;
-      return m_sqrt(uniform01<T>(rng) * uniform01<T>(rng));
-    }
-    if (s < (T)2) {
-      while (budget--) {
-        ++trials;
-        const T t = m_sqrt(uniform01<T>(rng) * uniform01<T>(rng));
-        const T u3 = uniform01<T>(rng);
-        const T x = t * s;
-        T i0m1, k0;
-        if (x <= (T)1) {
-          bessel_series<T>(x, &i0m1, &k0);
-        } else {
-          bessel_series<T>(x, &i0m1, nullptr);
-          k0 = bessel_k0e<T>(x) * m_exp(-x);
-        }
-        const T g = k0 - b.c2d * ((T)1 + i0m1);
-        if (u3 * -m_log(t) <= g) return t;
-      }
-      return (T)-1;
-    }
-    while (budget--) {
-      ++trials;
-      if constexpr (COUNT) ++tally->trials_free;
-      const T e1 = -m_log(uniform01<T>(rng));
-      const T e2 = -m_log(uniform01<T>(rng));
-      const T u3 = uniform01<T>(rng);
-      const T u = (T)2 * m_sqrt(e1 * e2);
-      if (u >= s) continue;
-      const T r = b.c2d * bessel_i0e<T>(u) / bessel_k0e<T>(u) * m_exp((T)2 * (u - s));
-      if (u3 <= (T)1 - r) return u / s;
-    }
-    return (T)-1;
-  } else {
-    if (harmonic || s < (T)2.449489742783178) {
-      while (budget--) {
-        ++trials;
-        // Beta(2,2) = median of three uniforms
-        const T a = uniform01<T>(rng), c = uniform01<T>(rng), d = uniform01<T>(rng);
-        const T t = fmax(fmin(a, c), fmin(fmax(a, c), d));
-        if (harmonic) return t;
-        const T u4 = uniform01<T>(rng);
-        const T omt = (T)1 - t;
-        // sinh(s(1-t)) / ((1-t) sinh s) = e^{-st} (1 - e^{-2s(1-t)}) / ((1 - e^{-2s}) (1-t))
-        const T acc = omt > (T)0 ? m_exp(-s * t) * m_expm1((T)-2 * s * omt) / (m_expm1((T)-2 * s) * omt) : (T)0;
-        if (u4 <= acc) return t;
-      }
-      return (T)-1;
-    }
-    while (budget--) {
-      ++trials;
-      if constexpr (COUNT) ++tally->trials_free;
-      const T u = -m_log(uniform01<T>(rng) * uniform01<T>(rng));
-      const T u3 = uniform01<T>(rng);
-      if (u >= s) continue;
-      // G^s/G^free = 1 - e^{u-s} sinh(u)/sinh(s) = 1 - e^{2(u-s)} (1 - e^{-2u})/(1 - e^{-2s})
-      const T r = m_exp((T)2 * (u - s)) * m_expm1((T)-2 * u) / m_expm1((T)-2 * s);
-      if (u3 <= (T)1 - r) return u / s;
-    }
-    return (T)-1;
+  for (uint32_t k = 0; k < kMaxTrials; ++k) {
+    ++trials;
+    const T t = radius_trial<T, DIM, COUNT>(rng, s, b, harmonic, tally);
+    if (t >= (T)0) return t;
   }
+  return (T)-1;
 }
 
 template <typename T, int DIM>
@@ -789,7 +791,7 @@ __device__ __forceinline__ PointCoef<T> point_coef(G<DevProblem<T>>& P, const T*
   T lnal;
   const FV<T, DIM> al = field_transform<T, DIM, true>(P.alpha, base[0], &lnal);
   if (P.alpha.transform != FT_EXP) lnal = m_log(al.v);
-  const T inv_al = (T)1 / al.v;
+  const T inv_al = m_rcp(al.v);
   T gl[DIM], ga2 = 0;
 #pragma unroll
   for (int i = 0; i < DIM; ++i) {
@@ -880,7 +882,7 @@ __device__ __forceinline__ T segment_dist2(const T* x, PT s, T* tpar) {
   const T ex = s[2] - s[0], ey = s[3] - s[1];
   const T px = x[0] - s[0], py = x[1] - s[1];
   const T l2 = m_fma(ex, ex, ey * ey);
-  T t = l2 > (T)0 ? m_fma(px, ex, py * ey) / l2 : (T)0;
+  T t = l2 > (T)0 ? m_div(m_fma(px, ex, py * ey), l2) : (T)0;
   t = fmin(fmax(t, (T)0), (T)1);
   const T dx = px - t * ex, dy = py - t * ey;
   *tpar = t;
@@ -910,7 +912,7 @@ __device__ __forceinline__ void triangle_closest(const T* p, PT tri, T* q) {
   if (d3 >= (T)0 && d4 <= d3) { for (int i = 0; i < 3; ++i) q[i] = a[i] + ab[i]; return; }
   const T vc = d1 * d4 - d3 * d2;
   if (vc <= (T)0 && d1 >= (T)0 && d3 <= (T)0) {
-    const T v = d1 / (d1 - d3);
+    const T v = m_div(d1, d1 - d3);
     for (int i = 0; i < 3; ++i) q[i] = a[i] + v * ab[i];
     return;
   }
@@ -921,17 +923,17 @@ __device__ __forceinline__ void triangle_closest(const T* p, PT tri, T* q) {
   if (d6 >= (T)0 && d5 <= d6) { for (int i = 0; i < 3; ++i) q[i] = a[i] + ac[i]; return; }
   const T vb = d5 * d2 - d1 * d6;
   if (vb <= (T)0 && d2 >= (T)0 && d6 <= (T)0) {
-    const T w = d2 / (d2 - d6);
+    const T w = m_div(d2, d2 - d6);
     for (int i = 0; i < 3; ++i) q[i] = a[i] + w * ac[i];
     return;
   }
   const T va = d3 * d6 - d5 * d4;
   if (va <= (T)0 && (d4 - d3) >= (T)0 && (d5 - d6) >= (T)0) {
-    const T w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+    const T w = m_div(d4 - d3, (d4 - d3) + (d5 - d6));
     for (int i = 0; i < 3; ++i) q[i] = a[i] + ab[i] + w * (ac[i] - ab[i]);
     return;
   }
-  const T denom = (T)1 / (va + vb + vc);
+  const T denom = m_rcp(va + vb + vc);
   const T v = vb * denom, w = vc * denom;
   for (int i = 0; i < 3; ++i) q[i] = a[i] + ab[i] * v + ac[i] * w;
 }

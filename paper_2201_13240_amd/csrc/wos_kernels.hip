@@ -127,6 +127,15 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* 
   // throughput, the ball radius and its 2D kernel constant. Pi holds prod_k T_k.
   T zr[DIM], xc[DIM];
   T nf_T = 0, nf_S = 0, nf_beta = 1, nf_R = 0, nf_c = 0;
+  // delta tracking: the current ball while its radius is being drawn (pending: the last
+  // proposal was rejected and the lane retries at the next iteration)
+  T bR = 0, bs = 0, bv[DIM];
+  Ball<T, DIM> bb;
+  bb.pb = 0;
+  bb.gnorm = 0;
+  bb.c2d = 0;
+  bool pending = false;
+  uint32_t ntry = 0;
 
   for (;;) {
     // ---------------------------------------------------------------- refill idle lanes
@@ -180,6 +189,7 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* 
           A = 0;
           Ac = 0;
           last_prim = -1;
+          pending = false;
           phase = 1;
           if constexpr (COUNT) {
             ++ev[EV_GAMMA];
@@ -312,14 +322,9 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* 
         T q[DIM];
   #pragma unroll
         for (int i = 0; i < DIM; ++i) q[i] = x[i];
-        T gb = 0, R = 0, t = 0;
-        T v[DIM];
-        Ball<T, DIM> b;
-        b.pb = 0;
-        b.gnorm = 0;
-        b.c2d = 0;
+        T gb = 0;
         if (phase == 2) rng.refill();
-        if (phase == 2) {
+        if (phase == 2 && !pending) {
           if constexpr (COUNT) ++ev[EV_STEPS];
           if (nsteps >= a.max_steps) {
             done = true;
@@ -345,27 +350,37 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* 
                 if (!gx_known) ++ev[EV_GAMMA];
               }
             } else {
-              R = d;
-              const bool harmonic = !(P.sigma_bar > (T)0);
-              const T s = R * P.sqrt_sigma_bar;
-              b = ball_terms<T, DIM>(R, s, P.inv_sigma_bar, harmonic);
+              // a new ball: its normalisation and the direction of y; the radius is drawn
+              // below, one proposal per iteration
+              bR = d;
+              bs = d * P.sqrt_sigma_bar;
+              bb = ball_terms<T, DIM>(d, bs, P.inv_sigma_bar, !(P.sigma_bar > (T)0));
               if constexpr (COUNT) {
-                if (s >= (DIM == 2 ? (T)2 : (T)1)) ++ev[EV_BALL_LARGE_S];
+                if (bs >= (DIM == 2 ? (T)2 : (T)1)) ++ev[EV_BALL_LARGE_S];
               }
-              uniform_direction<T, DIM>(rng, v);
-              t = sample_radius<T, DIM, COUNT>(rng, s, b, harmonic, ntrials, &tally);
-              if (t < (T)0) {  // sampler gave up (non-finite s): cut the walk
-                done = true;
-                flag = kFlagCapped;
-              } else {
-  #pragma unroll
-                for (int i = 0; i < DIM; ++i) q[i] = m_fma(t * R, v[i], x[i]);
-                sampled = true;
-              }
+              uniform_direction<T, DIM>(rng, bv);
+              pending = true;
+              ntry = 0;
             }
           }
         }
-        const bool evaluate = !done;
+        if (pending) {
+          ++ntrials;
+          const T t = radius_trial<T, DIM, COUNT>(rng, bs, bb, !(P.sigma_bar > (T)0), &tally);
+          if (t >= (T)0) {
+  #pragma unroll
+            for (int i = 0; i < DIM; ++i) q[i] = m_fma(t * bR, bv[i], x[i]);
+            sampled = true;
+            pending = false;
+          } else if (++ntry >= kMaxTrials) {  // only for a non-finite s: cut the walk
+            done = true;
+            flag = kFlagCapped;
+            pending = false;
+          }
+        }
+        const T R = bR;
+        const Ball<T, DIM>& b = bb;
+        const bool evaluate = phase == 1 || terminal || sampled;
         PointCoef<T> cq;
         cq.gamma = 0;
         cq.sigma_prime = 0;
@@ -378,15 +393,7 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* 
           gx_known = true;
           phase = 2;
         } else if (terminal) {
-          const T term = Pi * m_exp(cq.gamma - gamma0) * gb;
-          if (a.compensated) {
-            const T s2 = A + term;
-            const T bb = s2 - A;
-            Ac += (A - (s2 - bb)) + (term - bb);
-            A = s2;
-          } else {
-            A += term;
-          }
+          add_estimate(A, Ac, Pi * m_exp(cq.gamma - gamma0) * gb, a.compensated);
           done = true;
         } else if (sampled) {
           const T mu = uniform01<T>(rng);
@@ -395,14 +402,7 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* 
           T term = 0;
           if (a.variant == 0) term = b.gnorm * src;
           else if (volume) term = src * P.inv_sigma_bar;
-          if (a.compensated) {
-            const T s2 = A + term;
-            const T bb = s2 - A;
-            Ac += (A - (s2 - bb)) + (term - bb);
-            A = s2;
-          } else {
-            A += term;
-          }
+          add_estimate(A, Ac, term, a.compensated);
           if constexpr (COUNT) ++ev[volume ? EV_VOLUME : EV_EXIT];
           if (volume) {
             // null event: weight (1 - sigma'(y)/sigma_bar) e^{gamma(y) - gamma(x)}, move to y
