@@ -172,11 +172,17 @@ SegmentGrid build_segment_grid(const std::vector<double>& segs, int64_t n, const
       q.within(topo.root, cx, cy, &best, [&](int32_t, double d2) { best = std::min(best, d2); });
       const double r = std::sqrt(best) + 2 * halfdiag + margin;
       const double r2 = r * r;
-      const size_t first = g.prim.size();
+      std::vector<std::pair<double, int32_t>> cand;
       q.within(topo.root, cx, cy, &r2, [&](int32_t s, double d2) {
-        if (d2 <= r2) g.prim.push_back(s);
+        if (d2 <= r2) cand.emplace_back(d2, s);
       });
-      if (g.prim.size() - first > (size_t)max_candidates) g.prim.resize(first);  // empty list: use the BVH
+      if (cand.size() <= (size_t)max_candidates) {   // else an empty list: use the BVH
+        std::sort(cand.begin(), cand.end());
+        for (const auto& c : cand) {
+          g.prim.push_back(c.second);
+          g.dc.push_back(std::sqrt(c.first));
+        }
+      }
       g.start[(int64_t)j * g.nx + i + 1] = (uint32_t)g.prim.size();
     }
   return g;

@@ -36,12 +36,15 @@ struct SegmentGrid {
   double lo[2] = {0, 0};
   double h = 0;
   std::vector<uint32_t> start;   // [nx * ny + 1]
-  std::vector<int32_t> prim;     // candidate segment indices (leaf order)
+  std::vector<int32_t> prim;     // candidate segment indices (leaf order), nearest to the cell centre first
+  std::vector<double> dc;        // distance from the cell centre to each candidate (ascending per cell)
 };
 
 // segs: [n][4] in leaf order; topo/bounds: the BVH over them (child bounds as produced
 // by bvh_child_bounds<double>). target_cells bounds the grid size. A cell with more
-// than max_candidates candidates gets an empty list (its queries use the BVH).
+// than max_candidates candidates gets an empty list (its queries use the BVH). Each list
+// is sorted by distance from the cell centre, so a query at p can stop once
+// dc - |p - centre| exceeds its best distance (triangle inequality).
 SegmentGrid build_segment_grid(const std::vector<double>& segs, int64_t n, const BvhTopology& topo,
                                const std::vector<double>& bounds, int64_t target_cells, double margin,
                                int max_candidates);

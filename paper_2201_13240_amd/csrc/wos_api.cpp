@@ -176,6 +176,7 @@ struct HostGeometry {
   std::vector<double> bounds64;      // node child bounds
   std::vector<float> bounds32;
   SegmentGrid grid;                  // 2D polygons
+  double grid_margin = 0;            // rounding margin of the candidate lists
 };
 
 wos_status build_geometry(const wos_problem_desc& d, HostGeometry& g) {
@@ -285,7 +286,8 @@ wos_status build_geometry(const wos_problem_desc& d, HostGeometry& g) {
     double scale = 0;
     for (double c : g.prims64) scale = std::max(scale, std::fabs(c));
     const int64_t target = std::min<int64_t>(1 << 20, std::max<int64_t>(4096, 64 * n));
-    g.grid = build_segment_grid(g.prims64, n, g.topo, g.bounds64, target, 4e-6 * (scale + 1.0), 32);
+    g.grid_margin = 4e-6 * (scale + 1.0);
+    g.grid = build_segment_grid(g.prims64, n, g.topo, g.bounds64, target, g.grid_margin, 32);
   }
   return WOS_OK;
 }
@@ -394,7 +396,7 @@ size_t layout_problem(Blob& blob, const wos_problem_desc& d, const HostGeometry&
     G.hi[i] = (T)d.geometry.hi[i];
   }
   G.radius = (T)d.geometry.radius;
-  size_t node_off = 0, prim_off = 0, grid_start_off = 0, grid_prim_off = 0, grid_seg_off = 0;
+  size_t node_off = 0, prim_off = 0, grid_start_off = 0, grid_prim_off = 0, grid_seg_off = 0, grid_dc_off = 0;
   if (g.n_prims > 0) {
     G.n_prims = (int32_t)g.n_prims;
     G.n_nodes = (int32_t)(g.topo.child.size() / 2);
@@ -413,6 +415,7 @@ size_t layout_problem(Blob& blob, const wos_problem_desc& d, const HostGeometry&
         G.grid_lo[0] = (T)g.grid.lo[0];
         G.grid_lo[1] = (T)g.grid.lo[1];
         G.grid_inv_h = (T)(1.0 / g.grid.h);
+        G.grid_h = (T)g.grid.h;
         const size_t nc = g.grid.prim.size();
         grid_start_off = blob.alloc(g.grid.start.size() * sizeof(uint32_t));
         std::memcpy(blob.host.data() + grid_start_off, g.grid.start.data(), g.grid.start.size() * sizeof(uint32_t));
@@ -422,6 +425,9 @@ size_t layout_problem(Blob& blob, const wos_problem_desc& d, const HostGeometry&
         T* cs = (T*)(blob.host.data() + grid_seg_off);
         for (size_t k = 0; k < nc; ++k)
           for (int c = 0; c < 4; ++c) cs[4 * k + c] = prims[(size_t)g.grid.prim[k] * 4 + c];
+        grid_dc_off = blob.alloc(std::max<size_t>(nc, 1) * sizeof(T));
+        T* dc = (T*)(blob.host.data() + grid_dc_off);
+        for (size_t k = 0; k < nc; ++k) dc[k] = (T)(g.grid.dc[k] - g.grid_margin);
       }
     } else {
       node_off = blob.alloc(std::max<size_t>(1, G.n_nodes) * sizeof(BvhNode<T, 3>));
@@ -444,6 +450,7 @@ size_t layout_problem(Blob& blob, const wos_problem_desc& d, const HostGeometry&
       ptr_fixups.push_back({gbase + offsetof(DevGeometry<T>, cell_start), grid_start_off});
       ptr_fixups.push_back({gbase + offsetof(DevGeometry<T>, cell_prim), grid_prim_off});
       ptr_fixups.push_back({gbase + offsetof(DevGeometry<T>, cell_segs), grid_seg_off});
+      ptr_fixups.push_back({gbase + offsetof(DevGeometry<T>, cell_dc), grid_dc_off});
     }
   }
   return off_struct;

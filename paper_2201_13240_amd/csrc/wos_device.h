@@ -1127,13 +1127,23 @@ __device__ __forceinline__ T boundary_distance(G<DevGeometry<T>>& g, const T* x,
         const T fx = (x[0] - g.grid_lo[0]) * g.grid_inv_h;
         const T fy = (x[1] - g.grid_lo[1]) * g.grid_inv_h;
         if (fx >= (T)0 && fy >= (T)0 && fx < (T)g.grid_nx && fy < (T)g.grid_ny) {
-          const int c = (int)fy * g.grid_nx + (int)fx;
+          const int ix = (int)fx, iy = (int)fy;
+          const int c = iy * g.grid_nx + ix;
           const uint32_t b = gptr(g.cell_start)[c], e = gptr(g.cell_start)[c + 1];
           if (e > b) {
             const WOS_GLOBAL T* segs = gptr(g.cell_segs);
+            const WOS_GLOBAL T* dc = gptr(g.cell_dc);
+            // |x - centre|: candidates whose centre distance exceeds it by more than the
+            // best distance so far cannot be nearer (the list is sorted by that distance)
+            const T ox = x[0] - m_fma((T)ix + (T)0.5, g.grid_h, g.grid_lo[0]);
+            const T oy = x[1] - m_fma((T)iy + (T)0.5, g.grid_h, g.grid_lo[1]);
+            const T r_pc = m_sqrt(m_fma(ox, ox, oy * oy));
             T best = Consts<T>::kInf;
             uint32_t bk = b;
-            for (uint32_t k = b; k < e; ++k) {
+            uint32_t k = b;
+            for (; k < e; ++k) {
+              const T lim = dc[k] - r_pc;
+              if (lim > (T)0 && lim * lim >= best) break;
               T tp;
               const T d2 = segment_dist2<T>(x, segs + (size_t)k * 4, &tp);
               if (d2 < best) {
@@ -1143,7 +1153,7 @@ __device__ __forceinline__ T boundary_distance(G<DevGeometry<T>>& g, const T* x,
             }
             if constexpr (COUNT) {
               ++tally->cells;
-              tally->prims += e - b;
+              tally->prims += k - b;
             }
             *prim = gptr(g.cell_prim)[bk];
             return m_sqrt(best);

@@ -7,6 +7,13 @@
 #include "wos_device.h"
 #include "wos_launch.h"
 
+#ifndef WOS_WAVES_FP32
+#define WOS_WAVES_FP32 4
+#endif
+#ifndef WOS_WAVES_FP64
+#define WOS_WAVES_FP64 2
+#endif
+
 namespace wos {
 
 // ------------------------------------------------------------------ wave helpers (wave64)
@@ -87,9 +94,8 @@ __device__ __forceinline__ void add_estimate(T& A, T& Ac, T term, int compensate
 // Buffers written by the walker are separate __restrict__ parameters, so loads of the
 // problem tables (read-only, at wave-uniform addresses) can be served by scalar loads.
 template <typename T, int DIM, int GEOM, bool COUNT, bool NF>
-__global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* __restrict__ tile_counter,
-                                                     WalkRecord* __restrict__ records,
-                                                     uint64_t* __restrict__ events_out) {
+__device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restrict__ tile_counter,
+                                            WalkRecord* __restrict__ records, uint64_t* __restrict__ events_out) {
   const uint32_t lane = __lane_id();
   LdsStack<T> lds_stack{nullptr, nullptr, 0};
   if constexpr (GEOM == GK_POLYGON || GEOM == GK_TRIMESH) {
@@ -461,6 +467,23 @@ __global__ void __launch_bounds__(256) walker_kernel(WalkerArgs<T> a, uint32_t* 
   }
 }
 
+// Kernel entry points, one per precision so that each gets its own register budget: the
+// FP32 walker fits 128 VGPRs (4 waves per SIMD) without spills; the FP64 walker needs
+// more than 256 unless asked to fit 256 (2 waves per SIMD).
+template <int DIM, int GEOM, bool COUNT, bool NF>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WOS_WAVES_FP32)))
+walker_kernel_fp32(WalkerArgs<float> a, uint32_t* __restrict__ tile_counter, WalkRecord* __restrict__ records,
+                   uint64_t* __restrict__ events_out) {
+  walker_body<float, DIM, GEOM, COUNT, NF>(a, tile_counter, records, events_out);
+}
+
+template <int DIM, int GEOM, bool COUNT, bool NF>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WOS_WAVES_FP64)))
+walker_kernel_fp64(WalkerArgs<double> a, uint32_t* __restrict__ tile_counter, WalkRecord* __restrict__ records,
+                   uint64_t* __restrict__ events_out) {
+  walker_body<double, DIM, GEOM, COUNT, NF>(a, tile_counter, records, events_out);
+}
+
 // ------------------------------------------------------------------ reduce (fixed order)
 
 __global__ void reduce_kernel(DevItem it, const WalkRecord* __restrict__ records) {
@@ -755,6 +778,21 @@ __global__ void finalize_kernel(const double* sum, const double* sum_sq, const u
 
 static inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+template <typename T, int DIM, int GEOM, bool COUNT, bool NF>
+static const void* walker_entry() {
+  if constexpr (sizeof(T) == 4) return (const void*)&walker_kernel_fp32<DIM, GEOM, COUNT, NF>;
+  else return (const void*)&walker_kernel_fp64<DIM, GEOM, COUNT, NF>;
+}
+
+template <typename T, int DIM, int GEOM, bool COUNT, bool NF>
+static void launch_walker_k(dim3 g, dim3 b, hipStream_t st, const WalkerArgs<T>& a, uint32_t* counter,
+                            WalkRecord* records, uint64_t* events) {
+  if constexpr (sizeof(T) == 4)
+    hipLaunchKernelGGL((walker_kernel_fp32<DIM, GEOM, COUNT, NF>), g, b, 0, st, a, counter, records, events);
+  else
+    hipLaunchKernelGGL((walker_kernel_fp64<DIM, GEOM, COUNT, NF>), g, b, 0, st, a, counter, records, events);
+}
+
 template <typename T, int DIM, int GEOM>
 static hipError_t launch_walker_t(const WalkerLaunch& L, hipStream_t st) {
   WalkerArgs<T> a;
@@ -771,20 +809,13 @@ static hipError_t launch_walker_t(const WalkerLaunch& L, hipStream_t st) {
   a.ww_lo = (T)L.ww_lo;
   a.events = L.events;
   const dim3 g(L.grid), b(L.block);
+  uint64_t* ev = L.events;
   if (L.variant == 2) {
-    if (L.events)
-      hipLaunchKernelGGL((walker_kernel<T, DIM, GEOM, true, true>), g, b, 0, st, a, L.tile_counter, L.records,
-                         L.events);
-    else
-      hipLaunchKernelGGL((walker_kernel<T, DIM, GEOM, false, true>), g, b, 0, st, a, L.tile_counter, L.records,
-                         (uint64_t*)nullptr);
+    if (ev) launch_walker_k<T, DIM, GEOM, true, true>(g, b, st, a, L.tile_counter, L.records, ev);
+    else launch_walker_k<T, DIM, GEOM, false, true>(g, b, st, a, L.tile_counter, L.records, ev);
   } else {
-    if (L.events)
-      hipLaunchKernelGGL((walker_kernel<T, DIM, GEOM, true, false>), g, b, 0, st, a, L.tile_counter, L.records,
-                         L.events);
-    else
-      hipLaunchKernelGGL((walker_kernel<T, DIM, GEOM, false, false>), g, b, 0, st, a, L.tile_counter, L.records,
-                         (uint64_t*)nullptr);
+    if (ev) launch_walker_k<T, DIM, GEOM, true, false>(g, b, st, a, L.tile_counter, L.records, ev);
+    else launch_walker_k<T, DIM, GEOM, false, false>(g, b, st, a, L.tile_counter, L.records, ev);
   }
   return hipGetLastError();
 }
@@ -813,7 +844,7 @@ hipError_t launch_walker(const WalkerLaunch& L, hipStream_t st) {
 
 template <typename T, int DIM, int GEOM>
 static const void* walker_symbol_t(bool nf) {
-  return nf ? (const void*)&walker_kernel<T, DIM, GEOM, false, true> : (const void*)&walker_kernel<T, DIM, GEOM, false, false>;
+  return nf ? walker_entry<T, DIM, GEOM, false, true>() : walker_entry<T, DIM, GEOM, false, false>();
 }
 
 template <typename T>

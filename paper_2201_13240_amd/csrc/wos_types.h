@@ -52,14 +52,17 @@ struct DevGeometry {
   const T* prims;        // polygon: [n][4] (x0, y0, x1, y1); trimesh: [n][12] (a, b, c, padding)
   // 2D polygons: uniform candidate grid (grid_nx = 0: none). Cell (i, j) covers
   // [grid_lo + (i, j) h, grid_lo + (i + 1, j + 1) h]; its candidates are
-  // cell_prim[cell_start[c] .. cell_start[c + 1]) with their segments copied to cell_segs.
+  // cell_prim[cell_start[c] .. cell_start[c + 1]) with their segments copied to cell_segs,
+  // nearest to the cell centre first; cell_dc holds a lower bound of each one's distance
+  // from the centre (the distance minus the rounding margin).
   int32_t grid_nx, grid_ny;
   T grid_lo[2];
   T grid_inv_h;
-  T grid_pad;
+  T grid_h;
   const uint32_t* cell_start;
   const int32_t* cell_prim;
   const T* cell_segs;
+  const T* cell_dc;
 };
 
 // Dense trigonometric table of the 2D Fourier fields: for alpha, psi and sigma (slots
