@@ -362,7 +362,7 @@ size_t layout_problem(Blob& blob, const wos_problem_desc& d, const HostGeometry&
       for (int sidx = 0; sidx < 3; ++sidx) {
         if (!(eligible & (1 << sidx))) continue;
         const wos_field_desc& f = *slots[sidx];
-        double re[kSpecBasis] = {0}, im[kSpecBasis] = {0}, c = 0;
+        double re[kSpecK + 1][kSpecRow] = {}, im[kSpecK + 1][kSpecRow] = {}, c = 0;
         for (int j = 0; j < f.n_terms; ++j) {
           int kx = (int)f.terms[j * 4], ky = (int)f.terms[j * 4 + 1];
           const double a = f.terms[j * 4 + 2], phi = f.terms[j * 4 + 3];
@@ -376,14 +376,14 @@ size_t layout_problem(Blob& blob, const wos_problem_desc& d, const HostGeometry&
             ky = -ky;
             ci = -ci;
           }
-          const int b = kx == 0 ? ky - 1 : 3 + (kx - 1) * (2 * kSpecK + 1) + (ky + kSpecK);
-          re[b] += cr;
-          im[b] += ci;
+          re[kx][ky + kSpecK] += cr;
+          im[kx][ky + kSpecK] += ci;
         }
-        for (int b = 0; b < kSpecBasis; ++b) {
-          P.spec.re[sidx][b] = (T)re[b];
-          P.spec.im[sidx][b] = (T)im[b];
-        }
+        for (int kx = 0; kx <= kSpecK; ++kx)
+          for (int j = 0; j < kSpecRow; ++j) {
+            P.spec.row[kx][sidx][2 * j] = (T)re[kx][j];
+            P.spec.row[kx][sidx][2 * j + 1] = (T)im[kx][j];
+          }
         P.spec.c[sidx] = (T)c;
       }
     }

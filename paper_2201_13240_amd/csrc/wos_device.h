@@ -86,62 +86,84 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
       k.x += 0x9E3779B9u;
       k.y += 0xBB67AE85u;
     }
-    const uint32_t lo0 = 0xD2511F53u * c.x;
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
-    const uint32_t lo1 = 0xCD9E8D57u * c.z;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
-    c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+    // 32 x 32 -> 64-bit products: one v_mad_u64_u32 each instead of a mul_lo / mul_hi pair
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k.x, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k.y, (uint32_t)p0);
   }
   return c;
 }
 
 // Per-walk counter-based stream: key = seed, counter = (block, walk, point, problem).
-// Words come from an 8-word buffer. The walker refills it at the top of every step, in
-// lockstep across the wave (two Philox blocks), so the cipher does not run inside the
-// divergent branches that consume the words; a branch that runs out refills on its own.
-// Words left over at the end of a step are skipped, so the stream of a walk is a fixed
-// function of (seed, walk, point, problem) whatever the schedule.
+// The walker draws the words of one iteration in lockstep across the wave at the top of
+// the iteration (refill<NB>: NB Philox blocks, 4 words each), so the cipher never runs
+// inside the divergent branches that consume them. Every consumer reads its own fixed
+// word slot (a compile-time index), so no lane-varying word position has to be tracked.
+// Words a lane does not consume in an iteration are skipped, which keeps the stream of a
+// walk a fixed function of (seed, walk, point, problem) whatever the schedule.
+constexpr int kMaxRngBlocks = 5;
+
 struct Rng {
   uint2 key;
   uint32_t walk, point, problem;
   uint32_t block;   // next block index
-  uint4 b0, b1;
-  uint32_t pos;     // words of the buffer already used (8 = empty)
+  uint32_t w[4 * kMaxRngBlocks];
 
-  __device__ __forceinline__ void init(uint64_t seed, uint32_t w, uint32_t p, uint32_t prob) {
+  __device__ __forceinline__ void init(uint64_t seed, uint32_t wk, uint32_t p, uint32_t prob) {
     key = make_uint2((uint32_t)seed, (uint32_t)(seed >> 32));
-    walk = w;
+    walk = wk;
     point = p;
     problem = prob;
     block = 0;
-    pos = 8;
   }
+  template <int NB>
   __device__ __forceinline__ void refill() {
-    b0 = philox4x32_10(make_uint4(block, walk, point, problem), key);
-    b1 = philox4x32_10(make_uint4(block + 1, walk, point, problem), key);
-    block += 2;
-    pos = 0;
-  }
-  __device__ __forceinline__ uint32_t next() {
-    if (pos >= 8) refill();
-    const uint4 q = pos < 4 ? b0 : b1;
-    const uint32_t k = pos & 3;
-    const uint32_t v = k == 0 ? q.x : k == 1 ? q.y : k == 2 ? q.z : q.w;
-    ++pos;
-    return v;
+    static_assert(NB >= 1 && NB <= kMaxRngBlocks, "block count");
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const uint4 q = philox4x32_10(make_uint4(block + j, walk, point, problem), key);
+      w[4 * j] = q.x;
+      w[4 * j + 1] = q.y;
+      w[4 * j + 2] = q.z;
+      w[4 * j + 3] = q.w;
+    }
+    block += NB;
   }
 };
 
-// Uniform in (0, 1]: never zero, so logarithms are finite.
-template <typename T> __device__ __forceinline__ T uniform01(Rng& r);
-template <> __device__ __forceinline__ float uniform01<float>(Rng& r) {
-  return (float)((r.next() >> 8) + 1u) * 5.9604644775390625e-8f;  // 2^-24
+// Uniform in (0, 1] from uniform slot S of the current draw: FP32 takes 24 bits of word S,
+// FP64 53 bits of words 2S and 2S + 1. Never zero, so logarithms are finite.
+template <typename T, int S>
+__device__ __forceinline__ T uniform01(const Rng& r) {
+  if constexpr (sizeof(T) == 4) {
+    return (float)((r.w[S] >> 8) + 1u) * 5.9604644775390625e-8f;  // 2^-24
+  } else {
+    const uint64_t a = r.w[2 * S], b = r.w[2 * S + 1];
+    return (double)((((a << 32) | b) >> 11) + 1ull) * 1.1102230246251565404e-16;  // 2^-53
+  }
 }
-template <> __device__ __forceinline__ double uniform01<double>(Rng& r) {
-  const uint64_t a = r.next();
-  const uint64_t b = r.next();
-  return (double)((((a << 32) | b) >> 11) + 1ull) * 1.1102230246251565404e-16;  // 2^-53
-}
+
+// Uniform slots of one iteration of the walker. Delta tracking: ball direction, radius
+// proposal (3 uniforms in 2D, up to 4 in 3D), volume/exit choice, exit direction,
+// roulette. Next flight: roulette on the throughput, exit direction of a new ball, inner
+// point (direction and radius). Blocks: Philox blocks needed per iteration.
+template <typename T, int DIM>
+struct Slots {
+  static constexpr int kDir = 0;
+  static constexpr int kTrial = kDir + DIM - 1;
+  static constexpr int kMu = kTrial + (DIM == 2 ? 3 : 4);
+  static constexpr int kExitDir = kMu + 1;
+  static constexpr int kRoulette = kExitDir + DIM - 1;
+  static constexpr int kCount = kRoulette + 1;
+  static constexpr int kNfRoulette = 0;
+  static constexpr int kNfExitDir = 1;
+  static constexpr int kNfInner = kNfExitDir + DIM - 1;
+  static constexpr int kNfCount = kNfInner + DIM;
+  static constexpr int kWordsPerUniform = sizeof(T) == 4 ? 1 : 2;
+  static constexpr int kBlocks = (kCount * kWordsPerUniform + 3) / 4;
+  static constexpr int kNfBlocks = (kNfCount * kWordsPerUniform + 3) / 4;
+  static_assert(kBlocks <= kMaxRngBlocks && kNfBlocks <= kMaxRngBlocks, "slot layout exceeds the buffer");
+};
 
 // ------------------------------------------------------------------ modified Bessel functions
 
@@ -461,12 +483,13 @@ constexpr uint32_t kMaxTrials = 256;
 // One proposal and its accept/reject test; returns t in (0, 1] on acceptance and -1 on
 // rejection. The walker calls it once per iteration and lane, so a rejected lane retries
 // at the next iteration instead of holding its whole wavefront in a rejection loop.
-template <typename T, int DIM, bool COUNT = false>
-__device__ __forceinline__ T radius_trial(Rng& rng, T s, const Ball<T, DIM>& b, bool harmonic, Tally* tally = nullptr) {
+template <typename T, int DIM, int S, bool COUNT = false>
+__device__ __forceinline__ T radius_trial(const Rng& rng, T s, const Ball<T, DIM>& b, bool harmonic,
+                                        Tally* tally = nullptr) {
   if (DIM == 2) {
-    const T u1 = uniform01<T>(rng), u2 = uniform01<T>(rng);
+    const T u1 = uniform01<T, S>(rng), u2 = uniform01<T, S + 1>(rng);
     if (harmonic) return m_sqrt(u1 * u2);
-    const T u3 = uniform01<T>(rng);
+    const T u3 = uniform01<T, S + 2>(rng);
     if (s < (T)2) {
       // harmonic proposal t = sqrt(U1 U2), accept with G^s/G^0
       const T t = m_sqrt(u1 * u2);
@@ -490,18 +513,18 @@ __device__ __forceinline__ T radius_trial(Rng& rng, T s, const Ball<T, DIM>& b, 
   } else {
     if (harmonic || s < (T)2.449489742783178) {
       // Beta(2,2) = median of three uniforms
-      const T a = uniform01<T>(rng), c = uniform01<T>(rng), d = uniform01<T>(rng);
+      const T a = uniform01<T, S>(rng), c = uniform01<T, S + 1>(rng), d = uniform01<T, S + 2>(rng);
       const T t = fmax(fmin(a, c), fmin(fmax(a, c), d));
       if (harmonic) return t;
-      const T u4 = uniform01<T>(rng);
+      const T u4 = uniform01<T, S + 3>(rng);
       const T omt = (T)1 - t;
       // sinh(s(1-t)) / ((1-t) sinh s) = e^{-st} (1 - e^{-2s(1-t)}) / ((1 - e^{-2s}) (1-t))
       const T acc = omt > (T)0 ? m_div(m_exp(-s * t) * m_expm1((T)-2 * s * omt), m_expm1((T)-2 * s) * omt) : (T)0;
       return u4 <= acc ? t : (T)-1;
     }
     if constexpr (COUNT) ++tally->trials_free;
-    const T u = -m_log(uniform01<T>(rng) * uniform01<T>(rng));
-    const T u3 = uniform01<T>(rng);
+    const T u = -m_log(uniform01<T, S>(rng) * uniform01<T, S + 1>(rng));
+    const T u3 = uniform01<T, S + 2>(rng);
     if (!(u < s)) return (T)-1;
     // G^s/G^free = 1 - e^{u-s} sinh(u)/sinh(s) = 1 - e^{2(u-s)} (1 - e^{-2u})/(1 - e^{-2s})
     const T r = m_div(m_exp((T)2 * (u - s)) * m_expm1((T)-2 * u), m_expm1((T)-2 * s));
@@ -509,29 +532,32 @@ __device__ __forceinline__ T radius_trial(Rng& rng, T s, const Ball<T, DIM>& b, 
   }
 }
 
-// Trials until acceptance (at most kMaxTrials; -1 if none is accepted).
+// Trials until acceptance (at most kMaxTrials; -1 if none is accepted), each on a fresh
+// draw of the stream.
 template <typename T, int DIM, bool COUNT = false>
 __device__ __forceinline__ T sample_radius(Rng& rng, T s, const Ball<T, DIM>& b, bool harmonic, uint32_t& trials,
                                          Tally* tally = nullptr) {
   for (uint32_t k = 0; k < kMaxTrials; ++k) {
     ++trials;
-    const T t = radius_trial<T, DIM, COUNT>(rng, s, b, harmonic, tally);
+    rng.refill<(4 * Slots<T, DIM>::kWordsPerUniform + 3) / 4>();
+    const T t = radius_trial<T, DIM, 0, COUNT>(rng, s, b, harmonic, tally);
     if (t >= (T)0) return t;
   }
   return (T)-1;
 }
 
-template <typename T, int DIM>
-__device__ __forceinline__ void uniform_direction(Rng& rng, T* v) {
+// Uniform direction on the unit sphere from uniform slots S .. S + DIM - 2.
+template <typename T, int DIM, int S>
+__device__ __forceinline__ void uniform_direction(const Rng& rng, T* v) {
   if (DIM == 2) {
     T sn, cs;
-    m_sincospi2(uniform01<T>(rng), &sn, &cs);
+    m_sincospi2(uniform01<T, S>(rng), &sn, &cs);
     v[0] = cs;
     v[1] = sn;
   } else {
-    const T z = (T)1 - (T)2 * uniform01<T>(rng);
+    const T z = (T)1 - (T)2 * uniform01<T, S>(rng);
     T sn, cs;
-    m_sincospi2(uniform01<T>(rng), &sn, &cs);
+    m_sincospi2(uniform01<T, S + 1>(rng), &sn, &cs);
     const T rr = m_sqrt(fmax((T)0, (T)1 - z * z));
     v[0] = rr * cs;
     v[1] = rr * sn;
@@ -540,11 +566,11 @@ __device__ __forceinline__ void uniform_direction(Rng& rng, T* v) {
 }
 
 // Uniform point in the ball of radius R centred at the origin: uniform direction and
-// radius R U^{1/n}.
-template <typename T, int DIM>
-__device__ __forceinline__ void uniform_in_ball(Rng& rng, T R, T* p) {
-  uniform_direction<T, DIM>(rng, p);
-  const T u = uniform01<T>(rng);
+// radius R U^{1/n}, from uniform slots S .. S + DIM - 1.
+template <typename T, int DIM, int S>
+__device__ __forceinline__ void uniform_in_ball(const Rng& rng, T R, T* p) {
+  uniform_direction<T, DIM, S>(rng, p);
+  const T u = uniform01<T, S + DIM - 1>(rng);
   const T r = R * (DIM == 2 ? m_sqrt(u) : m_cbrt(u));
 #pragma unroll
   for (int i = 0; i < DIM; ++i) p[i] *= r;
@@ -653,16 +679,18 @@ __device__ __forceinline__ FV<T, DIM> field_base(G<DevField<T>>& f, const T* x) 
 // calls per point instead of one per mode), all loops unrolled at compile time.
 template <typename T, bool D>
 __device__ __forceinline__ void spectral2d(G<Spectral2D<T>>& sp, const T* x, FV<T, 2>* out) {
-  T cx[kSpecK + 1], sx[kSpecK + 1], cy[kSpecK + 1], sy[kSpecK + 1];
-  cx[0] = 1; sx[0] = 0; cy[0] = 1; sy[0] = 0;
-  m_sincospi2(x[0], &sx[1], &cx[1]);
-  m_sincospi2(x[1], &sy[1], &cy[1]);
+  // e^{2 pi i ky y} for ky = -K .. K from the powers of e^{2 pi i y}
+  T c1, s1, yr[kSpecRow], yi[kSpecRow];
+  m_sincospi2(x[1], &s1, &c1);
+  yr[kSpecK] = 1;
+  yi[kSpecK] = 0;
 #pragma unroll
-  for (int m = 2; m <= kSpecK; ++m) {
-    cx[m] = cx[m - 1] * cx[1] - sx[m - 1] * sx[1];
-    sx[m] = sx[m - 1] * cx[1] + cx[m - 1] * sx[1];
-    cy[m] = cy[m - 1] * cy[1] - sy[m - 1] * sy[1];
-    sy[m] = sy[m - 1] * cy[1] + cy[m - 1] * sy[1];
+  for (int m = 1; m <= kSpecK; ++m) {
+    const T pr = yr[kSpecK + m - 1], pi = yi[kSpecK + m - 1];
+    yr[kSpecK + m] = pr * c1 - pi * s1;
+    yi[kSpecK + m] = m_fma(pi, c1, pr * s1);
+    yr[kSpecK - m] = yr[kSpecK + m];
+    yi[kSpecK - m] = -yi[kSpecK + m];
   }
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
@@ -672,30 +700,37 @@ __device__ __forceinline__ void spectral2d(G<Spectral2D<T>>& sp, const T* x, FV<
     out[s].lap = 0;
   }
   constexpr T kTwoPi = (T)6.283185307179586476925286766559;
-  int b = 0;
-#pragma unroll
+  T cx1, sx1;
+  m_sincospi2(x[0], &sx1, &cx1);
+  T exr = 1, exi = 0;   // e^{2 pi i kx x}
+  // one row of wave vectors per pass: the loop is kept rolled so that only one row of
+  // coefficients (wave-uniform, scalar loads) is live at a time
+#pragma unroll 1
   for (int kx = 0; kx <= kSpecK; ++kx) {
+    const WOS_GLOBAL T* row = &sp.row[kx][0][0];
+    const T fx = kTwoPi * (T)kx;
+    const T fx2 = fx * fx;
 #pragma unroll
-    for (int ky = -kSpecK; ky <= kSpecK; ++ky) {
-      if (kx == 0 && ky <= 0) continue;
-      const int ay = ky < 0 ? -ky : ky;
-      const T yr = cy[ay], yi = ky < 0 ? -sy[ay] : sy[ay];
-      const T er = cx[kx] * yr - sx[kx] * yi;
-      const T ei = cx[kx] * yi + sx[kx] * yr;
+    for (int j = 0; j < kSpecRow; ++j) {
+      const int ky = j - kSpecK;
+      const T er = exr * yr[j] - exi * yi[j];
+      const T ei = m_fma(exr, yi[j], exi * yr[j]);
 #pragma unroll
       for (int s = 0; s < 3; ++s) {
-        const T cr = sp.re[s][b], ci = sp.im[s][b];
+        const T cr = row[s * 2 * kSpecRow + 2 * j], ci = row[s * 2 * kSpecRow + 2 * j + 1];
         const T re = m_fma(cr, er, -ci * ei);
         out[s].v += re;
         if (D && s < 2) {
           const T im = m_fma(cr, ei, ci * er);
-          out[s].g[0] = m_fma(-im, kTwoPi * (T)kx, out[s].g[0]);
+          out[s].g[0] = m_fma(-im, fx, out[s].g[0]);
           out[s].g[1] = m_fma(-im, kTwoPi * (T)ky, out[s].g[1]);
-          out[s].lap = m_fma(-re, kTwoPi * kTwoPi * (T)(kx * kx + ky * ky), out[s].lap);
+          out[s].lap = m_fma(-re, fx2 + kTwoPi * kTwoPi * (T)(ky * ky), out[s].lap);
         }
       }
-      ++b;
     }
+    const T t = exr * cx1 - exi * sx1;
+    exi = m_fma(exr, sx1, exi * cx1);
+    exr = t;
   }
 }
 

@@ -96,6 +96,7 @@ __device__ __forceinline__ void add_estimate(T& A, T& Ac, T term, int compensate
 template <typename T, int DIM, int GEOM, bool COUNT, bool NF>
 __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restrict__ tile_counter,
                                             WalkRecord* __restrict__ records, uint64_t* __restrict__ events_out) {
+  using SL = Slots<T, DIM>;
   const uint32_t lane = __lane_id();
   LdsStack<T> lds_stack{nullptr, nullptr, 0};
   if constexpr (GEOM == GK_POLYGON || GEOM == GK_TRIMESH) {
@@ -233,12 +234,12 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
           q[i] = x[i];
           xn[i] = 0;
         }
-        if (phase >= 2) rng.refill();
+        if (phase >= 2) rng.refill<SL::kNfBlocks>();
         if (phase == 3) {
           const NfBall<T, DIM> nb = nf_ball<T, DIM>(nf_R, P.sqrt_sigma_bar, nf_c);
           nf_T = m_fma(nf_poisson_area<T, DIM>(nb, xc, zr), nf_beta, nf_T);
           const T prr = fmin((T)1, nf_beta);
-          if (uniform01<T>(rng) <= prr) {
+          if (uniform01<T, SL::kNfRoulette>(rng) <= prr) {
             nf_beta /= prr;
             sample = true;
           } else {
@@ -280,7 +281,7 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
               nf_S = 0;
               nf_beta = 1;            // the first inner point is always taken
               T v[DIM];
-              uniform_direction<T, DIM>(rng, v);
+              uniform_direction<T, DIM, SL::kNfExitDir>(rng, v);
 #pragma unroll
               for (int i = 0; i < DIM; ++i) {
                 zr[i] = d * v[i];
@@ -291,7 +292,7 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
           }
         }
         if (sample) {
-          uniform_in_ball<T, DIM>(rng, nf_R, xn);
+          uniform_in_ball<T, DIM, SL::kNfInner>(rng, nf_R, xn);
 #pragma unroll
           for (int i = 0; i < DIM; ++i) q[i] = x[i] + xn[i];
         }
@@ -329,7 +330,7 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
   #pragma unroll
         for (int i = 0; i < DIM; ++i) q[i] = x[i];
         T gb = 0;
-        if (phase == 2) rng.refill();
+        if (phase == 2) rng.refill<SL::kBlocks>();
         if (phase == 2 && !pending) {
           if constexpr (COUNT) ++ev[EV_STEPS];
           if (nsteps >= a.max_steps) {
@@ -364,7 +365,7 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
               if constexpr (COUNT) {
                 if (bs >= (DIM == 2 ? (T)2 : (T)1)) ++ev[EV_BALL_LARGE_S];
               }
-              uniform_direction<T, DIM>(rng, bv);
+              uniform_direction<T, DIM, SL::kDir>(rng, bv);
               pending = true;
               ntry = 0;
             }
@@ -372,7 +373,7 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
         }
         if (pending) {
           ++ntrials;
-          const T t = radius_trial<T, DIM, COUNT>(rng, bs, bb, !(P.sigma_bar > (T)0), &tally);
+          const T t = radius_trial<T, DIM, SL::kTrial, COUNT>(rng, bs, bb, !(P.sigma_bar > (T)0), &tally);
           if (t >= (T)0) {
   #pragma unroll
             for (int i = 0; i < DIM; ++i) q[i] = m_fma(t * bR, bv[i], x[i]);
@@ -402,7 +403,7 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
           add_estimate(A, Ac, Pi * m_exp(cq.gamma - gamma0) * gb, a.compensated);
           done = true;
         } else if (sampled) {
-          const T mu = uniform01<T>(rng);
+          const T mu = uniform01<T, SL::kMu>(rng);
           const bool volume = mu <= b.pb;
           const T src = Pi * m_exp(cq.gamma - gamma0) * cq.f_over_alpha;
           T term = 0;
@@ -420,7 +421,7 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
           } else {
             // boundary term: uniform point on the sphere, weight e^{gamma(z) - gamma(x)}
             T vz[DIM];
-            uniform_direction<T, DIM>(rng, vz);
+            uniform_direction<T, DIM, SL::kExitDir>(rng, vz);
   #pragma unroll
             for (int i = 0; i < DIM; ++i) x[i] = m_fma(R, vz[i], x[i]);
             gx_known = false;
@@ -436,7 +437,7 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
             const T W = Pi * e;
             if (m_fabs(W) < a.ww_lo) {
               if constexpr (COUNT) ++ev[EV_RR_TESTS];
-              const T u = uniform01<T>(rng);
+              const T u = uniform01<T, SL::kRoulette>(rng);
               if (u * a.ww_lo <= m_fabs(W)) {
                 Pi = (W < (T)0 ? -a.ww_lo : a.ww_lo) / e;
               } else {

@@ -71,12 +71,13 @@ struct DevGeometry {
 // that B(x) = const + sum_k Re(C_k e^{2 pi i k.x}). A mode a cos(2 pi k.x + phi) adds
 // a e^{i phi} at k, or a e^{-i phi} at -k when k is in the other half plane.
 constexpr int kSpecK = 3;
-constexpr int kSpecBasis = 24;
+constexpr int kSpecRow = 2 * kSpecK + 1;   // ky = -kSpecK .. kSpecK
 
+// row[kx][slot][2 j], row[kx][slot][2 j + 1]: real and imaginary part of C_k for
+// k = (kx, j - kSpecK); the kx = 0 row only holds ky > 0 (the rest is zero).
 template <typename T>
 struct Spectral2D {
-  T re[3][kSpecBasis];
-  T im[3][kSpecBasis];
+  T row[kSpecK + 1][3][2 * kSpecRow];
   T c[3];
 };
 
