@@ -417,8 +417,18 @@ size_t layout_problem(Blob& blob, const wos_problem_desc& d, const HostGeometry&
         G.grid_inv_h = (T)(1.0 / g.grid.h);
         G.grid_h = (T)g.grid.h;
         const size_t nc = g.grid.prim.size();
-        grid_start_off = blob.alloc(g.grid.start.size() * sizeof(uint32_t));
-        std::memcpy(blob.host.data() + grid_start_off, g.grid.start.data(), g.grid.start.size() * sizeof(uint32_t));
+        const size_t ncell = g.grid.start.size() - 1;
+        grid_start_off = blob.alloc(ncell * sizeof(CellRec<T>));
+        CellRec<T>* cells = (CellRec<T>*)(blob.host.data() + grid_start_off);
+        for (size_t c = 0; c < ncell; ++c) {
+          CellRec<T> r;
+          std::memset(&r, 0, sizeof(r));
+          r.start = g.grid.start[c];
+          r.count = g.grid.start[c + 1] - g.grid.start[c];
+          for (uint32_t k = 0; k < std::min<uint32_t>(r.count, kCellInline); ++k)
+            for (int q = 0; q < 4; ++q) r.seg[k][q] = prims[(size_t)g.grid.prim[r.start + k] * 4 + q];
+          cells[c] = r;
+        }
         grid_prim_off = blob.alloc(std::max<size_t>(nc, 1) * sizeof(int32_t));
         std::memcpy(blob.host.data() + grid_prim_off, g.grid.prim.data(), nc * sizeof(int32_t));
         grid_seg_off = blob.alloc(std::max<size_t>(nc, 1) * 4 * sizeof(T));
@@ -447,7 +457,7 @@ size_t layout_problem(Blob& blob, const wos_problem_desc& d, const HostGeometry&
     ptr_fixups.push_back({gbase + offsetof(DevGeometry<T>, nodes), node_off});
     ptr_fixups.push_back({gbase + offsetof(DevGeometry<T>, prims), prim_off});
     if (g.grid.nx > 0) {
-      ptr_fixups.push_back({gbase + offsetof(DevGeometry<T>, cell_start), grid_start_off});
+      ptr_fixups.push_back({gbase + offsetof(DevGeometry<T>, cells), grid_start_off});
       ptr_fixups.push_back({gbase + offsetof(DevGeometry<T>, cell_prim), grid_prim_off});
       ptr_fixups.push_back({gbase + offsetof(DevGeometry<T>, cell_segs), grid_seg_off});
       ptr_fixups.push_back({gbase + offsetof(DevGeometry<T>, cell_dc), grid_dc_off});

@@ -1130,6 +1130,15 @@ __device__ __forceinline__ T bvh_nearest(G<DevGeometry<T>>& g, const T* x, int* 
   return best;
 }
 
+// A polygon grid query returns its candidate list position tagged with kGridPrimTag
+// instead of the primitive, so no load waits for the primitive index on every step.
+constexpr int kGridPrimTag = 1 << 30;
+
+template <typename T>
+__device__ __forceinline__ int resolve_prim(G<DevGeometry<T>>& g, int prim) {
+  return (prim >= 0 && (prim & kGridPrimTag)) ? gptr(g.cell_prim)[prim & (kGridPrimTag - 1)] : prim;
+}
+
 // Distance d from x to the boundary (Alg. 1, first step); prim receives what
 // closest_point needs to recover xbar.
 template <typename T, int DIM, int GEOM, bool COUNT = false>
@@ -1163,45 +1172,59 @@ __device__ __forceinline__ T boundary_distance(G<DevGeometry<T>>& g, const T* x,
         const T fy = (x[1] - g.grid_lo[1]) * g.grid_inv_h;
         if (fx >= (T)0 && fy >= (T)0 && fx < (T)g.grid_nx && fy < (T)g.grid_ny) {
           const int ix = (int)fx, iy = (int)fy;
-          const int c = iy * g.grid_nx + ix;
-          const uint32_t b = gptr(g.cell_start)[c], e = gptr(g.cell_start)[c + 1];
-          if (e > b) {
-            const WOS_GLOBAL T* segs = gptr(g.cell_segs);
-            const WOS_GLOBAL T* dc = gptr(g.cell_dc);
-            // |x - centre|: candidates whose centre distance exceeds it by more than the
-            // best distance so far cannot be nearer (the list is sorted by that distance)
-            const T ox = x[0] - m_fma((T)ix + (T)0.5, g.grid_h, g.grid_lo[0]);
-            const T oy = x[1] - m_fma((T)iy + (T)0.5, g.grid_h, g.grid_lo[1]);
-            const T r_pc = m_sqrt(m_fma(ox, ox, oy * oy));
+          const WOS_GLOBAL CellRec<T>* rec = (const WOS_GLOBAL CellRec<T>*)g.cells + (iy * g.grid_nx + ix);
+          const uint32_t n = rec->count, st = rec->start;
+          if (n > 0) {
+            // the inline candidates are tested unconditionally (their loads do not wait
+            // for the count; padding entries are ignored)
             T best = Consts<T>::kInf;
-            uint32_t bk = b;
-            uint32_t k = b;
-            for (; k < e; ++k) {
-              const T lim = dc[k] - r_pc;
-              if (lim > (T)0 && lim * lim >= best) break;
+            uint32_t bk = 0;
+#pragma unroll
+            for (int k = 0; k < kCellInline; ++k) {
               T tp;
-              const T d2 = segment_dist2<T>(x, segs + (size_t)k * 4, &tp);
-              if (d2 < best) {
+              const T d2 = segment_dist2<T>(x, rec->seg[k], &tp);
+              if ((uint32_t)k < n && d2 < best) {
                 best = d2;
-                bk = k;
+                bk = (uint32_t)k;
+              }
+            }
+            uint32_t k = kCellInline;
+            if (n > (uint32_t)kCellInline) {
+              // the rest of the list, nearest to the cell centre first: stop once a
+              // candidate's centre distance exceeds |x - centre| + best
+              const WOS_GLOBAL T* segs = gptr(g.cell_segs) + (size_t)st * 4;
+              const WOS_GLOBAL T* dc = gptr(g.cell_dc) + st;
+              const T ox = x[0] - m_fma((T)ix + (T)0.5, g.grid_h, g.grid_lo[0]);
+              const T oy = x[1] - m_fma((T)iy + (T)0.5, g.grid_h, g.grid_lo[1]);
+              const T r_pc = m_sqrt(m_fma(ox, ox, oy * oy));
+              for (; k < n; ++k) {
+                const T lim = dc[k] - r_pc;
+                if (lim > (T)0 && lim * lim >= best) break;
+                T tp;
+                const T d2 = segment_dist2<T>(x, segs + (size_t)k * 4, &tp);
+                if (d2 < best) {
+                  best = d2;
+                  bk = k;
+                }
               }
             }
             if constexpr (COUNT) {
               ++tally->cells;
-              tally->prims += k - b;
+              tally->prims += k < n ? k : n;
             }
-            *prim = gptr(g.cell_prim)[bk];
+            *prim = kGridPrimTag | (int)(st + bk);   // resolved through cell_prim when needed
             return m_sqrt(best);
           }
         }
       }
     }
-    return m_sqrt(bvh_nearest<T, DIM, COUNT>(g, x, prim, tally, lds, hint));
+    return m_sqrt(bvh_nearest<T, DIM, COUNT>(g, x, prim, tally, lds, resolve_prim(g, hint)));
   }
 }
 
 template <typename T, int DIM, int GEOM>
 __device__ __forceinline__ void closest_point(G<DevGeometry<T>>& g, const T* x, int prim, T* xb) {
+  prim = resolve_prim(g, prim);
   if (GEOM == GK_BALL) {
     T e[DIM], r2 = 0;
 #pragma unroll

@@ -29,6 +29,18 @@ struct DevField {
 // Binary BVH node that stores the bounds of both children, so a visit tests both
 // boxes with one load. A child reference c >= 0 is an inner node index; c < 0 encodes
 // a leaf: -1 - c = (first primitive << 3) | count, count in 1..7.
+constexpr int kCellInline = 5;
+
+// One cell of the polygon candidate grid: `count` candidates at cell_prim / cell_segs /
+// cell_dc [start, start + count), the first kCellInline also copied here (zero-padded).
+template <typename T>
+struct __attribute__((aligned(16))) CellRec {
+  uint32_t count;
+  uint32_t start;
+  uint32_t pad[2];
+  T seg[kCellInline][4];
+};
+
 template <typename T, int DIM>
 struct BvhNode {
   T lo[2][DIM];
@@ -55,11 +67,13 @@ struct DevGeometry {
   // cell_prim[cell_start[c] .. cell_start[c + 1]) with their segments copied to cell_segs,
   // nearest to the cell centre first; cell_dc holds a lower bound of each one's distance
   // from the centre (the distance minus the rounding margin).
+  // cells[c] holds the list's length and start and a copy of its first kCellInline
+  // segments, so most queries read one record.
   int32_t grid_nx, grid_ny;
   T grid_lo[2];
   T grid_inv_h;
   T grid_h;
-  const uint32_t* cell_start;
+  const void* cells;     // CellRec<T>[nx * ny]
   const int32_t* cell_prim;
   const T* cell_segs;
   const T* cell_dc;
