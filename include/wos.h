@@ -178,7 +178,11 @@ typedef struct {
   int32_t russian_roulette;   /* low side of the static weight window (Sec. 6) */
   int32_t pad;
   double ww_lo;               /* w-, default 0.5 (Sec. 6) */
-  double ww_hi;               /* w+, reserved (splitting is not implemented) */
+  double ww_hi;               /* w+ > 0: expected-value splitting of walks whose weight
+                                 exceeds it (Sec. 6): N branches of weight W/m, m = |W|/w+,
+                                 E[N] = m; 0: no splitting. Delta tracking only; needs
+                                 problem_index < 2^16 (branch streams use the top half
+                                 of that counter word) and ww_hi > ww_lo with roulette. */
   uint64_t max_steps;         /* distance queries per walk before it is cut (0: 10^6) */
   int32_t block_size;         /* 0: autotuned/default; else 64..1024, multiple of 64 */
   int32_t tile_walks;         /* 0: default; walks per work tile taken by a wavefront */

@@ -50,7 +50,8 @@ class OProblem(C.Structure):
 class OOptions(C.Structure):
     _fields_ = [("sigma_bar", C.c_double), ("seed", C.c_uint64), ("walk_offset", C.c_uint64),
                 ("n_walks", C.c_uint64), ("problem_index", C.c_uint32), ("variant", C.c_int32),
-                ("russian_roulette", C.c_int32), ("ww_lo", C.c_double), ("max_steps", C.c_uint64),
+                ("russian_roulette", C.c_int32), ("ww_lo", C.c_double), ("ww_hi", C.c_double),
+                ("max_steps", C.c_uint64),
                 ("threads", C.c_int32), ("pad", C.c_int32)]
 
 
@@ -253,7 +254,7 @@ def sigma_bar_default(prob, samples):
 
 
 def solve(prob, pts, n_walks, sigma_bar, seed=0, walk_offset=0, problem_index=0, variant=0,
-          russian_roulette=False, ww_lo=0.5, max_steps=10**7, threads=0):
+          russian_roulette=False, ww_lo=0.5, ww_hi=0.0, max_steps=10**7, threads=0):
     """Returns dict(sum, sum_sq, steps, mean, se, counters). variant: 0 Alg. 1, 1 eq. 28,
     2 next flight (Alg. 2), 3 next flight with exact series kernels. counters: invalid points, capped walks, roulette kills, inner
     samples (next flight)."""
@@ -262,7 +263,7 @@ def solve(prob, pts, n_walks, sigma_bar, seed=0, walk_offset=0, problem_index=0,
     n = pts.shape[0]
     o = OOptions(sigma_bar=float(sigma_bar), seed=int(seed), walk_offset=int(walk_offset),
                  n_walks=int(n_walks), problem_index=int(problem_index), variant=int(variant),
-                 russian_roulette=int(bool(russian_roulette)), ww_lo=float(ww_lo),
+                 russian_roulette=int(bool(russian_roulette)), ww_lo=float(ww_lo), ww_hi=float(ww_hi),
                  max_steps=int(max_steps), threads=int(threads))
     s = np.zeros(n)
     q = np.zeros(n)

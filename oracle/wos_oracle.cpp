@@ -23,7 +23,8 @@
 //   * the next-flight walk on spheres (Sec. 5.2, supplemental Alg. 2) with the
 //     off-centred Green's function and Poisson kernel approximations of supplemental
 //     Sec. 1.2 and uniform points inside each ball;
-//   * the low side of the static weight window (Russian roulette, Sec. 6);
+//   * the static weight window of Sec. 6: Russian roulette below w- and expected-value
+//     splitting above w+;
 //   * the per-point Monte Carlo mean (Sec. 3.1, eqs. 17-18).
 //
 // Readings of the paper taken here (where it is silent, ambiguous or garbled):
@@ -169,6 +170,7 @@ struct OOptions {
                           // off-centred kernels, 3: next flight with the exact series kernels
   int32_t russian_roulette;
   double ww_lo;
+  double ww_hi;           // > 0: split walks whose |weight| exceeds it (Sec. 6); 0: no splitting
   uint64_t max_steps;
   int32_t threads;
   int32_t pad;
@@ -585,17 +587,37 @@ struct WalkResult {
   uint64_t inner;   // next flight: points sampled inside balls
 };
 
-WalkResult walk(const OProblem& P, const OOptions& o, const double* x0, Stream* st) {
+// Streams of the branches of a split walk: branch b > 0 draws from the counter
+// (block, walk, point, problem + b 2^16).
+struct Family {
+  uint64_t seed;
+  uint32_t walk, point, problem;
+  uint32_t branches = 0;   // branches started so far
+};
+
+double walk_branch(const OProblem& P, const OOptions& o, const double* x_start, double W, Coef cx, Stream* st,
+                   Family& fam, WalkResult& res);
+
+WalkResult walk(const OProblem& P, const OOptions& o, const double* x0, Stream* st, Family& fam) {
+  WalkResult res = {0, 0, 0, 0, 0};
+  const Coef c0 = coefficients(P, x0);
+  res.value = walk_branch(P, o, x0, 1.0, c0, st, fam, res);
+  return res;
+}
+
+// One branch of a walk: from x with weight W (the product of the per-step factors that
+// multiply the recursive estimate), returns its contribution sum_k W_k (source estimate
+// at ball k) + W_K g(xbar_K). With ww_hi > 0 a branch whose |W| exceeds ww_hi splits into
+// N branches of weight W/m, m = |W|/ww_hi, N = floor(m) with probability floor(m) + 1 - m
+// and floor(m) + 1 otherwise (expected-value splitting, Sec. 6); E[N]/m = 1, so the
+// estimate stays unbiased.
+double walk_branch(const OProblem& P, const OOptions& o, const double* x_start, double W, Coef cx, Stream* st,
+                   Family& fam, WalkResult& res) {
   const int dim = P.dim;
   const double sb = o.sigma_bar;
   double x[3] = {0, 0, 0};
-  for (int i = 0; i < dim; ++i) x[i] = x0[i];
-  Coef cx = coefficients(P, x);
-  // The estimate of u(x0) is sum_k W_k * (source estimate at ball k) + W_K g(xbar_K),
-  // with W the product of the per-step factors that multiply the recursive estimate.
-  double W = 1.0;
+  for (int i = 0; i < dim; ++i) x[i] = x_start[i];
   double A = 0.0;
-  WalkResult res = {0, 0, 0, 0, 0};
   for (;;) {
     if (res.steps >= o.max_steps) {
       res.capped = 1;
@@ -651,10 +673,19 @@ WalkResult walk(const OProblem& P, const OOptions& o, const double* x0, Stream* 
         res.rr_killed = 1;
         break;
       }
+    } else if (o.ww_hi > 0 && std::fabs(W) > o.ww_hi && fam.branches < 65535) {  // high side
+      const double m = std::fabs(W) / o.ww_hi;
+      const double n = std::floor(m);
+      const int N = uniform(st) < n + 1 - m ? (int)n : (int)n + 1;
+      W /= m;
+      for (int c = 1; c < N && fam.branches < 65535; ++c) {
+        Stream child;
+        stream_init(&child, fam.seed, fam.walk, fam.point, fam.problem + ((++fam.branches) << 16));
+        A += walk_branch(P, o, x, W, cx, &child, fam, res);
+      }
     }
   }
-  res.value = A;
-  return res;
+  return A;
 }
 
 // ------------------------------------------------------------------ next flight (Sec. 5.2, Alg. 2)
@@ -993,7 +1024,8 @@ int oracle_solve(const OProblem* P, const OOptions* o, const double* pts, int64_
                  double* sum, double* sum_sq, uint64_t* steps, uint64_t* counters) {
   if (o->sigma_bar < 0) return 1;
   if (o->variant < 0 || o->variant > 3) return 1;
-  if (o->variant >= 2 && o->russian_roulette) return 1;   // next flight has its own roulette
+  if (o->variant >= 2 && (o->russian_roulette || o->ww_hi > 0)) return 1;   // next flight has its own roulette
+  if (o->ww_hi > 0 && (o->problem_index >= 65536 || (o->russian_roulette && !(o->ww_hi > o->ww_lo)))) return 1;
   if (o->variant == 3 && !(o->sigma_bar > 0)) return 1;    // exact kernels need sigma_bar > 0
   std::atomic<int64_t> next(0);
   std::atomic<uint64_t> bad(0), capped(0), killed(0), inner(0);
@@ -1015,7 +1047,12 @@ int oracle_solve(const OProblem* P, const OOptions* o, const double* pts, int64_
       for (uint64_t j = 0; j < o->n_walks; ++j) {
         Stream st;
         stream_init(&st, o->seed, (uint32_t)(o->walk_offset + j), (uint32_t)i, o->problem_index);
-        const WalkResult r = o->variant >= 2 ? walk_next_flight(*P, *o, x0, &st) : walk(*P, *o, x0, &st);
+        Family fam;
+        fam.seed = o->seed;
+        fam.walk = (uint32_t)(o->walk_offset + j);
+        fam.point = (uint32_t)i;
+        fam.problem = o->problem_index;
+        const WalkResult r = o->variant >= 2 ? walk_next_flight(*P, *o, x0, &st) : walk(*P, *o, x0, &st, fam);
         nst += r.steps;
         capped += r.capped;
         killed += r.rr_killed;

@@ -690,6 +690,11 @@ wos_status check_items(const wos_batch_item* items, int n_items, const wos_optio
   if (opt->walks_per_point == 0) return fail(WOS_ERR_INVALID_ARG, "walks_per_point must be > 0");
   if (opt->walk_offset + opt->walks_per_point > (1ull << 32)) return fail(WOS_ERR_INVALID_ARG, "walk indices exceed 32 bits");
   if (opt->russian_roulette && !(opt->ww_lo > 0)) return fail(WOS_ERR_INVALID_ARG, "ww_lo must be > 0");
+  if (opt->ww_hi < 0 || opt->ww_hi != opt->ww_hi) return fail(WOS_ERR_INVALID_ARG, "ww_hi must be >= 0");
+  if (opt->ww_hi > 0 && opt->variant == 2)
+    return fail(WOS_ERR_INVALID_ARG, "weight-window splitting applies to delta tracking (variant 0 or 1)");
+  if (opt->ww_hi > 0 && opt->russian_roulette && !(opt->ww_hi > opt->ww_lo))
+    return fail(WOS_ERR_INVALID_ARG, "ww_hi must exceed ww_lo");
   if (opt->block_size != 0 && (opt->block_size < 64 || opt->block_size > 256 || opt->block_size % 64))
     return fail(WOS_ERR_INVALID_ARG, "block_size must be 64, 128, 192 or 256");
   const wos_problem* p0 = items[0].problem;
@@ -708,6 +713,8 @@ wos_status check_items(const wos_batch_item* items, int n_items, const wos_optio
       return fail(WOS_ERR_UNSUPPORTED, "batch items must share dim, geometry kind and device");
     if (it.n_points < 0) return fail(WOS_ERR_INVALID_ARG, "n_points < 0");
     if (it.n_points >= (1ll << 32)) return fail(WOS_ERR_INVALID_ARG, "n_points must be < 2^32");
+    if (opt->ww_hi > 0 && it.problem_index >= (1u << 16))
+      return fail(WOS_ERR_INVALID_ARG, "problem_index must be < 2^16 with weight-window splitting");
     if (it.n_points > 0 && (!it.points || !it.sum || !it.sum_sq || !it.n_walks || !it.n_steps))
       return fail(WOS_ERR_INVALID_ARG, "null device pointer in batch item");
     s.total_points += (uint64_t)it.n_points;
@@ -915,6 +922,7 @@ WalkerLaunch walker_launch(const wos_options* opt, const Schedule& s, const Work
   L.compensated = s.compensated;
   L.rr = opt->russian_roulette;
   L.ww_lo = opt->ww_lo > 0 ? opt->ww_lo : 0.5;
+  L.ww_hi = opt->ww_hi > 0 ? opt->ww_hi : 0.0;
   L.events = nullptr;
   return L;
 }

@@ -8,7 +8,7 @@
 #include "wos_launch.h"
 
 #ifndef WOS_WAVES_FP32
-#define WOS_WAVES_FP32 4
+#define WOS_WAVES_FP32 5
 #endif
 #ifndef WOS_WAVES_FP64
 #define WOS_WAVES_FP64 2
@@ -62,6 +62,7 @@ struct WalkerArgs {
   int32_t compensated;
   int32_t rr;
   T ww_lo;
+  T ww_hi;               // > 0: expected-value splitting above this weight (delta tracking)
   uint64_t* events;      // event-counting build only: [kEvents]
 };
 
@@ -76,6 +77,19 @@ constexpr uint32_t kFlagRR = 1u << 30;
 constexpr uint32_t kStepMask = (1u << 30) - 1;
 
 __device__ __forceinline__ const void* uniform_ptr(const void* p) { return (const void*)uniform_u64((uint64_t)p); }
+
+// A walk split by the weight window resumes its pending sibling branches from this state.
+constexpr int kSplitDepth = 4;
+constexpr uint32_t kMaxBranches = 65535;   // the branch id fills the top half of a counter word
+
+template <typename T, int DIM>
+struct SplitEntry {
+  T x[DIM];
+  T Pi;
+  T gx;
+  int last_prim;
+  uint32_t remaining;
+};
 
 // A += term, with the rounding error of the addition carried in Ac when compensated
 // (TwoSum: Ac collects (A - (s - b)) + (term - b), b = s - A).
@@ -143,6 +157,13 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
   bb.c2d = 0;
   bool pending = false;
   uint32_t ntry = 0;
+  // weight window, high side: pending sibling branches (private memory, touched only on
+  // splits), branches started by the walk so far, flags of all its branches
+  // (split_state: stack depth in the low 8 bits, branches in the rest; the flags of
+  // finished branches are kept in the top bits of nsteps)
+  SplitEntry<T, DIM> split_stack[kSplitDepth];
+  uint32_t split_state = 0;
+  const bool window = a.rr || a.ww_hi > (T)0;
 
   for (;;) {
     // ---------------------------------------------------------------- refill idle lanes
@@ -197,6 +218,7 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
           Ac = 0;
           last_prim = -1;
           pending = false;
+          split_state = 0;
           phase = 1;
           if constexpr (COUNT) {
             ++ev[EV_GAMMA];
@@ -333,7 +355,7 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
         if (phase == 2) rng.refill<SL::kBlocks>();
         if (phase == 2 && !pending) {
           if constexpr (COUNT) ++ev[EV_STEPS];
-          if (nsteps >= a.max_steps) {
+          if ((nsteps & kStepMask) >= a.max_steps) {
             done = true;
             flag = kFlagCapped;
           } else {
@@ -425,17 +447,18 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
   #pragma unroll
             for (int i = 0; i < DIM; ++i) x[i] = m_fma(R, vz[i], x[i]);
             gx_known = false;
-            if (a.rr) {
+            if (window) {
               gx = point_gamma<T, DIM>(P, x);
               gx_known = true;
               if constexpr (COUNT) ++ev[EV_GAMMA];
             }
           }
-          if (a.rr) {
-            // static weight window, low side (Sec. 6): survive with probability |W|/w-
+          if (window) {
+            // static weight window (Sec. 6) on W = Pi e^{gamma(x) - gamma0}
             const T e = m_exp(gx - gamma0);
             const T W = Pi * e;
-            if (m_fabs(W) < a.ww_lo) {
+            if (a.rr && m_fabs(W) < a.ww_lo) {
+              // low side: survive with probability |W|/w-
               if constexpr (COUNT) ++ev[EV_RR_TESTS];
               const T u = uniform01<T, SL::kRoulette>(rng);
               if (u * a.ww_lo <= m_fabs(W)) {
@@ -444,13 +467,51 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
                 done = true;
                 flag = kFlagRR;
               }
+            } else if (a.ww_hi > (T)0 && m_fabs(W) > a.ww_hi && (split_state >> 8) < kMaxBranches) {
+              // high side: expected-value splitting into N branches of weight W/m,
+              // m = |W|/w+, N = floor(m) with probability floor(m) + 1 - m, else
+              // floor(m) + 1; N - 1 siblings wait on the lane's stack
+              const T m = m_fabs(W) / a.ww_hi;
+              const T fl = floor(m);
+              const uint32_t N = uniform01<T, SL::kRoulette>(rng) <= fl + (T)1 - m ? (uint32_t)fl : (uint32_t)fl + 1u;
+              if (N <= 1u) {
+                Pi /= m;
+              } else if ((split_state & 0xFFu) < (uint32_t)kSplitDepth) {
+                Pi /= m;
+                SplitEntry<T, DIM>& se = split_stack[split_state & 0xFFu];
+                ++split_state;
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) se.x[i] = x[i];
+                se.Pi = Pi;
+                se.gx = gx;
+                se.last_prim = last_prim;
+                se.remaining = N - 1u;
+              }
+              // a full stack leaves the walk unsplit (still unbiased)
             }
           }
         }
         if (done) {
-          records[wid] = WalkRecord{(double)A + (double)Ac, (nsteps & kStepMask) | flag, ntrials};
-          if constexpr (COUNT) ev[EV_TRIALS] += ntrials;
-          phase = 0;
+          nsteps |= flag;
+          if (split_state & 0xFFu) {
+            // the walk goes on as the next sibling branch of the latest split, from the
+            // split's state, with a stream of its own
+            SplitEntry<T, DIM>& se = split_stack[(split_state & 0xFFu) - 1u];
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) x[i] = se.x[i];
+            Pi = se.Pi;
+            gx = se.gx;
+            gx_known = true;
+            last_prim = se.last_prim;
+            if (--se.remaining == 0u) --split_state;
+            split_state += 1u << 8;
+            rng.init(seed, rng.walk, rng.point, (rng.problem & 0xFFFFu) | ((split_state >> 8) << 16));
+            pending = false;
+          } else {
+            records[wid] = WalkRecord{(double)A + (double)Ac, nsteps, ntrials};
+            if constexpr (COUNT) ev[EV_TRIALS] += ntrials;
+            phase = 0;
+          }
         }
       }
     }
@@ -469,8 +530,8 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
 }
 
 // Kernel entry points, one per precision so that each gets its own register budget: the
-// FP32 walker fits 128 VGPRs (4 waves per SIMD) without spills; the FP64 walker needs
-// more than 256 unless asked to fit 256 (2 waves per SIMD).
+// FP32 walker fits 96 VGPRs (5 waves per SIMD); the FP64 walker needs more than 256
+// unless asked to fit 256 (2 waves per SIMD).
 template <int DIM, int GEOM, bool COUNT, bool NF>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WOS_WAVES_FP32)))
 walker_kernel_fp32(WalkerArgs<float> a, uint32_t* __restrict__ tile_counter, WalkRecord* __restrict__ records,
@@ -808,6 +869,7 @@ static hipError_t launch_walker_t(const WalkerLaunch& L, hipStream_t st) {
   a.compensated = L.compensated;
   a.rr = L.rr;
   a.ww_lo = (T)L.ww_lo;
+  a.ww_hi = (T)L.ww_hi;
   a.events = L.events;
   const dim3 g(L.grid), b(L.block);
   uint64_t* ev = L.events;

@@ -25,6 +25,7 @@ struct WalkerLaunch {
   int compensated;
   int rr;
   double ww_lo;
+  double ww_hi;       // 0: no splitting
   uint64_t* events;   // non-null selects the event-counting build of the walker
 };
 

@@ -248,7 +248,7 @@ VARIANTS = {"alg1": 0, "eq28": 1, "next_flight": 2}
 
 
 def options(precision="fp32", walks=128, seed=0, walk_offset=0, variant=0, russian_roulette=False, ww_lo=0.5,
-            max_steps=0, block_size=0, tile_walks=0, workspace_bytes=0):
+            ww_hi=0.0, max_steps=0, block_size=0, tile_walks=0, workspace_bytes=0):
     o = Options()
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
@@ -257,7 +257,7 @@ def options(precision="fp32", walks=128, seed=0, walk_offset=0, variant=0, russi
     o.walk_offset = walk_offset
     o.russian_roulette = int(bool(russian_roulette))
     o.ww_lo = ww_lo
-    o.ww_hi = 1.5
+    o.ww_hi = ww_hi
     o.max_steps = max_steps
     o.block_size = block_size
     o.tile_walks = tile_walks

@@ -83,3 +83,9 @@ def test_solve_rejects_bad_batches_without_device(W):
     items = (W.BatchItem * 1)()
     assert W.lib().wos_solve(items, 1, C.byref(o), None) == 1   # null problem / zero walks
     assert W.lib().wos_last_error()
+    # weight-window options are checked before any problem is touched
+    for kw in ({"ww_hi": -1.0}, {"ww_hi": 1.5, "variant": 2}, {"ww_hi": 0.4, "russian_roulette": True, "ww_lo": 0.5},
+               {"variant": 2, "russian_roulette": True}, {"variant": 3}):
+        o = W.options(walks=16, **kw)
+        assert W.lib().wos_solve(items, 1, C.byref(o), None) == 1, kw
+        assert W.lib().wos_last_error()

@@ -277,3 +277,34 @@ def test_autotuned_plan_and_timed_run_match_fixed_shapes(W):
         assert np.array_equal(a.sum_sq.cpu().numpy(), ref.sum_sq.cpu().numpy())
         assert np.array_equal(a.n_steps.cpu().numpy(), ref.n_steps.cpu().numpy())
         assert np.all(a.n_walks.cpu().numpy() == walks)
+
+
+def test_weight_window_splitting(W, oracle):
+    """Static weight window [0.5, 1.5] with expected-value splitting above w+ (Sec. 6) on
+    the manufactured disk: parity with the oracle's split walks, agreement with
+    u = e^x cos y, more distance queries and a smaller spread than roulette alone, and
+    bit-identical sums across launch shapes (branches are walked depth-first by the lane
+    that split, each with a stream of its own)."""
+    torch = torch_cuda()
+    c = WL.config1(n_grid=16)
+    prob, pts = c["problems"][0], c["points"][0]
+    h = W.Problem(prob, sigma_bar_grid=512)
+    kw = dict(russian_roulette=True, ww_lo=0.5, ww_hi=1.5)
+    o = oracle.solve(prob, pts, 1024, h.sigma_bar, seed=41, **kw)
+    for precision in ("fp64", "fp32"):
+        r = gpu_solve(W, h, pts, 1024, precision, seed=42, **kw)
+        assert_parity(r["mean"], r["se"], o["mean"], o["se"], f"weight window {precision}", tol(precision))
+    inner = away_from_boundary(oracle, prob, pts)
+    r2 = gpu_solve(W, h, inner, 4096, "fp32", seed=43, **kw)
+    assert_parity(r2["mean"], r2["se"], u_expcos(inner), 0 * inner[:, 0], "weight window vs exact", tol("fp32"))
+    r_rr = gpu_solve(W, h, inner, 4096, "fp32", seed=43, russian_roulette=True, ww_lo=0.5)
+    assert r2["steps"].sum() > 1.05 * r_rr["steps"].sum()
+    assert np.mean(r2["se"]) < 0.95 * np.mean(r_rr["se"])
+    P = dev(inner)
+    sums = []
+    for shape in ({"block_size": 64, "tile_walks": 64}, {"block_size": 256, "tile_walks": 1024}):
+        acc = W.Accumulators(P.shape[0])
+        W.solve([(h, P, acc, 0)], W.options(precision="fp32", walks=512, seed=44, **kw, **shape))
+        torch.cuda.synchronize()
+        sums.append(acc.sum.cpu().numpy())
+    assert np.array_equal(sums[0], sums[1])

@@ -198,3 +198,22 @@ def test_invalid_point_and_step_cap(oracle):
     assert np.isnan(r["sum"][1]) and r["counters"][0] == 1
     r = oracle.solve(prob, pts[:1], 50, 0.0, seed=0, max_steps=2)
     assert r["counters"][1] > 0
+
+
+def test_weight_window_splitting_is_unbiased_and_reduces_variance(oracle):
+    """Sec. 6: walks whose weight exceeds w+ split into N branches of weight W/m with
+    E[N] = m. On the manufactured disk (sigma' in [-12.5, 41.5] with sigma_bar = 54, so
+    null-collision factors reach 1.23 and weights cross 1.5) the window [0.5, 1.5] still
+    reproduces u = e^x cos y, splits happen (more distance queries per walk than roulette
+    alone), and the per-walk spread falls."""
+    c = W.config1(n_grid=8)
+    prob, pts = c["problems"][0], c["points"][0]
+    ex = np.exp(pts[:, 0]) * np.cos(pts[:, 1])
+    rr = oracle.solve(prob, pts, 3000, 53.97, seed=3, russian_roulette=True, ww_lo=0.5)
+    ww = oracle.solve(prob, pts, 3000, 53.97, seed=3, russian_roulette=True, ww_lo=0.5, ww_hi=1.5)
+    z = zscores(ww, ex)
+    assert np.max(np.abs(z)) < 4.5 and abs(np.mean(z)) < 0.5, z
+    assert ww["steps"].sum() > 1.05 * rr["steps"].sum()
+    assert np.mean(ww["se"]) < 0.95 * np.mean(rr["se"])
+    with pytest.raises(ValueError):   # w+ must lie above w-
+        oracle.solve(prob, pts[:2], 8, 53.97, russian_roulette=True, ww_lo=0.5, ww_hi=0.4)
