@@ -79,6 +79,7 @@ def lib():
         L.oracle_ball_pb.argtypes = [C.c_int, C.c_double]
         L.oracle_radial_cdf_many.argtypes = [C.c_int, C.c_double, dp, C.c_int64, dp]
         L.oracle_nf_kernel.argtypes = [C.c_int, C.c_int, dp, dp, C.c_int64, C.c_double, C.c_double, dp]
+        L.oracle_grad_ratio.argtypes = [C.c_int, C.c_int, dp, C.c_double, C.c_double, dp]
         L.oracle_ball_gnorm.argtypes = [C.c_int, C.c_double, C.c_double]
         L.oracle_ball_gnorm.restype = C.c_double
         L.oracle_bessel.argtypes = [C.c_int, C.c_double]
@@ -89,6 +90,9 @@ def lib():
         L.oracle_solve.argtypes = [C.POINTER(OProblem), C.POINTER(OOptions), dp, C.c_int64, dp, dp,
                                    C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
         L.oracle_solve.restype = C.c_int
+        L.oracle_solve_grad.argtypes = [C.POINTER(OProblem), C.POINTER(OOptions), dp, C.c_int64, dp, dp,
+                                        C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), dp, dp]
+        L.oracle_solve_grad.restype = C.c_int
         _lib = L
     return _lib
 
@@ -197,6 +201,14 @@ def nf_kernel(which, dim, u, v, R, sigma_bar):
     return out
 
 
+def grad_ratio(which, dim, w, R, sigma_bar):
+    """grad_x G/G ('green', w = y - x) or grad_x P/P ('poisson', w = z - x) at the centre."""
+    w = np.ascontiguousarray(w, np.float64)
+    out = np.zeros(dim)
+    lib().oracle_grad_ratio({"green": 0, "poisson": 1}[which], dim, _dptr(w), R, sigma_bar, _dptr(out))
+    return out
+
+
 def radial_cdf(dim, s, t):
     return lib().oracle_radial_cdf(dim, s, t)
 
@@ -254,7 +266,7 @@ def sigma_bar_default(prob, samples):
 
 
 def solve(prob, pts, n_walks, sigma_bar, seed=0, walk_offset=0, problem_index=0, variant=0,
-          russian_roulette=False, ww_lo=0.5, ww_hi=0.0, max_steps=10**7, threads=0):
+          russian_roulette=False, ww_lo=0.5, ww_hi=0.0, max_steps=10**7, threads=0, gradient=False):
     """Returns dict(sum, sum_sq, steps, mean, se, counters). variant: 0 Alg. 1, 1 eq. 28,
     2 next flight (Alg. 2), 3 next flight with exact series kernels. counters: invalid points, capped walks, roulette kills, inner
     samples (next flight)."""
@@ -269,13 +281,24 @@ def solve(prob, pts, n_walks, sigma_bar, seed=0, walk_offset=0, problem_index=0,
     q = np.zeros(n)
     st = np.zeros(n, np.uint64)
     cnt = np.zeros(4, np.uint64)
-    rc = lib().oracle_solve(C.byref(P.c), C.byref(o), _dptr(pts), n, _dptr(s), _dptr(q),
-                            st.ctypes.data_as(C.POINTER(C.c_uint64)),
-                            cnt.ctypes.data_as(C.POINTER(C.c_uint64)))
+    dim = pts.shape[1]
+    gs = np.zeros((n, dim)) if gradient else None
+    gq = np.zeros((n, dim)) if gradient else None
+    rc = lib().oracle_solve_grad(C.byref(P.c), C.byref(o), _dptr(pts), n, _dptr(s), _dptr(q),
+                                 st.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                 cnt.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                 _dptr(gs) if gradient else None, _dptr(gq) if gradient else None)
     if rc != 0:
         raise ValueError("oracle_solve rejected its arguments")
     N = float(n_walks)
-    mean = s / N
-    var = np.maximum(q / N - mean * mean, 0.0) * N / max(N - 1.0, 1.0)
-    return {"sum": s, "sum_sq": q, "steps": st, "mean": mean, "se": np.sqrt(var / N),
-            "counters": cnt, "n_walks": n_walks}
+
+    def stats(sm, sq):
+        mean = sm / N
+        var = np.maximum(sq / N - mean * mean, 0.0) * N / max(N - 1.0, 1.0)
+        return mean, np.sqrt(var / N)
+
+    mean, se = stats(s, q)
+    out = {"sum": s, "sum_sq": q, "steps": st, "mean": mean, "se": se, "counters": cnt, "n_walks": n_walks}
+    if gradient:
+        out["grad_mean"], out["grad_se"] = stats(gs, gq)
+    return out

@@ -299,6 +299,7 @@ struct Coef {
   double sigma_prime;  // sigma/alpha + Lap gamma + |grad gamma|^2
   double f;            // source of eq. 1
   double f_prime;      // e^gamma f / alpha
+  double grad_gamma[3];
 };
 
 double source_value(const OProblem& P, const double* x, const FVal& al, const FVal& ps, double sg) {
@@ -351,6 +352,7 @@ Coef coefficients(const OProblem& P, const double* x) {
   c.sigma_prime = sg / al.v + lap_gamma + dot(grad_gamma, grad_gamma, 3);
   c.f = source_value(P, x, al, ps, sg);
   c.f_prime = std::exp(c.gamma) * c.f / al.v;
+  for (int i = 0; i < 3; ++i) c.grad_gamma[i] = grad_gamma[i];
   return c;
 }
 
@@ -587,6 +589,56 @@ struct WalkResult {
   uint64_t inner;   // next flight: points sampled inside balls
 };
 
+// ------------------------------------------------------------------ gradient (supp. Sec. 2)
+//
+// grad_x G(x, y) and grad_x P(x, z) at the centre x of the ball (supplemental Sec. 1.3),
+// as ratios to G(x, y) and P(x, z): the walk samples y ~ G/|G| and z uniform on the
+// sphere, so these ratios are what multiplies the sampled terms. w = y - x or z - x.
+void grad_ratio_green(int dim, const double* w, double R, double sb, double* out) {
+  double r2 = 0;
+  for (int i = 0; i < dim; ++i) r2 += w[i] * w[i];
+  const double r = std::sqrt(r2);
+  double f;
+  if (!(sb > 0)) {
+    f = dim == 2 ? (1 / r2 - 1 / (R * R)) / std::log(R / r) : (1 / (r2 * r) - 1 / (R * R * R)) / (1 / r - 1 / R);
+  } else {
+    const double k = std::sqrt(sb), s = R * k, a = r * k;
+    if (dim == 2) {
+      const double num = k / r * (K1(a) - K1(s) / I1(s) * I1(a));
+      const double den = K0(a) - K0(s) / I0(s) * I0(a);
+      f = num / den;
+    } else {
+      const double num = k / r2 * (std::exp(-a) * (1 + 1 / a) - (std::cosh(a) - std::sinh(a) / a) *
+                                                                  std::exp(-s) * (1 + 1 / s) / (std::cosh(s) - std::sinh(s) / s));
+      const double den = std::exp(-a) / r - std::exp(-s) / R * (std::sinh(a) / a) * (s / std::sinh(s));
+      f = num / den;
+    }
+  }
+  for (int i = 0; i < dim; ++i) out[i] = f * w[i];
+}
+
+void grad_ratio_poisson(int dim, const double* w, double R, double sb, double* out) {
+  double f;
+  if (!(sb > 0)) {
+    f = (dim == 2 ? 2.0 : 3.0) / (R * R);
+  } else {
+    const double s = R * std::sqrt(sb);
+    f = dim == 2 ? sb * I0(s) / (s * I1(s)) : sb * std::sinh(s) / (s * std::cosh(s) - std::sinh(s));
+  }
+  for (int i = 0; i < dim; ++i) out[i] = f * w[i];
+}
+
+// What the first ball of a walk leaves for the gradient estimate. With U = e^gamma u,
+// U(x0) = S0 + w1 U(x1) for the first ball (source term S0, first step factor w1), and
+// grad U(x0) has the same two terms with G replaced by grad_x G (and P by grad_x P on an
+// exit): grad U ~ S0 a + (U - S0) b with a = grad G/G at y, b = a (volume) or grad P/P at
+// z (exit). In u and relative to gamma(x0): grad u(x0) ~ A0 a + (A - A0) b - A grad gamma(x0).
+struct FirstBall {
+  bool set = false;
+  double A0 = 0;
+  double a[3] = {0, 0, 0}, b[3] = {0, 0, 0};
+};
+
 // Streams of the branches of a split walk: branch b > 0 draws from the counter
 // (block, walk, point, problem + b 2^16).
 struct Family {
@@ -596,12 +648,13 @@ struct Family {
 };
 
 double walk_branch(const OProblem& P, const OOptions& o, const double* x_start, double W, Coef cx, Stream* st,
-                   Family& fam, WalkResult& res);
+                   Family& fam, WalkResult& res, FirstBall* first);
 
-WalkResult walk(const OProblem& P, const OOptions& o, const double* x0, Stream* st, Family& fam) {
+WalkResult walk(const OProblem& P, const OOptions& o, const double* x0, Stream* st, Family& fam,
+                FirstBall* first = nullptr) {
   WalkResult res = {0, 0, 0, 0, 0};
   const Coef c0 = coefficients(P, x0);
-  res.value = walk_branch(P, o, x0, 1.0, c0, st, fam, res);
+  res.value = walk_branch(P, o, x0, 1.0, c0, st, fam, res, first);
   return res;
 }
 
@@ -612,7 +665,7 @@ WalkResult walk(const OProblem& P, const OOptions& o, const double* x0, Stream* 
 // and floor(m) + 1 otherwise (expected-value splitting, Sec. 6); E[N]/m = 1, so the
 // estimate stays unbiased.
 double walk_branch(const OProblem& P, const OOptions& o, const double* x_start, double W, Coef cx, Stream* st,
-                   Family& fam, WalkResult& res) {
+                   Family& fam, WalkResult& res, FirstBall* first) {
   const int dim = P.dim;
   const double sb = o.sigma_bar;
   double x[3] = {0, 0, 0};
@@ -644,10 +697,19 @@ double walk_branch(const OProblem& P, const OOptions& o, const double* x_start, 
     const double mu = uniform(st);
     const bool volume = mu < pb;
     // source estimate |G| f'(y) / (e^gamma(x)) = |G| e^{gamma(y)-gamma(x)} f(y)/alpha(y)
+    const double A_before = A;
     if (o.variant == 0) {
       A += W * gnorm * std::exp(cy.gamma - cx.gamma) * cy.f / cy.alpha;
     } else if (volume) {
       A += W * std::exp(cy.gamma - cx.gamma) * cy.f / (cy.alpha * sb);
+    }
+    if (first && !first->set) {
+      double w[3] = {0, 0, 0};
+      for (int i = 0; i < dim; ++i) w[i] = y[i] - x[i];
+      first->set = true;
+      first->A0 = A - A_before;
+      grad_ratio_green(dim, w, R, sb, first->a);
+      for (int i = 0; i < 3; ++i) first->b[i] = first->a[i];
     }
     if (volume) {
       // null event: weight (1 - sigma'(y)/sigma_bar) e^{gamma(y) - gamma(x)}, continue at y
@@ -660,6 +722,11 @@ double walk_branch(const OProblem& P, const OOptions& o, const double* x_start, 
       uniform_direction(st, dim, vz);
       double z[3] = {0, 0, 0};
       for (int i = 0; i < dim; ++i) z[i] = x[i] + R * vz[i];
+      if (first && res.steps == 1) {
+        double w[3] = {0, 0, 0};
+        for (int i = 0; i < dim; ++i) w[i] = R * vz[i];
+        grad_ratio_poisson(dim, w, R, sb, first->b);
+      }
       const Coef cz = coefficients(P, z);
       W *= std::exp(cz.gamma - cx.gamma);
       for (int i = 0; i < dim; ++i) x[i] = z[i];
@@ -681,7 +748,7 @@ double walk_branch(const OProblem& P, const OOptions& o, const double* x_start, 
       for (int c = 1; c < N && fam.branches < 65535; ++c) {
         Stream child;
         stream_init(&child, fam.seed, fam.walk, fam.point, fam.problem + ((++fam.branches) << 16));
-        A += walk_branch(P, o, x, W, cx, &child, fam, res);
+        A += walk_branch(P, o, x, W, cx, &child, fam, res, nullptr);
       }
     }
   }
@@ -967,6 +1034,13 @@ void oracle_nf_kernel(int which, int dim, const double* u, const double* v, int6
                           : nf_poisson_exact(dim, u + i * dim, v + i * dim, R, sigma_bar);
 }
 
+// grad_x G(x, y)/G(x, y) (which = 0) or grad_x P(x, z)/P(x, z) (which = 1) at the centre
+// x of the ball of radius R; w = y - x or z - x, out: [dim].
+void oracle_grad_ratio(int which, int dim, const double* w, double R, double sigma_bar, double* out) {
+  if (which == 0) grad_ratio_green(dim, w, R, sigma_bar, out);
+  else grad_ratio_poisson(dim, w, R, sigma_bar, out);
+}
+
 double oracle_ball_pb(int dim, double s) { return ball_pb(dim, s); }
 double oracle_ball_gnorm(int dim, double R, double sigma_bar) { return ball_gnorm(dim, R, sigma_bar); }
 double oracle_radial_cdf(int dim, double s, double t) { return radial_cdf(dim, s, t); }
@@ -1020,8 +1094,20 @@ void oracle_sigma_prime_range(const OProblem* P, const double* pts, int64_t n, d
 // Outputs (per point): sum of estimates, sum of squares, total distance queries.
 // counters: [0] invalid points, [1] capped walks, [2] Russian-roulette kills,
 // [3] next flight: points sampled inside balls.
+int oracle_solve_grad(const OProblem* P, const OOptions* o, const double* pts, int64_t n_points, double* sum,
+                      double* sum_sq, uint64_t* steps, uint64_t* counters, double* gsum, double* gsum_sq);
+
 int oracle_solve(const OProblem* P, const OOptions* o, const double* pts, int64_t n_points,
                  double* sum, double* sum_sq, uint64_t* steps, uint64_t* counters) {
+  return oracle_solve_grad(P, o, pts, n_points, sum, sum_sq, steps, counters, nullptr, nullptr);
+}
+
+// As oracle_solve, and with gsum / gsum_sq (both [n][dim], or null) the sums of the
+// per-walk gradient estimates and of their squares (supplemental Sec. 2; delta tracking
+// only).
+int oracle_solve_grad(const OProblem* P, const OOptions* o, const double* pts, int64_t n_points, double* sum,
+                      double* sum_sq, uint64_t* steps, uint64_t* counters, double* gsum, double* gsum_sq) {
+  if (gsum && o->variant >= 2) return 1;
   if (o->sigma_bar < 0) return 1;
   if (o->variant < 0 || o->variant > 3) return 1;
   if (o->variant >= 2 && (o->russian_roulette || o->ww_hi > 0)) return 1;   // next flight has its own roulette
@@ -1043,6 +1129,9 @@ int oracle_solve(const OProblem* P, const OOptions* o, const double* pts, int64_
       }
       // Neumaier-compensated sums
       double s = 0, cs = 0, q = 0, cq = 0;
+      double gs[3] = {0, 0, 0}, gq[3] = {0, 0, 0};
+      const int dim = P->dim;
+      const Coef c0 = coefficients(*P, x0);
       uint64_t nst = 0;
       for (uint64_t j = 0; j < o->n_walks; ++j) {
         Stream st;
@@ -1052,7 +1141,16 @@ int oracle_solve(const OProblem* P, const OOptions* o, const double* pts, int64_
         fam.walk = (uint32_t)(o->walk_offset + j);
         fam.point = (uint32_t)i;
         fam.problem = o->problem_index;
-        const WalkResult r = o->variant >= 2 ? walk_next_flight(*P, *o, x0, &st) : walk(*P, *o, x0, &st, fam);
+        FirstBall fb;
+        const WalkResult r = o->variant >= 2 ? walk_next_flight(*P, *o, x0, &st)
+                                             : walk(*P, *o, x0, &st, fam, gsum ? &fb : nullptr);
+        if (gsum) {
+          for (int k = 0; k < dim; ++k) {
+            const double g = fb.A0 * fb.a[k] + (r.value - fb.A0) * fb.b[k] - r.value * c0.grad_gamma[k];
+            gs[k] += g;
+            gq[k] += g * g;
+          }
+        }
         nst += r.steps;
         capped += r.capped;
         killed += r.rr_killed;
@@ -1068,6 +1166,11 @@ int oracle_solve(const OProblem* P, const OOptions* o, const double* pts, int64_
       sum[i] = s + cs;
       sum_sq[i] = q + cq;
       steps[i] = nst;
+      if (gsum)
+        for (int k = 0; k < dim; ++k) {
+          gsum[i * dim + k] = gs[k];
+          gsum_sq[i * dim + k] = gq[k];
+        }
     }
   };
   int nt = o->threads > 0 ? o->threads : (int)std::thread::hardware_concurrency();

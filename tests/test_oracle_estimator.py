@@ -217,3 +217,33 @@ def test_weight_window_splitting_is_unbiased_and_reduces_variance(oracle):
     assert np.mean(ww["se"]) < 0.95 * np.mean(rr["se"])
     with pytest.raises(ValueError):   # w+ must lie above w-
         oracle.solve(prob, pts[:2], 8, 53.97, russian_roulette=True, ww_lo=0.5, ww_hi=0.4)
+
+
+def test_gradient_estimator(oracle):
+    """Supplemental Sec. 2: the spatial gradient from the first ball of each walk, grad u ~
+    A0 grad G/G + (A - A0) (grad G/G or grad P/P) - A grad gamma(x0), against closed
+    forms: harmonic e^x cos y with and without null collisions, constant-sigma screened
+    Poisson in the unit ball (3D), and the variable-coefficient manufactured disk."""
+    def grad_expcos(p):
+        return np.c_[np.exp(p[:, 0]) * np.cos(p[:, 1]), -np.exp(p[:, 0]) * np.sin(p[:, 1])]
+
+    prob = harmonic_problem(W.geom_ball([0, 0], 1.0), 2, eps=1e-4)
+    pts = np.array([[0.0, 0.0], [0.3, -0.2], [-0.5, 0.4]])
+    for sb in (0.0, 9.0):
+        r = oracle.solve(prob, pts, 20000, sb, seed=2, gradient=True)
+        z = (r["grad_mean"] - grad_expcos(pts)) / r["grad_se"]
+        assert np.all(np.abs(z) < 4.5), (sb, z)
+    c = W.config1(n_grid=8)
+    prob, pts = c["problems"][0], c["points"][0][::6]
+    r = oracle.solve(prob, pts, 20000, 53.97, seed=2, gradient=True)
+    z = (r["grad_mean"] - grad_expcos(pts)) / r["grad_se"]
+    assert np.all(np.abs(z) < 4.5) and abs(np.mean(z)) < 1.0, z
+    sigma, f0, k = 9.0, 3.0, 3.0
+    prob = W.make_problem(3, W.geom_ball([0, 0, 0], 1.0), ONE, Z, W.field_const(sigma), W.field_const(f0), Z, 1e-4)
+    pts = np.array([[0.3, 0.1, -0.2], [-0.5, 0.2, 0.1]])
+    rr = np.linalg.norm(pts, axis=1)
+    dudr = -(f0 / sigma) / np.sinh(k) * (k * np.cosh(k * rr) * rr - np.sinh(k * rr)) / rr ** 2
+    for sb in (9.0, 20.0):
+        r = oracle.solve(prob, pts, 20000, sb, seed=2, gradient=True)
+        z = (r["grad_mean"] - dudr[:, None] * pts / rr[:, None]) / r["grad_se"]
+        assert np.all(np.abs(z) < 4.5), (sb, z)

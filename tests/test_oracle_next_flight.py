@@ -230,3 +230,45 @@ def test_next_flight_with_exact_kernels_is_unbiased(oracle, sb):
     exact = screened_ball_solution(2, sig, f0, np.linalg.norm(pts, axis=1))
     z = (o["mean"] - exact) / o["se"]
     assert np.all(np.abs(z) < 4), z
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("sb", [0.0, 2.0, 30.0])
+def test_gradient_kernels_match_derivatives_of_the_exact_series(oracle, dim, sb):
+    """grad_x G(x, y) and grad_x P(x, z) at the centre (supplemental Sec. 1.3, used by the
+    gradient estimator of supplemental Sec. 2) against central differences in x of the
+    exact off-centred kernels (or of the harmonic image formulas when sigma_bar = 0)."""
+    R, h = 0.9, 1e-5
+
+    def green(u, v):
+        if sb > 0:
+            return oracle.nf_kernel("green_exact", dim, u, v, R, sb)[0]
+        # harmonic: the image construction, G = Phi(|v - u|) - Phi(|u| |v - u*| / R), u* = R^2 u/|u|^2
+        a = np.linalg.norm(u)
+        img = R if a == 0 else a * np.linalg.norm(v - R * R * u / (a * a)) / R
+        w = np.linalg.norm(v - u)
+        return np.log(img / w) / (2 * np.pi) if dim == 2 else (1 / w - 1 / img) / (4 * np.pi)
+
+    def poisson(u, v):
+        if sb > 0:
+            return oracle.nf_kernel("poisson_exact", dim, u, v, R, sb)[0]
+        w = np.linalg.norm(v - u)
+        a2 = float(u @ u)
+        return (R * R - a2) / (2 * np.pi * R * w ** 2) if dim == 2 else (R * R - a2) / (4 * np.pi * R * w ** 3)
+
+    rng = np.random.default_rng(dim + int(sb))
+    for _ in range(4):
+        d = rng.normal(size=dim)
+        d /= np.linalg.norm(d)
+        y = d * R * rng.uniform(0.2, 0.8)
+        z = rng.normal(size=dim)
+        z = z / np.linalg.norm(z) * R
+        ratio_g = oracle.grad_ratio("green", dim, y, R, sb)
+        ratio_p = oracle.grad_ratio("poisson", dim, z, R, sb)
+        for i in range(dim):
+            e = np.zeros(dim)
+            e[i] = h
+            fd = (green(e, y) - green(-e, y)) / (2 * h)
+            assert fd == pytest.approx(ratio_g[i] * green(0 * e, y), rel=1e-5, abs=1e-7)
+            fd = (poisson(e, z) - poisson(-e, z)) / (2 * h)
+            assert fd == pytest.approx(ratio_p[i] * poisson(0 * e, z), rel=1e-5, abs=1e-7)
