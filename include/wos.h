@@ -209,6 +209,11 @@ typedef struct {
   uint64_t* n_walks;
   uint64_t* n_steps;
   uint64_t* counters;
+  double* grad_sum;       /* device [n_points][dim] or NULL: sums of the per-walk estimates of
+                             grad u (supplemental Sec. 2), accumulated like sum; delta
+                             tracking only (variant 0 or 1). Points within epsilon of the
+                             boundary get no gradient term from their (empty) first ball. */
+  double* grad_sum_sq;    /* device [n_points][dim]: sums of their squares (NULL iff grad_sum is) */
 } wos_batch_item;
 
 /* Runs walks_per_point walks from every query point of every item (Sec. 3.1: the estimate
@@ -236,6 +241,11 @@ wos_status wos_count_events(const wos_batch_item* items, int32_t n_items, const 
  * all device arrays of length n. */
 wos_status wos_finalize(const double* sum, const double* sum_sq, const uint64_t* n_walks, int64_t n,
                         double* mean, double* std_err, void* stream);
+
+/* The same for gradient sums (supplemental Sec. 2): grad_sum, grad_sum_sq, mean, std_err are
+ * device double [n][dim] (row-major), n_walks device uint64 [n]. */
+wos_status wos_finalize_grad(const double* grad_sum, const double* grad_sum_sq, const uint64_t* n_walks, int64_t n,
+                             int32_t dim, double* mean, double* std_err, void* stream);
 
 /* A plan fixes items and options once: it copies the item and tile tables to the device,
  * allocates the scratch memory, classifies the points, picks the launch shape and captures

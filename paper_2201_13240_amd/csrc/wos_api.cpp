@@ -674,6 +674,8 @@ namespace {
 struct Schedule {
   int fp64 = 0, compensated = 0, dim = 2, geom = 0, device = 0;
   int variant = 0;            // 2 selects the next-flight walker
+  int grad = 0;               // some item asks for gradient sums
+  int mode = 0;               // walker instantiation (walker_mode)
   unsigned block = 256, grid = 0;
   uint32_t tile_walks = 256;
   uint64_t chunk_walks = 0;   // walks per point per launch
@@ -717,9 +719,18 @@ wos_status check_items(const wos_batch_item* items, int n_items, const wos_optio
       return fail(WOS_ERR_INVALID_ARG, "problem_index must be < 2^16 with weight-window splitting");
     if (it.n_points > 0 && (!it.points || !it.sum || !it.sum_sq || !it.n_walks || !it.n_steps))
       return fail(WOS_ERR_INVALID_ARG, "null device pointer in batch item");
+    if ((it.grad_sum == nullptr) != (it.grad_sum_sq == nullptr))
+      return fail(WOS_ERR_INVALID_ARG, "grad_sum and grad_sum_sq must both be set or both be null");
+    if (it.grad_sum) s.grad = 1;
     s.total_points += (uint64_t)it.n_points;
   }
+  if (s.grad && s.variant == 2) return fail(WOS_ERR_INVALID_ARG, "gradient estimates need delta tracking (variant 0 or 1)");
+  s.mode = walker_mode(s.variant, s.grad != 0, opt->ww_hi > 0);
   return WOS_OK;
+}
+
+size_t grad_bytes_per_walk(const Schedule& s) {
+  return (size_t)(1 + 3 * s.dim) * (s.fp64 ? sizeof(double) : sizeof(float));
 }
 
 std::mutex g_occ_mutex;
@@ -729,17 +740,17 @@ std::map<std::tuple<int, int, int, int, int, unsigned>, unsigned> g_occ;
 std::map<std::tuple<int, int, int, int, int, int>, std::pair<unsigned, uint32_t>> g_tuned;
 
 std::tuple<int, int, int, int, int, int> tune_key(const Schedule& s) {
-  return std::make_tuple(s.device, s.fp64, s.compensated, s.dim, s.geom, s.variant == 2);
+  return std::make_tuple(s.device, s.fp64, s.compensated, s.dim, s.geom, s.mode);
 }
 
 // Persistent grid for a block size: resident blocks per CU times CUs.
 wos_status grid_for_block(Schedule& s, unsigned block) {
-  const auto key = std::make_tuple(s.device, s.fp64, s.dim, s.geom, (int)(s.variant == 2), block);
+  const auto key = std::make_tuple(s.device, s.fp64, s.dim, s.geom, s.mode, block);
   std::lock_guard<std::mutex> lk(g_occ_mutex);
   auto it = g_occ.find(key);
   if (it == g_occ.end()) {
     int per_cu = 0, cus = 0;
-    WOS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, walker_symbol(s.fp64, s.dim, s.geom, s.variant), (int)block, 0));
+    WOS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, walker_symbol(s.fp64, s.dim, s.geom, s.mode), (int)block, 0));
     WOS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s.device));
     unsigned grid = (unsigned)std::max(1, per_cu) * (unsigned)std::max(1, cus);
     it = g_occ.emplace(key, grid).first;
@@ -768,7 +779,7 @@ wos_status pick_shape(const wos_options* opt, Schedule& s) {
   wos_status r = grid_for_block(s, block);
   if (r != WOS_OK) return r;
   const uint64_t cap = opt->workspace_bytes ? opt->workspace_bytes : (4ull << 30);
-  const uint64_t per_walk = sizeof(WalkRecord);
+  const uint64_t per_walk = sizeof(WalkRecord) + (s.grad ? grad_bytes_per_walk(s) : 0);
   const uint64_t max_ids = std::max<uint64_t>(cap / per_walk, 1);
   const uint64_t N = opt->walks_per_point;
   uint64_t nc = s.total_points ? std::max<uint64_t>(1, max_ids / s.total_points) : N;
@@ -797,6 +808,8 @@ void build_tables(const wos_batch_item* items, int n_items, const wos_options* o
     d.n_walks = it.n_walks;
     d.n_steps = it.n_steps;
     d.counters = it.counters;
+    d.grad_sum = it.grad_sum;
+    d.grad_sum_sq = it.grad_sum_sq;
     d.n_points = it.n_points;
     d.walks = nw;
     d.walk_offset = opt->walk_offset + w0;
@@ -823,6 +836,7 @@ struct Workspace {
   uint32_t* counter = nullptr;
   LaunchParams* lp = nullptr;
   WalkRecord* records = nullptr;
+  void* grad = nullptr;           // gradient records, when any item asks for gradients
 };
 
 }  // namespace
@@ -846,7 +860,7 @@ __attribute__((unused)) size_t align_up(size_t v) { return (v + 255) / 256 * 256
 
 // Builds every launch's tables; returns the byte layout of the workspace.
 struct WsLayout {
-  size_t inside, items, tiles, counter, lp, records, total;
+  size_t inside, items, tiles, counter, lp, records, grad, total;
 };
 
 WsLayout ws_layout(const Schedule& s, int n_items, size_t max_tiles) {
@@ -864,6 +878,7 @@ WsLayout ws_layout(const Schedule& s, int n_items, size_t max_tiles) {
   L.counter = take(sizeof(uint32_t) * 64);
   L.lp = take(sizeof(LaunchParams));
   L.records = take(sizeof(WalkRecord) * std::max<uint64_t>(ids, 1));
+  L.grad = take(s.grad ? grad_bytes_per_walk(s) * std::max<uint64_t>(ids, 1) : 0);
   L.total = off;
   return L;
 }
@@ -876,6 +891,7 @@ void ws_bind(Workspace& w, void* base, const WsLayout& L) {
   w.counter = (uint32_t*)(b + L.counter);
   w.lp = (LaunchParams*)(b + L.lp);
   w.records = (WalkRecord*)(b + L.records);
+  w.grad = (void*)(b + L.grad);
 }
 
 // Prepares all tables of a job on the host.
@@ -923,6 +939,7 @@ WalkerLaunch walker_launch(const wos_options* opt, const Schedule& s, const Work
   L.rr = opt->russian_roulette;
   L.ww_lo = opt->ww_lo > 0 ? opt->ww_lo : 0.5;
   L.ww_hi = opt->ww_hi > 0 ? opt->ww_hi : 0.0;
+  L.grad = s.grad ? w.grad : nullptr;
   L.events = nullptr;
   return L;
 }
@@ -950,7 +967,10 @@ wos_status enqueue_job(const wos_batch_item* items, int n_items, const wos_optio
     if (marks) WOS_HIP(hipEventRecord((*marks)[2 * c], st));
     WOS_HIP(launch_walker(L, st));
     if (marks) WOS_HIP(hipEventRecord((*marks)[2 * c + 1], st));
-    for (int k = 0; k < n_items; ++k) WOS_HIP(launch_reduce(dit[c][k], w.records, st));
+    for (int k = 0; k < n_items; ++k) {
+      WOS_HIP(launch_reduce(dit[c][k], w.records, st));
+      if (s.grad) WOS_HIP(launch_reduce_grad(s.fp64, s.dim, dit[c][k], w.records, w.grad, st));
+    }
   }
   return WOS_OK;
 }
@@ -1206,6 +1226,14 @@ wos_status autotune(wos_plan* P, hipStream_t st, unsigned* block, uint32_t* tile
 }  // namespace
 
 extern "C" {
+
+wos_status wos_finalize_grad(const double* grad_sum, const double* grad_sum_sq, const uint64_t* n_walks, int64_t n,
+                             int32_t dim, double* mean, double* std_err, void* stream) {
+  if (n < 0 || (dim != 2 && dim != 3) || (n > 0 && (!grad_sum || !grad_sum_sq || !n_walks || !mean || !std_err)))
+    return fail(WOS_ERR_INVALID_ARG, "bad finalize arguments");
+  WOS_HIP(launch_finalize_components(grad_sum, grad_sum_sq, n_walks, n, dim, mean, std_err, (hipStream_t)stream));
+  return WOS_OK;
+}
 
 wos_status wos_plan_create(const wos_batch_item* items, int32_t n_items, const wos_options* opt, void* stream,
                            wos_plan** out) {

@@ -342,6 +342,71 @@ __device__ __forceinline__ Ball<T, DIM> ball_terms(T R, T s, T inv_sigma_bar, bo
   return b;
 }
 
+// ------------------------------------------------------------------ kernel gradients
+// grad_x G(x, y) and grad_x P(x, z) at the centre x of the ball (supplemental Sec. 1.3)
+// as ratios to G(x, y) and P(x, z), so that they multiply the walk's sampled terms
+// (y ~ G/|G|, z uniform on the sphere): a = f_G (y - x), b = f_P (z - x). Growing
+// exponentials are carried scaled (r <= R, so e^{2(r - R) k} <= 1).
+template <typename T, int DIM>
+__device__ __forceinline__ T grad_ratio_green(T r, T R, T k) {
+  if (!(k > (T)0)) {
+    return DIM == 2 ? m_div(m_rcp(r * r) - m_rcp(R * R), m_log(R / r))
+                    : m_div(m_rcp(r * r * r) - m_rcp(R * R * R), m_rcp(r) - m_rcp(R));
+  }
+  const T a = r * k, s = R * k;
+  if (DIM == 2) {
+    // (k/r) (K1(a) - (K1(s)/I1(s)) I1(a)) / (K0(a) - (K0(s)/I0(s)) I0(a)), times e^a / e^a
+    const T sh = m_exp((T)2 * (a - s));
+    const T c0 = m_div(bessel_k0e<T>(s), bessel_i0e<T>(s)), c1 = m_div(bessel_k1e<T>(s), bessel_i1e<T>(s));
+    const T num = bessel_k1e<T>(a) - c1 * bessel_i1e<T>(a) * sh;
+    const T den = bessel_k0e<T>(a) - c0 * bessel_i0e<T>(a) * sh;
+    return k * m_div(num, r * den);
+  }
+  // 3D: (k/r^2) N / Q with N = e^{-a} (1 + 1/a) - C(a) e^{-s} (1 + 1/s) / C(s),
+  // Q = (e^{-a} - e^{-s} sinh(a)/sinh(s)) / r and C(x) = cosh x - sinh(x)/x; both times e^a:
+  //   N e^a = (1 + 1/a) - e^a C(a) e^{-s} (1 + 1/s) / C(s)
+  //   Q e^a = (1 - (e^{2a} - 1)/(e^{2s} - 1)) / r
+  const T e2s = m_exp((T)-2 * s);
+  T prod;   // e^a C(a) e^{-s} (1 + 1/s) / C(s)
+  if (a >= (T)0.5) {
+    // e^a C(a) = (e^{2a} (1 - 1/a) + (1 + 1/a)) / 2 and C(s) = e^s ((1 - 1/s) + e^{-2s} (1 + 1/s)) / 2
+    const T dsn = ((T)1 - m_rcp(s)) + e2s * ((T)1 + m_rcp(s));
+    prod = m_div((m_exp((T)2 * (a - s)) * ((T)1 - m_rcp(a)) + e2s * ((T)1 + m_rcp(a))) * ((T)1 + m_rcp(s)), dsn);
+  } else {
+    const T a2 = a * a;
+    const T ca = a2 * ((T)(1.0 / 3.0) + a2 * ((T)(1.0 / 30.0) + a2 * ((T)(1.0 / 840.0) + a2 * (T)(1.0 / 45360.0))));
+    T cs;
+    if (s < (T)0.5) {
+      const T s2 = s * s;
+      cs = s2 * ((T)(1.0 / 3.0) + s2 * ((T)(1.0 / 30.0) + s2 * ((T)(1.0 / 840.0) + s2 * (T)(1.0 / 45360.0))));
+      prod = m_exp(a - s) * ca * m_div((T)1 + m_rcp(s), cs);
+    } else {
+      const T dsn = ((T)1 - m_rcp(s)) + e2s * ((T)1 + m_rcp(s));
+      prod = (T)2 * m_exp(a - (T)2 * s) * ca * m_div((T)1 + m_rcp(s), dsn);
+    }
+  }
+  const T num = ((T)1 + m_rcp(a)) - prod;
+  const T ratio = s <= (T)10 ? m_div(m_expm1((T)2 * a), m_expm1((T)2 * s))
+                             : m_div(m_exp((T)2 * (a - s)) - e2s, (T)1 - e2s);
+  return k * m_div(num, r * ((T)1 - ratio));
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ T grad_ratio_poisson(T R, T k) {
+  if (!(k > (T)0)) return (T)(DIM == 2 ? 2.0 : 3.0) * m_rcp(R * R);
+  const T s = R * k;
+  if (DIM == 2) return k * k * m_div(bessel_i0e<T>(s), s * bessel_i1e<T>(s));
+  // sigma sinh(s) / (s cosh(s) - sinh(s))
+  if (s < (T)0.5) {
+    const T s2 = s * s;
+    const T num = (T)1 + s2 * ((T)(1.0 / 6.0) + s2 * ((T)(1.0 / 120.0) + s2 * (T)(1.0 / 5040.0)));
+    const T den = s2 * ((T)(1.0 / 3.0) + s2 * ((T)(1.0 / 30.0) + s2 * ((T)(1.0 / 840.0) + s2 * (T)(1.0 / 45360.0))));
+    return k * k * m_div(num, den);
+  }
+  const T e2s = m_exp((T)-2 * s);
+  return k * k * m_div((T)1 - e2s, s * ((T)1 + e2s) - ((T)1 - e2s));
+}
+
 // ------------------------------------------------------------------ off-centred kernels
 // Closed-form approximations of the off-centred Green's function and Poisson kernel of
 // the ball B(c, R) for Lap - sigma_bar (supplemental Sec. 1.2), used by the next-flight
@@ -818,7 +883,7 @@ __device__ __forceinline__ void coefficient_bases(G<DevProblem<T>>& P, const T* 
 }
 
 template <typename T, int DIM, bool WITH_SOURCE>
-__device__ __forceinline__ PointCoef<T> point_coef(G<DevProblem<T>>& P, const T* x) {
+__device__ __forceinline__ PointCoef<T> point_coef(G<DevProblem<T>>& P, const T* x, T* grad_gamma = nullptr) {
   FV<T, DIM> base[3];
   coefficient_bases<T, DIM, true>(P, x, base);
   // ln alpha with its gradient and Laplacian: grad ln a = grad a / a,
@@ -851,6 +916,10 @@ __device__ __forceinline__ PointCoef<T> point_coef(G<DevProblem<T>>& P, const T*
   T g2 = 0;
 #pragma unroll
   for (int i = 0; i < DIM; ++i) g2 = m_fma(gg[i], gg[i], g2);
+  if (grad_gamma) {
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) grad_gamma[i] = gg[i];
+  }
   const T sig = field_transform<T, DIM, false>(P.sigma, base[2]).v;
   PointCoef<T> c;
   c.gamma = gamma;

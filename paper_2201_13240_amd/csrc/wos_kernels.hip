@@ -63,6 +63,7 @@ struct WalkerArgs {
   int32_t rr;
   T ww_lo;
   T ww_hi;               // > 0: expected-value splitting above this weight (delta tracking)
+  T* grad;               // [walk id][GradRecord<DIM>::kStride] or null: gradient records
   uint64_t* events;      // event-counting build only: [kEvents]
 };
 
@@ -107,10 +108,14 @@ __device__ __forceinline__ void add_estimate(T& A, T& Ac, T term, int compensate
 
 // Buffers written by the walker are separate __restrict__ parameters, so loads of the
 // problem tables (read-only, at wave-uniform addresses) can be served by scalar loads.
-template <typename T, int DIM, int GEOM, bool COUNT, bool NF>
+// MODE: 0 delta tracking, 1 delta tracking with the extras that cost registers (weight-window
+// splitting, gradient records), 2 next flight.
+template <typename T, int DIM, int GEOM, bool COUNT, int MODE>
 __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restrict__ tile_counter,
                                             WalkRecord* __restrict__ records, uint64_t* __restrict__ events_out) {
   using SL = Slots<T, DIM>;
+  constexpr bool NF = MODE == 2;
+  constexpr bool EXTRA = MODE == 1;
   const uint32_t lane = __lane_id();
   LdsStack<T> lds_stack{nullptr, nullptr, 0};
   if constexpr (GEOM == GK_POLYGON || GEOM == GK_TRIMESH) {
@@ -163,7 +168,7 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
   // finished branches are kept in the top bits of nsteps)
   SplitEntry<T, DIM> split_stack[kSplitDepth];
   uint32_t split_state = 0;
-  const bool window = a.rr || a.ww_hi > (T)0;
+  const bool window = a.rr || (EXTRA && a.ww_hi > (T)0);
 
   for (;;) {
     // ---------------------------------------------------------------- refill idle lanes
@@ -415,12 +420,25 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
         cq.sigma_prime = 0;
         cq.f_over_alpha = 0;
         cq.alpha = 1;
-        if (evaluate) cq = point_coef<T, DIM, true>(P, q);
+        T ggx[DIM];
+        if (evaluate) cq = point_coef<T, DIM, true>(P, q, EXTRA && a.grad ? ggx : nullptr);
         if (phase == 1) {
           gamma0 = cq.gamma;
           gx = gamma0;
           gx_known = true;
           phase = 2;
+          if (EXTRA && a.grad) {
+            // gradient record of the walk: grad gamma(x0) now, the first ball's terms
+            // when it is sampled (they stay zero for a walk that starts in the shell)
+            T* gr = a.grad + (size_t)wid * GradRecord<DIM>::kStride;
+            gr[0] = 0;
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) {
+              gr[1 + i] = 0;
+              gr[1 + DIM + i] = 0;
+              gr[1 + 2 * DIM + i] = ggx[i];
+            }
+          }
         } else if (terminal) {
           add_estimate(A, Ac, Pi * m_exp(cq.gamma - gamma0) * gb, a.compensated);
           done = true;
@@ -433,6 +451,27 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
           else if (volume) term = src * P.inv_sigma_bar;
           add_estimate(A, Ac, term, a.compensated);
           if constexpr (COUNT) ++ev[volume ? EV_VOLUME : EV_EXIT];
+          if (EXTRA && a.grad && (nsteps & kStepMask) == 1u && (split_state >> 8) == 0u) {
+            // first ball (supplemental Sec. 2): A0 = its source term, a = grad G/G at y,
+            // b = a after a volume event or grad P/P at the exit point z
+            T* gr = a.grad + (size_t)wid * GradRecord<DIM>::kStride;
+            T w[DIM], r2 = 0;
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) {
+              w[i] = q[i] - x[i];
+              r2 = m_fma(w[i], w[i], r2);
+            }
+            const T fg = grad_ratio_green<T, DIM>(m_sqrt(r2), R, P.sqrt_sigma_bar);
+            const T fp = grad_ratio_poisson<T, DIM>(R, P.sqrt_sigma_bar);
+            T vz[DIM];
+            uniform_direction<T, DIM, SL::kExitDir>(rng, vz);   // the exit direction drawn below
+            gr[0] = term;
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) {
+              gr[1 + i] = fg * w[i];
+              gr[1 + DIM + i] = volume ? fg * w[i] : fp * R * vz[i];
+            }
+          }
           if (volume) {
             // null event: weight (1 - sigma'(y)/sigma_bar) e^{gamma(y) - gamma(x)}, move to y
             Pi *= (T)1 - cq.sigma_prime * P.inv_sigma_bar;
@@ -467,7 +506,7 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
                 done = true;
                 flag = kFlagRR;
               }
-            } else if (a.ww_hi > (T)0 && m_fabs(W) > a.ww_hi && (split_state >> 8) < kMaxBranches) {
+            } else if (EXTRA && a.ww_hi > (T)0 && m_fabs(W) > a.ww_hi && (split_state >> 8) < kMaxBranches) {
               // high side: expected-value splitting into N branches of weight W/m,
               // m = |W|/w+, N = floor(m) with probability floor(m) + 1 - m, else
               // floor(m) + 1; N - 1 siblings wait on the lane's stack
@@ -493,7 +532,7 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
         }
         if (done) {
           nsteps |= flag;
-          if (split_state & 0xFFu) {
+          if (EXTRA && (split_state & 0xFFu)) {
             // the walk goes on as the next sibling branch of the latest split, from the
             // split's state, with a stream of its own
             SplitEntry<T, DIM>& se = split_stack[(split_state & 0xFFu) - 1u];
@@ -532,18 +571,18 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
 // Kernel entry points, one per precision so that each gets its own register budget: the
 // FP32 walker fits 96 VGPRs (5 waves per SIMD); the FP64 walker needs more than 256
 // unless asked to fit 256 (2 waves per SIMD).
-template <int DIM, int GEOM, bool COUNT, bool NF>
+template <int DIM, int GEOM, bool COUNT, int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WOS_WAVES_FP32)))
 walker_kernel_fp32(WalkerArgs<float> a, uint32_t* __restrict__ tile_counter, WalkRecord* __restrict__ records,
                    uint64_t* __restrict__ events_out) {
-  walker_body<float, DIM, GEOM, COUNT, NF>(a, tile_counter, records, events_out);
+  walker_body<float, DIM, GEOM, COUNT, MODE>(a, tile_counter, records, events_out);
 }
 
-template <int DIM, int GEOM, bool COUNT, bool NF>
+template <int DIM, int GEOM, bool COUNT, int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WOS_WAVES_FP64)))
 walker_kernel_fp64(WalkerArgs<double> a, uint32_t* __restrict__ tile_counter, WalkRecord* __restrict__ records,
                    uint64_t* __restrict__ events_out) {
-  walker_body<double, DIM, GEOM, COUNT, NF>(a, tile_counter, records, events_out);
+  walker_body<double, DIM, GEOM, COUNT, MODE>(a, tile_counter, records, events_out);
 }
 
 // ------------------------------------------------------------------ reduce (fixed order)
@@ -588,6 +627,41 @@ __global__ void reduce_kernel(DevItem it, const WalkRecord* __restrict__ records
       if (killed) atomicAdd((unsigned long long*)&it.counters[2], (unsigned long long)killed);
       if (ntr) atomicAdd((unsigned long long*)&it.counters[3], (unsigned long long)ntr);
     }
+  }
+}
+
+// Gradient sums per point (supplemental Sec. 2): each walk's estimate is
+// A0 a + (A - A0) b - A grad gamma(x0) from its record and its value A; fixed order
+// over walks, Neumaier-compensated per component.
+template <typename T, int DIM>
+__global__ void reduce_grad_kernel(DevItem it, const WalkRecord* __restrict__ records, const T* __restrict__ grad) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= it.n_points) return;
+  double s[DIM], cs[DIM], q[DIM], cq[DIM];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) s[k] = cs[k] = q[k] = cq[k] = 0;
+  constexpr int kS = GradRecord<DIM>::kStride;
+  for (uint64_t j = 0; j < it.walks; ++j) {
+    const uint64_t idx = it.walk_base + j * (uint64_t)it.n_points + (uint64_t)p;
+    const double v = records[idx].value;
+    const T* gr = grad + (size_t)idx * kS;
+    const double a0 = (double)gr[0];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      const double g = a0 * (double)gr[1 + k] + (v - a0) * (double)gr[1 + DIM + k] - v * (double)gr[1 + 2 * DIM + k];
+      double t = s[k] + g;
+      cs[k] += fabs(s[k]) >= fabs(g) ? (s[k] - t) + g : (g - t) + s[k];
+      s[k] = t;
+      const double g2 = g * g;
+      t = q[k] + g2;
+      cq[k] += fabs(q[k]) >= fabs(g2) ? (q[k] - t) + g2 : (g2 - t) + q[k];
+      q[k] = t;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    it.grad_sum[p * DIM + k] += s[k] + cs[k];
+    it.grad_sum_sq[p * DIM + k] += q[k] + cq[k];
   }
 }
 
@@ -840,19 +914,19 @@ __global__ void finalize_kernel(const double* sum, const double* sum_sq, const u
 
 static inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-template <typename T, int DIM, int GEOM, bool COUNT, bool NF>
+template <typename T, int DIM, int GEOM, bool COUNT, int MODE>
 static const void* walker_entry() {
-  if constexpr (sizeof(T) == 4) return (const void*)&walker_kernel_fp32<DIM, GEOM, COUNT, NF>;
-  else return (const void*)&walker_kernel_fp64<DIM, GEOM, COUNT, NF>;
+  if constexpr (sizeof(T) == 4) return (const void*)&walker_kernel_fp32<DIM, GEOM, COUNT, MODE>;
+  else return (const void*)&walker_kernel_fp64<DIM, GEOM, COUNT, MODE>;
 }
 
-template <typename T, int DIM, int GEOM, bool COUNT, bool NF>
+template <typename T, int DIM, int GEOM, bool COUNT, int MODE>
 static void launch_walker_k(dim3 g, dim3 b, hipStream_t st, const WalkerArgs<T>& a, uint32_t* counter,
                             WalkRecord* records, uint64_t* events) {
   if constexpr (sizeof(T) == 4)
-    hipLaunchKernelGGL((walker_kernel_fp32<DIM, GEOM, COUNT, NF>), g, b, 0, st, a, counter, records, events);
+    hipLaunchKernelGGL((walker_kernel_fp32<DIM, GEOM, COUNT, MODE>), g, b, 0, st, a, counter, records, events);
   else
-    hipLaunchKernelGGL((walker_kernel_fp64<DIM, GEOM, COUNT, NF>), g, b, 0, st, a, counter, records, events);
+    hipLaunchKernelGGL((walker_kernel_fp64<DIM, GEOM, COUNT, MODE>), g, b, 0, st, a, counter, records, events);
 }
 
 template <typename T, int DIM, int GEOM>
@@ -870,15 +944,20 @@ static hipError_t launch_walker_t(const WalkerLaunch& L, hipStream_t st) {
   a.rr = L.rr;
   a.ww_lo = (T)L.ww_lo;
   a.ww_hi = (T)L.ww_hi;
+  a.grad = (T*)L.grad;
   a.events = L.events;
   const dim3 g(L.grid), b(L.block);
   uint64_t* ev = L.events;
-  if (L.variant == 2) {
-    if (ev) launch_walker_k<T, DIM, GEOM, true, true>(g, b, st, a, L.tile_counter, L.records, ev);
-    else launch_walker_k<T, DIM, GEOM, false, true>(g, b, st, a, L.tile_counter, L.records, ev);
+  const int mode = walker_mode(L.variant, L.grad != nullptr, L.ww_hi > 0);
+  if (mode == 2) {
+    if (ev) launch_walker_k<T, DIM, GEOM, true, 2>(g, b, st, a, L.tile_counter, L.records, ev);
+    else launch_walker_k<T, DIM, GEOM, false, 2>(g, b, st, a, L.tile_counter, L.records, ev);
+  } else if (mode == 1) {
+    if (ev) launch_walker_k<T, DIM, GEOM, true, 1>(g, b, st, a, L.tile_counter, L.records, ev);
+    else launch_walker_k<T, DIM, GEOM, false, 1>(g, b, st, a, L.tile_counter, L.records, ev);
   } else {
-    if (ev) launch_walker_k<T, DIM, GEOM, true, false>(g, b, st, a, L.tile_counter, L.records, ev);
-    else launch_walker_k<T, DIM, GEOM, false, false>(g, b, st, a, L.tile_counter, L.records, ev);
+    if (ev) launch_walker_k<T, DIM, GEOM, true, 0>(g, b, st, a, L.tile_counter, L.records, ev);
+    else launch_walker_k<T, DIM, GEOM, false, 0>(g, b, st, a, L.tile_counter, L.records, ev);
   }
   return hipGetLastError();
 }
@@ -906,12 +985,14 @@ hipError_t launch_walker(const WalkerLaunch& L, hipStream_t st) {
 }
 
 template <typename T, int DIM, int GEOM>
-static const void* walker_symbol_t(bool nf) {
-  return nf ? walker_entry<T, DIM, GEOM, false, true>() : walker_entry<T, DIM, GEOM, false, false>();
+static const void* walker_symbol_t(int mode) {
+  return mode == 2 ? walker_entry<T, DIM, GEOM, false, 2>()
+         : mode == 1 ? walker_entry<T, DIM, GEOM, false, 1>()
+                     : walker_entry<T, DIM, GEOM, false, 0>();
 }
 
 template <typename T>
-static const void* walker_symbol_dim(int dim, int geom, bool nf) {
+static const void* walker_symbol_dim(int dim, int geom, int nf) {
   if (dim == 2)
     return geom == GK_BALL ? walker_symbol_t<T, 2, GK_BALL>(nf)
            : geom == GK_BOX ? walker_symbol_t<T, 2, GK_BOX>(nf)
@@ -921,13 +1002,29 @@ static const void* walker_symbol_dim(int dim, int geom, bool nf) {
                           : walker_symbol_t<T, 3, GK_TRIMESH>(nf);
 }
 
-const void* walker_symbol(int fp64, int dim, int geom, int variant) {
-  return fp64 ? walker_symbol_dim<double>(dim, geom, variant == 2) : walker_symbol_dim<float>(dim, geom, variant == 2);
+int walker_mode(int variant, bool grad, bool split) { return variant == 2 ? 2 : (grad || split) ? 1 : 0; }
+
+const void* walker_symbol(int fp64, int dim, int geom, int mode) {
+  return fp64 ? walker_symbol_dim<double>(dim, geom, mode) : walker_symbol_dim<float>(dim, geom, mode);
 }
 
 hipError_t launch_reduce(const DevItem& it, const WalkRecord* records, hipStream_t st) {
   if (it.n_points == 0) return hipSuccess;
   hipLaunchKernelGGL(reduce_kernel, dim3(blocks_for(it.n_points, 256)), dim3(256), 0, st, it, records);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_grad(int fp64, int dim, const DevItem& it, const WalkRecord* records, const void* grad,
+                              hipStream_t st) {
+  if (it.n_points == 0 || !it.grad_sum) return hipSuccess;
+  const dim3 g(blocks_for(it.n_points, 256)), b(256);
+  if (fp64) {
+    if (dim == 2) hipLaunchKernelGGL((reduce_grad_kernel<double, 2>), g, b, 0, st, it, records, (const double*)grad);
+    else hipLaunchKernelGGL((reduce_grad_kernel<double, 3>), g, b, 0, st, it, records, (const double*)grad);
+  } else {
+    if (dim == 2) hipLaunchKernelGGL((reduce_grad_kernel<float, 2>), g, b, 0, st, it, records, (const float*)grad);
+    else hipLaunchKernelGGL((reduce_grad_kernel<float, 3>), g, b, 0, st, it, records, (const float*)grad);
+  }
   return hipGetLastError();
 }
 
@@ -1085,6 +1182,26 @@ hipError_t launch_bessel(int fp64, int which, const double* x, int64_t n, double
   const dim3 g(blocks_for(n, 256)), b(256);
   if (fp64) hipLaunchKernelGGL((bessel_kernel<double>), g, b, 0, st, which, x, n, out);
   else hipLaunchKernelGGL((bessel_kernel<float>), g, b, 0, st, which, x, n, out);
+  return hipGetLastError();
+}
+
+// Per component of [n][dim] sums, with the walk count of its point.
+__global__ void finalize_components_kernel(const double* sum, const double* sum_sq, const uint64_t* nw, int64_t n,
+                                           int dim, double* mean, double* se) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * dim) return;
+  const double N = (double)nw[i / dim];
+  const double m = sum[i] / N;
+  const double var = N > 1 ? fmax(sum_sq[i] / N - m * m, 0.0) * N / (N - 1) : __builtin_nan("");
+  mean[i] = m;
+  se[i] = sqrt(var / N);
+}
+
+hipError_t launch_finalize_components(const double* sum, const double* sum_sq, const uint64_t* nw, int64_t n, int dim,
+                                      double* mean, double* se, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(finalize_components_kernel, dim3(blocks_for(n * dim, 256)), dim3(256), 0, st, sum, sum_sq, nw,
+                     n, dim, mean, se);
   return hipGetLastError();
 }
 

@@ -26,12 +26,19 @@ struct WalkerLaunch {
   int rr;
   double ww_lo;
   double ww_hi;       // 0: no splitting
+  void* grad;         // gradient records (T[walk id][1 + 3 dim]) or null
   uint64_t* events;   // non-null selects the event-counting build of the walker
 };
 
 hipError_t launch_walker(const WalkerLaunch& L, hipStream_t st);
-const void* walker_symbol(int fp64, int dim, int geom, int variant);
+// 0 delta tracking, 1 delta tracking with splitting or gradient records, 2 next flight
+int walker_mode(int variant, bool grad, bool split);
+const void* walker_symbol(int fp64, int dim, int geom, int mode);
 hipError_t launch_reduce(const DevItem& it, const WalkRecord* records, hipStream_t st);
+hipError_t launch_finalize_components(const double* sum, const double* sum_sq, const uint64_t* nw, int64_t n, int dim,
+                                      double* mean, double* se, hipStream_t st);
+hipError_t launch_reduce_grad(int fp64, int dim, const DevItem& it, const WalkRecord* records, const void* grad,
+                              hipStream_t st);
 hipError_t launch_reset(uint32_t* counter, hipStream_t st);
 hipError_t launch_set_params(LaunchParams* lp, uint64_t seed, uint64_t walk_offset_add, hipStream_t st);
 hipError_t launch_classify(int dim, int geom, const void* P64, const double* pts, int64_t n, int8_t* inside,

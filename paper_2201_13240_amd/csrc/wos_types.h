@@ -125,6 +125,8 @@ struct DevItem {
   uint64_t point_base;       // offset of this item in the launch's point space
   uint32_t problem_index;
   uint32_t pad;
+  double* grad_sum;          // [n_points][dim] or null
+  double* grad_sum_sq;
 };
 
 // A contiguous range of walk ids of one item; waves take whole tiles.
@@ -141,6 +143,13 @@ struct __attribute__((aligned(16))) WalkRecord {
   double value;
   uint32_t steps;
   uint32_t trials;
+};
+
+// Per-walk record of the gradient estimate (supplemental Sec. 2), in the walker's
+// precision: [A0, a (dim), b (dim), grad gamma(x0) (dim)].
+template <int DIM>
+struct GradRecord {
+  static constexpr int kStride = 1 + 3 * DIM;
 };
 
 struct LaunchParams {

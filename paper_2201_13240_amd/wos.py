@@ -58,12 +58,13 @@ class Options(C.Structure):
 class BatchItem(C.Structure):
     _fields_ = [("problem", C.c_void_p), ("points", C.c_void_p), ("n_points", C.c_int64),
                 ("problem_index", C.c_uint32), ("pad", C.c_uint32), ("sum", C.c_void_p), ("sum_sq", C.c_void_p),
-                ("n_walks", C.c_void_p), ("n_steps", C.c_void_p), ("counters", C.c_void_p)]
+                ("n_walks", C.c_void_p), ("n_steps", C.c_void_p), ("counters", C.c_void_p),
+                ("grad_sum", C.c_void_p), ("grad_sum_sq", C.c_void_p)]
 
 
 # Every symbol declared in include/wos.h.
 EXPORTS = ["wos_last_error", "wos_version", "wos_problem_create", "wos_problem_info", "wos_problem_bvh_info", "wos_problem_grid_info",
-           "wos_problem_destroy", "wos_solve", "wos_count_events", "wos_finalize", "wos_plan_create", "wos_plan_launch",
+           "wos_problem_destroy", "wos_solve", "wos_count_events", "wos_finalize", "wos_finalize_grad", "wos_plan_create", "wos_plan_launch",
            "wos_plan_time", "wos_plan_info", "wos_plan_destroy", "wos_eval_coefficients", "wos_eval_distance", "wos_eval_ball",
            "wos_sample_radius", "wos_philox", "wos_eval_bessel", "wos_eval_offcentred", "wos_classify"]
 
@@ -88,6 +89,7 @@ def lib():
         L.wos_solve.argtypes = [C.POINTER(BatchItem), i32, C.POINTER(Options), vp]
         L.wos_count_events.argtypes = [C.POINTER(BatchItem), i32, C.POINTER(Options), vp, vp]
         L.wos_finalize.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+        L.wos_finalize_grad.argtypes = [vp, vp, vp, i64, i32, vp, vp, vp]
         L.wos_plan_create.argtypes = [C.POINTER(BatchItem), i32, C.POINTER(Options), vp, C.POINTER(vp)]
         L.wos_plan_launch.argtypes = [vp, u64, u64, vp]
         L.wos_plan_time.argtypes = [vp, u64, u64, vp, dp, dp]
@@ -235,13 +237,16 @@ class Problem:
 class Accumulators:
     """Per-point device accumulators of one batch item (added into by every solve)."""
 
-    def __init__(self, n, device="cuda"):
+    def __init__(self, n, device="cuda", grad_dim=0):
+        """grad_dim > 0 adds gradient sums [n][grad_dim] (supplemental Sec. 2)."""
         import torch
         self.sum = torch.zeros(n, dtype=torch.float64, device=device)
         self.sum_sq = torch.zeros(n, dtype=torch.float64, device=device)
         self.n_walks = torch.zeros(n, dtype=torch.int64, device=device)
         self.n_steps = torch.zeros(n, dtype=torch.int64, device=device)
         self.counters = torch.zeros(4, dtype=torch.int64, device=device)
+        self.grad_sum = torch.zeros((n, grad_dim), dtype=torch.float64, device=device) if grad_dim else None
+        self.grad_sum_sq = torch.zeros_like(self.grad_sum) if grad_dim else None
 
 
 VARIANTS = {"alg1": 0, "eq28": 1, "next_flight": 2}
@@ -279,6 +284,10 @@ def _items(entries):
         it.n_walks = acc.n_walks.data_ptr()
         it.n_steps = acc.n_steps.data_ptr()
         it.counters = acc.counters.data_ptr()
+        if acc.grad_sum is not None:
+            assert acc.grad_sum.shape == (pts.shape[0], prob.dim)
+            it.grad_sum = acc.grad_sum.data_ptr()
+            it.grad_sum_sq = acc.grad_sum_sq.data_ptr()
     return arr
 
 
@@ -309,6 +318,17 @@ def finalize(acc, stream=None):
     se = torch.empty_like(mean)
     _check(lib().wos_finalize(_ptr(acc.sum), _ptr(acc.sum_sq), _ptr(acc.n_walks), n, _ptr(mean), _ptr(se),
                               _stream(stream)))
+    return mean, se
+
+
+def finalize_grad(acc, stream=None):
+    """Mean and standard error of the gradient estimates, [n][dim] each."""
+    import torch
+    n, dim = acc.grad_sum.shape
+    mean = torch.empty((n, dim), dtype=torch.float64, device=acc.grad_sum.device)
+    se = torch.empty_like(mean)
+    _check(lib().wos_finalize_grad(_ptr(acc.grad_sum), _ptr(acc.grad_sum_sq), _ptr(acc.n_walks), n, dim, _ptr(mean),
+                                   _ptr(se), _stream(stream)))
     return mean, se
 
 

@@ -36,3 +36,17 @@ def gpu_solve(W, prob_handle, pts, walks, precision="fp32", seed=0, **kw):
     return {"mean": mean.cpu().numpy(), "se": se.cpu().numpy(), "steps": acc.n_steps.cpu().numpy(),
             "n": acc.n_walks.cpu().numpy(), "counters": acc.counters.cpu().numpy(),
             "sum": acc.sum.cpu().numpy()}
+
+
+def gpu_solve_grad(W, prob_handle, pts, walks, precision="fp32", seed=0, **kw):
+    """As gpu_solve, with the gradient sums of supplemental Sec. 2."""
+    torch = torch_cuda()
+    P = dev(pts)
+    acc = W.Accumulators(P.shape[0], grad_dim=P.shape[1])
+    W.solve([(prob_handle, P, acc, kw.pop("problem_index", 0))], W.options(precision=precision, walks=walks,
+                                                                             seed=seed, **kw))
+    mean, se = W.finalize(acc)
+    gmean, gse = W.finalize_grad(acc)
+    torch.cuda.synchronize()
+    return {"mean": mean.cpu().numpy(), "se": se.cpu().numpy(), "grad_mean": gmean.cpu().numpy(),
+            "grad_se": gse.cpu().numpy(), "steps": acc.n_steps.cpu().numpy(), "sum": acc.sum.cpu().numpy()}

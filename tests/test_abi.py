@@ -38,7 +38,7 @@ def test_version_and_struct_sizes(W):
     assert W.lib().wos_version() >= 100
     # wos_options / wos_batch_item layouts as declared in the header
     assert C.sizeof(W.Options) == 80
-    assert C.sizeof(W.BatchItem) == 72
+    assert C.sizeof(W.BatchItem) == 88
 
 
 def _base_problem():

@@ -308,3 +308,50 @@ def test_weight_window_splitting(W, oracle):
         torch.cuda.synchronize()
         sums.append(acc.sum.cpu().numpy())
     assert np.array_equal(sums[0], sums[1])
+
+
+def test_gradient_estimates(W, oracle):
+    """Spatial gradient from the first ball of each walk (supplemental Sec. 2) against
+    closed forms (harmonic disk with and without null collisions, 3D screened ball) and
+    against the oracle on the manufactured disk; the value sums are unchanged by asking
+    for gradients."""
+    from tests.gpu_common import gpu_solve_grad
+
+    def grad_expcos(p):
+        return np.c_[np.exp(p[:, 0]) * np.cos(p[:, 1]), -np.exp(p[:, 0]) * np.sin(p[:, 1])]
+
+    disk = harmonic(WL.geom_ball([0, 0], 1.0), 2)
+    pts = WL.sample_inside(np.random.default_rng(3), disk["geometry"], 2, 48) * 0.8
+    for sb in (0.0, 9.0):
+        h = W.Problem(disk, sigma_bar=sb)
+        for precision in ("fp64", "fp32"):
+            r = gpu_solve_grad(W, h, pts, 8192, precision, seed=51)
+            ex = grad_expcos(pts)
+            assert_parity(r["grad_mean"].ravel(), r["grad_se"].ravel(), ex.ravel(), 0 * ex.ravel(),
+                          f"gradient harmonic sigma_bar={sb} {precision}", tol(precision))
+            r0 = gpu_solve(W, h, pts, 8192, precision, seed=51)
+            assert np.array_equal(r0["sum"], r["sum"])
+    sig, f0, k = 9.0, 3.0, 3.0
+    ball = WL.make_problem(3, WL.geom_ball([0, 0, 0], 1.0), ONE, Z, WL.field_const(sig), WL.field_const(f0), Z, 1e-4)
+    pts3 = WL.sample_inside(np.random.default_rng(4), ball["geometry"], 3, 32) * 0.8
+    rr = np.linalg.norm(pts3, axis=1)
+    dudr = -(f0 / sig) / np.sinh(k) * (k * np.cosh(k * rr) * rr - np.sinh(k * rr)) / rr ** 2
+    ex3 = dudr[:, None] * pts3 / rr[:, None]
+    for sb in (9.0, 20.0):
+        h = W.Problem(ball, sigma_bar=sb)
+        r = gpu_solve_grad(W, h, pts3, 8192, "fp32", seed=52)
+        assert_parity(r["grad_mean"].ravel(), r["grad_se"].ravel(), ex3.ravel(), 0 * ex3.ravel(),
+                      f"gradient screened ball sigma_bar={sb}", tol("fp32"))
+    c = WL.config1(n_grid=16)
+    prob = c["problems"][0]
+    pts = away_from_boundary(oracle, prob, c["points"][0])[::2]
+    h = W.Problem(prob, sigma_bar_grid=512)
+    o = oracle.solve(prob, pts, 2048, h.sigma_bar, seed=53, gradient=True)
+    for precision in ("fp64", "fp32"):
+        r = gpu_solve_grad(W, h, pts, 2048, precision, seed=54)
+        assert_parity(r["grad_mean"].ravel(), r["grad_se"].ravel(), o["grad_mean"].ravel(), o["grad_se"].ravel(),
+                      f"gradient manufactured disk vs oracle {precision}", tol(precision))
+    r = gpu_solve_grad(W, h, pts, 8192, "fp32", seed=55)
+    ex = grad_expcos(pts)
+    assert_parity(r["grad_mean"].ravel(), r["grad_se"].ravel(), ex.ravel(), 0 * ex.ravel(),
+                  "gradient manufactured disk vs exact", tol("fp32"))
