@@ -152,7 +152,8 @@ def device_source_hash():
 
 
 def walker_kernel_name(precision):
-    return "walker_kernel<%s, 2, 2, false>" % ("double" if precision == "fp64" else "float")
+    """Name of the delta-tracking walker on the 2-D polygon domain as the profiler reports it."""
+    return "walker_kernel_%s<2, 2, false, 0>" % precision
 
 
 def traffic_of(kernel):

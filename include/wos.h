@@ -56,8 +56,29 @@ int wos_version(void);
  *           loop; segment j joins vertex j and j+1 (mod n).
  *  TRIMESH: dim = 3; vertices: host double [n_vertices][3]; triangles: host int32
  *           [n_triangles][3], a closed surface.
+ *  SDF:     a list of constructive-solid-geometry operations on signed distance fields
+ *           (Sec. 7.2). vertices: host double [n_vertices][8], one operation per row:
+ *           (op, shape, c0, c1, c2, p0, p1, p2); n_vertices in 1..WOS_SDF_MAX_OPS.
+ *           shape 0 ball      |x - c| - p0                 (p0 > 0)
+ *           shape 1 box       exact distance to the box c +- (p0, p1, p2) (> 0 each)
+ *           shape 2 halfspace (x.c - p0) / |c|             (c != 0; inside: x.c < p0)
+ *           Starting from the empty set (f = +inf), row k combines its field f_k into f:
+ *           op 0 union min(f, f_k), op 1 intersection max(f, f_k), op 2 subtraction
+ *           max(f, -f_k); row 0 must be a union. The domain is {f < 0}; -f is the
+ *           distance used for the ball radius (a lower bound of the true distance, so
+ *           every ball stays inside), and the epsilon-shell exit point is
+ *           x - f(x) grad f(x) with the gradient of the row that decides f. Components
+ *           beyond dim are ignored. lo[dim], hi[dim]: a box that holds the (bounded)
+ *           domain, used to sample sigma'.
  * Polygons and meshes get an axis-aligned BVH (Sec. 7.1) built on the host. */
-typedef enum { WOS_GEOM_BALL = 0, WOS_GEOM_BOX = 1, WOS_GEOM_POLYGON = 2, WOS_GEOM_TRIMESH = 3 } wos_geom_kind;
+typedef enum {
+  WOS_GEOM_BALL = 0,
+  WOS_GEOM_BOX = 1,
+  WOS_GEOM_POLYGON = 2,
+  WOS_GEOM_TRIMESH = 3,
+  WOS_GEOM_SDF = 4
+} wos_geom_kind;
+#define WOS_SDF_MAX_OPS 256
 
 typedef struct {
   int32_t kind;               /* wos_geom_kind */

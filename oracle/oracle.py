@@ -57,7 +57,7 @@ class OOptions(C.Structure):
 
 _BASES = {"none": 0, "fourier": 1, "bumps": 2, "tanh": 3, "tanh_drift": 4, "manufactured": 5}
 _TRANSFORMS = {"affine": 0, "exp": 1}
-_GEOMS = {"ball": 0, "box": 1, "polygon": 2, "trimesh": 3}
+_GEOMS = {"ball": 0, "box": 1, "polygon": 2, "trimesh": 3, "sdf": 4}
 _US = {"expcos": 1, "quadratic": 2}
 
 _lib = None
@@ -127,6 +127,13 @@ class Problem:
                 G.center[i] = v
             G.radius = g["radius"]
         elif g["kind"] == "box":
+            for i in range(len(g["lo"])):
+                G.lo[i] = g["lo"][i]
+                G.hi[i] = g["hi"][i]
+        elif g["kind"] == "sdf":
+            V = self._arr(g["rows"])
+            G.vertices = _dptr(V)
+            G.n_vertices = V.shape[0]
             for i in range(len(g["lo"])):
                 G.lo[i] = g["lo"][i]
                 G.hi[i] = g["hi"][i]

@@ -25,7 +25,8 @@
 //     Sec. 1.2 and uniform points inside each ball;
 //   * the static weight window of Sec. 6: Russian roulette below w- and expected-value
 //     splitting above w+;
-//   * the per-point Monte Carlo mean (Sec. 3.1, eqs. 17-18).
+//   * the per-point Monte Carlo mean (Sec. 3.1, eqs. 17-18);
+//   * domains given as a list of CSG operations on signed distance fields (Sec. 7.2).
 //
 // Readings of the paper taken here (where it is silent, ambiguous or garbled):
 //   R1  the source sign in eq. 21 is taken as -f' (consistent with eq. 23 and App. A);
@@ -37,13 +38,16 @@
 //   R5  Russian roulette: when |W| < w_lo the walk survives with probability |W|/w_lo
 //       and then carries W = sign(W) w_lo; the estimate accumulated so far is kept;
 //   R6  for s = R sqrt(sigma_bar) < 1e-4 the harmonic (sigma_bar -> 0) limits are used
-//       for P_B = s^2/4 (2D), s^2/6 (3D) and for the radial law (relative error O(s^2)).
+//       for P_B = s^2/4 (2D), s^2/6 (3D) and for the radial law (relative error O(s^2));
+//   R7  an SDF domain is {f < 0}; -f serves as the distance (a lower bound of the true
+//       one for unions, exact for single primitives and intersections) and the walk
+//       ends at x - f grad f.
 //
 // Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), key = (seed lo,
 // seed hi), counter = (block index, walk index, point index, problem index); each
 // uniform double takes 53 bits from two consecutive 32-bit words.
 //
-// Build: g++ -O2 -std=c++17 -fPIC -shared -pthread (see build_oracle.py).
+// Build: g++ -O2 -std=c++17 -fPIC -shared -pthread (oracle.py runs it).
 
 #include <atomic>
 #include <cmath>
@@ -121,7 +125,7 @@ double uniform(Stream* st) {  // [0, 1)
 
 enum { B_NONE = 0, B_FOURIER = 1, B_BUMPS = 2, B_TANH = 3, B_TANH_DRIFT = 4, B_MANUFACTURED = 5 };
 enum { T_AFFINE = 0, T_EXP = 1 };
-enum { G_BALL = 0, G_BOX = 1, G_POLYGON = 2, G_TRIMESH = 3 };
+enum { G_BALL = 0, G_BOX = 1, G_POLYGON = 2, G_TRIMESH = 3, G_SDF = 4 };
 enum { U_EXPCOS = 1, U_QUADRATIC = 2 };
 
 }  // namespace
@@ -423,11 +427,79 @@ void closest_on_triangle(const double* p, const double* a, const double* b, cons
   }
 }
 
-// Unsigned distance d and closest point xbar on the boundary (Alg. 1, first line),
-// by brute force over all primitives.
+// ------------------------------------------------------------------ CSG signed distance fields
+// Sec. 7.2 represents the domain by a list of CSG operations on signed distance fields.
+// Reading: rows (op, shape, c[3], p[3]); the field starts as the empty set (+inf) and each
+// row takes min (union), max (intersection) or max with the negated field (subtraction);
+// the domain is {f < 0}, the ball radius is -f and the exit point is x - f grad f, the
+// gradient being that of the row deciding f (the first on ties).
+
+// Signed distance of one primitive and its gradient.
+double sdf_primitive(const double* row, const double* x, int dim, double* grad) {
+  const int shape = (int)row[1];
+  const double* c = row + 2;
+  const double* p = row + 5;
+  if (shape == 0) {  // ball of radius p0 about c
+    double r = std::sqrt(dist2(x, c, dim));
+    for (int i = 0; i < dim; ++i) grad[i] = r > 0 ? (x[i] - c[i]) / r : (i == 0 ? 1.0 : 0.0);
+    return r - p[0];
+  }
+  if (shape == 1) {  // box c +- p: distance to the nearest point of the box (outside) or
+                     // minus the distance to the nearest face (inside)
+    double q[3], out = 0, far = -INFINITY;
+    int axis = 0;
+    for (int i = 0; i < dim; ++i) {
+      q[i] = std::fabs(x[i] - c[i]) - p[i];
+      if (q[i] > 0) out += q[i] * q[i];
+      if (q[i] > far) {
+        far = q[i];
+        axis = i;
+      }
+    }
+    const bool outside = out > 0;
+    out = std::sqrt(out);
+    for (int i = 0; i < dim; ++i) {
+      const double sg = x[i] >= c[i] ? 1.0 : -1.0;
+      grad[i] = outside ? (q[i] > 0 ? sg * q[i] / out : 0.0) : (i == axis ? sg : 0.0);
+    }
+    return outside ? out : far;
+  }
+  // half-space {x . n < p0} with n = c / |c|
+  double nn = std::sqrt(dot(c, c, dim));
+  for (int i = 0; i < dim; ++i) grad[i] = c[i] / nn;
+  return (dot(x, c, dim) - p[0]) / nn;
+}
+
+double sdf_field(const OGeom& g, const double* x, int dim, double* grad) {
+  double f = INFINITY, gk[3];
+  for (int64_t k = 0; k < g.n_vertices; ++k) {
+    const double* row = g.vertices + 8 * k;
+    const int op = (int)row[0];
+    double fk = sdf_primitive(row, x, dim, gk);
+    if (op == 2) {
+      fk = -fk;
+      for (int i = 0; i < dim; ++i) gk[i] = -gk[i];
+    }
+    const bool take = op == 0 ? fk < f : fk > f;
+    if (take) {
+      f = fk;
+      for (int i = 0; i < dim; ++i) grad[i] = gk[i];
+    }
+  }
+  return f;
+}
+
+// Distance d and closest point xbar on the boundary (Alg. 1, first line), by brute force
+// over all primitives (unsigned for explicit boundaries, -f for SDF domains).
 double distance_to_boundary(const OProblem& P, const double* x, double* xbar) {
   const OGeom& g = P.geom;
   const int dim = P.dim;
+  if (g.kind == G_SDF) {
+    double grad[3];
+    const double f = sdf_field(g, x, dim, grad);
+    for (int i = 0; i < dim; ++i) xbar[i] = x[i] - f * grad[i];
+    return -f;
+  }
   if (g.kind == G_BALL) {
     double v[3], r = 0;
     for (int i = 0; i < dim; ++i) {

@@ -192,6 +192,51 @@ wos_status build_geometry(const wos_problem_desc& d, HostGeometry& g) {
       if (!(G.hi[i] > G.lo[i])) return fail(WOS_ERR_GEOMETRY, "box needs lo < hi");
     return WOS_OK;
   }
+  if (G.kind == WOS_GEOM_SDF) {
+    // CSG operation list (Sec. 7.2), stored as it is given, with half-space normals made
+    // unit length so that every primitive field is a true signed distance
+    if (!G.vertices || G.n_vertices < 1 || G.n_vertices > WOS_SDF_MAX_OPS)
+      return fail(WOS_ERR_GEOMETRY, "SDF needs 1..WOS_SDF_MAX_OPS operation rows");
+    for (int i = 0; i < dim; ++i)
+      if (!(G.hi[i] > G.lo[i]) || !std::isfinite(G.lo[i]) || !std::isfinite(G.hi[i]))
+        return fail(WOS_ERR_GEOMETRY, "SDF needs a bounding box lo < hi");
+    const int64_t n = G.n_vertices;
+    g.n_prims = n;
+    g.prims64.assign((size_t)n * kSdfStride, 0.0);
+    for (int64_t j = 0; j < n; ++j) {
+      const double* r = G.vertices + kSdfStride * j;
+      for (int k = 0; k < kSdfStride; ++k)
+        if (!std::isfinite(r[k])) return fail(WOS_ERR_GEOMETRY, "non-finite SDF row");
+      const double op = r[0], shape = r[1];
+      if (!(op == 0 || op == 1 || op == 2)) return fail(WOS_ERR_GEOMETRY, "SDF op must be 0, 1 or 2");
+      if (j == 0 && op != 0) return fail(WOS_ERR_GEOMETRY, "the first SDF row must be a union");
+      double* o = g.prims64.data() + kSdfStride * j;
+      o[0] = op;
+      o[1] = shape;
+      for (int i = 0; i < dim; ++i) o[2 + i] = r[2 + i];
+      if (shape == 0) {
+        if (!(r[5] > 0)) return fail(WOS_ERR_GEOMETRY, "SDF ball radius must be > 0");
+        o[5] = r[5];
+      } else if (shape == 1) {
+        for (int i = 0; i < dim; ++i) {
+          if (!(r[5 + i] > 0)) return fail(WOS_ERR_GEOMETRY, "SDF box half extents must be > 0");
+          o[5 + i] = r[5 + i];
+        }
+      } else if (shape == 2) {
+        double nn = 0;
+        for (int i = 0; i < dim; ++i) nn += r[2 + i] * r[2 + i];
+        nn = std::sqrt(nn);
+        if (!(nn > 0)) return fail(WOS_ERR_GEOMETRY, "SDF half-space normal must be nonzero");
+        for (int i = 0; i < dim; ++i) o[2 + i] = r[2 + i] / nn;
+        o[5] = r[5] / nn;
+      } else {
+        return fail(WOS_ERR_GEOMETRY, "SDF shape must be 0, 1 or 2");
+      }
+    }
+    g.prims32.resize(g.prims64.size());
+    for (size_t k = 0; k < g.prims64.size(); ++k) g.prims32[k] = (float)g.prims64[k];
+    return WOS_OK;
+  }
   const int pdim = dim;
   int stride;
   std::vector<double> lo, hi, cen, raw;
@@ -491,7 +536,7 @@ wos_status wos_problem_create(const wos_problem_desc* desc, int device, wos_prob
   if (d.dim != 2 && d.dim != 3) return fail(WOS_ERR_INVALID_ARG, "dim must be 2 or 3");
   if (!(d.epsilon > 0) || !std::isfinite(d.epsilon)) return fail(WOS_ERR_INVALID_ARG, "epsilon must be > 0");
   if (std::isnan(d.sigma_bar)) return fail(WOS_ERR_INVALID_ARG, "sigma_bar is NaN");
-  if (d.geometry.kind < 0 || d.geometry.kind > 3) return fail(WOS_ERR_INVALID_ARG, "unknown geometry kind");
+  if (d.geometry.kind < 0 || d.geometry.kind > 4) return fail(WOS_ERR_INVALID_ARG, "unknown geometry kind");
   const char* names[5] = {"alpha", "psi", "sigma", "source", "boundary"};
   const wos_field_desc* fds[5] = {&d.alpha, &d.psi, &d.sigma, &d.source, &d.boundary};
   for (int k = 0; k < 5; ++k) {
@@ -546,7 +591,7 @@ wos_status wos_problem_create(const wos_problem_desc* desc, int device, wos_prob
       lo[i] = d.geometry.center[i] - d.geometry.radius;
       hi[i] = d.geometry.center[i] + d.geometry.radius;
     }
-  } else if (g.kind == WOS_GEOM_BOX) {
+  } else if (g.kind == WOS_GEOM_BOX || g.kind == WOS_GEOM_SDF) {
     for (int i = 0; i < d.dim; ++i) {
       lo[i] = d.geometry.lo[i];
       hi[i] = d.geometry.hi[i];

@@ -1208,6 +1208,95 @@ __device__ __forceinline__ int resolve_prim(G<DevGeometry<T>>& g, int prim) {
   return (prim >= 0 && (prim & kGridPrimTag)) ? gptr(g.cell_prim)[prim & (kGridPrimTag - 1)] : prim;
 }
 
+// ------------------------------------------------------------------ CSG signed distance fields
+// (Sec. 7.2: the domain as a list of CSG operations on signed distance fields). The rows
+// sit at wave-uniform addresses, so their loads are scalar; each lane evaluates every row.
+
+// Signed distance of one primitive at x; with GRAD also its gradient.
+template <typename T, int DIM, bool GRAD>
+__device__ __forceinline__ T sdf_shape(const WOS_GLOBAL T* r, const T* x, T* gr) {
+  const int shape = (int)r[1];
+  T e[DIM];
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) e[i] = x[i] - r[2 + i];
+  if (shape == 0) {
+    T r2 = 0;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) r2 = m_fma(e[i], e[i], r2);
+    const T len = m_sqrt(r2);
+    if constexpr (GRAD) {
+      const T inv = len > (T)0 ? (T)1 / len : (T)0;
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) gr[i] = len > (T)0 ? e[i] * inv : (i == 0 ? (T)1 : (T)0);
+    }
+    return len - r[5];
+  } else if (shape == 1) {
+    // |max(q, 0)| outside, max_i q_i inside, q = |x - c| - h
+    T q[DIM], out2 = 0, qmax = -Consts<T>::kInf;
+    int amax = 0;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+      q[i] = fabs(e[i]) - r[5 + i];
+      if (q[i] > (T)0) out2 = m_fma(q[i], q[i], out2);
+      if (q[i] > qmax) {
+        qmax = q[i];
+        amax = i;
+      }
+    }
+    if (out2 > (T)0) {
+      const T len = m_sqrt(out2);
+      if constexpr (GRAD) {
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) gr[i] = q[i] > (T)0 ? copysign(q[i] / len, e[i]) : (T)0;
+      }
+      return len;
+    }
+    if constexpr (GRAD) {
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) gr[i] = i == amax ? copysign((T)1, e[i]) : (T)0;
+    }
+    return qmax;
+  } else {
+    T f = -r[5];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) f = m_fma(x[i], r[2 + i], f);
+    if constexpr (GRAD) {
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) gr[i] = r[2 + i];
+    }
+    return f;
+  }
+}
+
+// Combined field f of the operation list (from f = +inf: union min, intersection max,
+// subtraction max(f, -f_k)); *active = 2 k + (row k entered negated) for the row that
+// decides f (the first one on ties).
+template <typename T, int DIM>
+__device__ __forceinline__ T sdf_value(G<DevGeometry<T>>& g, const T* x, int* active) {
+  const WOS_GLOBAL T* rows = gptr(g.prims);
+  T f = Consts<T>::kInf;
+  int act = 0;
+  for (int k = 0; k < g.n_prims; ++k) {
+    const WOS_GLOBAL T* r = rows + (size_t)k * kSdfStride;
+    const int op = (int)r[0];
+    T fk = sdf_shape<T, DIM, false>(r, x, nullptr);
+    if (op == 0) {
+      if (fk < f) {
+        f = fk;
+        act = 2 * k;
+      }
+    } else {
+      if (op == 2) fk = -fk;
+      if (fk > f) {
+        f = fk;
+        act = 2 * k + (op == 2 ? 1 : 0);
+      }
+    }
+  }
+  *active = act;
+  return f;
+}
+
 // Distance d from x to the boundary (Alg. 1, first step); prim receives what
 // closest_point needs to recover xbar.
 template <typename T, int DIM, int GEOM, bool COUNT = false>
@@ -1233,6 +1322,9 @@ __device__ __forceinline__ T boundary_distance(G<DevGeometry<T>>& g, const T* x,
     }
     *prim = best;
     return d;
+  } else if (GEOM == GK_SDF) {
+    if constexpr (COUNT) tally->prims += g.n_prims;
+    return -sdf_value<T, DIM>(g, x, prim);
   } else {
     if constexpr (GEOM == GK_POLYGON) {
       if (g.grid_nx > 0) {
@@ -1309,6 +1401,12 @@ __device__ __forceinline__ void closest_point(G<DevGeometry<T>>& g, const T* x, 
     const int ax = prim >> 1;
 #pragma unroll
     for (int i = 0; i < DIM; ++i) xb[i] = i == ax ? ((prim & 1) ? g.hi[i] : g.lo[i]) : x[i];
+  } else if (GEOM == GK_SDF) {
+    // x - f grad f with the deciding row's field; a negated row flips both factors
+    T gr[DIM];
+    const T fk = sdf_shape<T, DIM, true>(gptr(g.prims) + (size_t)(prim >> 1) * kSdfStride, x, gr);
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) xb[i] = m_fma(-fk, gr[i], x[i]);
   } else if (DIM == 2) {
     const WOS_GLOBAL T* s = gptr(g.prims) + (size_t)prim * kPrimStride2;
     T t;

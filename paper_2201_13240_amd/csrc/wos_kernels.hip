@@ -691,6 +691,9 @@ __device__ bool inside_point(G<DevGeometry<double>>& g, const double* x) {
     for (int i = 0; i < DIM; ++i)
       if (!(x[i] > g.lo[i] && x[i] < g.hi[i])) return false;
     return true;
+  } else if (GEOM == GK_SDF) {
+    int act;
+    return sdf_value<double, DIM>(g, x, &act) < 0.0;
   } else if (GEOM == GK_POLYGON) {
     // even-odd crossing count of a horizontal ray
     bool in = false;
@@ -969,6 +972,7 @@ static hipError_t launch_walker_dim(const WalkerLaunch& L, hipStream_t st) {
       case GK_BALL: return launch_walker_t<T, 2, GK_BALL>(L, st);
       case GK_BOX: return launch_walker_t<T, 2, GK_BOX>(L, st);
       case GK_POLYGON: return launch_walker_t<T, 2, GK_POLYGON>(L, st);
+      case GK_SDF: return launch_walker_t<T, 2, GK_SDF>(L, st);
       default: return hipErrorInvalidValue;
     }
   }
@@ -976,6 +980,7 @@ static hipError_t launch_walker_dim(const WalkerLaunch& L, hipStream_t st) {
     case GK_BALL: return launch_walker_t<T, 3, GK_BALL>(L, st);
     case GK_BOX: return launch_walker_t<T, 3, GK_BOX>(L, st);
     case GK_TRIMESH: return launch_walker_t<T, 3, GK_TRIMESH>(L, st);
+    case GK_SDF: return launch_walker_t<T, 3, GK_SDF>(L, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -996,9 +1001,11 @@ static const void* walker_symbol_dim(int dim, int geom, int nf) {
   if (dim == 2)
     return geom == GK_BALL ? walker_symbol_t<T, 2, GK_BALL>(nf)
            : geom == GK_BOX ? walker_symbol_t<T, 2, GK_BOX>(nf)
+           : geom == GK_SDF ? walker_symbol_t<T, 2, GK_SDF>(nf)
                             : walker_symbol_t<T, 2, GK_POLYGON>(nf);
   return geom == GK_BALL ? walker_symbol_t<T, 3, GK_BALL>(nf)
          : geom == GK_BOX ? walker_symbol_t<T, 3, GK_BOX>(nf)
+         : geom == GK_SDF ? walker_symbol_t<T, 3, GK_SDF>(nf)
                           : walker_symbol_t<T, 3, GK_TRIMESH>(nf);
 }
 
@@ -1054,6 +1061,7 @@ hipError_t launch_classify(int dim, int geom, const void* P64, const double* pts
       case GK_BALL: return classify_t<2, GK_BALL>(P64, pts, n, inside, counters, st);
       case GK_BOX: return classify_t<2, GK_BOX>(P64, pts, n, inside, counters, st);
       case GK_POLYGON: return classify_t<2, GK_POLYGON>(P64, pts, n, inside, counters, st);
+      case GK_SDF: return classify_t<2, GK_SDF>(P64, pts, n, inside, counters, st);
       default: return hipErrorInvalidValue;
     }
   }
@@ -1061,6 +1069,7 @@ hipError_t launch_classify(int dim, int geom, const void* P64, const double* pts
     case GK_BALL: return classify_t<3, GK_BALL>(P64, pts, n, inside, counters, st);
     case GK_BOX: return classify_t<3, GK_BOX>(P64, pts, n, inside, counters, st);
     case GK_TRIMESH: return classify_t<3, GK_TRIMESH>(P64, pts, n, inside, counters, st);
+    case GK_SDF: return classify_t<3, GK_SDF>(P64, pts, n, inside, counters, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1080,6 +1089,7 @@ hipError_t launch_sigma_sample(int dim, int geom, const void* P64, const double*
       case GK_BALL: return sigma_t<2, GK_BALL>(P64, lo, h, grid, nblocks, out, st);
       case GK_BOX: return sigma_t<2, GK_BOX>(P64, lo, h, grid, nblocks, out, st);
       case GK_POLYGON: return sigma_t<2, GK_POLYGON>(P64, lo, h, grid, nblocks, out, st);
+      case GK_SDF: return sigma_t<2, GK_SDF>(P64, lo, h, grid, nblocks, out, st);
       default: return hipErrorInvalidValue;
     }
   }
@@ -1087,6 +1097,7 @@ hipError_t launch_sigma_sample(int dim, int geom, const void* P64, const double*
     case GK_BALL: return sigma_t<3, GK_BALL>(P64, lo, h, grid, nblocks, out, st);
     case GK_BOX: return sigma_t<3, GK_BOX>(P64, lo, h, grid, nblocks, out, st);
     case GK_TRIMESH: return sigma_t<3, GK_TRIMESH>(P64, lo, h, grid, nblocks, out, st);
+    case GK_SDF: return sigma_t<3, GK_SDF>(P64, lo, h, grid, nblocks, out, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1113,10 +1124,12 @@ static hipError_t distance_t(int dim, int geom, const void* P, const double* pts
   if (dim == 2) {
     if (geom == GK_BALL) hipLaunchKernelGGL((distance_kernel<T, 2, GK_BALL>), g, b, 0, st, p, pts, n, d, xb);
     else if (geom == GK_BOX) hipLaunchKernelGGL((distance_kernel<T, 2, GK_BOX>), g, b, 0, st, p, pts, n, d, xb);
+    else if (geom == GK_SDF) hipLaunchKernelGGL((distance_kernel<T, 2, GK_SDF>), g, b, 0, st, p, pts, n, d, xb);
     else hipLaunchKernelGGL((distance_kernel<T, 2, GK_POLYGON>), g, b, 0, st, p, pts, n, d, xb);
   } else {
     if (geom == GK_BALL) hipLaunchKernelGGL((distance_kernel<T, 3, GK_BALL>), g, b, 0, st, p, pts, n, d, xb);
     else if (geom == GK_BOX) hipLaunchKernelGGL((distance_kernel<T, 3, GK_BOX>), g, b, 0, st, p, pts, n, d, xb);
+    else if (geom == GK_SDF) hipLaunchKernelGGL((distance_kernel<T, 3, GK_SDF>), g, b, 0, st, p, pts, n, d, xb);
     else hipLaunchKernelGGL((distance_kernel<T, 3, GK_TRIMESH>), g, b, 0, st, p, pts, n, d, xb);
   }
   return hipGetLastError();

@@ -6,7 +6,10 @@ namespace wos {
 
 enum FieldBase : int32_t { FB_NONE = 0, FB_FOURIER = 1, FB_BUMPS = 2, FB_TANH = 3, FB_TANH_DRIFT = 4, FB_MANUFACTURED = 5 };
 enum FieldTransform : int32_t { FT_AFFINE = 0, FT_EXP = 1 };
-enum GeomKind : int32_t { GK_BALL = 0, GK_BOX = 1, GK_POLYGON = 2, GK_TRIMESH = 3 };
+enum GeomKind : int32_t { GK_BALL = 0, GK_BOX = 1, GK_POLYGON = 2, GK_TRIMESH = 3, GK_SDF = 4 };
+// CSG row of an SDF domain: op (0 union, 1 intersection, 2 subtraction), shape (0 ball,
+// 1 box, 2 half-space), c[3], p[3]; half-space normals are stored unit length.
+constexpr int kSdfStride = 8;
 enum SolutionId : int32_t { SOL_EXPCOS = 1, SOL_QUADRATIC = 2 };
 
 // Six numbers per term, in the precision of the walker:
@@ -61,7 +64,8 @@ struct DevGeometry {
   T lo[3];
   T hi[3];
   const void* nodes;     // BvhNode<T, DIM>[n_nodes]
-  const T* prims;        // polygon: [n][4] (x0, y0, x1, y1); trimesh: [n][12] (a, b, c, padding)
+  const T* prims;        // polygon: [n][4] (x0, y0, x1, y1); trimesh: [n][12] (a, b, c, padding);
+                         // SDF: [n][kSdfStride] CSG rows
   // 2D polygons: uniform candidate grid (grid_nx = 0: none). Cell (i, j) covers
   // [grid_lo + (i, j) h, grid_lo + (i + 1, j + 1) h]; its candidates are
   // cell_prim[cell_start[c] .. cell_start[c + 1]) with their segments copied to cell_segs,

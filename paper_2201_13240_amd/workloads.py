@@ -149,6 +149,53 @@ def geom_trimesh(vertices, triangles, star=None):
     return g
 
 
+SDF_UNION, SDF_INTERSECT, SDF_SUBTRACT = 0, 1, 2
+
+
+def sdf_row(op, shape, center, params):
+    """One CSG row (op, shape, c0, c1, c2, p0, p1, p2): shape "ball" (params = [radius]),
+    "box" (half extents) or "halfspace" (center holds the normal n, params = [offset];
+    the inside is x.n < offset)."""
+    r = np.zeros(8)
+    r[0] = op
+    r[1] = {"ball": 0, "box": 1, "halfspace": 2}[shape]
+    c = np.asarray(center, np.float64)
+    r[2:2 + c.size] = c
+    p = np.asarray(params, np.float64)
+    r[5:5 + p.size] = p
+    return r
+
+
+def geom_sdf(rows, lo, hi):
+    """Domain given by a list of CSG rows on signed distance fields (Sec. 7.2); lo/hi is
+    a box holding the domain."""
+    return {"kind": "sdf", "rows": np.ascontiguousarray(np.asarray(rows, np.float64).reshape(-1, 8)),
+            "lo": np.asarray(lo, np.float64), "hi": np.asarray(hi, np.float64)}
+
+
+def _sdf_member(rows, pts):
+    """Set membership of the CSG list by boolean set operations on the primitives'
+    interiors (harness helper for sampling query points)."""
+    dim = pts.shape[1]
+    inside = np.zeros(pts.shape[0], bool)
+    for r in rows:
+        op, shape = int(r[0]), int(r[1])
+        c = r[2:2 + dim]
+        if shape == 0:
+            m = ((pts - c) ** 2).sum(1) < r[5] ** 2
+        elif shape == 1:
+            m = np.all(np.abs(pts - c) < r[5:5 + dim], axis=1)
+        else:
+            m = pts @ c < r[5]
+        if op == SDF_UNION:
+            inside |= m
+        elif op == SDF_INTERSECT:
+            inside &= m
+        else:
+            inside &= ~m
+    return inside
+
+
 def star_polygon(rng, n_edges=256, n_modes=8, amp=0.3):
     """Vertices at theta_j = 2*pi*j/n, radius 1 + amp*P(theta_j) with P a sum of
     n_modes Fourier modes (N(0,1) coefficients) scaled so max_j |P(theta_j)| = 1."""
@@ -289,6 +336,8 @@ def inside_mask(geometry, pts):
         if geometry.get("star", False):
             return _star_polygon_inside(geometry["vertices"], pts)
         return _polygon_inside_crossing(geometry["vertices"], pts)
+    if k == "sdf":
+        return _sdf_member(geometry["rows"], pts)
     if k == "trimesh":
         if "star_dirs" not in geometry:
             raise ValueError("inside_mask: only star-shaped meshes are supported")
@@ -301,7 +350,7 @@ def _bbox(geometry, dim):
     if k == "ball":
         c, r = geometry["center"], geometry["radius"]
         return c - r, c + r
-    if k == "box":
+    if k in ("box", "sdf"):
         return geometry["lo"], geometry["hi"]
     V = geometry["vertices"]
     return V.min(0), V.max(0)

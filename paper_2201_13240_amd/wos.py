@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwos.so")
 
 WOS_FP32, WOS_FP32_COMPENSATED, WOS_FP64 = 0, 1, 2
-_GEOM = {"ball": 0, "box": 1, "polygon": 2, "trimesh": 3}
+_GEOM = {"ball": 0, "box": 1, "polygon": 2, "trimesh": 3, "sdf": 4}
 _BASE = {"none": 0, "fourier": 1, "bumps": 2, "tanh": 3, "tanh_drift": 4, "manufactured": 5}
 _TRANSFORM = {"affine": 0, "exp": 1}
 _SOLUTION = {"expcos": 1, "quadratic": 2}
@@ -158,6 +158,15 @@ class Problem:
                 G.center[i] = v
             G.radius = g["radius"]
         elif g["kind"] == "box":
+            for i in range(len(g["lo"])):
+                G.lo[i] = g["lo"][i]
+                G.hi[i] = g["hi"][i]
+        elif g["kind"] == "sdf":
+            V = self._arr(g["rows"])
+            if V.ndim != 2 or V.shape[1] != 8:
+                raise ValueError("SDF rows must be [n][8]")
+            G.vertices = V.ctypes.data_as(C.POINTER(C.c_double))
+            G.n_vertices = V.shape[0]
             for i in range(len(g["lo"])):
                 G.lo[i] = g["lo"][i]
                 G.hi[i] = g["hi"][i]

@@ -77,6 +77,29 @@ def test_invalid_descriptors_are_rejected(W):
     assert _create(W, p) == 2                      # triangle index out of range
 
 
+def test_invalid_sdf_programs_are_rejected(W):
+    from paper_2201_13240_amd import workloads as WL
+    c = WL.field_const(1.0)
+    ball = WL.sdf_row(WL.SDF_UNION, "ball", [0, 0], [1.0])
+
+    def prob(rows, lo=(-1, -1), hi=(1, 1)):
+        return WL.make_problem(2, WL.geom_sdf(rows, lo, hi), c, c, c, c, c)
+
+    first_not_union = ball.copy()
+    first_not_union[0] = WL.SDF_INTERSECT
+    bad_op, bad_shape, bad_radius = ball.copy(), ball.copy(), ball.copy()
+    bad_op[0], bad_shape[1], bad_radius[5] = 3, 7, 0.0
+    bad_box = WL.sdf_row(WL.SDF_UNION, "box", [0, 0], [1.0, 0.0])
+    zero_normal = WL.sdf_row(WL.SDF_INTERSECT, "halfspace", [0, 0], [0.5])
+    for rows in ([first_not_union], [ball, bad_op], [bad_shape], [bad_radius], [bad_box], [ball, zero_normal],
+                 [ball] * 257, np.zeros((0, 8))):
+        assert _create(W, prob(rows)) == 2
+    assert _create(W, prob([ball], lo=(1, -1), hi=(1, 1))) == 2   # empty bounding box
+    nan = ball.copy()
+    nan[2] = np.nan
+    assert _create(W, prob([nan])) == 2
+
+
 def test_solve_rejects_bad_batches_without_device(W):
     o = W.options(walks=0)
     assert W.lib().wos_solve(None, 0, C.byref(o), None) == 1
