@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--no-events", action="store_true")
     ap.add_argument("--variants", type=int, default=1,
                     help="also time next flight against delta tracking on the high-contrast square (0: skip)")
+    ap.add_argument("--extras", type=int, default=1,
+                    help="also time gradients, weight-window splitting and an SDF/CSG scene (0: skip)")
     ap.add_argument("--shape", default="auto",
                     help="walker launch shape: 'auto' (the plan autotunes block size and tile length) or "
                          "BLOCKxTILE, e.g. 256x256 (profiling runs pin the tuned shape so that no tuning "
@@ -310,6 +312,82 @@ def compare_variants(wos, WL, args):
     return out
 
 
+def _timed_plan(wos, torch, prob_handle, P, opt_kw, walks, reps, grad_dim=0):
+    """Creates a plan of one item, warms it up, then times `reps` graph replays with HIP
+    events on the current stream; returns timings and the accumulated statistics."""
+    n = P.shape[0]
+    acc = wos.Accumulators(n, grad_dim=grad_dim)
+    plan = wos.Plan([(prob_handle, P, acc, 0)], wos.options(walks=walks, seed=0, **opt_kw))
+    plan.launch(seed=999)
+    torch.cuda.synchronize()
+    for t in (acc.sum, acc.sum_sq, acc.n_walks, acc.n_steps, acc.counters, acc.grad_sum, acc.grad_sum_sq):
+        if t is not None:
+            t.zero_()
+    ms = []
+    for k in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        plan.launch(seed=k, walk_offset_add=k * walks)
+        b.record()
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    mean, se = wos.finalize(acc)
+    torch.cuda.synchronize()
+    nw = float(acc.n_walks[0].item())
+    steps = float(acc.n_steps.sum().item())
+    var = float(np.mean((se.cpu().numpy() ** 2) * nw))
+    info = plan.info()
+    plan.close()
+    t_walk = (np.mean(ms) / 1e3) / walks
+    return {"ms_per_pass": float(np.mean(ms)), "steps_per_s": steps / (sum(ms) / 1e3),
+            "distance_queries_per_walk": steps / (nw * n), "per_walk_variance": var,
+            "points_per_s_at_rmse_1e-2": n / ((var / 1e-4) * t_walk), "plan": info}
+
+
+def measure_extras(wos, WL):
+    """Throughput of the rows beyond the plain delta-tracking walk, FP32, each against the
+    plain walk on the same workload: gradients (supplemental Sec. 2) on the star polygon;
+    weight-window splitting (Sec. 6) on the manufactured disk, where sigma' < 0 lets
+    null-collision weights grow; an SDF/CSG scene (Sec. 7.2)."""
+    import torch
+    out = {}
+    # gradient estimates: the star-polygon workload at 256 walks per point
+    c = WL.config2(n_grid=512)
+    prob, pts = c["problems"][0], c["points"][0]
+    h = wos.Problem(prob)
+    P = torch.as_tensor(pts, dtype=torch.float64, device="cuda")
+    plain = _timed_plan(wos, torch, h, P, {"precision": "fp32"}, 256, 3)
+    grad = _timed_plan(wos, torch, h, P, {"precision": "fp32"}, 256, 3, grad_dim=2)
+    out["gradient"] = {"workload": "star polygon 256 edges, 512x512 grid inside, 256 walks per point",
+                       "plain_ms_per_pass": plain["ms_per_pass"], "gradient_ms_per_pass": grad["ms_per_pass"],
+                       "overhead": grad["ms_per_pass"] / plain["ms_per_pass"] - 1.0}
+    print(f"bench: gradient overhead {out['gradient']['overhead']:.3f}", file=sys.stderr, flush=True)
+    del P
+    # splitting: manufactured disk on a 256x256 grid, window [0.5, 1.5]
+    c = WL.config1(n_grid=256)
+    prob, pts = c["problems"][0], c["points"][0]
+    h = wos.Problem(prob)
+    P = torch.as_tensor(pts, dtype=torch.float64, device="cuda")
+    rr = _timed_plan(wos, torch, h, P, {"precision": "fp32", "russian_roulette": True, "ww_lo": 0.5}, 256, 3)
+    sp = _timed_plan(wos, torch, h, P, {"precision": "fp32", "russian_roulette": True, "ww_lo": 0.5,
+                                        "ww_hi": 1.5}, 256, 3)
+    out["splitting"] = {"workload": "manufactured disk, 256x256 grid inside, sigma_bar %.4g, 256 walks per point"
+                                    % h.sigma_bar, "roulette_only": rr, "roulette_and_splitting": sp}
+    print("bench: splitting pts/s at RMSE 1e-2 %.3e (roulette only %.3e)"
+          % (sp["points_per_s_at_rmse_1e-2"], rr["points_per_s_at_rmse_1e-2"]), file=sys.stderr, flush=True)
+    del P
+    # SDF/CSG scene
+    c = WL.config6(n_grid=256)
+    prob, pts = c["problems"][0], c["points"][0]
+    h = wos.Problem(prob)
+    P = torch.as_tensor(pts, dtype=torch.float64, device="cuda")
+    sdf = _timed_plan(wos, torch, h, P, {"precision": "fp32"}, 256, 3)
+    out["sdf"] = {"workload": "square with 24 round and 8 box holes (33 CSG rows), star-polygon fields, "
+                              "256x256 grid inside, 256 walks per point", "query_points": int(P.shape[0]), **sdf}
+    print(f"bench: sdf steps/s {sdf['steps_per_s']:.3e}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     args = parse()
     if args.summarize_trace:
@@ -479,6 +557,8 @@ def main():
     line.update(out64)
     if args.variants:
         line["next_flight_vs_delta_tracking"] = compare_variants(wos, WL, args)
+    if args.extras:
+        line["extras"] = measure_extras(wos, WL)
     print(json.dumps(line), flush=True)
 
 

@@ -470,8 +470,15 @@ size_t layout_problem(Blob& blob, const wos_problem_desc& d, const HostGeometry&
           std::memset(&r, 0, sizeof(r));
           r.start = g.grid.start[c];
           r.count = g.grid.start[c + 1] - g.grid.start[c];
-          for (uint32_t k = 0; k < std::min<uint32_t>(r.count, kCellInline); ++k)
-            for (int q = 0; q < 4; ++q) r.seg[k][q] = prims[(size_t)g.grid.prim[r.start + k] * 4 + q];
+          for (uint32_t k = 0; k < std::min<uint32_t>(r.count, kCellInline); ++k) {
+            const double* sg = g.prims64.data() + (size_t)g.grid.prim[r.start + k] * 4;
+            r.seg[k][0] = (T)sg[0];
+            r.seg[k][1] = (T)sg[1];
+            r.seg[k][2] = (T)(sg[2] - sg[0]);
+            r.seg[k][3] = (T)(sg[3] - sg[1]);
+            const double ex = (double)r.seg[k][2], ey = (double)r.seg[k][3], l2 = ex * ex + ey * ey;
+            r.inv_len2[k] = l2 > 0 ? (T)(1.0 / l2) : (T)0;
+          }
           cells[c] = r;
         }
         grid_prim_off = blob.alloc(std::max<size_t>(nc, 1) * sizeof(int32_t));

@@ -993,6 +993,16 @@ __device__ __forceinline__ T segment_dist2(const T* x, PT s, T* tpar) {
   return m_fma(dx, dx, dy * dy);
 }
 
+// The same for a segment given as start point, edge vector and 1/|e|^2 (0 for a point).
+template <typename T, typename PT>
+__device__ __forceinline__ T segment_dist2_pre(const T* x, PT s, T inv_len2) {
+  const T px = x[0] - s[0], py = x[1] - s[1];
+  T t = m_fma(px, s[2], py * s[3]) * inv_len2;
+  t = fmin(fmax(t, (T)0), (T)1);
+  const T dx = m_fma(-t, s[2], px), dy = m_fma(-t, s[3], py);
+  return m_fma(dx, dx, dy * dy);
+}
+
 // Closest point of triangle (a, b, c) = (tri[0..2], tri[3..5], tri[6..8]) to p, by the
 // Voronoi regions of its vertices, edges and face (Ericson, Real-Time Collision
 // Detection, Sec. 5.1.5).
@@ -1342,8 +1352,7 @@ __device__ __forceinline__ T boundary_distance(G<DevGeometry<T>>& g, const T* x,
             uint32_t bk = 0;
 #pragma unroll
             for (int k = 0; k < kCellInline; ++k) {
-              T tp;
-              const T d2 = segment_dist2<T>(x, rec->seg[k], &tp);
+              const T d2 = segment_dist2_pre<T>(x, rec->seg[k], rec->inv_len2[k]);
               if ((uint32_t)k < n && d2 < best) {
                 best = d2;
                 bk = (uint32_t)k;

@@ -35,13 +35,16 @@ struct DevField {
 constexpr int kCellInline = 5;
 
 // One cell of the polygon candidate grid: `count` candidates at cell_prim / cell_segs /
-// cell_dc [start, start + count), the first kCellInline also copied here (zero-padded).
+// cell_dc [start, start + count), the first kCellInline also held here (zero-padded) as
+// start point, edge vector and reciprocal squared length (x0, y0, ex, ey), 1/|e|^2, so
+// that their distance needs no division.
 template <typename T>
 struct __attribute__((aligned(16))) CellRec {
   uint32_t count;
   uint32_t start;
   uint32_t pad[2];
   T seg[kCellInline][4];
+  T inv_len2[kCellInline];
 };
 
 template <typename T, int DIM>

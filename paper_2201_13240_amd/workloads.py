@@ -391,7 +391,8 @@ def config1(n_grid=32):
 
 
 def _polygon_problem(rng, geometry, n_alpha=16, n_psi=16, n_sigma=16, drift=True):
-    lo, hi = geometry["vertices"].min(0), geometry["vertices"].max(0)
+    lo, hi = _bbox(geometry, 2)
+    lo, hi = np.asarray(lo, np.float64), np.asarray(hi, np.float64)
     k, a, phi = random_fourier(rng, n_alpha, 2, 0.5)
     alpha = field_fourier(k, a, phi, transform="exp")
     if drift:
@@ -460,6 +461,30 @@ def config4(n_problems=64, points_scale=1.0, min_edges=16, max_edges=4096,
         problems.append(_polygon_problem(rng, geometry))
         points.append(sample_inside(rng, geometry, 2, Q))
     return {"name": "batched-64-polygons", "problems": problems, "points": points, "walks": 512}
+
+
+def csg_scatter(rng, n_disks=24, n_boxes=8):
+    """CSG list of a square [-1, 1]^2 with n_disks round and n_boxes rectangular holes
+    scattered at uniform positions (radii U(0.03, 0.1), half sides U(0.03, 0.08)), in
+    the manner of Sec. 7.2's edited SDF scenes."""
+    rows = [sdf_row(SDF_UNION, "box", [0.0, 0.0], [1.0, 1.0])]
+    for _ in range(n_disks):
+        rows.append(sdf_row(SDF_SUBTRACT, "ball", rng.uniform(-0.9, 0.9, 2), [rng.uniform(0.03, 0.1)]))
+    for _ in range(n_boxes):
+        rows.append(sdf_row(SDF_SUBTRACT, "box", rng.uniform(-0.9, 0.9, 2), rng.uniform(0.03, 0.08, 2)))
+    return geom_sdf(rows, [-1.0, -1.0], [1.0, 1.0])
+
+
+def config6(n_grid=256):
+    """CSG scene (csg_scatter: square with 24 round and 8 rectangular holes) with the star
+    polygon's kind of fields (alpha = exp(16 modes), drift |omega| <= 1, sigma in [0, 10],
+    8-bump f and g); n_grid^2 grid on [-1, 1]^2 inside; 256 walks."""
+    rng = np.random.default_rng(6000)
+    geometry = csg_scatter(rng)
+    prob = _polygon_problem(rng, geometry)
+    pts = grid_points(n_grid, -1.0, 1.0)
+    pts = pts[inside_mask(geometry, pts)]
+    return {"name": "csg-scatter-32", "problems": [prob], "points": [pts], "walks": 256}
 
 
 def config5(n_grid=256):
