@@ -264,7 +264,9 @@ def compare_variants(wos, WL, args):
     short steps. Both FP32 at the same walks per point, one captured plan each; reports
     pass time, distance queries per walk, per-walk variance, points per second at RMSE
     1e-2 from that variance, and how far the two means are apart in combined standard
-    errors (next flight's off-centred kernel approximations are biased off the centre)."""
+    errors. On this problem sigma' < 0 in places and R sqrt(sigma_bar) is large, where
+    next flight's in-ball series has no finite variance, so only its time and distance
+    queries compare directly."""
     import torch
     c = WL.config5()
     prob, pts = c["problems"][0], c["points"][0]

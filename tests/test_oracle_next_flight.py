@@ -272,3 +272,25 @@ def test_gradient_kernels_match_derivatives_of_the_exact_series(oracle, dim, sb)
             assert fd == pytest.approx(ratio_g[i] * green(0 * e, y), rel=1e-5, abs=1e-7)
             fd = (poisson(e, z) - poisson(-e, z)) / (2 * h)
             assert fd == pytest.approx(ratio_p[i] * poisson(0 * e, z), rel=1e-5, abs=1e-7)
+
+
+def test_next_flight_with_exact_kernels_variable_coefficients(oracle):
+    """Variable coefficients inside every ball (alpha = 1 + 0.02 sin sin, drift potential
+    psi = sin(pi x / 2), so gamma varies by about 1 across the disk and sigma' in about
+    [1.1, 5.1]) at a small s = R sqrt(sigma_bar) (< 2.5, where the throughput has finite
+    variance): with the exact off-centred kernels the walk reproduces the manufactured
+    u = e^x cos y. This pins the gamma weights of the boundary and source terms and the
+    sigma' of the throughput for varying coefficients."""
+    alpha = WL.field_fourier([[1.0, -1.0], [1.0, 1.0]], [0.01, -0.01], [0.0, 0.0], transform="affine",
+                             c0=1.0, c1=1.0)
+    psi = WL.field_fourier([[0.25, 0.0]], [1.0], [-math.pi / 2])
+    prob = WL.make_problem(2, WL.geom_ball([0.0, 0.0], 1.0), alpha, psi, WL.field_const(3.0),
+                           WL.field_manufactured("expcos"), WL.field_manufactured("expcos"), 1e-4)
+    g = WL.grid_points(256, -1.0, 1.0)
+    mn, mx = oracle.sigma_prime_range(prob, g[WL.inside_mask(prob["geometry"], g)])
+    assert 1.0 < mn and mx < 6.0
+    pts = np.array([[0.0, 0.0], [0.3, -0.4], [-0.6, 0.5], [0.5, 0.5]])
+    exact = np.exp(pts[:, 0]) * np.cos(pts[:, 1])
+    o = oracle.solve(prob, pts, 10000, mx, seed=5, variant=3)
+    z = (o["mean"] - exact) / o["se"]
+    assert np.all(np.abs(z) < 4), z
