@@ -32,6 +32,10 @@ def parse():
     ap.add_argument("--grid", type=int, default=512)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp32c", "fp64"])
     ap.add_argument("--fp64-steps", type=int, default=1, help="timed passes of the FP64 walker")
+    ap.add_argument("--fp32c-steps", type=int, default=1,
+                    help="timed passes of the FP32 walker with compensated per-walk sums")
+    ap.add_argument("--ttr", type=int, default=1,
+                    help="also measure time to RMSE 1e-2 by doubling walks per point (0: skip)")
     ap.add_argument("--cpu-points", type=int, default=96, help="oracle sample size (0: skip)")
     ap.add_argument("--cpu-walks", type=int, default=8192)
     ap.add_argument("--no-events", action="store_true")
@@ -337,13 +341,31 @@ def _timed_plan(wos, torch, prob_handle, P, opt_kw, walks, reps, grad_dim=0):
     torch.cuda.synchronize()
     nw = float(acc.n_walks[0].item())
     steps = float(acc.n_steps.sum().item())
-    var = float(np.mean((se.cpu().numpy() ** 2) * nw))
+    se_np = se.cpu().numpy()
+    var = float(np.mean((se_np ** 2) * nw))
     info = plan.info()
     plan.close()
     t_walk = (np.mean(ms) / 1e3) / walks
     return {"ms_per_pass": float(np.mean(ms)), "steps_per_s": steps / (sum(ms) / 1e3),
             "distance_queries_per_walk": steps / (nw * n), "per_walk_variance": var,
-            "points_per_s_at_rmse_1e-2": n / ((var / 1e-4) * t_walk), "plan": info}
+            "points_per_s_at_rmse_1e-2": n / ((var / 1e-4) * t_walk), "plan": info,
+            "_mean": mean.cpu().numpy(), "_se": se_np}
+
+
+def time_to_rmse(wos, torch, prob_handle, P, ref_idx, ref_mean, ref_se, precision, max_walks=65536):
+    """Doubles the walks per point from 64 until the RMSE against the reference at the
+    reference points is at most 1e-2 (RMSE^2 = mean squared difference minus the mean
+    squared standard error of the reference); returns that run's walks, RMSE and graph
+    replay time, and query points per second over all points."""
+    walks = 64
+    while True:
+        r = _timed_plan(wos, torch, prob_handle, P, {"precision": precision}, walks, 1)
+        d2 = float(np.mean((r["_mean"][ref_idx] - ref_mean) ** 2) - np.mean(np.asarray(ref_se) ** 2))
+        rmse = math.sqrt(max(d2, 0.0))
+        if rmse <= 1e-2 or walks >= max_walks:
+            return {"walks": walks, "rmse": rmse, "ms": r["ms_per_pass"],
+                    "points_per_s": P.shape[0] / (r["ms_per_pass"] / 1e3), "reached": rmse <= 1e-2}
+        walks *= 2
 
 
 def measure_extras(wos, WL):
@@ -373,6 +395,9 @@ def measure_extras(wos, WL):
     rr = _timed_plan(wos, torch, h, P, {"precision": "fp32", "russian_roulette": True, "ww_lo": 0.5}, 256, 3)
     sp = _timed_plan(wos, torch, h, P, {"precision": "fp32", "russian_roulette": True, "ww_lo": 0.5,
                                         "ww_hi": 1.5}, 256, 3)
+    for r in (rr, sp):
+        r.pop("_mean")
+        r.pop("_se")
     out["splitting"] = {"workload": "manufactured disk, 256x256 grid inside, sigma_bar %.4g, 256 walks per point"
                                     % h.sigma_bar, "roulette_only": rr, "roulette_and_splitting": sp}
     print("bench: splitting pts/s at RMSE 1e-2 %.3e (roulette only %.3e)"
@@ -384,6 +409,8 @@ def measure_extras(wos, WL):
     h = wos.Problem(prob)
     P = torch.as_tensor(pts, dtype=torch.float64, device="cuda")
     sdf = _timed_plan(wos, torch, h, P, {"precision": "fp32"}, 256, 3)
+    sdf.pop("_mean")
+    sdf.pop("_se")
     out["sdf"] = {"workload": "square with 24 round and 8 box holes (33 CSG rows), star-polygon fields, "
                               "256x256 grid inside, 256 walks per point", "query_points": int(P.shape[0]), **sdf}
     print(f"bench: sdf steps/s {sdf['steps_per_s']:.3e}", file=sys.stderr, flush=True)
@@ -491,6 +518,7 @@ def main():
                 "flops_per_step": flops_per_step, "transcendentals_per_step": trans_per_step,
                 "events_per_step": {k: v / events["steps"] for k, v in events.items()}}
     r64 = run("fp64", args.fp64_steps, 0, args.walks) if args.fp64_steps > 0 else None
+    r32c = run("fp32c", args.fp32c_steps, 0, args.walks) if args.fp32c_steps > 0 else None
     ms_step = float(np.mean(r32["ms"]))
     steps_per_s = r32["steps"] / (sum(r32["ms"]) / 1e3)
     walks_per_pt = args.walks * args.steps
@@ -508,6 +536,9 @@ def main():
         n64 = float(np.mean(var64)) / 1e-4
         out64 = {"fp64_steps_per_s": s64, "fp64_ms_per_step": float(np.mean(r64["ms"])),
                  "fp64_points_per_s_at_rmse_1e-2": n_pts / (n64 * t64)}
+    if r32c is not None:
+        out64.update({"fp32c_steps_per_s": r32c["steps"] / (sum(r32c["ms"]) / 1e3),
+                      "fp32c_ms_per_step": float(np.mean(r32c["ms"]))})
 
     # CPU baseline: the FP64 oracle on a bounded sample of the same workload; its
     # estimates are the reference for the RMSE of the GPU walkers at those points.
@@ -524,12 +555,29 @@ def main():
                "kind": "oracle",
                "sample": f"{args.cpu_points} random query points x {args.cpu_walks} walks of the same workload, "
                          f"{dt:.1f} s"}
-        for name, r in (("fp32", r32), ("fp64", r64)):
+        for name, r in (("fp32", r32), ("fp32c", r32c), ("fp64", r64)):
             if r is None:
                 continue
             d2 = (r["mean"][idx] - o["mean"]) ** 2 - o["se"] ** 2
             rmse[name] = {"rmse_vs_oracle": float(math.sqrt(max(np.mean(d2), 0.0))),
                           "mean_se_gpu": float(np.mean(r["se"][idx])), "mean_se_oracle": float(np.mean(o["se"]))}
+
+    # time to RMSE 1e-2, walks doubled from 64: on this workload against the oracle's
+    # sample, and on the manufactured disk against its exact solution u = e^x cos y
+    ttr = {}
+    if args.ttr:
+        if args.cpu_points > 0:
+            ttr["star_polygon_vs_oracle_sample"] = {
+                prec: time_to_rmse(wos, torch, h, P, idx, o["mean"], o["se"], prec) for prec in ("fp32", "fp32c", "fp64")}
+        c1 = WL.config1()
+        h1 = wos.Problem(c1["problems"][0])
+        p1 = c1["points"][0]
+        P1 = torch.as_tensor(p1, dtype=torch.float64, device="cuda")
+        ex = np.exp(p1[:, 0]) * np.cos(p1[:, 1])
+        all1 = np.arange(p1.shape[0])
+        ttr["manufactured_disk_vs_exact"] = {
+            prec: time_to_rmse(wos, torch, h1, P1, all1, ex, np.zeros_like(ex), prec) for prec in ("fp32", "fp32c", "fp64")}
+        print("bench: time to RMSE 1e-2 " + json.dumps(ttr), file=sys.stderr, flush=True)
 
     line = {
         "metric": "walk steps/s and query pts/s at RMSE 1e-2 vs FP64 oracle (FP32 vs FP64 GPU)",
@@ -555,6 +603,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "rmse": rmse,
+        "time_to_rmse_1e-2": ttr,
     }
     line.update(out64)
     if args.variants:
