@@ -403,17 +403,17 @@ size_t layout_problem(Blob& blob, const wos_problem_desc& d, const HostGeometry&
       }
     }
     if (eligible && modes >= 12) {
-      P.spectral = eligible;
+      // complex coefficients per slot, in double
+      double re[3][kSpecK + 1][kSpecRow] = {}, im[3][kSpecK + 1][kSpecRow] = {}, c[3] = {0, 0, 0};
       for (int sidx = 0; sidx < 3; ++sidx) {
         if (!(eligible & (1 << sidx))) continue;
         const wos_field_desc& f = *slots[sidx];
-        double re[kSpecK + 1][kSpecRow] = {}, im[kSpecK + 1][kSpecRow] = {}, c = 0;
         for (int j = 0; j < f.n_terms; ++j) {
           int kx = (int)f.terms[j * 4], ky = (int)f.terms[j * 4 + 1];
           const double a = f.terms[j * 4 + 2], phi = f.terms[j * 4 + 3];
           double cr = a * std::cos(phi), ci = a * std::sin(phi);
           if (kx == 0 && ky == 0) {
-            c += cr;
+            c[sidx] += cr;
             continue;
           }
           if (kx < 0 || (kx == 0 && ky < 0)) {  // cos is even: use -k and the conjugate
@@ -421,15 +421,46 @@ size_t layout_problem(Blob& blob, const wos_problem_desc& d, const HostGeometry&
             ky = -ky;
             ci = -ci;
           }
-          re[kx][ky + kSpecK] += cr;
-          im[kx][ky + kSpecK] += ci;
+          re[sidx][kx][ky + kSpecK] += cr;
+          im[sidx][kx][ky + kSpecK] += ci;
         }
+      }
+      // With alpha = exp(c0 + c1 B_alpha) and an affine (or absent) psi, gamma =
+      // (ln alpha + psi)/2 is itself a trigonometric sum: slot 0 then holds gamma (the
+      // only slot whose derivatives are needed) and slot 1 the base of alpha.
+      const bool psi_none = d.psi.base == WOS_FIELD_NONE && d.psi.transform == WOS_TRANSFORM_AFFINE;
+      const bool merge = (eligible & 1) && d.alpha.transform == WOS_TRANSFORM_EXP &&
+                         (psi_none || ((eligible & 2) && d.psi.transform == WOS_TRANSFORM_AFFINE));
+      P.spectral = eligible;
+      if (merge) {
+        const double a0 = d.alpha.c0, a1 = d.alpha.c1;
+        const double p0 = d.psi.c0, p1 = psi_none ? 0.0 : d.psi.c1;
+        double gre[kSpecK + 1][kSpecRow], gim[kSpecK + 1][kSpecRow];
         for (int kx = 0; kx <= kSpecK; ++kx)
           for (int j = 0; j < kSpecRow; ++j) {
-            P.spec.row[kx][sidx][2 * j] = (T)re[kx][j];
-            P.spec.row[kx][sidx][2 * j + 1] = (T)im[kx][j];
+            gre[kx][j] = 0.5 * (a1 * re[0][kx][j] + p1 * re[1][kx][j]);
+            gim[kx][j] = 0.5 * (a1 * im[0][kx][j] + p1 * im[1][kx][j]);
           }
-        P.spec.c[sidx] = (T)c;
+        const double gc = 0.5 * (a0 + a1 * c[0] + p0 + p1 * c[1]);
+        for (int kx = 0; kx <= kSpecK; ++kx)
+          for (int j = 0; j < kSpecRow; ++j) {
+            re[1][kx][j] = re[0][kx][j];
+            im[1][kx][j] = im[0][kx][j];
+            re[0][kx][j] = gre[kx][j];
+            im[0][kx][j] = gim[kx][j];
+          }
+        c[1] = c[0];
+        c[0] = gc;
+        P.spectral = eligible | 1 | 2 | kSpecGammaMerged;
+      }
+      for (int sidx = 0; sidx < 3; ++sidx) {
+        if (!(P.spectral & (1 << sidx))) continue;
+        for (int kx = 0; kx <= kSpecK; ++kx)
+          for (int j = 0; j < kSpecRow; ++j) {
+            P.spec.row[kx][sidx][2 * j] = (T)re[sidx][kx][j];
+            P.spec.row[kx][sidx][2 * j + 1] = (T)im[sidx][kx][j];
+          }
+        P.spec.c[sidx] = (T)c[sidx];
       }
     }
   }

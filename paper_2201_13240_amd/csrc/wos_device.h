@@ -738,11 +738,28 @@ __device__ __forceinline__ FV<T, DIM> field_base(G<DevField<T>>& f, const T* x) 
   return r;
 }
 
-// Bases of the Fourier fields of a 2D problem from the dense table (slots 0, 1, 2 =
-// alpha, psi, sigma), with gradient and Laplacian for slots 0 and 1 when D is true.
-// e^{2 pi i k.x} comes from the powers of e^{2 pi i x} and e^{2 pi i y} (two sincos
-// calls per point instead of one per mode), all loops unrolled at compile time.
-template <typename T, bool D>
+// Bases of the Fourier fields of a 2D problem from the dense table (slots 0, 1, 2), with
+// gradient and Laplacian for the first ND slots when D is true. e^{2 pi i k.x} comes from
+// the powers of e^{2 pi i x} and e^{2 pi i y} (two sincos calls per point instead of one
+// per mode and field).
+template <typename T, bool D, int ND>
+__device__ __forceinline__ void spectral_terms(const WOS_GLOBAL T* row, T er, T ei, T fx, T fy, T f2,
+                                               FV<T, 2>* out, int j) {
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const T cr = row[s * 2 * kSpecRow + 2 * j], ci = row[s * 2 * kSpecRow + 2 * j + 1];
+    const T re = m_fma(cr, er, -ci * ei);
+    out[s].v += re;
+    if (D && s < ND) {
+      const T im = m_fma(cr, ei, ci * er);
+      out[s].g[0] = m_fma(-im, fx, out[s].g[0]);
+      out[s].g[1] = m_fma(-im, fy, out[s].g[1]);
+      out[s].lap = m_fma(-re, f2, out[s].lap);
+    }
+  }
+}
+
+template <typename T, bool D, int ND = 2>
 __device__ __forceinline__ void spectral2d(G<Spectral2D<T>>& sp, const T* x, FV<T, 2>* out) {
   // e^{2 pi i ky y} for ky = -K .. K from the powers of e^{2 pi i y}
   T c1, s1, yr[kSpecRow], yi[kSpecRow];
@@ -765,33 +782,28 @@ __device__ __forceinline__ void spectral2d(G<Spectral2D<T>>& sp, const T* x, FV<
     out[s].lap = 0;
   }
   constexpr T kTwoPi = (T)6.283185307179586476925286766559;
+  // kx = 0: only ky > 0 is stored, and e^{2 pi i k.x} = e^{2 pi i ky y}
+#pragma unroll
+  for (int j = kSpecK + 1; j < kSpecRow; ++j) {
+    const T fy = kTwoPi * (T)(j - kSpecK);
+    spectral_terms<T, D, ND>(&sp.row[0][0][0], yr[j], yi[j], (T)0, fy, fy * fy, out, j);
+  }
   T cx1, sx1;
   m_sincospi2(x[0], &sx1, &cx1);
-  T exr = 1, exi = 0;   // e^{2 pi i kx x}
+  T exr = cx1, exi = sx1;   // e^{2 pi i kx x}
   // one row of wave vectors per pass: the loop is kept rolled so that only one row of
   // coefficients (wave-uniform, scalar loads) is live at a time
 #pragma unroll 1
-  for (int kx = 0; kx <= kSpecK; ++kx) {
+  for (int kx = 1; kx <= kSpecK; ++kx) {
     const WOS_GLOBAL T* row = &sp.row[kx][0][0];
     const T fx = kTwoPi * (T)kx;
     const T fx2 = fx * fx;
 #pragma unroll
     for (int j = 0; j < kSpecRow; ++j) {
-      const int ky = j - kSpecK;
+      const T fy = kTwoPi * (T)(j - kSpecK);
       const T er = exr * yr[j] - exi * yi[j];
       const T ei = m_fma(exr, yi[j], exi * yr[j]);
-#pragma unroll
-      for (int s = 0; s < 3; ++s) {
-        const T cr = row[s * 2 * kSpecRow + 2 * j], ci = row[s * 2 * kSpecRow + 2 * j + 1];
-        const T re = m_fma(cr, er, -ci * ei);
-        out[s].v += re;
-        if (D && s < 2) {
-          const T im = m_fma(cr, ei, ci * er);
-          out[s].g[0] = m_fma(-im, fx, out[s].g[0]);
-          out[s].g[1] = m_fma(-im, kTwoPi * (T)ky, out[s].g[1]);
-          out[s].lap = m_fma(-re, fx2 + kTwoPi * kTwoPi * (T)(ky * ky), out[s].lap);
-        }
-      }
+      spectral_terms<T, D, ND>(row, er, ei, fx, fy, m_fma(fy, fy, fx2), out, j);
     }
     const T t = exr * cx1 - exi * sx1;
     exi = m_fma(exr, sx1, exi * cx1);
@@ -882,8 +894,23 @@ __device__ __forceinline__ void coefficient_bases(G<DevProblem<T>>& P, const T* 
   if (!(sp & 4)) b[2] = field_base<T, DIM, false>(P.sigma, x);
 }
 
-template <typename T, int DIM, bool WITH_SOURCE>
-__device__ __forceinline__ PointCoef<T> point_coef(G<DevProblem<T>>& P, const T* x, T* grad_gamma = nullptr) {
+// gamma with its gradient and Laplacian, alpha, 1/alpha and sigma at x.
+template <typename T, int DIM>
+__device__ __forceinline__ void gamma_alpha_sigma(G<DevProblem<T>>& P, const T* x, FV<T, DIM>& gam, T& alpha,
+                                                  T& inv_alpha, T& sigma) {
+  if constexpr (DIM == 2) {
+    if (P.spectral & kSpecGammaMerged) {
+      // the table holds gamma itself (slot 0) and the base of alpha = exp(c0 + c1 B) (slot 1)
+      FV<T, 2> b[3];
+      spectral2d<T, true, 1>(P.spec, x, b);
+      gam = b[0];
+      alpha = m_exp(m_fma(P.alpha.c1, b[1].v, P.alpha.c0));
+      inv_alpha = m_rcp(alpha);
+      if (!(P.spectral & 4)) b[2] = field_base<T, 2, false>(P.sigma, x);
+      sigma = field_transform<T, 2, false>(P.sigma, b[2]).v;
+      return;
+    }
+  }
   FV<T, DIM> base[3];
   coefficient_bases<T, DIM, true>(P, x, base);
   // ln alpha with its gradient and Laplacian: grad ln a = grad a / a,
@@ -899,32 +926,39 @@ __device__ __forceinline__ PointCoef<T> point_coef(G<DevProblem<T>>& P, const T*
     ga2 = m_fma(gl[i], gl[i], ga2);
   }
   const T lapl = m_fma(al.lap, inv_al, -ga2);
-  T gg[DIM], lapg;
-  T gamma;
   if (P.psi.base == FB_NONE && P.psi.transform == FT_AFFINE) {
-    gamma = (T)0.5 * (lnal + P.psi.c0);
+    gam.v = (T)0.5 * (lnal + P.psi.c0);
 #pragma unroll
-    for (int i = 0; i < DIM; ++i) gg[i] = (T)0.5 * gl[i];
-    lapg = (T)0.5 * lapl;
+    for (int i = 0; i < DIM; ++i) gam.g[i] = (T)0.5 * gl[i];
+    gam.lap = (T)0.5 * lapl;
   } else {
     const FV<T, DIM> ps = field_transform<T, DIM, true>(P.psi, base[1]);
-    gamma = (T)0.5 * (lnal + ps.v);
+    gam.v = (T)0.5 * (lnal + ps.v);
 #pragma unroll
-    for (int i = 0; i < DIM; ++i) gg[i] = (T)0.5 * (gl[i] + ps.g[i]);
-    lapg = (T)0.5 * (lapl + ps.lap);
+    for (int i = 0; i < DIM; ++i) gam.g[i] = (T)0.5 * (gl[i] + ps.g[i]);
+    gam.lap = (T)0.5 * (lapl + ps.lap);
   }
+  alpha = al.v;
+  inv_alpha = inv_al;
+  sigma = field_transform<T, DIM, false>(P.sigma, base[2]).v;
+}
+
+template <typename T, int DIM, bool WITH_SOURCE>
+__device__ __forceinline__ PointCoef<T> point_coef(G<DevProblem<T>>& P, const T* x, T* grad_gamma = nullptr) {
+  FV<T, DIM> gam;
+  T alpha, inv_al, sig;
+  gamma_alpha_sigma<T, DIM>(P, x, gam, alpha, inv_al, sig);
   T g2 = 0;
 #pragma unroll
-  for (int i = 0; i < DIM; ++i) g2 = m_fma(gg[i], gg[i], g2);
+  for (int i = 0; i < DIM; ++i) g2 = m_fma(gam.g[i], gam.g[i], g2);
   if (grad_gamma) {
 #pragma unroll
-    for (int i = 0; i < DIM; ++i) grad_gamma[i] = gg[i];
+    for (int i = 0; i < DIM; ++i) grad_gamma[i] = gam.g[i];
   }
-  const T sig = field_transform<T, DIM, false>(P.sigma, base[2]).v;
   PointCoef<T> c;
-  c.gamma = gamma;
-  c.alpha = al.v;
-  c.sigma_prime = m_fma(sig, inv_al, lapg + g2);
+  c.gamma = gam.v;
+  c.alpha = alpha;
+  c.sigma_prime = m_fma(sig, inv_al, gam.lap + g2);
   c.f_over_alpha = 0;
   if (WITH_SOURCE) {
     if (P.source.base == FB_MANUFACTURED) {
@@ -932,7 +966,7 @@ __device__ __forceinline__ PointCoef<T> point_coef(G<DevProblem<T>>& P, const T*
       const FV<T, DIM> u = solution<T, DIM>(P.source.sol, x);
       T gu = 0;
 #pragma unroll
-      for (int i = 0; i < DIM; ++i) gu = m_fma(gg[i], u.g[i], gu);
+      for (int i = 0; i < DIM; ++i) gu = m_fma(gam.g[i], u.g[i], gu);
       c.f_over_alpha = -(u.lap + (T)2 * gu) + sig * inv_al * u.v;
     } else {
       c.f_over_alpha = field_eval<T, DIM, false>(P.source, x).v * inv_al;
@@ -955,6 +989,7 @@ __device__ __forceinline__ T point_gamma(G<DevProblem<T>>& P, const T* x) {
   if (DIM == 2 && P.spectral) {
     FV<T, DIM> base[3];
     if constexpr (DIM == 2) spectral2d<T, false>(P.spec, x, base);
+    if (P.spectral & kSpecGammaMerged) return base[0].v;
     if (!(P.spectral & 1)) base[0] = field_base<T, DIM, false>(P.alpha, x);
     if (has_psi && !(P.spectral & 2)) base[1] = field_base<T, DIM, false>(P.psi, x);
     const FV<T, DIM> al = field_transform<T, DIM, false>(P.alpha, base[0], &lnal);

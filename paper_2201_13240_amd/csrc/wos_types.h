@@ -92,6 +92,7 @@ struct DevGeometry {
 // that B(x) = const + sum_k Re(C_k e^{2 pi i k.x}). A mode a cos(2 pi k.x + phi) adds
 // a e^{i phi} at k, or a e^{-i phi} at -k when k is in the other half plane.
 constexpr int kSpecK = 3;
+constexpr int kSpecGammaMerged = 8;
 constexpr int kSpecRow = 2 * kSpecK + 1;   // ky = -kSpecK .. kSpecK
 
 // row[kx][slot][2 j], row[kx][slot][2 j + 1]: real and imaginary part of C_k for
@@ -105,7 +106,8 @@ struct Spectral2D {
 template <typename T>
 struct DevProblem {
   int32_t dim;
-  int32_t spectral;        // bit s set: field slot s (alpha, psi, sigma) is in `spec`
+  int32_t spectral;        // bit s set: field slot s (alpha, psi, sigma) is in `spec`; with
+                           // kSpecGammaMerged, slot 0 holds gamma and slot 1 the base of alpha
   DevGeometry<T> geom;
   DevField<T> alpha, psi, sigma, source, boundary;
   T epsilon;
