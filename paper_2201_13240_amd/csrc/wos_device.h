@@ -194,7 +194,8 @@ template <> struct BesselTerms<double> {
                        kK1Mid = WOS_K1E_MID_N64, kK1Tail = WOS_K1E_TAIL_N64;
 };
 
-// Power series of I0 and K0 for small x (x <= 2 for I0, x <= 1 for K0):
+// Power series of I0 and K0 for x <= 2 (for K0 near x = 2 the two parts cancel to about a
+// tenth, which costs FP32 a few units in the last place):
 //   I0(x) - 1 = sum_{k>=1} q^k/(k!)^2,  q = x^2/4
 //   K0(x) = -(ln(x/2) + gamma_E) I0(x) + sum_{k>=1} q^k/(k!)^2 H_k
 template <typename T>
@@ -306,12 +307,7 @@ __device__ __forceinline__ Ball<T, DIM> ball_terms(T R, T s, T inv_sigma_bar, bo
   if (DIM == 2) {
     if (s < (T)2) {
       T i0m1, k0;
-      if (s <= (T)1) {
-        bessel_series<T>(s, &i0m1, &k0);
-      } else {
-        bessel_series<T>(s, &i0m1, nullptr);
-        k0 = bessel_k0e<T>(s) * m_exp(-s);
-      }
+      bessel_series<T>(s, &i0m1, &k0);
       const T i0 = (T)1 + i0m1;
       const T ii0 = m_rcp(i0);
       b.pb = i0m1 * ii0;
@@ -558,14 +554,9 @@ __device__ __forceinline__ T radius_trial(const Rng& rng, T s, const Ball<T, DIM
     if (s < (T)2) {
       // harmonic proposal t = sqrt(U1 U2), accept with G^s/G^0
       const T t = m_sqrt(u1 * u2);
-      const T x = t * s;
+      const T x = t * s;   // < 2: the series holds for K0 too (one code path for the wave)
       T i0m1, k0;
-      if (x <= (T)1) {
-        bessel_series<T>(x, &i0m1, &k0);
-      } else {
-        bessel_series<T>(x, &i0m1, nullptr);
-        k0 = bessel_k0e<T>(x) * m_exp(-x);
-      }
+      bessel_series<T>(x, &i0m1, &k0);
       const T g = k0 - b.c2d * ((T)1 + i0m1);
       return u3 * -m_log(t) <= g ? t : (T)-1;
     }
