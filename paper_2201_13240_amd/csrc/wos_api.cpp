@@ -874,8 +874,8 @@ wos_status pick_shape(const wos_options* opt, Schedule& s) {
 
 // Per-launch tables: item copies with walks/walk_offset of this chunk, and tiles.
 void build_tables(const wos_batch_item* items, int n_items, const wos_options* opt, const Schedule& s,
-                  uint64_t w0, uint64_t nw, const std::vector<int8_t*>& inside, std::vector<DevItem>& dit,
-                  std::vector<Tile>& tiles) {
+                  uint64_t w0, uint64_t nw, const std::vector<int8_t*>& inside, const std::vector<void*>& gamma0,
+                  std::vector<DevItem>& dit, std::vector<Tile>& tiles) {
   dit.resize(n_items);
   tiles.clear();
   uint64_t wbase = 0, pbase = 0;
@@ -886,6 +886,7 @@ void build_tables(const wos_batch_item* items, int n_items, const wos_options* o
     d.problem = s.fp64 ? it.problem->d64() : it.problem->d32();
     d.points = it.points;
     d.inside = inside[k];
+    d.gamma0 = gamma0[k];
     d.sum = it.sum;
     d.sum_sq = it.sum_sq;
     d.n_walks = it.n_walks;
@@ -914,6 +915,7 @@ void build_tables(const wos_batch_item* items, int n_items, const wos_options* o
 
 struct Workspace {
   int8_t* inside = nullptr;
+  unsigned char* gamma0 = nullptr;  // [total points] gamma(x0), walker precision
   DevItem* items = nullptr;       // [n_launches][n_items]
   Tile* tiles = nullptr;          // [n_launches][max tiles]
   uint32_t* counter = nullptr;
@@ -943,7 +945,7 @@ __attribute__((unused)) size_t align_up(size_t v) { return (v + 255) / 256 * 256
 
 // Builds every launch's tables; returns the byte layout of the workspace.
 struct WsLayout {
-  size_t inside, items, tiles, counter, lp, records, grad, total;
+  size_t inside, gamma0, items, tiles, counter, lp, records, grad, total;
 };
 
 WsLayout ws_layout(const Schedule& s, int n_items, size_t max_tiles) {
@@ -956,6 +958,7 @@ WsLayout ws_layout(const Schedule& s, int n_items, size_t max_tiles) {
   };
   const uint64_t ids = s.total_points * s.chunk_walks;
   L.inside = take(std::max<uint64_t>(s.total_points, 1));
+  L.gamma0 = take(std::max<uint64_t>(s.total_points, 1) * (s.fp64 ? 8 : 4));
   L.items = take(sizeof(DevItem) * (size_t)n_items * s.n_launches);
   L.tiles = take(sizeof(Tile) * std::max<size_t>(max_tiles, 1) * s.n_launches);
   L.counter = take(sizeof(uint32_t) * 64);
@@ -969,6 +972,7 @@ WsLayout ws_layout(const Schedule& s, int n_items, size_t max_tiles) {
 void ws_bind(Workspace& w, void* base, const WsLayout& L) {
   unsigned char* b = (unsigned char*)base;
   w.inside = (int8_t*)(b + L.inside);
+  w.gamma0 = b + L.gamma0;
   w.items = (DevItem*)(b + L.items);
   w.tiles = (Tile*)(b + L.tiles);
   w.counter = (uint32_t*)(b + L.counter);
@@ -981,9 +985,11 @@ void ws_bind(Workspace& w, void* base, const WsLayout& L) {
 void prepare(const wos_batch_item* items, int n_items, const wos_options* opt, const Schedule& s,
              const Workspace& w, std::vector<std::vector<DevItem>>& dit, std::vector<std::vector<Tile>>& tiles) {
   std::vector<int8_t*> inside(n_items);
+  std::vector<void*> gamma0(n_items);
   uint64_t pb = 0;
   for (int k = 0; k < n_items; ++k) {
     inside[k] = w.inside + pb;
+    gamma0[k] = w.gamma0 + pb * (s.fp64 ? 8 : 4);
     pb += (uint64_t)items[k].n_points;
   }
   dit.resize(s.n_launches);
@@ -991,7 +997,7 @@ void prepare(const wos_batch_item* items, int n_items, const wos_options* opt, c
   for (int c = 0; c < s.n_launches; ++c) {
     const uint64_t w0 = (uint64_t)c * s.chunk_walks;
     const uint64_t nw = std::min(s.chunk_walks, opt->walks_per_point - w0);
-    build_tables(items, n_items, opt, s, w0, nw, inside, dit[c], tiles[c]);
+    build_tables(items, n_items, opt, s, w0, nw, inside, gamma0, dit[c], tiles[c]);
   }
 }
 
@@ -1027,6 +1033,24 @@ WalkerLaunch walker_launch(const wos_options* opt, const Schedule& s, const Work
   return L;
 }
 
+// Classifies every query point (FP64) and evaluates gamma at the interior ones in the
+// walker's precision.
+hipError_t classify_items(const wos_batch_item* items, int n_items, const Schedule& s, const Workspace& w,
+                          hipStream_t st) {
+  uint64_t pb = 0;
+  for (int k = 0; k < n_items; ++k) {
+    const wos_batch_item& it = items[k];
+    hipError_t e = launch_classify(s.dim, s.geom, it.problem->d64(), it.points, it.n_points, w.inside + pb,
+                                   it.counters, st);
+    if (e == hipSuccess)
+      e = launch_gamma0(s.fp64, s.dim, s.fp64 ? it.problem->d64() : it.problem->d32(), it.points, it.n_points,
+                        w.inside + pb, w.gamma0 + pb * (s.fp64 ? 8 : 4), st);
+    if (e != hipSuccess) return e;
+    pb += (uint64_t)it.n_points;
+  }
+  return hipSuccess;
+}
+
 // Enqueues [reset, walker, reduce per item] for every launch of the schedule. With
 // `marks`, an event pair is recorded around each walker launch (eager timing only: a
 // captured job takes none).
@@ -1034,14 +1058,7 @@ wos_status enqueue_job(const wos_batch_item* items, int n_items, const wos_optio
                        const Workspace& w, const std::vector<std::vector<DevItem>>& dit,
                        const std::vector<uint32_t>& n_tiles, size_t max_tiles, bool classify, uint64_t* events,
                        hipStream_t st, const std::vector<hipEvent_t>* marks = nullptr) {
-  if (classify) {
-    uint64_t pb = 0;
-    for (int k = 0; k < n_items; ++k) {
-      WOS_HIP(launch_classify(s.dim, s.geom, items[k].problem->d64(), items[k].points, items[k].n_points,
-                              w.inside + pb, items[k].counters, st));
-      pb += (uint64_t)items[k].n_points;
-    }
-  }
+  if (classify) WOS_HIP(classify_items(items, n_items, s, w, st));
   for (int c = 0; c < s.n_launches; ++c) {
     if (n_tiles[c] == 0) continue;
     WOS_HIP(launch_reset(w.counter, st));
@@ -1185,14 +1202,9 @@ wos_status plan_build(const wos_batch_item* items, int32_t n_items, const wos_op
     return fail(code, m);
   };
   if ((r = upload_tables(s, n_items, P->ws, P->dit, tiles, max_tiles, st)) != WOS_OK) return bail(r, g_error);
-  // classification once, outside the graph
-  uint64_t pb = 0;
-  for (int k = 0; k < n_items; ++k) {
-    if ((e = launch_classify(s.dim, s.geom, items[k].problem->d64(), items[k].points, items[k].n_points,
-                             P->ws.inside + pb, items[k].counters, st)) != hipSuccess)
-      return bail(WOS_ERR_DEVICE, "classification launch failed");
-    pb += (uint64_t)items[k].n_points;
-  }
+  // classification and gamma(x0) once, outside the graph
+  if ((e = classify_items(items, n_items, s, P->ws, st)) != hipSuccess)
+    return bail(WOS_ERR_DEVICE, "classification launch failed");
   // capture reset + walker + reduce of every launch on a private stream
   hipStream_t cap;
   if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) return bail(WOS_ERR_DEVICE, "stream creation failed");

@@ -224,11 +224,16 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
           last_prim = -1;
           pending = false;
           split_state = 0;
-          phase = 1;
-          if constexpr (COUNT) {
-            ++ev[EV_GAMMA];
-            ++ev[EV_WALKS];
+          if (EXTRA && a.grad) {
+            phase = 1;   // gamma(x0) with its gradient, for the gradient record
+            if constexpr (COUNT) ++ev[EV_GAMMA];
+          } else {
+            gamma0 = gptr((const WOS_GLOBAL T*)it.gamma0)[p];
+            gx = gamma0;
+            gx_known = true;
+            phase = 2;
           }
+          if constexpr (COUNT) ++ev[EV_WALKS];
         }
       }
       res_next += take;
@@ -817,6 +822,21 @@ __global__ void coef_kernel(const DevProblem<T>* P, const double* pts, int64_t n
   o[5] = boundary_value<T, DIM>(PR, x);
 }
 
+// gamma(x0) of every interior query point: the same for all walks of a point, so each
+// walk starts from it instead of spending an iteration of the walker on it.
+template <typename T, int DIM>
+__global__ void gamma0_kernel(const DevProblem<T>* P, const double* pts, int64_t n, const int8_t* inside, T* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T g = 0;
+  if (inside[i]) {
+    T x[DIM];
+    for (int k = 0; k < DIM; ++k) x[k] = (T)pts[i * DIM + k];
+    g = point_gamma<T, DIM>(*gptr(P), x);
+  }
+  out[i] = g;
+}
+
 template <typename T, int DIM, int GEOM>
 __global__ void distance_kernel(const DevProblem<T>* P, const double* pts, int64_t n, double* d, double* xb) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1100,6 +1120,24 @@ hipError_t launch_sigma_sample(int dim, int geom, const void* P64, const double*
     case GK_SDF: return sigma_t<3, GK_SDF>(P64, lo, h, grid, nblocks, out, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_gamma0(int fp64, int dim, const void* P, const double* pts, int64_t n, const int8_t* inside,
+                         void* out, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const dim3 g(blocks_for(n, 256)), b(256);
+  if (fp64) {
+    if (dim == 2)
+      hipLaunchKernelGGL((gamma0_kernel<double, 2>), g, b, 0, st, (const DevProblem<double>*)P, pts, n, inside, (double*)out);
+    else
+      hipLaunchKernelGGL((gamma0_kernel<double, 3>), g, b, 0, st, (const DevProblem<double>*)P, pts, n, inside, (double*)out);
+  } else {
+    if (dim == 2)
+      hipLaunchKernelGGL((gamma0_kernel<float, 2>), g, b, 0, st, (const DevProblem<float>*)P, pts, n, inside, (float*)out);
+    else
+      hipLaunchKernelGGL((gamma0_kernel<float, 3>), g, b, 0, st, (const DevProblem<float>*)P, pts, n, inside, (float*)out);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_coefficients(int fp64, int dim, const void* P, const double* pts, int64_t n, double* out,

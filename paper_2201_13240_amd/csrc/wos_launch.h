@@ -45,6 +45,8 @@ hipError_t launch_classify(int dim, int geom, const void* P64, const double* pts
                            uint64_t* counters, hipStream_t st);
 hipError_t launch_sigma_sample(int dim, int geom, const void* P64, const double* lo, const double* h, int grid,
                                int nblocks, double* out, hipStream_t st);
+hipError_t launch_gamma0(int fp64, int dim, const void* P, const double* pts, int64_t n, const int8_t* inside,
+                         void* out, hipStream_t st);
 hipError_t launch_coefficients(int fp64, int dim, const void* P, const double* pts, int64_t n, double* out,
                                hipStream_t st);
 hipError_t launch_distance(int fp64, int dim, int geom, const void* P, const double* pts, int64_t n, double* d,

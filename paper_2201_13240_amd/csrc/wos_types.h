@@ -136,6 +136,7 @@ struct DevItem {
   uint32_t pad;
   double* grad_sum;          // [n_points][dim] or null
   double* grad_sum_sq;
+  const void* gamma0;        // [n_points] gamma at each interior query point, walker precision
 };
 
 // A contiguous range of walk ids of one item; waves take whole tiles.
