@@ -494,14 +494,17 @@ def main():
 
     r32 = run(args.precision, args.steps, args.warmup, args.walks)
 
-    # algorithmic work per distance query from the event-counting walker on a sample of
-    # the same workload (every 8th query point, 64 walks each)
+    # algorithmic work per distance query and lane occupancy from the event-counting
+    # walker over one full pass of the same workload (same shape as the timed plan)
     if args.no_events:
         events = {k: 1 for k in wos.EVENT_NAMES}   # profiling runs: no event-counting launch
     else:
-        sub = P[::8].contiguous()
-        acc_c = wos.Accumulators(sub.shape[0])
-        events = wos.count_events([(h, sub, acc_c, 0)], wos.options(precision=args.precision, walks=64, seed=99))
+        acc_c = wos.Accumulators(n_pts)
+        events = wos.count_events([(h, P, acc_c, 0)],
+                                  wos.options(precision=args.precision, walks=args.walks, seed=99,
+                                              block_size=r32["plan"]["block_size"],
+                                              tile_walks=r32["plan"]["tile_walks"]))
+        del acc_c
     flops_ev, trans_ev = algorithmic_work(events, prob)
     flops_per_step = flops_ev / events["steps"]
     trans_per_step = trans_ev / events["steps"]
@@ -517,6 +520,10 @@ def main():
                 "kernel": walker_kernel_name(args.precision), "kernel_ms": walker_ms,
                 "flops_per_step": flops_per_step, "transcendentals_per_step": trans_per_step,
                 "events_per_step": {k: v / events["steps"] for k, v in events.items()}}
+    if not args.no_events:
+        # lane occupancy of the walker's lockstep iterations (event-counting build)
+        roofline["lanes_holding_a_walk"] = events["active_lane_iterations"] / events["lane_iterations"]
+        roofline["lanes_evaluating_coefficients"] = events["coefficient_lane_iterations"] / events["lane_iterations"]
     r64 = run("fp64", args.fp64_steps, 0, args.walks) if args.fp64_steps > 0 else None
     r32c = run("fp32c", args.fp32c_steps, 0, args.walks) if args.fp32c_steps > 0 else None
     ms_step = float(np.mean(r32["ms"]))

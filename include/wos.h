@@ -248,13 +248,14 @@ wos_status wos_solve(const wos_batch_item* items, int32_t n_items, const wos_opt
 
 /* Runs the same walks as wos_solve (same outputs, accumulated the same way) with the
  * event-counting build of the walker, and adds per-launch totals into `events` (device
- * uint64 [13]): [0] distance queries, [1] BVH inner nodes visited, [2] primitives whose
+ * uint64 [16]): [0] distance queries, [1] BVH inner nodes visited, [2] primitives whose
  * distance was computed, [3] radius proposals, [4] of which from the free-space law,
  * [5] volume (null-collision) events, [6] exit events, [7] epsilon-shell terminations,
  * [8] gamma-only evaluations, [9] walks started, [10] Russian-roulette draws,
- * [11] balls with large s (2D s >= 2, 3D s >= 1), [12] candidate-grid lookups. For
- * measuring the algorithmic work of a workload; slower than wos_solve. events: device
- * uint64 [13]. */
+ * [11] balls with large s (2D s >= 2, 3D s >= 1), [12] candidate-grid lookups, and the
+ * walker's lane occupancy: [13] lane iterations (64 per wavefront iteration), [14] those
+ * of lanes holding a walk, [15] those that evaluated the coefficients. For measuring
+ * the algorithmic work of a workload; slower than wos_solve. events: device uint64 [16]. */
 wos_status wos_count_events(const wos_batch_item* items, int32_t n_items, const wos_options* opt, uint64_t* events,
                             void* stream);
 

@@ -70,7 +70,8 @@ struct WalkerArgs {
 // Events counted by the event-counting build of the walker (algorithmic work per step).
 enum Event {
   EV_STEPS = 0, EV_NODES, EV_PRIMS, EV_TRIALS, EV_TRIALS_FREE, EV_VOLUME, EV_EXIT, EV_TERMINAL,
-  EV_GAMMA, EV_WALKS, EV_RR_TESTS, EV_BALL_LARGE_S, EV_CELLS, kEvents
+  EV_GAMMA, EV_WALKS, EV_RR_TESTS, EV_BALL_LARGE_S, EV_CELLS, EV_LANE_ITERS, EV_ACTIVE_LANES, EV_COEF_LANES,
+  kEvents
 };
 
 constexpr uint32_t kFlagCapped = 1u << 31;
@@ -247,6 +248,10 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
     // Every active lane evaluates the coefficients at exactly one point per iteration:
     // x0 for a new walk, the current point for a walk that ends in the epsilon shell, and
     // the sampled point y otherwise, so the most expensive part runs in lockstep.
+    if constexpr (COUNT) {
+      ++ev[EV_LANE_ITERS];
+      if (phase != 0) ++ev[EV_ACTIVE_LANES];
+    }
     if (phase != 0) {
       G<DevProblem<T>>& P = *Pp;
       if constexpr (NF) {
@@ -333,7 +338,10 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
         cq.sigma_prime = 0;
         cq.f_over_alpha = 0;
         cq.alpha = 1;
-        if (phase == 1 || terminal || sample) cq = point_coef<T, DIM, true>(P, q);
+        if (phase == 1 || terminal || sample) {
+          cq = point_coef<T, DIM, true>(P, q);
+          if constexpr (COUNT) ++ev[EV_COEF_LANES];
+        }
         if (phase == 1) {
           gamma0 = cq.gamma;
           phase = 2;
@@ -426,7 +434,10 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
         cq.f_over_alpha = 0;
         cq.alpha = 1;
         T ggx[DIM];
-        if (evaluate) cq = point_coef<T, DIM, true>(P, q, EXTRA && a.grad ? ggx : nullptr);
+        if (evaluate) {
+          cq = point_coef<T, DIM, true>(P, q, EXTRA && a.grad ? ggx : nullptr);
+          if constexpr (COUNT) ++ev[EV_COEF_LANES];
+        }
         if (phase == 1) {
           gamma0 = cq.gamma;
           gx = gamma0;

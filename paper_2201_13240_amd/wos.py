@@ -307,7 +307,8 @@ def solve(entries, opt, stream=None):
 
 
 EVENT_NAMES = ["steps", "bvh_nodes", "prims", "trials", "trials_free", "volume", "exit", "terminal", "gamma_evals",
-               "walks", "rr_draws", "ball_large_s", "grid_cells"]
+               "walks", "rr_draws", "ball_large_s", "grid_cells", "lane_iterations", "active_lane_iterations",
+               "coefficient_lane_iterations"]
 
 
 def count_events(entries, opt, stream=None):

@@ -355,3 +355,25 @@ def test_gradient_estimates(W, oracle):
     ex = grad_expcos(pts)
     assert_parity(r["grad_mean"].ravel(), r["grad_se"].ravel(), ex.ravel(), 0 * ex.ravel(),
                   "gradient manufactured disk vs exact", tol("fp32"))
+
+
+def test_event_counts_match_solve(W):
+    """The event-counting walker runs the same walks: its distance queries equal the step
+    counts of the accumulators, every walk ends once, and the lane-occupancy counters are
+    ordered (all lanes >= lanes holding a walk >= lanes evaluating coefficients)."""
+    torch = torch_cuda()
+    c = WL.config2(n_grid=64)
+    prob, pts = c["problems"][0], c["points"][0]
+    h = W.Problem(prob)
+    P = dev(pts)
+    acc = W.Accumulators(P.shape[0])
+    ev = W.count_events([(h, P, acc, 0)], W.options(precision="fp32", walks=64, seed=3))
+    torch.cuda.synchronize()
+    n = P.shape[0] * 64
+    assert ev["walks"] == n and ev["terminal"] == n
+    assert ev["steps"] == int(acc.n_steps.sum().item())
+    assert ev["lane_iterations"] >= ev["active_lane_iterations"] >= ev["coefficient_lane_iterations"]
+    # one evaluation per sampled ball and per epsilon-shell ending; gamma(x0) comes from the
+    # per-point pre-pass
+    assert ev["coefficient_lane_iterations"] == ev["steps"]
+    assert ev["trials"] >= ev["steps"] - ev["terminal"]
