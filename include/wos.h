@@ -260,7 +260,7 @@ wos_status wos_count_events(const wos_batch_item* items, int32_t n_items, const 
                             void* stream);
 
 /* mean = sum / n, std_err = sqrt((sum_sq/n - mean^2) / (n - 1)) per point (eqs. 17-18);
- * all device arrays of length n. */
+ * all device arrays of length n. std_err is NaN where fewer than two walks were added. */
 wos_status wos_finalize(const double* sum, const double* sum_sq, const uint64_t* n_walks, int64_t n,
                         double* mean, double* std_err, void* stream);
 
