@@ -139,7 +139,8 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
   int pend_tile = -1;
   bool queue_done = false;
   const WOS_GLOBAL DevProblem<T>* Pp = nullptr;
-  // ---- lane state: phase 0 = idle, 1 = new walk (gamma0 pending), 2 = walking
+  // ---- lane state: phase 0 = idle, 1 = new walk whose gamma(x0) and its gradient are still
+  // to be evaluated (gradient records only), 2 = walking
   int phase = 0;
   uint64_t wid = 0;
   T x[DIM];
@@ -204,7 +205,8 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
       const uint32_t take = avail < (uint64_t)n_idle ? (uint32_t)avail : n_idle;
       const uint32_t rank = lanes_below(idle);
       if (phase == 0 && rank < take) {
-        // new walk: only set-up here; gamma(x0) is evaluated with the other lanes' step
+        // new walk: set-up only; gamma(x0) comes from the per-point table, or for gradient
+        // records is evaluated with the other lanes' step
         G<DevItem>& it = items[cur_item];
         wid = res_next + rank;
         const uint64_t local = wid - it.walk_base;
@@ -245,9 +247,10 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
       continue;
     }
     // ---------------------------------------------------------------- one step
-    // Every active lane evaluates the coefficients at exactly one point per iteration:
-    // x0 for a new walk, the current point for a walk that ends in the epsilon shell, and
-    // the sampled point y otherwise, so the most expensive part runs in lockstep.
+    // Every active lane evaluates the coefficients at no more than one point per iteration:
+    // x0 for a new walk with gradient records, the current point for a walk that ends in the
+    // epsilon shell, and the sampled point y otherwise (none while a radius proposal is
+    // being retried), so the most expensive part runs in lockstep.
     if constexpr (COUNT) {
       ++ev[EV_LANE_ITERS];
       if (phase != 0) ++ev[EV_ACTIVE_LANES];
