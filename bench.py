@@ -562,6 +562,13 @@ def main():
                "kind": "oracle",
                "sample": f"{args.cpu_points} random query points x {args.cpu_walks} walks of the same workload, "
                          f"{dt:.1f} s"}
+        # the same oracle on one thread, over a twelfth of the points
+        n1 = max(1, args.cpu_points // 12)
+        t0 = time.perf_counter()
+        o1 = O.solve(prob, pts[idx[:n1]], args.cpu_walks, h.sigma_bar, seed=78, threads=1)
+        dt1 = time.perf_counter() - t0
+        cpu["single_thread"] = {"value": float(o1["steps"].sum() / dt1), "cores": 1,
+                                "sample": f"{n1} of those points x {args.cpu_walks} walks, {dt1:.1f} s"}
         for name, r in (("fp32", r32), ("fp32c", r32c), ("fp64", r64)):
             if r is None:
                 continue
