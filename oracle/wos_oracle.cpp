@@ -43,6 +43,14 @@
 //       one for unions, exact for single primitives and intersections) and the walk
 //       ends at x - f grad f.
 //
+// Pins (tests/test_oracle_*.py): every function here is checked against closed forms,
+// quadrature, library routines or brute force. Parity unpinned: whole-walk estimates on
+// random coefficient fields (star polygons, the perturbed icosphere, the high-contrast
+// square) have no closed form and rest on the component pins only; the next-flight walk
+// with the approximate off-centred kernels (walk_next_flight, variant 2) is exact only
+// where those kernels are (the centre, the harmonic case, sigma' = sigma_bar), elsewhere
+// pinned through the exact-kernel variant 3 and the kernels' own pins.
+//
 // Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), key = (seed lo,
 // seed hi), counter = (block index, walk index, point index, problem index); each
 // uniform double takes 53 bits from two consecutive 32-bit words.
