@@ -155,3 +155,26 @@ def test_progressive_frames_equal_one_solve(W):
     ex = _expcos(P.cpu().numpy())
     e = [np.sqrt(np.mean((m - ex) ** 2)) for m in means]
     assert e[2] < 0.5 * e[0], e
+
+
+def test_cube_minus_ball_next_flight_and_gradient(W, oracle):
+    """3D CSG domain: next flight against the oracle's next flight (screened data), and the
+    gradient estimator against the exact gradient of harmonic data u = e^x cos y."""
+    geom, dim = SCENES["cube-minus-ball"]
+    prob = _prob(geom, 3, sigma=WL.field_const(4.0), source=WL.field_const(1.0),
+                 boundary=WL.field_manufactured("expcos"))
+    h = W.Problem(prob, sigma_bar=6.0)
+    pts = WL.sample_inside(np.random.default_rng(9), geom, 3, 32)
+    o = oracle.solve(prob, pts, 1024, 6.0, seed=91, variant=2)
+    for precision in ("fp64", "fp32"):
+        r = gpu_solve(W, h, pts, 1024, precision, seed=92, variant=2)
+        assert_parity(r["mean"], r["se"], o["mean"], o["se"], f"next flight cube minus ball {precision}",
+                      tol(precision))
+    harm = _prob(geom, 3, boundary=WL.field_manufactured("expcos"))
+    hh = W.Problem(harm)
+    r = gpu_solve_grad(W, hh, pts, 8192, "fp32", seed=93)
+    ex = _expcos(pts)
+    assert_parity(r["mean"], r["se"], ex, 0 * ex, "cube minus ball harmonic", tol("fp32"))
+    gex = np.c_[np.exp(pts[:, 0]) * np.cos(pts[:, 1]), -np.exp(pts[:, 0]) * np.sin(pts[:, 1]), 0 * pts[:, 0]]
+    assert_parity(r["grad_mean"].ravel(), r["grad_se"].ravel(), gex.ravel(), 0 * gex.ravel(),
+                  "cube minus ball gradient", tol("fp32"))
