@@ -243,6 +243,31 @@ __device__ T bessel_k0e(T x) {
   return m_div(chebyshev<T>(WOS_K0E_TAIL, BesselTerms<T>::kK0Tail, (T)16 * m_rcp(x) - (T)1), m_sqrt(x));
 }
 
+// I0 and K0 at x > 0 for the 2D ball terms and radius proposals, in one function so that
+// lanes of a wavefront whose arguments fall in different ranges still share its two code
+// paths: below 2 the series gives *a = I0 - 1 and *k = K0 (returns false); from 2 on the
+// Chebyshev fits give *a = e^-x I0 and *k = e^x K0 (returns true).
+template <typename T>
+__device__ __forceinline__ bool bessel_i0k0(T x, T* a, T* k) {
+  if (x < (T)2) {
+    bessel_series<T>(x, a, k);
+    return false;
+  }
+  if (x <= (T)8) {
+    *a = chebyshev<T>(WOS_I0E_MID, BesselTerms<T>::kI0Mid, (x - (T)5) * (T)(1.0 / 3.0));
+  } else {
+    *a = m_div(chebyshev<T>(WOS_I0E_TAIL, BesselTerms<T>::kI0Tail, (T)16 * m_rcp(x) - (T)1), m_sqrt(x));
+  }
+  if (x <= (T)3) {
+    *k = chebyshev<T>(WOS_K0E_LOW, BesselTerms<T>::kK0Low, x - (T)2);
+  } else if (x <= (T)8) {
+    *k = chebyshev<T>(WOS_K0E_MID, BesselTerms<T>::kK0Mid, ((T)2 * x - (T)11) * (T)0.2);
+  } else {
+    *k = m_div(chebyshev<T>(WOS_K0E_TAIL, BesselTerms<T>::kK0Tail, (T)16 * m_rcp(x) - (T)1), m_sqrt(x));
+  }
+  return true;
+}
+
 // Power series of I1 and K1 for small x (x <= 2 for I1, x <= 1 for K1), q = x^2/4:
 //   I1(x) = (x/2) sum_{k>=0} q^k/(k!(k+1)!)
 //   K1(x) = 1/x + ln(x/2) I1(x) - (x/4) sum_{k>=0} (psi(k+1) + psi(k+2)) q^k/(k!(k+1)!)
@@ -311,18 +336,15 @@ __device__ __forceinline__ Ball<T, DIM> ball_terms(T R, T s, T inv_sigma_bar, bo
     return b;
   }
   if (DIM == 2) {
-    if (s < (T)2) {
-      T i0m1, k0;
-      bessel_series<T>(s, &i0m1, &k0);
-      const T i0 = (T)1 + i0m1;
-      const T ii0 = m_rcp(i0);
-      b.pb = i0m1 * ii0;
-      b.c2d = k0 * ii0;
-    } else {
-      const T i0e = bessel_i0e<T>(s);
-      const T ii0 = m_rcp(i0e);
+    T a, k;
+    if (!bessel_i0k0<T>(s, &a, &k)) {   // s < 2: a = I0 - 1, k = K0
+      const T ii0 = m_rcp((T)1 + a);
+      b.pb = a * ii0;
+      b.c2d = k * ii0;
+    } else {                            // a = e^-s I0, k = e^s K0
+      const T ii0 = m_rcp(a);
       b.pb = (T)1 - m_exp(-s) * ii0;
-      b.c2d = bessel_k0e<T>(s) * ii0;
+      b.c2d = k * ii0;
     }
   } else {
     if (s < (T)1) {
@@ -557,21 +579,29 @@ __device__ __forceinline__ T radius_trial(const Rng& rng, T s, const Ball<T, DIM
     const T u1 = uniform01<T, S>(rng), u2 = uniform01<T, S + 1>(rng);
     if (harmonic) return m_sqrt(u1 * u2);
     const T u3 = uniform01<T, S + 2>(rng);
-    if (s < (T)2) {
-      // harmonic proposal t = sqrt(U1 U2), accept with G^s/G^0
-      const T t = m_sqrt(u1 * u2);
-      const T x = t * s;   // < 2: the series holds for K0 too (one code path for the wave)
-      T i0m1, k0;
-      bessel_series<T>(x, &i0m1, &k0);
-      const T g = k0 - b.c2d * ((T)1 + i0m1);
+    // s < 2: harmonic proposal t = sqrt(U1 U2), accepted with G^s/G^0; otherwise the
+    // free-space proposal u = ts = 2 sqrt(E1 E2), accepted with G_ball/G_free on u < s.
+    // Both need I0 and K0 at x = ts, taken from one call.
+    const bool hprop = s < (T)2;
+    T t, x;
+    if (hprop) {
+      t = m_sqrt(u1 * u2);
+      x = t * s;
+    } else {
+      if constexpr (COUNT) ++tally->trials_free;
+      x = (T)2 * m_sqrt(m_log(u1) * m_log(u2));
+      t = m_div(x, s);
+    }
+    T a, k;
+    const bool scaled = bessel_i0k0<T>(x, &a, &k);
+    if (hprop) {
+      // x < 2: a = I0(x) - 1, k = K0(x)
+      const T g = k - b.c2d * ((T)1 + a);
       return u3 * -m_log(t) <= g ? t : (T)-1;
     }
-    // free-space proposal u = 2 sqrt(E1 E2), accept with G_ball/G_free on u < s
-    if constexpr (COUNT) ++tally->trials_free;
-    const T u = (T)2 * m_sqrt(m_log(u1) * m_log(u2));
-    if (!(u < s)) return (T)-1;
-    const T r = b.c2d * m_div(bessel_i0e<T>(u), bessel_k0e<T>(u)) * m_exp((T)2 * (u - s));
-    return u3 <= (T)1 - r ? m_div(u, s) : (T)-1;
+    // 1 - G_ball/G_free = c2d I0(x)/K0(x) e^{-2s} with c2d = e^{2s} K0(s)/I0(s)
+    const T r = b.c2d * m_div(scaled ? a : (T)1 + a, k) * m_exp(scaled ? (T)2 * (x - s) : (T)-2 * s);
+    return (x < s && u3 <= (T)1 - r) ? t : (T)-1;
   } else {
     if (harmonic || s < (T)2.449489742783178) {
       // Beta(2,2) = median of three uniforms
