@@ -1125,15 +1125,22 @@ __device__ __forceinline__ T triangle_dist2(const T* p, PT tri) {
 constexpr int kPrimStride2 = 4;    // segment: x0 y0 x1 y1
 constexpr int kPrimStride3 = 12;   // triangle: a, b, c, (pad)
 constexpr int kStackDepth = 48;     // private (scratch) stack: any tree the host accepts
-constexpr int kLdsStackDepth = 16;  // LDS stack: trees of depth <= 16 (up to ~2^18 primitives)
+// LDS stack depths of the walker. The walker's LDS must leave room for five 256-thread
+// blocks per CU: the mesh walker takes trees of depth <= 15 (30 KB in FP32), the polygon
+// walker, whose candidate grid answers most queries, trees of depth <= 8 (16 KB). Deeper
+// trees use the private stack.
+constexpr int kLdsStackDepth = 15;
+constexpr int kLdsStackDepthPolygon = 8;
 
 // Traversal stack of far children with their box distances, either in LDS (one column
-// per lane: entry k of lane t at k * stride + t, conflict-free) or in private memory.
+// per lane: entry k of lane t at k * stride + t, conflict-free) for trees of depth <= depth,
+// or in private memory.
 template <typename T>
 struct LdsStack {
   int32_t* node;   // null: use the private stack
   T* dist;
   int stride;
+  int depth;
 };
 
 // Nearest primitive by BVH traversal; returns squared distance and primitive index.
@@ -1153,8 +1160,8 @@ __device__ __forceinline__ T prim_dist2(const WOS_GLOBAL T* prims, const T* x, i
 // is the exact nearest distance either way.
 template <typename T, int DIM, bool COUNT = false>
 __device__ __forceinline__ T bvh_nearest(G<DevGeometry<T>>& g, const T* x, int* best_prim, Tally* tally = nullptr,
-                                         LdsStack<T> lds = LdsStack<T>{nullptr, nullptr, 0}, int hint = -1) {
-  if (lds.node && g.depth <= kLdsStackDepth) {
+                                         LdsStack<T> lds = LdsStack<T>{nullptr, nullptr, 0, 0}, int hint = -1) {
+  if (lds.node && g.depth <= lds.depth) {
     const WOS_GLOBAL BvhNode<T, DIM>* nodes = (const WOS_GLOBAL BvhNode<T, DIM>*)g.nodes;
     const WOS_GLOBAL T* prims = gptr(g.prims);
     T best = Consts<T>::kInf;
@@ -1373,7 +1380,7 @@ __device__ __forceinline__ T sdf_value(G<DevGeometry<T>>& g, const T* x, int* ac
 // closest_point needs to recover xbar.
 template <typename T, int DIM, int GEOM, bool COUNT = false>
 __device__ __forceinline__ T boundary_distance(G<DevGeometry<T>>& g, const T* x, int* prim, Tally* tally = nullptr,
-                                               LdsStack<T> lds = LdsStack<T>{nullptr, nullptr, 0}, int hint = -1) {
+                                               LdsStack<T> lds = LdsStack<T>{nullptr, nullptr, 0, 0}, int hint = -1) {
   if (GEOM == GK_BALL) {
     T r2 = 0;
 #pragma unroll

@@ -118,11 +118,12 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
   constexpr bool NF = MODE == 2;
   constexpr bool EXTRA = MODE == 1;
   const uint32_t lane = __lane_id();
-  LdsStack<T> lds_stack{nullptr, nullptr, 0};
+  constexpr int kStack = GEOM == GK_POLYGON ? kLdsStackDepthPolygon : kLdsStackDepth;
+  LdsStack<T> lds_stack{nullptr, nullptr, 0, 0};
   if constexpr (GEOM == GK_POLYGON || GEOM == GK_TRIMESH) {
-    __shared__ int32_t s_node[kLdsStackDepth * 256];
-    __shared__ T s_dist[kLdsStackDepth * 256];
-    lds_stack = LdsStack<T>{s_node + threadIdx.x, s_dist + threadIdx.x, (int)blockDim.x};
+    __shared__ int32_t s_node[kStack * 256];
+    __shared__ T s_dist[kStack * 256];
+    lds_stack = LdsStack<T>{s_node + threadIdx.x, s_dist + threadIdx.x, (int)blockDim.x, kStack};
   }
   Tally tally = {0, 0, 0, 0};
   uint32_t ev[kEvents];
