@@ -32,7 +32,7 @@ struct DevField {
 // Binary BVH node that stores the bounds of both children, so a visit tests both
 // boxes with one load. A child reference c >= 0 is an inner node index; c < 0 encodes
 // a leaf: -1 - c = (first primitive << 3) | count, count in 1..7.
-constexpr int kCellInline = 5;
+constexpr int kCellInline = 7;
 
 // One cell of the polygon candidate grid: `count` candidates at cell_prim / cell_segs /
 // cell_dc [start, start + count), the first kCellInline also held here (zero-padded) as
