@@ -372,7 +372,8 @@ def measure_extras(wos, WL):
     """Throughput of the rows beyond the plain delta-tracking walk, FP32, each against the
     plain walk on the same workload: gradients (supplemental Sec. 2) on the star polygon;
     weight-window splitting (Sec. 6) on the manufactured disk, where sigma' < 0 lets
-    null-collision weights grow; an SDF/CSG scene (Sec. 7.2)."""
+    null-collision weights grow; an SDF/CSG scene (Sec. 7.2); and the other workload
+    shapes: the batch of 64 polygon problems in one plan and the 3D mesh walker."""
     import torch
     out = {}
     # gradient estimates: the star-polygon workload at 256 walks per point
@@ -414,6 +415,43 @@ def measure_extras(wos, WL):
     out["sdf"] = {"workload": "square with 24 round and 8 box holes (33 CSG rows), star-polygon fields, "
                               "256x256 grid inside, 256 walks per point", "query_points": int(P.shape[0]), **sdf}
     print(f"bench: sdf steps/s {sdf['steps_per_s']:.3e}", file=sys.stderr, flush=True)
+    del P
+    # the batch of 64 polygon problems (16-4096 edges, 2.65e6 points) in one plan
+    c = WL.config4()
+    entries, n_total = [], 0
+    for i, (p, q) in enumerate(zip(c["problems"], c["points"])):
+        Q = torch.as_tensor(q, dtype=torch.float64, device="cuda")
+        entries.append((wos.Problem(p), Q, wos.Accumulators(Q.shape[0]), i))
+        n_total += Q.shape[0]
+    plan = wos.Plan(entries, wos.options(precision="fp32", walks=512, seed=0))
+    plan.launch(seed=999)
+    torch.cuda.synchronize()
+    for _, _, acc, _ in entries:
+        acc.n_steps.zero_()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    plan.launch(seed=1, walk_offset_add=512)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    steps = sum(float(acc.n_steps.sum().item()) for _, _, acc, _ in entries)
+    out["batch64"] = {"workload": "64 star polygons with 16-4096 edges, log-uniform 1k-256k points each, 512 walks "
+                                  "per point, one plan", "query_points": n_total, "ms_per_pass": ms,
+                      "steps_per_s": steps / (ms / 1e3), "plan": plan.info()}
+    plan.close()
+    del entries
+    print(f"bench: 64-problem batch steps/s {out['batch64']['steps_per_s']:.3e}", file=sys.stderr, flush=True)
+    # 3D mesh walker on a slice of the perturbed icosphere (20,480 triangles)
+    c = WL.config3(n_grid=256)
+    prob, pts = c["problems"][0], c["points"][0]
+    h = wos.Problem(prob)
+    P = torch.as_tensor(pts, dtype=torch.float64, device="cuda")
+    ico = _timed_plan(wos, torch, h, P, {"precision": "fp32"}, 64, 2)
+    ico.pop("_mean")
+    ico.pop("_se")
+    out["icosphere"] = {"workload": "perturbed icosphere, 20,480 triangles, 256x256 slice grid inside, 64 walks per "
+                                    "point", "query_points": int(P.shape[0]), **ico}
+    print(f"bench: icosphere steps/s {ico['steps_per_s']:.3e}", file=sys.stderr, flush=True)
     return out
 
 

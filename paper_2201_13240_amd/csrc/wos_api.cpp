@@ -326,13 +326,14 @@ wos_status build_geometry(const wos_problem_desc& d, HostGeometry& g) {
   bvh_child_bounds<double>(g.topo, plo64, phi64, pdim, g.bounds64);
   bvh_child_bounds<float>(g.topo, plo32, phi32, pdim, g.bounds32);
   if (G.kind == WOS_GEOM_POLYGON) {
-    // about 64 cells per segment, between 64^2 and 2^20 cells; the margin covers
-    // FP32 rounding of the query point and of the cell index
+    // about 64 cells per segment, between 64^2 and 2^20 cells, lists of up to 128
+    // candidates (longer ones, deep inside large polygons, leave the query to the BVH);
+    // the margin covers FP32 rounding of the query point and of the cell index
     double scale = 0;
     for (double c : g.prims64) scale = std::max(scale, std::fabs(c));
     const int64_t target = std::min<int64_t>(1 << 20, std::max<int64_t>(4096, 64 * n));
     g.grid_margin = 4e-6 * (scale + 1.0);
-    g.grid = build_segment_grid(g.prims64, n, g.topo, g.bounds64, target, g.grid_margin, 32);
+    g.grid = build_segment_grid(g.prims64, n, g.topo, g.bounds64, target, g.grid_margin, 128);
   }
   return WOS_OK;
 }

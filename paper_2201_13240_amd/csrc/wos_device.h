@@ -1127,10 +1127,10 @@ constexpr int kPrimStride3 = 12;   // triangle: a, b, c, (pad)
 constexpr int kStackDepth = 48;     // private (scratch) stack: any tree the host accepts
 // LDS stack depths of the walker. The walker's LDS must leave room for five 256-thread
 // blocks per CU: the mesh walker takes trees of depth <= 15 (30 KB in FP32), the polygon
-// walker, whose candidate grid answers most queries, trees of depth <= 8 (16 KB). Deeper
-// trees use the private stack.
+// walker, whose candidate grid answers most queries, trees of depth <= 12 (24 KB; up to
+// about 8000 edges). Deeper trees use the private stack.
 constexpr int kLdsStackDepth = 15;
-constexpr int kLdsStackDepthPolygon = 8;
+constexpr int kLdsStackDepthPolygon = 12;
 
 // Traversal stack of far children with their box distances, either in LDS (one column
 // per lane: entry k of lane t at k * stride + t, conflict-free) for trees of depth <= depth,
