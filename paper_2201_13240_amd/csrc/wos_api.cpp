@@ -116,9 +116,11 @@ std::vector<T> field_terms(const wos_field_desc& f, int dim) {
     const double* t = f.terms + j * (dim + 2);
     T* o = out.data() + (size_t)j * kTermStride;
     if (f.base == WOS_FIELD_FOURIER) {
+      // wave vector in cycles per unit length: the device takes the sine and cosine of
+      // k.x in revolutions
       double k2 = 0;
       for (int i = 0; i < dim; ++i) {
-        o[i] = (T)(kTwoPi * t[i]);
+        o[i] = (T)t[i];
         k2 += (kTwoPi * t[i]) * (kTwoPi * t[i]);
       }
       const double a = t[dim], phi = t[dim + 1];

@@ -697,15 +697,17 @@ __device__ __forceinline__ FV<T, DIM> field_base(G<DevField<T>>& f, const T* x) 
   if (base == FB_FOURIER) {
     const WOS_GLOBAL T* p = gptr(f.terms);
     for (int j = 0; j < f.n; ++j, p += kTermStride) {
+      // phase k.x in revolutions (k in cycles per unit length)
       T th = p[0] * x[0] + p[1] * x[1];
       if (DIM == 3) th = m_fma(p[2], x[2], th);
       T sn, cs;
-      m_sincos(th, &sn, &cs);
+      m_sincospi2(th, &sn, &cs);
       const T ac = p[3], as = p[4];
-      const T val = ac * cs - as * sn;                 // a cos(th + phi)
+      const T val = ac * cs - as * sn;                 // a cos(2 pi k.x + phi)
       r.v += val;
       if (D) {
-        const T dval = -(ac * sn + as * cs);            // -a sin(th + phi)
+        constexpr T kTwoPi = (T)6.283185307179586476925286766559;
+        const T dval = -(ac * sn + as * cs) * kTwoPi;   // -2 pi a sin(2 pi k.x + phi)
 #pragma unroll
         for (int i = 0; i < DIM; ++i) r.g[i] = m_fma(dval, p[i], r.g[i]);
         r.lap = m_fma(-val, p[5], r.lap);                // Laplacian: -|2 pi k|^2 B_j
