@@ -70,7 +70,11 @@ int wos_version(void);
  *           x - f(x) grad f(x) with the gradient of the row that decides f. Components
  *           beyond dim are ignored. lo[dim], hi[dim]: a box that holds the (bounded)
  *           domain, used to sample sigma'.
- * Polygons and meshes get an axis-aligned BVH (Sec. 7.1) built on the host. */
+ * Polygons and meshes get an axis-aligned BVH (Sec. 7.1) and a candidate grid in front
+ * of it, built on the host (for meshes with up to 16 threads). In cells deep inside a
+ * mesh the walk's ball radius may be a certified lower bound of the distance, at least
+ * the cell size and 2 epsilon: every ball stays inside the domain, as the walk needs
+ * (Sec. 3), and no walk ends on such a value. Distance queries are exact. */
 typedef enum {
   WOS_GEOM_BALL = 0,
   WOS_GEOM_BOX = 1,
@@ -151,8 +155,8 @@ typedef struct {
 
 typedef struct wos_problem wos_problem;
 
-/* Validates the description, builds the BVH, copies fields and geometry to `device` in
- * FP32 and FP64, and fixes sigma_bar. Synchronous. Errors: WOS_ERR_INVALID_ARG (bad
+/* Validates the description, builds the BVH and candidate grid, copies fields and
+ * geometry to `device` in FP32 and FP64, and fixes sigma_bar. Synchronous. Errors: WOS_ERR_INVALID_ARG (bad
  * enums, dim, epsilon <= 0, empty terms), WOS_ERR_GEOMETRY (too few vertices, bad
  * indices, degenerate bounds), WOS_ERR_COEFFICIENT (alpha <= 0, sigma < 0 or
  * non-finite sigma' among the samples, or sigma_bar = 0 with sigma' != 0),
@@ -166,10 +170,15 @@ wos_status wos_problem_info(const wos_problem* p, double* sigma_prime_min, doubl
 /* BVH statistics: nodes, depth, primitives (0 for analytic shapes). */
 wos_status wos_problem_bvh_info(const wos_problem* p, int64_t* n_nodes, int32_t* depth, int64_t* n_prims);
 
-/* Candidate grid of a polygon (nx = ny = 0 otherwise): a uniform grid whose cells list
- * every segment that can be nearest to a point of the cell; closest-point queries then
- * scan one short list instead of traversing the BVH. n_candidates: total list length. */
-wos_status wos_problem_grid_info(const wos_problem* p, int32_t* nx, int32_t* ny, int64_t* n_candidates);
+/* Candidate grid of a polygon or a triangle mesh (all zero for analytic and SDF
+ * domains): a uniform grid (nx x ny cells in 2D, nz = 1; nx x ny x nz in 3D) whose cells
+ * list every segment or triangle that can be nearest to a point of the cell; closest-point
+ * queries then scan one short list instead of traversing the BVH (Sec. 7.1 answers them
+ * with a BVH). A polygon cell whose list would be too long has none and uses the BVH; a
+ * mesh cell keeps the 16 candidates nearest to its centre.
+ * n_candidates: total list length. Any output pointer may be null. */
+wos_status wos_problem_grid_info(const wos_problem* p, int32_t* nx, int32_t* ny, int32_t* nz,
+                                 int64_t* n_candidates);
 
 wos_status wos_problem_destroy(wos_problem* p);
 
@@ -309,8 +318,8 @@ wos_status wos_plan_destroy(wos_plan* plan);
 wos_status wos_eval_coefficients(const wos_problem* p, const double* points, int64_t n, int32_t precision,
                                  double* out, void* stream);
 
-/* Distance to the boundary and closest point (Alg. 1, first step). d: device double [n];
- * closest: device double [n][dim]. */
+/* Exact distance to the boundary and closest point (Alg. 1, first step). d: device
+ * double [n]; closest: device double [n][dim]. */
 wos_status wos_eval_distance(const wos_problem* p, const double* points, int64_t n, int32_t precision,
                              double* d, double* closest, void* stream);
 

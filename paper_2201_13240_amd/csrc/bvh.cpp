@@ -4,6 +4,7 @@
 #include <cmath>
 #include <functional>
 #include <limits>
+#include <thread>
 
 namespace wos {
 
@@ -137,6 +138,83 @@ struct SegQuery {
   }
 };
 
+double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+double seg3_dist2(const double* a, const double* b, const double* p) {
+  double e[3], q[3];
+  for (int k = 0; k < 3; ++k) {
+    e[k] = b[k] - a[k];
+    q[k] = p[k] - a[k];
+  }
+  const double l2 = dot3(e, e);
+  double t = l2 > 0 ? dot3(q, e) / l2 : 0.0;
+  t = std::min(1.0, std::max(0.0, t));
+  for (int k = 0; k < 3; ++k) q[k] -= t * e[k];
+  return dot3(q, q);
+}
+
+// Squared distance from p to triangle (a, b, c): the plane distance when the projection
+// of p falls inside the triangle (barycentric coordinates from the Gram system of the
+// two edges at a), else the nearest of the three edges.
+double tri_dist2(const double* t, const double* p) {
+  const double *a = t, *b = t + 3, *c = t + 6;
+  double e0[3], e1[3], ap[3];
+  for (int k = 0; k < 3; ++k) {
+    e0[k] = b[k] - a[k];
+    e1[k] = c[k] - a[k];
+    ap[k] = p[k] - a[k];
+  }
+  const double d00 = dot3(e0, e0), d01 = dot3(e0, e1), d11 = dot3(e1, e1);
+  const double den = d00 * d11 - d01 * d01;
+  if (den > 0) {
+    const double d20 = dot3(ap, e0), d21 = dot3(ap, e1);
+    const double v = (d11 * d20 - d01 * d21) / den, w = (d00 * d21 - d01 * d20) / den;
+    if (v >= 0 && w >= 0 && v + w <= 1) {
+      double q[3];
+      for (int k = 0; k < 3; ++k) q[k] = ap[k] - v * e0[k] - w * e1[k];
+      return dot3(q, q);
+    }
+  }
+  return std::min(seg3_dist2(a, b, p), std::min(seg3_dist2(b, c, p), seg3_dist2(c, a, p)));
+}
+
+double box3_d2(const double* lo, const double* hi, const double* p) {
+  double s = 0;
+  for (int k = 0; k < 3; ++k) {
+    const double e = std::max(std::max(lo[k] - p[k], p[k] - hi[k]), 0.0);
+    s += e * e;
+  }
+  return s;
+}
+
+struct TriQuery {
+  const std::vector<double>& tris;
+  const BvhTopology& topo;
+  const std::vector<double>& bounds;
+
+  // visits leaf triangles whose subtree box lies within sqrt(*r2) of p, nearer boxes
+  // first; f returns false to stop the whole traversal (then within returns false)
+  template <typename F>
+  bool within(int32_t c, const double* p, const double* r2, F&& f) const {
+    if (c < 0) {
+      const int32_t code = -1 - c;
+      const int32_t first = code >> 3, cnt = code & 7;
+      for (int32_t i = first; i < first + cnt; ++i)
+        if (!f(i, tri_dist2(&tris[12 * (size_t)i], p))) return false;
+      return true;
+    }
+    const double* b = &bounds[(size_t)c * 12];  // lo[2][3], hi[2][3]
+    const double da = box3_d2(b + 0, b + 6, p), db = box3_d2(b + 3, b + 9, p);
+    const int32_t ca = topo.child[2 * c], cb = topo.child[2 * c + 1];
+    const bool a_first = da <= db;
+    const int32_t c0 = a_first ? ca : cb, c1 = a_first ? cb : ca;
+    const double d0 = a_first ? da : db, d1 = a_first ? db : da;
+    if (d0 <= *r2 && !within(c0, p, r2, f)) return false;
+    if (d1 <= *r2 && !within(c1, p, r2, f)) return false;
+    return true;
+  }
+};
+
 }  // namespace
 
 SegmentGrid build_segment_grid(const std::vector<double>& segs, int64_t n, const BvhTopology& topo,
@@ -185,6 +263,105 @@ SegmentGrid build_segment_grid(const std::vector<double>& segs, int64_t n, const
       }
       g.start[(int64_t)j * g.nx + i + 1] = (uint32_t)g.prim.size();
     }
+  return g;
+}
+
+SegmentGrid build_triangle_grid(const std::vector<double>& tris, int64_t n, const BvhTopology& topo,
+                                const std::vector<double>& bounds, int64_t target_cells, double margin,
+                                int max_candidates, int threads) {
+  SegmentGrid g;
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t i = 0; i < n; ++i)
+    for (int v = 0; v < 3; ++v)
+      for (int k = 0; k < 3; ++k) {
+        lo[k] = std::min(lo[k], tris[12 * i + 3 * v + k]);
+        hi[k] = std::max(hi[k], tris[12 * i + 3 * v + k]);
+      }
+  double ext = 0, vol = 1;
+  for (int k = 0; k < 3; ++k) ext = std::max(ext, hi[k] - lo[k]);
+  const double pad = 1e-6 * ext + 1e-12;
+  for (int k = 0; k < 3; ++k) {
+    lo[k] -= pad;
+    vol *= hi[k] - lo[k] + pad;
+  }
+  const double h = std::cbrt(vol / (double)target_cells);
+  int32_t nn[3];
+  for (int k = 0; k < 3; ++k) {
+    nn[k] = std::max(1, (int32_t)std::ceil((hi[k] - lo[k] + pad) / h));
+    g.lo[k] = lo[k];
+  }
+  g.nx = nn[0];
+  g.ny = nn[1];
+  g.nz = nn[2];
+  g.h = h;
+  const double halfdiag = 0.5 * h * std::sqrt(3.0);
+  const TriQuery q{tris, topo, bounds};
+  const int64_t ncell = (int64_t)g.nx * g.ny * g.nz;
+  threads = (int)std::max<int64_t>(1, std::min<int64_t>(threads, (ncell + 4095) / 4096));
+  struct Part {
+    std::vector<uint32_t> count;
+    std::vector<int32_t> prim;
+    std::vector<double> dc, tail;
+  };
+  std::vector<Part> parts(threads);
+  auto work = [&](int t) {
+    Part& P = parts[t];
+    const int64_t c0 = ncell * t / threads, c1 = ncell * (t + 1) / threads;
+    P.count.resize(c1 - c0);
+    P.tail.resize(c1 - c0);
+    std::vector<std::pair<double, int32_t>> heap;   // max-heap of the kept candidates
+    const size_t keep = (size_t)max_candidates + 1;
+    for (int64_t c = c0; c < c1; ++c) {
+      const int64_t i = c % g.nx, j = (c / g.nx) % g.ny, k = c / ((int64_t)g.nx * g.ny);
+      const double p[3] = {lo[0] + (i + 0.5) * h, lo[1] + (j + 0.5) * h, lo[2] + (k + 0.5) * h};
+      double best = 1e300;
+      q.within(topo.root, p, &best, [&](int32_t, double d2) {
+        best = std::min(best, d2);
+        return true;
+      });
+      const double r = std::sqrt(best) + 2 * halfdiag + margin;
+      // the max_candidates + 1 nearest triangles within r of the centre; the bound
+      // shrinks to the farthest kept one once the heap is full
+      double r2 = r * r;
+      heap.clear();
+      q.within(topo.root, p, &r2, [&](int32_t s, double d2) {
+        if (d2 > r2) return true;
+        if (heap.size() == keep) {
+          std::pop_heap(heap.begin(), heap.end());
+          heap.pop_back();
+        }
+        heap.emplace_back(d2, s);
+        std::push_heap(heap.begin(), heap.end());
+        if (heap.size() == keep) r2 = heap.front().first;
+        return true;
+      });
+      std::sort(heap.begin(), heap.end());
+      const size_t n_keep = std::min(heap.size(), (size_t)max_candidates);
+      for (size_t e = 0; e < n_keep; ++e) {
+        P.prim.push_back(heap[e].second);
+        P.dc.push_back(std::sqrt(heap[e].first));
+      }
+      P.count[c - c0] = (uint32_t)n_keep;
+      P.tail[c - c0] = heap.size() > n_keep ? std::sqrt(heap[n_keep].first) : HUGE_VAL;
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < threads; ++t) pool.emplace_back(work, t);
+  work(0);
+  for (auto& th : pool) th.join();
+  g.start.resize(ncell + 1);
+  g.tail.resize(ncell);
+  g.start[0] = 0;
+  int64_t c = 0;
+  for (const Part& P : parts) {
+    for (size_t e = 0; e < P.count.size(); ++e) {
+      g.start[c + 1] = g.start[c] + P.count[e];
+      g.tail[c] = P.tail[e];
+      ++c;
+    }
+    g.prim.insert(g.prim.end(), P.prim.begin(), P.prim.end());
+    g.dc.insert(g.dc.end(), P.dc.begin(), P.dc.end());
+  }
   return g;
 }
 

@@ -27,17 +27,20 @@ void bvh_child_bounds(const BvhTopology& t, const std::vector<T>& plo, const std
 
 namespace wos {
 
-// Uniform grid over the bounding box of a 2D segment set. Cell c lists every segment
-// within d(center_c) + 2 * halfdiag + margin of its centre, a superset of the segments
-// that can be nearest to any point of the cell (or within `margin` of it): for p in the
-// cell and s* nearest to p, |c - s*| <= |p - s*| + halfdiag <= d(c) + 2 halfdiag.
+// Uniform grid over the bounding box of a 2D segment set or a 3D triangle set. Cell c
+// lists every primitive within d(center_c) + 2 * halfdiag + margin of its centre, a
+// superset of the primitives that can be nearest to any point of the cell (or within
+// `margin` of it): for p in the cell and s* nearest to p,
+// |c - s*| <= |p - s*| + halfdiag <= d(c) + 2 halfdiag.
 struct SegmentGrid {
-  int32_t nx = 0, ny = 0;
-  double lo[2] = {0, 0};
+  int32_t nx = 0, ny = 0, nz = 1;
+  double lo[3] = {0, 0, 0};
   double h = 0;
-  std::vector<uint32_t> start;   // [nx * ny + 1]
-  std::vector<int32_t> prim;     // candidate segment indices (leaf order), nearest to the cell centre first
+  std::vector<uint32_t> start;   // [nx * ny * nz + 1], cell (i, j, k) at (k * ny + j) * nx + i
+  std::vector<int32_t> prim;     // candidate indices (leaf order), nearest to the cell centre first
   std::vector<double> dc;        // distance from the cell centre to each candidate (ascending per cell)
+  std::vector<double> tail;      // triangle grids: per cell, the centre distance of the nearest
+                                 // candidate left off its list (+inf: the list is complete)
 };
 
 // segs: [n][4] in leaf order; topo/bounds: the BVH over them (child bounds as produced
@@ -48,5 +51,16 @@ struct SegmentGrid {
 SegmentGrid build_segment_grid(const std::vector<double>& segs, int64_t n, const BvhTopology& topo,
                                const std::vector<double>& bounds, int64_t target_cells, double margin,
                                int max_candidates);
+
+// The same for triangles: tris [n][12] (a, b, c, padding) in leaf order, a 3D grid of
+// cubic cells. A cell keeps at most max_candidates of its candidates, the nearest to its
+// centre, and records in `tail` the centre distance of the first one left off: for p in
+// the cell every omitted triangle lies at least tail - |p - centre| from p, so a scan of
+// the kept list either finds the nearest triangle or a lower bound of the distance.
+// Cells are filled by up to `threads` host threads; the result does not depend on their
+// number.
+SegmentGrid build_triangle_grid(const std::vector<double>& tris, int64_t n, const BvhTopology& topo,
+                                const std::vector<double>& bounds, int64_t target_cells, double margin,
+                                int max_candidates, int threads);
 
 }  // namespace wos

@@ -6,9 +6,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -61,7 +63,7 @@ struct wos_problem {
   size_t off32 = 0, off64 = 0;
   int64_t n_nodes = 0, n_prims = 0;
   int32_t depth = 0;
-  int32_t grid_nx = 0, grid_ny = 0;
+  int32_t grid_nx = 0, grid_ny = 0, grid_nz = 0;
   int64_t grid_candidates = 0;
   std::vector<unsigned char> staging;  // host copy of the device blob
   const void* d32() const { return (const unsigned char*)dmem + off32; }
@@ -177,7 +179,7 @@ struct HostGeometry {
   BvhTopology topo;
   std::vector<double> bounds64;      // node child bounds
   std::vector<float> bounds32;
-  SegmentGrid grid;                  // 2D polygons
+  SegmentGrid grid;                  // polygons and triangle meshes
   double grid_margin = 0;            // rounding margin of the candidate lists
 };
 
@@ -336,6 +338,15 @@ wos_status build_geometry(const wos_problem_desc& d, HostGeometry& g) {
     const int64_t target = std::min<int64_t>(1 << 20, std::max<int64_t>(4096, 64 * n));
     g.grid_margin = 4e-6 * (scale + 1.0);
     g.grid = build_segment_grid(g.prims64, n, g.topo, g.bounds64, target, g.grid_margin, 128);
+  } else {
+    // meshes: about 64 cells per triangle, between 32^3 and 2^21 cells, lists of the 16
+    // candidates nearest to the cell centre
+    double scale = 0;
+    for (double c : g.prims64) scale = std::max(scale, std::fabs(c));
+    const int64_t target = std::min<int64_t>(1 << 21, std::max<int64_t>(32768, 64 * n));
+    g.grid_margin = 4e-6 * (scale + 1.0);
+    const int threads = (int)std::min<unsigned>(16, std::max<unsigned>(1, std::thread::hardware_concurrency()));
+    g.grid = build_triangle_grid(g.prims64, n, g.topo, g.bounds64, target, g.grid_margin, kMeshCellList, threads);
   }
   return WOS_OK;
 }
@@ -528,6 +539,31 @@ size_t layout_problem(Blob& blob, const wos_problem_desc& d, const HostGeometry&
     } else {
       node_off = blob.alloc(std::max<size_t>(1, G.n_nodes) * sizeof(BvhNode<T, 3>));
       write_nodes<T, 3>(g, bounds, (BvhNode<T, 3>*)(blob.host.data() + node_off));
+      if (g.grid.nx > 0) {
+        G.grid_nx = g.grid.nx;
+        G.grid_ny = g.grid.ny;
+        G.grid_nz = g.grid.nz;
+        for (int k = 0; k < 3; ++k) G.grid_lo[k] = (T)g.grid.lo[k];
+        G.grid_inv_h = (T)(1.0 / g.grid.h);
+        G.grid_h = (T)g.grid.h;
+        G.grid_lb_min = (T)std::max(g.grid.h, 2.0 * d.epsilon);
+        const size_t nc = g.grid.prim.size();
+        const size_t ncell = g.grid.start.size() - 1;
+        grid_start_off = blob.alloc(ncell * sizeof(MeshCell<T>));
+        MeshCell<T>* cells = (MeshCell<T>*)(blob.host.data() + grid_start_off);
+        for (size_t c = 0; c < ncell; ++c) {
+          std::memset(&cells[c], 0, sizeof(MeshCell<T>));
+          cells[c].start = g.grid.start[c];
+          cells[c].count = g.grid.start[c + 1] - g.grid.start[c];
+          cells[c].tail = std::isfinite(g.grid.tail[c]) ? (T)(g.grid.tail[c] - g.grid_margin)
+                                                        : std::numeric_limits<T>::infinity();
+        }
+        grid_prim_off = blob.alloc(std::max<size_t>(nc, 1) * sizeof(int32_t));
+        std::memcpy(blob.host.data() + grid_prim_off, g.grid.prim.data(), nc * sizeof(int32_t));
+        grid_dc_off = blob.alloc(std::max<size_t>(nc, 1) * sizeof(T));
+        T* dc = (T*)(blob.host.data() + grid_dc_off);
+        for (size_t k = 0; k < nc; ++k) dc[k] = (T)(g.grid.dc[k] - g.grid_margin);
+      }
     }
   }
   std::memcpy(blob.host.data() + off_struct, &P, sizeof(P));
@@ -545,7 +581,7 @@ size_t layout_problem(Blob& blob, const wos_problem_desc& d, const HostGeometry&
     if (g.grid.nx > 0) {
       ptr_fixups.push_back({gbase + offsetof(DevGeometry<T>, cells), grid_start_off});
       ptr_fixups.push_back({gbase + offsetof(DevGeometry<T>, cell_prim), grid_prim_off});
-      ptr_fixups.push_back({gbase + offsetof(DevGeometry<T>, cell_segs), grid_seg_off});
+      if (grid_seg_off) ptr_fixups.push_back({gbase + offsetof(DevGeometry<T>, cell_segs), grid_seg_off});
       ptr_fixups.push_back({gbase + offsetof(DevGeometry<T>, cell_dc), grid_dc_off});
     }
   }
@@ -604,6 +640,7 @@ wos_status wos_problem_create(const wos_problem_desc* desc, int device, wos_prob
   p->depth = g.topo.depth;
   p->grid_nx = g.grid.nx;
   p->grid_ny = g.grid.ny;
+  p->grid_nz = g.grid.nx > 0 ? g.grid.nz : 0;
   p->grid_candidates = (int64_t)g.grid.prim.size();
   Blob blob;
   std::vector<std::pair<size_t, size_t>> fix;
@@ -735,10 +772,12 @@ wos_status wos_problem_bvh_info(const wos_problem* p, int64_t* n_nodes, int32_t*
   return WOS_OK;
 }
 
-wos_status wos_problem_grid_info(const wos_problem* p, int32_t* nx, int32_t* ny, int64_t* n_candidates) {
+wos_status wos_problem_grid_info(const wos_problem* p, int32_t* nx, int32_t* ny, int32_t* nz,
+                                 int64_t* n_candidates) {
   if (!p) return fail(WOS_ERR_INVALID_ARG, "null problem");
   if (nx) *nx = p->grid_nx;
   if (ny) *ny = p->grid_ny;
+  if (nz) *nz = p->grid_nz;
   if (n_candidates) *n_candidates = p->grid_candidates;
   return WOS_OK;
 }

@@ -1379,8 +1379,12 @@ __device__ __forceinline__ T sdf_value(G<DevGeometry<T>>& g, const T* x, int* ac
 }
 
 // Distance d from x to the boundary (Alg. 1, first step); prim receives what
-// closest_point needs to recover xbar.
-template <typename T, int DIM, int GEOM, bool COUNT = false>
+// closest_point needs to recover xbar. With BOUND, a triangle mesh may answer with a
+// certified lower bound of d instead (at least the cell size and twice epsilon) where the
+// truncated list of its grid cell cannot decide the nearest triangle (points deep inside,
+// where many triangles are nearly equidistant): the ball of that radius still lies inside
+// the domain, which is all the walk's step needs, and a walk never ends on such a value.
+template <typename T, int DIM, int GEOM, bool COUNT = false, bool BOUND = false>
 __device__ __forceinline__ T boundary_distance(G<DevGeometry<T>>& g, const T* x, int* prim, Tally* tally = nullptr,
                                                LdsStack<T> lds = LdsStack<T>{nullptr, nullptr, 0, 0}, int hint = -1) {
   if (GEOM == GK_BALL) {
@@ -1455,6 +1459,60 @@ __device__ __forceinline__ T boundary_distance(G<DevGeometry<T>>& g, const T* x,
             }
             *prim = kGridPrimTag | (int)(st + bk);   // resolved through cell_prim when needed
             return m_sqrt(best);
+          }
+        }
+      }
+    }
+    if constexpr (GEOM == GK_TRIMESH && DIM == 3) {
+      if (g.grid_nx > 0) {
+        // candidate grid: scan the list of the cell that contains x, nearest to the cell
+        // centre first, until a candidate's centre distance exceeds |x - centre| + best
+        T f[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) f[i] = (x[i] - g.grid_lo[i]) * g.grid_inv_h;
+        if (f[0] >= (T)0 && f[1] >= (T)0 && f[2] >= (T)0 && f[0] < (T)g.grid_nx && f[1] < (T)g.grid_ny &&
+            f[2] < (T)g.grid_nz) {
+          const int ix = (int)f[0], iy = (int)f[1], iz = (int)f[2];
+          const WOS_GLOBAL MeshCell<T>* rec =
+              (const WOS_GLOBAL MeshCell<T>*)g.cells + ((iz * g.grid_ny + iy) * g.grid_nx + ix);
+          const uint32_t n = rec->count, st = rec->start;
+          const T tail = rec->tail;
+          if (n > 0) {
+            const WOS_GLOBAL int32_t* cp = gptr(g.cell_prim) + st;
+            const WOS_GLOBAL T* dc = gptr(g.cell_dc) + st;
+            const WOS_GLOBAL T* prims = gptr(g.prims);
+            const T ox = x[0] - m_fma((T)ix + (T)0.5, g.grid_h, g.grid_lo[0]);
+            const T oy = x[1] - m_fma((T)iy + (T)0.5, g.grid_h, g.grid_lo[1]);
+            const T oz = x[2] - m_fma((T)iz + (T)0.5, g.grid_h, g.grid_lo[2]);
+            const T r_pc = m_sqrt(m_fma(ox, ox, m_fma(oy, oy, oz * oz)));
+            T best = Consts<T>::kInf;
+            int bp = 0;
+            uint32_t k = 0;
+            for (; k < n; ++k) {
+              const T lim = dc[k] - r_pc;
+              if (lim > (T)0 && lim * lim >= best) break;
+              const int pi = cp[k];
+              const T d2 = triangle_dist2<T>(x, prims + (size_t)pi * kPrimStride3);
+              if (d2 < best) {
+                best = d2;
+                bp = pi;
+              }
+            }
+            if constexpr (COUNT) {
+              ++tally->cells;
+              tally->prims += k;
+            }
+            // every triangle left off the list lies at least tail - r_pc from x
+            const T d = m_sqrt(best);
+            const T lb = tail - r_pc;
+            if (k < n || d <= lb) {
+              *prim = bp;
+              return d;
+            }
+            if (BOUND && lb >= g.grid_lb_min) {
+              *prim = bp;
+              return lb;
+            }
           }
         }
       }

@@ -298,7 +298,7 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
             flag = kFlagCapped;
           } else {
             int prim;
-            const T d = boundary_distance<T, DIM, GEOM, COUNT>(P.geom, x, &prim, &tally, lds_stack, last_prim);
+            const T d = boundary_distance<T, DIM, GEOM, COUNT, true>(P.geom, x, &prim, &tally, lds_stack, last_prim);
             last_prim = prim;
             ++nsteps;
             if (!(d == d)) {
@@ -382,7 +382,7 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
             flag = kFlagCapped;
           } else {
             int prim;
-            const T d = boundary_distance<T, DIM, GEOM, COUNT>(P.geom, x, &prim, &tally, lds_stack, last_prim);
+            const T d = boundary_distance<T, DIM, GEOM, COUNT, true>(P.geom, x, &prim, &tally, lds_stack, last_prim);
             last_prim = prim;
             ++nsteps;
             if (!(d == d)) {

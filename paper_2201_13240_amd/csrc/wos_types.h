@@ -29,10 +29,9 @@ struct DevField {
   T prm[8];          // tanh: axis, x0, 1/width ; tanh_drift: axis, x0, 1/width, A, B, omega*width/(A^2-B^2), ln A, omega
 };
 
-// Binary BVH node that stores the bounds of both children, so a visit tests both
-// boxes with one load. A child reference c >= 0 is an inner node index; c < 0 encodes
-// a leaf: -1 - c = (first primitive << 3) | count, count in 1..7.
 constexpr int kCellInline = 7;
+// Length of the candidate lists of the triangle-mesh grid.
+constexpr int kMeshCellList = 16;
 
 // One cell of the polygon candidate grid: `count` candidates at cell_prim / cell_segs /
 // cell_dc [start, start + count), the first kCellInline also held here (zero-padded) as
@@ -47,6 +46,19 @@ struct __attribute__((aligned(16))) CellRec {
   T inv_len2[kCellInline];
 };
 
+// One cell of the triangle-mesh candidate grid: `count` candidates at cell_prim /
+// cell_dc [start, start + count), and `tail`, a lower bound of the centre distance of
+// every triangle left off the list (+inf: none was).
+template <typename T>
+struct __attribute__((aligned(16))) MeshCell {
+  uint32_t count;
+  uint32_t start;
+  T tail;
+};
+
+// Binary BVH node that stores the bounds of both children, so a visit tests both
+// boxes with one load. A child reference c >= 0 is an inner node index; c < 0 encodes
+// a leaf: -1 - c = (first primitive << 3) | count, count in 1..7.
 template <typename T, int DIM>
 struct BvhNode {
   T lo[2][DIM];
@@ -69,18 +81,22 @@ struct DevGeometry {
   const void* nodes;     // BvhNode<T, DIM>[n_nodes]
   const T* prims;        // polygon: [n][4] (x0, y0, x1, y1); trimesh: [n][12] (a, b, c, padding);
                          // SDF: [n][kSdfStride] CSG rows
-  // 2D polygons: uniform candidate grid (grid_nx = 0: none). Cell (i, j) covers
-  // [grid_lo + (i, j) h, grid_lo + (i + 1, j + 1) h]; its candidates are
-  // cell_prim[cell_start[c] .. cell_start[c + 1]) with their segments copied to cell_segs,
-  // nearest to the cell centre first; cell_dc holds a lower bound of each one's distance
-  // from the centre (the distance minus the rounding margin).
-  // cells[c] holds the list's length and start and a copy of its first kCellInline
-  // segments, so most queries read one record.
-  int32_t grid_nx, grid_ny;
-  T grid_lo[2];
+  // Uniform candidate grid of polygons and triangle meshes (grid_nx = 0: none). Cell
+  // (i, j[, k]) covers [grid_lo + (i, j, k) h, grid_lo + (i + 1, j + 1, k + 1) h]; its
+  // candidates are cell_prim[start .. start + count), nearest to the cell centre first;
+  // cell_dc holds a lower bound of each one's distance from the centre (the distance
+  // minus the rounding margin).
+  // Polygons: cells[c] is a CellRec with the list's length and start and a copy of its
+  // first kCellInline segments, so most queries read one record; cell_segs holds the
+  // segments of the whole list. Meshes: cells[c] is a MeshCell, cell (i, j, k) at
+  // (k ny + j) nx + i, and cell_prim holds triangle indices.
+  int32_t grid_nx, grid_ny, grid_nz;
+  int32_t grid_pad;
+  T grid_lo[3];
   T grid_inv_h;
   T grid_h;
-  const void* cells;     // CellRec<T>[nx * ny]
+  T grid_lb_min;         // meshes: smallest lower bound a walk step may take (>= h, > epsilon)
+  const void* cells;     // CellRec<T>[nx * ny] or MeshCell<T>[nx * ny * nz]
   const int32_t* cell_prim;
   const T* cell_segs;
   const T* cell_dc;

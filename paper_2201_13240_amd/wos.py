@@ -84,7 +84,7 @@ def lib():
         L.wos_problem_create.argtypes = [C.POINTER(ProblemDesc), C.c_int, C.POINTER(vp)]
         L.wos_problem_info.argtypes = [vp, dp, dp, dp]
         L.wos_problem_bvh_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i32), C.POINTER(i64)]
-        L.wos_problem_grid_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i64)]
+        L.wos_problem_grid_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i64)]
         L.wos_problem_destroy.argtypes = [vp]
         L.wos_solve.argtypes = [C.POINTER(BatchItem), i32, C.POINTER(Options), vp]
         L.wos_count_events.argtypes = [C.POINTER(BatchItem), i32, C.POINTER(Options), vp, vp]
@@ -221,9 +221,9 @@ class Problem:
         return {"nodes": n.value, "depth": dpt.value, "prims": p.value}
 
     def grid_info(self):
-        nx, ny, nc = C.c_int32(), C.c_int32(), C.c_int64()
-        _check(lib().wos_problem_grid_info(self.handle, C.byref(nx), C.byref(ny), C.byref(nc)))
-        return {"nx": nx.value, "ny": ny.value, "candidates": nc.value}
+        nx, ny, nz, nc = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64()
+        _check(lib().wos_problem_grid_info(self.handle, C.byref(nx), C.byref(ny), C.byref(nz), C.byref(nc)))
+        return {"nx": nx.value, "ny": ny.value, "nz": nz.value, "candidates": nc.value}
 
     @property
     def sigma_bar(self):
