@@ -72,9 +72,9 @@ int wos_version(void);
  *           domain, used to sample sigma'.
  * Polygons and meshes get an axis-aligned BVH (Sec. 7.1) and a candidate grid in front
  * of it, built on the host (for meshes with up to 16 threads). In cells deep inside a
- * mesh the walk's ball radius may be a certified lower bound of the distance, at least
- * the cell size and 2 epsilon: every ball stays inside the domain, as the walk needs
- * (Sec. 3), and no walk ends on such a value. Distance queries are exact. */
+ * mesh or a large polygon the walk's ball radius may be a certified lower bound of the
+ * distance, at least the cell size and 2 epsilon: every ball stays inside the domain, as
+ * the walk needs (Sec. 3), and no walk ends on such a value. Distance queries are exact. */
 typedef enum {
   WOS_GEOM_BALL = 0,
   WOS_GEOM_BOX = 1,
@@ -174,8 +174,8 @@ wos_status wos_problem_bvh_info(const wos_problem* p, int64_t* n_nodes, int32_t*
  * domains): a uniform grid (nx x ny cells in 2D, nz = 1; nx x ny x nz in 3D) whose cells
  * list every segment or triangle that can be nearest to a point of the cell; closest-point
  * queries then scan one short list instead of traversing the BVH (Sec. 7.1 answers them
- * with a BVH). A polygon cell whose list would be too long has none and uses the BVH; a
- * mesh cell keeps the 16 candidates nearest to its centre.
+ * with a BVH). A polygon cell with more than 128 candidates, and every mesh cell, keeps
+ * at most the 16 candidates nearest to its centre.
  * n_candidates: total list length. Any output pointer may be null. */
 wos_status wos_problem_grid_info(const wos_problem* p, int32_t* nx, int32_t* ny, int32_t* nz,
                                  int64_t* n_candidates);

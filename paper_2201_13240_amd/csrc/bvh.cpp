@@ -219,7 +219,7 @@ struct TriQuery {
 
 SegmentGrid build_segment_grid(const std::vector<double>& segs, int64_t n, const BvhTopology& topo,
                                const std::vector<double>& bounds, int64_t target_cells, double margin,
-                               int max_candidates) {
+                               int max_candidates, int deep_list) {
   SegmentGrid g;
   double lo[2] = {1e300, 1e300}, hi[2] = {-1e300, -1e300};
   for (int64_t i = 0; i < n; ++i)
@@ -242,6 +242,7 @@ SegmentGrid build_segment_grid(const std::vector<double>& segs, int64_t n, const
   SegQuery q{segs, topo, bounds};
   const int64_t ncell = (int64_t)g.nx * g.ny;
   g.start.resize(ncell + 1);
+  g.tail.assign(ncell, HUGE_VAL);
   g.start[0] = 0;
   for (int32_t j = 0; j < g.ny; ++j)
     for (int32_t i = 0; i < g.nx; ++i) {
@@ -254,13 +255,14 @@ SegmentGrid build_segment_grid(const std::vector<double>& segs, int64_t n, const
       q.within(topo.root, cx, cy, &r2, [&](int32_t s, double d2) {
         if (d2 <= r2) cand.emplace_back(d2, s);
       });
-      if (cand.size() <= (size_t)max_candidates) {   // else an empty list: use the BVH
-        std::sort(cand.begin(), cand.end());
-        for (const auto& c : cand) {
-          g.prim.push_back(c.second);
-          g.dc.push_back(std::sqrt(c.first));
-        }
+      std::sort(cand.begin(), cand.end());
+      // a list too long keeps its deep_list nearest candidates and the tail distance
+      const size_t n_keep = cand.size() <= (size_t)max_candidates ? cand.size() : (size_t)deep_list;
+      for (size_t e = 0; e < n_keep; ++e) {
+        g.prim.push_back(cand[e].second);
+        g.dc.push_back(std::sqrt(cand[e].first));
       }
+      g.tail[(int64_t)j * g.nx + i] = n_keep < cand.size() ? std::sqrt(cand[n_keep].first) : HUGE_VAL;
       g.start[(int64_t)j * g.nx + i + 1] = (uint32_t)g.prim.size();
     }
   return g;

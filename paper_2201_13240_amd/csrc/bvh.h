@@ -39,18 +39,20 @@ struct SegmentGrid {
   std::vector<uint32_t> start;   // [nx * ny * nz + 1], cell (i, j, k) at (k * ny + j) * nx + i
   std::vector<int32_t> prim;     // candidate indices (leaf order), nearest to the cell centre first
   std::vector<double> dc;        // distance from the cell centre to each candidate (ascending per cell)
-  std::vector<double> tail;      // triangle grids: per cell, the centre distance of the nearest
-                                 // candidate left off its list (+inf: the list is complete)
+  std::vector<double> tail;      // per cell, the centre distance of the nearest candidate left
+                                 // off its list (+inf: the list is complete)
 };
 
 // segs: [n][4] in leaf order; topo/bounds: the BVH over them (child bounds as produced
-// by bvh_child_bounds<double>). target_cells bounds the grid size. A cell with more
-// than max_candidates candidates gets an empty list (its queries use the BVH). Each list
-// is sorted by distance from the cell centre, so a query at p can stop once
-// dc - |p - centre| exceeds its best distance (triangle inequality).
+// by bvh_child_bounds<double>). target_cells bounds the grid size. Each list is sorted by
+// distance from the cell centre, so a query at p can stop once dc - |p - centre| exceeds
+// its best distance (triangle inequality). A cell with more than max_candidates
+// candidates keeps only the deep_list nearest ones and records in `tail` the centre
+// distance of the first one left off (+inf for complete lists): every omitted segment
+// lies at least tail - |p - centre| from p.
 SegmentGrid build_segment_grid(const std::vector<double>& segs, int64_t n, const BvhTopology& topo,
                                const std::vector<double>& bounds, int64_t target_cells, double margin,
-                               int max_candidates);
+                               int max_candidates, int deep_list);
 
 // The same for triangles: tris [n][12] (a, b, c, padding) in leaf order, a 3D grid of
 // cubic cells. A cell keeps at most max_candidates of its candidates, the nearest to its

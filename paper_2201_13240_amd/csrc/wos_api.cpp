@@ -331,13 +331,14 @@ wos_status build_geometry(const wos_problem_desc& d, HostGeometry& g) {
   bvh_child_bounds<float>(g.topo, plo32, phi32, pdim, g.bounds32);
   if (G.kind == WOS_GEOM_POLYGON) {
     // about 64 cells per segment, between 64^2 and 2^20 cells, lists of up to 128
-    // candidates (longer ones, deep inside large polygons, leave the query to the BVH);
-    // the margin covers FP32 rounding of the query point and of the cell index
+    // candidates (longer ones, deep inside large polygons, keep their 16 nearest); the
+    // margin covers FP32 rounding of the query point and of the cell index
     double scale = 0;
     for (double c : g.prims64) scale = std::max(scale, std::fabs(c));
     const int64_t target = std::min<int64_t>(1 << 20, std::max<int64_t>(4096, 64 * n));
     g.grid_margin = 4e-6 * (scale + 1.0);
-    g.grid = build_segment_grid(g.prims64, n, g.topo, g.bounds64, target, g.grid_margin, 128);
+    g.grid = build_segment_grid(g.prims64, n, g.topo, g.bounds64, target, g.grid_margin, kPolygonCellMax,
+                                kPolygonDeepList);
   } else {
     // meshes: about 64 cells per triangle, between 32^3 and 2^21 cells, lists of the 16
     // candidates nearest to the cell centre
@@ -506,6 +507,7 @@ size_t layout_problem(Blob& blob, const wos_problem_desc& d, const HostGeometry&
         G.grid_lo[1] = (T)g.grid.lo[1];
         G.grid_inv_h = (T)(1.0 / g.grid.h);
         G.grid_h = (T)g.grid.h;
+        G.grid_lb_min = (T)std::max(g.grid.h, 2.0 * d.epsilon);
         const size_t nc = g.grid.prim.size();
         const size_t ncell = g.grid.start.size() - 1;
         grid_start_off = blob.alloc(ncell * sizeof(CellRec<T>));
@@ -515,6 +517,8 @@ size_t layout_problem(Blob& blob, const wos_problem_desc& d, const HostGeometry&
           std::memset(&r, 0, sizeof(r));
           r.start = g.grid.start[c];
           r.count = g.grid.start[c + 1] - g.grid.start[c];
+          r.tail = std::isfinite(g.grid.tail[c]) ? (T)(g.grid.tail[c] - g.grid_margin)
+                                                 : std::numeric_limits<T>::infinity();
           for (uint32_t k = 0; k < std::min<uint32_t>(r.count, kCellInline); ++k) {
             const double* sg = g.prims64.data() + (size_t)g.grid.prim[r.start + k] * 4;
             r.seg[k][0] = (T)sg[0];

@@ -1379,11 +1379,12 @@ __device__ __forceinline__ T sdf_value(G<DevGeometry<T>>& g, const T* x, int* ac
 }
 
 // Distance d from x to the boundary (Alg. 1, first step); prim receives what
-// closest_point needs to recover xbar. With BOUND, a triangle mesh may answer with a
-// certified lower bound of d instead (at least the cell size and twice epsilon) where the
-// truncated list of its grid cell cannot decide the nearest triangle (points deep inside,
-// where many triangles are nearly equidistant): the ball of that radius still lies inside
-// the domain, which is all the walk's step needs, and a walk never ends on such a value.
+// closest_point needs to recover xbar. With BOUND, a polygon or a triangle mesh may
+// answer with a certified lower bound of d instead (at least the cell size and twice
+// epsilon) where the truncated list of its grid cell cannot decide the nearest primitive
+// (points deep inside, where many primitives are nearly equidistant): the ball of that
+// radius still lies inside the domain, which is all the walk's step needs, and a walk
+// never ends on such a value.
 template <typename T, int DIM, int GEOM, bool COUNT = false, bool BOUND = false>
 __device__ __forceinline__ T boundary_distance(G<DevGeometry<T>>& g, const T* x, int* prim, Tally* tally = nullptr,
                                                LdsStack<T> lds = LdsStack<T>{nullptr, nullptr, 0, 0}, int hint = -1) {
@@ -1434,6 +1435,7 @@ __device__ __forceinline__ T boundary_distance(G<DevGeometry<T>>& g, const T* x,
               }
             }
             uint32_t k = kCellInline;
+            T lb = Consts<T>::kInf;
             if (n > (uint32_t)kCellInline) {
               // the rest of the list, nearest to the cell centre first: stop once a
               // candidate's centre distance exceeds |x - centre| + best
@@ -1452,13 +1454,23 @@ __device__ __forceinline__ T boundary_distance(G<DevGeometry<T>>& g, const T* x,
                   bk = k;
                 }
               }
+              // a truncated list scanned to its end: the segments left off lie at
+              // least tail - r_pc from x (complete lists have tail = +inf)
+              if (k >= n) lb = rec->tail - r_pc;
             }
             if constexpr (COUNT) {
               ++tally->cells;
               tally->prims += k < n ? k : n;
             }
-            *prim = kGridPrimTag | (int)(st + bk);   // resolved through cell_prim when needed
-            return m_sqrt(best);
+            const T d = m_sqrt(best);
+            if (d <= lb) {
+              *prim = kGridPrimTag | (int)(st + bk);   // resolved through cell_prim when needed
+              return d;
+            }
+            if (BOUND && lb >= g.grid_lb_min) {
+              *prim = kGridPrimTag | (int)(st + bk);
+              return lb;
+            }
           }
         }
       }

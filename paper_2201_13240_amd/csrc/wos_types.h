@@ -30,18 +30,25 @@ struct DevField {
 };
 
 constexpr int kCellInline = 7;
-// Length of the candidate lists of the triangle-mesh grid.
+// Length of the candidate lists of the triangle-mesh grid, and of the truncated lists
+// of polygon grid cells with more than kPolygonCellMax candidates.
 constexpr int kMeshCellList = 16;
+constexpr int kPolygonCellMax = 128;
+constexpr int kPolygonDeepList = 16;
 
 // One cell of the polygon candidate grid: `count` candidates at cell_prim / cell_segs /
 // cell_dc [start, start + count), the first kCellInline also held here (zero-padded) as
 // start point, edge vector and reciprocal squared length (x0, y0, ex, ey), 1/|e|^2, so
-// that their distance needs no division.
+// that their distance needs no division. `tail` bounds from below the centre distance
+// of every segment left off a truncated list (+inf: the list is complete).
 template <typename T>
 struct __attribute__((aligned(16))) CellRec {
   uint32_t count;
   uint32_t start;
-  uint32_t pad[2];
+  union {
+    T tail;
+    uint32_t pad[2];
+  };
   T seg[kCellInline][4];
   T inv_len2[kCellInline];
 };
@@ -95,7 +102,7 @@ struct DevGeometry {
   T grid_lo[3];
   T grid_inv_h;
   T grid_h;
-  T grid_lb_min;         // meshes: smallest lower bound a walk step may take (>= h, > epsilon)
+  T grid_lb_min;         // smallest lower bound a walk step may take (>= h, > epsilon)
   const void* cells;     // CellRec<T>[nx * ny] or MeshCell<T>[nx * ny * nz]
   const int32_t* cell_prim;
   const T* cell_segs;
