@@ -1,8 +1,8 @@
-"""The candidate grid of triangle meshes through the C ABI: exact closest-point queries
-everywhere (deep points whose truncated cell lists cannot decide fall back to the BVH),
-and walks that step by a certified lower bound of the distance in those cells, whose
-estimates keep the exact solution (Sec. 3: the mean value and Green's function
-identities hold on any ball inside the domain) at a step count close to the
+"""The candidate grids of triangle meshes and large polygons through the C ABI: exact
+closest-point queries everywhere (deep points whose truncated cell lists cannot decide
+fall back to the BVH), and walks that step by a certified lower bound of the distance in
+those cells, whose estimates keep the exact solution (Sec. 3: the mean value and Green's
+function identities hold on any ball inside the domain) at a step count close to the
 largest-ball walk of the oracle."""
 import numpy as np
 import pytest
@@ -91,3 +91,26 @@ def test_step_count_close_to_largest_ball_walks(W, oracle):
     ratio = (r["steps"].sum() / 8192) / (o["steps"].sum() / 2048)
     assert 0.98 < ratio < 1.05, ratio
     assert_parity(r["mean"], r["se"], o["mean"], o["se"], "screened ico1280", 2e-6)
+
+
+def test_large_polygon_deep_cells(W, oracle):
+    """A 4096-edge star polygon, whose cells deep inside list more than 128 candidates:
+    exact distances there, and walks from deep points that reproduce harmonic data with
+    almost no BVH visits."""
+    geom = WL.star_polygon(np.random.default_rng(9), 4096)
+    prob = WL.make_problem(2, geom, ONE, Z, Z, Z, WL.field_manufactured("expcos"), 1e-4)
+    h = W.Problem(prob)
+    pts = WL.sample_inside(np.random.default_rng(10), geom, 2, 4000)
+    rd, _ = oracle.distance(prob, pts)
+    deep = pts[np.argsort(-rd)[:400]]
+    rdd, _ = oracle.distance(prob, deep)
+    for precision, tol in (("fp64", 4e-12), ("fp32", 8e-6)):
+        d, _ = W.eval_distance(h, dev(deep), precision)
+        np.testing.assert_allclose(d.cpu().numpy(), rdd, rtol=0, atol=tol)
+    sel = deep[:32]
+    r = gpu_solve(W, h, sel, 8192, "fp32", seed=11)
+    ex = np.exp(sel[:, 0]) * np.cos(sel[:, 1])
+    assert_parity(r["mean"], r["se"], ex, 0 * ex, "deep star4096", 2e-6)
+    P = dev(sel)
+    ev = W.count_events([(h, P, W.Accumulators(P.shape[0]), 0)], W.options(precision="fp32", walks=256, seed=12))
+    assert ev["grid_cells"] == ev["steps"] and ev["bvh_nodes"] < 1e-3 * ev["steps"]
