@@ -174,8 +174,8 @@ wos_status wos_problem_bvh_info(const wos_problem* p, int64_t* n_nodes, int32_t*
  * domains): a uniform grid (nx x ny cells in 2D, nz = 1; nx x ny x nz in 3D) whose cells
  * list every segment or triangle that can be nearest to a point of the cell; closest-point
  * queries then scan one short list instead of traversing the BVH (Sec. 7.1 answers them
- * with a BVH). A polygon cell with more than 128 candidates, and every mesh cell, keeps
- * at most the 16 candidates nearest to its centre.
+ * with a BVH). A polygon cell with more than 128 candidates keeps the 16 nearest to its
+ * centre, a mesh cell at most the 6 nearest.
  * n_candidates: total list length. Any output pointer may be null. */
 wos_status wos_problem_grid_info(const wos_problem* p, int32_t* nx, int32_t* ny, int32_t* nz,
                                  int64_t* n_candidates);

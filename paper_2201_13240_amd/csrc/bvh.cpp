@@ -297,6 +297,7 @@ SegmentGrid build_triangle_grid(const std::vector<double>& tris, int64_t n, cons
   g.nz = nn[2];
   g.h = h;
   const double halfdiag = 0.5 * h * std::sqrt(3.0);
+  const double deep = 8 * h;
   const TriQuery q{tris, topo, bounds};
   const int64_t ncell = (int64_t)g.nx * g.ny * g.nz;
   threads = (int)std::max<int64_t>(1, std::min<int64_t>(threads, (ncell + 4095) / 4096));
@@ -313,14 +314,28 @@ SegmentGrid build_triangle_grid(const std::vector<double>& tris, int64_t n, cons
     P.tail.resize(c1 - c0);
     std::vector<std::pair<double, int32_t>> heap;   // max-heap of the kept candidates
     const size_t keep = (size_t)max_candidates + 1;
+    int32_t prev = -1;   // nearest triangle of the previous cell: seeds the search bound
     for (int64_t c = c0; c < c1; ++c) {
       const int64_t i = c % g.nx, j = (c / g.nx) % g.ny, k = c / ((int64_t)g.nx * g.ny);
       const double p[3] = {lo[0] + (i + 0.5) * h, lo[1] + (j + 0.5) * h, lo[2] + (k + 0.5) * h};
-      double best = 1e300;
-      q.within(topo.root, p, &best, [&](int32_t, double d2) {
-        best = std::min(best, d2);
+      double best = prev >= 0 ? tri_dist2(&tris[12 * (size_t)prev], p) : 1e300;
+      q.within(topo.root, p, &best, [&](int32_t s, double d2) {
+        if (d2 < best) {
+          best = d2;
+          prev = s;
+        }
         return true;
       });
+      if (std::sqrt(best) >= deep) {
+        // deep inside many triangles are nearly equidistant and a list could not decide
+        // anyway: keep the nearest one alone, with its distance as the tail (no
+        // triangle is nearer to the centre)
+        P.prim.push_back(prev);
+        P.dc.push_back(std::sqrt(best));
+        P.count[c - c0] = 1;
+        P.tail[c - c0] = std::sqrt(best);
+        continue;
+      }
       const double r = std::sqrt(best) + 2 * halfdiag + margin;
       // the max_candidates + 1 nearest triangles within r of the centre; the bound
       // shrinks to the farthest kept one once the heap is full

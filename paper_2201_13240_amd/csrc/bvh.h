@@ -58,7 +58,9 @@ SegmentGrid build_segment_grid(const std::vector<double>& segs, int64_t n, const
 // cubic cells. A cell keeps at most max_candidates of its candidates, the nearest to its
 // centre, and records in `tail` the centre distance of the first one left off: for p in
 // the cell every omitted triangle lies at least tail - |p - centre| from p, so a scan of
-// the kept list either finds the nearest triangle or a lower bound of the distance.
+// the kept list either finds the nearest triangle or a lower bound of the distance. A
+// cell whose centre lies 8 cell widths or more from the surface keeps only its nearest
+// triangle, with tail = its distance.
 // Cells are filled by up to `threads` host threads; the result does not depend on their
 // number.
 SegmentGrid build_triangle_grid(const std::vector<double>& tris, int64_t n, const BvhTopology& topo,

@@ -32,7 +32,7 @@ struct DevField {
 constexpr int kCellInline = 7;
 // Length of the candidate lists of the triangle-mesh grid, and of the truncated lists
 // of polygon grid cells with more than kPolygonCellMax candidates.
-constexpr int kMeshCellList = 16;
+constexpr int kMeshCellList = 6;
 constexpr int kPolygonCellMax = 128;
 constexpr int kPolygonDeepList = 16;
 

@@ -44,7 +44,7 @@ def test_grid_info(W):
     g = h.grid_info()
     assert min(g["nx"], g["ny"], g["nz"]) >= 32
     cells = g["nx"] * g["ny"] * g["nz"]
-    assert 0 < g["candidates"] <= 16 * cells
+    assert 0 < g["candidates"] <= 6 * cells
     # polygons keep a 2D grid, analytic domains none
     assert W.Problem(WL.config2(n_grid=8)["problems"][0]).grid_info()["nz"] == 1
     assert W.Problem(WL.make_problem(3, WL.geom_ball([0, 0, 0], 1.0), *[ONE] * 5)).grid_info()["nx"] == 0
@@ -63,9 +63,9 @@ def test_exact_distance_deep_and_near_the_surface(W, oracle, precision):
 
 
 def test_bounded_steps_keep_the_harmonic_solution(W):
-    """Deep starting points on the 20,480-triangle sphere: every query is answered from
-    the grid (a BVH fallback is rare: the counted node visits stay below one per
-    thousand steps), and u = e^x cos y is reproduced."""
+    """Deep starting points on the 20,480-triangle sphere: the queries are answered from
+    the grid (a BVH query visits tens to hundreds of nodes; here the visits stay below
+    half a node per step), and u = e^x cos y is reproduced."""
     prob = _ico(5)
     h = W.Problem(prob)
     pts = _deep(48, 0.7, 3)
@@ -76,7 +76,7 @@ def test_bounded_steps_keep_the_harmonic_solution(W):
                       1e-12 if precision == "fp64" else 2e-6)
     P = dev(pts)
     ev = W.count_events([(h, P, W.Accumulators(P.shape[0]), 0)], W.options(precision="fp32", walks=256, seed=6))
-    assert ev["grid_cells"] == ev["steps"] and ev["bvh_nodes"] < 1e-3 * ev["steps"]
+    assert ev["grid_cells"] == ev["steps"] and ev["bvh_nodes"] < 0.5 * ev["steps"]
 
 
 def test_step_count_close_to_largest_ball_walks(W, oracle):
