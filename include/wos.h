@@ -71,10 +71,12 @@ int wos_version(void);
  *           beyond dim are ignored. lo[dim], hi[dim]: a box that holds the (bounded)
  *           domain, used to sample sigma'.
  * Polygons and meshes get an axis-aligned BVH (Sec. 7.1) and a candidate grid in front
- * of it, built on the host (for meshes with up to 16 threads). In cells deep inside a
- * mesh or a large polygon the walk's ball radius may be a certified lower bound of the
- * distance, at least the cell size and 2 epsilon: every ball stays inside the domain, as
- * the walk needs (Sec. 3), and no walk ends on such a value. Distance queries are exact. */
+ * of it, built on the host (for meshes with up to 16 threads). Where a grid cell's
+ * truncated list cannot decide the nearest primitive (mostly deep inside a mesh or a
+ * large polygon), the walk's ball radius may be a certified lower bound of the distance,
+ * at least 2 epsilon and a cell (a quarter cell for meshes): every ball stays inside the
+ * domain, as the walk needs (Sec. 3), and no walk ends on such a value. Distance
+ * queries are exact. */
 typedef enum {
   WOS_GEOM_BALL = 0,
   WOS_GEOM_BOX = 1,

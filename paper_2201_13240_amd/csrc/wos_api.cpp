@@ -552,7 +552,9 @@ size_t layout_problem(Blob& blob, const wos_problem_desc& d, const HostGeometry&
         for (int k = 0; k < 3; ++k) G.grid_lo[k] = (T)g.grid.lo[k];
         G.grid_inv_h = (T)(1.0 / g.grid.h);
         G.grid_h = (T)g.grid.h;
-        G.grid_lb_min = (T)std::max(g.grid.h, 2.0 * d.epsilon);
+        // a quarter cell: lower, the walks make more steps; higher, more queries take the
+        // BVH, which a whole wave then waits for (h: 11% slower on the perturbed icosphere)
+        G.grid_lb_min = (T)std::max(0.25 * g.grid.h, 2.0 * d.epsilon);
         const size_t nc = g.grid.prim.size();
         const size_t ncell = g.grid.start.size() - 1;
         grid_start_off = blob.alloc(ncell * sizeof(MeshCell<T>));

@@ -102,7 +102,7 @@ struct DevGeometry {
   T grid_lo[3];
   T grid_inv_h;
   T grid_h;
-  T grid_lb_min;         // smallest lower bound a walk step may take (>= h, > epsilon)
+  T grid_lb_min;         // smallest lower bound a walk step may take (> 2 epsilon)
   const void* cells;     // CellRec<T>[nx * ny] or MeshCell<T>[nx * ny * nz]
   const int32_t* cell_prim;
   const T* cell_segs;
