@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from paper_2201_13240_amd import workloads as WL
-from tests.gpu_common import dev, gpu_solve, torch_cuda
+from tests.gpu_common import dev, gpu_solve, gpu_solve_grad, torch_cuda
 from tests.parity import assert_parity
 
 pytestmark = pytest.mark.gpu
@@ -114,3 +114,25 @@ def test_large_polygon_deep_cells(W, oracle):
     P = dev(sel)
     ev = W.count_events([(h, P, W.Accumulators(P.shape[0]), 0)], W.options(precision="fp32", walks=256, seed=12))
     assert ev["grid_cells"] == ev["steps"] and ev["bvh_nodes"] < 1e-3 * ev["steps"]
+
+
+def test_bounded_first_ball_gradient_and_next_flight(W, oracle):
+    """The first ball of a walk from a deep point may be a bounded one: the gradient
+    estimate (supplemental Sec. 2) still matches the exact gradient of harmonic data, and
+    next flight (Sec. 5.2) still matches the oracle's next flight with exact balls."""
+    prob = _ico(5)
+    h = W.Problem(prob)
+    pts = _deep(32, 0.6, 13)
+    r = gpu_solve_grad(W, h, pts, 8192, "fp32", seed=14)
+    ex = np.exp(pts[:, 0]) * np.cos(pts[:, 1])
+    assert_parity(r["mean"], r["se"], ex, 0 * ex, "deep gradient walks", 2e-6)
+    gex = np.c_[ex, -np.exp(pts[:, 0]) * np.sin(pts[:, 1]), 0 * ex]
+    assert_parity(r["grad_mean"].ravel(), r["grad_se"].ravel(), gex.ravel(), 0 * gex.ravel(), "deep gradient", 2e-6)
+    small = _ico(3, sigma=WL.field_const(4.0), source=ONE)
+    hs = W.Problem(small, sigma_bar=6.0)
+    sel = _deep(24, 0.6, 15)
+    o = oracle.solve(small, sel, 1024, 6.0, seed=16, variant=2)
+    for precision in ("fp32", "fp64"):
+        g = gpu_solve(W, hs, sel, 4096, precision, seed=17, variant=2)
+        assert_parity(g["mean"], g["se"], o["mean"], o["se"], f"next flight ico1280 {precision}",
+                      1e-12 if precision == "fp64" else 2e-6)
