@@ -74,7 +74,7 @@ int wos_version(void);
  * of it, built on the host (for meshes with up to 16 threads). Where a grid cell's
  * truncated list cannot decide the nearest primitive (mostly deep inside a mesh or a
  * large polygon), the walk's ball radius may be a certified lower bound of the distance,
- * at least 2 epsilon and a cell (a quarter cell for meshes): every ball stays inside the
+ * at least 2 epsilon and a quarter of the cell size: every ball stays inside the
  * domain, as the walk needs (Sec. 3), and no walk ends on such a value. Distance
  * queries are exact. */
 typedef enum {
@@ -176,7 +176,7 @@ wos_status wos_problem_bvh_info(const wos_problem* p, int64_t* n_nodes, int32_t*
  * domains): a uniform grid (nx x ny cells in 2D, nz = 1; nx x ny x nz in 3D) whose cells
  * list every segment or triangle that can be nearest to a point of the cell; closest-point
  * queries then scan one short list instead of traversing the BVH (Sec. 7.1 answers them
- * with a BVH). A polygon cell with more than 128 candidates keeps the 16 nearest to its
+ * with a BVH). A polygon cell with more than 32 candidates keeps the 16 nearest to its
  * centre, a mesh cell at most the 6 nearest.
  * n_candidates: total list length. Any output pointer may be null. */
 wos_status wos_problem_grid_info(const wos_problem* p, int32_t* nx, int32_t* ny, int32_t* nz,

@@ -330,7 +330,7 @@ wos_status build_geometry(const wos_problem_desc& d, HostGeometry& g) {
   bvh_child_bounds<double>(g.topo, plo64, phi64, pdim, g.bounds64);
   bvh_child_bounds<float>(g.topo, plo32, phi32, pdim, g.bounds32);
   if (G.kind == WOS_GEOM_POLYGON) {
-    // about 64 cells per segment, between 64^2 and 2^20 cells, lists of up to 128
+    // about 64 cells per segment, between 64^2 and 2^20 cells, lists of up to 32
     // candidates (longer ones, deep inside large polygons, keep their 16 nearest); the
     // margin covers FP32 rounding of the query point and of the cell index
     double scale = 0;
@@ -509,7 +509,7 @@ size_t layout_problem(Blob& blob, const wos_problem_desc& d, const HostGeometry&
         G.grid_lo[1] = (T)g.grid.lo[1];
         G.grid_inv_h = (T)(1.0 / g.grid.h);
         G.grid_h = (T)g.grid.h;
-        G.grid_lb_min = (T)std::max(g.grid.h, 2.0 * d.epsilon);
+        G.grid_lb_min = (T)std::max(0.25 * g.grid.h, 2.0 * d.epsilon);
         const size_t nc = g.grid.prim.size();
         const size_t ncell = g.grid.start.size() - 1;
         grid_start_off = blob.alloc(ncell * sizeof(CellRec<T>));

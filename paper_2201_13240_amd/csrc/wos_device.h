@@ -1380,9 +1380,9 @@ __device__ __forceinline__ T sdf_value(G<DevGeometry<T>>& g, const T* x, int* ac
 
 // Distance d from x to the boundary (Alg. 1, first step); prim receives what
 // closest_point needs to recover xbar. With BOUND, a polygon or a triangle mesh may
-// answer with a certified lower bound of d instead (at least grid_lb_min: a cell size for
-// polygons, a quarter cell for meshes, and twice epsilon) where the truncated list of its
-// grid cell cannot decide the nearest primitive
+// answer with a certified lower bound of d instead (at least grid_lb_min: a quarter cell
+// and twice epsilon) where the truncated list of its grid cell cannot decide the nearest
+// primitive
 // (points deep inside, where many primitives are nearly equidistant): the ball of that
 // radius still lies inside the domain, which is all the walk's step needs, and a walk
 // never ends on such a value.

@@ -33,7 +33,7 @@ constexpr int kCellInline = 7;
 // Length of the candidate lists of the triangle-mesh grid, and of the truncated lists
 // of polygon grid cells with more than kPolygonCellMax candidates.
 constexpr int kMeshCellList = 6;
-constexpr int kPolygonCellMax = 128;
+constexpr int kPolygonCellMax = 32;
 constexpr int kPolygonDeepList = 16;
 
 // One cell of the polygon candidate grid: `count` candidates at cell_prim / cell_segs /
