@@ -470,8 +470,8 @@ def main():
         copy_probe()
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the walk is embarrassingly parallel and would shard by walk range, see DESIGN.md",
+        print(f"bench.py: the benchmark runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the walks are independent and would shard by walk range, one process per GPU",
               file=sys.stderr)
         sys.exit(2)
     import torch
