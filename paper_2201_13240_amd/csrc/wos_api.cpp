@@ -30,6 +30,21 @@ wos_status fail(wos_status s, const std::string& msg) {
   return s;
 }
 
+// Runs f and turns a C++ exception (a failed host allocation, a thread that could not
+// start) into a status, so that none crosses the C ABI.
+template <typename F>
+wos_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return fail(WOS_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(WOS_ERR_INTERNAL, std::string("host error: ") + e.what());
+  } catch (...) {
+    return fail(WOS_ERR_INTERNAL, "unknown host error");
+  }
+}
+
 #define WOS_HIP(call)                                                                       \
   do {                                                                                      \
     hipError_t e_ = (call);                                                                 \
@@ -614,7 +629,7 @@ const char* wos_last_error(void) { return g_error.c_str(); }
 
 int wos_version(void) { return 100; }
 
-wos_status wos_problem_create(const wos_problem_desc* desc, int device, wos_problem** out) {
+static wos_status problem_create_impl(const wos_problem_desc* desc, int device, wos_problem** out) {
   if (!desc || !out) return fail(WOS_ERR_INVALID_ARG, "null argument");
   *out = nullptr;
   const wos_problem_desc& d = *desc;
@@ -762,6 +777,10 @@ wos_status wos_problem_create(const wos_problem_desc* desc, int device, wos_prob
   }
   *out = p;
   return WOS_OK;
+}
+
+wos_status wos_problem_create(const wos_problem_desc* desc, int device, wos_problem** out) {
+  return guarded([&] { return problem_create_impl(desc, device, out); });
 }
 
 wos_status wos_problem_info(const wos_problem* p, double* sp_min, double* sp_max, double* sigma_bar) {
@@ -1185,13 +1204,13 @@ static wos_status solve_impl(const wos_batch_item* items, int32_t n_items, const
 }
 
 wos_status wos_solve(const wos_batch_item* items, int32_t n_items, const wos_options* opt, void* stream) {
-  return solve_impl(items, n_items, opt, nullptr, stream);
+  return guarded([&] { return solve_impl(items, n_items, opt, nullptr, stream); });
 }
 
 wos_status wos_count_events(const wos_batch_item* items, int32_t n_items, const wos_options* opt, uint64_t* events,
                             void* stream) {
   if (!events) return fail(WOS_ERR_INVALID_ARG, "null events");
-  return solve_impl(items, n_items, opt, events, stream);
+  return guarded([&] { return solve_impl(items, n_items, opt, events, stream); });
 }
 
 wos_status wos_finalize(const double* sum, const double* sum_sq, const uint64_t* n_walks, int64_t n, double* mean,
@@ -1380,8 +1399,8 @@ wos_status wos_finalize_grad(const double* grad_sum, const double* grad_sum_sq, 
   return WOS_OK;
 }
 
-wos_status wos_plan_create(const wos_batch_item* items, int32_t n_items, const wos_options* opt, void* stream,
-                           wos_plan** out) {
+static wos_status plan_create_impl(const wos_batch_item* items, int32_t n_items, const wos_options* opt,
+                                   void* stream, wos_plan** out) {
   wos_status r = plan_build(items, n_items, opt, stream, out);
   if (r != WOS_OK || opt->block_size != 0 || opt->tile_walks != 0) return r;
   wos_plan* P = *out;
@@ -1406,6 +1425,11 @@ wos_status wos_plan_create(const wos_batch_item* items, int32_t n_items, const w
   o.block_size = (int32_t)block;
   o.tile_walks = (int32_t)tile;
   return plan_build(items, n_items, &o, stream, out);
+}
+
+wos_status wos_plan_create(const wos_batch_item* items, int32_t n_items, const wos_options* opt, void* stream,
+                           wos_plan** out) {
+  return guarded([&] { return plan_create_impl(items, n_items, opt, stream, out); });
 }
 
 wos_status wos_plan_time(wos_plan* P, uint64_t seed, uint64_t walk_offset_add, void* stream, double* walker_ms,
