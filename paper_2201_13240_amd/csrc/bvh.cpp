@@ -232,7 +232,12 @@ SegmentGrid build_segment_grid(const std::vector<double>& segs, int64_t n, const
   const double pad = 1e-6 * std::max(ex, ey) + 1e-12;
   lo[0] -= pad;
   lo[1] -= pad;
-  const double h = std::sqrt((ex + 2 * pad) * (ey + 2 * pad) / (double)target_cells);
+  double h = std::sqrt((ex + 2 * pad) * (ey + 2 * pad) / (double)target_cells);
+  // a nearly flat set (degenerate input) would make the cells tiny: coarsen until the
+  // grid holds at most twice the target
+  while (std::max(1.0, std::ceil((ex + 2 * pad) / h)) * std::max(1.0, std::ceil((ey + 2 * pad) / h)) >
+         2.0 * (double)target_cells)
+    h *= 1.25;
   g.nx = std::max(1, (int32_t)std::ceil((ex + 2 * pad) / h));
   g.ny = std::max(1, (int32_t)std::ceil((ey + 2 * pad) / h));
   g.lo[0] = lo[0];
@@ -286,7 +291,15 @@ SegmentGrid build_triangle_grid(const std::vector<double>& tris, int64_t n, cons
     lo[k] -= pad;
     vol *= hi[k] - lo[k] + pad;
   }
-  const double h = std::cbrt(vol / (double)target_cells);
+  // a nearly flat set (degenerate input) would make the cells tiny: coarsen until the
+  // grid holds at most twice the target
+  double h = std::cbrt(vol / (double)target_cells);
+  auto n_cells = [&](double hh) {
+    double c = 1;
+    for (int k = 0; k < 3; ++k) c *= std::max(1.0, std::ceil((hi[k] - lo[k] + pad) / hh));
+    return c;
+  };
+  while (n_cells(h) > 2.0 * (double)target_cells) h *= 1.25;
   int32_t nn[3];
   for (int k = 0; k < 3; ++k) {
     nn[k] = std::max(1, (int32_t)std::ceil((hi[k] - lo[k] + pad) / h));

@@ -5,7 +5,8 @@
 // grid does not depend on the number of build threads.
 //
 // Usage: grid_check <tri|seg> <file of doubles: [n][12] triangles or [n][4] segments>
-// Prints one line: "points P exact E bounded B bad_exact X bad_bound Y threads_equal T".
+// Prints one line: "points P exact E bounded B bad_exact X bad_bound Y threads_equal T
+// cells C" (the grid is built for 16 cells per primitive).
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -153,8 +154,8 @@ int main(int argc, char** argv) {
       if (lb > dt + 1e-12) ++bad_bound;
     }
   }
-  std::printf("points %lld exact %lld bounded %lld bad_exact %lld bad_bound %lld threads_equal %d\n",
+  std::printf("points %lld exact %lld bounded %lld bad_exact %lld bad_bound %lld threads_equal %d cells %lld\n",
               (long long)points, (long long)exact, (long long)bounded, (long long)bad_exact, (long long)bad_bound,
-              same ? 1 : 0);
+              same ? 1 : 0, (long long)ncell);
   return 0;
 }

@@ -54,3 +54,20 @@ def test_segment_grid_truncated_lists(driver):
     r = _run(driver, "seg", segs)
     assert r["points"] > 5000 and r["exact"] > 0 and r["bounded"] > 0, r
     assert r["bad_exact"] == 0 and r["bad_bound"] == 0, r
+
+
+def test_flat_input_keeps_the_grid_bounded(driver):
+    """A flat triangle set (degenerate input, zero volume) and a flat zigzag of segments:
+    the grids stay within twice their target of 16 cells per primitive."""
+    rng = np.random.default_rng(6)
+    P = rng.uniform(-1, 1, size=(40, 3, 3))
+    P[:, :, 2] = 0.0
+    tris = np.zeros((40, 12))
+    tris[:, :9] = P.reshape(40, 9)
+    r = _run(driver, "tri", tris)
+    assert 0 < r["cells"] <= 2 * 16 * 40 and r["bad_exact"] == 0 and r["bad_bound"] == 0, r
+    x = np.linspace(-1, 1, 41)
+    V = np.c_[x, 1e-9 * (np.arange(41) % 2)]
+    segs = np.c_[V[:-1], V[1:]]
+    r = _run(driver, "seg", segs)
+    assert 0 < r["cells"] <= 2 * 16 * 40 and r["bad_exact"] == 0 and r["bad_bound"] == 0, r
