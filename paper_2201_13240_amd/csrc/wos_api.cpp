@@ -1303,12 +1303,16 @@ wos_status time_shape(wos_plan* P, unsigned block, uint32_t tile, uint64_t walks
   Schedule s = P->s;
   wos_status r = grid_for_block(s, block);
   if (r != WOS_OK) return r;
+  // every item of the first launch contributes the first walks of its share, in item
+  // order as in the real tile table, so that the sample switches problems as the job does
   std::vector<Tile> t;
   const int n_items = (int)P->items.size();
-  uint64_t left = walks;
-  for (int k = 0; k < n_items && left > 0; ++k) {
+  double all = 0;
+  for (int k = 0; k < n_items; ++k) all += (double)P->dit[0][k].n_points * P->dit[0][k].walks;
+  for (int k = 0; k < n_items; ++k) {
     const DevItem& d = P->dit[0][k];
-    const uint64_t total = std::min<uint64_t>((uint64_t)d.n_points * d.walks, left);
+    const uint64_t item_walks = (uint64_t)d.n_points * d.walks;
+    const uint64_t total = std::min<uint64_t>(item_walks, (uint64_t)((double)walks * (double)item_walks / all));
     for (uint64_t f = 0; f < total; f += tile) {
       Tile x;
       x.item = (uint32_t)k;
@@ -1316,7 +1320,6 @@ wos_status time_shape(wos_plan* P, unsigned block, uint32_t tile, uint64_t walks
       x.first = d.walk_base + f;
       t.push_back(x);
     }
-    left -= total;
   }
   WOS_HIP(hipMemcpyAsync(dtiles, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice, st));
   WOS_HIP(hipStreamSynchronize(st));
@@ -1342,10 +1345,10 @@ wos_status time_shape(wos_plan* P, unsigned block, uint32_t tile, uint64_t walks
   return WOS_OK;
 }
 
-// Chooses block size and tile length for this walker by timing candidates on a prefix of
+// Chooses block size and tile length for this walker by timing candidates on a sample of
 // the plan's own walks (about eight walks per resident lane, so that every wave takes
-// several tiles), and caches the winner per process. Jobs too small to time leave the
-// defaults.
+// several tiles; each item contributes in proportion to its walks), and caches the
+// winner per process. Jobs too small to time leave the defaults.
 wos_status autotune(wos_plan* P, hipStream_t st, unsigned* block, uint32_t* tile) {
   static const unsigned kBlocks[] = {64, 128, 256};
   static const uint32_t kTiles[] = {64, 128, 256, 512, 1024};
