@@ -828,6 +828,8 @@ struct Schedule {
   int variant = 0;            // 2 selects the next-flight walker
   int grad = 0;               // some item asks for gradient sums
   int mode = 0;               // walker instantiation (walker_mode)
+  int batch = 0;              // more than one item: tuned apart from single problems, whose
+                              // tile length does not pay for problem switches
   unsigned block = 256, grid = 0;
   uint32_t tile_walks = 256;
   uint64_t chunk_walks = 0;   // walks per point per launch
@@ -860,6 +862,7 @@ wos_status check_items(const wos_batch_item* items, int n_items, const wos_optio
   s.variant = opt->variant;
   s.compensated = opt->precision == WOS_FP32_COMPENSATED;
   s.total_points = 0;
+  s.batch = n_items > 1 ? 1 : 0;
   for (int k = 0; k < n_items; ++k) {
     const wos_batch_item& it = items[k];
     if (!it.problem) return fail(WOS_ERR_INVALID_ARG, "null problem in batch");
@@ -889,10 +892,10 @@ std::mutex g_occ_mutex;
 std::map<std::tuple<int, int, int, int, int, unsigned>, unsigned> g_occ;
 
 // Launch shapes found by the plan autotuner, per (device, fp64, compensated, dim, geometry).
-std::map<std::tuple<int, int, int, int, int, int>, std::pair<unsigned, uint32_t>> g_tuned;
+std::map<std::tuple<int, int, int, int, int, int, int>, std::pair<unsigned, uint32_t>> g_tuned;
 
-std::tuple<int, int, int, int, int, int> tune_key(const Schedule& s) {
-  return std::make_tuple(s.device, s.fp64, s.compensated, s.dim, s.geom, s.mode);
+std::tuple<int, int, int, int, int, int, int> tune_key(const Schedule& s) {
+  return std::make_tuple(s.device, s.fp64, s.compensated, s.dim, s.geom, s.mode, s.batch);
 }
 
 // Persistent grid for a block size: resident blocks per CU times CUs.
