@@ -2,6 +2,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <exception>
 #include <functional>
 #include <limits>
 #include <thread>
@@ -375,10 +376,29 @@ SegmentGrid build_triangle_grid(const std::vector<double>& tris, int64_t n, cons
       P.tail[c - c0] = heap.size() > n_keep ? std::sqrt(heap[n_keep].first) : HUGE_VAL;
     }
   };
+  // an exception inside a worker (a failed allocation) is carried to this thread and
+  // rethrown after every worker has been joined; parts whose thread could not be started
+  // run here
+  std::vector<std::exception_ptr> errors(threads);
+  auto run = [&](int t) {
+    try {
+      work(t);
+    } catch (...) {
+      errors[t] = std::current_exception();
+    }
+  };
   std::vector<std::thread> pool;
-  for (int t = 1; t < threads; ++t) pool.emplace_back(work, t);
-  work(0);
+  int started = 1;
+  try {
+    pool.reserve(threads);
+    for (; started < threads; ++started) pool.emplace_back(run, started);
+  } catch (...) {
+  }
+  run(0);
+  for (int t = started; t < threads; ++t) run(t);
   for (auto& th : pool) th.join();
+  for (const std::exception_ptr& e : errors)
+    if (e) std::rethrow_exception(e);
   g.start.resize(ncell + 1);
   g.tail.resize(ncell);
   g.start[0] = 0;
