@@ -44,7 +44,7 @@ class OGeom(C.Structure):
 class OProblem(C.Structure):
     _fields_ = [("dim", C.c_int32), ("pad", C.c_int32), ("geom", OGeom), ("alpha", OField),
                 ("psi", OField), ("sigma", OField), ("source", OField), ("boundary", OField),
-                ("epsilon", C.c_double)]
+                ("epsilon", C.c_double), ("accel", C.c_void_p)]
 
 
 class OOptions(C.Structure):
@@ -52,7 +52,7 @@ class OOptions(C.Structure):
                 ("n_walks", C.c_uint64), ("problem_index", C.c_uint32), ("variant", C.c_int32),
                 ("russian_roulette", C.c_int32), ("ww_lo", C.c_double), ("ww_hi", C.c_double),
                 ("max_steps", C.c_uint64),
-                ("threads", C.c_int32), ("pad", C.c_int32)]
+                ("threads", C.c_int32), ("accel", C.c_int32)]
 
 
 _BASES = {"none": 0, "fourier": 1, "bumps": 2, "tanh": 3, "tanh_drift": 4, "manufactured": 5}
@@ -85,7 +85,7 @@ def lib():
         L.oracle_bessel.argtypes = [C.c_int, C.c_double]
         L.oracle_bessel.restype = C.c_double
         L.oracle_coefficients.argtypes = [C.POINTER(OProblem), dp, C.c_int64, dp]
-        L.oracle_distance.argtypes = [C.POINTER(OProblem), dp, C.c_int64, dp, dp]
+        L.oracle_distance.argtypes = [C.POINTER(OProblem), dp, C.c_int64, dp, dp, C.c_int]
         L.oracle_sigma_prime_range.argtypes = [C.POINTER(OProblem), dp, C.c_int64, dp, dp]
         L.oracle_solve.argtypes = [C.POINTER(OProblem), C.POINTER(OOptions), dp, C.c_int64, dp, dp,
                                    C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
@@ -249,12 +249,14 @@ def coefficients(prob, pts):
     return out
 
 
-def distance(prob, pts):
+def distance(prob, pts, bvh=False):
+    """Distance to the boundary and closest point; bvh=True answers polygon and mesh
+    queries through the oracle's own BVH (the brute-force minimum, faster)."""
     P = Problem(prob)
     pts = np.ascontiguousarray(pts, np.float64)
     d = np.empty(pts.shape[0])
     xb = np.empty_like(pts)
-    lib().oracle_distance(C.byref(P.c), _dptr(pts), pts.shape[0], _dptr(d), _dptr(xb))
+    lib().oracle_distance(C.byref(P.c), _dptr(pts), pts.shape[0], _dptr(d), _dptr(xb), int(bool(bvh)))
     return d, xb
 
 
@@ -273,8 +275,10 @@ def sigma_bar_default(prob, samples):
 
 
 def solve(prob, pts, n_walks, sigma_bar, seed=0, walk_offset=0, problem_index=0, variant=0,
-          russian_roulette=False, ww_lo=0.5, ww_hi=0.0, max_steps=10**7, threads=0, gradient=False):
-    """Returns dict(sum, sum_sq, steps, mean, se, counters). variant: 0 Alg. 1, 1 eq. 28,
+          russian_roulette=False, ww_lo=0.5, ww_hi=0.0, max_steps=10**7, threads=0, gradient=False,
+          bvh=False):
+    """Returns dict(sum, sum_sq, steps, mean, se, counters). bvh: closest points through the
+    oracle's BVH (timing mode; the same distances as brute force). variant: 0 Alg. 1, 1 eq. 28,
     2 next flight (Alg. 2), 3 next flight with exact series kernels. counters: invalid points, capped walks, roulette kills, inner
     samples (next flight)."""
     P = Problem(prob)
@@ -283,7 +287,7 @@ def solve(prob, pts, n_walks, sigma_bar, seed=0, walk_offset=0, problem_index=0,
     o = OOptions(sigma_bar=float(sigma_bar), seed=int(seed), walk_offset=int(walk_offset),
                  n_walks=int(n_walks), problem_index=int(problem_index), variant=int(variant),
                  russian_roulette=int(bool(russian_roulette)), ww_lo=float(ww_lo), ww_hi=float(ww_hi),
-                 max_steps=int(max_steps), threads=int(threads))
+                 max_steps=int(max_steps), threads=int(threads), accel=int(bool(bvh)))
     s = np.zeros(n)
     q = np.zeros(n)
     st = np.zeros(n, np.uint64)

@@ -57,6 +57,7 @@
 //
 // Build: g++ -O2 -std=c++17 -fPIC -shared -pthread (oracle.py runs it).
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdint>
@@ -169,6 +170,7 @@ struct OProblem {
   OGeom geom;
   OField alpha, psi, sigma, source, boundary;
   double epsilon;
+  const void* accel;      // null: brute-force closest points; else the OBvh of the boundary
 };
 
 struct OOptions {
@@ -185,7 +187,8 @@ struct OOptions {
   double ww_hi;           // > 0: split walks whose |weight| exceeds it (Sec. 6); 0: no splitting
   uint64_t max_steps;
   int32_t threads;
-  int32_t pad;
+  int32_t accel;          // 0: brute-force closest points (correctness mode); 1: the oracle's own
+                          // axis-aligned BVH over segments or triangles (timing mode, Sec. 7.1)
 };
 
 }  // extern "C"
@@ -497,8 +500,140 @@ double sdf_field(const OGeom& g, const double* x, int dim, double* grad) {
   return f;
 }
 
-// Distance d and closest point xbar on the boundary (Alg. 1, first line), by brute force
-// over all primitives (unsigned for explicit boundaries, -f for SDF domains).
+// Boundary primitives of a polygon (segment j joins vertex j and j + 1 of the closed
+// loop) or a triangle mesh.
+int64_t n_boundary_prims(const OGeom& g) { return g.kind == G_POLYGON ? g.n_vertices : g.n_prims; }
+
+void closest_on_prim(const OGeom& g, int64_t j, const double* x, double* q) {
+  if (g.kind == G_POLYGON) {
+    const int64_t n = g.n_vertices;
+    closest_on_segment(x, g.vertices + 2 * j, g.vertices + 2 * ((j + 1) % n), 2, q);
+  } else {
+    const int32_t* t = g.prims + 3 * j;
+    closest_on_triangle(x, g.vertices + 3 * t[0], g.vertices + 3 * t[1], g.vertices + 3 * t[2], q);
+  }
+}
+
+// ------------------------------------------------------------------ BVH (timing mode)
+// Sec. 7.1 answers closest-point queries with a basic axis-aligned BVH. This one is kept
+// plain: each node covers a range of a permutation of the primitives; a node with more
+// than 4 primitives is split at the median of their box centres along the longest axis
+// of those centres. The nearest-primitive query visits the nearer child first and skips
+// a box whose squared distance exceeds the best squared distance found so far (with a
+// relative margin of 1e-9 against rounding in the per-primitive distance), so it returns
+// the brute-force minimum: the same closest-point function runs on every primitive that
+// could attain it.
+struct OBvh {
+  int dim = 2;
+  std::vector<double> lo, hi;          // [node][dim] bounds
+  std::vector<int32_t> left, right;    // children; -1 for a leaf
+  std::vector<int64_t> first, count;   // leaf: range of `order`
+  std::vector<int64_t> order;          // primitive indices
+};
+
+int32_t bvh_build_node(OBvh& b, const std::vector<double>& plo, const std::vector<double>& phi,
+                       const std::vector<double>& cen, int64_t first, int64_t count) {
+  const int dim = b.dim;
+  const int32_t id = (int32_t)b.left.size();
+  b.left.push_back(-1);
+  b.right.push_back(-1);
+  b.first.push_back(first);
+  b.count.push_back(count);
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t k = first; k < first + count; ++k) {
+    const int64_t j = b.order[k];
+    for (int i = 0; i < dim; ++i) {
+      lo[i] = std::fmin(lo[i], plo[j * dim + i]);
+      hi[i] = std::fmax(hi[i], phi[j * dim + i]);
+      clo[i] = std::fmin(clo[i], cen[j * dim + i]);
+      chi[i] = std::fmax(chi[i], cen[j * dim + i]);
+    }
+  }
+  for (int i = 0; i < dim; ++i) {
+    b.lo.push_back(lo[i]);
+    b.hi.push_back(hi[i]);
+  }
+  if (count <= 4) return id;
+  int axis = 0;
+  for (int i = 1; i < dim; ++i)
+    if (chi[i] - clo[i] > chi[axis] - clo[axis]) axis = i;
+  const int64_t half = count / 2;
+  std::nth_element(b.order.begin() + first, b.order.begin() + first + half, b.order.begin() + first + count,
+                   [&](int64_t u, int64_t v) { return cen[u * dim + axis] < cen[v * dim + axis]; });
+  const int32_t l = bvh_build_node(b, plo, phi, cen, first, half);
+  const int32_t r = bvh_build_node(b, plo, phi, cen, first + half, count - half);
+  b.left[id] = l;
+  b.right[id] = r;
+  return id;
+}
+
+void bvh_build(const OGeom& g, int dim, OBvh& b) {
+  const int64_t n = n_boundary_prims(g);
+  const int nv = dim;   // vertices per primitive: 2 for segments, 3 for triangles
+  std::vector<double> plo(n * dim), phi(n * dim), cen(n * dim);
+  for (int64_t j = 0; j < n; ++j) {
+    for (int i = 0; i < dim; ++i) {
+      plo[j * dim + i] = INFINITY;
+      phi[j * dim + i] = -INFINITY;
+      cen[j * dim + i] = 0;
+    }
+    for (int v = 0; v < nv; ++v) {
+      const double* p = g.kind == G_POLYGON ? g.vertices + 2 * ((j + v) % g.n_vertices)
+                                            : g.vertices + 3 * g.prims[3 * j + v];
+      for (int i = 0; i < dim; ++i) {
+        plo[j * dim + i] = std::fmin(plo[j * dim + i], p[i]);
+        phi[j * dim + i] = std::fmax(phi[j * dim + i], p[i]);
+        cen[j * dim + i] += p[i] / nv;
+      }
+    }
+  }
+  b.dim = dim;
+  b.order.resize(n);
+  for (int64_t j = 0; j < n; ++j) b.order[j] = j;
+  bvh_build_node(b, plo, phi, cen, 0, n);
+}
+
+double box_dist2(const OBvh& b, int32_t node, const double* x) {
+  double s = 0;
+  for (int i = 0; i < b.dim; ++i) {
+    const double lo = b.lo[node * b.dim + i], hi = b.hi[node * b.dim + i];
+    const double e = x[i] < lo ? lo - x[i] : (x[i] > hi ? x[i] - hi : 0.0);
+    s += e * e;
+  }
+  return s;
+}
+
+double bvh_nearest(const OBvh& b, const OGeom& g, int dim, const double* x, double* xbar) {
+  double best = INFINITY, q[3];
+  int32_t stack[128];   // median splits: depth <= log2(n) + 1, at most one pending sibling per level
+  int top = 0;
+  stack[top++] = 0;
+  while (top > 0) {
+    const int32_t node = stack[--top];
+    if (box_dist2(b, node, x) > best * (1.0 + 1e-9)) continue;
+    if (b.left[node] < 0) {
+      for (int64_t k = b.first[node]; k < b.first[node] + b.count[node]; ++k) {
+        closest_on_prim(g, b.order[k], x, q);
+        const double d2 = dist2(x, q, dim);
+        if (d2 < best) {
+          best = d2;
+          for (int i = 0; i < dim; ++i) xbar[i] = q[i];
+        }
+      }
+      continue;
+    }
+    int32_t near = b.left[node], far = b.right[node];
+    if (box_dist2(b, far, x) < box_dist2(b, near, x)) std::swap(near, far);
+    stack[top++] = far;   // popped after the nearer child
+    stack[top++] = near;
+  }
+  return std::sqrt(best);
+}
+
+// Distance d and closest point xbar on the boundary (Alg. 1, first line): by brute force
+// over all primitives, or with P.accel through the BVH above (the same minimum);
+// unsigned for explicit boundaries, -f for SDF domains.
 double distance_to_boundary(const OProblem& P, const double* x, double* xbar) {
   const OGeom& g = P.geom;
   const int dim = P.dim;
@@ -535,31 +670,15 @@ double distance_to_boundary(const OProblem& P, const double* x, double* xbar) {
     }
     return std::sqrt(best);
   }
-  if (g.kind == G_POLYGON) {
-    double best = INFINITY, q[3];
-    const int64_t n = g.n_vertices;
-    for (int64_t j = 0; j < n; ++j) {
-      const double* a = g.vertices + 2 * j;
-      const double* b = g.vertices + 2 * ((j + 1) % n);
-      closest_on_segment(x, a, b, 2, q);
-      const double d2 = dist2(x, q, 2);
-      if (d2 < best) {
-        best = d2;
-        xbar[0] = q[0];
-        xbar[1] = q[1];
-      }
-    }
-    return std::sqrt(best);
-  }
-  // triangle mesh
+  if (P.accel) return bvh_nearest(*(const OBvh*)P.accel, g, dim, x, xbar);
+  // polygon or triangle mesh: every primitive
   double best = INFINITY, q[3];
-  for (int64_t j = 0; j < g.n_prims; ++j) {
-    const int32_t* t = g.prims + 3 * j;
-    closest_on_triangle(x, g.vertices + 3 * t[0], g.vertices + 3 * t[1], g.vertices + 3 * t[2], q);
-    const double d2 = dist2(x, q, 3);
+  for (int64_t j = 0; j < n_boundary_prims(g); ++j) {
+    closest_on_prim(g, j, x, q);
+    const double d2 = dist2(x, q, dim);
     if (d2 < best) {
       best = d2;
-      for (int i = 0; i < 3; ++i) xbar[i] = q[i];
+      for (int i = 0; i < dim; ++i) xbar[i] = q[i];
     }
   }
   return std::sqrt(best);
@@ -1153,8 +1272,16 @@ void oracle_coefficients(const OProblem* P, const double* pts, int64_t n, double
   }
 }
 
-void oracle_distance(const OProblem* P, const double* pts, int64_t n, double* d, double* xbar) {
-  for (int64_t i = 0; i < n; ++i) d[i] = distance_to_boundary(*P, pts + i * P->dim, xbar + i * P->dim);
+// accel = 1 answers polygon and mesh queries through the oracle's BVH (same minimum).
+void oracle_distance(const OProblem* P_in, const double* pts, int64_t n, double* d, double* xbar, int accel) {
+  OProblem Pl = *P_in;
+  OBvh bvh;
+  Pl.accel = nullptr;
+  if (accel && (Pl.geom.kind == G_POLYGON || Pl.geom.kind == G_TRIMESH)) {
+    bvh_build(Pl.geom, Pl.dim, bvh);
+    Pl.accel = &bvh;
+  }
+  for (int64_t i = 0; i < n; ++i) d[i] = distance_to_boundary(Pl, pts + i * Pl.dim, xbar + i * Pl.dim);
 }
 
 // sigma' min and max over the given sample points (the default majorant of Sec. 5.1 /
@@ -1185,8 +1312,17 @@ int oracle_solve(const OProblem* P, const OOptions* o, const double* pts, int64_
 // As oracle_solve, and with gsum / gsum_sq (both [n][dim], or null) the sums of the
 // per-walk gradient estimates and of their squares (supplemental Sec. 2; delta tracking
 // only).
-int oracle_solve_grad(const OProblem* P, const OOptions* o, const double* pts, int64_t n_points, double* sum,
+int oracle_solve_grad(const OProblem* P_in, const OOptions* o, const double* pts, int64_t n_points, double* sum,
                       double* sum_sq, uint64_t* steps, uint64_t* counters, double* gsum, double* gsum_sq) {
+  // the timing mode's BVH lives for this call; the walk sees it through P->accel
+  OProblem Pl = *P_in;
+  OBvh bvh;
+  Pl.accel = nullptr;
+  if (o->accel && (Pl.geom.kind == G_POLYGON || Pl.geom.kind == G_TRIMESH)) {
+    bvh_build(Pl.geom, Pl.dim, bvh);
+    Pl.accel = &bvh;
+  }
+  const OProblem* P = &Pl;
   if (gsum && o->variant >= 2) return 1;
   if (o->sigma_bar < 0) return 1;
   if (o->variant < 0 || o->variant > 3) return 1;

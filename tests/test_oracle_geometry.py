@@ -83,3 +83,44 @@ def test_trimesh_against_dense_sampling(oracle):
     # a projection closest point is where the offset is normal to the face
     for p, q in zip(pts, xb):
         assert np.all(np.abs(np.linalg.norm(S - q, axis=1).min()) < 2 * edge / m)
+
+
+def _near_boundary_and_inside(rng, prob, n):
+    """Interior samples plus points pushed towards the boundary (small and large distances)."""
+    dim = prob["dim"]
+    pts = W.sample_inside(rng, prob["geometry"], dim, n)
+    return np.concatenate([pts, 0.98 * pts, 0.5 * pts, pts + 0.2])
+
+
+@pytest.mark.parametrize("which", ["star256", "star4096", "ico20480"])
+def test_bvh_distance_equals_brute_force(oracle, which):
+    """The oracle's BVH (timing mode, Sec. 7.1) returns exactly the brute-force minimum
+    distance, at interior points, points near the boundary and points outside it."""
+    rng = np.random.default_rng(11)
+    if which == "ico20480":
+        g = W.icosphere(np.random.default_rng(3000), 5, 0.1)
+        dim, n = 3, 300
+    else:
+        g = W.star_polygon(np.random.default_rng(2000), 256 if which == "star256" else 4096)
+        dim, n = 2, 1000
+    prob = _prob(g, dim)
+    pts = _near_boundary_and_inside(rng, prob, n)
+    d0, x0 = oracle.distance(prob, pts, bvh=False)
+    d1, x1 = oracle.distance(prob, pts, bvh=True)
+    assert np.array_equal(d0, d1)
+    # where primitives tie (a closest point on a shared edge or vertex), another primitive
+    # may give it, with other rounding
+    np.testing.assert_allclose(np.linalg.norm(x1 - pts, axis=1), d1, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(x1, x0, rtol=0, atol=1e-12)
+
+
+def test_bvh_walk_equals_brute_force_walk(oracle):
+    """A walk in timing mode makes the same distance queries as in correctness mode (the
+    distances are identical), so step counts and estimates agree."""
+    c = W.config2(n_grid=64)
+    prob, pts = c["problems"][0], c["points"][0][:40]
+    sb = 12.0
+    a = oracle.solve(prob, pts, 64, sb, seed=3, bvh=False)
+    b = oracle.solve(prob, pts, 64, sb, seed=3, bvh=True)
+    assert np.array_equal(a["steps"], b["steps"])
+    np.testing.assert_allclose(a["sum"], b["sum"], rtol=1e-12, atol=1e-12)
