@@ -217,8 +217,13 @@ typedef struct {
                                  of that counter word) and ww_hi > ww_lo with roulette. */
   uint64_t max_steps;         /* distance queries per walk before it is cut (0: 10^6) */
   int32_t block_size;         /* 0: autotuned/default; else 64..1024, multiple of 64 */
-  int32_t tile_walks;         /* 0: default; walks per work tile taken by a wavefront */
-  uint64_t workspace_bytes;   /* 0: default cap (4 GiB) on per-walk scratch per launch */
+  int32_t tile_walks;         /* 0: default; walks of one point per work tile taken by a
+                                 wavefront (a tile holds whole points when a point has
+                                 fewer walks), at most 65536 */
+  uint64_t workspace_bytes;   /* 0: default cap (4 GiB) on the accumulation slots of one
+                                 launch (128 bytes per tile and point, 384 or 512 with
+                                 gradients); a job whose slots exceed it runs its walks per
+                                 point in several launches */
 } wos_options;
 
 /* One batch of query points of one problem.
@@ -250,11 +255,14 @@ typedef struct {
 
 /* Runs walks_per_point walks from every query point of every item (Sec. 3.1: the estimate
  * of u(x) is the mean of independent single-walk estimates) in one persistent kernel
- * launch per walk chunk. All items must share dim, geometry kind and device. Walk j of
- * point i of item k uses the Philox stream key = seed, counter = (draw, walk_offset + j,
- * i, problem_index), so results do not depend on scheduling; the per-point reduction is
- * in a fixed order, so results are bit-reproducible. Scratch memory is allocated and
- * freed in stream order. */
+ * launch (several only when workspace_bytes is too small for the job's accumulation
+ * slots). All items must share dim, geometry kind and device. Walk j of point i of item k
+ * uses the Philox stream key = seed, counter = (draw, walk_offset + j, i, problem_index),
+ * so the walks do not depend on scheduling; their estimates are summed exactly (as
+ * fixed-point integers, then rounded once to double per point and launch), so results
+ * are bit-reproducible whatever the launch shape. A walk estimate must stay below 2^47 in
+ * magnitude: a larger or non-finite one makes its point's sum and sum_sq NaN. Scratch
+ * memory is allocated and freed in stream order. */
 wos_status wos_solve(const wos_batch_item* items, int32_t n_items, const wos_options* opt, void* stream);
 
 /* Runs the same walks as wos_solve (same outputs, accumulated the same way) with the

@@ -835,6 +835,8 @@ struct Schedule {
   uint64_t chunk_walks = 0;   // walks per point per launch
   uint64_t total_points = 0;
   int n_launches = 0;
+  int slot_words = 16;        // words per accumulation slot
+  int grad_dim = 0;           // dim when gradient sums are asked for, else 0
 };
 
 wos_status check_items(const wos_batch_item* items, int n_items, const wos_options* opt, Schedule& s) {
@@ -853,6 +855,8 @@ wos_status check_items(const wos_batch_item* items, int n_items, const wos_optio
     return fail(WOS_ERR_INVALID_ARG, "ww_hi must exceed ww_lo");
   if (opt->block_size != 0 && (opt->block_size < 64 || opt->block_size > 256 || opt->block_size % 64))
     return fail(WOS_ERR_INVALID_ARG, "block_size must be 64, 128, 192 or 256");
+  if (opt->tile_walks < 0 || (uint32_t)opt->tile_walks > kMaxTileLen)
+    return fail(WOS_ERR_INVALID_ARG, "tile_walks must be in 0..65536");
   const wos_problem* p0 = items[0].problem;
   if (!p0) return fail(WOS_ERR_INVALID_ARG, "null problem in item 0");
   s.dim = p0->dim;
@@ -881,15 +885,20 @@ wos_status check_items(const wos_batch_item* items, int n_items, const wos_optio
   }
   if (s.grad && s.variant == 2) return fail(WOS_ERR_INVALID_ARG, "gradient estimates need delta tracking (variant 0 or 1)");
   s.mode = walker_mode(s.variant, s.grad != 0, opt->ww_hi > 0);
+  s.grad_dim = s.grad ? s.dim : 0;
+  s.slot_words = slot_words(s.grad_dim);
   return WOS_OK;
 }
 
-size_t grad_bytes_per_walk(const Schedule& s) {
+// Bytes of one lane's gradient record, and the lanes of any persistent grid on the device
+// (resident threads per CU at most 2048).
+size_t grad_record_bytes(const Schedule& s) {
   return (size_t)(1 + 3 * s.dim) * (s.fp64 ? sizeof(double) : sizeof(float));
 }
 
 std::mutex g_occ_mutex;
 std::map<std::tuple<int, int, int, int, int, unsigned>, unsigned> g_occ;
+std::map<int, int> g_cus;
 
 // Launch shapes found by the plan autotuner, per (device, fp64, compensated, dim, geometry).
 std::map<std::tuple<int, int, int, int, int, int, int>, std::pair<unsigned, uint32_t>> g_tuned;
@@ -898,16 +907,32 @@ std::tuple<int, int, int, int, int, int, int> tune_key(const Schedule& s) {
   return std::make_tuple(s.device, s.fp64, s.compensated, s.dim, s.geom, s.mode, s.batch);
 }
 
+wos_status device_cus(int device, int* cus) {
+  std::lock_guard<std::mutex> lk(g_occ_mutex);
+  auto it = g_cus.find(device);
+  if (it == g_cus.end()) {
+    int n = 0;
+    WOS_HIP(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device));
+    it = g_cus.emplace(device, std::max(1, n)).first;
+  }
+  *cus = it->second;
+  return WOS_OK;
+}
+
+uint64_t max_grid_lanes(int cus) { return (uint64_t)cus * 2048u; }
+
 // Persistent grid for a block size: resident blocks per CU times CUs.
 wos_status grid_for_block(Schedule& s, unsigned block) {
+  int cus = 0;
+  wos_status r = device_cus(s.device, &cus);
+  if (r != WOS_OK) return r;
   const auto key = std::make_tuple(s.device, s.fp64, s.dim, s.geom, s.mode, block);
   std::lock_guard<std::mutex> lk(g_occ_mutex);
   auto it = g_occ.find(key);
   if (it == g_occ.end()) {
-    int per_cu = 0, cus = 0;
+    int per_cu = 0;
     WOS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, walker_symbol(s.fp64, s.dim, s.geom, s.mode), (int)block, 0));
-    WOS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s.device));
-    unsigned grid = (unsigned)std::max(1, per_cu) * (unsigned)std::max(1, cus);
+    unsigned grid = (unsigned)std::max(1, per_cu) * (unsigned)cus;
     it = g_occ.emplace(key, grid).first;
   }
   s.block = block;
@@ -915,8 +940,15 @@ wos_status grid_for_block(Schedule& s, unsigned block) {
   return WOS_OK;
 }
 
+// Slots of one launch of `chunk` walks per point: every point takes max(1, ceil(chunk /
+// tile)) of them.
+uint64_t slots_for(uint64_t total_points, uint64_t chunk, uint32_t tile) {
+  return total_points * std::max<uint64_t>(1, (chunk + tile - 1) / tile);
+}
+
 // Block size and tile length: the caller's, else the tuned shape of this walker, else
-// 256 / 256.
+// 256 / 256. Walks per point are split into launches only when the slots of one launch
+// would exceed the workspace cap.
 wos_status pick_shape(const wos_options* opt, Schedule& s) {
   unsigned block = 256u;
   uint32_t tile = 256u;
@@ -934,23 +966,50 @@ wos_status pick_shape(const wos_options* opt, Schedule& s) {
   wos_status r = grid_for_block(s, block);
   if (r != WOS_OK) return r;
   const uint64_t cap = opt->workspace_bytes ? opt->workspace_bytes : (4ull << 30);
-  const uint64_t per_walk = sizeof(WalkRecord) + (s.grad ? grad_bytes_per_walk(s) : 0);
-  const uint64_t max_ids = std::max<uint64_t>(cap / per_walk, 1);
+  const uint64_t slot_bytes = (uint64_t)s.slot_words * 8u;
   const uint64_t N = opt->walks_per_point;
-  uint64_t nc = s.total_points ? std::max<uint64_t>(1, max_ids / s.total_points) : N;
-  nc = std::min(nc, N);
+  uint64_t nc = N;
+  if (s.total_points > 0 && slots_for(s.total_points, N, tile) * slot_bytes > cap) {
+    const uint64_t tiles_per_point = std::max<uint64_t>(1, cap / slot_bytes / s.total_points);
+    nc = std::min<uint64_t>(N, tiles_per_point * tile);
+  }
   s.chunk_walks = nc;
   s.n_launches = (int)((N + nc - 1) / nc);
   return WOS_OK;
 }
 
-// Per-launch tables: item copies with walks/walk_offset of this chunk, and tiles.
-void build_tables(const wos_batch_item* items, int n_items, const wos_options* opt, const Schedule& s,
-                  uint64_t w0, uint64_t nw, const std::vector<int8_t*>& inside, const std::vector<void*>& gamma0,
-                  std::vector<DevItem>& dit, std::vector<Tile>& tiles) {
+// Cuts each item's walks of one launch into point-major tiles of `tile` walks and numbers
+// their slots (DevItem); returns the launch's tiles and slots.
+void layout_items(std::vector<DevItem>& dit, uint32_t tile, uint64_t* n_tiles, uint64_t* n_slots) {
+  uint64_t tb = 0, sb = 0;
+  for (DevItem& d : dit) {
+    const uint64_t n = (uint64_t)d.n_points;
+    d.tile_len = tile;
+    d.tile_base = tb;
+    d.slot_base = sb;
+    if (d.walks >= tile) {
+      d.tiles_per_point = (uint32_t)((d.walks + tile - 1) / tile);
+      d.points_per_tile = 0;
+      d.n_tiles = n * d.tiles_per_point;
+      sb += d.n_tiles;
+    } else {
+      d.tiles_per_point = 0;
+      d.points_per_tile = (uint32_t)(tile / d.walks);
+      d.n_tiles = (n + d.points_per_tile - 1) / d.points_per_tile;
+      sb += n;
+    }
+    tb += d.n_tiles;
+  }
+  *n_tiles = tb;
+  *n_slots = sb;
+}
+
+// Per-launch item tables (walks and walk offset of the launch's chunk, tile cut, slots).
+void build_items(const wos_batch_item* items, int n_items, const wos_options* opt, const Schedule& s, uint64_t w0,
+                 uint64_t nw, const std::vector<int8_t*>& inside, const std::vector<void*>& gamma0,
+                 std::vector<DevItem>& dit, uint64_t* n_tiles, uint64_t* n_slots) {
   dit.resize(n_items);
-  tiles.clear();
-  uint64_t wbase = 0, pbase = 0;
+  uint64_t pbase = 0;
   for (int k = 0; k < n_items; ++k) {
     const wos_batch_item& it = items[k];
     DevItem& d = dit[k];
@@ -969,31 +1028,21 @@ void build_tables(const wos_batch_item* items, int n_items, const wos_options* o
     d.n_points = it.n_points;
     d.walks = nw;
     d.walk_offset = opt->walk_offset + w0;
-    d.walk_base = wbase;
     d.point_base = pbase;
     d.problem_index = it.problem_index;
-    const uint64_t total = (uint64_t)it.n_points * nw;
-    for (uint64_t f = 0; f < total; f += s.tile_walks) {
-      Tile t;
-      t.item = (uint32_t)k;
-      t.count = (uint32_t)std::min<uint64_t>(s.tile_walks, total - f);
-      t.first = wbase + f;
-      tiles.push_back(t);
-    }
-    wbase += total;
     pbase += (uint64_t)it.n_points;
   }
+  layout_items(dit, s.tile_walks, n_tiles, n_slots);
 }
 
 struct Workspace {
   int8_t* inside = nullptr;
   unsigned char* gamma0 = nullptr;  // [total points] gamma(x0), walker precision
   DevItem* items = nullptr;       // [n_launches][n_items]
-  Tile* tiles = nullptr;          // [n_launches][max tiles]
   uint32_t* counter = nullptr;
   LaunchParams* lp = nullptr;
-  WalkRecord* records = nullptr;
-  void* grad = nullptr;           // gradient records, when any item asks for gradients
+  uint64_t* slots = nullptr;      // [slots of the largest launch][slot_words]
+  void* grad = nullptr;           // per-lane gradient records, when any item asks for gradients
 };
 
 }  // namespace
@@ -1004,23 +1053,23 @@ struct wos_plan {
   wos_options opt;
   Workspace ws;
   void* dmem = nullptr;
-  std::vector<uint32_t> n_tiles;      // per launch
+  std::vector<uint64_t> n_tiles;      // per launch
+  std::vector<uint64_t> n_slots;      // per launch
   std::vector<std::vector<DevItem>> dit;
-  size_t max_tiles = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
 
 namespace {
 
-__attribute__((unused)) size_t align_up(size_t v) { return (v + 255) / 256 * 256; }
+size_t align_up(size_t v) { return (v + 255) / 256 * 256; }
 
-// Builds every launch's tables; returns the byte layout of the workspace.
+// Byte layout of a job's workspace.
 struct WsLayout {
-  size_t inside, gamma0, items, tiles, counter, lp, records, grad, total;
+  size_t inside, gamma0, items, counter, lp, slots, grad, total;
 };
 
-WsLayout ws_layout(const Schedule& s, int n_items, size_t max_tiles) {
+WsLayout ws_layout(const Schedule& s, int n_items, uint64_t max_slots, int cus) {
   WsLayout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -1028,15 +1077,13 @@ WsLayout ws_layout(const Schedule& s, int n_items, size_t max_tiles) {
     off = align_up(off + bytes);
     return o;
   };
-  const uint64_t ids = s.total_points * s.chunk_walks;
   L.inside = take(std::max<uint64_t>(s.total_points, 1));
   L.gamma0 = take(std::max<uint64_t>(s.total_points, 1) * (s.fp64 ? 8 : 4));
   L.items = take(sizeof(DevItem) * (size_t)n_items * s.n_launches);
-  L.tiles = take(sizeof(Tile) * std::max<size_t>(max_tiles, 1) * s.n_launches);
   L.counter = take(sizeof(uint32_t) * 64);
   L.lp = take(sizeof(LaunchParams));
-  L.records = take(sizeof(WalkRecord) * std::max<uint64_t>(ids, 1));
-  L.grad = take(s.grad ? grad_bytes_per_walk(s) * std::max<uint64_t>(ids, 1) : 0);
+  L.slots = take((size_t)std::max<uint64_t>(max_slots, 1) * s.slot_words * sizeof(uint64_t));
+  L.grad = take(s.grad ? grad_record_bytes(s) * max_grid_lanes(cus) : 0);
   L.total = off;
   return L;
 }
@@ -1046,16 +1093,16 @@ void ws_bind(Workspace& w, void* base, const WsLayout& L) {
   w.inside = (int8_t*)(b + L.inside);
   w.gamma0 = b + L.gamma0;
   w.items = (DevItem*)(b + L.items);
-  w.tiles = (Tile*)(b + L.tiles);
   w.counter = (uint32_t*)(b + L.counter);
   w.lp = (LaunchParams*)(b + L.lp);
-  w.records = (WalkRecord*)(b + L.records);
+  w.slots = (uint64_t*)(b + L.slots);
   w.grad = (void*)(b + L.grad);
 }
 
-// Prepares all tables of a job on the host.
-void prepare(const wos_batch_item* items, int n_items, const wos_options* opt, const Schedule& s,
-             const Workspace& w, std::vector<std::vector<DevItem>>& dit, std::vector<std::vector<Tile>>& tiles) {
+// Item tables of every launch of a job, on the host; tiles and slots per launch.
+wos_status prepare(const wos_batch_item* items, int n_items, const wos_options* opt, const Schedule& s,
+                   const Workspace& w, std::vector<std::vector<DevItem>>& dit, std::vector<uint64_t>& n_tiles,
+                   std::vector<uint64_t>& n_slots) {
   std::vector<int8_t*> inside(n_items);
   std::vector<void*> gamma0(n_items);
   uint64_t pb = 0;
@@ -1065,34 +1112,46 @@ void prepare(const wos_batch_item* items, int n_items, const wos_options* opt, c
     pb += (uint64_t)items[k].n_points;
   }
   dit.resize(s.n_launches);
-  tiles.resize(s.n_launches);
+  n_tiles.assign(s.n_launches, 0);
+  n_slots.assign(s.n_launches, 0);
   for (int c = 0; c < s.n_launches; ++c) {
     const uint64_t w0 = (uint64_t)c * s.chunk_walks;
     const uint64_t nw = std::min(s.chunk_walks, opt->walks_per_point - w0);
-    build_tables(items, n_items, opt, s, w0, nw, inside, gamma0, dit[c], tiles[c]);
+    build_items(items, n_items, opt, s, w0, nw, inside, gamma0, dit[c], &n_tiles[c], &n_slots[c]);
+    if (n_tiles[c] >= (1ull << 32) || n_slots[c] >= (1ull << 32))
+      return fail(WOS_ERR_INVALID_ARG, "job too large: a launch would hold 2^32 tiles or slots or more");
   }
+  return WOS_OK;
 }
 
-std::vector<uint32_t> tile_counts(const std::vector<std::vector<Tile>>& tiles) {
-  std::vector<uint32_t> n;
-  for (auto& t : tiles) n.push_back((uint32_t)t.size());
-  return n;
+// Slots of the largest launch of a schedule (no tables are built).
+uint64_t max_launch_slots(const wos_batch_item* items, int n_items, const wos_options* opt, const Schedule& s) {
+  (void)items;
+  (void)n_items;
+  uint64_t m = 0;
+  for (int c = 0; c < s.n_launches; ++c) {
+    const uint64_t w0 = (uint64_t)c * s.chunk_walks;
+    const uint64_t nw = std::min(s.chunk_walks, opt->walks_per_point - w0);
+    m = std::max(m, slots_for(s.total_points, nw, s.tile_walks));
+  }
+  return m;
 }
 
-// Launch record of the walker for launch c of a schedule over the given tile table.
-WalkerLaunch walker_launch(const wos_options* opt, const Schedule& s, const Workspace& w, int c, int n_items,
-                           Tile* tiles, uint32_t n_tiles) {
+// Launch record of the walker for launch c of a schedule over the given item table.
+WalkerLaunch walker_launch(const wos_options* opt, const Schedule& s, const Workspace& w, const DevItem* items,
+                           int n_items, uint64_t n_tiles) {
   WalkerLaunch L;
   L.fp64 = s.fp64;
   L.dim = s.dim;
   L.geom = s.geom;
   L.grid = s.grid;
   L.block = s.block;
-  L.items = w.items + (size_t)c * n_items;
-  L.tiles = tiles;
-  L.n_tiles = n_tiles;
+  L.items = items;
+  L.n_items = n_items;
+  L.n_tiles = (uint32_t)n_tiles;
   L.tile_counter = w.counter;
-  L.records = w.records;
+  L.slots = w.slots;
+  L.slot_words = s.slot_words;
   L.lp = w.lp;
   L.max_steps = opt->max_steps ? opt->max_steps : 1000000ull;
   L.variant = opt->variant;
@@ -1123,42 +1182,33 @@ hipError_t classify_items(const wos_batch_item* items, int n_items, const Schedu
   return hipSuccess;
 }
 
-// Enqueues [reset, walker, reduce per item] for every launch of the schedule. With
+// Enqueues [clear, walker, reduce per item] for every launch of the schedule. With
 // `marks`, an event pair is recorded around each walker launch (eager timing only: a
 // captured job takes none).
 wos_status enqueue_job(const wos_batch_item* items, int n_items, const wos_options* opt, const Schedule& s,
                        const Workspace& w, const std::vector<std::vector<DevItem>>& dit,
-                       const std::vector<uint32_t>& n_tiles, size_t max_tiles, bool classify, uint64_t* events,
-                       hipStream_t st, const std::vector<hipEvent_t>* marks = nullptr) {
+                       const std::vector<uint64_t>& n_tiles, const std::vector<uint64_t>& n_slots, bool classify,
+                       uint64_t* events, hipStream_t st, const std::vector<hipEvent_t>* marks = nullptr) {
   if (classify) WOS_HIP(classify_items(items, n_items, s, w, st));
   for (int c = 0; c < s.n_launches; ++c) {
     if (n_tiles[c] == 0) continue;
-    WOS_HIP(launch_reset(w.counter, st));
-    WalkerLaunch L = walker_launch(opt, s, w, c, n_items, w.tiles + (size_t)c * max_tiles, n_tiles[c]);
+    WOS_HIP(launch_clear(w.slots, n_slots[c] * (uint64_t)s.slot_words, w.counter, st));
+    WalkerLaunch L = walker_launch(opt, s, w, w.items + (size_t)c * n_items, n_items, n_tiles[c]);
     L.events = events;
     if (marks) WOS_HIP(hipEventRecord((*marks)[2 * c], st));
     WOS_HIP(launch_walker(L, st));
     if (marks) WOS_HIP(hipEventRecord((*marks)[2 * c + 1], st));
-    for (int k = 0; k < n_items; ++k) {
-      WOS_HIP(launch_reduce(dit[c][k], w.records, st));
-      if (s.grad) WOS_HIP(launch_reduce_grad(s.fp64, s.dim, dit[c][k], w.records, w.grad, st));
-    }
+    for (int k = 0; k < n_items; ++k) WOS_HIP(launch_reduce(s.grad_dim, dit[c][k], w.slots, s.slot_words, st));
   }
   return WOS_OK;
 }
 
-wos_status upload_tables(const Schedule& s, int n_items, const Workspace& w,
-                         const std::vector<std::vector<DevItem>>& dit, const std::vector<std::vector<Tile>>& tiles,
-                         size_t max_tiles, hipStream_t st) {
-  // Pageable host sources: the runtime stages these copies before returning.
+wos_status upload_items(const Schedule& s, int n_items, const Workspace& w, const std::vector<std::vector<DevItem>>& dit,
+                        hipStream_t st) {
+  // Pageable host source: the runtime stages the copy before returning.
   std::vector<DevItem> all_items((size_t)n_items * s.n_launches);
-  std::vector<Tile> all_tiles(std::max<size_t>(max_tiles, 1) * s.n_launches);
-  for (int c = 0; c < s.n_launches; ++c) {
-    std::copy(dit[c].begin(), dit[c].end(), all_items.begin() + (size_t)c * n_items);
-    std::copy(tiles[c].begin(), tiles[c].end(), all_tiles.begin() + (size_t)c * max_tiles);
-  }
+  for (int c = 0; c < s.n_launches; ++c) std::copy(dit[c].begin(), dit[c].end(), all_items.begin() + (size_t)c * n_items);
   WOS_HIP(hipMemcpyAsync(w.items, all_items.data(), all_items.size() * sizeof(DevItem), hipMemcpyHostToDevice, st));
-  WOS_HIP(hipMemcpyAsync(w.tiles, all_tiles.data(), all_tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, st));
   WOS_HIP(hipStreamSynchronize(st));
   return WOS_OK;
 }
@@ -1175,32 +1225,23 @@ static wos_status solve_impl(const wos_batch_item* items, int32_t n_items, const
   WOS_HIP(hipSetDevice(s.device));
   if ((r = pick_shape(opt, s)) != WOS_OK) return r;
   if (s.total_points == 0) return WOS_OK;
+  int cus = 0;
+  if ((r = device_cus(s.device, &cus)) != WOS_OK) return r;
   hipStream_t st = (hipStream_t)stream;
   Workspace w;
   std::vector<std::vector<DevItem>> dit;
-  std::vector<std::vector<Tile>> tiles;
+  std::vector<uint64_t> n_tiles, n_slots;
   // tables reference workspace addresses, so allocate first
-  size_t max_tiles = 0;
-  {
-    // tile counts only depend on the schedule
-    for (int c = 0; c < s.n_launches; ++c) {
-      const uint64_t w0 = (uint64_t)c * s.chunk_walks;
-      const uint64_t nw = std::min(s.chunk_walks, opt->walks_per_point - w0);
-      size_t nt = 0;
-      for (int k = 0; k < n_items; ++k) nt += (size_t)(((uint64_t)items[k].n_points * nw + s.tile_walks - 1) / s.tile_walks);
-      max_tiles = std::max(max_tiles, nt);
-    }
-  }
-  const WsLayout L = ws_layout(s, n_items, max_tiles);
+  const WsLayout L = ws_layout(s, n_items, max_launch_slots(items, n_items, opt, s), cus);
   void* base = nullptr;
   WOS_HIP(hipMallocAsync(&base, L.total, st));
   ws_bind(w, base, L);
-  prepare(items, n_items, opt, s, w, dit, tiles);
-  r = upload_tables(s, n_items, w, dit, tiles, max_tiles, st);
+  r = prepare(items, n_items, opt, s, w, dit, n_tiles, n_slots);
+  if (r == WOS_OK) r = upload_items(s, n_items, w, dit, st);
   if (r == WOS_OK) {
     const hipError_t e = launch_set_params(w.lp, opt->seed, 0, st);
     r = e != hipSuccess ? fail(WOS_ERR_DEVICE, "launch failed")
-                        : enqueue_job(items, n_items, opt, s, w, dit, tile_counts(tiles), max_tiles, true, events, st);
+                        : enqueue_job(items, n_items, opt, s, w, dit, n_tiles, n_slots, true, events, st);
   }
   (void)hipFreeAsync(base, st);
   return r;
@@ -1243,29 +1284,22 @@ wos_status plan_build(const wos_batch_item* items, int32_t n_items, const wos_op
     delete P;
     return r;
   }
+  int cus = 0;
+  if ((r = device_cus(P->s.device, &cus)) != WOS_OK) {
+    delete P;
+    return r;
+  }
   P->items.assign(items, items + n_items);
   P->opt = *opt;
   hipStream_t st = (hipStream_t)stream;
   const Schedule& s = P->s;
-  size_t max_tiles = 0;
-  for (int c = 0; c < s.n_launches; ++c) {
-    const uint64_t w0 = (uint64_t)c * s.chunk_walks;
-    const uint64_t nw = std::min(s.chunk_walks, opt->walks_per_point - w0);
-    size_t nt = 0;
-    for (int k = 0; k < n_items; ++k) nt += (size_t)(((uint64_t)items[k].n_points * nw + s.tile_walks - 1) / s.tile_walks);
-    max_tiles = std::max(max_tiles, nt);
-  }
-  P->max_tiles = max_tiles;
-  const WsLayout L = ws_layout(s, n_items, max_tiles);
+  const WsLayout L = ws_layout(s, n_items, max_launch_slots(items, n_items, opt, s), cus);
   hipError_t e = hipMalloc(&P->dmem, L.total);
   if (e != hipSuccess) {
     delete P;
     return fail(e == hipErrorOutOfMemory ? WOS_ERR_OUT_OF_MEMORY : WOS_ERR_DEVICE, "plan workspace allocation failed");
   }
   ws_bind(P->ws, P->dmem, L);
-  std::vector<std::vector<Tile>> tiles;
-  prepare(items, n_items, opt, s, P->ws, P->dit, tiles);
-  for (auto& t : tiles) P->n_tiles.push_back((uint32_t)t.size());
   auto bail = [&](wos_status code, const std::string& m) {
     if (P->exec) (void)hipGraphExecDestroy(P->exec);
     if (P->graph) (void)hipGraphDestroy(P->graph);
@@ -1273,11 +1307,12 @@ wos_status plan_build(const wos_batch_item* items, int32_t n_items, const wos_op
     delete P;
     return fail(code, m);
   };
-  if ((r = upload_tables(s, n_items, P->ws, P->dit, tiles, max_tiles, st)) != WOS_OK) return bail(r, g_error);
+  if ((r = prepare(items, n_items, opt, s, P->ws, P->dit, P->n_tiles, P->n_slots)) != WOS_OK) return bail(r, g_error);
+  if ((r = upload_items(s, n_items, P->ws, P->dit, st)) != WOS_OK) return bail(r, g_error);
   // classification and gamma(x0) once, outside the graph
   if ((e = classify_items(items, n_items, s, P->ws, st)) != hipSuccess)
     return bail(WOS_ERR_DEVICE, "classification launch failed");
-  // capture reset + walker + reduce of every launch on a private stream
+  // capture clear + walker + reduce of every launch on a private stream
   hipStream_t cap;
   if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) return bail(WOS_ERR_DEVICE, "stream creation failed");
   if ((e = hipStreamSynchronize(st)) != hipSuccess) {
@@ -1288,7 +1323,7 @@ wos_status plan_build(const wos_batch_item* items, int32_t n_items, const wos_op
     (void)hipStreamDestroy(cap);
     return bail(WOS_ERR_DEVICE, "graph capture failed to start");
   }
-  r = enqueue_job(items, n_items, opt, s, P->ws, P->dit, P->n_tiles, max_tiles, false, nullptr, cap);
+  r = enqueue_job(items, n_items, opt, s, P->ws, P->dit, P->n_tiles, P->n_slots, false, nullptr, cap);
   const hipError_t ec = hipStreamEndCapture(cap, &P->graph);
   (void)hipStreamDestroy(cap);
   if (r != WOS_OK || ec != hipSuccess) return bail(WOS_ERR_DEVICE, "graph capture failed");
@@ -1298,42 +1333,59 @@ wos_status plan_build(const wos_batch_item* items, int32_t n_items, const wos_op
   return WOS_OK;
 }
 
-// Times the walker of launch 0 of a built plan over its first `walks` walk ids with the
-// given shape, on the plan's own workspace (the per-walk buffers only: the reduction,
-// and with it the caller's outputs, is not run). Returns the best of `reps` runs in ms.
-wos_status time_shape(wos_plan* P, unsigned block, uint32_t tile, uint64_t walks, Tile* dtiles, int reps,
-                      hipStream_t st, float* best_ms) {
+// Item table of an autotuning sample: every item of the plan's first launch contributes
+// the first tiles of its share, in item order as in the real job, so that the sample
+// switches problems as the job does; `walks` walks in all, each item in proportion to its
+// walks. Slots are numbered for the sample alone.
+void sample_items(const wos_plan* P, uint32_t tile, uint64_t walks, std::vector<DevItem>& d, uint64_t* n_tiles,
+                  uint64_t* n_slots) {
+  d = P->dit[0];
+  double all = 0;
+  for (const DevItem& x : d) all += (double)x.n_points * x.walks;
+  uint64_t dummy_t = 0, dummy_s = 0;
+  layout_items(d, tile, &dummy_t, &dummy_s);
+  uint64_t tb = 0, sb = 0;
+  for (DevItem& x : d) {
+    const uint64_t item_walks = (uint64_t)x.n_points * x.walks;
+    const uint64_t share = std::min<uint64_t>(item_walks, (uint64_t)((double)walks * (double)item_walks / all));
+    const uint64_t per_tile = x.tiles_per_point > 0 ? tile : (uint64_t)x.points_per_tile * x.walks;
+    const uint64_t m = std::min<uint64_t>(x.n_tiles, (share + per_tile - 1) / per_tile);
+    x.tile_base = tb;
+    x.slot_base = sb;
+    x.n_tiles = m;
+    tb += m;
+    sb += x.tiles_per_point > 0 ? m : m * x.points_per_tile;
+  }
+  *n_tiles = tb;
+  *n_slots = sb;
+}
+
+// Times the walker of a plan's first launch over an autotuning sample with the given
+// shape, on the plan's counter and launch parameters and the sample's own item table and
+// slots (the reduction, and with it the caller's outputs, is not run). Returns the best of
+// `reps` runs in ms.
+wos_status time_shape(wos_plan* P, unsigned block, uint32_t tile, uint64_t walks, DevItem* ditems, uint64_t* dslots,
+                      int reps, hipStream_t st, float* best_ms) {
   Schedule s = P->s;
   wos_status r = grid_for_block(s, block);
   if (r != WOS_OK) return r;
-  // every item of the first launch contributes the first walks of its share, in item
-  // order as in the real tile table, so that the sample switches problems as the job does
-  std::vector<Tile> t;
+  s.tile_walks = tile;
+  std::vector<DevItem> d;
+  uint64_t nt = 0, ns = 0;
+  sample_items(P, tile, walks, d, &nt, &ns);
   const int n_items = (int)P->items.size();
-  double all = 0;
-  for (int k = 0; k < n_items; ++k) all += (double)P->dit[0][k].n_points * P->dit[0][k].walks;
-  for (int k = 0; k < n_items; ++k) {
-    const DevItem& d = P->dit[0][k];
-    const uint64_t item_walks = (uint64_t)d.n_points * d.walks;
-    const uint64_t total = std::min<uint64_t>(item_walks, (uint64_t)((double)walks * (double)item_walks / all));
-    for (uint64_t f = 0; f < total; f += tile) {
-      Tile x;
-      x.item = (uint32_t)k;
-      x.count = (uint32_t)std::min<uint64_t>(tile, total - f);
-      x.first = d.walk_base + f;
-      t.push_back(x);
-    }
-  }
-  WOS_HIP(hipMemcpyAsync(dtiles, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice, st));
+  WOS_HIP(hipMemcpyAsync(ditems, d.data(), d.size() * sizeof(DevItem), hipMemcpyHostToDevice, st));
   WOS_HIP(hipStreamSynchronize(st));
-  const WalkerLaunch L = walker_launch(&P->opt, s, P->ws, 0, n_items, dtiles, (uint32_t)t.size());
+  Workspace w = P->ws;
+  w.slots = dslots;
+  const WalkerLaunch L = walker_launch(&P->opt, s, w, ditems, n_items, nt);
   hipEvent_t a, b;
   WOS_HIP(hipEventCreate(&a));
   WOS_HIP(hipEventCreate(&b));
   *best_ms = 1e30f;
   hipError_t e = hipSuccess;
   for (int i = 0; i < reps && e == hipSuccess; ++i) {
-    if ((e = launch_reset(P->ws.counter, st)) != hipSuccess) break;
+    if ((e = launch_clear(dslots, ns * (uint64_t)s.slot_words, P->ws.counter, st)) != hipSuccess) break;
     if ((e = hipEventRecord(a, st)) != hipSuccess) break;
     if ((e = launch_walker(L, st)) != hipSuccess) break;
     if ((e = hipEventRecord(b, st)) != hipSuccess) break;
@@ -1369,15 +1421,27 @@ wos_status autotune(wos_plan* P, hipStream_t st, unsigned* block, uint32_t* tile
   const uint64_t walks = 8 * lanes;
   if (launch0 < walks) return WOS_OK;
   WOS_HIP(launch_set_params(P->ws.lp, 0, 0, st));
-  Tile* dtiles = nullptr;
-  const size_t max_t = (size_t)(walks / kTiles[0]) + (size_t)P->items.size() + 1;
-  WOS_HIP(hipMalloc(&dtiles, max_t * sizeof(Tile)));
+  uint64_t max_slots = 0;
+  for (uint32_t t : kTiles) {
+    std::vector<DevItem> d;
+    uint64_t nt = 0, ns = 0;
+    sample_items(P, t, walks, d, &nt, &ns);
+    max_slots = std::max(max_slots, ns);
+  }
+  DevItem* ditems = nullptr;
+  uint64_t* dslots = nullptr;
+  WOS_HIP(hipMalloc(&ditems, P->items.size() * sizeof(DevItem)));
+  hipError_t e = hipMalloc(&dslots, std::max<uint64_t>(max_slots, 1) * P->s.slot_words * sizeof(uint64_t));
+  if (e != hipSuccess) {
+    (void)hipFree(ditems);
+    return fail(WOS_ERR_OUT_OF_MEMORY, "autotune slot allocation failed");
+  }
   float best = 1e30f;
   wos_status r = WOS_OK;
   for (unsigned b : kBlocks) {
     for (uint32_t t : kTiles) {
       float ms = 0;
-      if ((r = time_shape(P, b, t, walks, dtiles, 2, st, &ms)) != WOS_OK) break;
+      if ((r = time_shape(P, b, t, walks, ditems, dslots, 2, st, &ms)) != WOS_OK) break;
       if (ms < best) {
         best = ms;
         *block = b;
@@ -1386,7 +1450,8 @@ wos_status autotune(wos_plan* P, hipStream_t st, unsigned* block, uint32_t* tile
     }
     if (r != WOS_OK) break;
   }
-  (void)hipFree(dtiles);
+  (void)hipFree(ditems);
+  (void)hipFree(dslots);
   if (r != WOS_OK) return r;
   std::lock_guard<std::mutex> lk(g_occ_mutex);
   g_tuned[tune_key(P->s)] = std::make_pair(*block, *tile);
@@ -1460,7 +1525,7 @@ wos_status wos_plan_time(wos_plan* P, uint64_t seed, uint64_t walk_offset_add, v
     if (e != hipSuccess) r = fail(WOS_ERR_DEVICE, "launch failed");
   }
   if (r == WOS_OK)
-    r = enqueue_job(P->items.data(), (int)P->items.size(), &P->opt, P->s, P->ws, P->dit, P->n_tiles, P->max_tiles,
+    r = enqueue_job(P->items.data(), (int)P->items.size(), &P->opt, P->s, P->ws, P->dit, P->n_tiles, P->n_slots,
                     false, nullptr, st, &marks);
   if (r == WOS_OK) {
     hipError_t e = hipEventRecord(t1, st);

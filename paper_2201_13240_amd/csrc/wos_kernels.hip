@@ -1,6 +1,7 @@
 // Kernels of the delta-tracking walk on spheres and their host-side launchers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -32,12 +33,15 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
 
 // ------------------------------------------------------------------ walker
 //
-// Persistent kernel. Work is a table of tiles (contiguous walk ids of one item); a
-// wavefront takes one tile at a time with a single atomic and hands its walks to idle
-// lanes (ballot + mbcnt), so lanes whose walk ends pick up a new walk at the next step
-// instead of idling until the longest walk of the wave finishes. A wave only switches
-// to a tile of another item (another problem) once all its lanes are idle, so the
-// problem, and with it every field table and geometry pointer, stays wave-uniform.
+// Persistent kernel. Work is a sequence of tiles (a run of walks of one point, or whole
+// points; see DevItem); a wavefront takes one tile at a time with a single atomic and hands
+// its walks to idle lanes (ballot + mbcnt), so lanes whose walk ends pick up a new walk at
+// the next step instead of idling until the longest walk of the wave finishes. A wave only
+// switches to a tile of another item (another problem) once all its lanes are idle, so the
+// problem, and with it every field table and geometry pointer, stays wave-uniform. A walk
+// that ends adds its estimate, its square, its distance queries and its radius proposals
+// into the slot of its (tile, point) with integer atomics on exact fixed-point limbs
+// (see the slot layout), so the sums do not depend on the order in which walks end.
 //
 // One walk (Sec. 5.1, supplemental Alg. 1, after the change of variables of Sec. 4.1
 // and App. A) keeps
@@ -52,10 +56,11 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
 template <typename T>
 struct WalkerArgs {
   const DevItem* items;
-  const Tile* tiles;
-  uint32_t n_tiles;
+  int32_t n_items;
+  uint32_t n_tiles;      // tiles of all items
   uint32_t* tile_counter;
-  WalkRecord* records;   // [walk id] estimate, distance queries | flags, radius proposals
+  uint64_t* slots;       // accumulation slots (slot_words words each)
+  int32_t slot_words;
   const LaunchParams* lp;
   uint64_t max_steps;
   int32_t variant;
@@ -63,7 +68,7 @@ struct WalkerArgs {
   int32_t rr;
   T ww_lo;
   T ww_hi;               // > 0: expected-value splitting above this weight (delta tracking)
-  T* grad;               // [walk id][GradRecord<DIM>::kStride] or null: gradient records
+  T* grad;               // [grid lane][GradRecord<DIM>::kStride] or null: gradient records
   uint64_t* events;      // event-counting build only: [kEvents]
 };
 
@@ -107,13 +112,64 @@ __device__ __forceinline__ void add_estimate(T& A, T& Ac, T term, int compensate
   }
 }
 
+// Integer add into an accumulation slot. A slot is written only by the wavefront that runs
+// its tile (and read by a later kernel), so the atomic needs no scope beyond the work-group:
+// it is performed in the L2 of the wave's own XCD.
+__device__ __forceinline__ void slot_add(uint64_t* w, uint64_t v) {
+  __hip_atomic_fetch_add((unsigned long long*)w, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Adds v (|v| < 2^47, finite) to the fixed-point limbs L[0..5] (limb k has weight
+// 2^(32k - 96)): |v| 2^96 is cut into 32-bit chunks from the top with exact floating
+// operations (scaling by powers of two, floor and a fused multiply-add remainder), and a
+// negative v adds the negated chunks. Bits below 2^-96 are dropped (truncation).
+__device__ __forceinline__ void fx_add(uint64_t* L, double v) {
+  double a = fabs(v) * 0x1p96;
+  const bool neg = v < 0;
+#pragma unroll
+  for (int k = kFxLimbs - 1; k >= 0; --k) {
+    const double w = __builtin_ldexp(1.0, 32 * k);
+    const double c = floor(a * __builtin_ldexp(1.0, -32 * k));
+    a = fma(-c, w, a);
+    if (c != 0.0) {
+      const uint64_t u = (uint64_t)(uint32_t)c;
+      slot_add(&L[k], neg ? (uint64_t)0 - u : u);
+    }
+  }
+}
+
+// What a finished walk adds to its slot: the estimate v and v^2, its distance queries,
+// radius proposals and flags, and with gradient records the dim components of its
+// gradient estimate and their squares.
+__device__ __forceinline__ void emit_walk(uint64_t* slot, double v, uint32_t steps_flags, uint32_t trials,
+                                          uint32_t step_mask, uint32_t flag_capped, uint32_t flag_rr,
+                                          const double* g, int gdim) {
+  uint64_t flags = (steps_flags & flag_capped) ? 1ull : 0ull;
+  if (steps_flags & flag_rr) flags += 1ull << kFlagShiftKilled;
+  bool bad = !(fabs(v) < kFxMaxValue);
+  for (int c = 0; c < gdim; ++c) bad = bad || !(fabs(g[c]) < kFxMaxValue);
+  if (bad) {
+    flags += 1ull << kFlagShiftBad;
+  } else {
+    fx_add(slot + kSlotSum, v);
+    fx_add(slot + kSlotSumSq, v * v);
+    for (int c = 0; c < gdim; ++c) {
+      fx_add(slot + kSlotGrad + 2 * kFxLimbs * c, g[c]);
+      fx_add(slot + kSlotGrad + 2 * kFxLimbs * c + kFxLimbs, g[c] * g[c]);
+    }
+  }
+  slot_add(slot + kSlotSteps, steps_flags & step_mask);
+  if (trials) slot_add(slot + kSlotTrials, trials);
+  if (flags) slot_add(slot + kSlotFlags, flags);
+}
+
 // Buffers written by the walker are separate __restrict__ parameters, so loads of the
 // problem tables (read-only, at wave-uniform addresses) can be served by scalar loads.
 // MODE: 0 delta tracking, 1 delta tracking with the extras that cost registers (weight-window
 // splitting, gradient records), 2 next flight.
 template <typename T, int DIM, int GEOM, bool COUNT, int MODE>
 __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restrict__ tile_counter,
-                                            WalkRecord* __restrict__ records, uint64_t* __restrict__ events_out) {
+                                            uint64_t* __restrict__ slots, uint64_t* __restrict__ events_out) {
   using SL = Slots<T, DIM>;
   constexpr bool NF = MODE == 2;
   constexpr bool EXTRA = MODE == 1;
@@ -133,17 +189,21 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
   const uint64_t seed = a.lp->seed;
   const uint64_t offset_add = a.lp->walk_offset_add;
   const WOS_GLOBAL DevItem* items = gptr(a.items);
-  const WOS_GLOBAL Tile* tiles = gptr(a.tiles);
-  // ---- wave-uniform scheduling state
-  int cur_item = -1;
-  uint64_t res_next = 0, res_end = 0;
-  int pend_tile = -1;
+  // ---- wave-uniform scheduling state: the current item, the tile being handed out
+  // (walks res_next .. res_end - 1 of it: point tl_p0 + (tl_j0 + r) / walks), the next
+  // claimed tile, and the item searched for it (tiles are claimed in increasing order)
+  int cur_item = -1, search_item = 0;
+  uint32_t res_next = 0, res_end = 0;
+  uint32_t tl_p0 = 0, tl_j0 = 0, tl_slot0 = 0, tl_walks = 1, tl_single = 1;
+  int64_t pend_tile = -1;
   bool queue_done = false;
   const WOS_GLOBAL DevProblem<T>* Pp = nullptr;
   // ---- lane state: phase 0 = idle, 1 = new walk whose gamma(x0) and its gradient are still
-  // to be evaluated (gradient records only), 2 = walking
+  // to be evaluated (gradient records only), 2 = walking; slot: accumulation slot of the walk
   int phase = 0;
-  uint64_t wid = 0;
+  uint32_t slot = 0;
+  T* const grad_rec = EXTRA && a.grad ? a.grad + ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * GradRecord<DIM>::kStride
+                                     : nullptr;
   T x[DIM];
   T gamma0 = 0, gx = 0;
   bool gx_known = false;
@@ -188,40 +248,66 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
             queue_done = true;
             break;
           }
-          pend_tile = uniform_int((int)t);
+          pend_tile = (int64_t)t;
+          while (pend_tile >= (int64_t)(items[search_item].tile_base + items[search_item].n_tiles))
+            search_item = uniform_int(search_item + 1);
         }
-        const uint32_t tl_item = tiles[pend_tile].item;
-        if ((int)tl_item != cur_item) {
+        if (search_item != cur_item) {
           if (idle != ~0ull) break;  // drain the wave before switching problems
-          cur_item = uniform_int((int)tl_item);
+          cur_item = uniform_int(search_item);
           Pp = (const WOS_GLOBAL DevProblem<T>*)uniform_ptr(items[cur_item].problem);
         }
-        const uint64_t tl_first = tiles[pend_tile].first;
-        res_next = uniform_u64(tl_first);
-        res_end = uniform_u64(tl_first + tiles[pend_tile].count);
+        // the tile's walks, from the item's regular cut (DevItem)
+        G<DevItem>& it = items[cur_item];
+        const uint64_t tl = (uint64_t)pend_tile - it.tile_base;
+        const uint32_t walks = (uint32_t)it.walks;
+        if (it.tiles_per_point > 0u) {
+          const uint32_t tpp = it.tiles_per_point;
+          const uint32_t p0 = (uint32_t)(tl / tpp);
+          const uint32_t j0 = (uint32_t)(tl - (uint64_t)p0 * tpp) * it.tile_len;
+          tl_p0 = uniform_int((int)p0);
+          tl_j0 = uniform_int((int)j0);
+          res_end = uniform_int((int)min(it.tile_len, walks - j0));
+          tl_single = 1;
+        } else {
+          const uint32_t p0 = (uint32_t)tl * it.points_per_tile;
+          const uint32_t np = (uint32_t)min((int64_t)it.points_per_tile, it.n_points - (int64_t)p0);
+          tl_p0 = uniform_int((int)p0);
+          tl_j0 = 0;
+          res_end = uniform_int((int)(np * walks));
+          tl_single = 0;
+        }
+        tl_slot0 = uniform_int((int)(it.slot_base + (it.tiles_per_point > 0u ? tl : (uint64_t)tl_p0)));
+        tl_walks = uniform_int((int)walks);
+        res_next = 0;
         pend_tile = -1;
       }
       const uint32_t n_idle = __popcll(idle);
-      const uint64_t avail = res_end - res_next;
-      const uint32_t take = avail < (uint64_t)n_idle ? (uint32_t)avail : n_idle;
+      const uint32_t avail = res_end - res_next;
+      const uint32_t take = avail < n_idle ? avail : n_idle;
       const uint32_t rank = lanes_below(idle);
       if (phase == 0 && rank < take) {
         // new walk: set-up only; gamma(x0) comes from the per-point table, or for gradient
         // records is evaluated with the other lanes' step
         G<DevItem>& it = items[cur_item];
-        wid = res_next + rank;
-        const uint64_t local = wid - it.walk_base;
-        const uint64_t n = (uint64_t)it.n_points;
-        const uint64_t p = local % n;
-        const uint64_t j = local / n;
+        const uint32_t r = res_next + rank;
+        uint32_t p, j;
+        if (tl_single) {
+          p = tl_p0;
+          j = tl_j0 + r;
+          slot = tl_slot0;
+        } else {
+          const uint32_t dq = r / tl_walks;
+          p = tl_p0 + dq;
+          j = r - dq * tl_walks;
+          slot = tl_slot0 + dq;
+        }
         nsteps = 0;
         ntrials = 0;
-        if (!gptr(it.inside)[p]) {
-          records[wid] = WalkRecord{__builtin_nan(""), 0u, 0u};
-        } else {
+        if (gptr(it.inside)[p]) {
 #pragma unroll
-          for (int i = 0; i < DIM; ++i) x[i] = (T)gptr(it.points)[p * DIM + i];
-          rng.init(seed, (uint32_t)(it.walk_offset + offset_add + j), (uint32_t)p, it.problem_index);
+          for (int i = 0; i < DIM; ++i) x[i] = (T)gptr(it.points)[(size_t)p * DIM + i];
+          rng.init(seed, (uint32_t)(it.walk_offset + offset_add + j), p, it.problem_index);
           Pi = 1;
           A = 0;
           Ac = 0;
@@ -239,6 +325,7 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
           }
           if constexpr (COUNT) ++ev[EV_WALKS];
         }
+        // a point outside the domain runs no walk; the reduction marks its sums
       }
       res_next += take;
       idle = __ballot(phase == 0);
@@ -363,7 +450,8 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
           phase = 3;
         }
         if (done) {
-          records[wid] = WalkRecord{(double)A + (double)Ac, (nsteps & kStepMask) | flag, ntrials};
+          emit_walk(slots + (size_t)slot * a.slot_words, (double)A + (double)Ac, (nsteps & kStepMask) | flag, ntrials,
+                    kStepMask, kFlagCapped, kFlagRR, nullptr, 0);
           if constexpr (COUNT) ev[EV_TRIALS] += ntrials;
           phase = 0;
         }
@@ -450,7 +538,7 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
           if (EXTRA && a.grad) {
             // gradient record of the walk: grad gamma(x0) now, the first ball's terms
             // when it is sampled (they stay zero for a walk that starts in the shell)
-            T* gr = a.grad + (size_t)wid * GradRecord<DIM>::kStride;
+            T* gr = grad_rec;
             gr[0] = 0;
 #pragma unroll
             for (int i = 0; i < DIM; ++i) {
@@ -474,7 +562,7 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
           if (EXTRA && a.grad && (nsteps & kStepMask) == 1u && (split_state >> 8) == 0u) {
             // first ball (supplemental Sec. 2): A0 = its source term, a = grad G/G at y,
             // b = a after a volume event or grad P/P at the exit point z
-            T* gr = a.grad + (size_t)wid * GradRecord<DIM>::kStride;
+            T* gr = grad_rec;
             T w[DIM], r2 = 0;
 #pragma unroll
             for (int i = 0; i < DIM; ++i) {
@@ -567,7 +655,20 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
             rng.init(seed, rng.walk, rng.point, (rng.problem & 0xFFFFu) | ((split_state >> 8) << 16));
             pending = false;
           } else {
-            records[wid] = WalkRecord{(double)A + (double)Ac, nsteps, ntrials};
+            const double v = (double)A + (double)Ac;
+            double g[DIM];
+            int gdim = 0;
+            if (EXTRA && a.grad) {
+              // per-walk gradient estimate (supplemental Sec. 2):
+              // A0 a + (A - A0) b - A grad gamma(x0), from the lane's record
+              const T* gr = grad_rec;
+              const double a0 = (double)gr[0];
+#pragma unroll
+              for (int c = 0; c < DIM; ++c)
+                g[c] = a0 * (double)gr[1 + c] + (v - a0) * (double)gr[1 + DIM + c] - v * (double)gr[1 + 2 * DIM + c];
+              gdim = DIM;
+            }
+            emit_walk(slots + (size_t)slot * a.slot_words, v, nsteps, ntrials, kStepMask, kFlagCapped, kFlagRR, g, gdim);
             if constexpr (COUNT) ev[EV_TRIALS] += ntrials;
             phase = 0;
           }
@@ -593,48 +694,104 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
 // unless asked to fit 256 (2 waves per SIMD).
 template <int DIM, int GEOM, bool COUNT, int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WOS_WAVES_FP32)))
-walker_kernel_fp32(WalkerArgs<float> a, uint32_t* __restrict__ tile_counter, WalkRecord* __restrict__ records,
+walker_kernel_fp32(WalkerArgs<float> a, uint32_t* __restrict__ tile_counter, uint64_t* __restrict__ slots,
                    uint64_t* __restrict__ events_out) {
-  walker_body<float, DIM, GEOM, COUNT, MODE>(a, tile_counter, records, events_out);
+  walker_body<float, DIM, GEOM, COUNT, MODE>(a, tile_counter, slots, events_out);
 }
 
 template <int DIM, int GEOM, bool COUNT, int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WOS_WAVES_FP64)))
-walker_kernel_fp64(WalkerArgs<double> a, uint32_t* __restrict__ tile_counter, WalkRecord* __restrict__ records,
+walker_kernel_fp64(WalkerArgs<double> a, uint32_t* __restrict__ tile_counter, uint64_t* __restrict__ slots,
                    uint64_t* __restrict__ events_out) {
-  walker_body<double, DIM, GEOM, COUNT, MODE>(a, tile_counter, records, events_out);
+  walker_body<double, DIM, GEOM, COUNT, MODE>(a, tile_counter, slots, events_out);
 }
 
-// ------------------------------------------------------------------ reduce (fixed order)
+// ------------------------------------------------------------------ reduce (exact sums)
 
-__global__ void reduce_kernel(DevItem it, const WalkRecord* __restrict__ records) {
+// Carries of limbs L[0..5] so that L[0..4] lie in [0, 2^32); the top limb keeps the sign.
+__device__ __forceinline__ void fx_normalize(int64_t* L) {
+#pragma unroll
+  for (int k = 0; k < kFxLimbs - 1; ++k) {
+    const int64_t c = L[k] >> 32;   // floor division by 2^32
+    L[k] -= c * 4294967296ll;
+    L[k + 1] += c;
+  }
+}
+
+// The value sum_k L[k] 2^(32k - 96) of normalised limbs, summed in a fixed order with
+// the Neumaier correction (each term is exact in double).
+__device__ __forceinline__ double fx_value(const int64_t* L) {
+  double s = 0, c = 0;
+#pragma unroll
+  for (int k = 0; k < kFxLimbs; ++k) {
+    const double t = (double)L[k] * __builtin_ldexp(1.0, 32 * k - kFxFracBits);
+    const double u = s + t;
+    c += fabs(s) >= fabs(t) ? (s - u) + t : (t - u) + s;
+    s = u;
+  }
+  return s + c;
+}
+
+// Adds the limbs of `words` (a slot field) to L and normalises.
+__device__ __forceinline__ void fx_accumulate(int64_t* L, const uint64_t* words) {
+#pragma unroll
+  for (int k = 0; k < kFxLimbs; ++k) L[k] += (int64_t)words[k];
+  fx_normalize(L);
+}
+
+// Per point: the exact sums of its slots (one per tile it was cut into), converted to
+// double once and added into the caller's accumulators. With grad_dim > 0 also the sums
+// of the gradient components (supplemental Sec. 2).
+template <int GD>
+__global__ void reduce_kernel(DevItem it, const uint64_t* __restrict__ slots, int slot_words) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint64_t capped = 0, killed = 0, ntr = 0;
   if (p < it.n_points) {
-    double s = 0, cs = 0, q = 0, cq = 0;
-    uint64_t nst = 0;
-    for (uint64_t j = 0; j < it.walks; ++j) {
-      const uint64_t idx = it.walk_base + j * (uint64_t)it.n_points + (uint64_t)p;
-      const WalkRecord r = records[idx];
-      const double v = r.value;
-      const uint32_t st = r.steps;
-      nst += st & kStepMask;
-      capped += (st & kFlagCapped) ? 1 : 0;
-      killed += (st & kFlagRR) ? 1 : 0;
-      ntr += r.trials;
-      // Neumaier summation of v and v^2
-      double t = s + v;
-      cs += fabs(s) >= fabs(v) ? (s - t) + v : (v - t) + s;
-      s = t;
-      const double v2 = v * v;
-      t = q + v2;
-      cq += fabs(q) >= fabs(v2) ? (q - t) + v2 : (v2 - t) + q;
-      q = t;
+    const uint32_t spp = it.tiles_per_point > 0u ? it.tiles_per_point : 1u;
+    if (!it.inside[p]) {
+      const double nan = __builtin_nan("");
+      it.sum[p] += nan;
+      it.sum_sq[p] += nan;
+#pragma unroll
+      for (int c = 0; c < GD; ++c) {
+        it.grad_sum[p * GD + c] += nan;
+        it.grad_sum_sq[p * GD + c] += nan;
+      }
+    } else {
+      int64_t S[kFxLimbs] = {0}, Q[kFxLimbs] = {0};
+      int64_t GS[GD > 0 ? GD : 1][kFxLimbs], GQ[GD > 0 ? GD : 1][kFxLimbs];
+#pragma unroll
+      for (int c = 0; c < (GD > 0 ? GD : 1); ++c)
+#pragma unroll
+        for (int k = 0; k < kFxLimbs; ++k) GS[c][k] = GQ[c][k] = 0;
+      uint64_t nst = 0, bad = 0;
+      for (uint32_t k = 0; k < spp; ++k) {
+        const uint64_t* w = slots + (size_t)(it.slot_base + (uint64_t)p * spp + k) * slot_words;
+        fx_accumulate(S, w + kSlotSum);
+        fx_accumulate(Q, w + kSlotSumSq);
+        nst += w[kSlotSteps];
+        ntr += w[kSlotTrials];
+        const uint64_t f = w[kSlotFlags];
+        capped += f & ((1ull << kFlagShiftKilled) - 1);
+        killed += (f >> kFlagShiftKilled) & ((1ull << (kFlagShiftBad - kFlagShiftKilled)) - 1);
+        bad += f >> kFlagShiftBad;
+#pragma unroll
+        for (int c = 0; c < GD; ++c) {
+          fx_accumulate(GS[c], w + kSlotGrad + 2 * kFxLimbs * c);
+          fx_accumulate(GQ[c], w + kSlotGrad + 2 * kFxLimbs * c + kFxLimbs);
+        }
+      }
+      const double nan = __builtin_nan("");
+      it.sum[p] += bad ? nan : fx_value(S);
+      it.sum_sq[p] += bad ? nan : fx_value(Q);
+#pragma unroll
+      for (int c = 0; c < GD; ++c) {
+        it.grad_sum[p * GD + c] += bad ? nan : fx_value(GS[c]);
+        it.grad_sum_sq[p * GD + c] += bad ? nan : fx_value(GQ[c]);
+      }
+      it.n_steps[p] += nst;
     }
-    it.sum[p] += s + cs;
-    it.sum_sq[p] += q + cq;
     it.n_walks[p] += it.walks;
-    it.n_steps[p] += nst;
   }
   if (it.counters) {
     for (int off = 32; off > 0; off >>= 1) {
@@ -650,39 +807,12 @@ __global__ void reduce_kernel(DevItem it, const WalkRecord* __restrict__ records
   }
 }
 
-// Gradient sums per point (supplemental Sec. 2): each walk's estimate is
-// A0 a + (A - A0) b - A grad gamma(x0) from its record and its value A; fixed order
-// over walks, Neumaier-compensated per component.
-template <typename T, int DIM>
-__global__ void reduce_grad_kernel(DevItem it, const WalkRecord* __restrict__ records, const T* __restrict__ grad) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= it.n_points) return;
-  double s[DIM], cs[DIM], q[DIM], cq[DIM];
-#pragma unroll
-  for (int k = 0; k < DIM; ++k) s[k] = cs[k] = q[k] = cq[k] = 0;
-  constexpr int kS = GradRecord<DIM>::kStride;
-  for (uint64_t j = 0; j < it.walks; ++j) {
-    const uint64_t idx = it.walk_base + j * (uint64_t)it.n_points + (uint64_t)p;
-    const double v = records[idx].value;
-    const T* gr = grad + (size_t)idx * kS;
-    const double a0 = (double)gr[0];
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-      const double g = a0 * (double)gr[1 + k] + (v - a0) * (double)gr[1 + DIM + k] - v * (double)gr[1 + 2 * DIM + k];
-      double t = s[k] + g;
-      cs[k] += fabs(s[k]) >= fabs(g) ? (s[k] - t) + g : (g - t) + s[k];
-      s[k] = t;
-      const double g2 = g * g;
-      t = q[k] + g2;
-      cq[k] += fabs(q[k]) >= fabs(g2) ? (q[k] - t) + g2 : (g2 - t) + q[k];
-      q[k] = t;
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < DIM; ++k) {
-    it.grad_sum[p * DIM + k] += s[k] + cs[k];
-    it.grad_sum_sq[p * DIM + k] += q[k] + cq[k];
-  }
+// Zeroes the slots (and the tile counter) before a walker launch; a kernel rather than a
+// memset node, so that it can be captured in the plan's graph.
+__global__ void clear_kernel(uint64_t* __restrict__ p, uint64_t n, uint32_t* counter) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
 }
 
 __global__ void reset_kernel(uint32_t* counter) {
@@ -960,21 +1090,22 @@ static const void* walker_entry() {
 
 template <typename T, int DIM, int GEOM, bool COUNT, int MODE>
 static void launch_walker_k(dim3 g, dim3 b, hipStream_t st, const WalkerArgs<T>& a, uint32_t* counter,
-                            WalkRecord* records, uint64_t* events) {
+                            uint64_t* slots, uint64_t* events) {
   if constexpr (sizeof(T) == 4)
-    hipLaunchKernelGGL((walker_kernel_fp32<DIM, GEOM, COUNT, MODE>), g, b, 0, st, a, counter, records, events);
+    hipLaunchKernelGGL((walker_kernel_fp32<DIM, GEOM, COUNT, MODE>), g, b, 0, st, a, counter, slots, events);
   else
-    hipLaunchKernelGGL((walker_kernel_fp64<DIM, GEOM, COUNT, MODE>), g, b, 0, st, a, counter, records, events);
+    hipLaunchKernelGGL((walker_kernel_fp64<DIM, GEOM, COUNT, MODE>), g, b, 0, st, a, counter, slots, events);
 }
 
 template <typename T, int DIM, int GEOM>
 static hipError_t launch_walker_t(const WalkerLaunch& L, hipStream_t st) {
   WalkerArgs<T> a;
   a.items = L.items;
-  a.tiles = L.tiles;
+  a.n_items = L.n_items;
   a.n_tiles = L.n_tiles;
   a.tile_counter = L.tile_counter;
-  a.records = L.records;
+  a.slots = L.slots;
+  a.slot_words = L.slot_words;
   a.lp = L.lp;
   a.max_steps = L.max_steps;
   a.variant = L.variant;
@@ -988,14 +1119,14 @@ static hipError_t launch_walker_t(const WalkerLaunch& L, hipStream_t st) {
   uint64_t* ev = L.events;
   const int mode = walker_mode(L.variant, L.grad != nullptr, L.ww_hi > 0);
   if (mode == 2) {
-    if (ev) launch_walker_k<T, DIM, GEOM, true, 2>(g, b, st, a, L.tile_counter, L.records, ev);
-    else launch_walker_k<T, DIM, GEOM, false, 2>(g, b, st, a, L.tile_counter, L.records, ev);
+    if (ev) launch_walker_k<T, DIM, GEOM, true, 2>(g, b, st, a, L.tile_counter, L.slots, ev);
+    else launch_walker_k<T, DIM, GEOM, false, 2>(g, b, st, a, L.tile_counter, L.slots, ev);
   } else if (mode == 1) {
-    if (ev) launch_walker_k<T, DIM, GEOM, true, 1>(g, b, st, a, L.tile_counter, L.records, ev);
-    else launch_walker_k<T, DIM, GEOM, false, 1>(g, b, st, a, L.tile_counter, L.records, ev);
+    if (ev) launch_walker_k<T, DIM, GEOM, true, 1>(g, b, st, a, L.tile_counter, L.slots, ev);
+    else launch_walker_k<T, DIM, GEOM, false, 1>(g, b, st, a, L.tile_counter, L.slots, ev);
   } else {
-    if (ev) launch_walker_k<T, DIM, GEOM, true, 0>(g, b, st, a, L.tile_counter, L.records, ev);
-    else launch_walker_k<T, DIM, GEOM, false, 0>(g, b, st, a, L.tile_counter, L.records, ev);
+    if (ev) launch_walker_k<T, DIM, GEOM, true, 0>(g, b, st, a, L.tile_counter, L.slots, ev);
+    else launch_walker_k<T, DIM, GEOM, false, 0>(g, b, st, a, L.tile_counter, L.slots, ev);
   }
   return hipGetLastError();
 }
@@ -1050,23 +1181,18 @@ const void* walker_symbol(int fp64, int dim, int geom, int mode) {
   return fp64 ? walker_symbol_dim<double>(dim, geom, mode) : walker_symbol_dim<float>(dim, geom, mode);
 }
 
-hipError_t launch_reduce(const DevItem& it, const WalkRecord* records, hipStream_t st) {
+hipError_t launch_reduce(int grad_dim, const DevItem& it, const uint64_t* slots, int slot_words, hipStream_t st) {
   if (it.n_points == 0) return hipSuccess;
-  hipLaunchKernelGGL(reduce_kernel, dim3(blocks_for(it.n_points, 256)), dim3(256), 0, st, it, records);
+  const dim3 g(blocks_for(it.n_points, 256)), b(256);
+  if (grad_dim == 2) hipLaunchKernelGGL(reduce_kernel<2>, g, b, 0, st, it, slots, slot_words);
+  else if (grad_dim == 3) hipLaunchKernelGGL(reduce_kernel<3>, g, b, 0, st, it, slots, slot_words);
+  else hipLaunchKernelGGL(reduce_kernel<0>, g, b, 0, st, it, slots, slot_words);
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_grad(int fp64, int dim, const DevItem& it, const WalkRecord* records, const void* grad,
-                              hipStream_t st) {
-  if (it.n_points == 0 || !it.grad_sum) return hipSuccess;
-  const dim3 g(blocks_for(it.n_points, 256)), b(256);
-  if (fp64) {
-    if (dim == 2) hipLaunchKernelGGL((reduce_grad_kernel<double, 2>), g, b, 0, st, it, records, (const double*)grad);
-    else hipLaunchKernelGGL((reduce_grad_kernel<double, 3>), g, b, 0, st, it, records, (const double*)grad);
-  } else {
-    if (dim == 2) hipLaunchKernelGGL((reduce_grad_kernel<float, 2>), g, b, 0, st, it, records, (const float*)grad);
-    else hipLaunchKernelGGL((reduce_grad_kernel<float, 3>), g, b, 0, st, it, records, (const float*)grad);
-  }
+hipError_t launch_clear(uint64_t* p, uint64_t n, uint32_t* counter, hipStream_t st) {
+  const unsigned blocks = (unsigned)std::min<uint64_t>(std::max<uint64_t>((n + 255) / 256, 1), 4096);
+  hipLaunchKernelGGL(clear_kernel, dim3(blocks), dim3(256), 0, st, p, n, counter);
   return hipGetLastError();
 }
 

@@ -15,10 +15,11 @@ struct WalkerLaunch {
   unsigned grid;
   unsigned block;
   const DevItem* items;
-  const Tile* tiles;
-  uint32_t n_tiles;
+  int n_items;
+  uint32_t n_tiles;   // tiles of all items
   uint32_t* tile_counter;
-  WalkRecord* records;
+  uint64_t* slots;    // accumulation slots, slot_words(grad dim) words each, zeroed before the launch
+  int slot_words;
   const LaunchParams* lp;
   uint64_t max_steps;
   int variant;
@@ -26,7 +27,7 @@ struct WalkerLaunch {
   int rr;
   double ww_lo;
   double ww_hi;       // 0: no splitting
-  void* grad;         // gradient records (T[walk id][1 + 3 dim]) or null
+  void* grad;         // gradient records (T[grid lane][1 + 3 dim]) or null
   uint64_t* events;   // non-null selects the event-counting build of the walker
 };
 
@@ -34,11 +35,12 @@ hipError_t launch_walker(const WalkerLaunch& L, hipStream_t st);
 // 0 delta tracking, 1 delta tracking with splitting or gradient records, 2 next flight
 int walker_mode(int variant, bool grad, bool split);
 const void* walker_symbol(int fp64, int dim, int geom, int mode);
-hipError_t launch_reduce(const DevItem& it, const WalkRecord* records, hipStream_t st);
+// Per-point sums of one item from its slots, added into the item's outputs.
+hipError_t launch_reduce(int grad_dim, const DevItem& it, const uint64_t* slots, int slot_words, hipStream_t st);
+// Zeroes n words at p and the tile counter (a kernel, so that it can sit in a captured graph).
+hipError_t launch_clear(uint64_t* p, uint64_t n, uint32_t* counter, hipStream_t st);
 hipError_t launch_finalize_components(const double* sum, const double* sum_sq, const uint64_t* nw, int64_t n, int dim,
                                       double* mean, double* se, hipStream_t st);
-hipError_t launch_reduce_grad(int fp64, int dim, const DevItem& it, const WalkRecord* records, const void* grad,
-                              hipStream_t st);
 hipError_t launch_reset(uint32_t* counter, hipStream_t st);
 hipError_t launch_set_params(LaunchParams* lp, uint64_t seed, uint64_t walk_offset_add, hipStream_t st);
 hipError_t launch_classify(int dim, int geom, const void* P64, const double* pts, int64_t n, int8_t* inside,

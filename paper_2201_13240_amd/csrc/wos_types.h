@@ -140,7 +140,12 @@ struct DevProblem {
   Spectral2D<T> spec;
 };
 
-// One query batch of a launch (device copy).
+// One query batch of a launch (device copy). Walk j of point p is walk (p, j); the
+// item's walks are cut into tiles in point-major order: with tiles_per_point > 0 every
+// point takes that many tiles of tile_len walks (the last one may be shorter), otherwise
+// a tile takes points_per_tile whole points. A wavefront runs every walk of a tile it
+// takes. Each (tile, point) pair owns one accumulation slot; the slots of point p are
+// slot_base + p * max(1, tiles_per_point) + k for its k-th tile.
 struct DevItem {
   const void* problem;       // DevProblem<T>* in the walker's precision
   const double* points;      // [n_points][dim]
@@ -153,33 +158,46 @@ struct DevItem {
   int64_t n_points;
   uint64_t walks;            // walks per point in this launch
   uint64_t walk_offset;      // first global walk index of this launch
-  uint64_t walk_base;        // offset of this item in the launch's walk-id space
   uint64_t point_base;       // offset of this item in the launch's point space
   uint32_t problem_index;
-  uint32_t pad;
+  uint32_t tile_len;         // walks per tile when tiles_per_point > 0
   double* grad_sum;          // [n_points][dim] or null
   double* grad_sum_sq;
   const void* gamma0;        // [n_points] gamma at each interior query point, walker precision
+  uint64_t tile_base;        // index of the item's first tile in the launch
+  uint64_t n_tiles;          // tiles of this item
+  uint64_t slot_base;        // first accumulation slot of this item
+  uint32_t tiles_per_point;
+  uint32_t points_per_tile;  // used when tiles_per_point == 0
 };
 
-// A contiguous range of walk ids of one item; waves take whole tiles.
-struct Tile {
-  uint32_t item;
-  uint32_t count;
-  uint64_t first;            // first walk id (launch space)
-};
-
-// What a finished walk leaves for the per-point reduction: its estimate, its distance
-// queries with the cap / roulette flags in the top bits, and its radius proposals. One
-// 16-byte record per walk id, written with a single vector store.
-struct __attribute__((aligned(16))) WalkRecord {
-  double value;
-  uint32_t steps;
-  uint32_t trials;
-};
+// Per-(tile, point) accumulation slot, in 64-bit words. Sums of per-walk estimates are
+// kept exactly, as fixed-point numbers: v 2^96 is cut into 32-bit chunks of weight
+// 2^(32k - 96), k = 0..5, and chunk k is added to limb k with an integer atomic. Integer
+// addition is associative, so a slot's content does not depend on the order in which
+// the walks of its tile finish, and results are reproducible bit for bit whatever the
+// launch shape. A double has 53 significant bits, so a walk touches at most three limbs
+// per sum. Per-walk estimates are limited to |v| < 2^47 (then v^2 < 2^94 fits the top
+// limb); a larger or non-finite one is counted in the `bad` field and makes the
+// point's sums NaN.
+constexpr int kFxLimbs = 6;
+constexpr int kFxFracBits = 96;
+constexpr double kFxMaxValue = 140737488355328.0;   // 2^47
+constexpr int kSlotSum = 0;       // [kFxLimbs] limbs of the sum of estimates
+constexpr int kSlotSumSq = 6;     // [kFxLimbs] limbs of the sum of their squares
+constexpr int kSlotSteps = 12;    // distance queries
+constexpr int kSlotTrials = 13;   // radius proposals (next flight: inner points)
+constexpr int kSlotFlags = 14;    // walks cut at max_steps | roulette kills << 21 | bad << 42
+constexpr int kSlotGrad = 16;     // per gradient component c: [kFxLimbs] sum, [kFxLimbs] sum of squares
+constexpr int kFlagShiftKilled = 21;
+constexpr int kFlagShiftBad = 42;
+constexpr uint32_t kMaxTileLen = 65536;   // keeps a slot's limbs below 2^49 before carries
+// Words per slot (a multiple of 16: 128 bytes, one cache line).
+inline constexpr int slot_words(int grad_dim) { return grad_dim ? (kSlotGrad + 2 * kFxLimbs * grad_dim + 15) / 16 * 16 : 16; }
 
 // Per-walk record of the gradient estimate (supplemental Sec. 2), in the walker's
-// precision: [A0, a (dim), b (dim), grad gamma(x0) (dim)].
+// precision: [A0, a (dim), b (dim), grad gamma(x0) (dim)]. One record per lane of the
+// persistent grid (a lane runs one walk at a time); it is read back when the walk ends.
 template <int DIM>
 struct GradRecord {
   static constexpr int kStride = 1 + 3 * DIM;

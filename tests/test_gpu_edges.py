@@ -101,3 +101,36 @@ def test_tile_tails(W, n):
                                                      tile_walks=64))
     torch.cuda.synchronize()
     assert np.array_equal(small.sum.cpu().numpy(), big.sum.cpu().numpy()[:n])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_sums_are_exact_sums_of_the_walks(W, precision):
+    """The per-point sums (Sec. 3.1, eqs. 17-18) are exact: each walk's estimate is added
+    as a fixed-point number with integer atomics, so a solve of N walks returns the exact
+    sum of the N estimates rounded once (within one unit in the last place), whatever the
+    order in which the walks ended. The estimates are taken one by one from N solves of
+    one walk each (walk_offset j), whose sums are the estimates themselves."""
+    from fractions import Fraction
+    torch = torch_cuda()
+    h = W.Problem(screened_disk(1e-3))
+    pts = WL.sample_inside(np.random.default_rng(12), WL.geom_ball([0.0, 0.0], 1.0), 2, 40)
+    P = dev(pts)
+    n_w = 24
+    single = []
+    for j in range(n_w):
+        a = W.Accumulators(40)
+        W.solve([(h, P, a, 0)], W.options(precision=precision, walks=1, seed=3, walk_offset=j))
+        single.append(a)
+    full = W.Accumulators(40)
+    W.solve([(h, P, full, 0)], W.options(precision=precision, walks=n_w, seed=3, block_size=64, tile_walks=64))
+    torch.cuda.synchronize()
+    v = np.stack([a.sum.cpu().numpy() for a in single])       # [walk][point]
+    q = np.stack([a.sum_sq.cpu().numpy() for a in single])
+    assert np.array_equal(q, v * v)                           # one walk: v^2 exactly
+    got, got_sq = full.sum.cpu().numpy(), full.sum_sq.cpu().numpy()
+    for i in range(40):
+        exact = float(sum(Fraction(float(x)) for x in v[:, i]))
+        exact_sq = float(sum(Fraction(float(x)) * Fraction(float(x)) for x in v[:, i]))
+        assert abs(got[i] - exact) <= np.spacing(abs(exact)), (i, got[i], exact)
+        assert abs(got_sq[i] - exact_sq) <= np.spacing(abs(exact_sq)), (i, got_sq[i], exact_sq)
+    assert np.array_equal(full.n_steps.cpu().numpy(), sum(a.n_steps.cpu().numpy() for a in single))

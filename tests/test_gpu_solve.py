@@ -172,11 +172,18 @@ def test_deterministic_and_offsets_compose(W):
     torch.cuda.synchronize()
     np.testing.assert_allclose(acc.sum.cpu().numpy(), a["sum"], rtol=1e-12, atol=1e-12)
     assert np.array_equal(acc.n_steps.cpu().numpy(), a["steps"])
-    # chunked launches (tiny workspace) give the same per-walk values
+    # chunked launches (a workspace of one 128-byte slot per point: 64 walks per launch)
+    # give the same per-walk values; each launch's exact sums are rounded once
     acc2 = W.Accumulators(P.shape[0])
-    W.solve([(h, P, acc2, 0)], W.options(precision="fp32", walks=256, seed=7, workspace_bytes=16 * 60 * P.shape[0]))
+    small = dict(precision="fp32", walks=256, seed=7, workspace_bytes=128 * P.shape[0], tile_walks=64)
+    W.solve([(h, P, acc2, 0)], W.options(**small))
     torch.cuda.synchronize()
     np.testing.assert_allclose(acc2.sum.cpu().numpy(), a["sum"], rtol=1e-12, atol=1e-12)
+    assert np.array_equal(acc2.n_steps.cpu().numpy(), a["steps"])
+    acc3 = W.Accumulators(P.shape[0])
+    plan = W.Plan([(h, P, acc3, 0)], W.options(**small))
+    assert plan.info()["launches"] == 4
+    plan.close()
 
 
 def test_plan_graph_replays_match_solve(W):
