@@ -1118,8 +1118,8 @@ wos_status prepare(const wos_batch_item* items, int n_items, const wos_options* 
     const uint64_t w0 = (uint64_t)c * s.chunk_walks;
     const uint64_t nw = std::min(s.chunk_walks, opt->walks_per_point - w0);
     build_items(items, n_items, opt, s, w0, nw, inside, gamma0, dit[c], &n_tiles[c], &n_slots[c]);
-    if (n_tiles[c] >= (1ull << 32) || n_slots[c] >= (1ull << 32))
-      return fail(WOS_ERR_INVALID_ARG, "job too large: a launch would hold 2^32 tiles or slots or more");
+    if (n_tiles[c] >= (1ull << 32) || n_slots[c] >= (1ull << 31))
+      return fail(WOS_ERR_INVALID_ARG, "job too large: a launch would hold 2^32 tiles or 2^31 slots or more");
   }
   return WOS_OK;
 }

@@ -112,55 +112,155 @@ __device__ __forceinline__ void add_estimate(T& A, T& Ac, T term, int compensate
   }
 }
 
-// Integer add into an accumulation slot. A slot is written only by the wavefront that runs
-// its tile (and read by a later kernel), so the atomic needs no scope beyond the work-group:
-// it is performed in the L2 of the wave's own XCD.
-__device__ __forceinline__ void slot_add(uint64_t* w, uint64_t v) {
-  __hip_atomic_fetch_add((unsigned long long*)w, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-// Adds v (|v| < 2^47, finite) to the fixed-point limbs L[0..5] (limb k has weight
-// 2^(32k - 96)): |v| 2^96 is cut into 32-bit chunks from the top with exact floating
-// operations (scaling by powers of two, floor and a fused multiply-add remainder), and a
-// negative v adds the negated chunks. Bits below 2^-96 are dropped (truncation).
-__device__ __forceinline__ void fx_add(uint64_t* L, double v) {
-  double a = fabs(v) * 0x1p96;
-  const bool neg = v < 0;
-#pragma unroll
-  for (int k = kFxLimbs - 1; k >= 0; --k) {
-    const double w = __builtin_ldexp(1.0, 32 * k);
-    const double c = floor(a * __builtin_ldexp(1.0, -32 * k));
-    a = fma(-c, w, a);
-    if (c != 0.0) {
-      const uint64_t u = (uint64_t)(uint32_t)c;
-      slot_add(&L[k], neg ? (uint64_t)0 - u : u);
-    }
+// Integer add into an accumulation slot in global memory. A slot is written only by the
+// wavefront that runs its tile (and read by a later kernel), so the atomic needs no scope
+// beyond the work-group: it is performed in the L2 of the wave's own XCD.
+struct GlobalAdd {
+  __device__ __forceinline__ static void add(uint64_t* w, uint64_t v) {
+    __hip_atomic_fetch_add((unsigned long long*)w, (unsigned long long)v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
   }
+};
+
+// The same into the wave's LDS copy of a slot (see SlotCache).
+struct LdsAdd {
+  __device__ __forceinline__ static void add(uint64_t* w, uint64_t v) {
+    __hip_atomic_fetch_add((unsigned long long*)w, (unsigned long long)v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WAVEFRONT);
+  }
+};
+
+// Adds u to word w of a slot: of the wave's LDS copy when `cached`, else of the global slot.
+__device__ __forceinline__ void slot_word_add(uint64_t* lds, uint64_t* glob, bool cached, int w, uint64_t u) {
+  if (cached) LdsAdd::add(lds + w, u);
+  else GlobalAdd::add(glob + w, u);
 }
 
-// What a finished walk adds to its slot: the estimate v and v^2, its distance queries,
-// radius proposals and flags, and with gradient records the dim components of its
-// gradient estimate and their squares.
-__device__ __forceinline__ void emit_walk(uint64_t* slot, double v, uint32_t steps_flags, uint32_t trials,
-                                          uint32_t step_mask, uint32_t flag_capped, uint32_t flag_rr,
-                                          const double* g, int gdim) {
+// Adds v (finite; below 2^94 in magnitude, the square of an estimate below 2^47) to the
+// fixed-point limbs at word `base` of a slot (limb k has weight 2^(32k - 96)).
+// v = m 2^(E - 1075) with its 53-bit integer mantissa m, so v 2^96 = m 2^sh, sh = E - 979;
+// bits below 2^-96 are dropped (truncation towards zero). m 2^(sh mod 32) spans at most
+// 85 bits, i.e. three 32-bit chunks starting at limb sh / 32; a negative v adds the
+// negated chunks.
+__device__ __forceinline__ void fx_add(uint64_t* lds, uint64_t* glob, bool cached, int base, double v) {
+  const uint64_t bits = (uint64_t)__double_as_longlong(v);
+  const int e = (int)((bits >> 52) & 0x7FFu);
+  uint64_t m = (bits & 0xFFFFFFFFFFFFFull) | (e ? (1ull << 52) : 0ull);
+  int sh = (e ? e : 1) - 979;
+  if (sh < 0) {
+    m = sh > -64 ? m >> -sh : 0ull;
+    sh = 0;
+  }
+  if (m == 0ull) return;
+  const int k = base + (sh >> 5), b = sh & 31;
+  const uint64_t lo = m << b;
+  const uint64_t hi = b ? m >> (64 - b) : 0ull;
+  const bool neg = (int64_t)bits < 0;
+  const uint64_t c0 = lo & 0xFFFFFFFFull, c1 = lo >> 32, c2 = hi;
+  if (c0) slot_word_add(lds, glob, cached, k, neg ? 0ull - c0 : c0);
+  if (c1) slot_word_add(lds, glob, cached, k + 1, neg ? 0ull - c1 : c1);
+  if (c2 && k + 2 < base + kFxLimbs) slot_word_add(lds, glob, cached, k + 2, neg ? 0ull - c2 : c2);
+}
+
+// What a finished walk adds to its slot: the estimate v and v^2, its distance queries and
+// flags, and with gradient records (GD = dim) the components of its gradient estimate and
+// their squares.
+template <int GD>
+__device__ __forceinline__ void emit_walk(uint64_t* lds, uint64_t* glob, bool cached, double v, uint32_t steps_flags,
+                                          uint32_t step_mask, uint32_t flag_capped, uint32_t flag_rr, const double* g) {
   uint64_t flags = (steps_flags & flag_capped) ? 1ull : 0ull;
   if (steps_flags & flag_rr) flags += 1ull << kFlagShiftKilled;
   bool bad = !(fabs(v) < kFxMaxValue);
-  for (int c = 0; c < gdim; ++c) bad = bad || !(fabs(g[c]) < kFxMaxValue);
+#pragma unroll
+  for (int c = 0; c < GD; ++c) bad = bad || !(fabs(g[c]) < kFxMaxValue);
   if (bad) {
     flags += 1ull << kFlagShiftBad;
   } else {
-    fx_add(slot + kSlotSum, v);
-    fx_add(slot + kSlotSumSq, v * v);
-    for (int c = 0; c < gdim; ++c) {
-      fx_add(slot + kSlotGrad + 2 * kFxLimbs * c, g[c]);
-      fx_add(slot + kSlotGrad + 2 * kFxLimbs * c + kFxLimbs, g[c] * g[c]);
+    fx_add(lds, glob, cached, kSlotSum, v);
+    fx_add(lds, glob, cached, kSlotSumSq, v * v);
+#pragma unroll
+    for (int c = 0; c < GD; ++c) {
+      fx_add(lds, glob, cached, kSlotGrad + 2 * kFxLimbs * c, g[c]);
+      fx_add(lds, glob, cached, kSlotGrad + 2 * kFxLimbs * c + kFxLimbs, g[c] * g[c]);
     }
   }
-  slot_add(slot + kSlotSteps, steps_flags & step_mask);
-  if (trials) slot_add(slot + kSlotTrials, trials);
-  if (flags) slot_add(slot + kSlotFlags, flags);
+  slot_word_add(lds, glob, cached, kSlotSteps, steps_flags & step_mask);
+  if (flags) slot_word_add(lds, glob, cached, kSlotFlags, flags);
+}
+
+// A wavefront's cache of accumulation slots in LDS: the slots of the last ENTRIES
+// single-point tiles it started. A walk's slot reference is either kCachedSlot | e (entry
+// e of the cache) or a global slot index. Walks whose slot is cached add into LDS (cheap
+// atomics); the others (tiles of several points) add into global memory. When a new tile
+// takes over an entry, the entry is added into its global slot and cleared, and the
+// lanes still running walks of the old tile switch their reference to the global slot;
+// the rest is added at the end of the kernel. All sums are integers, so the split
+// between the two paths does not change any result. Called with every lane active.
+constexpr uint32_t kCachedSlot = 0x80000000u;
+
+template <int WORDS, int ENTRIES>
+struct SlotCache {
+  uint64_t* lds;             // this wave's ENTRIES x WORDS words
+  uint32_t tag[ENTRIES];     // global slot held by each entry (~0u: none); wave-uniform
+  uint32_t next;             // entry the next single-point tile takes; wave-uniform
+
+  __device__ __forceinline__ void init(uint64_t* base, uint32_t lane) {
+    lds = base;
+#pragma unroll
+    for (int e = 0; e < ENTRIES; ++e) tag[e] = ~0u;
+    next = 0;
+    for (int w = (int)lane; w < ENTRIES * WORDS; w += 64) lds[w] = 0;
+  }
+  // Adds entry e (wave-uniform) into its global slot t and clears it.
+  __device__ __forceinline__ void flush(int e, uint32_t t, uint64_t* slots, int slot_words, uint32_t lane) {
+    if (t == ~0u) return;
+    for (int w = (int)lane; w < slot_words; w += 64) {
+      const uint64_t v = lds[e * WORDS + w];
+      if (v) GlobalAdd::add(slots + (size_t)t * slot_words + w, v);
+      lds[e * WORDS + w] = 0;
+    }
+  }
+  // Entry for a new single-point tile with global slot `slot`; returns the reference its
+  // walks carry. `ref` is the calling lane's current reference, rewritten if it pointed
+  // into the entry taken over.
+  __device__ __forceinline__ uint32_t take(uint32_t slot, uint64_t* slots, int slot_words, uint32_t lane,
+                                           uint32_t& ref) {
+    const int e = (int)next;
+    uint32_t t = ~0u;
+#pragma unroll
+    for (int c = 0; c < ENTRIES; ++c)
+      if (c == e) t = tag[c];
+    flush(e, t, slots, slot_words, lane);
+    if (ref == (kCachedSlot | (uint32_t)e)) ref = t;
+#pragma unroll
+    for (int c = 0; c < ENTRIES; ++c)
+      if (c == e) tag[c] = slot;
+    next = next + 1 == (uint32_t)ENTRIES ? 0u : next + 1;
+    return kCachedSlot | (uint32_t)e;
+  }
+  __device__ __forceinline__ void flush_all(uint64_t* slots, int slot_words, uint32_t lane) {
+#pragma unroll
+    for (int e = 0; e < ENTRIES; ++e) flush(e, tag[e], slots, slot_words, lane);
+  }
+  // Adds a finished walk into the slot it references.
+  template <int GD>
+  __device__ __forceinline__ void emit(uint32_t ref, uint64_t* slots, int slot_words, double v, uint32_t steps_flags,
+                                       uint32_t step_mask, uint32_t flag_capped, uint32_t flag_rr, const double* g) {
+    const bool cached = (ref & kCachedSlot) != 0u;
+    emit_walk<GD>(lds + (ref & (uint32_t)(ENTRIES - 1)) * WORDS, slots + (size_t)(cached ? 0u : ref) * slot_words,
+                  cached, v, steps_flags, step_mask, flag_capped, flag_rr, g);
+  }
+};
+
+// Radius proposals (next flight: inner points) drawn by the wave's lanes for the current
+// item, added to the item's counter [3] when the wave leaves the item (all lanes idle) and
+// at the end; with the event-counting build also to the wave's event tally.
+__device__ __forceinline__ void flush_trials(uint64_t* counters, uint32_t& ntrials, uint32_t* ev_trials) {
+  uint64_t t = ntrials;
+  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+  if (counters && __lane_id() == 0 && t) atomicAdd((unsigned long long*)&counters[3], (unsigned long long)t);
+  if (ev_trials) *ev_trials += ntrials;
+  ntrials = 0;
 }
 
 // Buffers written by the walker are separate __restrict__ parameters, so loads of the
@@ -181,6 +281,12 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
     __shared__ T s_dist[kStack * 256];
     lds_stack = LdsStack<T>{s_node + threadIdx.x, s_dist + threadIdx.x, (int)blockDim.x, kStack};
   }
+  // LDS cache of accumulation slots: gradient slots are larger, so fewer entries
+  constexpr int kCacheWords = EXTRA ? 64 : 16;
+  constexpr int kCacheEntries = EXTRA ? 2 : 4;
+  __shared__ uint64_t s_slot_cache[4 * kCacheEntries * kCacheWords];
+  SlotCache<kCacheWords, kCacheEntries> cache;
+  cache.init(s_slot_cache + uniform_int((int)(threadIdx.x >> 6)) * (kCacheEntries * kCacheWords), lane);
   Tally tally = {0, 0, 0, 0};
   uint32_t ev[kEvents];
   if constexpr (COUNT) {
@@ -199,7 +305,8 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
   bool queue_done = false;
   const WOS_GLOBAL DevProblem<T>* Pp = nullptr;
   // ---- lane state: phase 0 = idle, 1 = new walk whose gamma(x0) and its gradient are still
-  // to be evaluated (gradient records only), 2 = walking; slot: accumulation slot of the walk
+  // to be evaluated (gradient records only), 2 = walking (3: next flight inside a ball),
+  // 4 = ended, its result still to be added; slot: accumulation slot of the walk
   int phase = 0;
   uint32_t slot = 0;
   T* const grad_rec = EXTRA && a.grad ? a.grad + ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * GradRecord<DIM>::kStride
@@ -234,6 +341,26 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
   const bool window = a.rr || (EXTRA && a.ww_hi > (T)0);
 
   for (;;) {
+    // ---------------------------------------------------------------- finished walks
+    // A walk that ended in the last iteration adds its estimate A + Ac, its square, its
+    // distance queries and flags (in nsteps) to its slot here, where little else is live.
+    if (phase == 4) {
+      const double v = (double)A + (double)Ac;
+      if (EXTRA && a.grad) {
+        // per-walk gradient estimate (supplemental Sec. 2):
+        // A0 a + (A - A0) b - A grad gamma(x0), from the lane's record
+        double g[DIM];
+        const T* gr = grad_rec;
+        const double a0 = (double)gr[0];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c)
+          g[c] = a0 * (double)gr[1 + c] + (v - a0) * (double)gr[1 + DIM + c] - v * (double)gr[1 + 2 * DIM + c];
+        cache.template emit<DIM>(slot, slots, a.slot_words, v, nsteps, kStepMask, kFlagCapped, kFlagRR, g);
+      } else {
+        cache.template emit<0>(slot, slots, a.slot_words, v, nsteps, kStepMask, kFlagCapped, kFlagRR, nullptr);
+      }
+      phase = 0;
+    }
     // ---------------------------------------------------------------- refill idle lanes
     uint64_t idle = __ballot(phase == 0);
     while (idle != 0) {
@@ -254,6 +381,7 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
         }
         if (search_item != cur_item) {
           if (idle != ~0ull) break;  // drain the wave before switching problems
+          if (cur_item >= 0) flush_trials(items[cur_item].counters, ntrials, COUNT ? &ev[EV_TRIALS] : nullptr);
           cur_item = uniform_int(search_item);
           Pp = (const WOS_GLOBAL DevProblem<T>*)uniform_ptr(items[cur_item].problem);
         }
@@ -279,6 +407,7 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
         }
         tl_slot0 = uniform_int((int)(it.slot_base + (it.tiles_per_point > 0u ? tl : (uint64_t)tl_p0)));
         tl_walks = uniform_int((int)walks);
+        if (tl_single) tl_slot0 = uniform_int((int)cache.take(tl_slot0, slots, a.slot_words, lane, slot));
         res_next = 0;
         pend_tile = -1;
       }
@@ -303,7 +432,6 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
           slot = tl_slot0 + dq;
         }
         nsteps = 0;
-        ntrials = 0;
         if (gptr(it.inside)[p]) {
 #pragma unroll
           for (int i = 0; i < DIM; ++i) x[i] = (T)gptr(it.points)[(size_t)p * DIM + i];
@@ -450,10 +578,8 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
           phase = 3;
         }
         if (done) {
-          emit_walk(slots + (size_t)slot * a.slot_words, (double)A + (double)Ac, (nsteps & kStepMask) | flag, ntrials,
-                    kStepMask, kFlagCapped, kFlagRR, nullptr, 0);
-          if constexpr (COUNT) ev[EV_TRIALS] += ntrials;
-          phase = 0;
+          nsteps = (nsteps & kStepMask) | flag;
+          phase = 4;   // added to its slot at the top of the next iteration
         }
       } else {
         bool done = false, terminal = false, sampled = false;
@@ -655,27 +781,14 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
             rng.init(seed, rng.walk, rng.point, (rng.problem & 0xFFFFu) | ((split_state >> 8) << 16));
             pending = false;
           } else {
-            const double v = (double)A + (double)Ac;
-            double g[DIM];
-            int gdim = 0;
-            if (EXTRA && a.grad) {
-              // per-walk gradient estimate (supplemental Sec. 2):
-              // A0 a + (A - A0) b - A grad gamma(x0), from the lane's record
-              const T* gr = grad_rec;
-              const double a0 = (double)gr[0];
-#pragma unroll
-              for (int c = 0; c < DIM; ++c)
-                g[c] = a0 * (double)gr[1 + c] + (v - a0) * (double)gr[1 + DIM + c] - v * (double)gr[1 + 2 * DIM + c];
-              gdim = DIM;
-            }
-            emit_walk(slots + (size_t)slot * a.slot_words, v, nsteps, ntrials, kStepMask, kFlagCapped, kFlagRR, g, gdim);
-            if constexpr (COUNT) ev[EV_TRIALS] += ntrials;
-            phase = 0;
+            phase = 4;   // added to its slot at the top of the next iteration
           }
         }
       }
     }
   }
+  if (cur_item >= 0) flush_trials(items[cur_item].counters, ntrials, COUNT ? &ev[EV_TRIALS] : nullptr);
+  cache.flush_all(slots, a.slot_words, lane);
   if constexpr (COUNT) {
     ev[EV_NODES] = tally.nodes;
     ev[EV_PRIMS] = tally.prims;
@@ -745,7 +858,7 @@ __device__ __forceinline__ void fx_accumulate(int64_t* L, const uint64_t* words)
 template <int GD>
 __global__ void reduce_kernel(DevItem it, const uint64_t* __restrict__ slots, int slot_words) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint64_t capped = 0, killed = 0, ntr = 0;
+  uint64_t capped = 0, killed = 0;
   if (p < it.n_points) {
     const uint32_t spp = it.tiles_per_point > 0u ? it.tiles_per_point : 1u;
     if (!it.inside[p]) {
@@ -770,7 +883,6 @@ __global__ void reduce_kernel(DevItem it, const uint64_t* __restrict__ slots, in
         fx_accumulate(S, w + kSlotSum);
         fx_accumulate(Q, w + kSlotSumSq);
         nst += w[kSlotSteps];
-        ntr += w[kSlotTrials];
         const uint64_t f = w[kSlotFlags];
         capped += f & ((1ull << kFlagShiftKilled) - 1);
         killed += (f >> kFlagShiftKilled) & ((1ull << (kFlagShiftBad - kFlagShiftKilled)) - 1);
@@ -797,12 +909,10 @@ __global__ void reduce_kernel(DevItem it, const uint64_t* __restrict__ slots, in
     for (int off = 32; off > 0; off >>= 1) {
       capped += __shfl_xor(capped, off);
       killed += __shfl_xor(killed, off);
-      ntr += __shfl_xor(ntr, off);
     }
     if (__lane_id() == 0) {
       if (capped) atomicAdd((unsigned long long*)&it.counters[1], (unsigned long long)capped);
       if (killed) atomicAdd((unsigned long long*)&it.counters[2], (unsigned long long)killed);
-      if (ntr) atomicAdd((unsigned long long*)&it.counters[3], (unsigned long long)ntr);
     }
   }
 }

@@ -186,8 +186,7 @@ constexpr double kFxMaxValue = 140737488355328.0;   // 2^47
 constexpr int kSlotSum = 0;       // [kFxLimbs] limbs of the sum of estimates
 constexpr int kSlotSumSq = 6;     // [kFxLimbs] limbs of the sum of their squares
 constexpr int kSlotSteps = 12;    // distance queries
-constexpr int kSlotTrials = 13;   // radius proposals (next flight: inner points)
-constexpr int kSlotFlags = 14;    // walks cut at max_steps | roulette kills << 21 | bad << 42
+constexpr int kSlotFlags = 13;    // walks cut at max_steps | roulette kills << 21 | bad << 42
 constexpr int kSlotGrad = 16;     // per gradient component c: [kFxLimbs] sum, [kFxLimbs] sum of squares
 constexpr int kFlagShiftKilled = 21;
 constexpr int kFlagShiftBad = 42;
