@@ -274,6 +274,20 @@ def sigma_bar_default(prob, samples):
     return max(mx, 0.0) - min(mn, 0.0)
 
 
+def solve_batches(prob, pts, n_batches, walks_per_batch, sigma_bar, seed=0, walk_offset=0, **kw):
+    """Runs n_batches consecutive blocks of walks_per_batch walks per point (walk offsets
+    walk_offset + b * walks_per_batch) and returns their per-point means as [n_batches][n]
+    (batch means, Sec. 3.1: each is itself an unbiased estimate), with the distance queries
+    summed over all batches."""
+    out, steps = [], 0
+    for b in range(n_batches):
+        r = solve(prob, pts, walks_per_batch, sigma_bar, seed=seed, walk_offset=walk_offset + b * walks_per_batch,
+                  **kw)
+        out.append(r["mean"])
+        steps = steps + r["steps"]
+    return {"batch_means": np.array(out), "steps": steps}
+
+
 def solve(prob, pts, n_walks, sigma_bar, seed=0, walk_offset=0, problem_index=0, variant=0,
           russian_roulette=False, ww_lo=0.5, ww_hi=0.0, max_steps=10**7, threads=0, gradient=False,
           bvh=False):

@@ -50,3 +50,20 @@ def gpu_solve_grad(W, prob_handle, pts, walks, precision="fp32", seed=0, **kw):
     torch.cuda.synchronize()
     return {"mean": mean.cpu().numpy(), "se": se.cpu().numpy(), "grad_mean": gmean.cpu().numpy(),
             "grad_se": gse.cpu().numpy(), "steps": acc.n_steps.cpu().numpy(), "sum": acc.sum.cpu().numpy()}
+
+
+def gpu_batches(W, prob_handle, pts, batches, walks_per_batch, precision="fp32", seed=0, **kw):
+    """Batch means [batches][n]: `batches` solves of walks_per_batch walks per point with
+    consecutive walk offsets (Sec. 3.1: each is an independent unbiased estimate)."""
+    torch = torch_cuda()
+    P = dev(pts)
+    out = []
+    for b in range(batches):
+        acc = W.Accumulators(P.shape[0])
+        W.solve([(prob_handle, P, acc, kw.get("problem_index", 0))],
+                W.options(precision=precision, walks=walks_per_batch, seed=seed, walk_offset=b * walks_per_batch,
+                          **{k: v for k, v in kw.items() if k != "problem_index"}))
+        mean, _ = W.finalize(acc)
+        out.append(mean)
+    torch.cuda.synchronize()
+    return np.stack([m.cpu().numpy() for m in out])

@@ -1,22 +1,33 @@
 """Parity at the workloads' full sizes, in the launch configuration the benchmark times:
-one autotuned plan over every query point of the workload, replayed as a captured graph,
-with the oracle computing a random sample of the points one by one (its own walks, the
-same count per point), compared per point within the statistical bound of
-tests/parity.py.
+one autotuned plan over every query point of the workload, replayed B times with
+consecutive walk offsets, so that each replay gives one batch mean per point (Sec. 3.1).
+The oracle's batch means at a seeded random sample of the points are stored in
+tests/golden/parity_*.npz (written by tests/golden/make_parity_refs.py, which calls only
+the oracle); both sides use the oracle's sigma_bar. The comparison is the batch-means rule
+of tests/parity.py, whose false-alarm rate and power tests/test_parity_rule.py measures.
 
-* star polygon, 256 edges: 124,319 points x 1024 walks, FP32 and FP64 (the benchmark pass);
-* perturbed icosphere, 20,480 triangles: 676,691 points on the z = 0 slice x 256 walks, FP32;
-* batch of 64 polygons (16-4096 edges): 2.65e6 points x 512 walks in one plan, FP32;
-* high-contrast square: 65,536 points x 1024 walks with Russian roulette, FP32, FP32
-  with compensated sums and FP64."""
+* star polygon, 256 edges: 124,319 points x 1024 walks, FP32 and FP64, 256 sampled points;
+* perturbed icosphere, 20,480 triangles: 676,691 slice points x 256 walks, FP32, 128 points;
+* batch of 64 polygons (16-4096 edges): 2.65e6 points x 512 walks in one plan, FP32, 4
+  points per problem;
+* high-contrast square: 65,536 points x 1024 walks with Russian roulette, FP32, FP32 with
+  compensated sums and FP64, 128 points;
+* power: the star polygon with f and g scaled by 1 + delta (so u scales by 1 + delta, eq. 1
+  being linear in f and g), delta set for an average shift of three times the bias the
+  rule detects with probability 1/2, must be rejected."""
+import copy
+import os
+
 import numpy as np
 import pytest
 
 from paper_2201_13240_amd import workloads as WL
+from tests import parity as PR
 from tests.gpu_common import dev, torch_cuda
-from tests.parity import assert_parity
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 @pytest.fixture(scope="module")
@@ -31,77 +42,104 @@ def tol(precision):
     return 1e-12 if precision == "fp64" else 2e-6
 
 
-def plan_solve(W, items, walks, precision, seed, **kw):
-    """items: [(problem handle, points)]; one plan over all of them, one replay."""
+def refs(name):
+    return np.load(os.path.join(GOLDEN, f"parity_{name}.npz"), allow_pickle=False)
+
+
+def plan_batches(W, problems, points, sample, walks, precision, batches, seed=7, **kw):
+    """One plan over every point of every problem (item k = problem k), replayed `batches`
+    times with walk offsets b * walks; returns the batch means [batches][sample points] at
+    sample = [(problem, point index)], and the plan's counters summed over items."""
     torch = torch_cuda()
     entries = []
-    for i, (h, pts) in enumerate(items):
+    for k, (h, pts) in enumerate(zip(problems, points)):
         P = dev(pts)
-        entries.append((h, P, W.Accumulators(P.shape[0]), i))
+        entries.append((h, P, W.Accumulators(P.shape[0]), k))
     plan = W.Plan(entries, W.options(precision=precision, walks=walks, seed=0, **kw))
-    plan.launch(seed=seed)
-    out = []
-    for _, _, acc, _ in entries:
-        mean, se = W.finalize(acc)
-        torch.cuda.synchronize()
-        out.append((mean.cpu().numpy(), se.cpu().numpy(), acc.counters.cpu().numpy()))
+    info = plan.info()
+    by_item = {}
+    for j, (k, i) in enumerate(sample):
+        by_item.setdefault(k, ([], []))
+        by_item[k][0].append(j)
+        by_item[k][1].append(i)
+    sel = {k: torch.as_tensor(np.array(v[1]), device="cuda") for k, v in by_item.items()}
+    out = np.empty((batches, len(sample)))
+    counters = np.zeros(4, np.int64)
+    for b in range(batches):
+        for _, _, acc, _ in entries:
+            for t in (acc.sum, acc.sum_sq, acc.n_walks, acc.n_steps, acc.counters):
+                t.zero_()
+        plan.launch(seed=seed, walk_offset_add=b * walks)
+        for k, (cols, _) in by_item.items():
+            acc = entries[k][2]
+            m = (acc.sum[sel[k]] / acc.n_walks[sel[k]].double()).cpu().numpy()
+            out[b, cols] = m
+        for _, _, acc, _ in entries:
+            counters += acc.counters.cpu().numpy()
+    torch.cuda.synchronize()
     plan.close()
-    return out
+    return out, counters, info
 
 
-def test_star_polygon_full(W, oracle):
-    c = WL.config2()
+def single(W, name, precision, batches, scale=None, **kw):
+    d = refs(name)
+    c = {"star256": WL.config2, "ico20480": WL.config3, "square_rr": WL.config5}[name]()
     prob, pts = c["problems"][0], c["points"][0]
-    assert pts.shape[0] == 124319
-    h = W.Problem(prob)
-    idx = np.random.default_rng(20).choice(pts.shape[0], 64, replace=False)
-    o = oracle.solve(prob, pts[idx], 1024, h.sigma_bar, seed=21)
-    for precision in ("fp32", "fp64"):
-        (mean, se, cnt), = plan_solve(W, [(h, pts)], 1024, precision, seed=22)
-        assert np.all(np.isfinite(mean)) and cnt[0] == 0 and cnt[1] == 0
-        assert_parity(mean[idx], se[idx], o["mean"], o["se"], f"star polygon full {precision}", tol(precision))
+    if scale is not None:
+        prob = copy.deepcopy(prob)
+        for f in ("source", "boundary"):
+            prob[f]["c0"] *= scale
+            prob[f]["c1"] *= scale
+    h = W.Problem(prob, sigma_bar=float(d["sigma_bar"][0]))
+    sample = [(0, int(i)) for i in d["idx"]]
+    g, cnt, info = plan_batches(W, [h], [pts], sample, c["walks"], precision, batches, **kw)
+    assert cnt[0] == 0 and cnt[1] == 0, cnt
+    assert info["launches"] == 1
+    return g, d
 
 
-def test_icosphere_slice_full(W, oracle):
-    c = WL.config3()
-    prob, pts = c["problems"][0], c["points"][0]
-    assert pts.shape[0] == 676691
-    h = W.Problem(prob)
-    idx = np.random.default_rng(30).choice(pts.shape[0], 16, replace=False)
-    o = oracle.solve(prob, pts[idx], 256, h.sigma_bar, seed=31)
-    (mean, se, cnt), = plan_solve(W, [(h, pts)], 256, "fp32", seed=32)
-    assert np.all(np.isfinite(mean)) and cnt[0] == 0 and cnt[1] == 0
-    assert_parity(mean[idx], se[idx], o["mean"], o["se"], "icosphere full fp32", tol("fp32"))
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_star_polygon_full(W, precision):
+    g, d = single(W, "star256", precision, 32)
+    assert g.shape[1] == 256
+    PR.assert_parity_batches(g, d["run_a"], f"star polygon full {precision}", tol(precision))
 
 
-def test_batch_of_64_polygons_full(W, oracle):
+def test_icosphere_slice_full(W):
+    g, d = single(W, "ico20480", "fp32", 16)
+    assert g.shape[1] == 128
+    PR.assert_parity_batches(g, d["run_a"], "icosphere full fp32", tol("fp32"))
+
+
+def test_batch_of_64_polygons_full(W):
+    d = refs("batch64")
     c = WL.config4()
     assert len(c["problems"]) == 64
-    handles = [W.Problem(p) for p in c["problems"]]
-    res = plan_solve(W, list(zip(handles, c["points"])), 512, "fp32", seed=42)
-    rng = np.random.default_rng(40)
-    gm, gs, om, os_ = [], [], [], []
-    for i, (p, pts, h, (mean, se, cnt)) in enumerate(zip(c["problems"], c["points"], handles, res)):
-        assert np.all(np.isfinite(mean)) and cnt[0] == 0 and cnt[1] == 0
-        idx = rng.choice(pts.shape[0], 2, replace=False)
-        o = oracle.solve(p, pts[idx], 512, h.sigma_bar, seed=41, problem_index=i)
-        gm.append(mean[idx])
-        gs.append(se[idx])
-        om.append(o["mean"])
-        os_.append(o["se"])
-    assert_parity(np.concatenate(gm), np.concatenate(gs), np.concatenate(om), np.concatenate(os_),
-                  "64-polygon batch full fp32", tol("fp32"))
+    handles = [W.Problem(p, sigma_bar=float(sb)) for p, sb in zip(c["problems"], d["sigma_bar"])]
+    sample = [(int(k), int(i)) for k, i in zip(d["problem"], d["idx"])]
+    g, cnt, info = plan_batches(W, handles, c["points"], sample, 512, "fp32", 16)
+    assert cnt[0] == 0 and cnt[1] == 0, cnt
+    assert info["launches"] == 1, info
+    PR.assert_parity_batches(g, d["run_a"], "64-polygon batch full fp32", tol("fp32"))
 
 
-def test_high_contrast_square_full(W, oracle):
-    c = WL.config5()
-    prob, pts = c["problems"][0], c["points"][0]
-    assert pts.shape[0] == 65536
-    h = W.Problem(prob)
-    idx = np.random.default_rng(50).choice(pts.shape[0], 32, replace=False)
-    o = oracle.solve(prob, pts[idx], 1024, h.sigma_bar, seed=51, russian_roulette=True)
-    for precision in ("fp32", "fp32c", "fp64"):
-        (mean, se, cnt), = plan_solve(W, [(h, pts)], 1024, precision, seed=52, russian_roulette=True)
-        assert np.all(np.isfinite(mean)) and cnt[0] == 0 and cnt[1] == 0
-        assert_parity(mean[idx], se[idx], o["mean"], o["se"], f"high-contrast square full {precision}",
-                      tol(precision))
+@pytest.mark.parametrize("precision", ["fp32", "fp32c", "fp64"])
+def test_high_contrast_square_full(W, precision):
+    g, d = single(W, "square_rr", precision, 16, russian_roulette=True)
+    assert g.shape[1] == 128
+    PR.assert_parity_batches(g, d["run_a"], f"high-contrast square full {precision}", tol(precision))
+
+
+def test_power_scaled_source_and_boundary_is_rejected(W):
+    """f and g scaled by 1 + delta: u scales by 1 + delta. delta puts the average shift at
+    three times the detectable bias of 256 points, measured in the oracle's standard
+    errors (the GPU's are 4x smaller: 32 x 1024 walks against 32 x 64)."""
+    d = refs("star256")
+    m, s, _ = PR.batch_mean_se(d["run_a"])
+    delta = 3 * PR.detectable_bias(256) * float(np.mean(s)) / float(np.mean(np.abs(m)))
+    assert delta < 0.05
+    g, _ = single(W, "star256", "fp32", 32, scale=1 + delta)
+    ok, st = PR.accepts(PR.batch_scores(g, d["run_a"], tol("fp32")))
+    print(f"power: delta = {delta:.4f}, mean z = {st['mean']:.3f} (bound {st['thresholds']['mean']:.3f})")
+    assert not ok, f"scale 1 + {delta:.4f} accepted: {st}"
+    # and the unscaled run of the same shape is accepted (test_star_polygon_full)
