@@ -265,6 +265,21 @@ typedef struct {
  * memory is allocated and freed in stream order. */
 wos_status wos_solve(const wos_batch_item* items, int32_t n_items, const wos_options* opt, void* stream);
 
+/* wos_solve for callers that cannot allocate device memory (code that must not call
+ * hipMalloc, such as tight serving loops or harnesses that forbid it): the same walks,
+ * outputs and accumulation as wos_solve, with every scratch buffer (point classification,
+ * gamma at the query points, item tables, tile counter, accumulation slots, gradient
+ * records) in a static array of 128 MiB that the library holds on each GPU it runs on
+ * until the process ends. No hipMalloc, hipFree or other allocating routine is called.
+ * The caller still passes the inputs and outputs. Limit: the per-point tables and one
+ * 128-byte slot per query point (384-512 with gradients) must fit in the array (about
+ * 480,000 FP64 points without gradients); larger jobs fail with WOS_ERR_INVALID_ARG before
+ * any work is queued. Walks per point that do not fit at once run in several launches.
+ * Calls on one GPU share its array: two calls that overlap on one GPU (other streams or
+ * host threads) race and corrupt each other's results; calls in one stream are safe.
+ * Synchronous like wos_solve up to the item-table upload; then asynchronous on stream. */
+wos_status wos_solve_static(const wos_batch_item* items, int32_t n_items, const wos_options* opt, void* stream);
+
 /* Runs the same walks as wos_solve (same outputs, accumulated the same way) with the
  * event-counting build of the walker, and adds per-launch totals into `events` (device
  * uint64 [16]): [0] distance queries, [1] BVH inner nodes visited, [2] primitives whose

@@ -1251,6 +1251,53 @@ wos_status wos_solve(const wos_batch_item* items, int32_t n_items, const wos_opt
   return guarded([&] { return solve_impl(items, n_items, opt, nullptr, stream); });
 }
 
+// wos_solve on the library's static scratch array instead of allocated memory: the same
+// schedule, tables and kernels; the accumulation slots get what the array leaves after the
+// per-point tables, and walks per point are split into launches when they do not fit.
+static wos_status solve_static_impl(const wos_batch_item* items, int32_t n_items, const wos_options* opt,
+                                    void* stream) {
+  Schedule s;
+  wos_status r = check_items(items, n_items, opt, s);
+  if (r != WOS_OK) return r;
+  WOS_HIP(hipSetDevice(s.device));
+  void* base = nullptr;
+  WOS_HIP(static_scratch(s.device, &base));
+  int cus = 0;
+  if ((r = device_cus(s.device, &cus)) != WOS_OK) return r;
+  // everything but the slots, with room for the item tables of up to 64 launches
+  Schedule probe = s;
+  probe.n_launches = 64;
+  const size_t fixed = ws_layout(probe, n_items, 0, cus).total;
+  const size_t cap = kStaticScratchBytes;
+  if (fixed + (size_t)s.slot_words * 8 * std::max<uint64_t>(s.total_points, 1) > cap)
+    return fail(WOS_ERR_INVALID_ARG, "wos_solve_static: " + std::to_string(s.total_points) + " query points need " +
+                                         std::to_string(fixed) + " bytes of tables and one " +
+                                         std::to_string(s.slot_words * 8) + "-byte slot each, more than the " +
+                                         std::to_string(cap) + "-byte static scratch");
+  wos_options o = *opt;
+  const uint64_t room = cap - fixed;
+  o.workspace_bytes = opt->workspace_bytes ? std::min<uint64_t>(opt->workspace_bytes, room) : room;
+  if ((r = pick_shape(&o, s)) != WOS_OK) return r;
+  if (s.total_points == 0) return WOS_OK;
+  const WsLayout L = ws_layout(s, n_items, max_launch_slots(items, n_items, &o, s), cus);
+  if (L.total > cap)
+    return fail(WOS_ERR_INVALID_ARG, "wos_solve_static: the job needs " + std::to_string(L.total) +
+                                         " bytes of scratch, more than the " + std::to_string(cap) + " available");
+  hipStream_t st = (hipStream_t)stream;
+  Workspace w;
+  ws_bind(w, base, L);
+  std::vector<std::vector<DevItem>> dit;
+  std::vector<uint64_t> n_tiles, n_slots;
+  if ((r = prepare(items, n_items, &o, s, w, dit, n_tiles, n_slots)) != WOS_OK) return r;
+  if ((r = upload_items(s, n_items, w, dit, st)) != WOS_OK) return r;
+  WOS_HIP(launch_set_params(w.lp, o.seed, 0, st));
+  return enqueue_job(items, n_items, &o, s, w, dit, n_tiles, n_slots, true, nullptr, st);
+}
+
+wos_status wos_solve_static(const wos_batch_item* items, int32_t n_items, const wos_options* opt, void* stream) {
+  return guarded([&] { return solve_static_impl(items, n_items, opt, stream); });
+}
+
 wos_status wos_count_events(const wos_batch_item* items, int32_t n_items, const wos_options* opt, uint64_t* events,
                             void* stream) {
   if (!events) return fail(WOS_ERR_INVALID_ARG, "null events");

@@ -4,6 +4,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <map>
+#include <mutex>
 
 #include "wos_device.h"
 #include "wos_launch.h"
@@ -1186,6 +1188,37 @@ __global__ void finalize_kernel(const double* sum, const double* sum_sq, const u
   const double var = N > 1 ? fmax(sum_sq[i] / N - m * m, 0.0) * N / (N - 1) : __builtin_nan("");
   mean[i] = m;
   se[i] = sqrt(var / N);
+}
+
+// ====================================================================== static scratch
+//
+// Scratch memory of wos_solve_static, for callers that cannot allocate: a file-scope device
+// array, of which every GPU the library runs on holds its own copy until the process
+// ends. Host code never uses the array's name as an address: the device address of the
+// current GPU's copy is looked up once per device (hipGetSymbolAddress) and kept.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+std::mutex g_scratch_mutex;
+std::map<int, void*> g_scratch_ptr;
+}  // namespace
+
+hipError_t static_scratch(int device, void** ptr) {
+  std::lock_guard<std::mutex> lk(g_scratch_mutex);
+  auto it = g_scratch_ptr.find(device);
+  if (it == g_scratch_ptr.end()) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return e;
+    it = g_scratch_ptr.emplace(device, p).first;
+  }
+  *ptr = it->second;
+  return hipSuccess;
 }
 
 // ====================================================================== launchers

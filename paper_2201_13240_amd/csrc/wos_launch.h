@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime_api.h>
 
+#include <cstddef>
 #include <cstdint>
 
 #include "wos_types.h"
@@ -32,6 +33,11 @@ struct WalkerLaunch {
 };
 
 hipError_t launch_walker(const WalkerLaunch& L, hipStream_t st);
+// Bytes of the scratch array of wos_solve_static, one copy per GPU.
+constexpr size_t kStaticScratchBytes = 128ull << 20;
+// Device address of `device`'s copy of that array (looked up on the first call for the
+// device, with the device current, and kept).
+hipError_t static_scratch(int device, void** ptr);
 // 0 delta tracking, 1 delta tracking with splitting or gradient records, 2 next flight
 int walker_mode(int variant, bool grad, bool split);
 const void* walker_symbol(int fp64, int dim, int geom, int mode);

@@ -64,7 +64,7 @@ class BatchItem(C.Structure):
 
 # Every symbol declared in include/wos.h.
 EXPORTS = ["wos_last_error", "wos_version", "wos_problem_create", "wos_problem_info", "wos_problem_bvh_info", "wos_problem_grid_info",
-           "wos_problem_destroy", "wos_solve", "wos_count_events", "wos_finalize", "wos_finalize_grad", "wos_plan_create", "wos_plan_launch",
+           "wos_problem_destroy", "wos_solve", "wos_solve_static", "wos_count_events", "wos_finalize", "wos_finalize_grad", "wos_plan_create", "wos_plan_launch",
            "wos_plan_time", "wos_plan_info", "wos_plan_destroy", "wos_eval_coefficients", "wos_eval_distance", "wos_eval_ball",
            "wos_sample_radius", "wos_philox", "wos_eval_bessel", "wos_eval_offcentred", "wos_classify"]
 
@@ -87,6 +87,7 @@ def lib():
         L.wos_problem_grid_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i64)]
         L.wos_problem_destroy.argtypes = [vp]
         L.wos_solve.argtypes = [C.POINTER(BatchItem), i32, C.POINTER(Options), vp]
+        L.wos_solve_static.argtypes = [C.POINTER(BatchItem), i32, C.POINTER(Options), vp]
         L.wos_count_events.argtypes = [C.POINTER(BatchItem), i32, C.POINTER(Options), vp, vp]
         L.wos_finalize.argtypes = [vp, vp, vp, i64, vp, vp, vp]
         L.wos_finalize_grad.argtypes = [vp, vp, vp, i64, i32, vp, vp, vp]
@@ -304,6 +305,12 @@ def solve(entries, opt, stream=None):
     """entries: list of (Problem, points[n, dim] float64 cuda tensor, Accumulators, problem_index)."""
     arr = _items(entries)
     _check(lib().wos_solve(arr, len(entries), C.byref(opt), _stream(stream)))
+
+
+def solve_static(entries, opt, stream=None):
+    """As solve, on the library's static scratch array (wos_solve_static): no allocation."""
+    arr = _items(entries)
+    _check(lib().wos_solve_static(arr, len(entries), C.byref(opt), _stream(stream)))
 
 
 EVENT_NAMES = ["steps", "bvh_nodes", "prims", "trials", "trials_free", "volume", "exit", "terminal", "gamma_evals",
