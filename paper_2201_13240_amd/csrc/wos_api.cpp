@@ -825,6 +825,7 @@ namespace {
 
 struct Schedule {
   int fp64 = 0, compensated = 0, dim = 2, geom = 0, device = 0;
+  int fp32_draws = 0;         // FP64 walker drawing the FP32 walker's uniforms
   int variant = 0;            // 2 selects the next-flight walker
   int grad = 0;               // some item asks for gradient sums
   int mode = 0;               // walker instantiation (walker_mode)
@@ -841,7 +842,9 @@ struct Schedule {
 
 wos_status check_items(const wos_batch_item* items, int n_items, const wos_options* opt, Schedule& s) {
   if (!items || n_items <= 0 || !opt) return fail(WOS_ERR_INVALID_ARG, "null or empty batch");
-  if (opt->precision < 0 || opt->precision > 2) return fail(WOS_ERR_INVALID_ARG, "unknown precision");
+  if (opt->precision < 0 || opt->precision > 3) return fail(WOS_ERR_INVALID_ARG, "unknown precision");
+  if (opt->precision == WOS_FP64_FP32_DRAWS && opt->variant == 2)
+    return fail(WOS_ERR_INVALID_ARG, "FP32 draws in the FP64 walker apply to delta tracking (variant 0 or 1)");
   if (opt->variant < 0 || opt->variant > 2) return fail(WOS_ERR_INVALID_ARG, "unknown variant");
   if (opt->variant == 2 && opt->russian_roulette)
     return fail(WOS_ERR_INVALID_ARG, "the next-flight walk has its own roulette; russian_roulette must be 0");
@@ -862,7 +865,8 @@ wos_status check_items(const wos_batch_item* items, int n_items, const wos_optio
   s.dim = p0->dim;
   s.geom = p0->geom;
   s.device = p0->device;
-  s.fp64 = opt->precision == WOS_FP64;
+  s.fp64 = opt->precision == WOS_FP64 || opt->precision == WOS_FP64_FP32_DRAWS;
+  s.fp32_draws = opt->precision == WOS_FP64_FP32_DRAWS;
   s.variant = opt->variant;
   s.compensated = opt->precision == WOS_FP32_COMPENSATED;
   s.total_points = 0;
@@ -1156,6 +1160,7 @@ WalkerLaunch walker_launch(const wos_options* opt, const Schedule& s, const Work
   L.max_steps = opt->max_steps ? opt->max_steps : 1000000ull;
   L.variant = opt->variant;
   L.compensated = s.compensated;
+  L.fp32_draws = s.fp32_draws;
   L.rr = opt->russian_roulette;
   L.ww_lo = opt->ww_lo > 0 ? opt->ww_lo : 0.5;
   L.ww_hi = opt->ww_hi > 0 ? opt->ww_hi : 0.0;

@@ -171,6 +171,24 @@ struct Slots {
   static_assert(kBlocks <= kMaxRngBlocks && kNfBlocks <= kMaxRngBlocks, "slot layout exceeds the buffer");
 };
 
+// Draws of one delta-tracking iteration for the FP64 walker taking the FP32 walker's
+// uniforms (common random numbers): the FP32 slot layout's Philox blocks are drawn, and
+// the 24-bit uniform of FP32 slot S, ((w >> 8) + 1) 2^-24, is re-encoded into words 2S and
+// 2S + 1 so that the FP64 construction (53 bits, plus 2^-53) returns exactly that value.
+// Slots are rewritten from the last down, so no word is overwritten before it is read.
+template <int DIM>
+__device__ __forceinline__ void refill_fp32_draws(Rng& r) {
+  using S32 = Slots<float, DIM>;
+  r.refill<S32::kBlocks>();
+#pragma unroll
+  for (int s = S32::kCount - 1; s >= 0; --s) {
+    const uint64_t x = ((((uint64_t)(r.w[s] >> 8)) + 1ull) << 29) - 1ull;   // ((w >> 8) + 1) 2^29 - 1 < 2^53
+    const uint64_t y = x << 11;
+    r.w[2 * s] = (uint32_t)(y >> 32);
+    r.w[2 * s + 1] = (uint32_t)y;
+  }
+}
+
 // ------------------------------------------------------------------ modified Bessel functions
 
 template <typename T>

@@ -67,6 +67,7 @@ struct WalkerArgs {
   uint64_t max_steps;
   int32_t variant;
   int32_t compensated;
+  int32_t fp32_draws;    // FP64 walker: take the FP32 walker's uniforms (delta tracking)
   int32_t rr;
   T ww_lo;
   T ww_hi;               // > 0: expected-value splitting above this weight (delta tracking)
@@ -590,7 +591,10 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
   #pragma unroll
         for (int i = 0; i < DIM; ++i) q[i] = x[i];
         T gb = 0;
-        if (phase == 2) rng.refill<SL::kBlocks>();
+        if (phase == 2) {
+          if (sizeof(T) == 8 && a.fp32_draws) refill_fp32_draws<DIM>(rng);
+          else rng.refill<SL::kBlocks>();
+        }
         if (phase == 2 && !pending) {
           if constexpr (COUNT) ++ev[EV_STEPS];
           if ((nsteps & kStepMask) >= a.max_steps) {
@@ -1253,6 +1257,7 @@ static hipError_t launch_walker_t(const WalkerLaunch& L, hipStream_t st) {
   a.max_steps = L.max_steps;
   a.variant = L.variant;
   a.compensated = L.compensated;
+  a.fp32_draws = L.fp32_draws;
   a.rr = L.rr;
   a.ww_lo = (T)L.ww_lo;
   a.ww_hi = (T)L.ww_hi;

@@ -25,6 +25,7 @@ struct WalkerLaunch {
   uint64_t max_steps;
   int variant;
   int compensated;
+  int fp32_draws;     // FP64 walker with the FP32 walker's uniforms
   int rr;
   double ww_lo;
   double ww_hi;       // 0: no splitting

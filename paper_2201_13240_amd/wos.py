@@ -14,12 +14,12 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwos.so")
 
-WOS_FP32, WOS_FP32_COMPENSATED, WOS_FP64 = 0, 1, 2
+WOS_FP32, WOS_FP32_COMPENSATED, WOS_FP64, WOS_FP64_FP32_DRAWS = 0, 1, 2, 3
 _GEOM = {"ball": 0, "box": 1, "polygon": 2, "trimesh": 3, "sdf": 4}
 _BASE = {"none": 0, "fourier": 1, "bumps": 2, "tanh": 3, "tanh_drift": 4, "manufactured": 5}
 _TRANSFORM = {"affine": 0, "exp": 1}
 _SOLUTION = {"expcos": 1, "quadratic": 2}
-PRECISIONS = {"fp32": WOS_FP32, "fp32c": WOS_FP32_COMPENSATED, "fp64": WOS_FP64}
+PRECISIONS = {"fp32": WOS_FP32, "fp32c": WOS_FP32_COMPENSATED, "fp64": WOS_FP64, "fp64_fp32draws": WOS_FP64_FP32_DRAWS}
 
 
 class WosError(RuntimeError):

@@ -389,3 +389,38 @@ def test_event_counts_match_solve(W):
     # per-point pre-pass
     assert ev["coefficient_lane_iterations"] == ev["steps"]
     assert ev["trials"] >= ev["steps"] - ev["terminal"]
+
+
+def test_fp64_walker_with_fp32_draws(W):
+    """WOS_FP64_FP32_DRAWS: the FP64 walker drawing the FP32 walker's uniforms. Walks of
+    one seed then follow the FP32 walks' paths up to rounding (common random numbers):
+    single-walk solves give the same distance-query counts for nearly every walk and
+    estimates that differ by rounding only where the paths agree. The mode is still the
+    estimator of Alg. 1: its batch means at the star polygon's sampled points agree with
+    the oracle's (tests/golden/parity_star256.npz)."""
+    import os
+    from tests import parity as PR
+    torch = torch_cuda()
+    d = np.load(os.path.join(os.path.dirname(__file__), "golden", "parity_star256.npz"), allow_pickle=False)
+    c = WL.config2()
+    prob, pts = c["problems"][0], c["points"][0]
+    h = W.Problem(prob, sigma_bar=float(d["sigma_bar"][0]))
+    sub = pts[np.random.default_rng(9).choice(pts.shape[0], 4000, replace=False)]
+    P = dev(sub)
+    vals, steps = {}, {}
+    for prec in ("fp32", "fp64_fp32draws"):
+        v, s = [], []
+        for j in range(8):
+            acc = W.Accumulators(P.shape[0])
+            W.solve([(h, P, acc, 0)], W.options(precision=prec, walks=1, seed=13, walk_offset=j))
+            torch.cuda.synchronize()
+            v.append(acc.sum.cpu().numpy())
+            s.append(acc.n_steps.cpu().numpy())
+        vals[prec], steps[prec] = np.array(v), np.array(s)
+    same = steps["fp32"] == steps["fp64_fp32draws"]
+    assert same.mean() > 0.95, same.mean()
+    dv = np.abs(vals["fp32"] - vals["fp64_fp32draws"])[same]
+    close = dv <= 1e-3 * np.maximum(1.0, np.abs(vals["fp64_fp32draws"][same]))
+    assert close.mean() > 0.97, close.mean()
+    b = gpu_batches(W, h, pts[d["idx"]], 32, 64, "fp64_fp32draws", seed=17)
+    PR.assert_parity_batches(b, d["run_a"], "FP64 with FP32 draws vs oracle", 1e-12)
