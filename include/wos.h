@@ -169,6 +169,12 @@ wos_status wos_problem_create(const wos_problem_desc* desc, int device, wos_prob
 wos_status wos_problem_info(const wos_problem* p, double* sigma_prime_min, double* sigma_prime_max,
                             double* sigma_bar);
 
+/* Set-up time of wos_problem_create in milliseconds of host wall clock (any output may be
+ * null): geometry_ms building the BVH and the candidate grid (Sec. 7.1), sigma_bar_ms
+ * sampling sigma' and fixing sigma_bar (Sec. 5.1), upload_ms laying out and copying the
+ * problem tables to the device. */
+wos_status wos_problem_setup_times(const wos_problem* p, double* geometry_ms, double* sigma_bar_ms, double* upload_ms);
+
 /* BVH statistics: nodes, depth, primitives (0 for analytic shapes). */
 wos_status wos_problem_bvh_info(const wos_problem* p, int64_t* n_nodes, int32_t* depth, int64_t* n_prims);
 
@@ -336,7 +342,25 @@ wos_status wos_plan_time(wos_plan* plan, uint64_t seed, uint64_t walk_offset_add
 /* Launch shape chosen by the plan. */
 wos_status wos_plan_info(const wos_plan* plan, int32_t* block_size, int32_t* tile_walks,
                          int32_t* grid_size, int32_t* n_launches);
+/* Set-up time of wos_plan_create in milliseconds of host wall clock: build_ms for the
+ * tables, scratch, classification, gamma(x0) and graph capture of the final plan, tune_ms
+ * for the autotuning runs (0 when the shape was given or already tuned); tuned_here = 1
+ * when this plan ran the autotuner. Any output may be null. */
+wos_status wos_plan_setup_times(const wos_plan* plan, double* build_ms, double* tune_ms, int32_t* tuned_here);
 wos_status wos_plan_destroy(wos_plan* plan);
+
+/* Persistence of the autotuner's choices (the launch shapes of the batched schedule).
+ * wos_tune_cache_save writes every shape tuned in this process to the text file `path`,
+ * one line per walker variant: device architecture and compute-unit count, precision,
+ * dimension, geometry kind, walker mode, batch flag, block size and tile length.
+ * wos_tune_cache_load reads such a file and makes its shapes the tuned shapes of every
+ * device of this process with the same architecture and compute-unit count (replacing
+ * shapes tuned before), so that later plans of those variants skip the autotuning runs.
+ * Errors: WOS_ERR_INVALID_ARG for a null path, a file that cannot be opened or written,
+ * or a malformed line (nothing is loaded then). n_saved / n_loaded (may be null): lines
+ * written, shapes set. */
+wos_status wos_tune_cache_save(const char* path, int32_t* n_saved);
+wos_status wos_tune_cache_load(const char* path, int32_t* n_loaded);
 
 /* ---------------------------------------------------------------- diagnostics
  * These run the walker's own device functions on explicit inputs so each step of the

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -81,6 +82,7 @@ struct wos_problem {
   int32_t grid_nx = 0, grid_ny = 0, grid_nz = 0;
   int64_t grid_candidates = 0;
   std::vector<unsigned char> staging;  // host copy of the device blob
+  double geometry_ms = 0, sigma_bar_ms = 0, upload_ms = 0;   // set-up time (host wall clock)
   const void* d32() const { return (const unsigned char*)dmem + off32; }
   const void* d64() const { return (const unsigned char*)dmem + off64; }
 };
@@ -643,11 +645,16 @@ static wos_status problem_create_impl(const wos_problem_desc* desc, int device, 
     const wos_status s = check_field(*fds[k], d.dim, names[k], k >= 3);
     if (s != WOS_OK) return s;
   }
+  using clock = std::chrono::steady_clock;
+  auto ms_since = [](clock::time_point t) { return std::chrono::duration<double, std::milli>(clock::now() - t).count(); };
+  clock::time_point t0 = clock::now();
   HostGeometry g;
   {
     const wos_status s = build_geometry(d, g);
     if (s != WOS_OK) return s;
   }
+  const double geometry_ms = ms_since(t0);
+  t0 = clock::now();
   int n_dev = 0;
   WOS_HIP(hipGetDeviceCount(&n_dev));
   if (device < 0 || device >= n_dev) return fail(WOS_ERR_DEVICE, "no such device");
@@ -685,6 +692,8 @@ static wos_status problem_create_impl(const wos_problem_desc* desc, int device, 
     delete p;
     return fail(WOS_ERR_DEVICE, "upload of problem data failed");
   }
+  const double upload_ms = ms_since(t0);
+  t0 = clock::now();
   // sample alpha, sigma and sigma' in FP64 over a grid of the bounding box (interior points)
   double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
   if (g.kind == WOS_GEOM_BALL) {
@@ -775,6 +784,9 @@ static wos_status problem_create_impl(const wos_problem_desc* desc, int device, 
     cleanup();
     return fail(WOS_ERR_DEVICE, "upload of sigma_bar failed");
   }
+  p->geometry_ms = geometry_ms;
+  p->upload_ms = upload_ms;
+  p->sigma_bar_ms = ms_since(t0);
   *out = p;
   return WOS_OK;
 }
@@ -788,6 +800,14 @@ wos_status wos_problem_info(const wos_problem* p, double* sp_min, double* sp_max
   if (sp_min) *sp_min = p->sp_min;
   if (sp_max) *sp_max = p->sp_max;
   if (sigma_bar) *sigma_bar = p->sigma_bar;
+  return WOS_OK;
+}
+
+wos_status wos_problem_setup_times(const wos_problem* p, double* geometry_ms, double* sigma_bar_ms, double* upload_ms) {
+  if (!p) return fail(WOS_ERR_INVALID_ARG, "null problem");
+  if (geometry_ms) *geometry_ms = p->geometry_ms;
+  if (sigma_bar_ms) *sigma_bar_ms = p->sigma_bar_ms;
+  if (upload_ms) *upload_ms = p->upload_ms;
   return WOS_OK;
 }
 
@@ -1062,6 +1082,8 @@ struct wos_plan {
   std::vector<std::vector<DevItem>> dit;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  double tune_ms = 0, build_ms = 0;   // set-up time (host wall clock)
+  int tuned_here = 0;                 // 1 if this plan ran the autotuner
 };
 
 namespace {
@@ -1524,8 +1546,13 @@ wos_status wos_finalize_grad(const double* grad_sum, const double* grad_sum_sq, 
 
 static wos_status plan_create_impl(const wos_batch_item* items, int32_t n_items, const wos_options* opt,
                                    void* stream, wos_plan** out) {
+  using clock = std::chrono::steady_clock;
+  auto ms_since = [](clock::time_point t) { return std::chrono::duration<double, std::milli>(clock::now() - t).count(); };
+  clock::time_point t0 = clock::now();
   wos_status r = plan_build(items, n_items, opt, stream, out);
-  if (r != WOS_OK || opt->block_size != 0 || opt->tile_walks != 0) return r;
+  if (r != WOS_OK) return r;
+  (*out)->build_ms = ms_since(t0);
+  if (opt->block_size != 0 || opt->tile_walks != 0) return r;
   wos_plan* P = *out;
   bool tuned;
   {
@@ -1535,19 +1562,131 @@ static wos_status plan_create_impl(const wos_batch_item* items, int32_t n_items,
   if (tuned) return WOS_OK;
   unsigned block = 0;
   uint32_t tile = 0;
+  t0 = clock::now();
   if ((r = autotune(P, (hipStream_t)stream, &block, &tile)) != WOS_OK) {
     wos_plan_destroy(P);
     *out = nullptr;
     return r;
   }
-  if (block == P->s.block && tile == P->s.tile_walks) return WOS_OK;
+  const double tune_ms = ms_since(t0);
+  if (block == P->s.block && tile == P->s.tile_walks) {
+    P->tune_ms = tune_ms;
+    P->tuned_here = 1;
+    return WOS_OK;
+  }
   // rebuild with the tuned shape (tile tables and workspace depend on it)
   wos_plan_destroy(P);
   *out = nullptr;
   wos_options o = *opt;
   o.block_size = (int32_t)block;
   o.tile_walks = (int32_t)tile;
-  return plan_build(items, n_items, &o, stream, out);
+  t0 = clock::now();
+  r = plan_build(items, n_items, &o, stream, out);
+  if (r == WOS_OK) {
+    (*out)->build_ms = ms_since(t0);
+    (*out)->tune_ms = tune_ms;
+    (*out)->tuned_here = 1;
+  }
+  return r;
+}
+
+// ---------------------------------------------------------------- tuned-shape cache
+// One line per tuned walker variant: arch CUs fp64 compensated dim geom mode batch block tile.
+// The device is named by its architecture string and compute-unit count, so that a file
+// written on one GPU applies to every GPU of the same kind.
+
+static wos_status device_signature(int device, std::string* arch, int* cus) {
+  hipDeviceProp_t prop;
+  WOS_HIP(hipGetDeviceProperties(&prop, device));
+  *arch = prop.gcnArchName;
+  *cus = prop.multiProcessorCount;
+  return WOS_OK;
+}
+
+static wos_status tune_cache_save_impl(const char* path, int32_t* n_saved) {
+  if (!path) return fail(WOS_ERR_INVALID_ARG, "null path");
+  std::map<std::tuple<int, int, int, int, int, int, int>, std::pair<unsigned, uint32_t>> tuned;
+  {
+    std::lock_guard<std::mutex> lk(g_occ_mutex);
+    tuned = g_tuned;
+  }
+  std::string text = "# walk-on-spheres tuned launch shapes: arch cus fp64 compensated dim geom mode batch block tile\n";
+  int n = 0;
+  for (const auto& kv : tuned) {
+    std::string arch;
+    int cus = 0;
+    const wos_status r = device_signature(std::get<0>(kv.first), &arch, &cus);
+    if (r != WOS_OK) return r;
+    char line[512];
+    std::snprintf(line, sizeof(line), "%s %d %d %d %d %d %d %d %u %u\n", arch.c_str(), cus, std::get<1>(kv.first),
+                  std::get<2>(kv.first), std::get<3>(kv.first), std::get<4>(kv.first), std::get<5>(kv.first),
+                  std::get<6>(kv.first), kv.second.first, kv.second.second);
+    text += line;
+    ++n;
+  }
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(WOS_ERR_INVALID_ARG, std::string("cannot write ") + path);
+  const bool ok = std::fwrite(text.data(), 1, text.size(), f) == text.size();
+  if (std::fclose(f) != 0 || !ok) return fail(WOS_ERR_INVALID_ARG, std::string("write to ") + path + " failed");
+  if (n_saved) *n_saved = n;
+  return WOS_OK;
+}
+
+static wos_status tune_cache_load_impl(const char* path, int32_t* n_loaded) {
+  if (!path) return fail(WOS_ERR_INVALID_ARG, "null path");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(WOS_ERR_INVALID_ARG, std::string("cannot read ") + path);
+  struct Entry {
+    std::string arch;
+    int cus, key[6];
+    unsigned block, tile;
+  };
+  std::vector<Entry> entries;
+  char line[512];
+  int lineno = 0;
+  while (std::fgets(line, sizeof(line), f)) {
+    ++lineno;
+    if (line[0] == '#' || line[0] == '\n') continue;
+    char arch[256];
+    Entry e;
+    if (std::sscanf(line, "%255s %d %d %d %d %d %d %d %u %u", arch, &e.cus, &e.key[0], &e.key[1], &e.key[2],
+                    &e.key[3], &e.key[4], &e.key[5], &e.block, &e.tile) != 10 ||
+        e.block < 64 || e.block > 256 || e.block % 64 || e.tile < 1 || e.tile > kMaxTileLen || e.key[0] < 0 ||
+        e.key[0] > 1 || e.key[1] < 0 || e.key[1] > 1 || (e.key[2] != 2 && e.key[2] != 3) || e.key[3] < 0 ||
+        e.key[3] > 4 || e.key[4] < 0 || e.key[4] > 2 || e.key[5] < 0 || e.key[5] > 1) {
+      std::fclose(f);
+      return fail(WOS_ERR_INVALID_ARG, std::string(path) + ": malformed line " + std::to_string(lineno));
+    }
+    e.arch = arch;
+    entries.push_back(e);
+  }
+  std::fclose(f);
+  int n_dev = 0;
+  WOS_HIP(hipGetDeviceCount(&n_dev));
+  int n = 0;
+  for (int d = 0; d < n_dev; ++d) {
+    std::string arch;
+    int cus = 0;
+    const wos_status r = device_signature(d, &arch, &cus);
+    if (r != WOS_OK) return r;
+    std::lock_guard<std::mutex> lk(g_occ_mutex);
+    for (const Entry& e : entries) {
+      if (e.arch != arch || e.cus != cus) continue;
+      g_tuned[std::make_tuple(d, e.key[0], e.key[1], e.key[2], e.key[3], e.key[4], e.key[5])] =
+          std::make_pair(e.block, (uint32_t)e.tile);
+      ++n;
+    }
+  }
+  if (n_loaded) *n_loaded = n;
+  return WOS_OK;
+}
+
+wos_status wos_tune_cache_save(const char* path, int32_t* n_saved) {
+  return guarded([&] { return tune_cache_save_impl(path, n_saved); });
+}
+
+wos_status wos_tune_cache_load(const char* path, int32_t* n_loaded) {
+  return guarded([&] { return tune_cache_load_impl(path, n_loaded); });
 }
 
 wos_status wos_plan_create(const wos_batch_item* items, int32_t n_items, const wos_options* opt, void* stream,
@@ -1618,6 +1757,14 @@ wos_status wos_plan_info(const wos_plan* P, int32_t* block_size, int32_t* tile_w
   if (tile_walks) *tile_walks = (int32_t)P->s.tile_walks;
   if (grid_size) *grid_size = (int32_t)P->s.grid;
   if (n_launches) *n_launches = P->s.n_launches;
+  return WOS_OK;
+}
+
+wos_status wos_plan_setup_times(const wos_plan* P, double* build_ms, double* tune_ms, int32_t* tuned_here) {
+  if (!P) return fail(WOS_ERR_INVALID_ARG, "null plan");
+  if (build_ms) *build_ms = P->build_ms;
+  if (tune_ms) *tune_ms = P->tune_ms;
+  if (tuned_here) *tuned_here = P->tuned_here;
   return WOS_OK;
 }
 

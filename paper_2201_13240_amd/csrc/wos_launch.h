@@ -34,6 +34,15 @@ struct WalkerLaunch {
 };
 
 hipError_t launch_walker(const WalkerLaunch& L, hipStream_t st);
+// The walkers of one precision and dimension (wos_walker_{f32,f64}_{2d,3d}.hip).
+hipError_t launch_walker_f32_2d(const WalkerLaunch& L, hipStream_t st);
+hipError_t launch_walker_f32_3d(const WalkerLaunch& L, hipStream_t st);
+hipError_t launch_walker_f64_2d(const WalkerLaunch& L, hipStream_t st);
+hipError_t launch_walker_f64_3d(const WalkerLaunch& L, hipStream_t st);
+const void* walker_symbol_f32_2d(int geom, int mode);
+const void* walker_symbol_f32_3d(int geom, int mode);
+const void* walker_symbol_f64_2d(int geom, int mode);
+const void* walker_symbol_f64_3d(int geom, int mode);
 // Bytes of the scratch array of wos_solve_static, one copy per GPU.
 constexpr size_t kStaticScratchBytes = 128ull << 20;
 // Device address of `device`'s copy of that array (looked up on the first call for the

@@ -66,7 +66,8 @@ class BatchItem(C.Structure):
 EXPORTS = ["wos_last_error", "wos_version", "wos_problem_create", "wos_problem_info", "wos_problem_bvh_info", "wos_problem_grid_info",
            "wos_problem_destroy", "wos_solve", "wos_solve_static", "wos_count_events", "wos_finalize", "wos_finalize_grad", "wos_plan_create", "wos_plan_launch",
            "wos_plan_time", "wos_plan_info", "wos_plan_destroy", "wos_eval_coefficients", "wos_eval_distance", "wos_eval_ball",
-           "wos_sample_radius", "wos_philox", "wos_eval_bessel", "wos_eval_offcentred", "wos_classify"]
+           "wos_sample_radius", "wos_philox", "wos_eval_bessel", "wos_eval_offcentred", "wos_classify",
+           "wos_problem_setup_times", "wos_plan_setup_times", "wos_tune_cache_save", "wos_tune_cache_load"]
 
 _lib = None
 
@@ -96,6 +97,10 @@ def lib():
         L.wos_plan_time.argtypes = [vp, u64, u64, vp, dp, dp]
         L.wos_plan_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
         L.wos_plan_destroy.argtypes = [vp]
+        L.wos_problem_setup_times.argtypes = [vp, dp, dp, dp]
+        L.wos_plan_setup_times.argtypes = [vp, dp, dp, C.POINTER(i32)]
+        L.wos_tune_cache_save.argtypes = [C.c_char_p, C.POINTER(i32)]
+        L.wos_tune_cache_load.argtypes = [C.c_char_p, C.POINTER(i32)]
         L.wos_eval_coefficients.argtypes = [vp, vp, i64, i32, vp, vp]
         L.wos_eval_distance.argtypes = [vp, vp, i64, i32, vp, vp, vp]
         L.wos_eval_ball.argtypes = [i32, i32, vp, i64, vp, vp]
@@ -204,12 +209,10 @@ class Problem:
         elif b == "manufactured":
             F.solution_id = _SOLUTION[f["u"]]
 
-    def time(self, seed, walk_offset_add=0, stream=None):
-        """Runs the plan's work once as separate launches with HIP events around the
-        walker; returns (walker_ms, total_ms). Accumulates like launch()."""
-        w, t = C.c_double(), C.c_double()
-        _check(lib().wos_plan_time(self.handle, seed, walk_offset_add, _stream(stream), C.byref(w), C.byref(t)))
-        return w.value, t.value
+    def setup_times(self):
+        g, s, u = C.c_double(), C.c_double(), C.c_double()
+        _check(lib().wos_problem_setup_times(self.handle, C.byref(g), C.byref(s), C.byref(u)))
+        return {"geometry_ms": g.value, "sigma_bar_ms": s.value, "upload_ms": u.value}
 
     def info(self):
         a, b, c = C.c_double(), C.c_double(), C.c_double()
@@ -374,6 +377,11 @@ class Plan:
         _check(lib().wos_plan_info(self.handle, C.byref(b), C.byref(t), C.byref(g), C.byref(n)))
         return {"block_size": b.value, "tile_walks": t.value, "grid": g.value, "launches": n.value}
 
+    def setup_times(self):
+        b, t, h = C.c_double(), C.c_double(), C.c_int32()
+        _check(lib().wos_plan_setup_times(self.handle, C.byref(b), C.byref(t), C.byref(h)))
+        return {"build_ms": b.value, "tune_ms": t.value, "tuned_here": bool(h.value)}
+
     def close(self):
         if getattr(self, "handle", None):
             lib().wos_plan_destroy(self.handle)
@@ -384,6 +392,20 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def tune_cache_save(path):
+    """Writes the launch shapes tuned in this process to `path`; returns the lines written."""
+    n = C.c_int32()
+    _check(lib().wos_tune_cache_save(str(path).encode(), C.byref(n)))
+    return n.value
+
+
+def tune_cache_load(path):
+    """Makes the shapes in `path` the tuned shapes of matching devices; returns how many were set."""
+    n = C.c_int32()
+    _check(lib().wos_tune_cache_load(str(path).encode(), C.byref(n)))
+    return n.value
 
 
 # ----------------------------------------------------------------------------- diagnostics

@@ -112,3 +112,18 @@ def test_solve_rejects_bad_batches_without_device(W):
         o = W.options(walks=16, **kw)
         assert W.lib().wos_solve(items, 1, C.byref(o), None) == 1, kw
         assert W.lib().wos_last_error()
+
+
+def test_tune_cache_rejects_bad_files(W, tmp_path):
+    """A malformed tuned-shape file or a path that cannot be read is rejected before any
+    shape is set (no device call is made)."""
+    bad = tmp_path / "bad.txt"
+    bad.write_text("# header\ngfx950 256 0 0 2 2 0 0 100 64\n")      # block size not a multiple of 64
+    with pytest.raises(W.WosError) as e:
+        W.tune_cache_load(bad)
+    assert e.value.status == 1 and "line 2" in str(e.value)
+    bad.write_text("gfx950 256 0 0 4 2 0 0 256 64\n")                  # no such dimension
+    with pytest.raises(W.WosError):
+        W.tune_cache_load(bad)
+    with pytest.raises(W.WosError):
+        W.tune_cache_load(tmp_path / "missing.txt")
