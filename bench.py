@@ -4,9 +4,14 @@ Workload: the 256-edge star polygon problem with random alpha, drift and sigma f
 (Gaussian-bump f and g), all query points of a 512 x 512 grid inside the domain, 1024
 walks per point. One "step" of this benchmark is one full pass of the hot path over
 that batch: a captured hipGraph replay of [tile-counter reset, persistent walker,
-per-point reduction]. The metric is walk steps (distance queries) per second; points
+per-point exact sums]. The metric is walk steps (distance queries) per second; points
 per second at RMSE 1e-2 against the FP64 oracle is derived from the measured per-walk
-variance. Prints one JSON line.
+variance. Beside it the line reports the walker's vector-ALU roofline, the FP64 walker,
+the FP32 rounding error against the FP64 walker on common random numbers, the FP64 CPU
+oracle as a baseline, time to RMSE 1e-2, next flight against delta tracking, the RMSE
+against the oracle versus walks per point on the high-contrast square, set-up times, and
+the throughput and roofline of every other walker (gradients, splitting, an SDF scene,
+the 64-problem batch, the full icosphere slice). Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -40,9 +45,17 @@ def parse():
     ap.add_argument("--cpu-walks", type=int, default=8192)
     ap.add_argument("--no-events", action="store_true")
     ap.add_argument("--variants", type=int, default=1,
-                    help="also time next flight against delta tracking on the high-contrast square (0: skip)")
+                    help="also time next flight against delta tracking on a screened disk and on the high-contrast "
+                         "square (0: skip)")
     ap.add_argument("--extras", type=int, default=1,
-                    help="also time gradients, weight-window splitting and an SDF/CSG scene (0: skip)")
+                    help="also time (with rooflines) the FP64 walker, gradients, weight-window splitting, an SDF/CSG "
+                         "scene, the 64-problem batch and the full icosphere slice (0: skip)")
+    ap.add_argument("--fp32-error", type=int, default=1,
+                    help="FP32 against FP64 on common random numbers (0: skip)")
+    ap.add_argument("--sweep", type=int, default=1,
+                    help="RMSE against the oracle versus walks per point on the high-contrast square (0: skip)")
+    ap.add_argument("--tune-cache", default="",
+                    help="file of tuned launch shapes: loaded before the runs if it exists, written after them")
     ap.add_argument("--shape", default="auto",
                     help="walker launch shape: 'auto' (the plan autotunes block size and tile length) or "
                          "BLOCKxTILE, e.g. 256x256 (profiling runs pin the tuned shape so that no tuning "
@@ -93,7 +106,9 @@ def _field_cost(f, dim, derivs):
     return fl, tr
 
 
-def event_weights(prob):
+def _coefficient_costs(prob):
+    """(flops, transcendentals) of the coefficient program at one point, of gamma alone,
+    and of the boundary field."""
     dim = prob["dim"]
     af, at = _field_cost(prob["alpha"], dim, True)
     pf, pt = _field_cost(prob["psi"], dim, True) if prob["psi"]["base"] != "none" else (0, 0)
@@ -108,14 +123,24 @@ def event_weights(prob):
     ps_f = _field_cost(prob["psi"], dim, False) if prob["psi"]["base"] != "none" else (0, 0)
     gamma_only = (ga_f[0] + ps_f[0] + 2, ga_f[1] + ps_f[1])
     bf, bt = _field_cost(prob["boundary"], dim, False) if prob["boundary"]["base"] != "manufactured" else (6, 3)
+    return (coef, coef_t), gamma_only, (bf, bt)
+
+
+def _geometry_costs(prob):
+    dim = prob["dim"]
     seg = 21 if dim == 2 else 75                                         # segment / triangle distance
     node = 2 * (3 * dim) + 2                                             # two child boxes + ordering
-    W = {
-        # per distance query: sqrt, epsilon test, ball radius
-        "steps": (3, 1),
-        "bvh_nodes": (node, 0),
-        "grid_cells": (2 * dim + 4, 0),                                  # cell index of the query point
-        "prims": (seg, 0),
+    return {"steps": (3, 1),                                             # per query: sqrt, epsilon test, radius
+            "bvh_nodes": (node, 0),
+            "grid_cells": (2 * dim + 4, 0),                              # cell index of the query point
+            "prims": (seg, 0)}
+
+
+def event_weights(prob):
+    """Per-event (flops, transcendentals) of the delta-tracking walk (Sec. 5.1, Alg. 1)."""
+    (coef, coef_t), gamma_only, (bf, bt) = _coefficient_costs(prob)
+    W = _geometry_costs(prob)
+    W.update({
         # per sampled ball: normalisation (series), direction, y, mu, coefficients at y, source
         "sampled": (73 + 2 + 5 + 1 + coef + 5, 1 + 2 + coef_t + 1),
         "ball_large_s": (42, 2),                                         # Chebyshev instead of series
@@ -126,12 +151,35 @@ def event_weights(prob):
         "terminal": (12 + bf + 4, bt + 1),
         "gamma_evals": gamma_only,
         "rr_draws": (4, 0),
-    }
+    })
     return W
 
 
-def algorithmic_work(events, prob):
-    W = event_weights(prob)
+def nf_event_weights(prob):
+    """Per-event (flops, transcendentals) of the next-flight walk (Sec. 5.2, supplemental
+    Alg. 2). A ball (a distance query that does not end the walk) takes the centred ball
+    terms and its exit direction; an inner point (counted as a proposal, events[3]) takes a
+    uniform point in the ball, the coefficients there, the off-centred Green's function (two
+    radial profiles of about 45 flops and 2 exponentials each), the source and throughput
+    updates, the off-centred Poisson kernel at the exit point (two profiles) and the
+    throughput roulette."""
+    (coef, coef_t), gamma_only, (bf, bt) = _coefficient_costs(prob)
+    dim = prob["dim"]
+    W = _geometry_costs(prob)
+    green = 4 * dim + 5 + 2 * 45, 1 + 2 * 2                               # nf_green_vol
+    poisson = 4 * dim + 11 + 2 * 45, 1 + 2 * 2                            # nf_poisson_area
+    W.update({
+        "sampled": (73 + 2 + 6, 1 + 2),                                  # ball terms, exit direction
+        "ball_large_s": (42, 2),
+        "trials": (8 + dim + coef + green[0] + 6 + 3 + poisson[0] + 3, 3 + coef_t + green[1] + 1 + poisson[1]),
+        "terminal": (12 + bf + 4, bt + 1),
+        "gamma_evals": gamma_only,
+    })
+    return W
+
+
+def algorithmic_work(events, prob, next_flight=False):
+    W = nf_event_weights(prob) if next_flight else event_weights(prob)
     ev = dict(events)
     ev["sampled"] = ev["steps"] - ev["terminal"]
     flops = sum(W[k][0] * ev[k] for k in W)
@@ -262,62 +310,6 @@ def copy_probe():
     print("copied bytes", n * 4, flush=True)
 
 
-def compare_variants(wos, WL, args):
-    """Next flight (Sec. 5.2) against delta tracking (Sec. 5.1) on the high-contrast unit
-    square: 65,536 query points, sigma_bar about 1.2e4, where delta tracking takes many
-    short steps. Both FP32 at the same walks per point, one captured plan each; reports
-    pass time, distance queries per walk, per-walk variance, points per second at RMSE
-    1e-2 from that variance, and how far the two means are apart in combined standard
-    errors. On this problem sigma' < 0 in places and R sqrt(sigma_bar) is large, where
-    next flight's in-ball series has no finite variance, so only its time and distance
-    queries compare directly."""
-    import torch
-    c = WL.config5()
-    prob, pts = c["problems"][0], c["points"][0]
-    n = pts.shape[0]
-    h = wos.Problem(prob)
-    P = torch.as_tensor(pts, dtype=torch.float64, device="cuda")
-    walks = 256
-    out = {"workload": "unit square, alpha tanh jump 1..100, omega = (50, 0), sigma in [100, 1000], "
-                       "256x256 points", "walks_per_point": walks, "sigma_bar": h.sigma_bar}
-    res = {}
-    for name, variant, rr in (("delta_tracking", 0, True), ("next_flight", 2, False)):
-        acc = wos.Accumulators(n)
-        plan = wos.Plan([(h, P, acc, 0)], wos.options(precision="fp32", walks=walks, seed=0, variant=variant,
-                                                      russian_roulette=rr))
-        plan.launch(seed=99)
-        torch.cuda.synchronize()
-        for t in (acc.sum, acc.sum_sq, acc.n_walks, acc.n_steps, acc.counters):
-            t.zero_()
-        ms = []
-        for k in range(3):
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
-            plan.launch(seed=k, walk_offset_add=k * walks)
-            b.record()
-            torch.cuda.synchronize()
-            ms.append(a.elapsed_time(b))
-        mean, se = wos.finalize(acc)
-        torch.cuda.synchronize()
-        plan.close()
-        nw = float(acc.n_walks[0].item())
-        var = float(np.mean((se.cpu().numpy() ** 2) * nw))
-        t_walk = (np.mean(ms) / 1e3) / walks
-        res[name] = (mean.cpu().numpy(), se.cpu().numpy())
-        out[name] = {"ms_per_pass": float(np.mean(ms)),
-                     "distance_queries_per_walk": float(acc.n_steps.sum().item()) / (nw * n),
-                     "ball_samples_per_walk": float(acc.counters[3].item()) / (nw * n),
-                     "per_walk_variance": var,
-                     "points_per_s_at_rmse_1e-2": n / ((var / 1e-4) * t_walk)}
-        print(f"bench: {name} on the high-contrast square, ms/pass {np.round(ms, 2).tolist()}", file=sys.stderr,
-              flush=True)
-    (m0, s0), (m1, s1) = res["delta_tracking"], res["next_flight"]
-    z = (m1 - m0) / np.sqrt(s0 ** 2 + s1 ** 2)
-    out["mean_abs_z_next_flight_vs_delta_tracking"] = float(np.mean(np.abs(z)))
-    out["mean_abs_difference"] = float(np.mean(np.abs(m1 - m0)))
-    return out
-
-
 def _timed_plan(wos, torch, prob_handle, P, opt_kw, walks, reps, grad_dim=0):
     """Creates a plan of one item, warms it up, then times `reps` graph replays with HIP
     events on the current stream; returns timings and the accumulated statistics."""
@@ -368,91 +360,383 @@ def time_to_rmse(wos, torch, prob_handle, P, ref_idx, ref_mean, ref_se, precisio
         walks *= 2
 
 
-def measure_extras(wos, WL):
-    """Throughput of the rows beyond the plain delta-tracking walk, FP32, each against the
-    plain walk on the same workload: gradients (supplemental Sec. 2) on the star polygon;
-    weight-window splitting (Sec. 6) on the manufactured disk, where sigma' < 0 lets
-    null-collision weights grow; an SDF/CSG scene (Sec. 7.2); and the other workload
-    shapes: the batch of 64 polygon problems in one plan and the 3D mesh walker."""
-    import torch
+def measure_extras(wos, torch, WL, setup):
+    """Throughput and vector-ALU roofline of every other walker the benchmark times, FP32
+    unless stated: the FP64 walker on the star polygon; gradients (supplemental Sec. 2) on
+    the star polygon; weight-window splitting (Sec. 6) on the manufactured disk, where
+    sigma' < 0 lets null-collision weights grow; an SDF/CSG scene (Sec. 7.2); the batch of
+    64 polygon problems in one plan; and the 3D mesh walker on the perturbed icosphere's
+    z = 0 slice at its full size (676,691 points x 256 walks). `setup` collects the set-up
+    time of each problem."""
     out = {}
-    # gradient estimates: the star-polygon workload at 256 walks per point
+
+    def problem(name, prob, **kw):
+        t0 = time.perf_counter()
+        h = wos.Problem(prob, **kw)
+        setup[name] = {"problem_create_ms": (time.perf_counter() - t0) * 1e3, **h.setup_times()}
+        return h
+
+    def one(h, pts, grad_dim=0):
+        P = torch.as_tensor(pts, dtype=torch.float64, device="cuda")
+        return [(h, P, wos.Accumulators(P.shape[0], grad_dim=grad_dim), 0)]
+
     c = WL.config2(n_grid=512)
     prob, pts = c["problems"][0], c["points"][0]
-    h = wos.Problem(prob)
-    P = torch.as_tensor(pts, dtype=torch.float64, device="cuda")
-    plain = _timed_plan(wos, torch, h, P, {"precision": "fp32"}, 256, 3)
-    grad = _timed_plan(wos, torch, h, P, {"precision": "fp32"}, 256, 3, grad_dim=2)
+    h = problem("star_polygon_again", prob)
+    out["fp64_star"] = {"workload": "star polygon 256 edges, 512x512 grid inside, 1024 walks per point, FP64",
+                        **_strip(measure_walker(wos, torch, one(h, pts), {"precision": "fp64"}, 1024, 2, prob,
+                                                label="FP64 star polygon"))}
+    plain = _strip(measure_walker(wos, torch, one(h, pts), {"precision": "fp32"}, 256, 3, prob, label="plain 256"))
+    grad = _strip(measure_walker(wos, torch, one(h, pts, 2), {"precision": "fp32"}, 256, 3, prob,
+                                 label="gradient 256"))
     out["gradient"] = {"workload": "star polygon 256 edges, 512x512 grid inside, 256 walks per point",
-                       "plain_ms_per_pass": plain["ms_per_pass"], "gradient_ms_per_pass": grad["ms_per_pass"],
+                       "plain": plain, "with_gradient": grad,
                        "overhead": grad["ms_per_pass"] / plain["ms_per_pass"] - 1.0}
-    print(f"bench: gradient overhead {out['gradient']['overhead']:.3f}", file=sys.stderr, flush=True)
-    del P
     # splitting: manufactured disk on a 256x256 grid, window [0.5, 1.5]
     c = WL.config1(n_grid=256)
     prob, pts = c["problems"][0], c["points"][0]
-    h = wos.Problem(prob)
-    P = torch.as_tensor(pts, dtype=torch.float64, device="cuda")
-    rr = _timed_plan(wos, torch, h, P, {"precision": "fp32", "russian_roulette": True, "ww_lo": 0.5}, 256, 3)
-    sp = _timed_plan(wos, torch, h, P, {"precision": "fp32", "russian_roulette": True, "ww_lo": 0.5,
-                                        "ww_hi": 1.5}, 256, 3)
-    for r in (rr, sp):
-        r.pop("_mean")
-        r.pop("_se")
+    h = problem("manufactured_disk", prob)
+    rr = _strip(measure_walker(wos, torch, one(h, pts), {"precision": "fp32", "russian_roulette": True,
+                                                         "ww_lo": 0.5}, 256, 3, prob, label="roulette"))
+    sp = _strip(measure_walker(wos, torch, one(h, pts), {"precision": "fp32", "russian_roulette": True,
+                                                         "ww_lo": 0.5, "ww_hi": 1.5}, 256, 3, prob,
+                               label="roulette and splitting"))
     out["splitting"] = {"workload": "manufactured disk, 256x256 grid inside, sigma_bar %.4g, 256 walks per point"
                                     % h.sigma_bar, "roulette_only": rr, "roulette_and_splitting": sp}
-    print("bench: splitting pts/s at RMSE 1e-2 %.3e (roulette only %.3e)"
-          % (sp["points_per_s_at_rmse_1e-2"], rr["points_per_s_at_rmse_1e-2"]), file=sys.stderr, flush=True)
-    del P
     # SDF/CSG scene
     c = WL.config6(n_grid=256)
     prob, pts = c["problems"][0], c["points"][0]
-    h = wos.Problem(prob)
-    P = torch.as_tensor(pts, dtype=torch.float64, device="cuda")
-    sdf = _timed_plan(wos, torch, h, P, {"precision": "fp32"}, 256, 3)
-    sdf.pop("_mean")
-    sdf.pop("_se")
+    h = problem("sdf_scene", prob)
     out["sdf"] = {"workload": "square with 24 round and 8 box holes (33 CSG rows), star-polygon fields, "
-                              "256x256 grid inside, 256 walks per point", "query_points": int(P.shape[0]), **sdf}
-    print(f"bench: sdf steps/s {sdf['steps_per_s']:.3e}", file=sys.stderr, flush=True)
-    del P
+                              "256x256 grid inside, 256 walks per point",
+                  **_strip(measure_walker(wos, torch, one(h, pts), {"precision": "fp32"}, 256, 3, prob,
+                                          label="sdf"))}
     # the batch of 64 polygon problems (16-4096 edges, 2.65e6 points) in one plan
     c = WL.config4()
-    entries, n_total = [], 0
+    t0 = time.perf_counter()
+    entries = []
     for i, (p, q) in enumerate(zip(c["problems"], c["points"])):
         Q = torch.as_tensor(q, dtype=torch.float64, device="cuda")
         entries.append((wos.Problem(p), Q, wos.Accumulators(Q.shape[0]), i))
-        n_total += Q.shape[0]
-    plan = wos.Plan(entries, wos.options(precision="fp32", walks=512, seed=0))
+    setup["batch64"] = {"problems_create_ms": (time.perf_counter() - t0) * 1e3,
+                        "geometry_ms": sum(e[0].setup_times()["geometry_ms"] for e in entries),
+                        "sigma_bar_ms": sum(e[0].setup_times()["sigma_bar_ms"] for e in entries)}
+    out["batch64"] = {"workload": "64 star polygons with 16-4096 edges, log-uniform 1k-256k points each, 512 walks "
+                                  "per point, one plan",
+                      **_strip(measure_walker(wos, torch, entries, {"precision": "fp32"}, 512, 1, c["problems"][0],
+                                              label="64-problem batch"))}
+    del entries
+    # 3D mesh walker on the perturbed icosphere's slice (20,480 triangles), full size
+    c = WL.config3()
+    prob, pts = c["problems"][0], c["points"][0]
+    h = problem("icosphere", prob)
+    out["icosphere"] = {"workload": "perturbed icosphere, 20,480 triangles, 1024x1024 slice grid inside, 256 walks "
+                                    "per point",
+                        **_strip(measure_walker(wos, torch, one(h, pts), {"precision": "fp32"}, 256, 2, prob,
+                                                label="icosphere"))}
+    return out
+
+
+def _zero(acc):
+    for t in (acc.sum, acc.sum_sq, acc.n_walks, acc.n_steps, acc.counters, acc.grad_sum, acc.grad_sum_sq):
+        if t is not None:
+            t.zero_()
+
+
+def measure_walker(wos, torch, entries, opt_kw, walks, reps, weights_prob, next_flight=False, events=True,
+                   label=""):
+    """One plan over `entries` (one item per problem), replayed `reps` times (graph replays,
+    HIP events on the current stream) and then timed `reps` times as separate launches with
+    HIP events around the walker kernel (wos_plan_time). With `events`, the event-counting
+    build runs the same job once in the plan's launch shape and gives the algorithmic
+    flops per distance query (per-event weights of `weights_prob`); achieved = flops per
+    step x steps per walker launch / the walker's mean launch time."""
+    t0 = time.perf_counter()
+    plan = wos.Plan(entries, wos.options(walks=walks, seed=0, **opt_kw))
+    plan_wall_ms = (time.perf_counter() - t0) * 1e3
+    setup = plan.setup_times()
+    info = plan.info()
     plan.launch(seed=999)
     torch.cuda.synchronize()
     for _, _, acc, _ in entries:
-        acc.n_steps.zero_()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    plan.launch(seed=1, walk_offset_add=512)
-    b.record()
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b)
+        _zero(acc)
+    stream = torch.cuda.current_stream()
+    ms = []
+    for k in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        plan.launch(seed=k, walk_offset_add=k * walks)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    n_pts = sum(int(P.shape[0]) for _, P, _, _ in entries)
     steps = sum(float(acc.n_steps.sum().item()) for _, _, acc, _ in entries)
-    out["batch64"] = {"workload": "64 star polygons with 16-4096 edges, log-uniform 1k-256k points each, 512 walks "
-                                  "per point, one plan", "query_points": n_total, "ms_per_pass": ms,
-                      "steps_per_s": steps / (ms / 1e3), "plan": plan.info()}
+    var, nw = [], 0.0
+    means = []
+    for _, _, acc, _ in entries:
+        mean, se = wos.finalize(acc)
+        torch.cuda.synchronize()
+        nw = float(acc.n_walks[0].item()) if acc.n_walks.numel() else nw
+        se_np = se.cpu().numpy()
+        var.append((se_np ** 2) * nw)
+        means.append((mean.cpu().numpy(), se_np))
+    var = np.concatenate(var)
+    var_mean = float(np.nanmean(var))
+    walker_ms, steps_w = [], 0.0
+    for _, _, acc, _ in entries:
+        _zero(acc)
+    for k in range(reps):
+        wm, _ = plan.time(seed=500 + k, walk_offset_add=k * walks, stream=stream)
+        walker_ms.append(wm)
+    torch.cuda.synchronize()
+    steps_w = sum(float(acc.n_steps.sum().item()) for _, _, acc, _ in entries)
     plan.close()
-    del entries
-    print(f"bench: 64-problem batch steps/s {out['batch64']['steps_per_s']:.3e}", file=sys.stderr, flush=True)
-    # 3D mesh walker on a slice of the perturbed icosphere (20,480 triangles)
-    c = WL.config3(n_grid=256)
-    prob, pts = c["problems"][0], c["points"][0]
-    h = wos.Problem(prob)
-    P = torch.as_tensor(pts, dtype=torch.float64, device="cuda")
-    ico = _timed_plan(wos, torch, h, P, {"precision": "fp32"}, 64, 2)
-    ico.pop("_mean")
-    ico.pop("_se")
-    out["icosphere"] = {"workload": "perturbed icosphere, 20,480 triangles, 256x256 slice grid inside, 64 walks per "
-                                    "point", "query_points": int(P.shape[0]), **ico}
-    print(f"bench: icosphere steps/s {ico['steps_per_s']:.3e}", file=sys.stderr, flush=True)
+    t_walk = (np.mean(ms) / 1e3) / walks
+    out = {"query_points": n_pts, "walks_per_point": walks, "ms_per_pass": float(np.mean(ms)),
+           "steps_per_s": steps / (sum(ms) / 1e3), "distance_queries_per_walk": steps / (reps * walks * n_pts),
+           "per_walk_variance": var_mean, "points_per_s_at_rmse_1e-2": n_pts / ((var_mean / 1e-4) * t_walk),
+           "plan": info, "setup_ms": {"plan_create": plan_wall_ms, **setup}}
+    if events:
+        accs = [(h, P, wos.Accumulators(P.shape[0], grad_dim=(acc.grad_sum.shape[1] if acc.grad_sum is not None
+                                                              else 0)), i) for h, P, acc, i in entries]
+        ev = wos.count_events(accs, wos.options(walks=walks, seed=99, block_size=info["block_size"],
+                                                tile_walks=info["tile_walks"], **opt_kw))
+        del accs
+        flops, trans = algorithmic_work(ev, weights_prob, next_flight)
+        fps = flops / ev["steps"]
+        wms = float(np.mean(walker_ms))
+        prec = opt_kw.get("precision", "fp32")
+        peak = 78.6 if prec.startswith("fp64") else 157.3
+        ach = fps * (steps_w / reps) / (wms / 1e3) / 1e12
+        out["roofline"] = {"bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+                           "kernel_ms": wms, "flops_per_step": fps, "transcendentals_per_step": trans / ev["steps"],
+                           "lanes_holding_a_walk": ev["active_lane_iterations"] / ev["lane_iterations"],
+                           "lanes_evaluating_coefficients": ev["coefficient_lane_iterations"] / ev["lane_iterations"]}
+    out["_means"] = means
+    if label:
+        print(f"bench: {label}: {out['ms_per_pass']:.2f} ms/pass, {out['steps_per_s']:.3e} steps/s"
+              + (f", {out['roofline']['frac']:.3f} of peak" if events else ""), file=sys.stderr, flush=True)
     return out
+
+
+def _strip(d):
+    d.pop("_means", None)
+    return d
+
+
+def max_ball_s(wos, h, P):
+    """Largest s = R sqrt(sigma_bar) of a first ball: the largest distance to the boundary
+    over the query points (FP64 distance queries) times sqrt(sigma_bar)."""
+    d, _ = wos.eval_distance(h, P, precision="fp64")
+    return float(d.max().item()) * math.sqrt(max(h.sigma_bar, 0.0))
+
+
+def compare_variants(wos, torch, WL):
+    """Next flight (Sec. 5.2) against delta tracking (Sec. 5.1), FP32, same walks per point.
+
+    * screened disk (sigma' = sigma in [0.5, 3.5], s < 2 in every ball): both walks have
+      finite variance, so time, distance queries and query points per second at RMSE 1e-2
+      compare directly; the mean difference in combined standard errors shows the bias of
+      the off-centred kernel approximations (supplemental Sec. 1.2).
+    * high-contrast square (sigma' changes sign, s up to about 50): next flight takes far
+      fewer distance queries, but its in-ball series has no finite variance there, so its
+      points per second at RMSE 1e-2 is reported as null with the reason."""
+    out = {}
+    for name, cfg, walks in (("screened_disk", WL.config7(), 1024), ("high_contrast_square", WL.config5(), 256)):
+        prob, pts = cfg["problems"][0], cfg["points"][0]
+        h = wos.Problem(prob)
+        P = torch.as_tensor(pts, dtype=torch.float64, device="cuda")
+        info = h.info()
+        s_max = max_ball_s(wos, h, P)
+        rec = {"query_points": int(P.shape[0]), "walks_per_point": walks, "sigma_bar": info["sigma_bar"],
+               "sigma_prime_range": [info["sigma_prime_min"], info["sigma_prime_max"]], "max_s": s_max}
+        res = {}
+        for vname, variant, rr in (("delta_tracking", 0, name == "high_contrast_square"), ("next_flight", 2, False)):
+            r = measure_walker(wos, torch, [(h, P, wos.Accumulators(P.shape[0]), 0)],
+                               {"precision": "fp32", "variant": variant, "russian_roulette": rr}, walks, 3, prob,
+                               next_flight=variant == 2, label=f"{vname} on the {name}")
+            res[vname] = r.pop("_means")[0]
+            rec[vname] = r
+        valid = info["sigma_prime_min"] >= 0 and s_max < 2.0
+        if not valid:
+            rec["next_flight"]["points_per_s_at_rmse_1e-2"] = None
+            rec["next_flight"]["note"] = (
+                "null: sigma' < 0 somewhere (a throughput factor can exceed one) and s = R sqrt(sigma_bar) reaches "
+                f"{s_max:.3g} > 2, where the second moment of the in-ball series diverges; its sample variance "
+                "does not estimate a finite variance")
+        (m0, s0), (m1, s1) = res["delta_tracking"], res["next_flight"]
+        z = (m1 - m0) / np.sqrt(s0 ** 2 + s1 ** 2)
+        rec["mean_abs_z_next_flight_vs_delta_tracking"] = float(np.nanmean(np.abs(z)))
+        rec["mean_z_next_flight_vs_delta_tracking"] = float(np.nanmean(z))
+        rec["mean_abs_difference"] = float(np.nanmean(np.abs(m1 - m0)))
+        rec["next_flight_valid"] = bool(valid)
+        out[name] = rec
+        del P, h
+    return out
+
+
+def fp32_error(wos, torch, h, P, walks, single_walk_passes=8, russian_roulette=False):
+    """Rounding error of the FP32 walker (Sec. 3.1's estimator, eqs. 17-18) on common random
+    numbers: the FP64 walker drawing the FP32 walker's uniforms (WOS_FP64_FP32_DRAWS) runs
+    the same walks from the same uniforms, so the per-point means differ only by rounding
+    along paths that coincide, plus the walks whose paths part when rounding flips a
+    branch. Reports the RMSE over all points of (FP32 - FP64) and (FP32 compensated - FP64)
+    with its standard error (delta method over the points), and from single-walk passes
+    the fraction of walks whose step counts differ or whose estimates differ by more than
+    1e-4 max(1, |v|)."""
+    n = int(P.shape[0])
+    means = {}
+    for prec in ("fp32", "fp32c", "fp64_fp32draws"):
+        acc = wos.Accumulators(n)
+        plan = wos.Plan([(h, P, acc, 0)], wos.options(precision=prec, walks=walks, seed=0,
+                                                      russian_roulette=russian_roulette))
+        plan.launch(seed=4242)
+        torch.cuda.synchronize()
+        means[prec] = (acc.sum / acc.n_walks.double()).cpu().numpy()
+        plan.close()
+    out = {"workload_points": n, "walks_per_point": walks}
+    for name in ("fp32", "fp32c"):
+        d = means[name] - means["fp64_fp32draws"]
+        d = d[np.isfinite(d)]
+        d2 = d * d
+        msd = float(np.mean(d2))
+        rmse = math.sqrt(msd)
+        se_msd = float(np.std(d2, ddof=1) / math.sqrt(d2.size))
+        out[f"{name}_minus_fp64"] = {"rmse": rmse, "rmse_se": se_msd / (2 * rmse) if rmse > 0 else 0.0,
+                                     "max_abs": float(np.max(np.abs(d))), "median_abs": float(np.median(np.abs(d)))}
+    # walk by walk: single-walk passes of both walkers
+    vals = {}
+    for prec in ("fp32", "fp64_fp32draws"):
+        acc = wos.Accumulators(n)
+        plan = wos.Plan([(h, P, acc, 0)], wos.options(precision=prec, walks=1, seed=0, block_size=256,
+                                                      tile_walks=64, russian_roulette=russian_roulette))
+        v, st = [], []
+        for k in range(single_walk_passes):
+            _zero(acc)
+            plan.launch(seed=4242, walk_offset_add=k)
+            torch.cuda.synchronize()
+            v.append(acc.sum.cpu().numpy().copy())
+            st.append(acc.n_steps.cpu().numpy().copy())
+        plan.close()
+        vals[prec] = (np.concatenate(v), np.concatenate(st))
+    (v32, s32), (v64, s64) = vals["fp32"], vals["fp64_fp32draws"]
+    ok = np.isfinite(v32) & np.isfinite(v64)
+    v32, v64, s32, s64 = v32[ok], v64[ok], s32[ok], s64[ok]
+    steps_differ = s32 != s64
+    value_differ = np.abs(v32 - v64) > 1e-4 * np.maximum(1.0, np.abs(v64))
+    same = ~(steps_differ | value_differ)
+    out["single_walks"] = {
+        "walks": int(v32.size), "diverged_fraction": float(np.mean(~same)),
+        "steps_differ_fraction": float(np.mean(steps_differ)),
+        "rms_difference_of_coinciding_walks": float(np.sqrt(np.mean((v32[same] - v64[same]) ** 2))),
+        "rms_difference_of_diverged_walks": float(np.sqrt(np.mean((v32[~same] - v64[~same]) ** 2)))
+        if np.any(~same) else 0.0}
+    return out
+
+
+def rmse_vs_reference(m, se, ref_mean, ref_se):
+    """Raw RMSE of estimates m (standard errors se) against a reference (ref_mean, ref_se)
+    at the same points, and the part of it that the two Monte Carlo errors do not explain:
+    excess = mean((m - ref)^2) - mean(se^2 + ref_se^2), with its standard error over the
+    points. No clamping: a negative excess means the difference is all noise."""
+    d2 = (np.asarray(m) - np.asarray(ref_mean)) ** 2
+    noise = np.asarray(se) ** 2 + np.asarray(ref_se) ** 2
+    ex = d2 - noise
+    return {"rmse_raw": float(math.sqrt(np.mean(d2))), "rms_noise": float(math.sqrt(np.mean(noise))),
+            "excess_ms": float(np.mean(ex)), "excess_ms_se": float(np.std(ex, ddof=1) / math.sqrt(ex.size)),
+            "points": int(ex.size)}
+
+
+def rmse_sweep(wos, torch, WL, walks_list=(64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384)):
+    """RMSE against the FP64 oracle versus walks per point on the high-contrast square with
+    Russian roulette (Sec. 3.1 eq. 18: RMSE ~ N^-1/2; Sec. 6), for FP32, FP32 with
+    compensated per-walk sums and FP64. Every walker runs all 65,536 points; the walks are
+    added in doublings (walk offsets), so each N's estimate extends the previous one. The
+    reference is the oracle at a seeded sample of the points (tests/golden/sweep_square_rr.npz,
+    written by tests/golden/make_sweep_ref.py from the oracle alone, 32,768 walks per point);
+    the RMSE is taken over the sampled points whose reference standard error is at most
+    2.5e-3, and, split into the part the two Monte Carlo errors explain and the excess,
+    over all sampled points. The pass time of each N (sum of its doublings) gives query
+    points per second."""
+    path = os.path.join(ROOT, "tests", "golden", "sweep_square_rr.npz")
+    if not os.path.exists(path):
+        return None
+    ref = np.load(path, allow_pickle=False)
+    c = WL.config5()
+    prob, pts = c["problems"][0], c["points"][0]
+    h = wos.Problem(prob, sigma_bar=float(ref["sigma_bar"][0]))
+    P = torch.as_tensor(pts, dtype=torch.float64, device="cuda")
+    sel = np.asarray(ref["se"]) <= 2.5e-3
+    idx_all = np.asarray(ref["idx"])
+    idx = idx_all[sel]
+    rmean, rse = np.asarray(ref["mean"])[sel], np.asarray(ref["se"])[sel]
+    idx_t = torch.as_tensor(idx, device="cuda")
+    all_t = torch.as_tensor(idx_all, device="cuda")
+    out = {"workload": "high-contrast unit square, 65,536 points, Russian roulette", "reference_points": int(sel.sum()),
+           "sampled_points": int(sel.size), "reference_walks": int(ref["walks"]),
+           "reference_max_se": float(rse.max()), "walks": list(walks_list), "curves": {}}
+
+    def point_stats(acc, t):
+        sm, sq = acc.sum[t].cpu().numpy(), acc.sum_sq[t].cpu().numpy()
+        nw = acc.n_walks[t].cpu().numpy().astype(np.float64)
+        m = sm / nw
+        return m, np.sqrt(np.maximum(sq / nw - m * m, 0.0) / (nw - 1))
+    for prec in ("fp32", "fp32c", "fp64"):
+        acc = wos.Accumulators(P.shape[0])
+        done, total_ms, curve = 0, 0.0, []
+        for N in walks_list:
+            plan = wos.Plan([(h, P, acc, 0)], wos.options(precision=prec, walks=N - done, seed=0, walk_offset=done,
+                                                          russian_roulette=True))
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            plan.launch(seed=77)
+            b.record()
+            torch.cuda.synchronize()
+            total_ms += a.elapsed_time(b)
+            plan.close()
+            done = N
+            m, se = point_stats(acc, idx_t)
+            r = rmse_vs_reference(m, se, rmean, rse)
+            # the GPU side's own error: mean squared difference minus the reference's variance
+            r["rmse_gpu"] = float(math.sqrt(max(r["rmse_raw"] ** 2 - float(np.mean(rse ** 2)), 0.0)))
+            # all sampled points, whatever their reference error
+            ma, sa = point_stats(acc, all_t)
+            r["all_sampled_points"] = rmse_vs_reference(ma, sa, np.asarray(ref["mean"]), np.asarray(ref["se"]))
+            curve.append({"walks": N, "ms": total_ms, "points_per_s": P.shape[0] / (total_ms / 1e3), **r})
+        # log-log slope of the GPU-side error over the walks where it exceeds twice the
+        # reference's own error
+        xs = [math.log(e["walks"]) for e in curve if e["rmse_gpu"] > 2 * math.sqrt(float(np.mean(rse ** 2)))]
+        ys = [math.log(e["rmse_gpu"]) for e in curve if e["rmse_gpu"] > 2 * math.sqrt(float(np.mean(rse ** 2)))]
+        slope = float(np.polyfit(xs, ys, 1)[0]) if len(xs) >= 3 else None
+        reached = [e for e in curve if e["rmse_raw"] <= 1e-2]
+        out["curves"][prec] = {"points": curve, "loglog_slope": slope,
+                               "walks_to_rmse_1e-2": reached[0]["walks"] if reached else None,
+                               "points_per_s_at_rmse_1e-2": reached[0]["points_per_s"] if reached else None}
+        print(f"bench: sweep {prec}: slope {slope}, rmse at {curve[-1]['walks']} walks {curve[-1]['rmse_raw']:.3e}",
+              file=sys.stderr, flush=True)
+    # common random numbers at 1024 walks: what compensation changes against the FP64 walk
+    out["common_random_numbers_1024"] = fp32_error(wos, torch, h, P, 1024, single_walk_passes=2,
+                                                   russian_roulette=True)
+    return out
+
+
+def host_cpu():
+    """Model name of the host CPU and the threads the oracle may use (the process's CPU
+    share, at most 16)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    return model, min(cores, 16)
 
 
 def main():
@@ -480,22 +764,27 @@ def main():
     from paper_2201_13240_amd import workloads as WL
 
     torch.cuda.set_device(0)
+    if args.tune_cache and os.path.exists(args.tune_cache):
+        print(f"bench: {wos.tune_cache_load(args.tune_cache)} tuned shapes loaded", file=sys.stderr, flush=True)
     c = WL.config2(n_grid=args.grid)
     prob, pts = c["problems"][0], c["points"][0]
     n_pts = pts.shape[0]
+    t0 = time.perf_counter()
     h = wos.Problem(prob)
+    setup = {"star_polygon": {"problem_create_ms": (time.perf_counter() - t0) * 1e3, **h.setup_times()}}
     P = torch.as_tensor(pts, dtype=torch.float64, device="cuda")
 
     def run(precision, steps, warmup, walks):
         acc = wos.Accumulators(n_pts)
         shape = {} if args.shape == "auto" else dict(zip(("block_size", "tile_walks"),
                                                          map(int, args.shape.lower().split("x"))))
+        t0 = time.perf_counter()
         plan = wos.Plan([(h, P, acc, 0)], wos.options(precision=precision, walks=walks, seed=0, **shape))
+        plan_ms = (time.perf_counter() - t0) * 1e3
         for w in range(warmup):
             plan.launch(seed=1000 + w, walk_offset_add=0)
         torch.cuda.synchronize()
-        for t in (acc.sum, acc.sum_sq, acc.n_walks, acc.n_steps, acc.counters):
-            t.zero_()
+        _zero(acc)
         stream = torch.cuda.current_stream()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         torch.cuda.synchronize()
@@ -523,14 +812,17 @@ def main():
         mean, se = wos.finalize(acc)
         torch.cuda.synchronize()
         info = plan.info()
+        st = plan.setup_times()
         plan.close()
         return {"wall_s": wall, "ms": ms, "steps": n_steps, "walks": n_walks,
                 "walker_ms": walker_ms, "walker_steps": timed_steps,
                 "walks_total": int(acc.n_walks.sum().item()),
                 "mean": mean.cpu().numpy(), "se": se.cpu().numpy(),
-                "counters": acc.counters.cpu().numpy().tolist(), "plan": info}
+                "counters": acc.counters.cpu().numpy().tolist(), "plan": info,
+                "setup_ms": {"plan_create": plan_ms, **st}}
 
     r32 = run(args.precision, args.steps, args.warmup, args.walks)
+    setup["star_polygon"]["plan_" + args.precision] = r32["setup_ms"]
 
     # algorithmic work per distance query and lane occupancy from the event-counting
     # walker over one full pass of the same workload (same shape as the timed plan)
@@ -585,34 +877,38 @@ def main():
         out64.update({"fp32c_steps_per_s": r32c["steps"] / (sum(r32c["ms"]) / 1e3),
                       "fp32c_ms_per_step": float(np.mean(r32c["ms"]))})
 
-    # CPU baseline: the FP64 oracle on a bounded sample of the same workload; its
-    # estimates are the reference for the RMSE of the GPU walkers at those points.
+    # rounding error of the FP32 walker against the FP64 walker on common random numbers
+    fp32err = fp32_error(wos, torch, h, P, args.walks) if args.fp32_error else None
+    if fp32err:
+        print("bench: FP32 - FP64 on common random numbers " + json.dumps(fp32err), file=sys.stderr, flush=True)
+
+    # CPU baseline: the FP64 oracle (timing mode: its own BVH for closest points) on a
+    # bounded sample of the same workload; its estimates are also the reference for the
+    # RMSE of the GPU walkers at those points.
     cpu = None
     rmse = {}
     if args.cpu_points > 0:
         from oracle import oracle as O
+        model, threads = host_cpu()
         idx = np.random.default_rng(0).choice(n_pts, args.cpu_points, replace=False)
-        threads = os.cpu_count() or 1
         t0 = time.perf_counter()
-        o = O.solve(prob, pts[idx], args.cpu_walks, h.sigma_bar, seed=77, threads=threads)
+        o = O.solve(prob, pts[idx], args.cpu_walks, h.sigma_bar, seed=77, threads=threads, bvh=True)
         dt = time.perf_counter() - t0
         cpu = {"value": float(o["steps"].sum() / dt), "unit": "walk steps/s", "cores": threads,
-               "kind": "oracle",
+               "kind": "oracle", "cpu_model": model,
                "sample": f"{args.cpu_points} random query points x {args.cpu_walks} walks of the same workload, "
-                         f"{dt:.1f} s"}
+                         f"{dt:.1f} s; FP64 oracle with its own BVH for closest points (timing mode)"}
         # the same oracle on one thread, over a twelfth of the points
         n1 = max(1, args.cpu_points // 12)
         t0 = time.perf_counter()
-        o1 = O.solve(prob, pts[idx[:n1]], args.cpu_walks, h.sigma_bar, seed=78, threads=1)
+        o1 = O.solve(prob, pts[idx[:n1]], args.cpu_walks, h.sigma_bar, seed=78, threads=1, bvh=True)
         dt1 = time.perf_counter() - t0
         cpu["single_thread"] = {"value": float(o1["steps"].sum() / dt1), "cores": 1,
                                 "sample": f"{n1} of those points x {args.cpu_walks} walks, {dt1:.1f} s"}
         for name, r in (("fp32", r32), ("fp32c", r32c), ("fp64", r64)):
             if r is None:
                 continue
-            d2 = (r["mean"][idx] - o["mean"]) ** 2 - o["se"] ** 2
-            rmse[name] = {"rmse_vs_oracle": float(math.sqrt(max(np.mean(d2), 0.0))),
-                          "mean_se_gpu": float(np.mean(r["se"][idx])), "mean_se_oracle": float(np.mean(o["se"]))}
+            rmse[name] = rmse_vs_reference(r["mean"][idx], r["se"][idx], o["mean"], o["se"])
 
     # time to RMSE 1e-2, walks doubled from 64: on this workload against the oracle's
     # sample, and on the manufactured disk against its exact solution u = e^x cos y
@@ -654,14 +950,20 @@ def main():
         "counters": r32["counters"],
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "rmse": rmse,
+        "fp32_error_vs_fp64": fp32err,
+        "rmse_vs_oracle_sample": rmse,
         "time_to_rmse_1e-2": ttr,
     }
     line.update(out64)
     if args.variants:
-        line["next_flight_vs_delta_tracking"] = compare_variants(wos, WL, args)
+        line["next_flight_vs_delta_tracking"] = compare_variants(wos, torch, WL)
+    if args.sweep:
+        line["rmse_sweep_high_contrast_square"] = rmse_sweep(wos, torch, WL)
     if args.extras:
-        line["extras"] = measure_extras(wos, WL)
+        line["extras"] = measure_extras(wos, torch, WL, setup)
+    line["setup_ms"] = setup
+    if args.tune_cache:
+        wos.tune_cache_save(args.tune_cache)
     print(json.dumps(line), flush=True)
 
 

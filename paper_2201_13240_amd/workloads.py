@@ -505,4 +505,23 @@ def config5(n_grid=256):
     return {"name": "high-contrast-square", "problems": [prob], "points": [pts], "walks": 64}
 
 
+def config7(n_grid=256):
+    """Unit disk; alpha = 1, omega = 0, sigma = 2 + 1.5 (16 random Fourier modes) in
+    [0.5, 3.5], so that sigma' = sigma >= 0 and every ball has s = R sqrt(sigma_bar) < 2;
+    f, g = 8 bumps; n_grid^2 cell-centred points on [-1, 1]^2 inside. The regime in which
+    the next-flight walk (Sec. 5.2) has finite variance."""
+    rng = np.random.default_rng(7000)
+    geometry = geom_ball([0.0, 0.0], 1.0)
+    k3, a3, phi3 = random_fourier(rng, 16, 2, 1.0)
+    sigma = field_fourier(k3, a3, phi3, transform="affine", c0=2.0, c1=1.5)
+    c, w, am = random_bumps(rng, 8, [-1, -1], [1, 1], (0.05, 0.3), (-10.0, 10.0))
+    source = field_bumps(c, w, am)
+    c, w, am = random_bumps(rng, 8, [-1, -1], [1, 1], (0.1, 0.5), (-1.0, 1.0))
+    boundary = field_bumps(c, w, am)
+    prob = make_problem(2, geometry, field_const(1.0), field_const(0.0), sigma, source, boundary, 1e-3)
+    pts = grid_points(n_grid, -1.0, 1.0)
+    pts = pts[inside_mask(geometry, pts)]
+    return {"name": "screened-disk", "problems": [prob], "points": [pts], "walks": 256}
+
+
 CONFIG_BUILDERS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
