@@ -647,17 +647,20 @@ def rmse_vs_reference(m, se, ref_mean, ref_se):
             "points": int(ex.size)}
 
 
-def rmse_sweep(wos, torch, WL, walks_list=(64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384)):
+def rmse_sweep(wos, torch, WL, walks_list=(64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384), replicates=32):
     """RMSE against the FP64 oracle versus walks per point on the high-contrast square with
     Russian roulette (Sec. 3.1 eq. 18: RMSE ~ N^-1/2; Sec. 6), for FP32, FP32 with
-    compensated per-walk sums and FP64. Every walker runs all 65,536 points; the walks are
-    added in doublings (walk offsets), so each N's estimate extends the previous one. The
-    reference is the oracle at a seeded sample of the points (tests/golden/sweep_square_rr.npz,
-    written by tests/golden/make_sweep_ref.py from the oracle alone, 32,768 walks per point);
-    the RMSE is taken over the sampled points whose reference standard error is at most
-    2.5e-3, and, split into the part the two Monte Carlo errors explain and the excess,
-    over all sampled points. The pass time of each N (sum of its doublings) gives query
-    points per second."""
+    compensated per-walk sums and FP64. The reference is the oracle at a seeded sample of
+    48 points (tests/golden/sweep_square_rr.npz, written by tests/golden/make_sweep_ref.py
+    from the oracle alone, 32,768 walks per point); the curve is taken over the sampled
+    points whose reference standard error is at most 2.5e-3, and, split into the part the
+    two Monte Carlo errors explain and the excess, over all 48. Single walks are heavy-tailed
+    there (null-collision weights above one where sigma' < 0), so each N is run as
+    `replicates` independent estimates (items of one plan with their own Philox streams,
+    walks added in doublings) and the mean squared error is their average:
+    MSE(N) = mean over replicates and points of (m - ref)^2 - mean(ref_se^2); beside it the
+    median over replicates, which a rare heavy walk does not move. Query points per second
+    come from a full pass over all 65,536 points at 1024 walks."""
     path = os.path.join(ROOT, "tests", "golden", "sweep_square_rr.npz")
     if not os.path.exists(path):
         return None
@@ -665,57 +668,61 @@ def rmse_sweep(wos, torch, WL, walks_list=(64, 128, 256, 512, 1024, 2048, 4096, 
     c = WL.config5()
     prob, pts = c["problems"][0], c["points"][0]
     h = wos.Problem(prob, sigma_bar=float(ref["sigma_bar"][0]))
-    P = torch.as_tensor(pts, dtype=torch.float64, device="cuda")
-    sel = np.asarray(ref["se"]) <= 2.5e-3
     idx_all = np.asarray(ref["idx"])
-    idx = idx_all[sel]
-    rmean, rse = np.asarray(ref["mean"])[sel], np.asarray(ref["se"])[sel]
-    idx_t = torch.as_tensor(idx, device="cuda")
-    all_t = torch.as_tensor(idx_all, device="cuda")
-    out = {"workload": "high-contrast unit square, 65,536 points, Russian roulette", "reference_points": int(sel.sum()),
-           "sampled_points": int(sel.size), "reference_walks": int(ref["walks"]),
-           "reference_max_se": float(rse.max()), "walks": list(walks_list), "curves": {}}
-
-    def point_stats(acc, t):
-        sm, sq = acc.sum[t].cpu().numpy(), acc.sum_sq[t].cpu().numpy()
-        nw = acc.n_walks[t].cpu().numpy().astype(np.float64)
-        m = sm / nw
-        return m, np.sqrt(np.maximum(sq / nw - m * m, 0.0) / (nw - 1))
+    sel = np.asarray(ref["se"]) <= 2.5e-3
+    rmean_all, rse_all = np.asarray(ref["mean"]), np.asarray(ref["se"])
+    Psel = torch.as_tensor(pts[idx_all], dtype=torch.float64, device="cuda")
+    Pall = torch.as_tensor(pts, dtype=torch.float64, device="cuda")
+    out = {"workload": "high-contrast unit square, 65,536 points, Russian roulette",
+           "reference_points": int(sel.sum()), "sampled_points": int(sel.size),
+           "reference_walks": int(ref["walks"]), "reference_max_se": float(rse_all[sel].max()),
+           "replicates": replicates, "walks": list(walks_list), "curves": {}}
+    ref_var_sel = float(np.mean(rse_all[sel] ** 2))
     for prec in ("fp32", "fp32c", "fp64"):
-        acc = wos.Accumulators(P.shape[0])
-        done, total_ms, curve = 0, 0.0, []
+        # time per walk and point over the whole grid
+        r = measure_walker(wos, torch, [(h, Pall, wos.Accumulators(Pall.shape[0]), 0)],
+                           {"precision": prec, "russian_roulette": True}, 1024, 1, prob, events=False)
+        t_walk = (r["ms_per_pass"] / 1e3) / 1024
+        entries = [(h, Psel, wos.Accumulators(Psel.shape[0]), k) for k in range(replicates)]
+        done, curve = 0, []
         for N in walks_list:
-            plan = wos.Plan([(h, P, acc, 0)], wos.options(precision=prec, walks=N - done, seed=0, walk_offset=done,
-                                                          russian_roulette=True))
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
+            plan = wos.Plan(entries, wos.options(precision=prec, walks=N - done, seed=0, walk_offset=done,
+                                                 russian_roulette=True))
             plan.launch(seed=77)
-            b.record()
             torch.cuda.synchronize()
-            total_ms += a.elapsed_time(b)
             plan.close()
             done = N
-            m, se = point_stats(acc, idx_t)
-            r = rmse_vs_reference(m, se, rmean, rse)
-            # the GPU side's own error: mean squared difference minus the reference's variance
-            r["rmse_gpu"] = float(math.sqrt(max(r["rmse_raw"] ** 2 - float(np.mean(rse ** 2)), 0.0)))
-            # all sampled points, whatever their reference error
-            ma, sa = point_stats(acc, all_t)
-            r["all_sampled_points"] = rmse_vs_reference(ma, sa, np.asarray(ref["mean"]), np.asarray(ref["se"]))
-            curve.append({"walks": N, "ms": total_ms, "points_per_s": P.shape[0] / (total_ms / 1e3), **r})
-        # log-log slope of the GPU-side error over the walks where it exceeds twice the
-        # reference's own error
-        xs = [math.log(e["walks"]) for e in curve if e["rmse_gpu"] > 2 * math.sqrt(float(np.mean(rse ** 2)))]
-        ys = [math.log(e["rmse_gpu"]) for e in curve if e["rmse_gpu"] > 2 * math.sqrt(float(np.mean(rse ** 2)))]
-        slope = float(np.polyfit(xs, ys, 1)[0]) if len(xs) >= 3 else None
-        reached = [e for e in curve if e["rmse_raw"] <= 1e-2]
-        out["curves"][prec] = {"points": curve, "loglog_slope": slope,
+            m = np.stack([(acc.sum / acc.n_walks.double()).cpu().numpy() for _, _, acc, _ in entries])
+            d2 = (m - rmean_all[None, :]) ** 2                        # [replicate][point]
+            mse_r = d2[:, sel].mean(1) - ref_var_sel
+            mse = float(mse_r.mean())
+            mse_se = float(mse_r.std(ddof=1) / math.sqrt(replicates))
+            all_r = d2.mean(1) - float(np.mean(rse_all ** 2))
+            # the median over replicates, which one rare heavy walk does not move
+            med = float(np.median(mse_r))
+            curve.append({"walks": N, "rmse": math.sqrt(max(mse, 0.0)), "mse": mse, "mse_se": mse_se,
+                          "rmse_median_replicate": math.sqrt(max(med, 0.0)),
+                          "rmse_all_sampled": math.sqrt(max(float(all_r.mean()), 0.0)),
+                          "mse_all_sampled_se": float(all_r.std(ddof=1) / math.sqrt(replicates)),
+                          "points_per_s": Pall.shape[0] / (N * t_walk)})
+        ok = [e for e in curve if e["mse"] > 2 * e["mse_se"]]
+        slope = (float(np.polyfit([math.log(e["walks"]) for e in ok], [0.5 * math.log(e["mse"]) for e in ok], 1)[0])
+                 if len(ok) >= 3 else None)
+        okm = [e for e in curve if e["rmse_median_replicate"] > 0]
+        slope_med = (float(np.polyfit([math.log(e["walks"]) for e in okm],
+                                      [math.log(e["rmse_median_replicate"]) for e in okm], 1)[0])
+                     if len(okm) >= 3 else None)
+        reached = [e for e in curve if e["rmse"] <= 1e-2]
+        out["curves"][prec] = {"points": curve, "loglog_slope": slope, "loglog_slope_median_replicate": slope_med,
+                               "seconds_per_walk_and_point": t_walk,
                                "walks_to_rmse_1e-2": reached[0]["walks"] if reached else None,
                                "points_per_s_at_rmse_1e-2": reached[0]["points_per_s"] if reached else None}
-        print(f"bench: sweep {prec}: slope {slope}, rmse at {curve[-1]['walks']} walks {curve[-1]['rmse_raw']:.3e}",
-              file=sys.stderr, flush=True)
-    # common random numbers at 1024 walks: what compensation changes against the FP64 walk
-    out["common_random_numbers_1024"] = fp32_error(wos, torch, h, P, 1024, single_walk_passes=2,
+        print(f"bench: sweep {prec}: slope {slope} (median replicate {slope_med}), "
+              f"rmse at {curve[0]['walks']} walks {curve[0]['rmse']:.3e}, "
+              f"at {curve[-1]['walks']} walks {curve[-1]['rmse']:.3e}", file=sys.stderr, flush=True)
+    # common random numbers at 1024 walks over all points: what compensation changes
+    # against the FP64 walk
+    out["common_random_numbers_1024"] = fp32_error(wos, torch, h, Pall, 1024, single_walk_passes=2,
                                                    russian_roulette=True)
     return out
 

@@ -344,8 +344,9 @@ wos_status wos_plan_info(const wos_plan* plan, int32_t* block_size, int32_t* til
                          int32_t* grid_size, int32_t* n_launches);
 /* Set-up time of wos_plan_create in milliseconds of host wall clock: build_ms for the
  * tables, scratch, classification, gamma(x0) and graph capture of the final plan, tune_ms
- * for the autotuning runs (0 when the shape was given or already tuned); tuned_here = 1
- * when this plan ran the autotuner. Any output may be null. */
+ * for the autotuning runs (0 when the shape was given, already tuned, or the job has too
+ * few walks to time); tuned_here = 1 when this plan ran the autotuner. Any output may be
+ * null. */
 wos_status wos_plan_setup_times(const wos_plan* plan, double* build_ms, double* tune_ms, int32_t* tuned_here);
 wos_status wos_plan_destroy(wos_plan* plan);
 

@@ -1478,11 +1478,12 @@ wos_status time_shape(wos_plan* P, unsigned block, uint32_t tile, uint64_t walks
 // the plan's own walks (about eight walks per resident lane, so that every wave takes
 // several tiles; each item contributes in proportion to its walks), and caches the
 // winner per process. Jobs too small to time leave the defaults.
-wos_status autotune(wos_plan* P, hipStream_t st, unsigned* block, uint32_t* tile) {
+wos_status autotune(wos_plan* P, hipStream_t st, unsigned* block, uint32_t* tile, bool* ran) {
   static const unsigned kBlocks[] = {64, 128, 256};
   static const uint32_t kTiles[] = {64, 128, 256, 512, 1024};
   *block = P->s.block;
   *tile = P->s.tile_walks;
+  *ran = false;
   uint64_t launch0 = 0;
   for (const DevItem& d : P->dit[0]) launch0 += (uint64_t)d.n_points * d.walks;
   uint64_t lanes = 0;
@@ -1529,6 +1530,7 @@ wos_status autotune(wos_plan* P, hipStream_t st, unsigned* block, uint32_t* tile
   if (r != WOS_OK) return r;
   std::lock_guard<std::mutex> lk(g_occ_mutex);
   g_tuned[tune_key(P->s)] = std::make_pair(*block, *tile);
+  *ran = true;
   return WOS_OK;
 }
 
@@ -1562,16 +1564,17 @@ static wos_status plan_create_impl(const wos_batch_item* items, int32_t n_items,
   if (tuned) return WOS_OK;
   unsigned block = 0;
   uint32_t tile = 0;
+  bool ran = false;
   t0 = clock::now();
-  if ((r = autotune(P, (hipStream_t)stream, &block, &tile)) != WOS_OK) {
+  if ((r = autotune(P, (hipStream_t)stream, &block, &tile, &ran)) != WOS_OK) {
     wos_plan_destroy(P);
     *out = nullptr;
     return r;
   }
   const double tune_ms = ms_since(t0);
   if (block == P->s.block && tile == P->s.tile_walks) {
-    P->tune_ms = tune_ms;
-    P->tuned_here = 1;
+    P->tune_ms = ran ? tune_ms : 0.0;
+    P->tuned_here = ran ? 1 : 0;
     return WOS_OK;
   }
   // rebuild with the tuned shape (tile tables and workspace depend on it)
@@ -1585,7 +1588,7 @@ static wos_status plan_create_impl(const wos_batch_item* items, int32_t n_items,
   if (r == WOS_OK) {
     (*out)->build_ms = ms_since(t0);
     (*out)->tune_ms = tune_ms;
-    (*out)->tuned_here = 1;
+    (*out)->tuned_here = ran ? 1 : 0;
   }
   return r;
 }

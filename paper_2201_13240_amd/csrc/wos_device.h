@@ -206,6 +206,7 @@ __device__ __forceinline__ T chebyshev(const double* c, int n, T t) {
 
 template <typename T> struct BesselTerms;
 template <> struct BesselTerms<float> {
+  static constexpr int kI0Wide = WOS_I0E_WIDE_TAIL_N32, kK0Wide = WOS_K0E_WIDE_TAIL_N32;
   static constexpr int kSeries = 9, kI0Mid = WOS_I0E_MID_N32, kI0Tail = WOS_I0E_TAIL_N32,
                        kK0Low = WOS_K0E_LOW_N32, kK0Mid = WOS_K0E_MID_N32, kK0Tail = WOS_K0E_TAIL_N32,
                        kI1Mid = WOS_I1E_MID_N32, kI1Tail = WOS_I1E_TAIL_N32, kK1Low = WOS_K1E_LOW_N32,
@@ -264,12 +265,23 @@ __device__ T bessel_k0e(T x) {
 // I0 and K0 at x > 0 for the 2D ball terms and radius proposals, in one function so that
 // lanes of a wavefront whose arguments fall in different ranges still share its two code
 // paths: below 2 the series gives *a = I0 - 1 and *k = K0 (returns false); from 2 on the
-// Chebyshev fits give *a = e^-x I0 and *k = e^x K0 (returns true).
+// Chebyshev fits give *a = e^-x I0 and *k = e^x K0 (returns true). In FP32 each function
+// has a single fit from 2 on (in t = 4/x - 1, of sqrt(x) e^-x I0 and sqrt(x) e^x K0), so
+// every lane with x >= 2 runs the same two polynomials; FP64 keeps the narrower ranges,
+// whose fits reach double precision with fewer terms.
 template <typename T>
 __device__ __forceinline__ bool bessel_i0k0(T x, T* a, T* k) {
   if (x < (T)2) {
     bessel_series<T>(x, a, k);
     return false;
+  }
+  if constexpr (sizeof(T) == 4) {
+    const T rx = m_rcp(x);
+    const T t = m_fma((T)4, rx, (T)-1);
+    const T rs = __builtin_amdgcn_rsqf(x);
+    *a = chebyshev<T>(WOS_I0E_WIDE_TAIL, BesselTerms<T>::kI0Wide, t) * rs;
+    *k = chebyshev<T>(WOS_K0E_WIDE_TAIL, BesselTerms<T>::kK0Wide, t) * rs;
+    return true;
   }
   if (x <= (T)8) {
     *a = chebyshev<T>(WOS_I0E_MID, BesselTerms<T>::kI0Mid, (x - (T)5) * (T)(1.0 / 3.0));
@@ -795,13 +807,16 @@ __device__ __forceinline__ void spectral_terms(const WOS_GLOBAL T* row, T er, T 
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
     const T cr = row[s * 2 * kSpecRow + 2 * j], ci = row[s * 2 * kSpecRow + 2 * j + 1];
-    const T re = m_fma(cr, er, -ci * ei);
-    out[s].v += re;
     if (D && s < ND) {
+      const T re = m_fma(cr, er, -ci * ei);
       const T im = m_fma(cr, ei, ci * er);
+      out[s].v += re;
       out[s].g[0] = m_fma(-im, fx, out[s].g[0]);
       out[s].g[1] = m_fma(-im, fy, out[s].g[1]);
       out[s].lap = m_fma(-re, f2, out[s].lap);
+    } else {
+      // a value-only slot accumulates Re(c e) = cr er - ci ei in two fused steps
+      out[s].v = m_fma(cr, er, m_fma(-ci, ei, out[s].v));
     }
   }
 }

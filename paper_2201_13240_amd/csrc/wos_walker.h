@@ -391,7 +391,7 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
   T nf_T = 0, nf_S = 0, nf_beta = 1, nf_R = 0, nf_c = 0;
   // delta tracking: the current ball while its radius is being drawn (pending: the last
   // proposal was rejected and the lane retries at the next iteration)
-  T bR = 0, bs = 0, bv[DIM];
+  T bR = 0, bs = 0;
   Ball<T, DIM> bb;
   bb.pb = 0;
   bb.gnorm = 0;
@@ -693,15 +693,15 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
                 if (!gx_known) ++ev[EV_GAMMA];
               }
             } else {
-              // a new ball: its normalisation and the direction of y; the radius is drawn
-              // below, one proposal per iteration
+              // a new ball and its normalisation; the radius is drawn below, one proposal
+              // per iteration, and the direction of y once a radius is accepted (it is
+              // independent of the radius, so no direction is kept across retries)
               bR = d;
               bs = d * P.sqrt_sigma_bar;
               bb = ball_terms<T, DIM>(d, bs, P.inv_sigma_bar, !(P.sigma_bar > (T)0));
               if constexpr (COUNT) {
                 if (bs >= (DIM == 2 ? (T)2 : (T)1)) ++ev[EV_BALL_LARGE_S];
               }
-              uniform_direction<T, DIM, SL::kDir>(rng, bv);
               pending = true;
               ntry = 0;
             }
@@ -711,6 +711,8 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
           ++ntrials;
           const T t = radius_trial<T, DIM, SL::kTrial, COUNT>(rng, bs, bb, !(P.sigma_bar > (T)0), &tally);
           if (t >= (T)0) {
+            T bv[DIM];
+            uniform_direction<T, DIM, SL::kDir>(rng, bv);
   #pragma unroll
             for (int i = 0; i < DIM; ++i) q[i] = m_fma(t * bR, bv[i], x[i]);
             sampled = true;
@@ -759,7 +761,10 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
           const bool volume = mu <= b.pb;
           const T src = Pi * m_exp(cq.gamma - gamma0) * cq.f_over_alpha;
           T term = 0;
-          if (a.variant == 0) term = b.gnorm * src;
+          // |G| = P_B / sigma_bar (R^2 / 2n when sigma_bar = 0) is formed here rather than
+          // kept from the ball's first iteration, which saves a register across retries
+          const T gnorm = P.sigma_bar > (T)0 ? b.pb * P.inv_sigma_bar : R * R * (T)(DIM == 2 ? 0.25 : 1.0 / 6.0);
+          if (a.variant == 0) term = gnorm * src;
           else if (volume) term = src * P.inv_sigma_bar;
           add_estimate(A, Ac, term, a.compensated);
           if constexpr (COUNT) ++ev[volume ? EV_VOLUME : EV_EXIT];
@@ -818,17 +823,19 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
                 done = true;
                 flag = kFlagRR;
               }
-            } else if (EXTRA && a.ww_hi > (T)0 && m_fabs(W) > a.ww_hi && (split_state >> 8) < kMaxBranches) {
+            } else if (EXTRA && a.ww_hi > (T)0 && m_fabs(W) > a.ww_hi && (split_state >> 8) < kMaxBranches &&
+                       (split_state & 0xFFu) < (uint32_t)kSplitDepth) {
               // high side: expected-value splitting into N branches of weight W/m,
               // m = |W|/w+, N = floor(m) with probability floor(m) + 1 - m, else
-              // floor(m) + 1; N - 1 siblings wait on the lane's stack
+              // floor(m) + 1 (E[N] = m); N - 1 siblings wait on the lane's stack. The
+              // decision is taken only when the stack has room: every outcome, N = 1
+              // included, takes the weight W/m, so a walk whose stack is full must skip the
+              // split altogether and go on at weight W (unbiased either way)
               const T m = m_fabs(W) / a.ww_hi;
               const T fl = floor(m);
               const uint32_t N = uniform01<T, SL::kRoulette>(rng) <= fl + (T)1 - m ? (uint32_t)fl : (uint32_t)fl + 1u;
-              if (N <= 1u) {
-                Pi /= m;
-              } else if ((split_state & 0xFFu) < (uint32_t)kSplitDepth) {
-                Pi /= m;
+              Pi /= m;
+              if (N > 1u) {
                 SplitEntry<T, DIM>& se = split_stack[split_state & 0xFFu];
                 ++split_state;
 #pragma unroll
@@ -838,7 +845,6 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
                 se.last_prim = last_prim;
                 se.remaining = N - 1u;
               }
-              // a full stack leaves the walk unsplit (still unbiased)
             }
           }
         }

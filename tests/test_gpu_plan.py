@@ -19,8 +19,10 @@ def W():
 
 
 def _plan(W, h, P, **kw):
+    # 1024 walks per point on the 64^2 disk grid: more walks than the autotuner's sample
+    # (eight per resident lane), so that the plan tunes its variant if no earlier plan did
     acc = W.Accumulators(P.shape[0])
-    return W.Plan([(h, P, acc, 0)], W.options(precision="fp32", walks=256, seed=3, **kw)), acc
+    return W.Plan([(h, P, acc, 0)], W.options(precision="fp32", walks=1024, seed=3, **kw)), acc
 
 
 def test_problem_setup_times(W):
