@@ -193,7 +193,8 @@ def algorithmic_work(events, prob, next_flight=False):
 # the same counters read for a copy of known size (the calibration factors) and a hash of
 # the device sources the counters were taken with. A changed kernel makes them stale:
 # traffic is then reported as null.
-DEVICE_SOURCES = ("wos_kernels.hip", "wos_device.h", "wos_types.h", "bessel_tables.h")
+DEVICE_SOURCES = ("wos_walker.h", "wos_walker_f32_2d.hip", "wos_walker_f64_2d.hip", "wos_kernels.hip", "wos_device.h",
+                  "wos_types.h", "bessel_tables.h")
 
 
 def device_source_hash():
