@@ -44,9 +44,10 @@
 //       ends at x - f grad f.
 //
 // Pins (tests/test_oracle_*.py): every function here is checked against closed forms,
-// quadrature, library routines or brute force. Parity unpinned: whole-walk estimates on
-// random coefficient fields (star polygons, the perturbed icosphere, the high-contrast
-// square) have no closed form and rest on the component pins only; the next-flight walk
+// quadrature, library routines or brute force. Whole-walk estimates on random coefficient
+// fields (the star polygons, the perturbed icosphere, the high-contrast square's field
+// families) are pinned by running the same fields with the data of a manufactured
+// solution (f from eq. 1, g = u) against u itself. Parity unpinned: the next-flight walk
 // with the approximate off-centred kernels (walk_next_flight, variant 2) is exact only
 // where those kernels are (the centre, the harmonic case, sigma' = sigma_bar), elsewhere
 // pinned through the exact-kernel variant 3 and the kernels' own pins.

@@ -524,4 +524,17 @@ def config7(n_grid=256):
     return {"name": "screened-disk", "problems": [prob], "points": [pts], "walks": 256}
 
 
+def manufactured(prob, u="expcos", epsilon=1e-4):
+    """The same geometry and coefficient fields (alpha, drift potential, sigma) with the
+    source and boundary data of a manufactured solution u (eq. 1 gives f from u and the
+    problem's own alpha, psi and sigma; g = u), so that the solution is known exactly on a
+    workload of any shape. The epsilon shell is narrowed (1e-4) so that its O(epsilon)
+    bias stays far below the Monte Carlo error of long runs."""
+    q = dict(prob)
+    q["source"] = field_manufactured(u)
+    q["boundary"] = field_manufactured(u)
+    q["epsilon"] = epsilon
+    return q
+
+
 CONFIG_BUILDERS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}

@@ -143,3 +143,64 @@ def test_power_scaled_source_and_boundary_is_rejected(W):
     print(f"power: delta = {delta:.4f}, mean z = {st['mean']:.3f} (bound {st['thresholds']['mean']:.3f})")
     assert not ok, f"scale 1 + {delta:.4f} accepted: {st}"
     # and the unscaled run of the same shape is accepted (test_star_polygon_full)
+
+
+# ---------------------------------------------------------------- manufactured variants
+# The same workloads at their full sizes, with their own geometry and coefficient fields
+# but the source and boundary data of u = e^x cos y (f from eq. 1 with each workload's
+# alpha, drift and sigma): the GPU must reproduce u itself, not only the oracle's
+# estimate. Compared by batch means at interior points at least 0.05 from the boundary
+# (the epsilon shell is 1e-4). The high-contrast square enters through its field
+# families at a contrast with sigma' >= 0 (tests/test_oracle_manufactured.py says why).
+
+def u_expcos(p):
+    return np.exp(p[:, 0]) * np.cos(p[:, 1])
+
+
+def interior_sample(prob, pts, n, seed, margin=0.05):
+    """n distinct random indices of points at least `margin` from the boundary."""
+    from oracle import oracle as O
+    cand = np.random.default_rng(seed).choice(pts.shape[0], min(pts.shape[0], 20 * n), replace=False)
+    d, _ = O.distance(prob, np.ascontiguousarray(pts[cand]), bvh=True)
+    ok = cand[d >= margin]
+    assert ok.size >= n
+    return np.sort(ok[:n])
+
+
+def manufactured_case(name):
+    from tests.test_oracle_manufactured import square_tanh_layer
+    if name == "star256":
+        c = WL.config2()
+        return WL.manufactured(c["problems"][0]), c["points"][0], c["walks"], 256
+    if name == "ico20480":
+        c = WL.config3()
+        return WL.manufactured(c["problems"][0]), c["points"][0], c["walks"], 128
+    prob = square_tanh_layer()
+    return WL.manufactured(prob), WL.grid_points(256, 0.0, 1.0), 256, 128
+
+
+@pytest.mark.parametrize("name,precision", [("star256", "fp32"), ("star256", "fp64"), ("ico20480", "fp32"),
+                                            ("square_tanh_layer", "fp32")])
+def test_manufactured_full(W, name, precision):
+    prob, pts, walks, n = manufactured_case(name)
+    h = W.Problem(prob)
+    idx = interior_sample(prob, pts, n, seed=61)
+    g, cnt, info = plan_batches(W, [h], [pts], [(0, int(i)) for i in idx], walks, precision, 16)
+    assert cnt[0] == 0 and cnt[1] == 0, cnt
+    assert info["launches"] == 1
+    PR.assert_parity_batches_exact(g, u_expcos(pts[idx]), f"{name} manufactured full {precision}", tol(precision))
+
+
+def test_manufactured_batch_of_64_polygons_full(W):
+    c = WL.config4()
+    probs = [WL.manufactured(p) for p in c["problems"]]
+    handles = [W.Problem(p) for p in probs]
+    sample, exact = [], []
+    for k, (p, q) in enumerate(zip(probs, c["points"])):
+        idx = interior_sample(p, q, 4, seed=70 + k)
+        sample += [(k, int(i)) for i in idx]
+        exact.append(u_expcos(q[idx]))
+    g, cnt, info = plan_batches(W, handles, c["points"], sample, 512, "fp32", 16)
+    assert cnt[0] == 0 and cnt[1] == 0, cnt
+    assert info["launches"] == 1, info
+    PR.assert_parity_batches_exact(g, np.concatenate(exact), "64-polygon batch manufactured full fp32", tol("fp32"))
