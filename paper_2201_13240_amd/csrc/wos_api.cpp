@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <limits>
@@ -487,14 +488,42 @@ size_t layout_problem(Blob& blob, const wos_problem_desc& d, const HostGeometry&
         c[0] = gc;
         P.spectral = eligible | 1 | 2 | kSpecGammaMerged;
       }
+      // product form: Re(C e^{i(A + B)}) = cr cA cB - cr sA sB - ci sA cB - ci cA sB with
+      // A = 2 pi kx x, B = 2 pi ky y; cos(ky y) and sin(ky y) are the basis functions of
+      // |ky| (the sine with the sign of ky). Basis index: 0 for the constant, 2n - 1 for
+      // cos(2 pi n .), 2n for sin(2 pi n .).
+      const double two_pi = 6.283185307179586476925286766559;
       for (int sidx = 0; sidx < 3; ++sidx) {
         if (!(P.spectral & (1 << sidx))) continue;
+        double M[kSpecRow][kSpecRow] = {};
+        M[0][0] = c[sidx];
         for (int kx = 0; kx <= kSpecK; ++kx)
           for (int j = 0; j < kSpecRow; ++j) {
-            P.spec.row[kx][sidx][2 * j] = (T)re[sidx][kx][j];
-            P.spec.row[kx][sidx][2 * j + 1] = (T)im[sidx][kx][j];
+            const double cr = re[sidx][kx][j], ci = im[sidx][kx][j];
+            if (cr == 0.0 && ci == 0.0) continue;
+            const int ky = j - kSpecK, ay = std::abs(ky);
+            const double sg = ky < 0 ? -1.0 : 1.0;
+            const int ac = kx ? 2 * kx - 1 : 0, as = 2 * kx, bc = ay ? 2 * ay - 1 : 0, bs = 2 * ay;
+            M[ac][bc] += cr;
+            if (kx && ay) M[as][bs] -= cr * sg;
+            if (kx) M[as][bc] -= ci;
+            if (ay) M[ac][bs] -= ci * sg;
           }
-        P.spec.c[sidx] = (T)c[sidx];
+        for (int a = 0; a < kSpecRow; ++a) {
+          double My[kSpecRow] = {}, Myy[kSpecRow] = {};
+          for (int n = 1; n <= kSpecK; ++n) {
+            const double w = two_pi * n;
+            My[2 * n] = -w * M[a][2 * n - 1];      // d/dy cos = -w sin
+            My[2 * n - 1] = w * M[a][2 * n];       // d/dy sin = w cos
+            Myy[2 * n - 1] = -w * w * M[a][2 * n - 1];
+            Myy[2 * n] = -w * w * M[a][2 * n];
+          }
+          for (int b = 0; b < kSpecRow; ++b) {
+            P.spec.m[a][sidx][0][b] = (T)M[a][b];
+            P.spec.m[a][sidx][1][b] = (T)My[b];
+            P.spec.m[a][sidx][2][b] = (T)Myy[b];
+          }
+        }
       }
     }
   }

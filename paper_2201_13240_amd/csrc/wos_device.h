@@ -798,78 +798,85 @@ __device__ __forceinline__ FV<T, DIM> field_base(G<DevField<T>>& f, const T* x) 
 }
 
 // Bases of the Fourier fields of a 2D problem from the dense table (slots 0, 1, 2), with
-// gradient and Laplacian for the first ND slots when D is true. e^{2 pi i k.x} comes from
-// the powers of e^{2 pi i x} and e^{2 pi i y} (two sincos calls per point instead of one
-// per mode and field).
-template <typename T, bool D, int ND>
-__device__ __forceinline__ void spectral_terms(const WOS_GLOBAL T* row, T er, T ei, T fx, T fy, T f2,
-                                               FV<T, 2>* out, int j) {
+// gradient and Laplacian for the first ND slots when D is true. The table is in product
+// form, B = sum_a psi_a(x) (M phi(y))_a: for each row a one dot product with the seven y
+// basis functions per slot (and per derivative in y), then one multiply-add with psi_a;
+// the x derivatives come from the same row sums with the derivatives of psi_a. Only two
+// sincos calls per point; the rest are fused multiply-adds on wave-uniform coefficients.
+template <typename T>
+__device__ __forceinline__ T spectral_dot(const WOS_GLOBAL T* r, const T* phi) {
+  T v = r[0];
 #pragma unroll
-  for (int s = 0; s < 3; ++s) {
-    const T cr = row[s * 2 * kSpecRow + 2 * j], ci = row[s * 2 * kSpecRow + 2 * j + 1];
-    if (D && s < ND) {
-      const T re = m_fma(cr, er, -ci * ei);
-      const T im = m_fma(cr, ei, ci * er);
-      out[s].v += re;
-      out[s].g[0] = m_fma(-im, fx, out[s].g[0]);
-      out[s].g[1] = m_fma(-im, fy, out[s].g[1]);
-      out[s].lap = m_fma(-re, f2, out[s].lap);
-    } else {
-      // a value-only slot accumulates Re(c e) = cr er - ci ei in two fused steps
-      out[s].v = m_fma(cr, er, m_fma(-ci, ei, out[s].v));
-    }
-  }
+  for (int b = 1; b < kSpecRow; ++b) v = m_fma(r[b], phi[b], v);
+  return v;
 }
 
 template <typename T, bool D, int ND = 2>
 __device__ __forceinline__ void spectral2d(G<Spectral2D<T>>& sp, const T* x, FV<T, 2>* out) {
-  // e^{2 pi i ky y} for ky = -K .. K from the powers of e^{2 pi i y}
-  T c1, s1, yr[kSpecRow], yi[kSpecRow];
-  m_sincospi2(x[1], &s1, &c1);
-  yr[kSpecK] = 1;
-  yi[kSpecK] = 0;
+  // phi(y) = 1, cos 2 pi y, sin 2 pi y, cos 4 pi y, sin 4 pi y, cos 6 pi y, sin 6 pi y
+  T phi[kSpecRow];
+  phi[0] = 1;
+  m_sincospi2(x[1], &phi[2], &phi[1]);
 #pragma unroll
-  for (int m = 1; m <= kSpecK; ++m) {
-    const T pr = yr[kSpecK + m - 1], pi = yi[kSpecK + m - 1];
-    yr[kSpecK + m] = pr * c1 - pi * s1;
-    yi[kSpecK + m] = m_fma(pi, c1, pr * s1);
-    yr[kSpecK - m] = yr[kSpecK + m];
-    yi[kSpecK - m] = -yi[kSpecK + m];
+  for (int n = 2; n <= kSpecK; ++n) {
+    const T pc = phi[2 * n - 3], ps = phi[2 * n - 2];
+    phi[2 * n - 1] = m_fma(pc, phi[1], -ps * phi[2]);
+    phi[2 * n] = m_fma(ps, phi[1], pc * phi[2]);
   }
+  // row a = 0 (psi_0 = 1)
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
-    out[s].v = sp.c[s];
-    out[s].g[0] = 0;
-    out[s].g[1] = 0;
-    out[s].lap = 0;
-  }
-  constexpr T kTwoPi = (T)6.283185307179586476925286766559;
-  // kx = 0: only ky > 0 is stored, and e^{2 pi i k.x} = e^{2 pi i ky y}
-#pragma unroll
-  for (int j = kSpecK + 1; j < kSpecRow; ++j) {
-    const T fy = kTwoPi * (T)(j - kSpecK);
-    spectral_terms<T, D, ND>(&sp.row[0][0][0], yr[j], yi[j], (T)0, fy, fy * fy, out, j);
+    out[s].v = spectral_dot<T>(sp.m[0][s][0], phi);
+    if (D && s < ND) {
+      out[s].g[0] = 0;
+      out[s].g[1] = spectral_dot<T>(sp.m[0][s][1], phi);
+      out[s].lap = spectral_dot<T>(sp.m[0][s][2], phi);
+    }
   }
   T cx1, sx1;
   m_sincospi2(x[0], &sx1, &cx1);
-  T exr = cx1, exi = sx1;   // e^{2 pi i kx x}
-  // one row of wave vectors per pass: the loop is kept rolled so that only one row of
-  // coefficients (wave-uniform, scalar loads) is live at a time
-#pragma unroll 1
-  for (int kx = 1; kx <= kSpecK; ++kx) {
-    const WOS_GLOBAL T* row = &sp.row[kx][0][0];
-    const T fx = kTwoPi * (T)kx;
-    const T fx2 = fx * fx;
+  T c = cx1, sn = sx1;   // cos and sin of 2 pi n x
+  T gx[ND > 0 ? ND : 1], lx[ND > 0 ? ND : 1];
 #pragma unroll
-    for (int j = 0; j < kSpecRow; ++j) {
-      const T fy = kTwoPi * (T)(j - kSpecK);
-      const T er = exr * yr[j] - exi * yi[j];
-      const T ei = m_fma(exr, yi[j], exi * yr[j]);
-      spectral_terms<T, D, ND>(row, er, ei, fx, fy, m_fma(fy, fy, fx2), out, j);
+  for (int s = 0; s < ND; ++s) {
+    gx[s] = 0;
+    lx[s] = 0;
+  }
+  // rows 2n - 1 (cos 2 pi n x) and 2n (sin 2 pi n x); the loop is kept rolled so that one
+  // pair of rows of coefficients (scalar loads) is live at a time
+#pragma unroll 1
+  for (int n = 1; n <= kSpecK; ++n) {
+    const T fn = (T)n;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      const T vc = spectral_dot<T>(sp.m[2 * n - 1][s][0], phi);
+      const T vs = spectral_dot<T>(sp.m[2 * n][s][0], phi);
+      const T u = m_fma(vc, c, vs * sn);
+      out[s].v += u;
+      if (D && s < ND) {
+        // d/dx: 2 pi n (vs cos - vc sin); d2/dx2: -(2 pi n)^2 u (2 pi factors applied below)
+        gx[s] = m_fma(fn, m_fma(vs, c, -vc * sn), gx[s]);
+        lx[s] = m_fma(-fn * fn, u, lx[s]);
+        const T wc = spectral_dot<T>(sp.m[2 * n - 1][s][1], phi);
+        const T ws = spectral_dot<T>(sp.m[2 * n][s][1], phi);
+        out[s].g[1] += m_fma(wc, c, ws * sn);
+        const T zc = spectral_dot<T>(sp.m[2 * n - 1][s][2], phi);
+        const T zs = spectral_dot<T>(sp.m[2 * n][s][2], phi);
+        out[s].lap += m_fma(zc, c, zs * sn);
+      }
     }
-    const T t = exr * cx1 - exi * sx1;
-    exi = m_fma(exr, sx1, exi * cx1);
-    exr = t;
+    const T t = m_fma(c, cx1, -sn * sx1);
+    sn = m_fma(sn, cx1, c * sx1);
+    c = t;
+  }
+  constexpr T kTwoPi = (T)6.283185307179586476925286766559;
+  constexpr T kFourPi2 = (T)39.478417604357434475337963999505;
+#pragma unroll
+  for (int s = 0; s < ND; ++s) {
+    if (D) {
+      out[s].g[0] = kTwoPi * gx[s];
+      out[s].lap = m_fma(kFourPi2, lx[s], out[s].lap);
+    }
   }
 }
 

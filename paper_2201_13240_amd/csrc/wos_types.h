@@ -109,21 +109,21 @@ struct DevGeometry {
   const T* cell_dc;
 };
 
-// Dense trigonometric table of the 2D Fourier fields: for alpha, psi and sigma (slots
-// 0, 1, 2) the complex coefficient C_k of each wave vector k of the half plane
-// {kx > 0, |ky| <= 3} u {kx = 0, ky > 0}, kx <= 3, in the order kx = 0..3, ky = -3..3, so
-// that B(x) = const + sum_k Re(C_k e^{2 pi i k.x}). A mode a cos(2 pi k.x + phi) adds
-// a e^{i phi} at k, or a e^{-i phi} at -k when k is in the other half plane.
+// Dense trigonometric table of the 2D Fourier fields (alpha, psi and sigma: slots 0, 1,
+// 2) with integer wave vectors |k_i| <= 3, in product form. With the bases
+//   psi_a(x) = 1, cos 2 pi x, sin 2 pi x, cos 4 pi x, sin 4 pi x, cos 6 pi x, sin 6 pi x
+// (a = 0 .. 6) and phi_b(y) the same in y, the base of a slot is
+//   B(x, y) = sum_{a, b} M[a][b] psi_a(x) phi_b(y),
+// which holds every mode a cos(2 pi k.x + phi) with |k_i| <= 3 and the constant. m[a][slot]
+// holds row a of M (kind 0) and the same row of the matrices of dB/dy (kind 1) and
+// d2B/dy2 (kind 2), so that each is one dot product with phi per row.
 constexpr int kSpecK = 3;
 constexpr int kSpecGammaMerged = 8;
-constexpr int kSpecRow = 2 * kSpecK + 1;   // ky = -kSpecK .. kSpecK
+constexpr int kSpecRow = 2 * kSpecK + 1;   // basis functions per variable
 
-// row[kx][slot][2 j], row[kx][slot][2 j + 1]: real and imaginary part of C_k for
-// k = (kx, j - kSpecK); the kx = 0 row only holds ky > 0 (the rest is zero).
 template <typename T>
 struct Spectral2D {
-  T row[kSpecK + 1][3][2 * kSpecRow];
-  T c[3];
+  T m[kSpecRow][3][3][kSpecRow];
 };
 
 template <typename T>
