@@ -63,6 +63,9 @@ def parse():
     # profiling helpers (each does only this and exits)
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 1 GiB device-to-device copy: the calibration kernel for FETCH_SIZE/WRITE_SIZE")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run one pass of the 64-problem batch (512 walks per point, --shape or autotuned) "
+                         "after one warm-up pass: the profiling run for the batch's own counters")
     ap.add_argument("--summarize-trace", nargs="+", metavar=("DB", "SUBSTR"),
                     help="print the kernel table of a rocprofv3 --kernel-trace --stats results.db")
     ap.add_argument("--summarize-pmc", nargs="+", metavar=("SUBSTR", "DB"),
@@ -298,6 +301,25 @@ def write_traffic(walker_fetch, walker_write, copy_fetch, copy_write):
     with open(path, "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec, indent=1))
+
+
+def batch_only(wos, torch, WL, shape_arg):
+    """One warm-up and one timed pass of the 64-problem batch in one plan (the extras
+    workload), so that counter runs see only its walker dispatches."""
+    c = WL.config4()
+    entries = []
+    for i, (p, q) in enumerate(zip(c["problems"], c["points"])):
+        Q = torch.as_tensor(q, dtype=torch.float64, device="cuda")
+        entries.append((wos.Problem(p), Q, wos.Accumulators(Q.shape[0]), i))
+    shape = {} if shape_arg == "auto" else dict(zip(("block_size", "tile_walks"),
+                                                    map(int, shape_arg.lower().split("x"))))
+    plan = wos.Plan(entries, wos.options(precision="fp32", walks=512, seed=0, **shape))
+    for k in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.launch(seed=k, walk_offset_add=0)
+        torch.cuda.synchronize()
+        print(f"batch pass {k}: {(time.perf_counter() - t0) * 1e3:.1f} ms, plan {plan.info()}", flush=True)
 
 
 def copy_probe():
@@ -772,6 +794,9 @@ def main():
     from paper_2201_13240_amd import workloads as WL
 
     torch.cuda.set_device(0)
+    if args.batch_only:
+        batch_only(wos, torch, WL, args.shape)
+        return
     if args.tune_cache and os.path.exists(args.tune_cache):
         print(f"bench: {wos.tune_cache_load(args.tune_cache)} tuned shapes loaded", file=sys.stderr, flush=True)
     c = WL.config2(n_grid=args.grid)
