@@ -147,6 +147,10 @@ std::vector<T> field_terms(const wos_field_desc& f, int dim) {
       o[3] = (T)(a * std::cos(phi));
       o[4] = (T)(a * std::sin(phi));
       o[5] = (T)k2;
+      // the phase in revolutions, reduced to [-1/2, 1/2]
+      const double rev = phi / kTwoPi;
+      o[6] = (T)a;
+      o[7] = (T)(rev - std::nearbyint(rev));
     } else {  // bumps
       for (int i = 0; i < dim; ++i) o[i] = (T)t[i];
       const double w = t[dim];

@@ -59,6 +59,9 @@ __device__ __forceinline__ void m_sincospi2(float r, float* s, float* c) {
   *c = __builtin_amdgcn_cosf(f);
 }
 __device__ __forceinline__ void m_sincospi2(double r, double* s, double* c) { ::sincospi(2.0 * r, s, c); }
+// cos(2 pi r), r in revolutions
+__device__ __forceinline__ float m_cospi2(float r) { return __builtin_amdgcn_cosf(r - __builtin_rintf(r)); }
+__device__ __forceinline__ double m_cospi2(double r) { return ::cospi(2.0 * r); }
 __device__ __forceinline__ void m_sincos(float x, float* s, float* c) { ::sincosf(x, s, c); }
 __device__ __forceinline__ void m_sincos(double x, double* s, double* c) { ::sincos(x, s, c); }
 
@@ -727,6 +730,13 @@ __device__ __forceinline__ FV<T, DIM> field_base(G<DevField<T>>& f, const T* x) 
   if (base == FB_FOURIER) {
     const WOS_GLOBAL T* p = gptr(f.terms);
     for (int j = 0; j < f.n; ++j, p += kTermStride) {
+      if (!D) {
+        // value alone: a cos(2 pi (k.x + phi / 2 pi)), one cosine
+        T th = m_fma(p[0], x[0], m_fma(p[1], x[1], p[7]));
+        if (DIM == 3) th = m_fma(p[2], x[2], th);
+        r.v = m_fma(p[6], m_cospi2(th), r.v);
+        continue;
+      }
       // phase k.x in revolutions (k in cycles per unit length)
       T th = p[0] * x[0] + p[1] * x[1];
       if (DIM == 3) th = m_fma(p[2], x[2], th);

@@ -12,11 +12,13 @@ enum GeomKind : int32_t { GK_BALL = 0, GK_BOX = 1, GK_POLYGON = 2, GK_TRIMESH = 
 constexpr int kSdfStride = 8;
 enum SolutionId : int32_t { SOL_EXPCOS = 1, SOL_QUADRATIC = 2 };
 
-// Six numbers per term, in the precision of the walker:
-//   fourier: 2 pi k0, 2 pi k1, 2 pi k2, a cos(phi), a sin(phi), |2 pi k|^2
-//            (a cos(2 pi k.x + phi) = ac cos(th) - as sin(th), th = 2 pi k.x)
-//   bumps:   c0, c1, c2, 1/(2 w^2), amp, 1/w^2
-constexpr int kTermStride = 6;
+// Eight numbers per term, in the precision of the walker:
+//   fourier: k0, k1, k2 (cycles per unit length), a cos(phi), a sin(phi), |2 pi k|^2, a,
+//            phi / (2 pi): a cos(2 pi k.x + phi) = ac cos(th) - as sin(th) with
+//            th = 2 pi k.x where derivatives are needed, a cos(2 pi (k.x + phi / 2 pi))
+//            (one cosine) for the value alone
+//   bumps:   c0, c1, c2, 1/(2 w^2), amp, 1/w^2 (the last two unused)
+constexpr int kTermStride = 8;
 
 template <typename T>
 struct DevField {
