@@ -664,8 +664,15 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
         for (int i = 0; i < DIM; ++i) q[i] = x[i];
         T gb = 0;
         if (phase == 2) {
-          if (sizeof(T) == 8 && a.fp32_draws) refill_fp32_draws<DIM>(rng);
-          else rng.refill<SL::kBlocks>();
+          // the roulette slot's block only where a weight window can use it
+          if (sizeof(T) == 8 && a.fp32_draws) {
+            if (window) refill_fp32_draws<DIM, Slots<float, DIM>::kBlocks>(rng);
+            else refill_fp32_draws<DIM, Slots<float, DIM>::kBlocksPlain>(rng);
+          } else if (window) {
+            rng.refill<SL::kBlocks>();
+          } else {
+            rng.refill<SL::kBlocksPlain>();
+          }
         }
         if (phase == 2 && !pending) {
           if constexpr (COUNT) ++ev[EV_STEPS];
@@ -780,8 +787,8 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
             }
             const T fg = grad_ratio_green<T, DIM>(m_sqrt(r2), R, P.sqrt_sigma_bar);
             const T fp = grad_ratio_poisson<T, DIM>(R, P.sqrt_sigma_bar);
-            T vz[DIM];
-            uniform_direction<T, DIM, SL::kExitDir>(rng, vz);   // the exit direction drawn below
+            T vz[DIM] = {};
+            if (!volume) exit_direction<T, DIM, SL::kExitDir2>(rng, m_div(mu - b.pb, (T)1 - b.pb), vz);   // as below
             gr[0] = term;
 #pragma unroll
             for (int i = 0; i < DIM; ++i) {
@@ -797,9 +804,11 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
             gx = cq.gamma;
             gx_known = true;
           } else {
-            // boundary term: uniform point on the sphere, weight e^{gamma(z) - gamma(x)}
+            // boundary term: uniform point on the sphere, weight e^{gamma(z) - gamma(x)}; the
+            // direction's first uniform is mu's residual (mu - P_B)/(1 - P_B), uniform on
+            // (0, 1] given the exit
             T vz[DIM];
-            uniform_direction<T, DIM, SL::kExitDir>(rng, vz);
+            exit_direction<T, DIM, SL::kExitDir2>(rng, m_div(mu - b.pb, (T)1 - b.pb), vz);
   #pragma unroll
             for (int i = 0; i < DIM; ++i) x[i] = m_fma(R, vz[i], x[i]);
             gx_known = false;
