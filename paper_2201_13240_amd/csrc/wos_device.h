@@ -140,24 +140,29 @@ struct Rng {
   }
 };
 
-// Uniform in (0, 1] from uniform slot S of the current draw. FP32 takes 24 bits, five
-// uniforms per Philox block: slot 5b + j (j < 4) is the top 24 bits of word 4b + j, slot
-// 5b + 4 the low bytes of words 4b, 4b + 1 and 4b + 2. FP64 takes 53 bits of words 2S and
-// 2S + 1. Never zero, so logarithms are finite.
+// Uniform from slot S of the current draw. FP32: (k + 1/2) 2^-21 for the 21-bit field k
+// of the slot, in (0, 1) (never 0 or 1, so a logarithm is finite and nonzero: a
+// free-space radius proposal 2 sqrt(ln u1 ln u2) is never 0), six uniforms per Philox
+// block: slot 6b + j is bits 21j .. 21j + 20 of the 128-bit block b (words 4b .. 4b + 3,
+// least significant first), so one block serves a 2D delta-tracking step. FP64: 53 bits
+// of words 2S and 2S + 1, plus 2^-53, in (0, 1].
+constexpr int kFp32UniformBits = 21;
+
 template <int S>
-__device__ __forceinline__ uint32_t uniform_bits24(const Rng& r) {
-  constexpr int b = S / 5, j = S % 5;
-  if constexpr (j < 4) {
-    return r.w[4 * b + j] >> 8;
+__device__ __forceinline__ uint32_t uniform_bits_fp32(const Rng& r) {
+  constexpr int b = S / 6, o = 21 * (S % 6), i = 4 * b + o / 32, sh = o % 32;
+  constexpr uint32_t mask = (1u << kFp32UniformBits) - 1u;
+  if constexpr (sh + kFp32UniformBits <= 32) {
+    return (r.w[i] >> sh) & mask;
   } else {
-    return ((r.w[4 * b] & 0xFFu) << 16) | ((r.w[4 * b + 1] & 0xFFu) << 8) | (r.w[4 * b + 2] & 0xFFu);
+    return __builtin_amdgcn_alignbit(r.w[i + 1], r.w[i], sh) & mask;
   }
 }
 
 template <typename T, int S>
 __device__ __forceinline__ T uniform01(const Rng& r) {
   if constexpr (sizeof(T) == 4) {
-    return (float)(uniform_bits24<S>(r) + 1u) * 5.9604644775390625e-8f;  // 2^-24
+    return (float)((uniform_bits_fp32<S>(r) << 1) | 1u) * 2.384185791015625e-7f;  // (2k + 1) 2^-22
   } else {
     const uint64_t a = r.w[2 * S], b = r.w[2 * S + 1];
     return (double)((((a << 32) | b) >> 11) + 1ull) * 1.1102230246251565404e-16;  // 2^-53
@@ -165,26 +170,23 @@ __device__ __forceinline__ T uniform01(const Rng& r) {
 }
 
 // Uniform slots of one iteration of the walker. Delta tracking: ball direction, radius
-// proposal (3 uniforms in 2D, 4 in 3D), volume/exit choice mu, in 3D the second uniform
-// of the exit direction, roulette. The exit direction's (first) uniform is the residual
-// of mu: given an exit (mu > P_B), (mu - P_B)/(1 - P_B) is uniform on (0, 1] and
-// independent of the rest of the walk. Next flight: roulette on the throughput, exit
-// direction of a new ball, inner point (direction and radius). Blocks: Philox blocks per
-// iteration with the roulette slot (kBlocks) and without it (kBlocksPlain: no weight
-// window, FP32 2D: one block).
+// proposal (3 uniforms in 2D, 4 in 3D), volume/exit choice, exit direction, roulette.
+// Next flight: roulette on the throughput, exit direction of a new ball, inner point
+// (direction and radius). Blocks: Philox blocks per iteration with the roulette slot
+// (kBlocks) and without it (kBlocksPlain: no weight window; FP32 2D: one block).
 template <typename T, int DIM>
 struct Slots {
   static constexpr int kDir = 0;
   static constexpr int kTrial = kDir + DIM - 1;
   static constexpr int kMu = kTrial + (DIM == 2 ? 3 : 4);
-  static constexpr int kExitDir2 = kMu + 1;   // 3D only
-  static constexpr int kRoulette = kMu + 1 + (DIM == 3 ? 1 : 0);
+  static constexpr int kExitDir = kMu + 1;
+  static constexpr int kRoulette = kExitDir + DIM - 1;
   static constexpr int kCount = kRoulette + 1;
   static constexpr int kNfRoulette = 0;
   static constexpr int kNfExitDir = 1;
   static constexpr int kNfInner = kNfExitDir + DIM - 1;
   static constexpr int kNfCount = kNfInner + DIM;
-  static constexpr int blocks(int slots) { return sizeof(T) == 4 ? (slots + 4) / 5 : (2 * slots + 3) / 4; }
+  static constexpr int blocks(int slots) { return sizeof(T) == 4 ? (slots + 5) / 6 : (2 * slots + 3) / 4; }
   static constexpr int kBlocks = blocks(kCount);
   static constexpr int kBlocksPlain = blocks(kCount - 1);
   static constexpr int kNfBlocks = blocks(kNfCount);
@@ -193,15 +195,17 @@ struct Slots {
 
 // Draws of one delta-tracking iteration for the FP64 walker taking the FP32 walker's
 // uniforms (common random numbers): the FP32 slot layout's Philox blocks are drawn (with
-// or without the roulette slot, as the FP32 walker does), and the 24-bit uniform of FP32
-// slot S, (bits + 1) 2^-24, is re-encoded into words 2S and 2S + 1 so that the FP64
+// or without the roulette slot, as the FP32 walker does), and the uniform of FP32 slot
+// S, (2k + 1) 2^-22, is re-encoded into words 2S and 2S + 1 so that the FP64
 // construction (53 bits, plus 2^-53) returns exactly that value. Slots are rewritten from
-// the last down: FP32 slot S reads only words at or below S, and slot S' < S writes words
-// 2S' and 2S' + 1, so no word is overwritten before it is read.
+// the last down: FP32 slot S reads only words below 2S + 2, and slot S' < S writes words
+// 2S' and 2S' + 1, above every word a lower slot reads, so no word is overwritten before
+// it is read.
 template <int S>
 __device__ __forceinline__ void reencode_fp32_slots(Rng& r) {
   if constexpr (S >= 0) {
-    const uint64_t x = (((uint64_t)uniform_bits24<S>(r) + 1ull) << 29) - 1ull;   // (bits + 1) 2^29 - 1 < 2^53
+    // (2k + 1) 2^(53 - 22) - 1 < 2^53
+    const uint64_t x = ((((uint64_t)uniform_bits_fp32<S>(r) << 1) | 1ull) << (52 - kFp32UniformBits)) - 1ull;
     const uint64_t y = x << 11;
     r.w[2 * S] = (uint32_t)(y >> 32);
     r.w[2 * S + 1] = (uint32_t)y;
@@ -707,26 +711,6 @@ __device__ __forceinline__ void uniform_direction(const Rng& rng, T* v) {
     const T z = (T)1 - (T)2 * uniform01<T, S>(rng);
     T sn, cs;
     m_sincospi2(uniform01<T, S + 1>(rng), &sn, &cs);
-    const T rr = m_sqrt(fmax((T)0, (T)1 - z * z));
-    v[0] = rr * cs;
-    v[1] = rr * sn;
-    v[2] = z;
-  }
-}
-
-// Exit direction of the delta-tracking walk on the unit sphere: its first uniform is u
-// (the residual of the volume/exit draw), the second (3D) from slot S2.
-template <typename T, int DIM, int S2>
-__device__ __forceinline__ void exit_direction(const Rng& rng, T u, T* v) {
-  if (DIM == 2) {
-    T sn, cs;
-    m_sincospi2(u, &sn, &cs);
-    v[0] = cs;
-    v[1] = sn;
-  } else {
-    const T z = (T)1 - (T)2 * u;
-    T sn, cs;
-    m_sincospi2(uniform01<T, S2>(rng), &sn, &cs);
     const T rr = m_sqrt(fmax((T)0, (T)1 - z * z));
     v[0] = rr * cs;
     v[1] = rr * sn;

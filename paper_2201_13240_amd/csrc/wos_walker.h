@@ -787,8 +787,8 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
             }
             const T fg = grad_ratio_green<T, DIM>(m_sqrt(r2), R, P.sqrt_sigma_bar);
             const T fp = grad_ratio_poisson<T, DIM>(R, P.sqrt_sigma_bar);
-            T vz[DIM] = {};
-            if (!volume) exit_direction<T, DIM, SL::kExitDir2>(rng, m_div(mu - b.pb, (T)1 - b.pb), vz);   // as below
+            T vz[DIM];
+            uniform_direction<T, DIM, SL::kExitDir>(rng, vz);   // the exit direction drawn below
             gr[0] = term;
 #pragma unroll
             for (int i = 0; i < DIM; ++i) {
@@ -804,11 +804,9 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
             gx = cq.gamma;
             gx_known = true;
           } else {
-            // boundary term: uniform point on the sphere, weight e^{gamma(z) - gamma(x)}; the
-            // direction's first uniform is mu's residual (mu - P_B)/(1 - P_B), uniform on
-            // (0, 1] given the exit
+            // boundary term: uniform point on the sphere, weight e^{gamma(z) - gamma(x)}
             T vz[DIM];
-            exit_direction<T, DIM, SL::kExitDir2>(rng, m_div(mu - b.pb, (T)1 - b.pb), vz);
+            uniform_direction<T, DIM, SL::kExitDir>(rng, vz);
   #pragma unroll
             for (int i = 0; i < DIM; ++i) x[i] = m_fma(R, vz[i], x[i]);
             gx_known = false;
