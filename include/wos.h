@@ -197,8 +197,8 @@ wos_status wos_problem_destroy(wos_problem* p);
  *                    exact per-point sums, rounded once to FP64.
  *  FP32_COMPENSATED: as FP32 with a compensated (two-sum) per-walk sum.
  *  FP64:             everything in FP64 (the plain FP64 walker).
- *  FP64_FP32_DRAWS:  the FP64 walker drawing exactly the FP32 walker's uniforms (24 bits
- *                    of one Philox word each, the FP32 word layout), so that FP32 and FP64
+ *  FP64_FP32_DRAWS:  the FP64 walker drawing exactly the FP32 walker's uniforms (21-bit
+ *                    fields of the Philox blocks, the FP32 layout), so that FP32 and FP64
  *                    walks of one seed follow the same path up to rounding (common random
  *                    numbers: for measuring the error of the FP32 walker, Sec. 3.1).
  *                    Delta tracking only (variant 0 or 1). */
