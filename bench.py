@@ -149,6 +149,9 @@ def event_weights(prob):
         "ball_large_s": (42, 2),                                         # Chebyshev instead of series
         "trials": (78, 3),                                               # harmonic-law proposal
         "trials_free": (37, 1),                                          # free-space proposal, extra
+        # 2D below s = 3.5: the harmonic draw mapped to t0^a (a, ln t0, t0^a), the Bessel
+        # values unscaled, the envelope constant (12-term Chebyshev series) and t0^(2a - 2)
+        "trials_power": (34, 3) if prob["dim"] == 2 else (0, 0),
         "volume": (3, 0),
         "exit": (6, 2),
         "terminal": (12 + bf + 4, bt + 1),
@@ -185,6 +188,7 @@ def algorithmic_work(events, prob, next_flight=False):
     W = nf_event_weights(prob) if next_flight else event_weights(prob)
     ev = dict(events)
     ev["sampled"] = ev["steps"] - ev["terminal"]
+    ev["trials_power"] = ev["trials"] - ev["trials_free"]
     flops = sum(W[k][0] * ev[k] for k in W)
     trans = sum(W[k][1] * ev[k] for k in W)
     return flops, trans
@@ -197,7 +201,7 @@ def algorithmic_work(events, prob, next_flight=False):
 # the device sources the counters were taken with. A changed kernel makes them stale:
 # traffic is then reported as null.
 DEVICE_SOURCES = ("wos_walker.h", "wos_walker_f32_2d.hip", "wos_walker_f64_2d.hip", "wos_kernels.hip", "wos_device.h",
-                  "wos_types.h", "bessel_tables.h")
+                  "wos_types.h", "bessel_tables.h", "proposal_bound.h")
 
 
 def device_source_hash():

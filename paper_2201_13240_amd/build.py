@@ -16,7 +16,8 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 # compile in parallel with the rest.
 SOURCES = ["wos_walker_f64_3d.hip", "wos_walker_f64_2d.hip", "wos_walker_f32_3d.hip", "wos_walker_f32_2d.hip",
            "wos_kernels.hip", "wos_api.cpp", "bvh.cpp"]
-HEADERS = ["wos_walker.h", "wos_device.h", "wos_types.h", "wos_launch.h", "bvh.h", "bessel_tables.h"]
+HEADERS = ["wos_walker.h", "wos_device.h", "wos_types.h", "wos_launch.h", "bvh.h", "bessel_tables.h",
+           "proposal_bound.h"]
 
 # Packed FP32 instructions are disabled for all device code (the compiler forms them
 # from scalar float code on its own otherwise).

@@ -10,6 +10,7 @@
 #include <cstdint>
 
 #include "bessel_tables.h"
+#include "proposal_bound.h"
 #include "wos_types.h"
 
 namespace wos {
@@ -633,6 +634,13 @@ constexpr uint32_t kMaxTrials = 256;
 // One proposal and its accept/reject test; returns t in (0, 1] on acceptance and -1 on
 // rejection. The walker calls it once per iteration and lane, so a rejected lane retries
 // at the next iteration instead of holding its whole wavefront in a rejection loop.
+// 2D: below s = WOS_PROP_SMAX the proposal is a harmonic-law draw t0 = sqrt(U1 U2) mapped
+// to t = t0^a, a = 1 + WOS_PROP_KAPPA s^2 (density proportional to t^(2/a - 1) ln(1/t)),
+// accepted with t^(2 - 2/a) G(t) / (C ln(1/t)), G the screened Green's function of the unit
+// disk and C >= the supremum of that ratio (proposal_bound.h): 88-100% of proposals are
+// accepted there, against 56% for either proposal alone at s = 2. From WOS_PROP_SMAX on
+// the free-space proposal u = 2 sqrt(E1 E2), accepted with G_ball/G_free on u < s (86% and
+// more).
 template <typename T, int DIM, int S, bool COUNT = false>
 __device__ __forceinline__ T radius_trial(const Rng& rng, T s, const Ball<T, DIM>& b, bool harmonic,
                                         Tally* tally = nullptr) {
@@ -640,13 +648,12 @@ __device__ __forceinline__ T radius_trial(const Rng& rng, T s, const Ball<T, DIM
     const T u1 = uniform01<T, S>(rng), u2 = uniform01<T, S + 1>(rng);
     if (harmonic) return m_sqrt(u1 * u2);
     const T u3 = uniform01<T, S + 2>(rng);
-    // s < 2: harmonic proposal t = sqrt(U1 U2), accepted with G^s/G^0; otherwise the
-    // free-space proposal u = ts = 2 sqrt(E1 E2), accepted with G_ball/G_free on u < s.
-    // Both need I0 and K0 at x = ts, taken from one call.
-    const bool hprop = s < (T)2;
-    T t, x;
-    if (hprop) {
-      t = m_sqrt(u1 * u2);
+    const bool pprop = s < (T)WOS_PROP_SMAX;
+    T t, x, la = 0, ae = 1;
+    if (pprop) {
+      ae = m_fma((T)WOS_PROP_KAPPA * s, s, (T)1);
+      la = (T)-0.5 * m_log(u1 * u2);     // ln(1/t0)
+      t = m_exp(-ae * la);
       x = t * s;
     } else {
       if constexpr (COUNT) ++tally->trials_free;
@@ -655,10 +662,17 @@ __device__ __forceinline__ T radius_trial(const Rng& rng, T s, const Ball<T, DIM
     }
     T a, k;
     const bool scaled = bessel_i0k0<T>(x, &a, &k);
-    if (hprop) {
-      // x < 2: a = I0(x) - 1, k = K0(x)
-      const T g = k - b.c2d * ((T)1 + a);
-      return u3 * -m_log(t) <= g ? t : (T)-1;
+    if (pprop) {
+      // G(t) = K0(x) - K0(s) I0(x) / I0(s); the ball's c2d is K0(s)/I0(s), scaled by e^{2s}
+      // from s = 2 on
+      const T ex = scaled ? m_exp(x) : (T)1;
+      const T i0x = scaled ? a * ex : (T)1 + a;
+      const T k0x = scaled ? k * m_rcp(ex) : k;
+      const T ks = s >= (T)2 ? b.c2d * m_exp((T)-2 * s) : b.c2d;
+      const T g = k0x - ks * i0x;
+      const T C = chebyshev<T>(WOS_PROP_C, WOS_PROP_N, s * (T)(2.0 / WOS_PROP_SMAX) - (T)1);
+      // accept if u3 C ln(1/t) <= t^(2 - 2/a) G(t), ln(1/t) = a ln(1/t0), t^(2 - 2/a) = t0^(2a - 2)
+      return u3 * C * ae * la <= m_exp((T)-2 * (ae - (T)1) * la) * g ? t : (T)-1;
     }
     // 1 - G_ball/G_free = c2d I0(x)/K0(x) e^{-2s} with c2d = e^{2s} K0(s)/I0(s)
     const T r = b.c2d * m_div(scaled ? a : (T)1 + a, k) * m_exp(scaled ? (T)2 * (x - s) : (T)-2 * s);
