@@ -149,9 +149,10 @@ def event_weights(prob):
         "ball_large_s": (42, 2),                                         # Chebyshev instead of series
         "trials": (78, 3),                                               # harmonic-law proposal
         "trials_free": (37, 1),                                          # free-space proposal, extra
-        # 2D below s = 3.5: the harmonic draw mapped to t0^a (a, ln t0, t0^a), the Bessel
-        # values unscaled, the envelope constant (12-term Chebyshev series) and t0^(2a - 2)
-        "trials_power": (34, 3) if prob["dim"] == 2 else (0, 0),
+        # below s = 3.5 (2D) or 4 (3D): the harmonic draw mapped to t0^a (a, ln t0, t0^a),
+        # in 2D the Bessel values unscaled, the envelope constant (closed form or 12-term
+        # Chebyshev series) and t0^(2a - 2)
+        "trials_power": (34, 3) if prob["dim"] == 2 else (26, 3),
         "volume": (3, 0),
         "exit": (6, 2),
         "terminal": (12 + bf + 4, bt + 1),

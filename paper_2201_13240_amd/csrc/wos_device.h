@@ -640,7 +640,8 @@ constexpr uint32_t kMaxTrials = 256;
 // disk and C >= the supremum of that ratio (proposal_bound.h): 88-100% of proposals are
 // accepted there, against 56% for either proposal alone at s = 2. From WOS_PROP_SMAX on
 // the free-space proposal u = 2 sqrt(E1 E2), accepted with G_ball/G_free on u < s (86% and
-// more).
+// more). 3D likewise with the Beta(2, 2) harmonic law below s = WOS_PROP3_SMAX (acceptance
+// 0.88-1.0, against 0.57-0.97 for the harmonic law alone below sqrt 6).
 template <typename T, int DIM, int S, bool COUNT = false>
 __device__ __forceinline__ T radius_trial(const Rng& rng, T s, const Ball<T, DIM>& b, bool harmonic,
                                         Tally* tally = nullptr) {
@@ -678,16 +679,29 @@ __device__ __forceinline__ T radius_trial(const Rng& rng, T s, const Ball<T, DIM
     const T r = b.c2d * m_div(scaled ? a : (T)1 + a, k) * m_exp(scaled ? (T)2 * (x - s) : (T)-2 * s);
     return (x < s && u3 <= (T)1 - r) ? t : (T)-1;
   } else {
-    if (harmonic || s < (T)2.449489742783178) {
-      // Beta(2,2) = median of three uniforms
+    if (harmonic || s < (T)WOS_PROP3_SMAX) {
+      // Beta(2,2) = median of three uniforms, t0; below s = WOS_PROP3_SMAX mapped to
+      // t = t0^a, a = 1 + WOS_PROP3_KAPPA s^2 (proposal density proportional to
+      // t^(2/a - 1) (1 - t^(1/a))), accepted with t^(2 - 2/a) sinh(s (1 - t)) /
+      // (C sinh(s) (1 - t0)), C >= its supremum over t: a s / sinh(s) below
+      // WOS_PROP3_SK, the series of proposal_bound.h above
       const T a = uniform01<T, S>(rng), c = uniform01<T, S + 1>(rng), d = uniform01<T, S + 2>(rng);
-      const T t = fmax(fmin(a, c), fmin(fmax(a, c), d));
-      if (harmonic) return t;
+      const T t0 = fmax(fmin(a, c), fmin(fmax(a, c), d));
+      if (harmonic) return t0;
       const T u4 = uniform01<T, S + 3>(rng);
+      const T ae = m_fma((T)WOS_PROP3_KAPPA * s, s, (T)1);
+      const T lt0 = m_log(t0);
+      const T t = m_exp(ae * lt0);
       const T omt = (T)1 - t;
-      // sinh(s(1-t)) / ((1-t) sinh s) = e^{-st} (1 - e^{-2s(1-t)}) / ((1 - e^{-2s}) (1-t))
-      const T acc = omt > (T)0 ? m_div(m_exp(-s * t) * m_expm1((T)-2 * s * omt), m_expm1((T)-2 * s) * omt) : (T)0;
-      return u4 <= acc ? t : (T)-1;
+      // sinh(s(1-t)) / sinh(s) = e^{-st} (1 - e^{-2s(1-t)}) / (1 - e^{-2s})
+      const T e2s = m_expm1((T)-2 * s);
+      const T sr = omt > (T)0 ? m_div(m_exp(-s * t) * m_expm1((T)-2 * s * omt), e2s) : (T)0;
+      const T rho = m_exp((T)2 * (ae - (T)1) * lt0) * m_div(sr, (T)1 - t0);
+      const T C = s < (T)WOS_PROP3_SK
+                      ? ae * m_div((T)-2 * s * m_exp(-s), e2s) * (T)1.00001
+                      : chebyshev<T>(WOS_PROP3_C, WOS_PROP3_N,
+                                     (s - (T)WOS_PROP3_SK) * (T)(2.0 / (WOS_PROP3_SMAX - WOS_PROP3_SK)) - (T)1);
+      return u4 * C <= rho ? t : (T)-1;
     }
     if constexpr (COUNT) ++tally->trials_free;
     const T u = -m_log(uniform01<T, S>(rng) * uniform01<T, S + 1>(rng));
