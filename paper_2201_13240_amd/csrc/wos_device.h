@@ -236,9 +236,17 @@ __device__ __forceinline__ T chebyshev(const double* c, int n, T t) {
   return m_fma(t, b1, (T)c[0] - b2);
 }
 
+// Horner's rule for sum_j p_j t^j, one FMA per term
+template <typename T>
+__device__ __forceinline__ T horner(const double* p, int n, T t) {
+  T acc = (T)p[n - 1];
+  for (int j = n - 2; j >= 0; --j) acc = m_fma(acc, t, (T)p[j]);
+  return acc;
+}
+
 template <typename T> struct BesselTerms;
 template <> struct BesselTerms<float> {
-  static constexpr int kI0Wide = WOS_I0E_WIDE_TAIL_N32, kK0Wide = WOS_K0E_WIDE_TAIL_N32;
+  static constexpr int kI0Wide = WOS_I0E_WIDE_TAIL_NH32, kK0Wide = WOS_K0E_WIDE_TAIL_NH32;
   static constexpr int kSeries = 9, kI0Mid = WOS_I0E_MID_N32, kI0Tail = WOS_I0E_TAIL_N32,
                        kK0Low = WOS_K0E_LOW_N32, kK0Mid = WOS_K0E_MID_N32, kK0Tail = WOS_K0E_TAIL_N32,
                        kI1Mid = WOS_I1E_MID_N32, kI1Tail = WOS_I1E_TAIL_N32, kK1Low = WOS_K1E_LOW_N32,
@@ -251,19 +259,53 @@ template <> struct BesselTerms<double> {
                        kK1Mid = WOS_K1E_MID_N64, kK1Tail = WOS_K1E_TAIL_N64;
 };
 
+// Coefficients of the power series below: 1/(k!)^2, H_k = 1 + 1/2 + ... + 1/k and their
+// product
+struct BesselSeriesCoef {
+  double a[16], h[16], b[16];
+};
+constexpr BesselSeriesCoef make_bessel_series_coef() {
+  BesselSeriesCoef c{};
+  double f = 1, h = 0;
+  for (int k = 1; k < 16; ++k) {
+    f /= (double)k * (double)k;
+    h += 1.0 / k;
+    c.a[k] = f;
+    c.h[k] = h;
+    c.b[k] = f * h;
+  }
+  return c;
+}
+static constexpr BesselSeriesCoef kBesselSeries = make_bessel_series_coef();
+
 // Power series of I0 and K0 for x <= 2 (for K0 near x = 2 the two parts cancel to about a
-// tenth, which costs FP32 a few units in the last place):
+// tenth, which costs FP32 a few units in the last place); FP32 takes both as polynomials
+// in q by Horner's rule, FP64 sums the terms upward:
 //   I0(x) - 1 = sum_{k>=1} q^k/(k!)^2,  q = x^2/4
 //   K0(x) = -(ln(x/2) + gamma_E) I0(x) + sum_{k>=1} q^k/(k!)^2 H_k
 template <typename T>
 __device__ __forceinline__ void bessel_series(T x, T* i0m1, T* k0) {
+  constexpr int n = BesselTerms<T>::kSeries;
   const T q = (T)0.25 * x * x;
-  T term = 1, s_i = 0, s_k = 0, h = 0;
-  for (int k = 1; k <= BesselTerms<T>::kSeries; ++k) {
-    term *= q * (T)(1.0 / (k * k));
-    h += (T)1 / (T)k;
-    s_i += term;
-    s_k = m_fma(term, h, s_k);
+  T s_i, s_k;
+  if constexpr (sizeof(T) == 4) {
+    s_i = (T)kBesselSeries.a[n];
+    s_k = (T)kBesselSeries.b[n];
+    for (int k = n - 1; k >= 1; --k) {
+      s_i = m_fma(s_i, q, (T)kBesselSeries.a[k]);
+      s_k = m_fma(s_k, q, (T)kBesselSeries.b[k]);
+    }
+    s_i *= q;
+    s_k *= q;
+  } else {
+    T term = 1;
+    s_i = 0;
+    s_k = 0;
+    for (int k = 1; k <= n; ++k) {
+      term *= q * (T)(1.0 / (k * k));
+      s_i += term;
+      s_k = m_fma(term, (T)kBesselSeries.h[k], s_k);
+    }
   }
   *i0m1 = s_i;
   if (k0) *k0 = -(m_log((T)0.5 * x) + Consts<T>::kEulerGamma) * ((T)1 + s_i) + s_k;
@@ -299,8 +341,8 @@ __device__ T bessel_k0e(T x) {
 // paths: below 2 the series gives *a = I0 - 1 and *k = K0 (returns false); from 2 on the
 // Chebyshev fits give *a = e^-x I0 and *k = e^x K0 (returns true). In FP32 each function
 // has a single fit from 2 on (in t = 4/x - 1, of sqrt(x) e^-x I0 and sqrt(x) e^x K0), so
-// every lane with x >= 2 runs the same two polynomials; FP64 keeps the narrower ranges,
-// whose fits reach double precision with fewer terms.
+// every lane with x >= 2 runs the same two polynomials, as power series in t by Horner's
+// rule; FP64 keeps the narrower ranges, whose fits reach double precision with fewer terms.
 template <typename T>
 __device__ __forceinline__ bool bessel_i0k0(T x, T* a, T* k) {
   if (x < (T)2) {
@@ -311,8 +353,8 @@ __device__ __forceinline__ bool bessel_i0k0(T x, T* a, T* k) {
     const T rx = m_rcp(x);
     const T t = m_fma((T)4, rx, (T)-1);
     const T rs = __builtin_amdgcn_rsqf(x);
-    *a = chebyshev<T>(WOS_I0E_WIDE_TAIL, BesselTerms<T>::kI0Wide, t) * rs;
-    *k = chebyshev<T>(WOS_K0E_WIDE_TAIL, BesselTerms<T>::kK0Wide, t) * rs;
+    *a = horner<T>(WOS_I0E_WIDE_TAIL_POW32, BesselTerms<T>::kI0Wide, t) * rs;
+    *k = horner<T>(WOS_K0E_WIDE_TAIL_POW32, BesselTerms<T>::kK0Wide, t) * rs;
     return true;
   }
   if (x <= (T)8) {
@@ -377,6 +419,21 @@ __device__ T bessel_k1e(T x) {
 }
 
 // ------------------------------------------------------------------ ball kernels
+// 1/(2k+3)!, k = 0..8: the power series of (sinh s - s)/s^3 in s^2
+struct SinhSeriesCoef {
+  double c[9];
+};
+constexpr SinhSeriesCoef make_sinh_series_coef() {
+  SinhSeriesCoef r{};
+  double f = 6;
+  for (int k = 0; k < 9; ++k) {
+    r.c[k] = 1.0 / f;
+    f *= (double)(2 * k + 4) * (double)(2 * k + 5);
+  }
+  return r;
+}
+static constexpr SinhSeriesCoef kSinhSeries = make_sinh_series_coef();
+
 // Centred Green's function of Laplace - sigma_bar on the ball of radius R (supp. Sec. 1.1):
 //   |G| = P_B / sigma_bar with P_B = 1 - 1/I0(s) (2D), 1 - s/sinh(s) (3D), s = R sqrt(sigma_bar),
 // and the Poisson kernel (1 - P_B)/|dB|, so P_B is the probability of the volume term
@@ -410,13 +467,11 @@ __device__ __forceinline__ Ball<T, DIM> ball_terms(T R, T s, T inv_sigma_bar, bo
     }
   } else {
     if (s < (T)1) {
-      // (sinh s - s) = s^3 sum_{k>=0} s^{2k} / (2k+3)!
+      // (sinh s - s) = s^3 sum_{k>=0} s^{2k} / (2k+3)!, a polynomial in s^2 by Horner
+      constexpr int n = sizeof(T) == 4 ? 4 : 8;
       const T s2 = s * s;
-      T term = (T)(1.0 / 6.0), acc = term;
-      for (int k = 1; k <= (sizeof(T) == 4 ? 4 : 8); ++k) {
-        term *= s2 * (T)(1.0 / ((2 * k + 2) * (2 * k + 3)));
-        acc += term;
-      }
+      T acc = (T)kSinhSeries.c[n];
+      for (int k = n - 1; k >= 0; --k) acc = m_fma(acc, s2, (T)kSinhSeries.c[k]);
       const T shm = s * s2 * acc;
       b.pb = m_div(shm, s + shm);
     } else {
