@@ -40,7 +40,8 @@ __device__ __forceinline__ double m_log(double x) { return ::log(x); }
 // ln 2 of the library logarithm (about 1 ulp more error, 2 instructions instead of 13)
 __device__ __forceinline__ float m_logn(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945309f; }
 __device__ __forceinline__ double m_logn(double x) { return ::log(x); }
-__device__ __forceinline__ float m_sqrt(float x) { return __fsqrt_rn(x); }
+// hardware square root (within 1 ulp; no rescaling of inputs below 2^-96)
+__device__ __forceinline__ float m_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double m_sqrt(double x) { return ::sqrt(x); }
 __device__ __forceinline__ float m_tanh(float x) { return ::tanhf(x); }
 __device__ __forceinline__ double m_tanh(double x) { return ::tanh(x); }
@@ -168,7 +169,8 @@ __device__ __forceinline__ uint32_t uniform_bits_fp32(const Rng& r) {
 template <typename T, int S>
 __device__ __forceinline__ T uniform01(const Rng& r) {
   if constexpr (sizeof(T) == 4) {
-    return (float)((uniform_bits_fp32<S>(r) << 1) | 1u) * 2.384185791015625e-7f;  // (2k + 1) 2^-22
+    // (2k + 1) 2^-22 = 1.m - 1 with the 23-bit mantissa m = 4k + 2 (exact)
+    return __uint_as_float((uniform_bits_fp32<S>(r) << 2) | 0x3F800002u) - 1.0f;
   } else {
     const uint64_t a = r.w[2 * S], b = r.w[2 * S + 1];
     return (double)((((a << 32) | b) >> 11) + 1ull) * 1.1102230246251565404e-16;  // 2^-53
@@ -737,13 +739,12 @@ __device__ __forceinline__ T radius_trial(const Rng& rng, T s, const Ball<T, DIM
     T a, k;
     const bool scaled = bessel_i0k0<T>(x, &a, &k);
     if (pprop) {
-      // G(t) = K0(x) - K0(s) I0(x) / I0(s); the ball's c2d is K0(s)/I0(s), scaled by e^{2s}
-      // from s = 2 on
-      const T ex = scaled ? m_exp(x) : (T)1;
-      const T i0x = scaled ? a * ex : (T)1 + a;
-      const T k0x = scaled ? k * m_rcp(ex) : k;
-      const T ks = s >= (T)2 ? b.c2d * m_exp((T)-2 * s) : b.c2d;
-      const T g = k0x - ks * i0x;
+      // G(t) = K0(x) - K0(s) I0(x) / I0(s). From x = 2 on the Bessel values are scaled
+      // (K0(x) = k e^-x, I0(x) = a e^x), and so is the ball's c2d from s = 2 on (K0(s)/I0(s)
+      // = c2d e^-2s); x <= s, so the two exponentials of the second term combine into one
+      const T k0x = scaled ? k * m_exp(-x) : k;
+      const T e2 = m_exp((s >= (T)2 ? (T)-2 * s : (T)0) + (scaled ? x : (T)0));
+      const T g = k0x - b.c2d * (scaled ? a : (T)1 + a) * e2;
       const T C = envelope_series<T>(WOS_PROP_C, WOS_PROP_P, WOS_PROP_N, s * (T)(2.0 / WOS_PROP_SMAX) - (T)1);
       // accept if u3 C ln(1/t) <= t^(2 - 2/a) G(t), ln(1/t) = a ln(1/t0), t^(2 - 2/a) = t0^(2a - 2)
       return u3 * C * ae * la <= m_exp((T)-2 * (ae - (T)1) * la) * g ? t : (T)-1;
