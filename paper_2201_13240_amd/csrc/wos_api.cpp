@@ -154,7 +154,7 @@ std::vector<T> field_terms(const wos_field_desc& f, int dim) {
     } else {  // bumps
       for (int i = 0; i < dim; ++i) o[i] = (T)t[i];
       const double w = t[dim];
-      o[3] = (T)(1.0 / (2 * w * w));
+      o[3] = (T)(1.4426950408889634074 / (2 * w * w));   // log2(e) / (2 w^2): the device takes exp2
       o[4] = (T)t[dim + 1];
       o[5] = (T)(1.0 / (w * w));
     }

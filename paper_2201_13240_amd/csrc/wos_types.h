@@ -17,7 +17,7 @@ enum SolutionId : int32_t { SOL_EXPCOS = 1, SOL_QUADRATIC = 2 };
 //            phi / (2 pi): a cos(2 pi k.x + phi) = ac cos(th) - as sin(th) with
 //            th = 2 pi k.x where derivatives are needed, a cos(2 pi (k.x + phi / 2 pi))
 //            (one cosine) for the value alone
-//   bumps:   c0, c1, c2, 1/(2 w^2), amp, 1/w^2 (the last two unused)
+//   bumps:   c0, c1, c2, log2(e)/(2 w^2) (for exp2), amp, 1/w^2 (the last two unused)
 constexpr int kTermStride = 8;
 
 template <typename T>
