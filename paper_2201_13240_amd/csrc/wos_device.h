@@ -122,13 +122,14 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
 constexpr int kMaxRngBlocks = 5;
 
 struct Rng {
-  uint2 key;
+  uint2 key;        // the seed: one key for every stream of a launch, set once by set_key so
+                    // that it stays wave-uniform (the round keys then come from scalar adds)
   uint32_t walk, point, problem;
   uint32_t block;   // next block index
   uint32_t w[4 * kMaxRngBlocks];
 
-  __device__ __forceinline__ void init(uint64_t seed, uint32_t wk, uint32_t p, uint32_t prob) {
-    key = make_uint2((uint32_t)seed, (uint32_t)(seed >> 32));
+  __device__ __forceinline__ void set_key(uint64_t seed) { key = make_uint2((uint32_t)seed, (uint32_t)(seed >> 32)); }
+  __device__ __forceinline__ void init(uint32_t wk, uint32_t p, uint32_t prob) {
     walk = wk;
     point = p;
     problem = prob;
@@ -137,9 +138,14 @@ struct Rng {
   template <int NB>
   __device__ __forceinline__ void refill() {
     static_assert(NB >= 1 && NB <= kMaxRngBlocks, "block count");
+    // the round keys are formed here by scalar adds: an empty asm statement keeps the
+    // compiler from hoisting all twenty of them out of the walker's loop into scalar
+    // registers, which it would then spill
+    uint32_t kx = key.x, ky = key.y;
+    asm volatile("" : "+s"(kx), "+s"(ky));
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      const uint4 q = philox4x32_10(make_uint4(block + j, walk, point, problem), key);
+      const uint4 q = philox4x32_10(make_uint4(block + j, walk, point, problem), make_uint2(kx, ky));
       w[4 * j] = q.x;
       w[4 * j + 1] = q.y;
       w[4 * j + 2] = q.z;
@@ -265,7 +271,7 @@ __device__ __forceinline__ T envelope_series(const double* cheb, const double* p
 template <typename T> struct BesselTerms;
 template <> struct BesselTerms<float> {
   static constexpr int kI0Wide = WOS_I0E_WIDE_TAIL_NH32, kK0Wide = WOS_K0E_WIDE_TAIL_NH32;
-  static constexpr int kSeries = 9, kI0Mid = WOS_I0E_MID_N32, kI0Tail = WOS_I0E_TAIL_N32,
+  static constexpr int kSeries = 7, kI0Mid = WOS_I0E_MID_N32, kI0Tail = WOS_I0E_TAIL_N32,
                        kK0Low = WOS_K0E_LOW_N32, kK0Mid = WOS_K0E_MID_N32, kK0Tail = WOS_K0E_TAIL_N32,
                        kI1Mid = WOS_I1E_MID_N32, kI1Tail = WOS_I1E_TAIL_N32, kK1Low = WOS_K1E_LOW_N32,
                        kK1Mid = WOS_K1E_MID_N32, kK1Tail = WOS_K1E_TAIL_N32;
@@ -298,7 +304,8 @@ static constexpr BesselSeriesCoef kBesselSeries = make_bessel_series_coef();
 
 // Power series of I0 and K0 for x <= 2 (for K0 near x = 2 the two parts cancel to about a
 // tenth, which costs FP32 a few units in the last place); FP32 takes both as polynomials
-// in q by Horner's rule, FP64 sums the terms upward:
+// in q by Horner's rule, FP64 sums the terms upward. FP32 stops at k = 7 (the terms
+// dropped sum to less than 2e-9 at q = 1, 2e-8 of K0(2)), FP64 at k = 15:
 //   I0(x) - 1 = sum_{k>=1} q^k/(k!)^2,  q = x^2/4
 //   K0(x) = -(ln(x/2) + gamma_E) I0(x) + sum_{k>=1} q^k/(k!)^2 H_k
 template <typename T>

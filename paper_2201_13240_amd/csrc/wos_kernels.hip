@@ -316,7 +316,8 @@ __global__ void sample_kernel(double s, int64_t n, uint64_t seed, double* t, uin
   uint32_t tr = 0;
   if (i < n) {
     Rng rng;
-    rng.init(seed, (uint32_t)i, 0, 0);
+    rng.set_key(seed);
+    rng.init((uint32_t)i, 0, 0);
     const T sv = (T)s;
     const bool harmonic = !(sv > (T)0);
     const Ball<T, DIM> b = ball_terms<T, DIM>((T)1, sv, harmonic ? (T)0 : (T)1 / (sv * sv), harmonic);

@@ -384,6 +384,7 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
   uint32_t nsteps = 0, ntrials = 0;
   int last_prim = -1;   // closest primitive of the previous step (bounds the next query)
   Rng rng;
+  rng.set_key(seed);
   // next flight (phase 3 = inside the unrolled series of a ball): exit point z and current
   // inner point, both relative to the ball centre x; the series T and S of the ball, the
   // throughput, the ball radius and its 2D kernel constant. Pi holds prod_k T_k.
@@ -510,7 +511,7 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
         if (gptr(it.inside)[p]) {
 #pragma unroll
           for (int i = 0; i < DIM; ++i) x[i] = (T)gptr(it.points)[(size_t)p * DIM + i];
-          rng.init(seed, (uint32_t)(it.walk_offset + offset_add + j), p, it.problem_index);
+          rng.init((uint32_t)(it.walk_offset + offset_add + j), p, it.problem_index);
           Pi = 1;
           A = 0;
           Ac = 0;
@@ -869,7 +870,7 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
             last_prim = se.last_prim;
             if (--se.remaining == 0u) --split_state;
             split_state += 1u << 8;
-            rng.init(seed, rng.walk, rng.point, (rng.problem & 0xFFFFu) | ((split_state >> 8) << 16));
+            rng.init(rng.walk, rng.point, (rng.problem & 0xFFFFu) | ((split_state >> 8) << 16));
             pending = false;
           } else {
             phase = 4;   // added to its slot at the top of the next iteration
