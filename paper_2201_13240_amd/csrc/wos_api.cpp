@@ -571,8 +571,11 @@ size_t layout_problem(Blob& blob, const wos_problem_desc& d, const HostGeometry&
           r.count = g.grid.start[c + 1] - g.grid.start[c];
           r.tail = std::isfinite(g.grid.tail[c]) ? (T)(g.grid.tail[c] - g.grid_margin)
                                                  : std::numeric_limits<T>::infinity();
-          for (uint32_t k = 0; k < std::min<uint32_t>(r.count, kCellInline); ++k) {
-            const double* sg = g.prims64.data() + (size_t)g.grid.prim[r.start + k] * 4;
+          // inline entries beyond the list repeat its last candidate: their distance equals
+          // that candidate's, so they never replace it as the nearest (strict comparison)
+          for (uint32_t k = 0; r.count > 0 && k < (uint32_t)kCellInline; ++k) {
+            const uint32_t kk = std::min<uint32_t>(k, r.count - 1);
+            const double* sg = g.prims64.data() + (size_t)g.grid.prim[r.start + kk] * 4;
             r.seg[k][0] = (T)sg[0];
             r.seg[k][1] = (T)sg[1];
             r.seg[k][2] = (T)(sg[2] - sg[0]);

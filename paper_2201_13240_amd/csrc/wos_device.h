@@ -484,16 +484,13 @@ __device__ __forceinline__ Ball<T, DIM> ball_terms(T R, T s, T inv_sigma_bar, bo
     return b;
   }
   if (DIM == 2) {
+    // s < 2: a = I0 - 1, k = K0; from s = 2 on: a = e^-s I0, k = e^s K0 (one reciprocal
+    // for both cases)
     T a, k;
-    if (!bessel_i0k0<T>(s, &a, &k)) {   // s < 2: a = I0 - 1, k = K0
-      const T ii0 = m_rcp((T)1 + a);
-      b.pb = a * ii0;
-      b.c2d = k * ii0;
-    } else {                            // a = e^-s I0, k = e^s K0
-      const T ii0 = m_rcp(a);
-      b.pb = (T)1 - m_exp(-s) * ii0;
-      b.c2d = k * ii0;
-    }
+    const bool scaled = bessel_i0k0<T>(s, &a, &k);
+    const T ii0 = m_rcp(scaled ? a : (T)1 + a);
+    b.pb = scaled ? (T)1 - m_exp(-s) * ii0 : a * ii0;
+    b.c2d = k * ii0;
   } else {
     if (s < (T)1) {
       // (sinh s - s) = s^3 sum_{k>=0} s^{2k} / (2k+3)!, a polynomial in s^2 by Horner
@@ -1673,13 +1670,14 @@ __device__ __forceinline__ T boundary_distance(G<DevGeometry<T>>& g, const T* x,
           const uint32_t n = rec->count, st = rec->start;
           if (n > 0) {
             // the inline candidates are tested unconditionally (their loads do not wait
-            // for the count; padding entries are ignored)
+            // for the count); entries past a shorter list repeat its last candidate, which
+            // ties and so never replaces it
             T best = Consts<T>::kInf;
             uint32_t bk = 0;
 #pragma unroll
             for (int k = 0; k < kCellInline; ++k) {
               const T d2 = segment_dist2_pre<T>(x, rec->seg[k], rec->inv_len2[k]);
-              if ((uint32_t)k < n && d2 < best) {
+              if (d2 < best) {
                 best = d2;
                 bk = (uint32_t)k;
               }

@@ -39,10 +39,11 @@ constexpr int kPolygonCellMax = 32;
 constexpr int kPolygonDeepList = 16;
 
 // One cell of the polygon candidate grid: `count` candidates at cell_prim / cell_segs /
-// cell_dc [start, start + count), the first kCellInline also held here (zero-padded) as
-// start point, edge vector and reciprocal squared length (x0, y0, ex, ey), 1/|e|^2, so
-// that their distance needs no division. `tail` bounds from below the centre distance
-// of every segment left off a truncated list (+inf: the list is complete).
+// cell_dc [start, start + count), the first kCellInline also held here as start point,
+// edge vector and reciprocal squared length (x0, y0, ex, ey), 1/|e|^2, so that their
+// distance needs no division (a shorter list is padded with copies of its last
+// candidate). `tail` bounds from below the centre distance of every segment left off a
+// truncated list (+inf: the list is complete).
 template <typename T>
 struct __attribute__((aligned(16))) CellRec {
   uint32_t count;
