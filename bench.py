@@ -151,8 +151,8 @@ def event_weights(prob):
         "trials_free": (37, 1),                                          # free-space proposal, extra
         # below s = 3.5 (2D) or 4 (3D): the harmonic draw mapped to t0^a (a, ln t0, t0^a),
         # in 2D the Bessel values unscaled, the envelope constant (closed form or 12-term
-        # Chebyshev series) and t0^(2a - 2)
-        "trials_power": (34, 3) if prob["dim"] == 2 else (26, 3),
+        # polynomial) and the acceptance test with t0^(2a - 2) = t^2 / t0^2
+        "trials_power": (33, 2) if prob["dim"] == 2 else (26, 2),
         "volume": (3, 0),
         "exit": (6, 2),
         "terminal": (12 + bf + 4, bt + 1),

@@ -731,10 +731,11 @@ __device__ __forceinline__ T radius_trial(const Rng& rng, T s, const Ball<T, DIM
     if (harmonic) return m_sqrt(u1 * u2);
     const T u3 = uniform01<T, S + 2>(rng);
     const bool pprop = s < (T)WOS_PROP_SMAX;
-    T t, x, la = 0, ae = 1;
+    T t, x, la = 0, ae = 1, w = 1;
     if (pprop) {
       ae = m_fma((T)WOS_PROP_KAPPA * s, s, (T)1);
-      la = (T)-0.5 * m_logn(u1 * u2);     // ln(1/t0)
+      w = u1 * u2;                        // t0^2
+      la = (T)-0.5 * m_logn(w);           // ln(1/t0)
       t = m_exp(-ae * la);
       x = t * s;
     } else {
@@ -752,8 +753,9 @@ __device__ __forceinline__ T radius_trial(const Rng& rng, T s, const Ball<T, DIM
       const T e2 = m_exp((s >= (T)2 ? (T)-2 * s : (T)0) + (scaled ? x : (T)0));
       const T g = k0x - b.c2d * (scaled ? a : (T)1 + a) * e2;
       const T C = envelope_series<T>(WOS_PROP_C, WOS_PROP_P, WOS_PROP_N, s * (T)(2.0 / WOS_PROP_SMAX) - (T)1);
-      // accept if u3 C ln(1/t) <= t^(2 - 2/a) G(t), ln(1/t) = a ln(1/t0), t^(2 - 2/a) = t0^(2a - 2)
-      return u3 * C * ae * la <= m_exp((T)-2 * (ae - (T)1) * la) * g ? t : (T)-1;
+      // accept if u3 C ln(1/t) <= t^(2 - 2/a) G(t), with ln(1/t) = a ln(1/t0) and
+      // t^(2 - 2/a) = t0^(2a - 2) = t^2 / t0^2, multiplied through by t0^2
+      return u3 * C * ae * la * w <= t * t * g ? t : (T)-1;
     }
     // 1 - G_ball/G_free = c2d I0(x)/K0(x) e^{-2s} with c2d = e^{2s} K0(s)/I0(s)
     const T r = b.c2d * m_div(scaled ? a : (T)1 + a, k) * m_exp(scaled ? (T)2 * (x - s) : (T)-2 * s);
@@ -776,12 +778,13 @@ __device__ __forceinline__ T radius_trial(const Rng& rng, T s, const Ball<T, DIM
       // sinh(s(1-t)) / sinh(s) = e^{-st} (1 - e^{-2s(1-t)}) / (1 - e^{-2s})
       const T e2s = m_expm1((T)-2 * s);
       const T sr = omt > (T)0 ? m_div(m_exp(-s * t) * m_expm1((T)-2 * s * omt), e2s) : (T)0;
-      const T rho = m_exp((T)2 * (ae - (T)1) * lt0) * m_div(sr, (T)1 - t0);
       const T C = s < (T)WOS_PROP3_SK
                       ? ae * m_div((T)-2 * s * m_exp(-s), e2s) * (T)1.00001
                       : envelope_series<T>(WOS_PROP3_C, WOS_PROP3_P, WOS_PROP3_N,
                                      (s - (T)WOS_PROP3_SK) * (T)(2.0 / (WOS_PROP3_SMAX - WOS_PROP3_SK)) - (T)1);
-      return u4 * C <= rho ? t : (T)-1;
+      // u4 C <= t0^(2a - 2) sr / (1 - t0), with t0^(2a - 2) = t^2 / t0^2, multiplied through
+      // by t0^2 (1 - t0)
+      return u4 * C * (t0 * t0) * ((T)1 - t0) <= t * t * sr ? t : (T)-1;
     }
     if constexpr (COUNT) ++tally->trials_free;
     const T u = -m_logn(uniform01<T, S>(rng) * uniform01<T, S + 1>(rng));

@@ -744,6 +744,9 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
           cq = point_coef<T, DIM, true>(P, q, EXTRA && a.grad ? ggx : nullptr);
           if constexpr (COUNT) ++ev[EV_COEF_LANES];
         }
+        // weight of a term at the evaluated point, Pi e^{gamma(q) - gamma(x0)} (the boundary
+        // value of a walk in the shell, the source at a sampled point), formed once for both
+        const T pe = Pi * m_exp(cq.gamma - gamma0);
         if (phase == 1) {
           gamma0 = cq.gamma;
           gx = gamma0;
@@ -762,12 +765,12 @@ __device__ __forceinline__ void walker_body(WalkerArgs<T> a, uint32_t* __restric
             }
           }
         } else if (terminal) {
-          add_estimate(A, Ac, Pi * m_exp(cq.gamma - gamma0) * gb, a.compensated);
+          add_estimate(A, Ac, pe * gb, a.compensated);
           done = true;
         } else if (sampled) {
           const T mu = uniform01<T, SL::kMu>(rng);
           const bool volume = mu <= b.pb;
-          const T src = Pi * m_exp(cq.gamma - gamma0) * cq.f_over_alpha;
+          const T src = pe * cq.f_over_alpha;
           T term = 0;
           // |G| = P_B / sigma_bar (R^2 / 2n when sigma_bar = 0) is formed here rather than
           // kept from the ball's first iteration, which saves a register across retries
