@@ -846,10 +846,11 @@ def main():
             walker_ms.append(wm)
         torch.cuda.synchronize()
         timed_steps = int(acc.n_steps.sum().item()) - n_steps
-        print(f"bench: {precision} walker ms/launch {np.round(walker_ms, 2).tolist()}", file=sys.stderr, flush=True)
+        info = plan.info()
+        print(f"bench: {precision} walker ms/launch {np.round(walker_ms, 2).tolist()}, plan {info}", file=sys.stderr,
+              flush=True)
         mean, se = wos.finalize(acc)
         torch.cuda.synchronize()
-        info = plan.info()
         st = plan.setup_times()
         plan.close()
         return {"wall_s": wall, "ms": ms, "steps": n_steps, "walks": n_walks,

@@ -1510,9 +1510,9 @@ wos_status time_shape(wos_plan* P, unsigned block, uint32_t tile, uint64_t walks
   return WOS_OK;
 }
 
-// Chooses block size and tile length for this walker by timing candidates on a sample of
-// the plan's own walks (about eight walks per resident lane, so that every wave takes
-// several tiles; each item contributes in proportion to its walks), and caches the
+// Chooses block size and tile length for this walker by timing candidates on samples of
+// the plan's own walks (about eight and 40 walks per resident lane, so that every wave
+// takes several tiles; each item contributes in proportion to its walks), and caches the
 // winner per process. Jobs too small to time leave the defaults.
 wos_status autotune(wos_plan* P, hipStream_t st, unsigned* block, uint32_t* tile, bool* ran) {
   static const unsigned kBlocks[] = {64, 128, 256};
@@ -1531,12 +1531,19 @@ wos_status autotune(wos_plan* P, hipStream_t st, unsigned* block, uint32_t* tile
   }
   const uint64_t walks = 8 * lanes;
   if (launch0 < walks) return WOS_OK;
+  // A shape is scored by the marginal time of 4W more walks, T(5W) - T(W): in samples
+  // this small the launch's drain (lanes idle while the last walks finish) is a large part
+  // of T(W) and favours short tiles, which lose at full size (the FP64 walker ran 25%
+  // slower with the shape chosen by T(W)). Jobs below 5W are scored by T(W). Shapes within
+  // 1% of the best score count as ties, won by the longer tile (fewer slots).
+  const bool marginal = launch0 >= 5 * walks;
+  const uint64_t sample_max = marginal ? 5 * walks : walks;
   WOS_HIP(launch_set_params(P->ws.lp, 0, 0, st));
   uint64_t max_slots = 0;
   for (uint32_t t : kTiles) {
     std::vector<DevItem> d;
     uint64_t nt = 0, ns = 0;
-    sample_items(P, t, walks, d, &nt, &ns);
+    sample_items(P, t, sample_max, d, &nt, &ns);
     max_slots = std::max(max_slots, ns);
   }
   DevItem* ditems = nullptr;
@@ -1547,19 +1554,36 @@ wos_status autotune(wos_plan* P, hipStream_t st, unsigned* block, uint32_t* tile
     (void)hipFree(ditems);
     return fail(WOS_ERR_OUT_OF_MEMORY, "autotune slot allocation failed");
   }
-  float best = 1e30f;
+  struct Scored {
+    unsigned block;
+    uint32_t tile;
+    float ms;
+  };
+  std::vector<Scored> scores;
   wos_status r = WOS_OK;
   for (unsigned b : kBlocks) {
     for (uint32_t t : kTiles) {
       float ms = 0;
       if ((r = time_shape(P, b, t, walks, ditems, dslots, 2, st, &ms)) != WOS_OK) break;
-      if (ms < best) {
-        best = ms;
-        *block = b;
-        *tile = t;
+      if (marginal) {
+        float ms5 = 0;
+        if ((r = time_shape(P, b, t, 5 * walks, ditems, dslots, 2, st, &ms5)) != WOS_OK) break;
+        ms = ms5 - ms;
       }
+      scores.push_back({b, t, ms});
     }
     if (r != WOS_OK) break;
+  }
+  if (r == WOS_OK && !scores.empty()) {
+    float best = scores[0].ms;
+    for (const Scored& c : scores) best = std::min(best, c.ms);
+    const Scored* pick = nullptr;
+    for (const Scored& c : scores) {
+      if (c.ms > best + 0.01f * std::fabs(best)) continue;
+      if (!pick || c.tile > pick->tile || (c.tile == pick->tile && c.ms < pick->ms)) pick = &c;
+    }
+    *block = pick->block;
+    *tile = pick->tile;
   }
   (void)hipFree(ditems);
   (void)hipFree(dslots);
