@@ -60,16 +60,22 @@ __device__ __forceinline__ double m_fabs(double x) { return ::fabs(x); }
 __device__ __forceinline__ float m_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double m_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 // sin and cos of 2*pi*r (r in revolutions). FP32: the hardware sine and cosine take
-// revolutions directly; r is first reduced to [-1/2, 1/2] (exactly: r - rint(r)), inside
-// their input range. Measured on MI355X over r in [-2, 2]: max abs error 1.2e-7.
+// revolutions directly; r is first reduced to [0, 1) by the hardware fraction (exact,
+// r - floor(r)), inside their input range. m_sincospi2_unit takes an r already in (0, 1)
+// (a uniform) as it is.
 __device__ __forceinline__ void m_sincospi2(float r, float* s, float* c) {
-  const float f = r - __builtin_rintf(r);
+  const float f = __builtin_amdgcn_fractf(r);
   *s = __builtin_amdgcn_sinf(f);
   *c = __builtin_amdgcn_cosf(f);
 }
+__device__ __forceinline__ void m_sincospi2_unit(float r, float* s, float* c) {
+  *s = __builtin_amdgcn_sinf(r);
+  *c = __builtin_amdgcn_cosf(r);
+}
 __device__ __forceinline__ void m_sincospi2(double r, double* s, double* c) { ::sincospi(2.0 * r, s, c); }
+__device__ __forceinline__ void m_sincospi2_unit(double r, double* s, double* c) { ::sincospi(2.0 * r, s, c); }
 // cos(2 pi r), r in revolutions
-__device__ __forceinline__ float m_cospi2(float r) { return __builtin_amdgcn_cosf(r - __builtin_rintf(r)); }
+__device__ __forceinline__ float m_cospi2(float r) { return __builtin_amdgcn_cosf(__builtin_amdgcn_fractf(r)); }
 __device__ __forceinline__ double m_cospi2(double r) { return ::cospi(2.0 * r); }
 __device__ __forceinline__ void m_sincos(float x, float* s, float* c) { ::sincosf(x, s, c); }
 __device__ __forceinline__ void m_sincos(double x, double* s, double* c) { ::sincos(x, s, c); }
@@ -379,9 +385,8 @@ __device__ __forceinline__ bool bessel_i0k0(T x, T* a, T* k) {
     return false;
   }
   if constexpr (sizeof(T) == 4) {
-    const T rx = m_rcp(x);
-    const T t = m_fma((T)4, rx, (T)-1);
     const T rs = __builtin_amdgcn_rsqf(x);
+    const T t = m_fma((T)4, rs * rs, (T)-1);   // 4/x - 1
     *a = horner<T>(WOS_I0E_WIDE_TAIL_POW32, BesselTerms<T>::kI0Wide, t) * rs;
     *k = horner<T>(WOS_K0E_WIDE_TAIL_POW32, BesselTerms<T>::kK0Wide, t) * rs;
     return true;
@@ -815,13 +820,13 @@ template <typename T, int DIM, int S>
 __device__ __forceinline__ void uniform_direction(const Rng& rng, T* v) {
   if (DIM == 2) {
     T sn, cs;
-    m_sincospi2(uniform01<T, S>(rng), &sn, &cs);
+    m_sincospi2_unit(uniform01<T, S>(rng), &sn, &cs);
     v[0] = cs;
     v[1] = sn;
   } else {
     const T z = (T)1 - (T)2 * uniform01<T, S>(rng);
     T sn, cs;
-    m_sincospi2(uniform01<T, S + 1>(rng), &sn, &cs);
+    m_sincospi2_unit(uniform01<T, S + 1>(rng), &sn, &cs);
     const T rr = m_sqrt(fmax((T)0, (T)1 - z * z));
     v[0] = rr * cs;
     v[1] = rr * sn;
@@ -1182,8 +1187,9 @@ __device__ __forceinline__ void gamma_alpha_sigma(G<DevProblem<T>>& P, const T* 
       FV<T, 2> b[3];
       spectral2d<T, true, 1>(P.spec, x, b);
       gam = b[0];
-      alpha = m_exp(m_fma(P.alpha.c1, b[1].v, P.alpha.c0));
-      inv_alpha = m_rcp(alpha);
+      const T la = m_fma(P.alpha.c1, b[1].v, P.alpha.c0);
+      alpha = m_exp(la);
+      inv_alpha = m_exp(-la);   // (the walker uses 1/alpha alone: one exponential)
       if (!(P.spectral & 4)) b[2] = field_base<T, 2, false>(P.sigma, x);
       sigma = field_transform<T, 2, false>(P.sigma, b[2]).v;
       return;
