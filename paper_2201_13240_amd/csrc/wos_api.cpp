@@ -1559,10 +1559,18 @@ wos_status autotune(wos_plan* P, hipStream_t st, unsigned* block, uint32_t* tile
     uint32_t tile;
     float ms;
   };
+  // Tiles longer than a point's walks hold several points, whose walks add into global
+  // slots instead of the wave's LDS slot cache; the samples underrate that (on the
+  // 64-polygon batch, 512 walks per point, tiles of 1024 ran 24% slower than 256 at full
+  // size), so such tiles are tried only when no candidate fits one point.
+  uint64_t min_walks = ~0ull;
+  for (const DevItem& d : P->dit[0]) min_walks = std::min<uint64_t>(min_walks, (uint64_t)d.walks);
+  const bool fits = min_walks >= kTiles[0];
   std::vector<Scored> scores;
   wos_status r = WOS_OK;
   for (unsigned b : kBlocks) {
     for (uint32_t t : kTiles) {
+      if (fits && t > min_walks) continue;
       float ms = 0;
       if ((r = time_shape(P, b, t, walks, ditems, dslots, 2, st, &ms)) != WOS_OK) break;
       if (marginal) {
