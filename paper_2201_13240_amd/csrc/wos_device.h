@@ -982,10 +982,10 @@ __device__ __forceinline__ void spectral2d_first_slot(G<Spectral2D<T>>& sp, cons
   for (int s = 0; s < 3; ++s) out[s].v = spectral_dot<T>(sp.m[0][s][0], phi);
   T cx1, sx1;
   m_sincospi2(x[0], &sx1, &cx1);
-  T c = cx1, sn = sx1, gx = 0, lx = 0;
+  T c = cx1, sn = sx1, gx = 0, lx = 0, fn = 0;
 #pragma unroll 1
   for (int n = 1; n <= kSpecK; ++n) {
-    const T fn = (T)n;
+    fn += (T)1;
     const WOS_GLOBAL T* rc = sp.m[2 * n - 1][0][0];
     const WOS_GLOBAL T* rs = sp.m[2 * n][0][0];
     const T vc = spectral_dot<T>(rc, phi);
@@ -1000,7 +1000,7 @@ __device__ __forceinline__ void spectral2d_first_slot(G<Spectral2D<T>>& sp, cons
     for (int s = 1; s < 3; ++s) {
       const T wc = spectral_dot<T>(sp.m[2 * n - 1][s][0], phi);
       const T ws = spectral_dot<T>(sp.m[2 * n][s][0], phi);
-      out[s].v += m_fma(wc, c, ws * sn);
+      out[s].v = m_fma(wc, c, m_fma(ws, sn, out[s].v));
     }
     const T t = m_fma(c, cx1, -sn * sx1);
     sn = m_fma(sn, cx1, c * sx1);
